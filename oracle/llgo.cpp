@@ -1,0 +1,874 @@
+// llgo.cpp -- FP64 CPU oracle for one semi-implicit BDF1 Landau-Lifshitz step.
+//
+// TEST INFRASTRUCTURE ONLY (see llgo.h).  Plain, single-threaded, double
+// precision, no blocking or fusion: each function follows one passage of the
+// paper, cited in its comment, or the reading of it recorded in the design
+// notes when the paper is silent.
+#include "llgo.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+struct Graph {  // integer-weighted undirected graph, CSR, no self loops
+  int64_t n = 0;
+  std::vector<int64_t> rp;
+  std::vector<int32_t> ci;
+  std::vector<int64_t> w;
+};
+
+struct Bsr {  // 3x3 block CSR
+  int64_t n = 0;
+  std::vector<int64_t> rp;
+  std::vector<int32_t> ci;
+  std::vector<double> v;  // 9 per block, row-major
+  int64_t nnzb() const { return (int64_t)ci.size(); }
+};
+
+struct Level {
+  Bsr A;
+  std::vector<double> dinv;  // 9 per node: inverse of the diagonal block
+  std::vector<int32_t> agg;  // node -> aggregate on the next level (empty at the coarsest)
+  int64_t nc = 0;
+};
+
+struct Hier {
+  llgo_grid g;
+  llgo_opts o;
+  double omega = 0;
+  Bsr A;                      // unscaled fine operator
+  std::vector<double> dinv0;  // inverse diagonal blocks of A
+  std::vector<Level> lv;
+  // dense LU of the coarsest matrix
+  int64_t nd = 0;
+  std::vector<double> lu;
+  std::vector<int64_t> piv;
+};
+
+// ---------------------------------------------------------------- grid (O1)
+// Cell-centred grid, homogeneous Neumann boundary by mirrored ghosts: a missing
+// neighbour is replaced by the node itself, so its term cancels and the row of
+// the Laplacian is L_ij = 1/h^2 per in-grid neighbour, L_ii = -deg_i/h^2.
+int64_t num_nodes(const llgo_grid& g) { return (int64_t)g.n[0] * g.n[1] * g.n[2]; }
+
+// Neighbours of node p in ascending index order (k-1, j-1, i-1, i+1, j+1, k+1).
+int neighbours(const llgo_grid& g, int64_t p, int64_t* nb) {
+  const int64_t nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const int64_t i = p % nx, j = (p / nx) % ny, k = p / (nx * ny);
+  int c = 0;
+  if (k > 0) nb[c++] = p - nx * ny;
+  if (j > 0) nb[c++] = p - nx;
+  if (i > 0) nb[c++] = p - 1;
+  if (i < nx - 1) nb[c++] = p + 1;
+  if (j < ny - 1) nb[c++] = p + nx;
+  if (k < nz - 1) nb[c++] = p + nx * ny;
+  return c;
+}
+
+bool grid_ok(const llgo_grid* g) {
+  if (!g) return false;
+  if (g->dim != 2 && g->dim != 3) return false;
+  if (g->n[0] < 2 || g->n[1] < 2) return false;
+  if (g->dim == 2 && g->n[2] != 1) return false;
+  if (g->dim == 3 && g->n[2] < 2) return false;
+  if (!(g->h > 0) || !std::isfinite(g->h)) return false;
+  return true;
+}
+
+// --------------------------------------------------- block assembly (O3, Sec. 2.1)
+// The damped component-wise system of Sec. 2.1 reads, for node i with frozen
+// m = (m1, m2, m3), u + dt * M_i (Delta_h u)_i = m^n, where row r of M_i holds
+// the coefficients of (Delta_h u_1, Delta_h u_2, Delta_h u_3) in equation r.
+void block_M(const double* m, double a, double* M) {
+  const double m1 = m[0], m2 = m[1], m3 = m[2];
+  M[0] = -(a * (m2 * m2 + m3 * m3));
+  M[1] = -m3 + a * (m1 * m2);
+  M[2] = m2 + a * (m1 * m3);
+  M[3] = m3 + a * (m1 * m2);
+  M[4] = -(a * (m1 * m1 + m3 * m3));
+  M[5] = -m1 + a * (m2 * m3);
+  M[6] = -m2 + a * (m1 * m3);
+  M[7] = m1 + a * (m2 * m3);
+  M[8] = -(a * (m1 * m1 + m2 * m2));
+}
+
+void assemble(const llgo_grid& g, const double* m, double alpha, double dt, Bsr& A) {
+  const int64_t N = num_nodes(g);
+  const double inv_h2 = 1.0 / (g.h * g.h);
+  A.n = N;
+  A.rp.assign(N + 1, 0);
+  A.ci.clear();
+  A.v.clear();
+  int64_t nb[6];
+  for (int64_t p = 0; p < N; ++p) {
+    const int deg = neighbours(g, p, nb);
+    double M[9];
+    block_M(m + 3 * p, alpha, M);
+    const double s_off = dt * inv_h2;
+    const double s_diag = dt * (-(double)deg * inv_h2);
+    // columns ascending: neighbours below p, p itself, neighbours above p
+    std::vector<int64_t> cols(nb, nb + deg);
+    cols.push_back(p);
+    std::sort(cols.begin(), cols.end());
+    for (int64_t q : cols) {
+      A.ci.push_back((int32_t)q);
+      for (int e = 0; e < 9; ++e) {
+        if (q == p) {
+          double val = s_diag * M[e];
+          if (e == 0 || e == 4 || e == 8) val = 1.0 + val;
+          A.v.push_back(val);
+        } else {
+          A.v.push_back(s_off * M[e]);
+        }
+      }
+    }
+    A.rp[p + 1] = (int64_t)A.ci.size();
+  }
+}
+
+// -------------------------------------------------- 3x3 inverse (O4)
+// Inverse of a 3x3 block by the adjugate divided by the determinant.
+void inv3(const double* D, double* R) {
+  const double a = D[0], b = D[1], c = D[2], d = D[3], e = D[4], f = D[5], g = D[6], h = D[7],
+               i = D[8];
+  double adj[9];
+  adj[0] = e * i - f * h;
+  adj[1] = c * h - b * i;
+  adj[2] = b * f - c * e;
+  adj[3] = f * g - d * i;
+  adj[4] = a * i - c * g;
+  adj[5] = c * d - a * f;
+  adj[6] = d * h - e * g;
+  adj[7] = b * g - a * h;
+  adj[8] = a * e - b * d;
+  const double det = (a * adj[0] + b * adj[3]) + c * adj[6];
+  const double rdet = 1.0 / det;
+  for (int k = 0; k < 9; ++k) R[k] = adj[k] * rdet;
+}
+
+// C = X * Y for 3x3 blocks, each entry summed over k = 0, 1, 2 in order.
+void mul3(const double* X, const double* Y, double* C) {
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      C[3 * r + c] = (X[3 * r + 0] * Y[0 * 3 + c] + X[3 * r + 1] * Y[1 * 3 + c]) +
+                     X[3 * r + 2] * Y[2 * 3 + c];
+}
+
+void diag_inverses(const Bsr& A, std::vector<double>& dinv) {
+  dinv.assign(9 * A.n, 0.0);
+  for (int64_t i = 0; i < A.n; ++i)
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+      if (A.ci[k] == i) inv3(&A.v[9 * k], &dinv[9 * i]);
+}
+
+// Left scaling: row i of A multiplied by D_i^{-1}; the diagonal block becomes
+// the identity and is stored as exactly I.
+void left_scale(const Bsr& A, const std::vector<double>& dinv, Bsr& S) {
+  S.n = A.n;
+  S.rp = A.rp;
+  S.ci = A.ci;
+  S.v.assign(A.v.size(), 0.0);
+  for (int64_t i = 0; i < A.n; ++i)
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      if (A.ci[k] == i) {
+        for (int e = 0; e < 9; ++e) S.v[9 * k + e] = (e == 0 || e == 4 || e == 8) ? 1.0 : 0.0;
+      } else {
+        mul3(&dinv[9 * i], &A.v[9 * k], &S.v[9 * k]);
+      }
+    }
+}
+
+// ------------------------------------------------------ aggregation (O5, Sec. 3.1)
+uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+struct Edge {
+  int64_t w;
+  uint64_t rank;  // visiting rank of the endpoint that is visited first
+  int32_t first;  // that endpoint
+  uint64_t h;     // edge hash
+  int32_t i, j;   // i < j
+};
+
+// Visiting rank of node v in a pass: a hash of v, ties broken by v.
+uint64_t node_rank(int64_t v, uint64_t salt) {
+  return splitmix64((((uint64_t)v) << 32 | (uint64_t)v) ^ salt);
+}
+
+bool visited_before(uint64_t ra, int64_t a, uint64_t rb, int64_t b) {
+  return ra != rb ? ra < rb : a < b;
+}
+
+// Strict total order on edges: by the visiting rank of the first-visited
+// endpoint, then larger weight, then larger edge hash, then smaller (i, j).
+bool edge_before(const Edge& x, const Edge& y) {
+  if (x.rank != y.rank) return x.rank < y.rank;
+  if (x.first != y.first) return x.first < y.first;
+  if (x.w != y.w) return x.w > y.w;
+  if (x.h != y.h) return x.h > y.h;
+  if (x.i != y.i) return x.i < y.i;
+  return x.j < y.j;
+}
+
+// One pass of pairwise matching favouring the strongest couplings (Sec. 3.1,
+// Sec. 3.1.1).  Nodes are visited in a hashed order; a node that is still
+// free when visited pairs with its strongest free neighbour among those whose
+// coupling reaches beta times the node's largest coupling, and otherwise stays
+// a singleton.  Written here as the equivalent greedy scan over edges sorted by
+// (visit rank of the first-visited endpoint, weight, hash), an edge being a
+// candidate when it is strong for that first-visited endpoint.
+void match_pass(const Graph& G, uint64_t salt, int bnum, int bden, std::vector<int32_t>& agg,
+                std::vector<int32_t>& mate, int64_t& nc) {
+  const int64_t n = G.n;
+  std::vector<int64_t> mx(n, 0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = G.rp[i]; k < G.rp[i + 1]; ++k) mx[i] = std::max(mx[i], G.w[k]);
+  std::vector<Edge> E;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = G.rp[i]; k < G.rp[i + 1]; ++k) {
+      const int64_t j = G.ci[k];
+      if (!(i < j)) continue;
+      const int64_t w = G.w[k];
+      const uint64_t ri = node_rank(i, salt), rj = node_rank(j, salt);
+      const int64_t f = visited_before(ri, i, rj, j) ? i : j;
+      if (!((int64_t)bden * w >= (int64_t)bnum * mx[f])) continue;
+      const uint64_t key = ((uint64_t)i << 32) | (uint64_t)j;
+      E.push_back(Edge{w, f == i ? ri : rj, (int32_t)f, splitmix64(key ^ salt), (int32_t)i, (int32_t)j});
+    }
+  std::sort(E.begin(), E.end(), edge_before);
+  mate.assign(n, -1);
+  for (const Edge& e : E)
+    if (mate[e.i] < 0 && mate[e.j] < 0) {
+      mate[e.i] = e.j;
+      mate[e.j] = e.i;
+    }
+  // numbering: scan nodes in ascending order; an unassigned node opens the
+  // next aggregate and its partner joins it
+  agg.assign(n, -1);
+  nc = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    agg[i] = (int32_t)nc;
+    if (mate[i] >= 0) agg[mate[i]] = (int32_t)nc;
+    ++nc;
+  }
+}
+
+// Coarse graph P^T G P with the diagonal dropped; weights are summed.
+void coarse_graph(const Graph& G, const std::vector<int32_t>& agg, int64_t nc, Graph& C) {
+  std::vector<std::vector<std::pair<int32_t, int64_t>>> rows(nc);
+  for (int64_t i = 0; i < G.n; ++i)
+    for (int64_t k = G.rp[i]; k < G.rp[i + 1]; ++k) {
+      const int32_t I = agg[i], J = agg[G.ci[k]];
+      if (I != J) rows[I].push_back({J, G.w[k]});
+    }
+  C.n = nc;
+  C.rp.assign(nc + 1, 0);
+  C.ci.clear();
+  C.w.clear();
+  for (int64_t I = 0; I < nc; ++I) {
+    auto& r = rows[I];
+    std::sort(r.begin(), r.end());
+    for (size_t t = 0; t < r.size(); ++t) {
+      if (t > 0 && r[t].first == r[t - 1].first) {
+        C.w.back() += r[t].second;
+      } else {
+        C.ci.push_back(r[t].first);
+        C.w.push_back(r[t].second);
+      }
+    }
+    C.rp[I + 1] = (int64_t)C.ci.size();
+  }
+}
+
+void grid_graph(const llgo_grid& g, Graph& G) {
+  const int64_t N = num_nodes(g);
+  G.n = N;
+  G.rp.assign(N + 1, 0);
+  G.ci.clear();
+  G.w.clear();
+  int64_t nb[6];
+  for (int64_t p = 0; p < N; ++p) {
+    const int d = neighbours(g, p, nb);
+    for (int t = 0; t < d; ++t) {
+      G.ci.push_back((int32_t)nb[t]);
+      G.w.push_back(1);
+    }
+    G.rp[p + 1] = (int64_t)G.ci.size();
+  }
+}
+
+// ------------------------------------------------------ Galerkin (O6, eq. Ac_direct)
+// (A_c)_{IJ} = sum over fine rows i in aggregate I (ascending i) and stored
+// blocks (i, j) (ascending j) with agg(j) = J of the block a_ij.
+void galerkin(const Bsr& A, const std::vector<int32_t>& agg, int64_t nc, Bsr& C) {
+  // members of each aggregate in ascending order
+  std::vector<std::vector<int64_t>> mem(nc);
+  for (int64_t i = 0; i < A.n; ++i) mem[agg[i]].push_back(i);
+  C.n = nc;
+  C.rp.assign(nc + 1, 0);
+  C.ci.clear();
+  C.v.clear();
+  for (int64_t I = 0; I < nc; ++I) {
+    std::vector<int32_t> cols;
+    for (int64_t i : mem[I])
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) cols.push_back(agg[A.ci[k]]);
+    std::sort(cols.begin(), cols.end());
+    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+    const int64_t base = (int64_t)C.ci.size();
+    for (int32_t J : cols) C.ci.push_back(J);
+    C.v.resize(9 * C.ci.size(), 0.0);
+    for (int64_t i : mem[I])
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        const int32_t J = agg[A.ci[k]];
+        const int64_t s = base + (std::lower_bound(cols.begin(), cols.end(), J) - cols.begin());
+        for (int e = 0; e < 9; ++e) C.v[9 * s + e] += A.v[9 * k + e];
+      }
+    C.rp[I + 1] = (int64_t)C.ci.size();
+  }
+}
+
+// -------------------------------------------------- dense LU (O8)
+// Partial pivoting: the pivot is the first entry of largest magnitude.
+void dense_from_bsr(const Bsr& A, std::vector<double>& D) {
+  const int64_t m = 3 * A.n;
+  D.assign(m * m, 0.0);
+  for (int64_t i = 0; i < A.n; ++i)
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      const int64_t j = A.ci[k];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) D[(3 * i + r) * m + 3 * j + c] = A.v[9 * k + 3 * r + c];
+    }
+}
+
+void lu_factor(int64_t m, std::vector<double>& a, std::vector<int64_t>& piv) {
+  piv.assign(m, 0);
+  for (int64_t k = 0; k < m; ++k) {
+    int64_t p = k;
+    double best = std::fabs(a[k * m + k]);
+    for (int64_t i = k + 1; i < m; ++i)
+      if (std::fabs(a[i * m + k]) > best) {
+        best = std::fabs(a[i * m + k]);
+        p = i;
+      }
+    piv[k] = p;
+    if (p != k)
+      for (int64_t j = 0; j < m; ++j) std::swap(a[k * m + j], a[p * m + j]);
+    for (int64_t i = k + 1; i < m; ++i) {
+      const double l = a[i * m + k] / a[k * m + k];
+      a[i * m + k] = l;
+      for (int64_t j = k + 1; j < m; ++j) a[i * m + j] -= l * a[k * m + j];
+    }
+  }
+}
+
+void lu_solve(int64_t m, const std::vector<double>& a, const std::vector<int64_t>& piv, double* x) {
+  for (int64_t k = 0; k < m; ++k)
+    if (piv[k] != k) std::swap(x[k], x[piv[k]]);
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t j = 0; j < i; ++j) x[i] -= a[i * m + j] * x[j];
+  for (int64_t i = m - 1; i >= 0; --i) {
+    for (int64_t j = i + 1; j < m; ++j) x[i] -= a[i * m + j] * x[j];
+    x[i] /= a[i * m + i];
+  }
+}
+
+// ------------------------------------------------------ vectors
+void spmv(const Bsr& A, const double* x, double* y) {
+  for (int64_t i = 0; i < A.n; ++i) {
+    double s[3] = {0, 0, 0};
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      const double* b = &A.v[9 * k];
+      const double* xj = x + 3 * (int64_t)A.ci[k];
+      for (int r = 0; r < 3; ++r) s[r] += b[3 * r] * xj[0] + b[3 * r + 1] * xj[1] + b[3 * r + 2] * xj[2];
+    }
+    y[3 * i] = s[0];
+    y[3 * i + 1] = s[1];
+    y[3 * i + 2] = s[2];
+  }
+}
+
+void apply_blocks(const std::vector<double>& B, int64_t n, const double* x, double* y) {
+  for (int64_t i = 0; i < n; ++i) {
+    const double* b = &B[9 * i];
+    const double* xi = x + 3 * i;
+    for (int r = 0; r < 3; ++r) y[3 * i + r] = b[3 * r] * xi[0] + b[3 * r + 1] * xi[1] + b[3 * r + 2] * xi[2];
+  }
+}
+
+double dot(int64_t m, const double* x, const double* y) {
+  double s = 0;
+  for (int64_t i = 0; i < m; ++i) s += x[i] * y[i];
+  return s;
+}
+
+double nrm2(int64_t m, const double* x) { return std::sqrt(dot(m, x, x)); }
+
+// ------------------------------------------------------ V-cycle (O7, O9, Sec. 3)
+// Multigrid = smoothing + coarse grid correction; damped block Jacobi with
+// nu_pre / nu_post sweeps, restriction P^T, prolongation P, exact solve at the
+// coarsest level.
+void vcycle(const Hier& H, size_t l, const double* b, double* x) {
+  const Level& L = H.lv[l];
+  const int64_t n = L.A.n, m = 3 * n;
+  if (l + 1 == H.lv.size()) {
+    std::copy(b, b + m, x);
+    lu_solve(H.nd, H.lu, H.piv, x);
+    return;
+  }
+  std::vector<double> r(m), t(m);
+  std::fill(x, x + m, 0.0);
+  for (int s = 0; s < H.o.nu_pre; ++s) {  // x += omega D^{-1} (b - A x)
+    spmv(L.A, x, t.data());
+    for (int64_t i = 0; i < m; ++i) r[i] = b[i] - t[i];
+    apply_blocks(L.dinv, n, r.data(), t.data());
+    for (int64_t i = 0; i < m; ++i) x[i] += H.omega * t[i];
+  }
+  spmv(L.A, x, t.data());
+  for (int64_t i = 0; i < m; ++i) r[i] = b[i] - t[i];
+  const int64_t nc = L.nc;
+  std::vector<double> bc(3 * nc, 0.0), xc(3 * nc, 0.0);
+  for (int64_t i = 0; i < n; ++i)  // restriction: P^T r
+    for (int c = 0; c < 3; ++c) bc[3 * (int64_t)L.agg[i] + c] += r[3 * i + c];
+  vcycle(H, l + 1, bc.data(), xc.data());
+  for (int64_t i = 0; i < n; ++i)  // prolongation: x += P e
+    for (int c = 0; c < 3; ++c) x[3 * i + c] += xc[3 * (int64_t)L.agg[i] + c];
+  for (int s = 0; s < H.o.nu_post; ++s) {
+    spmv(L.A, x, t.data());
+    for (int64_t i = 0; i < m; ++i) r[i] = b[i] - t[i];
+    apply_blocks(L.dinv, n, r.data(), t.data());
+    for (int64_t i = 0; i < m; ++i) x[i] += H.omega * t[i];
+  }
+}
+
+// Preconditioner B(v) = V(0, D^{-1} v) when the hierarchy is built on D^{-1} A.
+void precond(const Hier& H, const double* v, double* z) {
+  const int64_t m = 3 * H.A.n;
+  if (H.o.left_scale) {
+    std::vector<double> s(m);
+    apply_blocks(H.dinv0, H.A.n, v, s.data());
+    vcycle(H, 0, s.data(), z);
+  } else {
+    vcycle(H, 0, v, z);
+  }
+}
+
+// ------------------------------------------------------ FGMRES (O10)
+// Right-preconditioned flexible GMRES with modified Gram-Schmidt Arnoldi and
+// Givens rotations (Saad 1993); it replaces the GCR of Algorithm 1, to which it
+// is equivalent for a fixed linear preconditioner.
+int fgmres(const Hier& H, const double* b, const double* u0, double* u, llgo_stats* st) {
+  const int64_t m = 3 * H.A.n;
+  const int R = H.o.restart;
+  std::vector<double> V((size_t)(R + 1) * m), Z((size_t)R * m), w(m), r(m);
+  std::vector<double> Hm((size_t)(R + 1) * R, 0.0), cs(R), sn(R), g(R + 1);
+  std::copy(u0, u0 + m, u);
+  const double bnorm = nrm2(m, b);
+  const double target = H.o.rtol * bnorm;
+  int total = 0, restarts = 0;
+  double est = 0, truer = 0;
+  spmv(H.A, u, w.data());
+  for (int64_t i = 0; i < m; ++i) r[i] = b[i] - w[i];
+  double beta = nrm2(m, r.data());
+  truer = beta;
+  if (bnorm == 0.0 || beta <= target) {
+    if (st) *st = llgo_stats{0, 0, (int32_t)H.lv.size(), 1, bnorm > 0 ? beta / bnorm : 0, bnorm > 0 ? beta / bnorm : 0};
+    return LLGO_OK;
+  }
+  bool converged = false;
+  while (!converged && total < H.o.max_iters) {
+    for (int64_t i = 0; i < m; ++i) V[i] = r[i] / beta;
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j = 0;
+    for (; j < R && total < H.o.max_iters; ++j) {
+      double* vj = &V[(size_t)j * m];
+      double* zj = &Z[(size_t)j * m];
+      precond(H, vj, zj);
+      spmv(H.A, zj, w.data());
+      const double wnorm0 = nrm2(m, w.data());
+      for (int i = 0; i <= j; ++i) {
+        const double* vi = &V[(size_t)i * m];
+        const double hij = dot(m, vi, w.data());
+        Hm[(size_t)i * R + j] = hij;
+        for (int64_t q = 0; q < m; ++q) w[q] -= hij * vi[q];
+      }
+      const double hn = nrm2(m, w.data());
+      Hm[(size_t)(j + 1) * R + j] = hn;
+      const bool breakdown = hn <= 1e-14 * wnorm0;
+      if (!breakdown) {
+        double* vn = &V[(size_t)(j + 1) * m];
+        for (int64_t q = 0; q < m; ++q) vn[q] = w[q] / hn;
+      }
+      for (int i = 0; i < j; ++i) {  // previous rotations on column j
+        const double a = Hm[(size_t)i * R + j], c = Hm[(size_t)(i + 1) * R + j];
+        Hm[(size_t)i * R + j] = cs[i] * a + sn[i] * c;
+        Hm[(size_t)(i + 1) * R + j] = -sn[i] * a + cs[i] * c;
+      }
+      const double a = Hm[(size_t)j * R + j], c = Hm[(size_t)(j + 1) * R + j];
+      const double rho = std::hypot(a, c);
+      cs[j] = a / rho;
+      sn[j] = c / rho;
+      Hm[(size_t)j * R + j] = rho;
+      Hm[(size_t)(j + 1) * R + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++total;
+      est = std::fabs(g[j + 1]);
+      if (est <= target || breakdown) {
+        ++j;
+        break;
+      }
+    }
+    // y = H^{-1} g (upper triangular j x j); u += Z y
+    std::vector<double> y(j);
+    for (int i = j - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int k = i + 1; k < j; ++k) s -= Hm[(size_t)i * R + k] * y[k];
+      y[i] = s / Hm[(size_t)i * R + i];
+    }
+    for (int k = 0; k < j; ++k) {
+      const double* zk = &Z[(size_t)k * m];
+      for (int64_t q = 0; q < m; ++q) u[q] += y[k] * zk[q];
+    }
+    spmv(H.A, u, w.data());
+    for (int64_t i = 0; i < m; ++i) r[i] = b[i] - w[i];
+    beta = nrm2(m, r.data());
+    truer = beta;
+    converged = beta <= target;
+    if (!converged) ++restarts;
+  }
+  if (st) *st = llgo_stats{total, restarts, (int32_t)H.lv.size(), converged ? 1 : 0, est / bnorm, truer / bnorm};
+  return converged ? LLGO_OK : LLGO_ERR_NOT_CONVERGED;
+}
+
+// ------------------------------------------------------ GCR (Algorithm 1)
+// Preconditioned GCR: z_j from the preconditioner applied to the current
+// residual, c_j = A z_j orthogonalized against the previous c_i and
+// normalized, residual update along c_j, and the solution assembled once at
+// the end from Z (Gamma^{-1} a).  Restarted after `restart` iterations.
+int gcr(const Hier& H, const double* b, const double* u0, double* u, llgo_stats* st) {
+  const int64_t m = 3 * H.A.n;
+  const int R = H.o.restart;
+  std::vector<double> Z((size_t)R * m), C((size_t)R * m), r(m), w(m);
+  std::vector<double> G((size_t)R * R, 0.0), al(R);
+  std::copy(u0, u0 + m, u);
+  const double bnorm = nrm2(m, b);
+  const double target = H.o.rtol * bnorm;
+  spmv(H.A, u, w.data());
+  for (int64_t i = 0; i < m; ++i) r[i] = b[i] - w[i];
+  double rn = nrm2(m, r.data());
+  int total = 0, restarts = 0;
+  bool converged = bnorm == 0.0 || rn <= target;
+  double est = bnorm > 0 ? rn / bnorm : 0;
+  while (!converged && total < H.o.max_iters) {
+    int j = 0;
+    for (; j < R && total < H.o.max_iters; ++j) {
+      double* zj = &Z[(size_t)j * m];
+      double* cj = &C[(size_t)j * m];
+      precond(H, r.data(), zj);
+      spmv(H.A, zj, cj);
+      for (int i = 0; i < j; ++i) {
+        const double* ci = &C[(size_t)i * m];
+        const double gij = dot(m, ci, cj);
+        G[(size_t)i * R + j] = gij;
+        for (int64_t q = 0; q < m; ++q) cj[q] -= gij * ci[q];
+      }
+      const double gjj = nrm2(m, cj);
+      G[(size_t)j * R + j] = gjj;
+      for (int64_t q = 0; q < m; ++q) cj[q] /= gjj;
+      al[j] = dot(m, cj, r.data());
+      for (int64_t q = 0; q < m; ++q) r[q] -= al[j] * cj[q];
+      ++total;
+      rn = nrm2(m, r.data());
+      est = rn / bnorm;
+      if (rn < target) {
+        ++j;
+        break;
+      }
+    }
+    std::vector<double> y(j);  // Gamma y = a, Gamma upper triangular
+    for (int i = j - 1; i >= 0; --i) {
+      double s = al[i];
+      for (int k = i + 1; k < j; ++k) s -= G[(size_t)i * R + k] * y[k];
+      y[i] = s / G[(size_t)i * R + i];
+    }
+    for (int k = 0; k < j; ++k) {
+      const double* zk = &Z[(size_t)k * m];
+      for (int64_t q = 0; q < m; ++q) u[q] += y[k] * zk[q];
+    }
+    spmv(H.A, u, w.data());
+    for (int64_t i = 0; i < m; ++i) r[i] = b[i] - w[i];
+    rn = nrm2(m, r.data());
+    converged = rn <= target;
+    if (!converged) ++restarts;
+  }
+  if (st) *st = llgo_stats{total, restarts, (int32_t)H.lv.size(), converged ? 1 : 0, est, bnorm > 0 ? rn / bnorm : 0};
+  return converged ? LLGO_OK : LLGO_ERR_NOT_CONVERGED;
+}
+
+// ------------------------------------------------------ setup
+int build(Hier& H, const double* m_tilde, double alpha, double dt) {
+  const llgo_grid& g = H.g;
+  const llgo_opts& o = H.o;
+  H.omega = o.omega > 0 ? o.omega : (g.dim == 2 ? 4.0 / 5.0 : 6.0 / 7.0);
+  assemble(g, m_tilde, alpha, dt, H.A);
+  diag_inverses(H.A, H.dinv0);
+  H.lv.clear();
+  H.lv.emplace_back();
+  if (o.left_scale)
+    left_scale(H.A, H.dinv0, H.lv[0].A);
+  else
+    H.lv[0].A = H.A;
+  Graph G;
+  grid_graph(g, G);
+  for (int l = 0;; ++l) {
+    Level& L = H.lv[l];
+    diag_inverses(L.A, L.dinv);
+    const int64_t N = L.A.n;
+    if (N <= o.max_coarse || l + 1 >= o.max_levels) break;
+    // npass passes of pairwise matching; the composite aggregate map is the
+    // composition of the per-pass maps
+    std::vector<int32_t> agg(N);
+    for (int64_t i = 0; i < N; ++i) agg[i] = (int32_t)i;
+    Graph cur = G;
+    int64_t nc = N;
+    for (int p = 0; p < o.npass; ++p) {
+      std::vector<int32_t> a, mate;
+      int64_t c = 0;
+      const uint64_t salt = o.agg_salt ^ (((uint64_t)l << 8) | (uint64_t)p);
+      match_pass(cur, salt, o.beta_num, o.beta_den, a, mate, c);
+      Graph nxt;
+      coarse_graph(cur, a, c, nxt);
+      for (int64_t i = 0; i < N; ++i) agg[i] = a[agg[i]];
+      cur = nxt;
+      nc = c;
+    }
+    if ((double)nc > o.stagnation * (double)N) break;
+    L.agg = agg;
+    L.nc = nc;
+    Level next;
+    galerkin(L.A, L.agg, nc, next.A);
+    H.lv.push_back(std::move(next));
+    G = cur;
+  }
+  const Level& C = H.lv.back();
+  if (C.A.n > o.max_dense) return LLGO_ERR_UNSUPPORTED;
+  H.nd = 3 * C.A.n;
+  dense_from_bsr(C.A, H.lu);
+  lu_factor(H.nd, H.lu, H.piv);
+  return LLGO_OK;
+}
+
+bool opts_ok(const llgo_opts* o) {
+  return o && o->rtol >= 0 && o->restart >= 1 && o->max_iters >= 1 && o->nu_pre >= 0 &&
+         o->nu_post >= 0 && o->npass >= 1 && o->beta_num >= 0 && o->beta_den >= 1 &&
+         o->max_coarse >= 1 && o->max_levels >= 1 && o->max_dense >= 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+void llgo_default_opts(llgo_opts* o) {
+  o->rtol = 1e-10;
+  o->restart = 30;
+  o->max_iters = 1000;
+  o->nu_pre = 1;
+  o->nu_post = 1;
+  o->omega = 0.0;
+  o->npass = 2;
+  o->beta_num = 1;
+  o->beta_den = 4;
+  o->max_coarse = 256;
+  o->stagnation = 0.8;
+  o->max_levels = 40;
+  o->max_dense = 4096;
+  o->left_scale = 1;
+  o->project = 1;
+  o->x0_is_mn = 1;
+  o->agg_salt = 0;
+  o->krylov = 0;
+}
+
+uint64_t llgo_splitmix64(uint64_t x) { return splitmix64(x); }
+
+int llgo_match_pass(int64_t n, const int64_t* rp, const int32_t* ci, const int64_t* w,
+                    uint64_t salt, int32_t beta_num, int32_t beta_den, int32_t* agg,
+                    int32_t* mate, int64_t* nc) {
+  if (n < 0 || !rp || !agg || !nc || beta_den < 1) return LLGO_ERR_ARG;
+  Graph G;
+  G.n = n;
+  G.rp.assign(rp, rp + n + 1);
+  G.ci.assign(ci, ci + rp[n]);
+  G.w.assign(w, w + rp[n]);
+  std::vector<int32_t> a, mt;
+  match_pass(G, salt, beta_num, beta_den, a, mt, *nc);
+  std::copy(a.begin(), a.end(), agg);
+  if (mate) std::copy(mt.begin(), mt.end(), mate);
+  return LLGO_OK;
+}
+
+int llgo_galerkin(int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
+                  const int32_t* agg, int64_t nc, int64_t* nnzb_c, int64_t* rp_c, int32_t* ci_c,
+                  double* val_c) {
+  if (n < 0 || nc < 0 || !rp || !agg || !nnzb_c) return LLGO_ERR_ARG;
+  Bsr A;
+  A.n = n;
+  A.rp.assign(rp, rp + n + 1);
+  A.ci.assign(ci, ci + rp[n]);
+  A.v.assign(val, val + 9 * rp[n]);
+  std::vector<int32_t> ag(agg, agg + n);
+  Bsr C;
+  galerkin(A, ag, nc, C);
+  *nnzb_c = C.nnzb();
+  if (rp_c) std::copy(C.rp.begin(), C.rp.end(), rp_c);
+  if (ci_c) std::copy(C.ci.begin(), C.ci.end(), ci_c);
+  if (val_c) std::copy(C.v.begin(), C.v.end(), val_c);
+  return LLGO_OK;
+}
+
+int llgo_assemble_nnzb(const llgo_grid* g, int64_t* nnzb) {
+  if (!grid_ok(g) || !nnzb) return LLGO_ERR_ARG;
+  int64_t s = 0, nb[6];
+  for (int64_t p = 0; p < num_nodes(*g); ++p) s += 1 + neighbours(*g, p, nb);
+  *nnzb = s;
+  return LLGO_OK;
+}
+
+int llgo_assemble(const llgo_grid* g, const double* m_tilde, double alpha, double dt, int64_t* rp,
+                  int32_t* ci, double* val) {
+  if (!grid_ok(g) || !m_tilde || !rp || !ci || !val) return LLGO_ERR_ARG;
+  Bsr A;
+  assemble(*g, m_tilde, alpha, dt, A);
+  std::copy(A.rp.begin(), A.rp.end(), rp);
+  std::copy(A.ci.begin(), A.ci.end(), ci);
+  std::copy(A.v.begin(), A.v.end(), val);
+  return LLGO_OK;
+}
+
+void* llgo_setup(const llgo_grid* g, const llgo_opts* o, const double* m_tilde, double alpha,
+                 double dt, int* status) {
+  int s = LLGO_OK;
+  Hier* H = nullptr;
+  if (!grid_ok(g) || !opts_ok(o) || !m_tilde || !(dt > 0) || !(alpha >= 0) || !std::isfinite(dt) ||
+      !std::isfinite(alpha)) {
+    s = LLGO_ERR_ARG;
+  } else {
+    H = new Hier();
+    H->g = *g;
+    H->o = *o;
+    s = build(*H, m_tilde, alpha, dt);
+    if (s != LLGO_OK) {
+      delete H;
+      H = nullptr;
+    }
+  }
+  if (status) *status = s;
+  return H;
+}
+
+void llgo_free(void* h) { delete (Hier*)h; }
+
+int llgo_num_levels(void* h) { return h ? (int)((Hier*)h)->lv.size() : LLGO_ERR_ARG; }
+
+static const Bsr* level_bsr(Hier* H, int level) {
+  if (level == -1) return &H->A;
+  if (level < 0 || level >= (int)H->lv.size()) return nullptr;
+  return &H->lv[level].A;
+}
+
+int llgo_level_info(void* h, int level, int64_t* n, int64_t* nnzb) {
+  if (!h) return LLGO_ERR_ARG;
+  const Bsr* A = level_bsr((Hier*)h, level);
+  if (!A) return LLGO_ERR_ARG;
+  if (n) *n = A->n;
+  if (nnzb) *nnzb = A->nnzb();
+  return LLGO_OK;
+}
+
+int llgo_level_matrix(void* h, int level, int64_t* rp, int32_t* ci, double* val) {
+  if (!h) return LLGO_ERR_ARG;
+  const Bsr* A = level_bsr((Hier*)h, level);
+  if (!A) return LLGO_ERR_ARG;
+  if (rp) std::copy(A->rp.begin(), A->rp.end(), rp);
+  if (ci) std::copy(A->ci.begin(), A->ci.end(), ci);
+  if (val) std::copy(A->v.begin(), A->v.end(), val);
+  return LLGO_OK;
+}
+
+int llgo_level_dinv(void* h, int level, double* dinv) {
+  Hier* H = (Hier*)h;
+  if (!H || !dinv) return LLGO_ERR_ARG;
+  if (level == -1) {
+    std::copy(H->dinv0.begin(), H->dinv0.end(), dinv);
+    return LLGO_OK;
+  }
+  if (level < 0 || level >= (int)H->lv.size()) return LLGO_ERR_ARG;
+  std::copy(H->lv[level].dinv.begin(), H->lv[level].dinv.end(), dinv);
+  return LLGO_OK;
+}
+
+int llgo_level_agg(void* h, int level, int32_t* agg) {
+  Hier* H = (Hier*)h;
+  if (!H || !agg || level < 0 || level + 1 >= (int)H->lv.size()) return LLGO_ERR_ARG;
+  std::copy(H->lv[level].agg.begin(), H->lv[level].agg.end(), agg);
+  return LLGO_OK;
+}
+
+int llgo_apply_A(void* h, const double* x, double* y) {
+  if (!h || !x || !y) return LLGO_ERR_ARG;
+  spmv(((Hier*)h)->A, x, y);
+  return LLGO_OK;
+}
+
+int llgo_precond(void* h, const double* v, double* z) {
+  if (!h || !v || !z) return LLGO_ERR_ARG;
+  precond(*(Hier*)h, v, z);
+  return LLGO_OK;
+}
+
+int llgo_solve(void* h, const double* b, const double* u0, double* u, llgo_stats* st) {
+  if (!h || !b || !u0 || !u) return LLGO_ERR_ARG;
+  Hier* H = (Hier*)h;
+  return H->o.krylov == 1 ? gcr(*H, b, u0, u, st) : fgmres(*H, b, u0, u, st);
+}
+
+// One semi-implicit step (Sec. 2.1): m~ = m^n, b = m^n + dt F, solve, project
+// (Sec. 4.3).
+int llgo_step(const llgo_grid* g, const llgo_opts* o, const double* m_n, double alpha, double dt,
+              const double* F, double* m_np1, llgo_stats* st) {
+  if (!grid_ok(g) || !opts_ok(o) || !m_n || !m_np1) return LLGO_ERR_ARG;
+  const int64_t N = num_nodes(*g), m = 3 * N;
+  for (int64_t i = 0; i < m; ++i)
+    if (!std::isfinite(m_n[i])) return LLGO_ERR_NONFINITE;
+  int s = LLGO_OK;
+  Hier* H = (Hier*)llgo_setup(g, o, m_n, alpha, dt, &s);
+  if (!H) return s;
+  std::vector<double> b(m), u0(m, 0.0), u(m);
+  for (int64_t i = 0; i < m; ++i) b[i] = F ? m_n[i] + dt * F[i] : m_n[i];
+  if (o->x0_is_mn) std::copy(m_n, m_n + m, u0.begin());
+  s = llgo_solve(H, b.data(), u0.data(), u.data(), st);
+  delete H;
+  if (s != LLGO_OK && s != LLGO_ERR_NOT_CONVERGED) return s;
+  if (o->project) {
+    for (int64_t p = 0; p < N; ++p) {
+      const double* x = &u[3 * p];
+      const double nrm = std::sqrt((x[0] * x[0] + x[1] * x[1]) + x[2] * x[2]);
+      if (!(nrm > 0) || !std::isfinite(nrm)) return LLGO_ERR_NONFINITE;
+      for (int c = 0; c < 3; ++c) m_np1[3 * p + c] = x[c] / nrm;
+    }
+  } else {
+    std::copy(u.begin(), u.end(), m_np1);
+  }
+  return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+/*
+ * llgo.h -- FP64 CPU oracle for one semi-implicit BDF1 Landau-Lifshitz step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the checker that the HIP path is
+ * compared against.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it.  It shares no code, header, table or
+ * constant generator with the HIP library: everything here is written out
+ * plainly, single threaded, in double precision, built with -ffp-contract=off.
+ *
+ * What it computes (paper references are to sections, equations, tables):
+ *   - the damped semi-implicit BDF1 scheme of Sec. 2.1 (the component-wise
+ *     form of the damped linear system) on a cell-centred finite-difference
+ *     grid with homogeneous Neumann boundaries (Sec. 2.2 leaves the spatial
+ *     discretization open; mirrored ghosts are the reading taken here);
+ *   - the 3x3-block sparse operator A = I + dt * M_i * (L (x) I3);
+ *   - an aggregation AMG hierarchy (Sec. 3.1, Sec. 3.1.1): two passes of
+ *     pairwise matching per level, Boolean prolongation (eq. Pagg), Galerkin
+ *     coarse operators computed by block sums (eq. galerkin, eq. Ac_direct);
+ *   - one V-cycle (damped block Jacobi smoothing, exact dense LU at the
+ *     coarsest level, Sec. 3) as preconditioner of a restarted flexible GMRES,
+ *     or of the preconditioned GCR of Algorithm 1 (Sec. 3.1.2);
+ *   - the projection m <- m/|m| (Sec. 4.3).
+ *
+ * Layout: a field on the grid is double[N][3], node-major, node index
+ * p = i + nx*(j + ny*k).  BSR matrices: int64 row_ptr[n+1], int32 col[nnzb]
+ * (ascending within a row, diagonal always present), double val[nnzb][3][3]
+ * row-major inside each block.  All pointers are host pointers owned by the
+ * caller.  Functions return 0 on success and a negative code on failure.
+ */
+#ifndef LLGO_H
+#define LLGO_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LLGO_OK = 0,
+  LLGO_ERR_ARG = -1,          /* bad argument */
+  LLGO_ERR_UNSUPPORTED = -2,  /* coarsest level too large for the dense solve */
+  LLGO_ERR_NOT_CONVERGED = -5,
+  LLGO_ERR_NONFINITE = -6
+};
+
+typedef struct {
+  int32_t dim;   /* 2 or 3 */
+  int32_t n[3];  /* points per axis; n[2] == 1 when dim == 2 */
+  double h;      /* isotropic spacing */
+} llgo_grid;
+
+typedef struct {
+  double rtol;          /* stop when ||b - A u|| <= rtol ||b|| */
+  int32_t restart;      /* Krylov basis size per cycle */
+  int32_t max_iters;    /* total iterations */
+  int32_t nu_pre, nu_post;
+  double omega;         /* Jacobi damping; <= 0 selects 4/5 (2D) or 6/7 (3D) */
+  int32_t npass;        /* pairwise matching passes per level */
+  int32_t beta_num, beta_den;  /* strength threshold beta = num/den */
+  int32_t max_coarse;   /* stop coarsening at <= this many nodes */
+  double stagnation;    /* stop if N_{l+1} > stagnation * N_l */
+  int32_t max_levels;
+  int32_t max_dense;    /* largest coarsest level (nodes) for the dense LU */
+  int32_t left_scale;   /* build the hierarchy on D^{-1} A */
+  int32_t project;      /* normalize the solution node by node */
+  int32_t x0_is_mn;     /* initial guess m^n (else zero) */
+  uint64_t agg_salt;
+  int32_t krylov;       /* 0 = FGMRES, 1 = GCR (Algorithm 1) */
+} llgo_opts;
+
+typedef struct {
+  int32_t iters, restarts, levels, converged;
+  double relres_est, relres_true;
+} llgo_stats;
+
+void llgo_default_opts(llgo_opts* o);
+
+/* SplitMix64 finalizer applied to x + golden gamma (Steele, Lea, Flood 2014). */
+uint64_t llgo_splitmix64(uint64_t x);
+
+/* One pass of pairwise matching on an integer-weighted graph (CSR, no self
+ * loops, symmetric).  agg[n] receives aggregate ids, mate[n] the partner or -1,
+ * *nc the number of aggregates. */
+int llgo_match_pass(int64_t n, const int64_t* rp, const int32_t* ci, const int64_t* w,
+                    uint64_t salt, int32_t beta_num, int32_t beta_den,
+                    int32_t* agg, int32_t* mate, int64_t* nc);
+
+/* Galerkin product P^T A P of a 3x3 BSR matrix for Boolean P given by agg.
+ * Call with out arrays NULL to get *nnzb_c; then call again with storage. */
+int llgo_galerkin(int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
+                  const int32_t* agg, int64_t nc,
+                  int64_t* nnzb_c, int64_t* rp_c, int32_t* ci_c, double* val_c);
+
+/* Assemble the unscaled operator A for the frozen field m_tilde. */
+int llgo_assemble_nnzb(const llgo_grid* g, int64_t* nnzb);
+int llgo_assemble(const llgo_grid* g, const double* m_tilde, double alpha, double dt,
+                  int64_t* rp, int32_t* ci, double* val);
+
+/* Hierarchy handle: assembly, scaling, aggregation and Galerkin levels. */
+void* llgo_setup(const llgo_grid* g, const llgo_opts* o, const double* m_tilde,
+                 double alpha, double dt, int* status);
+void llgo_free(void* h);
+int llgo_num_levels(void* h);
+/* level -1 is the unscaled fine operator A; level 0.. are the hierarchy. */
+int llgo_level_info(void* h, int level, int64_t* n, int64_t* nnzb);
+int llgo_level_matrix(void* h, int level, int64_t* rp, int32_t* ci, double* val);
+int llgo_level_dinv(void* h, int level, double* dinv);
+int llgo_level_agg(void* h, int level, int32_t* agg);  /* map level -> level+1 */
+int llgo_apply_A(void* h, const double* x, double* y);
+int llgo_precond(void* h, const double* v, double* z);
+int llgo_solve(void* h, const double* b, const double* u0, double* u, llgo_stats* st);
+
+/* One full step: m_np1 = P(A^{-1} (m_n + dt F)), F may be NULL. */
+int llgo_step(const llgo_grid* g, const llgo_opts* o, const double* m_n, double alpha,
+              double dt, const double* F, double* m_np1, llgo_stats* st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
