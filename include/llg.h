@@ -1,0 +1,192 @@
+/*
+ * llg.h -- C ABI of the MI355X library for one semi-implicit BDF1 step of the
+ * damped Landau-Lifshitz equation, solved by aggregation-AMG-preconditioned
+ * flexible GMRES on the GPU.
+ *
+ * The operation (paper, Sec. 2.1 and Sec. 2.2): given the magnetization m^n on
+ * a uniform finite-difference grid with homogeneous Neumann boundaries, the
+ * damping alpha and the time step dt, compute m^{n+1} from
+ *
+ *     (I + dt m^n x Delta_h + alpha dt m^n x (m^n x Delta_h)) u = m^n + dt F,
+ *     m^{n+1} = u / |u|            (node by node; the projection of Sec. 4.3)
+ *
+ * where m^n is frozen in the operator (the semi-implicit linearization of
+ * eq. BDF1_linearized, extended to the damped scheme).  The linear system
+ * (eq. linear_system) is assembled as a 3x3-block sparse matrix and solved by
+ * FGMRES preconditioned with one V-cycle of aggregation AMG (Sec. 3, Sec. 3.1:
+ * two passes of pairwise matching per level, Boolean prolongation P of
+ * eq. Pagg, Galerkin coarse matrices P^T A P of eq. galerkin computed by the
+ * block sums of eq. Ac_direct).  All of it runs in HIP kernels on the GPU.
+ *
+ * Conventions for every entry point:
+ *   - Fields are double[N][3], node-major, contiguous, node p = i + nx*(j + ny*k)
+ *     (x fastest), N = nx*ny*nz; node p is the cell centre ((i+1/2)h, (j+1/2)h,
+ *     (k+1/2)h).  Pointers named d_* are DEVICE pointers on the context's
+ *     device; pointers named h_* are HOST pointers.  The caller owns every
+ *     buffer it passes; the library never frees or retains them past the call.
+ *   - Every call returns llg_status.  LLG_ERR_DEVICE carries a message that
+ *     llg_last_error() returns (thread-local).  Arguments are validated before
+ *     any device work; on an argument error nothing is launched.
+ *   - All device work of a context runs on the HIP stream given to
+ *     llg_create().  llg_step() returns after that work is complete.  One
+ *     context must not be used from two threads at once; distinct contexts are
+ *     independent and may run concurrently on distinct streams.
+ *   - Device memory: llg_create() and llg_step() allocate no device memory;
+ *     the caller lends one workspace of llg_workspace_bytes() bytes for the
+ *     context's lifetime.  llg_workspace_bytes() itself runs the (field
+ *     independent) aggregation once on the current device, using temporary
+ *     device memory that it frees before returning, and caches the result per
+ *     grid and options.
+ */
+#ifndef LLG_H
+#define LLG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LLG_MAX_LEVELS 40
+
+typedef enum {
+  LLG_OK = 0,
+  LLG_ERR_INVALID_ARG = 1,   /* null/misaligned pointer, bad size or option, aliasing */
+  LLG_ERR_UNSUPPORTED = 2,   /* boundary condition, or coarsest level above max_dense */
+  LLG_ERR_WORKSPACE = 3,     /* workspace smaller than llg_workspace_bytes() */
+  LLG_ERR_DEVICE = 4,        /* HIP runtime error or failed device-side consistency check */
+  LLG_ERR_NOT_CONVERGED = 5, /* max_iters reached; the output is still written */
+  LLG_ERR_NONFINITE = 6      /* non-finite m^n, or |u_i| = 0 / non-finite at projection */
+} llg_status;
+
+typedef enum { LLG_BC_NEUMANN = 0 } llg_bc;
+
+typedef enum {
+  LLG_PREC_FP64 = 0,     /* whole solve in FP64 */
+  LLG_PREC_FP32_AMG = 1  /* AMG hierarchy and V-cycle in FP32 inside FP64 FGMRES */
+} llg_precision;
+
+typedef struct {
+  int32_t dim;   /* 2 or 3 */
+  int32_t n[3];  /* points per axis, each >= 2; n[2] == 1 when dim == 2 */
+  double h;      /* isotropic grid spacing, > 0 (the unit square/cube: h = 1/n) */
+  int32_t bc;    /* llg_bc; only homogeneous Neumann */
+} llg_grid;
+
+typedef struct {
+  double rtol;          /* converged when ||b - A u||_2 <= rtol ||b||_2 (true residual) */
+  int32_t restart;      /* FGMRES basis size per cycle, 1..64 */
+  int32_t max_iters;    /* total FGMRES iterations */
+  int32_t precision;    /* llg_precision */
+  int32_t nu_pre, nu_post;  /* damped block-Jacobi sweeps, each 0..4 */
+  double omega;         /* Jacobi damping; <= 0 selects 4/5 (2D) or 6/7 (3D) */
+  int32_t npass;        /* pairwise matching passes per level, 1..3 */
+  int32_t beta_num, beta_den;  /* strong coupling: den * w >= num * max_w */
+  int32_t max_coarse;   /* stop coarsening at <= this many nodes */
+  double stagnation;    /* stop if N_{l+1} > stagnation * N_l */
+  int32_t max_levels;   /* <= LLG_MAX_LEVELS */
+  int32_t max_dense;    /* largest coarsest level (nodes) for the dense solve */
+  int32_t left_scale;   /* build the hierarchy on D^{-1} A (block-diagonal scaling) */
+  int32_t project;      /* normalize u node by node */
+  int32_t x0_is_mn;     /* initial guess m^n (else 0) */
+  uint64_t agg_salt;    /* salt of the hashed matching order */
+  int32_t rebuild_aggregates; /* 1: recompute the matching every step (default) */
+} llg_opts;
+
+typedef struct {
+  int32_t iters, restarts, levels, converged;
+  double relres_est, relres_true;
+  int64_t level_nodes[LLG_MAX_LEVELS];
+  int64_t level_nnzb[LLG_MAX_LEVELS];
+  double ms_setup;   /* assembly + hierarchy + coarsest factorization */
+  double ms_solve;   /* FGMRES */
+  double ms_total;
+  /* timing of one kernel class selected by llg_set_kernel_timing() */
+  double kernel_ms;
+  int64_t kernel_launches;
+} llg_stats;
+
+typedef struct llg_ctx llg_ctx;
+
+/* Kernel classes that llg_set_kernel_timing() can time with HIP events. */
+typedef enum {
+  LLG_KT_NONE = 0,
+  LLG_KT_OUTER_SPMV = 1,   /* w = A z, FP64 fine operator */
+  LLG_KT_SMOOTH = 2,       /* damped block-Jacobi sweeps, all levels */
+  LLG_KT_RESIDUAL = 3,     /* r = b - A x with restriction, all levels */
+  LLG_KT_ARNOLDI = 4,      /* multi-dot and update passes of the Gram-Schmidt step */
+  LLG_KT_GALERKIN = 5,     /* P^T A P values */
+  LLG_KT_ASSEMBLE = 6      /* fine operator assembly */
+} llg_kernel_class;
+
+/* Defaults: rtol 1e-10, restart 30, max_iters 1000, FP64, nu 1/1, omega by
+ * dimension, npass 2, beta 1/4, max_coarse 40, stagnation 0.8, max_levels 40,
+ * max_dense 512, left_scale 1, project 1, x0_is_mn 1, salt 0, rebuild 1. */
+void llg_default_opts(llg_opts* opts);
+
+/* Exact device bytes a context for (grid, opts) needs.  Runs the aggregation
+ * of the grid graph on the current device (field independent).  Errors:
+ * INVALID_ARG, UNSUPPORTED, DEVICE. */
+llg_status llg_workspace_bytes(const llg_grid* grid, const llg_opts* opts, size_t* bytes);
+
+/* Create a context on the current device.  d_workspace: device memory of at
+ * least llg_workspace_bytes() bytes, 256-byte aligned, lent until
+ * llg_destroy().  hip_stream: a hipStream_t (NULL = default stream).
+ * Builds the grid pattern and the aggregation hierarchy structure. */
+llg_status llg_create(const llg_grid* grid, const llg_opts* opts, void* d_workspace,
+                      size_t bytes, void* hip_stream, llg_ctx** out);
+
+/* One time step.  d_m_n: m^n (N x 3); d_m_nm1: m^{n-1}, accepted and unused by
+ * BDF1 (may be NULL); alpha >= 0 and dt > 0 finite; d_forcing: F (N x 3) or
+ * NULL, giving b = m^n + dt F; d_m_np1: output m^{n+1}, must not overlap
+ * d_m_n.  stats may be NULL.  NOT_CONVERGED still writes d_m_np1 (the
+ * projected last iterate) and stats. */
+llg_status llg_step(llg_ctx* ctx, const double* d_m_n, const double* d_m_nm1, double alpha,
+                    double dt, const double* d_forcing, double* d_m_np1, llg_stats* stats);
+
+/* Assemble the operator for the frozen field d_m_tilde and build the AMG
+ * hierarchy values (what llg_step does before the Krylov solve).  Used with
+ * the inspection calls below. */
+llg_status llg_setup(llg_ctx* ctx, const double* d_m_tilde, double alpha, double dt);
+
+/* Number of levels of the hierarchy, and the size of one level.  level -1 is
+ * the unscaled fine operator A; levels 0.. are the hierarchy (level 0 is
+ * D^{-1} A when left_scale is on). */
+llg_status llg_num_levels(llg_ctx* ctx, int32_t* levels);
+llg_status llg_level_info(llg_ctx* ctx, int32_t level, int64_t* n, int64_t* nnzb);
+
+/* Host copy of a level in BSR form: h_row_ptr[n+1], h_col[nnzb] ascending per
+ * row, h_vals[nnzb][3][3] row-major (FP32 levels are widened to double).
+ * cap_nnzb is the capacity of h_col (blocks).  Synchronizes the stream. */
+llg_status llg_get_level(llg_ctx* ctx, int32_t level, int32_t* h_row_ptr, int32_t* h_col,
+                         double* h_vals, int64_t cap_nnzb);
+
+/* Host copy of the aggregate map of `level` (node -> aggregate on level+1),
+ * n entries.  Synchronizes the stream. */
+llg_status llg_get_aggregates(llg_ctx* ctx, int32_t level, int32_t* h_out, int64_t n);
+
+/* z = B v: one V-cycle applied to D^{-1} v (the FGMRES preconditioner), both
+ * FP64 device vectors of 3N entries.  Requires a prior llg_setup/llg_step. */
+llg_status llg_apply_precond(llg_ctx* ctx, const double* d_v, double* d_z);
+
+/* y = A x with the unscaled FP64 fine operator.  Requires a prior setup. */
+llg_status llg_apply_A(llg_ctx* ctx, const double* d_x, double* d_y);
+
+/* Time every launch of one kernel class with HIP events on the context's
+ * stream; the totals are reported in llg_stats.kernel_ms/kernel_launches of
+ * each subsequent llg_step.  LLG_KT_NONE switches timing off. */
+llg_status llg_set_kernel_timing(llg_ctx* ctx, int32_t kernel_class);
+
+/* Bytes the context uses inside its workspace. */
+llg_status llg_ctx_bytes(llg_ctx* ctx, size_t* bytes);
+
+llg_status llg_destroy(llg_ctx* ctx);
+
+const char* llg_status_str(llg_status status);
+const char* llg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LLG_H */

@@ -687,10 +687,10 @@ void llgo_default_opts(llgo_opts* o) {
   o->npass = 2;
   o->beta_num = 1;
   o->beta_den = 4;
-  o->max_coarse = 256;
+  o->max_coarse = 40;
   o->stagnation = 0.8;
   o->max_levels = 40;
-  o->max_dense = 4096;
+  o->max_dense = 512;
   o->left_scale = 1;
   o->project = 1;
   o->x0_is_mn = 1;

@@ -1,0 +1,1060 @@
+// engine.hip -- host side of the library: workspace planning, hierarchy
+// construction, V-cycle, FGMRES driver, the time step and the C ABI.
+//
+// Planning.  The aggregation depends only on the grid graph (its edge weights
+// are integers, m-independent), so the sizes of every hierarchy level are a
+// function of the grid and the options.  llg_workspace_bytes() runs the
+// structure build once in PLAN mode: buffers are allocated as they are
+// requested, every size the host needs (aggregate counts, graph sizes, slot
+// counts, handshake rounds) is read back and logged.  A context replays the
+// same code in REPLAY mode: buffer requests are served from the caller's
+// workspace in the same order, logged sizes are used instead of read-backs,
+// and each logged value is re-checked on the device (a mismatch sets a flag
+// that turns into LLG_ERR_DEVICE).  The per-step rebuild therefore needs no
+// host round trip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/llg.h"
+#include "llg_internal.h"
+
+namespace llg {
+
+namespace {
+
+thread_local std::string g_err;
+
+void set_err(const std::string& s) { g_err = s; }
+
+struct DevError {
+  std::string msg;
+};
+
+#define HIPX(expr)                                                                                 \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess)                                                                          \
+      throw DevError{std::string(#expr) + ": " + hipGetErrorString(e_) + " @" + std::to_string(__LINE__)}; \
+  } while (0)
+
+inline void check_launch(int line) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw DevError{std::string("kernel launch: ") + hipGetErrorString(e) + " @" + std::to_string(line)};
+}
+#define LCHK() check_launch(__LINE__)
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+// device flag bits
+constexpr int32_t F_NONFINITE_IN = 1, F_SINGULAR = 2, F_PROJECT = 4, F_PLAN = 8;
+
+enum class Mode { PLAN, REPLAY };
+
+struct Plan {
+  std::vector<size_t> sizes;     // every buffer request, in order
+  std::vector<uint8_t> lazy;     // request is not materialized in PLAN mode
+  std::vector<int64_t> counts;   // every host-visible count, in order
+  size_t total = 0;
+  int status = LLG_OK;
+};
+
+// Buffer and count provider for the structure build (see file comment).
+struct Arena {
+  Mode mode;
+  Plan* plan;
+  bool first = true;              // REPLAY: first pass assigns addresses
+  std::vector<void*>* ptrs;       // REPLAY: addresses by request index
+  char* base = nullptr;
+  size_t cap = 0, off = 0;
+  size_t ri = 0, ci = 0;
+  std::vector<void*> owned;       // PLAN: temporary allocations
+  hipStream_t st = nullptr;
+  int32_t* flag = nullptr;        // REPLAY: mismatch flag
+  int32_t* hcount = nullptr;      // PLAN: pinned read-back slot
+
+  void* get(size_t bytes, bool lazy) {
+    bytes = align_up(bytes ? bytes : ALIGN);
+    if (mode == Mode::PLAN) {
+      plan->sizes.push_back(bytes);
+      plan->lazy.push_back(lazy ? 1 : 0);
+      plan->total += bytes;
+      if (lazy) return nullptr;
+      void* p = nullptr;
+      HIPX(hipMalloc(&p, bytes));
+      owned.push_back(p);
+      return p;
+    }
+    if (ri >= plan->sizes.size() || plan->sizes[ri] != bytes)
+      throw DevError{"workspace layout differs from the plan"};
+    void* p;
+    if (first) {
+      if (off + bytes > cap) throw DevError{"workspace overflow"};
+      p = base + off;
+      off += bytes;
+      ptrs->push_back(p);
+    } else {
+      p = (*ptrs)[ri];
+    }
+    ++ri;
+    return p;
+  }
+  template <typename X>
+  X* alloc(int64_t n) { return (X*)get((size_t)std::max<int64_t>(n, 1) * sizeof(X), false); }
+  template <typename X>
+  X* lazy(int64_t n) { return (X*)get((size_t)std::max<int64_t>(n, 1) * sizeof(X), true); }
+
+  // host-visible count stored at device address p
+  int64_t count(const int32_t* p) {
+    if (mode == Mode::PLAN) {
+      HIPX(hipMemcpyAsync(hcount, p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIPX(hipStreamSynchronize(st));
+      plan->counts.push_back(*hcount);
+      return *hcount;
+    }
+    if (ci >= plan->counts.size()) throw DevError{"count log exhausted"};
+    const int64_t v = plan->counts[ci++];
+    launch_check_eq(st, p, (int32_t)v, flag, F_PLAN);
+    LCHK();
+    return v;
+  }
+  void release() {
+    for (void* p : owned) (void)hipFree(p);
+    owned.clear();
+  }
+};
+
+struct Level {
+  Sell A;
+  int32_t* brp = nullptr;  // BSR pattern (CSR) of the level
+  int32_t* bci = nullptr;
+  int64_t nnzb = 0;
+  int32_t *grp = nullptr, *gci = nullptr, *gw = nullptr;  // integer graph
+  int64_t gnnz = 0;
+  int32_t *agg = nullptr, *mptr = nullptr, *mem = nullptr;  // to the next level
+  int64_t nc = 0;
+  void* val = nullptr;
+  void* dinv = nullptr;
+  bool unit = false;
+  void *b = nullptr, *x = nullptr, *r = nullptr, *e = nullptr, *xo = nullptr;
+};
+
+struct PlanKey {
+  std::tuple<int, int, int, int, int, int, int, int, double, int, int, uint64_t, int, int, int> k;
+  bool operator<(const PlanKey& o) const { return k < o.k; }
+};
+
+std::mutex g_plan_mu;
+std::map<PlanKey, std::shared_ptr<Plan>> g_plans;
+
+PlanKey plan_key(const llg_grid& g, const llg_opts& o) {
+  PlanKey k;
+  k.k = std::make_tuple(g.dim, g.n[0], g.n[1], g.n[2], o.npass, o.beta_num, o.beta_den, o.max_coarse,
+                        o.stagnation, o.max_levels, o.max_dense, o.agg_salt, o.precision, o.restart,
+                        o.left_scale);
+  return k;
+}
+
+}  // namespace
+}  // namespace llg
+
+struct llg_ctx {
+  llg_grid grid;
+  llg_opts opts;
+  int device = 0;
+  hipStream_t st = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0, used = 0;
+  std::shared_ptr<llg::Plan> plan;
+  std::vector<void*> ptrs;
+  int L = 0;
+  llg::Level lv[LLG_MAX_LEVELS];
+  double omega = 0;
+  int64_t N = 0;
+  // fine operator (FP64) and its inverse diagonal blocks
+  double* Aval = nullptr;
+  double* dinv0 = nullptr;
+  // coarsest
+  int64_t nd = 0;
+  double* dense = nullptr;
+  int32_t* piv = nullptr;
+  // Krylov
+  double *u = nullptr, *b = nullptr, *r = nullptr, *w = nullptr, *V = nullptr;
+  void* Z = nullptr;
+  int64_t ld = 0;
+  double* part = nullptr;
+  int64_t npart_vec = 0, npart_rows = 0;
+  llg::KrylovScalars ks{};
+  double* delta = nullptr;
+  int32_t* flags = nullptr;
+  int32_t* count = nullptr;
+  int32_t* scan_tmp = nullptr;
+  double* host = nullptr;     // pinned scalars
+  int32_t* hflags = nullptr;  // pinned flags
+  bool setup_done = false;
+  // timing of one kernel class
+  int timed = LLG_KT_NONE;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  double kernel_ms = 0;
+  int64_t launches = 0;
+};
+
+namespace llg {
+namespace {
+
+// ------------------------------------------------------------------ timing
+struct KTimer {
+  llg_ctx& c;
+  bool on;
+  KTimer(llg_ctx& cc, int cls) : c(cc), on(cc.timed == cls) {
+    if (!on) return;
+    if (c.ev_used + 2 > c.ev.size()) {
+      for (int k = 0; k < 2; ++k) {
+        hipEvent_t e;
+        HIPX(hipEventCreate(&e));
+        c.ev.push_back(e);
+      }
+    }
+    HIPX(hipEventRecord(c.ev[c.ev_used], c.st));
+  }
+  ~KTimer() {
+    if (!on) return;
+    (void)hipEventRecord(c.ev[c.ev_used + 1], c.st);
+    c.ev_used += 2;
+  }
+};
+
+// after a stream synchronization: add up the recorded kernel intervals
+void harvest(llg_ctx& c) {
+  for (size_t k = 0; k + 1 < c.ev_used; k += 2) {
+    float ms = 0;
+    HIPX(hipEventElapsedTime(&ms, c.ev[k], c.ev[k + 1]));
+    c.kernel_ms += ms;
+    c.launches += 1;
+  }
+  c.ev_used = 0;
+}
+
+void sync(llg_ctx& c) {
+  HIPX(hipStreamSynchronize(c.st));
+  harvest(c);
+}
+
+// ------------------------------------------------------------------ structure
+void build_sell(Arena& ar, hipStream_t st, Level& L, int64_t n, int64_t gnnz) {
+  L.A.n = n;
+  L.A.nslices = ceil_div(n, SL);
+  L.brp = ar.alloc<int32_t>(n + 1);
+  launch_pattern_rp(st, n, L.grp, L.brp);
+  LCHK();
+  L.nnzb = gnnz + n;
+  L.bci = ar.alloc<int32_t>(L.nnzb);
+  launch_pattern_cols(st, n, L.grp, L.gci, L.brp, L.bci);
+  LCHK();
+  L.A.sl_ptr = ar.alloc<int32_t>(L.A.nslices + 1);
+  launch_slice_width(st, n, L.brp, L.A.sl_ptr);
+  LCHK();
+}
+
+void finish_sell(Arena& ar, hipStream_t st, Level& L, int32_t* scan_tmp) {
+  launch_scan_excl(st, L.A.sl_ptr, L.A.sl_ptr, L.A.nslices, L.A.sl_ptr + L.A.nslices, scan_tmp);
+  LCHK();
+  L.A.nslots = ar.count(L.A.sl_ptr + L.A.nslices);
+  L.A.col = ar.alloc<int32_t>(L.A.nslots);
+  launch_sell_cols(st, L.A.n, L.brp, L.bci, L.A.sl_ptr, L.A.col);
+  LCHK();
+}
+
+// Grid pattern, then per level: npass handshake-matching passes on the
+// integer graph, composite aggregates, member lists, next-level graph and
+// block pattern.  Returns the number of levels.
+int build_structure(llg_ctx& c, Arena& ar) {
+  hipStream_t st = c.st;
+  const llg_grid& g = c.grid;
+  const llg_opts& o = c.opts;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const int64_t N = (int64_t)nx * ny * nz;
+  c.flags = ar.alloc<int32_t>(8);
+  c.count = ar.alloc<int32_t>(8);
+  c.scan_tmp = ar.alloc<int32_t>(scan_tmp_ints(N + 1) + 64);
+  if (ar.mode == Mode::PLAN || ar.first) {
+    launch_fill_i32(st, c.flags, 8, 0);
+    LCHK();
+  }
+  ar.flag = c.flags;
+  Level& L0 = c.lv[0];
+  L0.grp = ar.alloc<int32_t>(N + 1);
+  launch_grid_degree(st, nx, ny, nz, L0.grp);
+  LCHK();
+  launch_scan_excl(st, L0.grp, L0.grp, N, L0.grp + N, c.scan_tmp);
+  LCHK();
+  L0.gnnz = ar.count(L0.grp + N);
+  L0.gci = ar.alloc<int32_t>(L0.gnnz);
+  L0.gw = ar.alloc<int32_t>(L0.gnnz);
+  launch_grid_graph(st, nx, ny, nz, L0.grp, L0.gci, L0.gw);
+  LCHK();
+  build_sell(ar, st, L0, N, L0.gnnz);
+  finish_sell(ar, st, L0, c.scan_tmp);
+
+  int l = 0;
+  for (;; ++l) {
+    Level& L = c.lv[l];
+    const int64_t n = L.A.n;
+    if (n <= o.max_coarse || l + 1 >= o.max_levels) break;
+    int32_t* acc = ar.alloc<int32_t>(n);
+    int64_t cn = n, cg = L.gnnz;
+    int32_t *crp = L.grp, *cci = L.gci, *cw = L.gw;
+    for (int p = 0; p < o.npass; ++p) {
+      const uint64_t salt = o.agg_salt ^ (((uint64_t)l << 8) | (uint64_t)p);
+      int32_t* mx = ar.alloc<int32_t>(cn);
+      int32_t* mate = ar.alloc<int32_t>(cn);
+      int32_t* prop = ar.alloc<int32_t>(cn);
+      int32_t* id = ar.alloc<int32_t>(cn + 1);
+      int32_t* aggp = ar.alloc<int32_t>(cn);
+      int32_t* lead = ar.alloc<int32_t>(cn);
+      launch_row_max(st, cn, crp, cw, mx);
+      launch_fill_i32(st, mate, cn, -1);
+      LCHK();
+      // handshake rounds: PLAN runs until a round has no proposal and logs
+      // the number of rounds; REPLAY runs that many and checks the extra
+      // round proposes nothing
+      if (ar.mode == Mode::PLAN) {
+        int64_t rounds = 0;
+        for (;;) {
+          launch_fill_i32(st, c.count, 1, 0);
+          launch_propose(st, cn, crp, cci, cw, mx, mate, salt, o.beta_num, o.beta_den, prop, c.count);
+          LCHK();
+          HIPX(hipMemcpyAsync(ar.hcount, c.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+          HIPX(hipStreamSynchronize(st));
+          if (*ar.hcount == 0) break;
+          launch_accept(st, cn, prop, mate);
+          LCHK();
+          ++rounds;
+          if (rounds > cn + 2) throw DevError{"matching did not terminate"};
+        }
+        ar.plan->counts.push_back(rounds);
+      } else {
+        const int64_t rounds = ar.plan->counts[ar.ci++];
+        launch_fill_i32(st, c.count + 1, 1, 0);
+        for (int64_t r = 0; r < rounds; ++r) {
+          launch_propose(st, cn, crp, cci, cw, mx, mate, salt, o.beta_num, o.beta_den, prop, c.count + 1);
+          launch_accept(st, cn, prop, mate);
+        }
+        launch_fill_i32(st, c.count, 1, 0);
+        launch_propose(st, cn, crp, cci, cw, mx, mate, salt, o.beta_num, o.beta_den, prop, c.count);
+        launch_check_eq(st, c.count, 0, c.flags, F_PLAN);
+        LCHK();
+      }
+      launch_leader_flag(st, cn, mate, id);
+      launch_scan_excl(st, id, id, cn, id + cn, c.scan_tmp);
+      LCHK();
+      const int64_t nc = ar.count(id + cn);
+      launch_assign(st, cn, mate, id, aggp, lead);
+      int32_t* cnt = ar.alloc<int32_t>(nc + 1);
+      launch_cg_count(st, nc, lead, mate, crp, cnt);
+      launch_scan_excl(st, cnt, cnt, nc, cnt + nc, c.scan_tmp);
+      LCHK();
+      const int64_t ncand = ar.count(cnt + nc);
+      int32_t* cj = ar.alloc<int32_t>(ncand);
+      int32_t* cwt = ar.alloc<int32_t>(ncand);
+      int32_t* nrp = ar.alloc<int32_t>(nc + 1);
+      launch_cg_fill(st, nc, lead, mate, crp, cci, cw, aggp, cnt, cj, cwt, nrp);
+      launch_scan_excl(st, nrp, nrp, nc, nrp + nc, c.scan_tmp);
+      LCHK();
+      const int64_t ng = ar.count(nrp + nc);
+      int32_t* nci = ar.alloc<int32_t>(ng);
+      int32_t* nw = ar.alloc<int32_t>(ng);
+      launch_cg_copy(st, nc, cnt, cj, cwt, nrp, nci, nw);
+      launch_compose(st, n, acc, aggp, p == 0);
+      LCHK();
+      cn = nc;
+      cg = ng;
+      crp = nrp;
+      cci = nci;
+      cw = nw;
+    }
+    if ((double)cn > o.stagnation * (double)n) break;
+    // members of the composite aggregates, ascending
+    int32_t* mptr = ar.alloc<int32_t>(cn + 1);
+    int32_t* cursor = ar.alloc<int32_t>(cn);
+    int32_t* mem = ar.alloc<int32_t>(n);
+    launch_fill_i32(st, mptr, cn + 1, 0);
+    launch_fill_i32(st, cursor, cn, 0);
+    launch_member_count(st, n, acc, mptr);
+    launch_scan_excl(st, mptr, mptr, cn, mptr + cn, c.scan_tmp);
+    launch_member_fill(st, n, acc, mptr, cursor, mem);
+    launch_member_sort(st, cn, mptr, mem);
+    LCHK();
+    L.agg = acc;
+    L.mptr = mptr;
+    L.mem = mem;
+    L.nc = cn;
+    Level& Nx = c.lv[l + 1];
+    Nx.grp = crp;
+    Nx.gci = cci;
+    Nx.gw = cw;
+    Nx.gnnz = cg;
+    build_sell(ar, st, Nx, cn, cg);
+    finish_sell(ar, st, Nx, c.scan_tmp);
+  }
+  return l + 1;
+}
+
+// Values, vectors and Krylov storage (never materialized when planning).
+void allocate_numeric(llg_ctx& c, Arena& ar) {
+  const bool f32 = c.opts.precision == LLG_PREC_FP32_AMG;
+  const size_t ts = f32 ? sizeof(float) : sizeof(double);
+  const int R = c.opts.restart;
+  Level& L0 = c.lv[0];
+  c.Aval = ar.lazy<double>(9 * L0.A.nslots);
+  c.dinv0 = ar.lazy<double>(9 * L0.A.nslices * SL);
+  for (int l = 0; l < c.L; ++l) {
+    Level& L = c.lv[l];
+    const int64_t n = L.A.n;
+    L.val = ar.get(ts * 9 * L.A.nslots, true);
+    L.unit = l == 0 && c.opts.left_scale;
+    L.dinv = ar.get(ts * 9 * L.A.nslices * SL, true);
+    L.b = ar.get(ts * 3 * n, true);
+    L.x = ar.get(ts * 3 * n, true);
+    L.r = ar.get(ts * 3 * n, true);
+    L.e = ar.get(ts * 3 * n, true);
+    L.xo = ar.get(ts * 3 * n, true);
+  }
+  c.nd = 3 * c.lv[c.L - 1].A.n;
+  c.dense = ar.lazy<double>(c.nd * c.nd);
+  c.piv = (int32_t*)ar.get(sizeof(int32_t) * (c.nd + 2) + sizeof(double) * c.nd, true);
+  const int64_t m = 3 * c.N;
+  c.ld = (int64_t)(align_up((size_t)m * sizeof(double)) / sizeof(double));
+  c.u = ar.lazy<double>(m);
+  c.b = ar.lazy<double>(m);
+  c.r = ar.lazy<double>(m);
+  c.w = ar.lazy<double>(m);
+  c.V = ar.lazy<double>((R + 1) * c.ld);
+  c.Z = ar.get(ts * (size_t)R * c.ld, true);
+  c.npart_vec = red_blocks(m);
+  c.npart_rows = ceil_div(c.N, 256);
+  c.part = ar.lazy<double>(std::max<int64_t>((R + 2) * c.npart_vec, c.npart_rows) + 64);
+  c.ks.H = ar.lazy<double>((R + 1) * R);
+  c.ks.cs = ar.lazy<double>(R);
+  c.ks.sn = ar.lazy<double>(R);
+  c.ks.g = ar.lazy<double>(R + 1);
+  c.ks.hcol = ar.lazy<double>(R + 2);
+  c.ks.y = ar.lazy<double>(R);
+  c.ks.sc = ar.lazy<double>(16);
+  c.delta = ar.lazy<double>(R + 2);
+}
+
+bool grid_ok(const llg_grid* g) {
+  if (!g) return false;
+  if (g->dim != 2 && g->dim != 3) return false;
+  if (g->n[0] < 2 || g->n[1] < 2) return false;
+  if (g->dim == 2 && g->n[2] != 1) return false;
+  if (g->dim == 3 && g->n[2] < 2) return false;
+  if (!(g->h > 0) || !std::isfinite(g->h)) return false;
+  const double N = (double)g->n[0] * g->n[1] * g->n[2];
+  if (N * 7.0 > 2.0e9) return false;  // int32 block indices
+  return true;
+}
+
+bool opts_ok(const llg_opts* o) {
+  return o && o->rtol >= 0 && std::isfinite(o->rtol) && o->restart >= 1 && o->restart <= 32 &&
+         o->max_iters >= 1 && o->nu_pre >= 0 && o->nu_pre <= 4 && o->nu_post >= 0 && o->nu_post <= 4 &&
+         o->npass >= 1 && o->npass <= MAX_PASS && o->beta_num >= 0 && o->beta_den >= 1 &&
+         o->max_coarse >= 1 && o->max_levels >= 1 && o->max_levels <= LLG_MAX_LEVELS && o->max_dense >= 1 &&
+         (o->precision == LLG_PREC_FP64 || o->precision == LLG_PREC_FP32_AMG) && std::isfinite(o->omega) &&
+         std::isfinite(o->stagnation);
+}
+
+// Plan for (grid, opts): cached; computed on the current device.
+std::shared_ptr<Plan> get_plan(const llg_grid& g, const llg_opts& o) {
+  const PlanKey key = plan_key(g, o);
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) return it->second;
+  }
+  auto plan = std::make_shared<Plan>();
+  llg_ctx c;
+  c.grid = g;
+  c.opts = o;
+  c.N = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  HIPX(hipStreamCreate(&c.st));
+  Arena ar;
+  ar.mode = Mode::PLAN;
+  ar.plan = plan.get();
+  ar.st = c.st;
+  int32_t* hc = nullptr;
+  HIPX(hipHostMalloc((void**)&hc, sizeof(int32_t) * 4, hipHostMallocDefault));
+  ar.hcount = hc;
+  try {
+    c.L = build_structure(c, ar);
+    if (c.lv[c.L - 1].A.n > o.max_dense) plan->status = LLG_ERR_UNSUPPORTED;
+    allocate_numeric(c, ar);
+    HIPX(hipStreamSynchronize(c.st));
+  } catch (...) {
+    ar.release();
+    (void)hipHostFree(hc);
+    (void)hipStreamDestroy(c.st);
+    throw;
+  }
+  ar.release();
+  (void)hipHostFree(hc);
+  (void)hipStreamDestroy(c.st);
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  g_plans[key] = plan;
+  return plan;
+}
+
+// ------------------------------------------------------------------ setup
+template <typename T>
+void setup_values(llg_ctx& c, const double* m, double alpha, double dt, const double* F) {
+  hipStream_t st = c.st;
+  const llg_grid& g = c.grid;
+  if (c.opts.rebuild_aggregates) {
+    Arena ar;
+    ar.mode = Mode::REPLAY;
+    ar.plan = c.plan.get();
+    ar.first = false;
+    ar.ptrs = &c.ptrs;
+    ar.st = st;
+    (void)build_structure(c, ar);
+  }
+  Level& L0 = c.lv[0];
+  {
+    KTimer kt(c, LLG_KT_ASSEMBLE);
+    launch_assemble<T>(st, g.n[0], g.n[1], g.n[2], 1.0 / (g.h * g.h), dt, alpha, c.opts.left_scale,
+                       c.opts.x0_is_mn, m, F, L0.A, c.Aval, (T*)L0.val, c.dinv0, (T*)L0.dinv, c.b, c.u,
+                       c.flags);
+    LCHK();
+  }
+  for (int l = 0; l + 1 < c.L; ++l) {
+    Level& L = c.lv[l];
+    Level& Nx = c.lv[l + 1];
+    KTimer kt(c, LLG_KT_GALERKIN);
+    launch_galerkin<T>(st, Nx.A, (T*)Nx.val, (T*)Nx.dinv, L.mptr, L.mem, L.A, (const T*)L.val, L.agg);
+    LCHK();
+  }
+  Level& C = c.lv[c.L - 1];
+  launch_dense_scatter<T>(st, C.A, (const T*)C.val, c.dense);
+  launch_gauss_jordan(st, c.nd, c.dense, c.piv, c.flags);
+  LCHK();
+  c.setup_done = true;
+}
+
+// ------------------------------------------------------------------ V-cycle
+template <typename T>
+void vcycle(llg_ctx& c, int l, const T* b, T* out) {
+  hipStream_t st = c.st;
+  if (l == c.L - 1) {
+    launch_dense_apply<T>(st, c.nd, c.dense, b, out);
+    LCHK();
+    return;
+  }
+  Level& L = c.lv[l];
+  Level& Nx = c.lv[l + 1];
+  const llg_opts& o = c.opts;
+  const T* val = (const T*)L.val;
+  const T* dinv = (const T*)L.dinv;
+  const double om = c.omega;
+  T* X = (T*)L.x;
+  T* XO = (T*)L.xo;
+  // pre-smoothing from x = 0
+  int xmode = 2;
+  const T* xcur = nullptr;
+  {
+    KTimer kt(c, LLG_KT_SMOOTH);
+    for (int s = 0; s < o.nu_pre; ++s) {
+      if (s == 0) {
+        if (L.unit) {
+          xmode = 1;  // x = omega b, never stored
+        } else {
+          launch_smooth_first<T>(st, L.A, dinv, om, b, X);
+          xmode = 0;
+          xcur = X;
+        }
+      } else {
+        T* dst = (xcur == X) ? XO : X;
+        launch_post_smooth<T>(st, L.A, val, dinv, L.unit, xmode, om, b, xcur, nullptr, nullptr, dst);
+        xmode = 0;
+        xcur = dst;
+      }
+      LCHK();
+    }
+  }
+  {
+    KTimer kt(c, LLG_KT_RESIDUAL);
+    if (xmode == 2) {
+      launch_restrict<T>(st, L.nc, L.mptr, L.mem, b, (T*)Nx.b);
+    } else {
+      launch_residual<T>(st, L.A, val, xmode, om, b, xcur, (T*)L.r);
+      launch_restrict<T>(st, L.nc, L.mptr, L.mem, (const T*)L.r, (T*)Nx.b);
+    }
+    LCHK();
+  }
+  vcycle<T>(c, l + 1, (const T*)Nx.b, (T*)Nx.e);
+  const T* ec = (const T*)Nx.e;
+  KTimer kt(c, LLG_KT_SMOOTH);
+  if (o.nu_post == 0) {
+    launch_prolong<T>(st, L.A.n, xmode, om, b, xcur, L.agg, ec, out);
+    LCHK();
+    return;
+  }
+  // buffers for extra sweeps alternate between XO and X (X is free once the
+  // first post-smoothing sweep has read it)
+  for (int s = 0; s < o.nu_post; ++s) {
+    const bool last = s == o.nu_post - 1;
+    T* dst = last ? out : ((s % 2 == 0) ? XO : X);
+    if (s == 0) {
+      launch_post_smooth<T>(st, L.A, val, dinv, L.unit, xmode, om, b, xcur, L.agg, ec, dst);
+    } else {
+      launch_post_smooth<T>(st, L.A, val, dinv, L.unit, 0, om, b, xcur, nullptr, nullptr, dst);
+    }
+    LCHK();
+    xcur = dst;
+  }
+}
+
+template <typename T>
+void precond(llg_ctx& c, const double* v, T* z) {
+  Level& L0 = c.lv[0];
+  launch_scale_in<T>(c.st, c.N, c.dinv0, c.opts.left_scale, v, (T*)L0.b);
+  LCHK();
+  vcycle<T>(c, 0, (const T*)L0.b, z);
+}
+
+// ------------------------------------------------------------------ FGMRES
+struct SolveOut {
+  int iters = 0, restarts = 0;
+  bool converged = false;
+  double est = 0, truer = 0;
+};
+
+template <typename T>
+SolveOut fgmres(llg_ctx& c) {
+  hipStream_t st = c.st;
+  const int R = c.opts.restart;
+  const int64_t m = 3 * c.N;
+  Level& L0 = c.lv[0];
+  double* H = c.host;
+  T* Z = (T*)c.Z;
+  SolveOut so;
+  // ||b|| and r = b - A u
+  launch_norm_part(st, m, c.b, c.part);
+  launch_norm_finish_n(st, c.part, c.npart_vec, 2, c.ks.sc, H);
+  launch_resid_outer(st, L0.A, c.Aval, c.b, c.u, c.r, c.part);
+  launch_norm_finish_n(st, c.part, c.npart_rows, 0, c.ks.sc, H);
+  LCHK();
+  HIPX(hipMemcpyAsync(c.hflags, c.flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  sync(c);
+  if (*c.hflags & F_NONFINITE_IN) throw LLG_ERR_NONFINITE;
+  const double bnorm = H[2];
+  const double target = c.opts.rtol * bnorm;
+  double beta = H[0];
+  so.truer = bnorm > 0 ? beta / bnorm : 0;
+  so.est = so.truer;
+  if (bnorm == 0.0 || beta <= target) {
+    so.converged = true;
+    return so;
+  }
+  while (!so.converged && so.iters < c.opts.max_iters) {
+    launch_cycle_start(st, R, c.ks);
+    launch_scale_vec(st, m, c.r, c.ks.sc + 1, c.V);
+    LCHK();
+    int j = 0;
+    for (; j < R && so.iters < c.opts.max_iters; ++j) {
+      const double* vj = c.V + (int64_t)j * c.ld;
+      T* zj = Z + (int64_t)j * c.ld;
+      precond<T>(c, vj, zj);
+      {
+        KTimer kt(c, LLG_KT_OUTER_SPMV);
+        launch_spmv_outer<T>(st, L0.A, c.Aval, zj, c.w);
+        LCHK();
+      }
+      {
+        KTimer kt(c, LLG_KT_ARNOLDI);
+        // classical Gram-Schmidt, two passes
+        launch_mdot(st, m, j + 1, c.V, c.ld, c.w, c.part);
+        launch_dots_finish_n(st, c.part, c.npart_vec, j + 1, c.ks.hcol, c.delta, 0, c.ks.sc + 5);
+        launch_mupdate_dot(st, m, j + 1, c.V, c.ld, c.ks.hcol, c.w, c.part, 1);
+        launch_dots_finish_n(st, c.part, c.npart_vec, j + 1, c.ks.hcol, c.delta, 1, nullptr);
+        launch_mupdate_dot(st, m, j + 1, c.V, c.ld, c.delta, c.w, c.part, 0);
+        launch_arnoldi_finish_n(st, c.part, c.npart_vec, j, R, c.ks, H);
+        launch_scale_vec(st, m, c.w, c.ks.sc + 1, c.V + (int64_t)(j + 1) * c.ld);
+        LCHK();
+      }
+      sync(c);
+      ++so.iters;
+      so.est = bnorm > 0 ? H[3] / bnorm : 0;
+      if (H[3] <= target || H[6] != 0.0) {
+        ++j;
+        break;
+      }
+    }
+    launch_solve_y(st, j, R, c.ks);
+    launch_zy<T>(st, m, j, Z, c.ld, c.ks.y, c.u);
+    launch_resid_outer(st, L0.A, c.Aval, c.b, c.u, c.r, c.part);
+    launch_norm_finish_n(st, c.part, c.npart_rows, 0, c.ks.sc, H);
+    LCHK();
+    sync(c);
+    beta = H[0];
+    so.truer = beta / bnorm;
+    so.converged = beta <= target;
+    if (!so.converged) ++so.restarts;
+  }
+  return so;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+template <typename T>
+llg_status run_step(llg_ctx& c, const double* m_n, double alpha, double dt, const double* F, double* m_np1,
+                    llg_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  c.kernel_ms = 0;
+  c.launches = 0;
+  c.ev_used = 0;
+  launch_fill_i32(c.st, c.flags, 1, 0);
+  LCHK();
+  setup_values<T>(c, m_n, alpha, dt, F);
+  HIPX(hipStreamSynchronize(c.st));
+  const double t_setup = ms_since(t0);
+  SolveOut so = fgmres<T>(c);
+  launch_project(c.st, c.N, c.u, m_np1, c.opts.project, c.flags);
+  LCHK();
+  HIPX(hipMemcpyAsync(c.hflags, c.flags, sizeof(int32_t), hipMemcpyDeviceToHost, c.st));
+  sync(c);
+  const int32_t fl = *c.hflags;
+  if (stats) {
+    stats->iters = so.iters;
+    stats->restarts = so.restarts;
+    stats->levels = c.L;
+    stats->converged = so.converged ? 1 : 0;
+    stats->relres_est = so.est;
+    stats->relres_true = so.truer;
+    for (int l = 0; l < LLG_MAX_LEVELS; ++l) {
+      stats->level_nodes[l] = l < c.L ? c.lv[l].A.n : 0;
+      stats->level_nnzb[l] = l < c.L ? c.lv[l].nnzb : 0;
+    }
+    stats->ms_setup = t_setup;
+    stats->ms_total = ms_since(t0);
+    stats->ms_solve = stats->ms_total - t_setup;
+    stats->kernel_ms = c.kernel_ms;
+    stats->kernel_launches = c.launches;
+  }
+  if (fl & F_PLAN) {
+    set_err("device-side check of the hierarchy structure failed");
+    return LLG_ERR_DEVICE;
+  }
+  if (fl & F_NONFINITE_IN) return LLG_ERR_NONFINITE;
+  if (fl & F_SINGULAR) {
+    set_err("coarsest-level matrix is singular");
+    return LLG_ERR_DEVICE;
+  }
+  if (fl & F_PROJECT) return LLG_ERR_NONFINITE;
+  return so.converged ? LLG_OK : LLG_ERR_NOT_CONVERGED;
+}
+
+// Run f, mapping exceptions to status codes.
+template <typename Fn>
+llg_status guard(Fn f) {
+  try {
+    return f();
+  } catch (const DevError& e) {
+    set_err(e.msg);
+    return LLG_ERR_DEVICE;
+  } catch (llg_status s) {
+    return s;
+  } catch (const std::bad_alloc&) {
+    set_err("host allocation failed");
+    return LLG_ERR_DEVICE;
+  }
+}
+
+bool aligned8(const void* p) { return ((uintptr_t)p & 7) == 0; }
+
+}  // namespace
+}  // namespace llg
+
+using namespace llg;
+
+extern "C" {
+
+void llg_default_opts(llg_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->rtol = 1e-10;
+  o->restart = 30;
+  o->max_iters = 1000;
+  o->precision = LLG_PREC_FP64;
+  o->nu_pre = 1;
+  o->nu_post = 1;
+  o->omega = 0.0;
+  o->npass = 2;
+  o->beta_num = 1;
+  o->beta_den = 4;
+  o->max_coarse = 40;
+  o->stagnation = 0.8;
+  o->max_levels = 40;
+  o->max_dense = 512;
+  o->left_scale = 1;
+  o->project = 1;
+  o->x0_is_mn = 1;
+  o->agg_salt = 0;
+  o->rebuild_aggregates = 1;
+}
+
+llg_status llg_workspace_bytes(const llg_grid* grid, const llg_opts* opts, size_t* bytes) {
+  if (!grid_ok(grid) || !opts_ok(opts) || !bytes) return LLG_ERR_INVALID_ARG;
+  if (grid->bc != LLG_BC_NEUMANN) return LLG_ERR_UNSUPPORTED;
+  return guard([&]() -> llg_status {
+    auto plan = get_plan(*grid, *opts);
+    if (plan->status != LLG_OK) return (llg_status)plan->status;
+    *bytes = plan->total;
+    return LLG_OK;
+  });
+}
+
+llg_status llg_create(const llg_grid* grid, const llg_opts* opts, void* d_workspace, size_t bytes,
+                      void* hip_stream, llg_ctx** out) {
+  if (!grid_ok(grid) || !opts_ok(opts) || !out || !d_workspace) return LLG_ERR_INVALID_ARG;
+  if (((uintptr_t)d_workspace & (ALIGN - 1)) != 0) return LLG_ERR_INVALID_ARG;
+  if (grid->bc != LLG_BC_NEUMANN) return LLG_ERR_UNSUPPORTED;
+  *out = nullptr;
+  return guard([&]() -> llg_status {
+    auto plan = get_plan(*grid, *opts);
+    if (plan->status != LLG_OK) return (llg_status)plan->status;
+    if (bytes < plan->total) return LLG_ERR_WORKSPACE;
+    std::unique_ptr<llg_ctx> c(new llg_ctx());
+    c->grid = *grid;
+    c->opts = *opts;
+    c->plan = plan;
+    HIPX(hipGetDevice(&c->device));
+    c->st = (hipStream_t)hip_stream;
+    c->ws = (char*)d_workspace;
+    c->ws_bytes = bytes;
+    c->N = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
+    c->omega = opts->omega > 0 ? opts->omega : (grid->dim == 2 ? 4.0 / 5.0 : 6.0 / 7.0);
+    HIPX(hipHostMalloc((void**)&c->host, sizeof(double) * 16, hipHostMallocDefault));
+    HIPX(hipHostMalloc((void**)&c->hflags, sizeof(int32_t) * 4, hipHostMallocDefault));
+    Arena ar;
+    ar.mode = Mode::REPLAY;
+    ar.plan = plan.get();
+    ar.first = true;
+    ar.ptrs = &c->ptrs;
+    ar.base = c->ws;
+    ar.cap = bytes;
+    ar.st = c->st;
+    c->L = build_structure(*c, ar);
+    allocate_numeric(*c, ar);
+    c->used = ar.off;
+    HIPX(hipMemcpyAsync(c->hflags, c->flags, sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+    HIPX(hipStreamSynchronize(c->st));
+    if (*c->hflags & F_PLAN) {
+      set_err("hierarchy structure differs from the plan");
+      (void)hipHostFree(c->host);
+      (void)hipHostFree(c->hflags);
+      return LLG_ERR_DEVICE;
+    }
+    *out = c.release();
+    return LLG_OK;
+  });
+}
+
+static llg_status check_ctx(llg_ctx* c) {
+  if (!c) return LLG_ERR_INVALID_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device) {
+    set_err("context used on a device other than the one it was created on");
+    return LLG_ERR_INVALID_ARG;
+  }
+  return LLG_OK;
+}
+
+llg_status llg_setup(llg_ctx* ctx, const double* d_m_tilde, double alpha, double dt) {
+  llg_status s = check_ctx(ctx);
+  if (s != LLG_OK) return s;
+  if (!d_m_tilde || !aligned8(d_m_tilde) || !(dt > 0) || !std::isfinite(dt) || !(alpha >= 0) ||
+      !std::isfinite(alpha))
+    return LLG_ERR_INVALID_ARG;
+  return guard([&]() -> llg_status {
+    launch_fill_i32(ctx->st, ctx->flags, 1, 0);
+    if (ctx->opts.precision == LLG_PREC_FP32_AMG)
+      setup_values<float>(*ctx, d_m_tilde, alpha, dt, nullptr);
+    else
+      setup_values<double>(*ctx, d_m_tilde, alpha, dt, nullptr);
+    HIPX(hipMemcpyAsync(ctx->hflags, ctx->flags, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->st));
+    sync(*ctx);
+    if (*ctx->hflags & F_PLAN) return LLG_ERR_DEVICE;
+    if (*ctx->hflags & F_NONFINITE_IN) return LLG_ERR_NONFINITE;
+    return LLG_OK;
+  });
+}
+
+llg_status llg_step(llg_ctx* ctx, const double* d_m_n, const double* d_m_nm1, double alpha, double dt,
+                    const double* d_forcing, double* d_m_np1, llg_stats* stats) {
+  (void)d_m_nm1;
+  llg_status s = check_ctx(ctx);
+  if (s != LLG_OK) return s;
+  if (!d_m_n || !d_m_np1 || !aligned8(d_m_n) || !aligned8(d_m_np1) || (d_forcing && !aligned8(d_forcing)))
+    return LLG_ERR_INVALID_ARG;
+  if (!(dt > 0) || !std::isfinite(dt) || !(alpha >= 0) || !std::isfinite(alpha)) return LLG_ERR_INVALID_ARG;
+  const size_t fb = sizeof(double) * 3 * (size_t)ctx->N;
+  const char* a0 = (const char*)d_m_n;
+  const char* b0 = (const char*)d_m_np1;
+  if (a0 < b0 + fb && b0 < a0 + fb) return LLG_ERR_INVALID_ARG;
+  return guard([&]() -> llg_status {
+    if (ctx->opts.precision == LLG_PREC_FP32_AMG)
+      return run_step<float>(*ctx, d_m_n, alpha, dt, d_forcing, d_m_np1, stats);
+    return run_step<double>(*ctx, d_m_n, alpha, dt, d_forcing, d_m_np1, stats);
+  });
+}
+
+llg_status llg_num_levels(llg_ctx* ctx, int32_t* levels) {
+  llg_status s = check_ctx(ctx);
+  if (s != LLG_OK) return s;
+  if (!levels) return LLG_ERR_INVALID_ARG;
+  *levels = ctx->L;
+  return LLG_OK;
+}
+
+llg_status llg_level_info(llg_ctx* ctx, int32_t level, int64_t* n, int64_t* nnzb) {
+  llg_status s = check_ctx(ctx);
+  if (s != LLG_OK) return s;
+  if (level < -1 || level >= ctx->L) return LLG_ERR_INVALID_ARG;
+  const Level& L = ctx->lv[level < 0 ? 0 : level];
+  if (n) *n = L.A.n;
+  if (nnzb) *nnzb = L.nnzb;
+  return LLG_OK;
+}
+
+llg_status llg_get_level(llg_ctx* ctx, int32_t level, int32_t* h_row_ptr, int32_t* h_col, double* h_vals,
+                         int64_t cap_nnzb) {
+  llg_status s = check_ctx(ctx);
+  if (s != LLG_OK) return s;
+  if (level < -1 || level >= ctx->L || !h_row_ptr || !h_col || !h_vals) return LLG_ERR_INVALID_ARG;
+  const Level& L = ctx->lv[level < 0 ? 0 : level];
+  if (cap_nnzb < L.nnzb) return LLG_ERR_INVALID_ARG;
+  if (!ctx->setup_done) return LLG_ERR_INVALID_ARG;
+  return guard([&]() -> llg_status {
+    const bool f32 = level >= 0 && ctx->opts.precision == LLG_PREC_FP32_AMG;
+    const size_t ts = f32 ? 4 : 8;
+    const void* val = level < 0 ? (const void*)ctx->Aval : L.val;
+    std::vector<int32_t> sl(L.A.nslices + 1), col(L.A.nslots);
+    std::vector<char> v(ts * 9 * (size_t)L.A.nslots);
+    HIPX(hipStreamSynchronize(ctx->st));
+    HIPX(hipMemcpy(h_row_ptr, L.brp, sizeof(int32_t) * (L.A.n + 1), hipMemcpyDeviceToHost));
+    HIPX(hipMemcpy(sl.data(), L.A.sl_ptr, sizeof(int32_t) * sl.size(), hipMemcpyDeviceToHost));
+    HIPX(hipMemcpy(col.data(), L.A.col, sizeof(int32_t) * col.size(), hipMemcpyDeviceToHost));
+    HIPX(hipMemcpy(v.data(), val, v.size(), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < L.A.n; ++i) {
+      const int64_t sidx = i / SL, lane = i % SL;
+      const int64_t cb = sl[sidx];
+      const int64_t len = h_row_ptr[i + 1] - h_row_ptr[i];
+      for (int64_t t = 0; t < len; ++t) {
+        const int64_t o = h_row_ptr[i] + t;
+        h_col[o] = col[cb + t * SL + lane];
+        for (int e = 0; e < 9; ++e) {
+          const int64_t vi = cb * 9 + (t * 9 + e) * SL + lane;
+          h_vals[9 * o + e] = f32 ? (double)((const float*)v.data())[vi] : ((const double*)v.data())[vi];
+        }
+      }
+    }
+    return LLG_OK;
+  });
+}
+
+llg_status llg_get_aggregates(llg_ctx* ctx, int32_t level, int32_t* h_out, int64_t n) {
+  llg_status s = check_ctx(ctx);
+  if (s != LLG_OK) return s;
+  if (level < 0 || level + 1 >= ctx->L || !h_out || n != ctx->lv[level].A.n) return LLG_ERR_INVALID_ARG;
+  return guard([&]() -> llg_status {
+    HIPX(hipStreamSynchronize(ctx->st));
+    HIPX(hipMemcpy(h_out, ctx->lv[level].agg, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    return LLG_OK;
+  });
+}
+
+llg_status llg_apply_precond(llg_ctx* ctx, const double* d_v, double* d_z) {
+  llg_status s = check_ctx(ctx);
+  if (s != LLG_OK) return s;
+  if (!d_v || !d_z || !aligned8(d_v) || !aligned8(d_z) || !ctx->setup_done) return LLG_ERR_INVALID_ARG;
+  return guard([&]() -> llg_status {
+    if (ctx->opts.precision == LLG_PREC_FP32_AMG) {
+      float* z = (float*)ctx->Z;
+      precond<float>(*ctx, d_v, z);
+      launch_cast<float, double>(ctx->st, 3 * ctx->N, z, d_z);
+    } else {
+      precond<double>(*ctx, d_v, d_z);
+    }
+    LCHK();
+    sync(*ctx);
+    return LLG_OK;
+  });
+}
+
+llg_status llg_apply_A(llg_ctx* ctx, const double* d_x, double* d_y) {
+  llg_status s = check_ctx(ctx);
+  if (s != LLG_OK) return s;
+  if (!d_x || !d_y || !aligned8(d_x) || !aligned8(d_y) || !ctx->setup_done) return LLG_ERR_INVALID_ARG;
+  return guard([&]() -> llg_status {
+    launch_spmv_outer<double>(ctx->st, ctx->lv[0].A, ctx->Aval, d_x, d_y);
+    LCHK();
+    sync(*ctx);
+    return LLG_OK;
+  });
+}
+
+llg_status llg_set_kernel_timing(llg_ctx* ctx, int32_t kernel_class) {
+  llg_status s = check_ctx(ctx);
+  if (s != LLG_OK) return s;
+  if (kernel_class < LLG_KT_NONE || kernel_class > LLG_KT_ASSEMBLE) return LLG_ERR_INVALID_ARG;
+  ctx->timed = kernel_class;
+  return LLG_OK;
+}
+
+llg_status llg_ctx_bytes(llg_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return LLG_ERR_INVALID_ARG;
+  *bytes = ctx->used;
+  return LLG_OK;
+}
+
+llg_status llg_destroy(llg_ctx* ctx) {
+  if (!ctx) return LLG_ERR_INVALID_ARG;
+  (void)hipStreamSynchronize(ctx->st);
+  for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  (void)hipHostFree(ctx->host);
+  (void)hipHostFree(ctx->hflags);
+  delete ctx;
+  return LLG_OK;
+}
+
+const char* llg_status_str(llg_status s) {
+  switch (s) {
+    case LLG_OK: return "ok";
+    case LLG_ERR_INVALID_ARG: return "invalid argument";
+    case LLG_ERR_UNSUPPORTED: return "unsupported configuration";
+    case LLG_ERR_WORKSPACE: return "workspace too small";
+    case LLG_ERR_DEVICE: return "device error";
+    case LLG_ERR_NOT_CONVERGED: return "not converged";
+    case LLG_ERR_NONFINITE: return "non-finite value";
+  }
+  return "unknown status";
+}
+
+const char* llg_last_error(void) { return llg::g_err.c_str(); }
+
+}  // extern "C"

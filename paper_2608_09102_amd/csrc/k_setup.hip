@@ -1,0 +1,888 @@
+// k_setup.hip -- setup kernels: grid pattern, fine-operator assembly,
+// pairwise-matching aggregation, Galerkin coarse operators, dense coarsest
+// inverse.  Built with -ffp-contract=off: the assembly and Galerkin sums are
+// evaluated in the exact operation order stated in their comments.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "llg_internal.h"
+
+namespace llg {
+
+namespace {
+
+constexpr int TPB = 256;
+
+inline unsigned nblk(int64_t n, int t = TPB) { return (unsigned)ceil_div(n > 0 ? n : 1, t); }
+
+// ---------------------------------------------------------------- utilities
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Exclusive scan, three phases: per-block sums of 1024 items, a single-block
+// scan of the block sums, then per-block scans with the block offset added.
+constexpr int SCAN_T = 256, SCAN_ITEMS = 4, SCAN_CHUNK = SCAN_T * SCAN_ITEMS;
+
+__device__ inline int32_t block_excl_scan(int32_t v, int32_t* sh, int32_t* total) {
+  // inclusive Hillis-Steele scan over 256 threads in LDS
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < SCAN_T; off <<= 1) {
+    int32_t a = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += a;
+    __syncthreads();
+  }
+  int32_t incl = sh[t];
+  *total = sh[SCAN_T - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void k_scan_reduce(const int32_t* in, int64_t n, int32_t* bsum) {
+  __shared__ int32_t sh[SCAN_T];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
+  int32_t s = 0;
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + k;
+    if (i < n) s += in[i];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = SCAN_T / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = sh[0];
+}
+
+__global__ void k_scan_top(int32_t* bsum, int64_t nb, int32_t* total) {
+  __shared__ int32_t sh[SCAN_T];
+  __shared__ int32_t tot;
+  int32_t carry = 0;
+  for (int64_t base = 0; base < nb; base += SCAN_T) {
+    int64_t i = base + threadIdx.x;
+    int32_t v = i < nb ? bsum[i] : 0;
+    int32_t t;
+    int32_t ex = block_excl_scan(v, sh, &t);
+    if (threadIdx.x == 0) tot = t;
+    __syncthreads();
+    if (i < nb) bsum[i] = carry + ex;
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void k_scan_down(const int32_t* in, int32_t* out, int64_t n, const int32_t* bsum) {
+  __shared__ int32_t sh[SCAN_T];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int32_t v[SCAN_ITEMS];
+  int32_t s = 0;
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    v[k] = base + k < n ? in[base + k] : 0;
+    s += v[k];
+  }
+  int32_t tot;
+  int32_t ex = block_excl_scan(s, sh, &tot) + bsum[blockIdx.x];
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    if (base + k < n) out[base + k] = ex;
+    ex += v[k];
+  }
+}
+
+__global__ void k_check_eq(const int32_t* a, int32_t expect, int32_t* flag, int32_t bit) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && a[0] != expect) atomicOr(flag, bit);
+}
+
+// ---------------------------------------------------------------- grid graph
+// Neighbours of node p in ascending index order: k-1, j-1, i-1, i+1, j+1, k+1
+// (homogeneous Neumann: missing neighbours are simply absent).
+__device__ inline int grid_nbrs(int nx, int ny, int nz, int64_t p, int64_t* nb) {
+  const int64_t nxy = (int64_t)nx * ny;
+  const int64_t k = p / nxy, r = p - k * nxy;
+  const int64_t j = r / nx, i = r - j * nx;
+  int c = 0;
+  if (k > 0) nb[c++] = p - nxy;
+  if (j > 0) nb[c++] = p - nx;
+  if (i > 0) nb[c++] = p - 1;
+  if (i < nx - 1) nb[c++] = p + 1;
+  if (j < ny - 1) nb[c++] = p + nx;
+  if (k < nz - 1) nb[c++] = p + nxy;
+  return c;
+}
+
+__global__ void k_grid_degree(int nx, int ny, int nz, int32_t* deg) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = (int64_t)nx * ny * nz;
+  if (p >= N) return;
+  int64_t nb[6];
+  deg[p] = grid_nbrs(nx, ny, nz, p, nb);
+}
+
+__global__ void k_grid_graph(int nx, int ny, int nz, const int32_t* grp, int32_t* gci, int32_t* gw) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = (int64_t)nx * ny * nz;
+  if (p >= N) return;
+  int64_t nb[6];
+  int c = grid_nbrs(nx, ny, nz, p, nb);
+  int32_t o = grp[p];
+  for (int t = 0; t < c; ++t) {
+    gci[o + t] = (int32_t)nb[t];
+    gw[o + t] = 1;
+  }
+}
+
+// Block pattern of a level: the graph (no self loops) plus the diagonal.
+__global__ void k_pattern_rp(int64_t n, const int32_t* grp, int32_t* brp) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= n) brp[i] = grp[i] + (int32_t)i;
+}
+
+__global__ void k_pattern_cols(int64_t n, const int32_t* grp, const int32_t* gci, const int32_t* brp,
+                               int32_t* bci) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t o = brp[i];
+  bool placed = false;
+  for (int32_t k = grp[i]; k < grp[i + 1]; ++k) {
+    int32_t c = gci[k];
+    if (!placed && c > i) {
+      bci[o++] = (int32_t)i;
+      placed = true;
+    }
+    bci[o++] = c;
+  }
+  if (!placed) bci[o++] = (int32_t)i;
+}
+
+__global__ void k_slice_width(int64_t n, const int32_t* brp, int32_t* wslots) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ns = ceil_div(n, SL);
+  if (s >= ns) return;
+  int32_t w = 0;
+  for (int64_t i = s * SL; i < (s + 1) * SL && i < n; ++i) w = max(w, brp[i + 1] - brp[i]);
+  wslots[s] = w * SL;
+}
+
+__global__ void k_sell_cols(int64_t n, const int32_t* brp, const int32_t* bci, const int32_t* sl_ptr,
+                            int32_t* col) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ns = ceil_div(n, SL);
+  if (i >= ns * SL) return;
+  const int64_t s = i / SL;
+  const int l = (int)(i - s * SL);
+  const int32_t base = sl_ptr[s];
+  const int w = (sl_ptr[s + 1] - base) / SL;
+  const int len = i < n ? brp[i + 1] - brp[i] : 0;
+  for (int t = 0; t < w; ++t) col[base + t * SL + l] = t < len ? bci[brp[i] + t] : -1;
+}
+
+// ---------------------------------------------------------------- matching
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): mix of x + golden gamma.
+__device__ inline uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+__device__ inline uint64_t node_rank(int64_t v, uint64_t salt) {
+  return splitmix64((((uint64_t)v) << 32 | (uint64_t)v) ^ salt);
+}
+
+struct EdgeKey {
+  uint64_t rank;  // visiting rank of the first-visited endpoint
+  int32_t first;
+  int32_t w;
+  uint64_t h;
+  int32_t lo, hi;
+};
+
+// true when a precedes b in the matching order: earlier first-visited
+// endpoint, then larger weight, then larger hash, then smaller (lo, hi)
+__device__ inline bool key_before(const EdgeKey& a, const EdgeKey& b) {
+  if (a.rank != b.rank) return a.rank < b.rank;
+  if (a.first != b.first) return a.first < b.first;
+  if (a.w != b.w) return a.w > b.w;
+  if (a.h != b.h) return a.h > b.h;
+  if (a.lo != b.lo) return a.lo < b.lo;
+  return a.hi < b.hi;
+}
+
+__global__ void k_row_max(int64_t n, const int32_t* grp, const int32_t* gw, int32_t* mx) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t m = 0;
+  for (int32_t k = grp[i]; k < grp[i + 1]; ++k) m = max(m, gw[k]);
+  mx[i] = m;
+}
+
+// Handshake round: every free node proposes its best available edge (both
+// endpoints free, strong for the first-visited endpoint).
+__global__ void k_propose(int64_t n, const int32_t* grp, const int32_t* gci, const int32_t* gw,
+                          const int32_t* mx, const int32_t* mate, uint64_t salt, int32_t bnum,
+                          int32_t bden, int32_t* prop, int32_t* count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool proposed = false;
+  if (i < n) {
+    int32_t best = -1;
+    if (mate[i] < 0) {
+      const uint64_t ri = node_rank(i, salt);
+      EdgeKey bk{};
+      for (int32_t k = grp[i]; k < grp[i + 1]; ++k) {
+        const int32_t j = gci[k];
+        if (mate[j] >= 0) continue;
+        const int32_t w = gw[k];
+        const uint64_t rj = node_rank(j, salt);
+        const bool ifirst = ri != rj ? ri < rj : i < j;
+        const int32_t f = ifirst ? (int32_t)i : j;
+        if ((int64_t)bden * w < (int64_t)bnum * mx[f]) continue;
+        EdgeKey e;
+        e.rank = ifirst ? ri : rj;
+        e.first = f;
+        e.w = w;
+        e.lo = (int32_t)min((int64_t)j, i);
+        e.hi = (int32_t)max((int64_t)j, i);
+        e.h = splitmix64(((((uint64_t)e.lo) << 32) | (uint64_t)e.hi) ^ salt);
+        if (best < 0 || key_before(e, bk)) {
+          bk = e;
+          best = j;
+        }
+      }
+    }
+    prop[i] = best;
+    proposed = best >= 0;
+  }
+  // one atomic per wavefront
+  unsigned long long ballot = __ballot(proposed);
+  if ((threadIdx.x & 63) == 0 && ballot) atomicAdd(count, (int32_t)__popcll(ballot));
+}
+
+__global__ void k_accept(int64_t n, const int32_t* prop, int32_t* mate) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t p = prop[i];
+  if (p >= 0 && prop[p] == (int32_t)i) mate[i] = p;
+}
+
+__global__ void k_leader_flag(int64_t n, const int32_t* mate, int32_t* flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t m = mate[i];
+  flag[i] = (m < 0 || (int32_t)i < m) ? 1 : 0;
+}
+
+// Aggregates are numbered by their smallest member (ascending scan order).
+__global__ void k_assign(int64_t n, const int32_t* mate, const int32_t* id, int32_t* agg,
+                         int32_t* lead) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t m = mate[i];
+  const bool leader = m < 0 || (int32_t)i < m;
+  const int32_t L = leader ? (int32_t)i : m;
+  const int32_t a = id[L];
+  agg[i] = a;
+  if (leader) lead[a] = (int32_t)i;
+}
+
+__global__ void k_cg_count(int64_t nc, const int32_t* lead, const int32_t* mate, const int32_t* grp,
+                           int32_t* cnt) {
+  int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int32_t a = lead[I], b = mate[a];
+  int32_t c = grp[a + 1] - grp[a];
+  if (b >= 0) c += grp[b + 1] - grp[b];
+  cnt[I] = c;
+}
+
+// Coarse graph row I: (agg(j), w) over the rows of the (one or two) members,
+// sorted by coarse column, duplicates summed, the diagonal dropped.
+__global__ void k_cg_fill(int64_t nc, const int32_t* lead, const int32_t* mate, const int32_t* grp,
+                          const int32_t* gci, const int32_t* gw, const int32_t* agg,
+                          const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt) {
+  int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int32_t a = lead[I], b = mate[a];
+  const int32_t o = cptr[I];
+  int32_t c = 0;
+  for (int mem = 0; mem < 2; ++mem) {
+    const int32_t v = mem == 0 ? a : b;
+    if (v < 0) break;
+    for (int32_t k = grp[v]; k < grp[v + 1]; ++k) {
+      const int32_t J = agg[gci[k]];
+      const int32_t w = gw[k];
+      // insertion into the sorted prefix
+      int32_t q = c;
+      while (q > 0 && cj[o + q - 1] > J) {
+        cj[o + q] = cj[o + q - 1];
+        cw[o + q] = cw[o + q - 1];
+        --q;
+      }
+      cj[o + q] = J;
+      cw[o + q] = w;
+      ++c;
+    }
+  }
+  int32_t u = 0;
+  for (int32_t q = 0; q < c; ++q) {
+    const int32_t J = cj[o + q], w = cw[o + q];
+    if (J == (int32_t)I) continue;
+    if (u > 0 && cj[o + u - 1] == J) {
+      cw[o + u - 1] += w;
+    } else {
+      cj[o + u] = J;
+      cw[o + u] = w;
+      ++u;
+    }
+  }
+  ucnt[I] = u;
+}
+
+__global__ void k_cg_copy(int64_t nc, const int32_t* cptr, const int32_t* cj, const int32_t* cw,
+                          const int32_t* nrp, int32_t* nci, int32_t* nw) {
+  int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int32_t o = cptr[I], d = nrp[I], len = nrp[I + 1] - nrp[I];
+  for (int32_t q = 0; q < len; ++q) {
+    nci[d + q] = cj[o + q];
+    nw[d + q] = cw[o + q];
+  }
+}
+
+__global__ void k_compose(int64_t n, int32_t* acc, const int32_t* aggp, int first) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  acc[i] = first ? aggp[i] : aggp[acc[i]];
+}
+
+__global__ void k_member_count(int64_t n, const int32_t* agg, int32_t* cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(&cnt[agg[i]], 1);
+}
+
+__global__ void k_member_fill(int64_t n, const int32_t* agg, const int32_t* mptr, int32_t* cursor,
+                              int32_t* mem) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t a = agg[i];
+  const int32_t pos = atomicAdd(&cursor[a], 1);
+  mem[mptr[a] + pos] = (int32_t)i;
+}
+
+// Members of each aggregate in ascending order (at most 2^npass of them).
+__global__ void k_member_sort(int64_t nc, const int32_t* mptr, int32_t* mem) {
+  int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int32_t o = mptr[I], c = mptr[I + 1] - o;
+  for (int32_t a = 1; a < c; ++a) {
+    const int32_t v = mem[o + a];
+    int32_t q = a;
+    while (q > 0 && mem[o + q - 1] > v) {
+      mem[o + q] = mem[o + q - 1];
+      --q;
+    }
+    mem[o + q] = v;
+  }
+}
+
+// ---------------------------------------------------------------- assembly
+// Row r of M collects the coefficients of (Lap u1, Lap u2, Lap u3) in
+// equation r of the damped component-wise system (Sec. 2.1):
+//   M = [ -a(m2^2+m3^2)     -m3 + a m1 m2     m2 + a m1 m3 ]
+//       [  m3 + a m1 m2    -a(m1^2+m3^2)     -m1 + a m2 m3 ]
+//       [ -m2 + a m1 m3     m1 + a m2 m3    -a(m1^2+m2^2)  ]
+__device__ inline void block_M(double m1, double m2, double m3, double a, double* M) {
+  M[0] = -(a * (m2 * m2 + m3 * m3));
+  M[1] = -m3 + a * (m1 * m2);
+  M[2] = m2 + a * (m1 * m3);
+  M[3] = m3 + a * (m1 * m2);
+  M[4] = -(a * (m1 * m1 + m3 * m3));
+  M[5] = -m1 + a * (m2 * m3);
+  M[6] = -m2 + a * (m1 * m3);
+  M[7] = m1 + a * (m2 * m3);
+  M[8] = -(a * (m1 * m1 + m2 * m2));
+}
+
+// 3x3 inverse: adjugate times the reciprocal of the determinant (cofactor
+// expansion along the first row).
+__device__ inline void inv3(const double* D, double* R) {
+  const double a = D[0], b = D[1], c = D[2], d = D[3], e = D[4], f = D[5], g = D[6], h = D[7],
+               i = D[8];
+  double adj[9];
+  adj[0] = e * i - f * h;
+  adj[1] = c * h - b * i;
+  adj[2] = b * f - c * e;
+  adj[3] = f * g - d * i;
+  adj[4] = a * i - c * g;
+  adj[5] = c * d - a * f;
+  adj[6] = d * h - e * g;
+  adj[7] = b * g - a * h;
+  adj[8] = a * e - b * d;
+  const double det = (a * adj[0] + b * adj[3]) + c * adj[6];
+  const double rdet = 1.0 / det;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) R[k] = adj[k] * rdet;
+}
+
+// One thread per node.  A_pq = dt L_pq M_p (+ I on the diagonal) in FP64;
+// level-0 block D_p^{-1} A_pq with the diagonal stored as exactly I when
+// left scaling is on; D_p^{-1} kept for the preconditioner input; b and the
+// initial guess written alongside.
+template <typename T>
+__global__ void k_assemble(int nx, int ny, int nz, double inv_h2, double dt, double alpha,
+                           int left_scale, int x0_is_mn, const double* __restrict__ m,
+                           const double* __restrict__ F, const int32_t* __restrict__ sl_ptr,
+                           const int32_t* __restrict__ col, double* __restrict__ Aval,
+                           T* __restrict__ Lval, double* __restrict__ dinv0, T* __restrict__ ldinv,
+                           double* __restrict__ b, double* __restrict__ u, int32_t* flag) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = (int64_t)nx * ny * nz;
+  if (p >= N) return;
+  const double m1 = m[3 * p], m2 = m[3 * p + 1], m3 = m[3 * p + 2];
+  if (!isfinite(m1) || !isfinite(m2) || !isfinite(m3)) atomicOr(flag, 1);
+  int64_t nb[6];
+  const int deg = grid_nbrs(nx, ny, nz, p, nb);
+  double M[9];
+  block_M(m1, m2, m3, alpha, M);
+  const double s_off = dt * inv_h2;
+  const double s_diag = dt * (-(double)deg * inv_h2);
+  double D[9], Di[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    double v = s_diag * M[e];
+    if (e == 0 || e == 4 || e == 8) v = 1.0 + v;
+    D[e] = v;
+  }
+  inv3(D, Di);
+  const int64_t s = p / SL;
+  const int l = (int)(p - s * SL);
+  const int64_t cb = sl_ptr[s];
+  const int w = (int)((sl_ptr[s + 1] - cb) / SL);
+  for (int t = 0; t < w; ++t) {
+    const int32_t c = col[cb + (int64_t)t * SL + l];
+    if (c < 0) break;
+    double blk[9], sb[9];
+    if (c == p) {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) blk[e] = D[e];
+      if (left_scale) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) sb[e] = (e == 0 || e == 4 || e == 8) ? 1.0 : 0.0;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) sb[e] = D[e];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) blk[e] = s_off * M[e];
+      if (left_scale) {
+        // D^{-1} A_pq, each entry summed over k = 0, 1, 2 in order
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int q = 0; q < 3; ++q)
+            sb[3 * r + q] = (Di[3 * r] * blk[q] + Di[3 * r + 1] * blk[3 + q]) + Di[3 * r + 2] * blk[6 + q];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) sb[e] = blk[e];
+      }
+    }
+    const int64_t vb = cb * 9 + (int64_t)t * 9 * SL + l;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      Aval[vb + e * SL] = blk[e];
+      Lval[vb + e * SL] = (T)sb[e];
+    }
+  }
+  const int64_t db = s * 9 * SL + l;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    dinv0[db + e * SL] = Di[e];
+    if (!left_scale) ldinv[db + e * SL] = (T)Di[e];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double mc = m[3 * p + c];
+    b[3 * p + c] = F ? mc + dt * F[3 * p + c] : mc;
+    u[3 * p + c] = x0_is_mn ? mc : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------- Galerkin
+// One thread per coarse row I.  For every stored coarse block (I, J): sum,
+// over members i of aggregate I in ascending order and over the stored blocks
+// (i, j) of row i in ascending j with agg(j) = J, of the fine block a_ij
+// (eq. Ac_direct), accumulated in FP64 starting from zero.  The inverse of
+// the diagonal block is computed from the stored (rounded) block.
+template <typename T>
+__global__ void k_galerkin(int64_t nc, const int32_t* __restrict__ csl, const int32_t* __restrict__ ccol,
+                           T* __restrict__ cval, T* __restrict__ cdinv, const int32_t* __restrict__ mptr,
+                           const int32_t* __restrict__ mem, const int32_t* __restrict__ fsl,
+                           const int32_t* __restrict__ fcol, const T* __restrict__ fval,
+                           const int32_t* __restrict__ agg) {
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ns = ceil_div(nc, SL);
+  if (I >= ns * SL) return;
+  const int64_t s = I / SL;
+  const int l = (int)(I - s * SL);
+  const int64_t cb = csl[s];
+  const int w = (int)((csl[s + 1] - cb) / SL);
+  if (I >= nc) return;
+  const int32_t q0 = mptr[I], q1 = mptr[I + 1];
+  for (int t = 0; t < w; ++t) {
+    const int32_t J = ccol[cb + (int64_t)t * SL + l];
+    if (J < 0) break;
+    double acc[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) acc[e] = 0.0;
+    for (int32_t q = q0; q < q1; ++q) {
+      const int32_t i = mem[q];
+      const int64_t fs = i / SL;
+      const int fl = i - (int)(fs * SL);
+      const int64_t fb = fsl[fs];
+      const int fw = (int)((fsl[fs + 1] - fb) / SL);
+      for (int u = 0; u < fw; ++u) {
+        const int32_t j = fcol[fb + (int64_t)u * SL + fl];
+        if (j < 0) break;
+        if (agg[j] != J) continue;
+        const int64_t vb = fb * 9 + (int64_t)u * 9 * SL + fl;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) acc[e] += (double)fval[vb + e * SL];
+      }
+    }
+    const int64_t vb = cb * 9 + (int64_t)t * 9 * SL + l;
+    T st[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      st[e] = (T)acc[e];
+      cval[vb + e * SL] = st[e];
+    }
+    if (J == (int32_t)I) {
+      double D[9], Di[9];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) D[e] = (double)st[e];
+      inv3(D, Di);
+      const int64_t db = s * 9 * SL + l;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) cdinv[db + e * SL] = (T)Di[e];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- coarsest
+template <typename T>
+__global__ void k_dense_scatter(int64_t n, const int32_t* __restrict__ sl, const int32_t* __restrict__ col,
+                                const T* __restrict__ val, double* __restrict__ dense) {
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= n) return;
+  const int64_t s = I / SL;
+  const int l = (int)(I - s * SL);
+  const int64_t cb = sl[s];
+  const int w = (int)((sl[s + 1] - cb) / SL);
+  const int64_t nd = 3 * n;
+  for (int t = 0; t < w; ++t) {
+    const int32_t J = col[cb + (int64_t)t * SL + l];
+    if (J < 0) break;
+    const int64_t vb = cb * 9 + (int64_t)t * 9 * SL + l;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) dense[(3 * I + r) * nd + 3 * J + c] = (double)val[vb + (3 * r + c) * SL];
+  }
+}
+
+// In-place Gauss-Jordan inversion with partial pivoting (first largest
+// magnitude in the pivot column), one workgroup.  Row interchanges are undone
+// at the end by swapping columns in reverse order.  The matrix lives in LDS
+// when it fits (a != dense), else in global memory.
+constexpr int GJ_T = 1024;
+
+__device__ void gauss_jordan(int64_t nd, double* a, int32_t* piv, int32_t* flag, double* colk,
+                             double* redv, int32_t* redi) {
+  const int t = threadIdx.x;
+  for (int64_t k = 0; k < nd; ++k) {
+    // pivot search: first row of largest |a_ik|, i >= k
+    double best = -1.0;
+    int32_t bi = (int32_t)nd;
+    for (int64_t i = k + t; i < nd; i += GJ_T) {
+      const double v = fabs(a[i * nd + k]);
+      if (v > best) {
+        best = v;
+        bi = (int32_t)i;
+      }
+    }
+    redv[t] = best;
+    redi[t] = bi;
+    __syncthreads();
+    for (int off = GJ_T / 2; off > 0; off >>= 1) {
+      if (t < off) {
+        const double v2 = redv[t + off];
+        const int32_t i2 = redi[t + off];
+        if (v2 > redv[t] || (v2 == redv[t] && i2 < redi[t])) {
+          redv[t] = v2;
+          redi[t] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    // no usable pivot (zero or NaN column): keep row k and report singular
+    const int32_t p = (redi[0] < nd && redv[0] > 0.0) ? redi[0] : (int32_t)k;
+    if (t == 0) {
+      piv[k] = p;
+      if (!(redv[0] > 0.0)) atomicOr(flag, 2);
+    }
+    __syncthreads();
+    if (p != k) {
+      for (int64_t j = t; j < nd; j += GJ_T) {
+        const double x = a[k * nd + j];
+        a[k * nd + j] = a[(int64_t)p * nd + j];
+        a[(int64_t)p * nd + j] = x;
+      }
+      __syncthreads();
+    }
+    for (int64_t i = t; i < nd; i += GJ_T) colk[i] = a[i * nd + k];
+    __syncthreads();
+    const double pv = colk[k];
+    for (int64_t j = t; j < nd; j += GJ_T) a[k * nd + j] = (j == k ? 1.0 : a[k * nd + j]) / pv;
+    __syncthreads();
+    for (int64_t e = t; e < nd * nd; e += GJ_T) {
+      const int64_t i = e / nd, j = e - i * nd;
+      if (i == k) continue;
+      const double f = colk[i];
+      if (j == k)
+        a[e] = -f * a[k * nd + k];
+      else
+        a[e] -= f * a[k * nd + j];
+    }
+    __syncthreads();
+  }
+  for (int64_t k = nd - 1; k >= 0; --k) {
+    const int32_t p = piv[k];
+    if (p != k) {
+      for (int64_t i = t; i < nd; i += GJ_T) {
+        const double x = a[i * nd + k];
+        a[i * nd + k] = a[i * nd + p];
+        a[i * nd + p] = x;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+constexpr int64_t GJ_LDS_MAX = 136;  // 136^2 doubles + work arrays fit in 160 KB LDS
+
+__global__ void __launch_bounds__(GJ_T) k_gauss_jordan_lds(int64_t nd, double* dense, int32_t* piv,
+                                                           int32_t* flag) {
+  extern __shared__ double lds[];
+  double* a = lds;
+  double* colk = a + nd * nd;
+  double* redv = colk + nd;
+  int32_t* redi = (int32_t*)(redv + GJ_T);
+  for (int64_t e = threadIdx.x; e < nd * nd; e += GJ_T) a[e] = dense[e];
+  __syncthreads();
+  gauss_jordan(nd, a, piv, flag, colk, redv, redi);
+  for (int64_t e = threadIdx.x; e < nd * nd; e += GJ_T) dense[e] = a[e];
+}
+
+__global__ void __launch_bounds__(GJ_T) k_gauss_jordan_global(int64_t nd, double* dense, int32_t* piv,
+                                                              int32_t* flag, double* colk) {
+  __shared__ double redv[GJ_T];
+  __shared__ int32_t redi[GJ_T];
+  gauss_jordan(nd, dense, piv, flag, colk, redv, redi);
+}
+
+template <typename T>
+__global__ void k_dense_apply(int64_t nd, const double* __restrict__ inv, const T* __restrict__ b,
+                              T* __restrict__ x) {
+  extern __shared__ double sb[];
+  for (int64_t i = threadIdx.x; i < nd; i += blockDim.x) sb[i] = (double)b[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int64_t r = (int64_t)blockIdx.x * nw + wv; r < nd; r += (int64_t)gridDim.x * nw) {
+    double s = 0.0;
+    for (int64_t c = lane; c < nd; c += 64) s += inv[r * nd + c] * sb[c];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) x[r] = (T)s;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+void launch_fill_i32(hipStream_t st, int32_t* p, int64_t n, int32_t v) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n)), dim3(TPB), 0, st, p, n, v);
+}
+void launch_fill_f64(hipStream_t st, double* p, int64_t n, double v) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_f64, dim3(nblk(n)), dim3(TPB), 0, st, p, n, v);
+}
+
+int64_t scan_tmp_ints(int64_t n) { return ceil_div(n > 0 ? n : 1, SCAN_CHUNK) + 1; }
+
+void launch_scan_excl(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, int32_t* total,
+                      int32_t* tmp) {
+  const int64_t nb = ceil_div(n > 0 ? n : 1, SCAN_CHUNK);
+  if (n <= 0) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, st, total, 1, 0);
+    return;
+  }
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, st, in, n, tmp);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_T), 0, st, tmp, nb, total);
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_T), 0, st, in, out, n, tmp);
+}
+
+void launch_check_eq(hipStream_t st, const int32_t* a, int32_t expect, int32_t* flag, int32_t bit) {
+  hipLaunchKernelGGL(k_check_eq, dim3(1), dim3(64), 0, st, a, expect, flag, bit);
+}
+
+void launch_grid_degree(hipStream_t st, int nx, int ny, int nz, int32_t* deg) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  hipLaunchKernelGGL(k_grid_degree, dim3(nblk(N)), dim3(TPB), 0, st, nx, ny, nz, deg);
+}
+void launch_grid_graph(hipStream_t st, int nx, int ny, int nz, const int32_t* grp, int32_t* gci,
+                       int32_t* gw) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  hipLaunchKernelGGL(k_grid_graph, dim3(nblk(N)), dim3(TPB), 0, st, nx, ny, nz, grp, gci, gw);
+}
+void launch_pattern_rp(hipStream_t st, int64_t n, const int32_t* grp, int32_t* brp) {
+  hipLaunchKernelGGL(k_pattern_rp, dim3(nblk(n + 1)), dim3(TPB), 0, st, n, grp, brp);
+}
+void launch_pattern_cols(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci,
+                         const int32_t* brp, int32_t* bci) {
+  if (n > 0) hipLaunchKernelGGL(k_pattern_cols, dim3(nblk(n)), dim3(TPB), 0, st, n, grp, gci, brp, bci);
+}
+void launch_slice_width(hipStream_t st, int64_t n, const int32_t* brp, int32_t* wslots) {
+  const int64_t ns = ceil_div(n, SL);
+  if (ns > 0) hipLaunchKernelGGL(k_slice_width, dim3(nblk(ns)), dim3(TPB), 0, st, n, brp, wslots);
+}
+void launch_sell_cols(hipStream_t st, int64_t n, const int32_t* brp, const int32_t* bci,
+                      const int32_t* sl_ptr, int32_t* col) {
+  const int64_t ns = ceil_div(n, SL);
+  if (ns > 0)
+    hipLaunchKernelGGL(k_sell_cols, dim3(nblk(ns * SL)), dim3(TPB), 0, st, n, brp, bci, sl_ptr, col);
+}
+void launch_row_max(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gw, int32_t* mx) {
+  if (n > 0) hipLaunchKernelGGL(k_row_max, dim3(nblk(n)), dim3(TPB), 0, st, n, grp, gw, mx);
+}
+void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci,
+                    const int32_t* gw, const int32_t* mx, const int32_t* mate, uint64_t salt,
+                    int32_t bnum, int32_t bden, int32_t* prop, int32_t* count) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_propose, dim3(nblk(n)), dim3(TPB), 0, st, n, grp, gci, gw, mx, mate, salt,
+                       bnum, bden, prop, count);
+}
+void launch_accept(hipStream_t st, int64_t n, const int32_t* prop, int32_t* mate) {
+  if (n > 0) hipLaunchKernelGGL(k_accept, dim3(nblk(n)), dim3(TPB), 0, st, n, prop, mate);
+}
+void launch_leader_flag(hipStream_t st, int64_t n, const int32_t* mate, int32_t* flag) {
+  if (n > 0) hipLaunchKernelGGL(k_leader_flag, dim3(nblk(n)), dim3(TPB), 0, st, n, mate, flag);
+}
+void launch_assign(hipStream_t st, int64_t n, const int32_t* mate, const int32_t* id, int32_t* agg,
+                   int32_t* lead) {
+  if (n > 0) hipLaunchKernelGGL(k_assign, dim3(nblk(n)), dim3(TPB), 0, st, n, mate, id, agg, lead);
+}
+void launch_cg_count(hipStream_t st, int64_t nc, const int32_t* lead, const int32_t* mate,
+                     const int32_t* grp, int32_t* cnt) {
+  if (nc > 0) hipLaunchKernelGGL(k_cg_count, dim3(nblk(nc)), dim3(TPB), 0, st, nc, lead, mate, grp, cnt);
+}
+void launch_cg_fill(hipStream_t st, int64_t nc, const int32_t* lead, const int32_t* mate,
+                    const int32_t* grp, const int32_t* gci, const int32_t* gw, const int32_t* agg,
+                    const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt) {
+  if (nc > 0)
+    hipLaunchKernelGGL(k_cg_fill, dim3(nblk(nc)), dim3(TPB), 0, st, nc, lead, mate, grp, gci, gw, agg,
+                       cptr, cj, cw, ucnt);
+}
+void launch_cg_copy(hipStream_t st, int64_t nc, const int32_t* cptr, const int32_t* cj,
+                    const int32_t* cw, const int32_t* nrp, int32_t* nci, int32_t* nw) {
+  if (nc > 0)
+    hipLaunchKernelGGL(k_cg_copy, dim3(nblk(nc)), dim3(TPB), 0, st, nc, cptr, cj, cw, nrp, nci, nw);
+}
+void launch_compose(hipStream_t st, int64_t n, int32_t* acc, const int32_t* aggp, int first) {
+  if (n > 0) hipLaunchKernelGGL(k_compose, dim3(nblk(n)), dim3(TPB), 0, st, n, acc, aggp, first);
+}
+void launch_member_count(hipStream_t st, int64_t n, const int32_t* agg, int32_t* cnt) {
+  if (n > 0) hipLaunchKernelGGL(k_member_count, dim3(nblk(n)), dim3(TPB), 0, st, n, agg, cnt);
+}
+void launch_member_fill(hipStream_t st, int64_t n, const int32_t* agg, const int32_t* mptr,
+                        int32_t* cursor, int32_t* mem) {
+  if (n > 0) hipLaunchKernelGGL(k_member_fill, dim3(nblk(n)), dim3(TPB), 0, st, n, agg, mptr, cursor, mem);
+}
+void launch_member_sort(hipStream_t st, int64_t nc, const int32_t* mptr, int32_t* mem) {
+  if (nc > 0) hipLaunchKernelGGL(k_member_sort, dim3(nblk(nc)), dim3(TPB), 0, st, nc, mptr, mem);
+}
+
+template <typename T>
+void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, double dt, double alpha,
+                     int left_scale, int x0_is_mn, const double* m, const double* F, Sell A,
+                     double* Aval, T* Lval, double* dinv0, T* ldinv, double* b, double* u,
+                     int32_t* flag) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  hipLaunchKernelGGL((k_assemble<T>), dim3(nblk(N)), dim3(TPB), 0, st, nx, ny, nz, inv_h2, dt, alpha,
+                     left_scale, x0_is_mn, m, F, A.sl_ptr, A.col, Aval, Lval, dinv0, ldinv, b, u, flag);
+}
+template void launch_assemble<double>(hipStream_t, int, int, int, double, double, double, int, int,
+                                      const double*, const double*, Sell, double*, double*, double*,
+                                      double*, double*, double*, int32_t*);
+template void launch_assemble<float>(hipStream_t, int, int, int, double, double, double, int, int,
+                                     const double*, const double*, Sell, double*, float*, double*,
+                                     float*, double*, double*, int32_t*);
+
+template <typename T>
+void launch_galerkin(hipStream_t st, Sell C, T* cval, T* cdinv, const int32_t* mptr,
+                     const int32_t* mem, Sell F, const T* fval, const int32_t* agg) {
+  if (C.n <= 0) return;
+  hipLaunchKernelGGL((k_galerkin<T>), dim3(nblk(C.nslices * SL)), dim3(TPB), 0, st, C.n, C.sl_ptr,
+                     C.col, cval, cdinv, mptr, mem, F.sl_ptr, F.col, fval, agg);
+}
+template void launch_galerkin<double>(hipStream_t, Sell, double*, double*, const int32_t*,
+                                      const int32_t*, Sell, const double*, const int32_t*);
+template void launch_galerkin<float>(hipStream_t, Sell, float*, float*, const int32_t*,
+                                     const int32_t*, Sell, const float*, const int32_t*);
+
+template <typename T>
+void launch_dense_scatter(hipStream_t st, Sell C, const T* cval, double* dense) {
+  const int64_t nd = 3 * C.n;
+  launch_fill_f64(st, dense, nd * nd, 0.0);
+  if (C.n > 0)
+    hipLaunchKernelGGL((k_dense_scatter<T>), dim3(nblk(C.n)), dim3(TPB), 0, st, C.n, C.sl_ptr, C.col,
+                       cval, dense);
+}
+template void launch_dense_scatter<double>(hipStream_t, Sell, const double*, double*);
+template void launch_dense_scatter<float>(hipStream_t, Sell, const float*, double*);
+
+void launch_gauss_jordan(hipStream_t st, int64_t nd, double* dense, int32_t* piv, int32_t* flag) {
+  static int lds_ok = -1;
+  const size_t lds_max = (size_t)(GJ_LDS_MAX * GJ_LDS_MAX + GJ_LDS_MAX + GJ_T) * sizeof(double) +
+                         GJ_T * sizeof(int32_t);
+  if (lds_ok < 0)
+    lds_ok = hipFuncSetAttribute((const void*)k_gauss_jordan_lds,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max) == hipSuccess;
+  if (nd <= GJ_LDS_MAX && lds_ok) {
+    const size_t lds = (size_t)(nd * nd + nd + GJ_T) * sizeof(double) + GJ_T * sizeof(int32_t);
+    hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(1), dim3(GJ_T), lds, st, nd, dense, piv, flag);
+  } else {
+    // the pivot column is staged after the pivot indices: callers size the
+    // pivot buffer for nd ints plus nd doubles
+    double* colk = (double*)(piv + ((nd + 1) & ~(int64_t)1));
+    hipLaunchKernelGGL(k_gauss_jordan_global, dim3(1), dim3(GJ_T), 0, st, nd, dense, piv, flag, colk);
+  }
+}
+
+template <typename T>
+void launch_dense_apply(hipStream_t st, int64_t nd, const double* inv, const T* b, T* x) {
+  const int wpb = 16;
+  const unsigned nb = (unsigned)std::min<int64_t>(ceil_div(nd, wpb), 64);
+  hipLaunchKernelGGL((k_dense_apply<T>), dim3(nb), dim3(64 * wpb), nd * sizeof(double), st, nd, inv, b, x);
+}
+template void launch_dense_apply<double>(hipStream_t, int64_t, const double*, const double*, double*);
+template void launch_dense_apply<float>(hipStream_t, int64_t, const double*, const float*, float*);
+
+}  // namespace llg

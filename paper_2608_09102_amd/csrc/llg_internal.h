@@ -1,0 +1,166 @@
+// llg_internal.h -- internal declarations shared by the HIP translation units
+// of the library (device helpers, matrix views, kernel launchers).
+//
+// Matrix storage (every AMG level and the outer operator): 3x3-block sliced
+// ELL with 64-row slices, one wavefront per slice.  Slice s covers rows
+// 64s .. 64s+63 and has width W_s = max row length in the slice; its block
+// slots occupy sl_ptr[s] .. sl_ptr[s+1] = sl_ptr[s] + 64 W_s.  Slot t of row
+// 64s+l is at index sl_ptr[s] + 64 t + l in col[] (column or -1 after the
+// row's last block) and its nine values at 9 sl_ptr[s] + 64 (9 t + e) + l in
+// val[], so that the 64 lanes of a wavefront read 64 consecutive words for
+// every (slot, entry).  Columns of a row are ascending; the diagonal block is
+// always present.  Per-node 3x3 blocks (inverse diagonals) use the layout
+// [slice][9][64].  Vectors are [N][3], node-major.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace llg {
+
+constexpr int SL = 64;          // rows per slice (wavefront size)
+constexpr int MAX_PASS = 3;     // pairwise matching passes per level
+constexpr int RED_BLOCKS = 1024;  // fixed partial-sum count of grid reductions
+
+struct Sell {
+  int64_t n = 0;        // rows
+  int64_t nslices = 0;  // ceil(n / 64)
+  int64_t nslots = 0;   // sl_ptr[nslices]
+  int32_t* sl_ptr = nullptr;
+  int32_t* col = nullptr;
+};
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ----------------------------------------------------------------- launchers
+// Every launcher enqueues on `st` and returns nothing; launch errors are
+// collected by the caller with hipGetLastError().
+
+// integer utilities
+void launch_fill_i32(hipStream_t st, int32_t* p, int64_t n, int32_t v);
+void launch_fill_f64(hipStream_t st, double* p, int64_t n, double v);
+// exclusive scan of n int32 values (in may equal out); out[n] is NOT written,
+// the total goes to *total.  tmp needs scan_tmp_ints(n) ints.
+int64_t scan_tmp_ints(int64_t n);
+void launch_scan_excl(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, int32_t* total,
+                      int32_t* tmp);
+// device flag |= (a[0] != expect)
+void launch_check_eq(hipStream_t st, const int32_t* a, int32_t expect, int32_t* flag, int32_t bit);
+
+// grid graph and patterns
+void launch_grid_degree(hipStream_t st, int nx, int ny, int nz, int32_t* deg);
+void launch_grid_graph(hipStream_t st, int nx, int ny, int nz, const int32_t* grp, int32_t* gci,
+                       int32_t* gw);
+void launch_pattern_rp(hipStream_t st, int64_t n, const int32_t* grp, int32_t* brp);
+void launch_pattern_cols(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci,
+                         const int32_t* brp, int32_t* bci);
+void launch_slice_width(hipStream_t st, int64_t n, const int32_t* brp, int32_t* wslots);
+void launch_sell_cols(hipStream_t st, int64_t n, const int32_t* brp, const int32_t* bci,
+                      const int32_t* sl_ptr, int32_t* col);
+
+// pairwise matching (one pass)
+void launch_row_max(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gw, int32_t* mx);
+void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci,
+                    const int32_t* gw, const int32_t* mx, const int32_t* mate, uint64_t salt,
+                    int32_t bnum, int32_t bden, int32_t* prop, int32_t* count);
+void launch_accept(hipStream_t st, int64_t n, const int32_t* prop, int32_t* mate);
+void launch_leader_flag(hipStream_t st, int64_t n, const int32_t* mate, int32_t* flag);
+void launch_assign(hipStream_t st, int64_t n, const int32_t* mate, const int32_t* id, int32_t* agg,
+                   int32_t* lead);
+void launch_cg_count(hipStream_t st, int64_t nc, const int32_t* lead, const int32_t* mate,
+                     const int32_t* grp, int32_t* cnt);
+void launch_cg_fill(hipStream_t st, int64_t nc, const int32_t* lead, const int32_t* mate,
+                    const int32_t* grp, const int32_t* gci, const int32_t* gw, const int32_t* agg,
+                    const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt);
+void launch_cg_copy(hipStream_t st, int64_t nc, const int32_t* cptr, const int32_t* cj,
+                    const int32_t* cw, const int32_t* nrp, int32_t* nci, int32_t* nw);
+void launch_compose(hipStream_t st, int64_t n, int32_t* acc, const int32_t* aggp, int first);
+void launch_member_count(hipStream_t st, int64_t n, const int32_t* agg, int32_t* cnt);
+void launch_member_fill(hipStream_t st, int64_t n, const int32_t* agg, const int32_t* mptr,
+                        int32_t* cursor, int32_t* mem);
+void launch_member_sort(hipStream_t st, int64_t nc, const int32_t* mptr, int32_t* mem);
+
+// assembly of the fine operator (FP64 A) and the scaled level-0 operator
+template <typename T>
+void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, double dt, double alpha,
+                     int left_scale, int x0_is_mn, const double* m, const double* F, Sell A,
+                     double* Aval, T* Lval, double* dinv0, T* ldinv, double* b, double* u,
+                     int32_t* flag);
+
+// Galerkin block sums P^T A P and the inverse diagonal blocks of the result
+template <typename T>
+void launch_galerkin(hipStream_t st, Sell C, T* cval, T* cdinv, const int32_t* mptr,
+                     const int32_t* mem, Sell F, const T* fval, const int32_t* agg);
+
+// coarsest level: dense copy and in-place Gauss-Jordan inverse
+template <typename T>
+void launch_dense_scatter(hipStream_t st, Sell C, const T* cval, double* dense);
+void launch_gauss_jordan(hipStream_t st, int64_t nd, double* dense, int32_t* piv, int32_t* flag);
+template <typename T>
+void launch_dense_apply(hipStream_t st, int64_t nd, const double* inv, const T* b, T* x);
+
+// V-cycle level kernels.  xmode: 0 = x stored, 1 = x = omega b (unit
+// diagonal, first sweep from zero), 2 = x = 0.
+template <typename T>
+void launch_smooth_first(hipStream_t st, Sell A, const T* dinv, double omega, const T* b, T* x);
+template <typename T>
+void launch_residual(hipStream_t st, Sell A, const T* val, int xmode, double omega, const T* b,
+                     const T* x, T* r);
+template <typename T>
+void launch_restrict(hipStream_t st, int64_t nc, const int32_t* mptr, const int32_t* mem,
+                     const T* r, T* bc);
+// out = x' + omega D^{-1} (b - A x') with x' = xbase + P ec (ec may be NULL)
+template <typename T>
+void launch_post_smooth(hipStream_t st, Sell A, const T* val, const T* dinv, int unit, int xmode,
+                        double omega, const T* b, const T* x, const int32_t* agg, const T* ec,
+                        T* out);
+// out = xbase + P ec
+template <typename T>
+void launch_prolong(hipStream_t st, int64_t n, int xmode, double omega, const T* b, const T* x,
+                    const int32_t* agg, const T* ec, T* out);
+// b0 = D0^{-1} v (or v), cast to T
+template <typename T>
+void launch_scale_in(hipStream_t st, int64_t n, const double* dinv0, int left_scale, const double* v,
+                     T* b0);
+
+// outer Krylov kernels (FP64)
+template <typename TZ>
+void launch_spmv_outer(hipStream_t st, Sell A, const double* val, const TZ* z, double* w);
+void launch_resid_outer(hipStream_t st, Sell A, const double* val, const double* b, const double* u,
+                        double* r, double* part);
+void launch_norm_part(hipStream_t st, int64_t m, const double* x, double* part);
+void launch_mdot(hipStream_t st, int64_t m, int nv, const double* V, int64_t ldv, const double* w,
+                 double* part);
+void launch_mupdate_dot(hipStream_t st, int64_t m, int nv, const double* V, int64_t ldv,
+                        const double* h, double* w, double* part, int want_dots);
+void launch_scale_vec(hipStream_t st, int64_t m, const double* x, const double* s, double* y);
+template <typename TS, typename TD>
+void launch_cast(hipStream_t st, int64_t m, const TS* x, TD* y);
+template <typename TZ>
+void launch_zy(hipStream_t st, int64_t m, int k, const TZ* Z, int64_t ldz, const double* y, double* u);
+void launch_project(hipStream_t st, int64_t n, const double* u, double* out, int project,
+                    int32_t* flag);
+
+// FGMRES scalar work, one workgroup
+struct KrylovScalars {
+  double* H;      // (R+1) x R, row-major
+  double* cs;     // R
+  double* sn;     // R
+  double* g;      // R+1
+  double* hcol;   // R+1 (dots of the current pass)
+  double* y;      // R
+  double* sc;     // scalars: [0] beta, [1] 1/beta or 1/h, [2] bnorm, [3] est, [4] hn, [5] wnorm0
+};
+int64_t red_blocks(int64_t m);  // partial-sum count of the grid reductions over m doubles
+void launch_norm_finish_n(hipStream_t st, const double* part, int64_t nparts, int slot, double* sc,
+                          double* host);
+// sum the partial dots of one pass: entries i < nv go to hcol (assign) or to
+// delta and hcol (accumulate); entry nv (a squared norm) goes to *normsq
+void launch_dots_finish_n(hipStream_t st, const double* part, int64_t nparts, int nv, double* hcol,
+                          double* delta, int accumulate, double* normsq);
+void launch_arnoldi_finish_n(hipStream_t st, const double* part, int64_t nparts, int j, int R,
+                             KrylovScalars ks, double* host);
+void launch_cycle_start(hipStream_t st, int R, KrylovScalars ks);
+void launch_solve_y(hipStream_t st, int k, int R, KrylovScalars ks);
+
+}  // namespace llg

@@ -1,0 +1,226 @@
+"""GPU parity tests: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: assembly, aggregates, coarse patterns and FP64 Galerkin values are
+bit-exact (both sides evaluate them in the same stated order, without
+contraction); the V-cycle agrees to 1e-12 relative (the GPU inverts the
+coarsest matrix by Gauss-Jordan, the oracle by LU); m^{n+1} agrees to 1e-8 in
+max norm (|m| = 1, so absolute = relative), the tolerance the target states.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import llg_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    import paper_2608_09102_amd as llg
+    assert torch.cuda.is_available()
+    return llg
+
+
+def _cuda(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+CASES = [
+    # name, dim, n (per axis), h, alpha, dt, field
+    ("vortex64", 2, (64, 64, 1), 1 / 64, 0.1, 1e-3, "vortex"),
+    ("rect2d_37x23", 2, (37, 23, 1), 1 / 37, 0.05, 2e-3, "rough"),
+    ("box3d_9x7x5", 3, (9, 7, 5), 1 / 9, 1.0, 1e-2, "rough"),
+    ("cube3d_20", 3, (20, 20, 20), 1 / 20, 0.01, 5e-4, "rough"),
+    ("tiny2d_3x5", 2, (3, 5, 1), 1 / 3, 0.3, 1e-2, "rough"),
+]
+
+
+def _field(dim, n, kind, seed=7):
+    if kind == "vortex":
+        return I.vortex_field(n[0], seed=1)
+    rng = np.random.default_rng(seed)
+    m = rng.standard_normal((int(np.prod(n)), 3))
+    return m / np.linalg.norm(m, axis=1, keepdims=True)
+
+
+def _both(gpu, orc, dim, n, h, opts_kw=None, orc_kw=None):
+    opts_kw = opts_kw or {}
+    g_gpu = gpu.make_grid(dim, n, h)
+    g_orc = orc.make_grid(dim, n, h)
+    return (g_gpu, gpu.default_opts(**opts_kw), g_orc, orc.default_opts(**(orc_kw or opts_kw)))
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_setup_bitwise(gpu, orc, case):
+    name, dim, n, h, alpha, dt, kind = case
+    say("[setup_bitwise]", name)
+    m = _field(dim, n, kind)
+    gg, go, og, oo = _both(gpu, orc, dim, n, h)
+    S = gpu.Solver(gg, go)
+    assert S.setup(_cuda(m), alpha, dt) == gpu.OK
+    H = orc.Hierarchy(og, oo, m, alpha, dt)
+    assert S.num_levels == H.num_levels
+    for l in range(-1, H.num_levels):
+        rp, ci, val = S.level(l)
+        R = H.level(l)
+        assert np.array_equal(rp, R.rp), (name, l)
+        assert np.array_equal(ci, R.ci), (name, l)
+        assert np.array_equal(val, R.val), (name, l, np.abs(val - R.val).max())
+        if 0 <= l < H.num_levels - 1:
+            assert np.array_equal(S.aggregates(l), R.agg), (name, l)
+
+
+@pytest.mark.parametrize("case", CASES[:4], ids=[c[0] for c in CASES[:4]])
+def test_operator_and_vcycle(gpu, orc, case):
+    name, dim, n, h, alpha, dt, kind = case
+    say("[operator_and_vcycle]", name)
+    m = _field(dim, n, kind)
+    gg, go, og, oo = _both(gpu, orc, dim, n, h)
+    S = gpu.Solver(gg, go)
+    assert S.setup(_cuda(m), alpha, dt) == gpu.OK
+    H = orc.Hierarchy(og, oo, m, alpha, dt)
+    rng = np.random.default_rng(3)
+    for _ in range(2):
+        v = rng.standard_normal(m.shape)
+        y = S.apply_A(_cuda(v)).cpu().numpy()
+        yr = H.apply_A(v)
+        assert np.abs(y - yr).max() <= 1e-14 * np.abs(yr).max()
+        z = S.precond(_cuda(v)).cpu().numpy()
+        zr = H.precond(v)
+        assert np.abs(z - zr).max() <= 1e-12 * np.abs(zr).max(), np.abs(z - zr).max() / np.abs(zr).max()
+
+
+def test_step_vortex64_trajectory(gpu, orc):
+    """Ten steps of the 64x64 vortex workload, rtol 1e-10 on the GPU, 1e-12
+    in the oracle: every step within 1e-8, both from the same m^n and along
+    the two trajectories; aggregates identical every step."""
+    w = I.WORKLOADS["vortex64"]
+    say("[step_vortex64_trajectory]")
+    gg = gpu.make_grid(2, w.n)
+    og = orc.make_grid(2, w.n)
+    S = gpu.Solver(gg, gpu.default_opts(rtol=w.rtol))
+    oo = orc.default_opts(rtol=1e-12)
+    m_gpu = w.m0()
+    m_orc = m_gpu.copy()
+    for k in range(w.steps):
+        out, s, st = S.step(_cuda(m_gpu), w.alpha, w.dt)
+        assert s == gpu.OK and st.converged
+        g1 = out.cpu().numpy()
+        rc, o1, ost = orc.step(og, oo, m_gpu, w.alpha, w.dt)  # same m^n
+        assert rc == 0
+        d_single = np.abs(g1 - o1).max()
+        rc, o2, _ = orc.step(og, oo, m_orc, w.alpha, w.dt)
+        d_traj = np.abs(g1 - o2).max()
+        say("  step %d iters gpu %d orc %d  single %.2e  trajectory %.2e" % (k, st.iters, ost.iters, d_single, d_traj))
+        assert d_single <= 1e-8 and d_traj <= 1e-8
+        H = orc.Hierarchy(og, oo, m_gpu, w.alpha, w.dt)
+        for l in range(H.num_levels - 1):
+            assert np.array_equal(S.aggregates(l), H.level(l).agg)
+        m_gpu, m_orc = g1, o2
+
+
+@pytest.mark.parametrize("alpha", [0.01, 0.1, 1.0])
+def test_fp32_amg_small_3d(gpu, orc, alpha):
+    """FP32 hierarchy inside FP64 FGMRES reaches the FP64 outer tolerance."""
+    dim, n = 3, 24
+    say("[fp32_amg_small_3d] alpha", alpha)
+    m = I.smooth_unit_field(dim, n, seed=3)
+    c = 8.19  # dt / h^2 of the 128^3 workload
+    dt = c / n ** 2
+    S32 = gpu.Solver(gpu.make_grid(dim, n), gpu.default_opts(rtol=1e-8, precision=gpu.PREC_FP32_AMG))
+    S64 = gpu.Solver(gpu.make_grid(dim, n), gpu.default_opts(rtol=1e-8))
+    o32, s32, st32 = S32.step(_cuda(m), alpha, dt)
+    o64, s64, st64 = S64.step(_cuda(m), alpha, dt)
+    assert s32 == gpu.OK and s64 == gpu.OK
+    assert st32.relres_true <= 1e-8
+    rc, ref, _ = orc.step(orc.make_grid(dim, n), orc.default_opts(rtol=1e-12), m, alpha, dt)
+    e32 = np.abs(o32.cpu().numpy() - ref).max()
+    e64 = np.abs(o64.cpu().numpy() - ref).max()
+    say("  iters fp32 %d fp64 %d  err fp32 %.2e fp64 %.2e" % (st32.iters, st64.iters, e32, e64))
+    assert e32 <= 1e-7 and e64 <= 1e-7
+    assert st32.iters <= st64.iters + 3
+
+
+def test_determinism(gpu):
+    say("[determinism]")
+    m = I.smooth_unit_field(2, 96, seed=5)
+    S = gpu.Solver(gpu.make_grid(2, 96), gpu.default_opts(rtol=1e-9))
+    a, _, _ = S.step(_cuda(m), 0.05, 1e-3)
+    b, _, _ = S.step(_cuda(m), 0.05, 1e-3)
+    S2 = gpu.Solver(gpu.make_grid(2, 96), gpu.default_opts(rtol=1e-9))
+    c, _, _ = S2.step(_cuda(m), 0.05, 1e-3)
+    assert bool((a == b).all()) and bool((a == c).all())
+
+
+def test_error_paths(gpu):
+    import torch
+    say("[error_paths]")
+    g = gpu.make_grid(2, 32)
+    m = I.smooth_unit_field(2, 32, seed=1)
+    S = gpu.Solver(g, gpu.default_opts(rtol=1e-14, max_iters=1))
+    out, s, st = S.step(_cuda(m), 0.1, 1e-2, check=False)
+    assert s == gpu.ERR_NOT_CONVERGED and st.iters == 1 and not st.converged
+    assert bool(torch.isfinite(out).all())
+    bad = m.copy()
+    bad[7, 2] = np.nan
+    S2 = gpu.Solver(g, gpu.default_opts())
+    _, s, _ = S2.step(_cuda(bad), 0.1, 1e-3, check=False)
+    assert s == gpu.ERR_NONFINITE
+    x = _cuda(m)
+    _, s, _ = S2.step(x, 0.1, 1e-3, out=x, check=False)
+    assert s == gpu.ERR_INVALID_ARG
+    with pytest.raises(gpu.LLGError) as ei:
+        o = gpu.default_opts()
+        ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+        gpu.Solver(g, o, workspace=ws)
+    assert ei.value.status == gpu.ERR_WORKSPACE
+    # the context still works after the failures
+    _, s, _ = S2.step(_cuda(m), 0.1, 1e-3)
+    assert s == gpu.OK
+
+
+def test_constant_field_fixed_point(gpu):
+    say("[constant_field_fixed_point]")
+    import torch
+    n = 40
+    m = np.tile(np.array([0.0, 0.6, 0.8]), (n * n, 1))
+    S = gpu.Solver(gpu.make_grid(2, n), gpu.default_opts())
+    out, s, st = S.step(_cuda(m), 0.1, 1e-3)
+    assert s == gpu.OK and st.iters == 0
+    assert bool((out == torch.from_numpy(m).cuda()).all())
+
+
+@pytest.mark.slow
+def test_full_size_rough2d_1024(gpu, orc):
+    """The 1024^2 workload at full size: aggregates bitwise at every level and
+    one step against the oracle (single threaded, about half a minute)."""
+    w = I.WORKLOADS["rough2d_1024"]
+    say("[full_size_rough2d_1024] generating")
+    m = w.m0()
+    gg = gpu.make_grid(2, w.n)
+    og = orc.make_grid(2, w.n)
+    S = gpu.Solver(gg, gpu.default_opts(rtol=w.rtol))
+    say("  gpu step")
+    out, s, st = S.step(_cuda(m), w.alpha, w.dt)
+    assert s == gpu.OK
+    say("  gpu iters", st.iters, "levels", st.levels, "ms", round(st.ms_total, 2))
+    oo = orc.default_opts(rtol=1e-11)
+    H = orc.Hierarchy(og, oo, m, w.alpha, w.dt)
+    assert S.num_levels == H.num_levels
+    for l in range(H.num_levels - 1):
+        assert np.array_equal(S.aggregates(l), H.level(l).agg), l
+    say("  oracle step")
+    rc, ref, ost = orc.step(og, oo, m, w.alpha, w.dt)
+    assert rc == 0
+    d = np.abs(out.cpu().numpy() - ref).max()
+    say("  oracle iters", ost.iters, "max diff %.2e" % d)
+    assert d <= 1e-8

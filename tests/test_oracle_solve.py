@@ -126,4 +126,4 @@ def test_vortex64_iteration_band(orc):
     rc, _, st = orc.step(g, orc.default_opts(rtol=w.rtol), w.m0(), w.alpha, w.dt)
     assert rc == 0
     assert 20 <= st.iters <= 45
-    assert st.levels == 4
+    assert st.levels == 5
