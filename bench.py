@@ -1,0 +1,215 @@
+"""Benchmark: semi-implicit Landau-Lifshitz time steps on one MI355X.
+
+One step = assemble the 3x3-block operator for m^n, rebuild the aggregation
+AMG hierarchy, solve with V-cycle-preconditioned FGMRES to rel. residual
+1e-8, project.  Default workload: 2D 1024x1024 Neumann grid (3,145,728
+unknowns), smoothed random unit field, alpha = 0.02, dt = 1e-4, FP64, the
+hierarchy rebuilt every step; the same run is repeated with the FP32-AMG form.
+Prints ONE JSON line (metric unknowns*steps/s).
+
+  python bench.py [--gpus 1] [--steps 50] [--warmup 3]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", default="rough2d_1024")
+    p.add_argument("--forms", default="fp64,fp32_amg", help="comma list; the first gives `value`")
+    p.add_argument("--roofline-class", default="outer_spmv")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-steps", type=int, default=1)
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="only run a plain device copy of known size (for the PMC byte counters)")
+    return p.parse_args()
+
+
+def source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("k_solve.hip", "k_setup.hip", "engine.hip", "llg_internal.h"):
+        with open(os.path.join(ROOT, "paper_2608_09102_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str, workload: str, launch_bytes: float):
+    """HBM bytes per launch from the committed PMC summary, or None when the
+    summary is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != source_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def algorithmic_bytes(cls: str, st, N: int, precision: str) -> float:
+    """Bytes one launch of the kernel class must move at minimum (values,
+    indices, input vector read once, output written once)."""
+    nnzb0 = st.level_nnzb[0]
+    if cls == "outer_spmv":
+        zb = 4 if precision == "fp32_amg" else 8
+        return 72.0 * nnzb0 + 4.0 * nnzb0 + 3.0 * zb * N + 24.0 * N
+    raise ValueError("no byte model for kernel class " + cls)
+
+
+def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str):
+    opts = llg.default_opts(rtol=w.rtol, precision=form)
+    grid = llg.make_grid(w.dim, w.n)
+    S = llg.Solver(grid, opts)
+    m0 = torch.from_numpy(w.m0()).cuda()
+    bufs = [m0.clone(), torch.empty_like(m0)]
+    F = None
+    cur = 0
+    for k in range(warmup):
+        _, s, st = S.step(bufs[cur], w.alpha, w.dt, forcing=F, out=bufs[1 - cur])
+        cur = 1 - cur
+        log("  warmup %d: iters %d, %.1f ms" % (k, st.iters, st.ms_total))
+    S.set_kernel_timing(cls)
+    iters = []
+    kms = 0.0
+    klaunch = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        _, s, st = S.step(bufs[cur], w.alpha, w.dt, forcing=F, out=bufs[1 - cur])
+        cur = 1 - cur
+        if s != llg.OK:
+            raise RuntimeError("step %d: %s" % (k, llg.status_str(s)))
+        iters.append(st.iters)
+        kms += st.kernel_ms
+        klaunch += st.kernel_launches
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    S.set_kernel_timing("none")
+    # single step from m0 for the cross-form comparison (outside the timed region)
+    one, _, _ = S.step(m0, w.alpha, w.dt)
+    return {"seconds": el, "iters": iters, "kernel_ms": kms, "kernel_launches": klaunch, "stats": st,
+            "one_step": one, "levels": st.levels, "level_nodes": list(st.level_nodes[:st.levels]),
+            "level_nnzb": list(st.level_nnzb[:st.levels])}
+
+
+def cpu_baseline(w, nsteps: int):
+    import numpy as np
+    import oracle
+    g = oracle.make_grid(w.dim, w.n)
+    o = oracle.default_opts(rtol=w.rtol)
+    m = w.m0()
+    t0 = time.perf_counter()
+    iters = []
+    for _ in range(nsteps):
+        rc, m, st = oracle.step(g, o, m, w.alpha, w.dt)
+        iters.append(st.iters)
+    el = time.perf_counter() - t0
+    return {"value": 3.0 * w.nodes * nsteps / el, "unit": "unknowns*steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%d step(s) of the %s workload (assembly, hierarchy, FGMRES to rtol %g, projection), "
+                      "single-threaded C++ oracle, %.1f s, %s FGMRES iterations"
+                      % (nsteps, w.name, w.rtol, el, iters),
+            "host_threads_available": os.cpu_count()}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if a.calibrate_copy:
+        n = 1 << 27  # 1 GiB of float64
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": n * 8, "bytes_written": n * 8, "launches": 5}))
+        return
+    import llg_inputs as I
+    import paper_2608_09102_amd as llg
+    w = I.WORKLOADS[a.workload]
+    forms = [f for f in a.forms.split(",") if f]
+    res = {}
+    for f in forms:
+        log("[bench] %s %s: %d warmup + %d timed steps" % (w.name, f, a.warmup, a.steps))
+        res[f] = run_form(llg, torch, w, f, a.steps, a.warmup, a.roofline_class)
+        r = res[f]
+        log("  %.3f s, %.2f ms/step, iters/step %.1f, %s kernel %.3f ms over %d launches"
+            % (r["seconds"], 1e3 * r["seconds"] / a.steps, sum(r["iters"]) / len(r["iters"]),
+               a.roofline_class, r["kernel_ms"], r["kernel_launches"]))
+    main_form = forms[0]
+    r = res[main_form]
+    unknowns = w.unknowns
+    value = unknowns * a.steps / r["seconds"]
+    # roofline of the timed kernel class
+    lb = algorithmic_bytes(a.roofline_class, r["stats"], w.nodes, main_form)
+    avg_s = r["kernel_ms"] / 1e3 / max(1, r["kernel_launches"])
+    achieved = lb / avg_s / 1e9 if avg_s > 0 else 0.0
+    traffic = read_traffic(a.roofline_class, w.name, lb)
+    out = {
+        "metric": "unknowns*steps/s (FP64 AMG-FGMRES, rel.res 1e-8)",
+        "value": value,
+        "unit": "unknowns*steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * r["seconds"] / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_form == "fp64" else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": "%dD %s" % (w.dim, "x".join([str(w.n)] * w.dim)),
+                   "unknowns": unknowns, "alpha": w.alpha, "dt": w.dt, "rtol": w.rtol,
+                   "form": main_form, "hierarchy": "rebuilt every step", "krylov": "FGMRES(30)",
+                   "preconditioner": "aggregation AMG V(1,1) block-Jacobi"},
+        "iters_per_step": sum(r["iters"]) / len(r["iters"]),
+        "levels": r["levels"],
+        "level_nodes": r["level_nodes"],
+        "roofline": {"bound": "hbm", "kernel": a.roofline_class, "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": traffic, "algorithmic_bytes_per_launch": lb,
+                     "avg_launch_us": avg_s * 1e6, "launches": r["kernel_launches"]},
+    }
+    for f in forms[1:]:
+        rf = res[f]
+        diff = float((rf["one_step"] - r["one_step"]).abs().max())
+        out[f] = {"value": unknowns * a.steps / rf["seconds"], "ms_per_step": 1e3 * rf["seconds"] / a.steps,
+                  "iters_per_step": sum(rf["iters"]) / len(rf["iters"]),
+                  "speedup_vs_" + main_form: (unknowns * a.steps / rf["seconds"]) / value,
+                  "max_abs_diff_one_step_vs_" + main_form: diff}
+    if not a.no_cpu_baseline:
+        log("[bench] cpu baseline: oracle, %d step(s)" % a.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

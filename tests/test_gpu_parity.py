@@ -201,15 +201,19 @@ def test_constant_field_fixed_point(gpu):
 
 @pytest.mark.slow
 def test_full_size_rough2d_1024(gpu, orc):
-    """The 1024^2 workload at full size: aggregates bitwise at every level and
-    one step against the oracle (single threaded, about half a minute)."""
+    """The 1024^2 workload at full size.  Aggregates bitwise at every level.
+    Parity of m^{n+1}: both sides solved to rtol 1e-11 must agree to 1e-8.
+    At the benchmark's rtol 1e-8 the operator's conditioning (dt/h^2 = 105)
+    allows a larger distance from the tight solution, so there the unprojected
+    GPU solution is checked through its true residual, computed with the
+    oracle's operator: ||b - A u|| <= 1e-8 ||b||."""
     w = I.WORKLOADS["rough2d_1024"]
     say("[full_size_rough2d_1024] generating")
     m = w.m0()
     gg = gpu.make_grid(2, w.n)
     og = orc.make_grid(2, w.n)
-    S = gpu.Solver(gg, gpu.default_opts(rtol=w.rtol))
-    say("  gpu step")
+    S = gpu.Solver(gg, gpu.default_opts(rtol=1e-11))
+    say("  gpu step rtol 1e-11")
     out, s, st = S.step(_cuda(m), w.alpha, w.dt)
     assert s == gpu.OK
     say("  gpu iters", st.iters, "levels", st.levels, "ms", round(st.ms_total, 2))
@@ -224,3 +228,12 @@ def test_full_size_rough2d_1024(gpu, orc):
     d = np.abs(out.cpu().numpy() - ref).max()
     say("  oracle iters", ost.iters, "max diff %.2e" % d)
     assert d <= 1e-8
+    S8 = gpu.Solver(gg, gpu.default_opts(rtol=w.rtol, project=0))
+    u, s, st8 = S8.step(_cuda(m), w.alpha, w.dt)
+    assert s == gpu.OK
+    u = u.cpu().numpy()
+    res = np.linalg.norm(m.ravel() - H.apply_A(u).ravel()) / np.linalg.norm(m.ravel())
+    proj = u / np.linalg.norm(u, axis=1, keepdims=True)
+    say("  rtol 1e-8: iters %d, true relres (oracle operator) %.2e, |m - tight| %.2e"
+        % (st8.iters, res, np.abs(proj - ref).max()))
+    assert res <= 1e-8
