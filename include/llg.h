@@ -76,7 +76,7 @@ typedef struct {
 
 typedef struct {
   double rtol;          /* converged when ||b - A u||_2 <= rtol ||b||_2 (true residual) */
-  int32_t restart;      /* FGMRES basis size per cycle, 1..64 */
+  int32_t restart;      /* FGMRES basis size per cycle, 1..32 */
   int32_t max_iters;    /* total FGMRES iterations */
   int32_t precision;    /* llg_precision */
   int32_t nu_pre, nu_post;  /* damped block-Jacobi sweeps, each 0..4 */
@@ -105,6 +105,7 @@ typedef struct {
   /* timing of one kernel class selected by llg_set_kernel_timing() */
   double kernel_ms;
   int64_t kernel_launches;
+  int32_t reorth_passes;  /* Arnoldi steps that needed a second Gram-Schmidt pass */
 } llg_stats;
 
 typedef struct llg_ctx llg_ctx;

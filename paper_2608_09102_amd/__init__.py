@@ -56,7 +56,7 @@ class Stats(ctypes.Structure):
         ("converged", ctypes.c_int32), ("relres_est", ctypes.c_double), ("relres_true", ctypes.c_double),
         ("level_nodes", ctypes.c_int64 * MAX_LEVELS), ("level_nnzb", ctypes.c_int64 * MAX_LEVELS),
         ("ms_setup", ctypes.c_double), ("ms_solve", ctypes.c_double), ("ms_total", ctypes.c_double),
-        ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int64),
+        ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int64), ("reorth_passes", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -65,7 +65,8 @@ class Stats(ctypes.Structure):
                 "relres_est": self.relres_est, "relres_true": self.relres_true,
                 "level_nodes": list(self.level_nodes[:L]), "level_nnzb": list(self.level_nnzb[:L]),
                 "ms_setup": self.ms_setup, "ms_solve": self.ms_solve, "ms_total": self.ms_total,
-                "kernel_ms": self.kernel_ms, "kernel_launches": self.kernel_launches}
+                "kernel_ms": self.kernel_ms, "kernel_launches": self.kernel_launches,
+                "reorth_passes": self.reorth_passes}
 
 
 _P = ctypes.c_void_p

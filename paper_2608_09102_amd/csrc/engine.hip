@@ -324,6 +324,8 @@ int build_structure(llg_ctx& c, Arena& ar) {
       int32_t* id = ar.alloc<int32_t>(cn + 1);
       int32_t* aggp = ar.alloc<int32_t>(cn);
       int32_t* lead = ar.alloc<int32_t>(cn);
+      uint64_t* rank = ar.alloc<uint64_t>(cn);
+      launch_node_rank(st, cn, salt, rank);
       launch_row_max(st, cn, crp, cw, mx);
       launch_fill_i32(st, mate, cn, -1);
       LCHK();
@@ -334,7 +336,7 @@ int build_structure(llg_ctx& c, Arena& ar) {
         int64_t rounds = 0;
         for (;;) {
           launch_fill_i32(st, c.count, 1, 0);
-          launch_propose(st, cn, crp, cci, cw, mx, mate, salt, o.beta_num, o.beta_den, prop, c.count);
+          launch_propose(st, cn, crp, cci, cw, mx, mate, rank, salt, o.beta_num, o.beta_den, prop, c.count);
           LCHK();
           HIPX(hipMemcpyAsync(ar.hcount, c.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
           HIPX(hipStreamSynchronize(st));
@@ -349,11 +351,11 @@ int build_structure(llg_ctx& c, Arena& ar) {
         const int64_t rounds = ar.plan->counts[ar.ci++];
         launch_fill_i32(st, c.count + 1, 1, 0);
         for (int64_t r = 0; r < rounds; ++r) {
-          launch_propose(st, cn, crp, cci, cw, mx, mate, salt, o.beta_num, o.beta_den, prop, c.count + 1);
+          launch_propose(st, cn, crp, cci, cw, mx, mate, rank, salt, o.beta_num, o.beta_den, prop, c.count + 1);
           launch_accept(st, cn, prop, mate);
         }
         launch_fill_i32(st, c.count, 1, 0);
-        launch_propose(st, cn, crp, cci, cw, mx, mate, salt, o.beta_num, o.beta_den, prop, c.count);
+        launch_propose(st, cn, crp, cci, cw, mx, mate, rank, salt, o.beta_num, o.beta_den, prop, c.count);
         launch_check_eq(st, c.count, 0, c.flags, F_PLAN);
         LCHK();
       }
@@ -554,6 +556,13 @@ void setup_values(llg_ctx& c, const double* m, double alpha, double dt, const do
 }
 
 // ------------------------------------------------------------------ V-cycle
+// V(l, b): pre-smoothing from x = 0, restriction of the residual, V(l+1) on
+// the coarse residual equation, prolongation of its correction fused with
+// post-smoothing; the exact (dense inverse) solve at the coarsest level
+// (Sec. 3).  The first pre-smoothing sweep of a coarse level is produced by
+// the restriction kernel of the level above (x_{l+1} = omega D^{-1} b_{l+1}),
+// and on the fine level with unit diagonal blocks it is x = omega b, never
+// stored, so each level costs one "down" and one "up" kernel.
 template <typename T>
 void vcycle(llg_ctx& c, int l, const T* b, T* out) {
   hipStream_t st = c.st;
@@ -570,37 +579,40 @@ void vcycle(llg_ctx& c, int l, const T* b, T* out) {
   const double om = c.omega;
   T* X = (T*)L.x;
   T* XO = (T*)L.xo;
-  // pre-smoothing from x = 0
-  int xmode = 2;
+  int xmode = 2;  // x = 0
   const T* xcur = nullptr;
   {
     KTimer kt(c, LLG_KT_SMOOTH);
-    for (int s = 0; s < o.nu_pre; ++s) {
-      if (s == 0) {
-        if (L.unit) {
-          xmode = 1;  // x = omega b, never stored
-        } else {
-          launch_smooth_first<T>(st, L.A, dinv, om, b, X);
-          xmode = 0;
-          xcur = X;
-        }
-      } else {
-        T* dst = (xcur == X) ? XO : X;
-        launch_post_smooth<T>(st, L.A, val, dinv, L.unit, xmode, om, b, xcur, nullptr, nullptr, dst);
+    if (o.nu_pre >= 1) {
+      if (l == 0 && L.unit) {
+        xmode = 1;  // x = omega b
+      } else if (l == 0) {
+        launch_smooth_first<T>(st, L.A, dinv, om, b, X);
         xmode = 0;
-        xcur = dst;
+        xcur = X;
+      } else {
+        xmode = 0;  // written by the restriction of the level above
+        xcur = X;
       }
-      LCHK();
     }
+    for (int s = 1; s < o.nu_pre; ++s) {
+      T* dst = (xcur == X) ? XO : X;
+      launch_post_smooth<T>(st, L.A, val, dinv, L.unit, xmode, om, b, xcur, nullptr, nullptr, dst);
+      xmode = 0;
+      xcur = dst;
+    }
+    LCHK();
   }
   {
     KTimer kt(c, LLG_KT_RESIDUAL);
-    if (xmode == 2) {
-      launch_restrict<T>(st, L.nc, L.mptr, L.mem, b, (T*)Nx.b);
-    } else {
+    const bool pre_next = o.nu_pre >= 1 && l + 1 < c.L - 1;
+    const T* rsrc = b;
+    if (xmode != 2) {
       launch_residual<T>(st, L.A, val, xmode, om, b, xcur, (T*)L.r);
-      launch_restrict<T>(st, L.nc, L.mptr, L.mem, (const T*)L.r, (T*)Nx.b);
+      rsrc = (const T*)L.r;
     }
+    launch_restrict<T>(st, L.nc, L.mptr, L.mem, rsrc, (T*)Nx.b, pre_next ? (const T*)Nx.dinv : nullptr, om,
+                       pre_next ? (T*)Nx.x : nullptr);
     LCHK();
   }
   vcycle<T>(c, l + 1, (const T*)Nx.b, (T*)Nx.e);
@@ -611,11 +623,11 @@ void vcycle(llg_ctx& c, int l, const T* b, T* out) {
     LCHK();
     return;
   }
-  // buffers for extra sweeps alternate between XO and X (X is free once the
-  // first post-smoothing sweep has read it)
+  // further sweeps alternate between XO and X (X is free once the first
+  // post-smoothing sweep has read it)
   for (int s = 0; s < o.nu_post; ++s) {
     const bool last = s == o.nu_post - 1;
-    T* dst = last ? out : ((s % 2 == 0) ? XO : X);
+    T* dst = last ? out : (xcur == XO ? X : XO);
     if (s == 0) {
       launch_post_smooth<T>(st, L.A, val, dinv, L.unit, xmode, om, b, xcur, L.agg, ec, dst);
     } else {
@@ -650,6 +662,7 @@ SolveOut fgmres(llg_ctx& c) {
   double* H = c.host;
   T* Z = (T*)c.Z;
   SolveOut so;
+  H[7] = 0.0;
   // ||b|| and r = b - A u
   launch_norm_part(st, m, c.b, c.part);
   launch_norm_finish_n(st, c.part, c.npart_vec, 2, c.ks.sc, H);
@@ -684,12 +697,13 @@ SolveOut fgmres(llg_ctx& c) {
       }
       {
         KTimer kt(c, LLG_KT_ARNOLDI);
-        // classical Gram-Schmidt, two passes
+        // classical Gram-Schmidt; the second pass only when the first lost
+        // more than half of ||w||^2
         launch_mdot(st, m, j + 1, c.V, c.ld, c.w, c.part);
-        launch_dots_finish_n(st, c.part, c.npart_vec, j + 1, c.ks.hcol, c.delta, 0, c.ks.sc + 5);
-        launch_mupdate_dot(st, m, j + 1, c.V, c.ld, c.ks.hcol, c.w, c.part, 1);
-        launch_dots_finish_n(st, c.part, c.npart_vec, j + 1, c.ks.hcol, c.delta, 1, nullptr);
-        launch_mupdate_dot(st, m, j + 1, c.V, c.ld, c.delta, c.w, c.part, 0);
+        launch_dots_finish_n(st, c.part, c.npart_vec, j + 1, c.ks.hcol, c.ks.sc);
+        launch_mupdate_dot(st, m, j + 1, c.V, c.ld, c.ks.hcol, c.w, c.part, 1, nullptr);
+        launch_reorth_finish_n(st, c.part, c.npart_vec, j + 1, c.ks.hcol, c.delta, c.ks.sc);
+        launch_mupdate_dot(st, m, j + 1, c.V, c.ld, c.delta, c.w, c.part, 0, c.ks.sc + 7);
         launch_arnoldi_finish_n(st, c.part, c.npart_vec, j, R, c.ks, H);
         launch_scale_vec(st, m, c.w, c.ks.sc + 1, c.V + (int64_t)(j + 1) * c.ld);
         LCHK();
@@ -754,6 +768,7 @@ llg_status run_step(llg_ctx& c, const double* m_n, double alpha, double dt, cons
     stats->ms_solve = stats->ms_total - t_setup;
     stats->kernel_ms = c.kernel_ms;
     stats->kernel_launches = c.launches;
+    stats->reorth_passes = (int32_t)c.host[7];
   }
   if (fl & F_PLAN) {
     set_err("device-side check of the hierarchy structure failed");

@@ -199,21 +199,31 @@ __device__ inline uint64_t node_rank(int64_t v, uint64_t salt) {
   return splitmix64((((uint64_t)v) << 32 | (uint64_t)v) ^ salt);
 }
 
+__global__ void k_node_rank(int64_t n, uint64_t salt, uint64_t* rank) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) rank[i] = node_rank(i, salt);
+}
+
 struct EdgeKey {
   uint64_t rank;  // visiting rank of the first-visited endpoint
   int32_t first;
   int32_t w;
-  uint64_t h;
   int32_t lo, hi;
 };
 
+__device__ inline uint64_t edge_hash(int32_t lo, int32_t hi, uint64_t salt) {
+  return splitmix64(((((uint64_t)lo) << 32) | (uint64_t)hi) ^ salt);
+}
+
 // true when a precedes b in the matching order: earlier first-visited
-// endpoint, then larger weight, then larger hash, then smaller (lo, hi)
-__device__ inline bool key_before(const EdgeKey& a, const EdgeKey& b) {
+// endpoint, then larger weight, then larger edge hash, then smaller (lo, hi);
+// the hashes are only evaluated when everything before them ties
+__device__ inline bool key_before(const EdgeKey& a, const EdgeKey& b, uint64_t salt) {
   if (a.rank != b.rank) return a.rank < b.rank;
   if (a.first != b.first) return a.first < b.first;
   if (a.w != b.w) return a.w > b.w;
-  if (a.h != b.h) return a.h > b.h;
+  const uint64_t ha = edge_hash(a.lo, a.hi, salt), hb = edge_hash(b.lo, b.hi, salt);
+  if (ha != hb) return ha > hb;
   if (a.lo != b.lo) return a.lo < b.lo;
   return a.hi < b.hi;
 }
@@ -227,44 +237,67 @@ __global__ void k_row_max(int64_t n, const int32_t* grp, const int32_t* gw, int3
 }
 
 // Handshake round: every free node proposes its best available edge (both
-// endpoints free, strong for the first-visited endpoint).
-__global__ void k_propose(int64_t n, const int32_t* grp, const int32_t* gci, const int32_t* gw,
-                          const int32_t* mx, const int32_t* mate, uint64_t salt, int32_t bnum,
-                          int32_t bden, int32_t* prop, int32_t* count) {
+// endpoints free, strong for the first-visited endpoint).  Neighbours are
+// examined four at a time so that their loads are in flight together.
+__global__ void k_propose(int64_t n, const int32_t* __restrict__ grp, const int32_t* __restrict__ gci,
+                          const int32_t* __restrict__ gw, const int32_t* __restrict__ mx,
+                          const int32_t* __restrict__ mate, const uint64_t* __restrict__ rank, uint64_t salt,
+                          int32_t bnum, int32_t bden, int32_t* __restrict__ prop, int32_t* count) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool proposed = false;
   if (i < n) {
     int32_t best = -1;
     if (mate[i] < 0) {
-      const uint64_t ri = node_rank(i, salt);
+      const uint64_t ri = rank[i];
+      const int32_t mxi = mx[i];
+      const int32_t k1 = grp[i + 1];
       EdgeKey bk{};
-      for (int32_t k = grp[i]; k < grp[i + 1]; ++k) {
-        const int32_t j = gci[k];
-        if (mate[j] >= 0) continue;
-        const int32_t w = gw[k];
-        const uint64_t rj = node_rank(j, salt);
-        const bool ifirst = ri != rj ? ri < rj : i < j;
-        const int32_t f = ifirst ? (int32_t)i : j;
-        if ((int64_t)bden * w < (int64_t)bnum * mx[f]) continue;
-        EdgeKey e;
-        e.rank = ifirst ? ri : rj;
-        e.first = f;
-        e.w = w;
-        e.lo = (int32_t)min((int64_t)j, i);
-        e.hi = (int32_t)max((int64_t)j, i);
-        e.h = splitmix64(((((uint64_t)e.lo) << 32) | (uint64_t)e.hi) ^ salt);
-        if (best < 0 || key_before(e, bk)) {
-          bk = e;
-          best = j;
+      for (int32_t k0 = grp[i]; k0 < k1; k0 += 4) {
+        int32_t jj[4], ww[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const bool ok = k0 + u < k1;
+          jj[u] = ok ? gci[k0 + u] : -1;
+          ww[u] = ok ? gw[k0 + u] : 0;
+        }
+        bool fr[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) fr[u] = jj[u] >= 0 && mate[jj[u]] < 0;
+        uint64_t rr[4];
+        int32_t mj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          rr[u] = fr[u] ? rank[jj[u]] : 0;
+          mj[u] = fr[u] ? mx[jj[u]] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (!fr[u]) continue;
+          const int32_t j = jj[u], w = ww[u];
+          const uint64_t rj = rr[u];
+          const bool ifirst = ri != rj ? ri < rj : i < j;
+          const int32_t mf = ifirst ? mxi : mj[u];
+          if ((int64_t)bden * w < (int64_t)bnum * mf) continue;
+          EdgeKey e;
+          e.rank = ifirst ? ri : rj;
+          e.first = ifirst ? (int32_t)i : j;
+          e.w = w;
+          e.lo = (int32_t)min((int64_t)j, i);
+          e.hi = (int32_t)max((int64_t)j, i);
+          if (best < 0 || key_before(e, bk, salt)) {
+            bk = e;
+            best = j;
+          }
         }
       }
     }
     prop[i] = best;
     proposed = best >= 0;
   }
-  // one atomic per wavefront
-  unsigned long long ballot = __ballot(proposed);
-  if ((threadIdx.x & 63) == 0 && ballot) atomicAdd(count, (int32_t)__popcll(ballot));
+  // "some node proposed": set once; most wavefronts see the flag already set
+  // and skip the atomic (same-address atomics from every wavefront serialize)
+  const unsigned long long ballot = __ballot(proposed);
+  if ((threadIdx.x & 63) == 0 && ballot && __atomic_load_n(count, __ATOMIC_RELAXED) == 0) atomicOr(count, 1);
 }
 
 __global__ void k_accept(int64_t n, const int32_t* prop, int32_t* mate) {
@@ -518,63 +551,66 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, double dt, dou
 }
 
 // ---------------------------------------------------------------- Galerkin
-// One thread per coarse row I.  For every stored coarse block (I, J): sum,
-// over members i of aggregate I in ascending order and over the stored blocks
+// One thread per coarse block slot (I, J).  The block is the sum, over the
+// members i of aggregate I in ascending order and over the stored blocks
 // (i, j) of row i in ascending j with agg(j) = J, of the fine block a_ij
-// (eq. Ac_direct), accumulated in FP64 starting from zero.  The inverse of
-// the diagonal block is computed from the stored (rounded) block.
+// (eq. Ac_direct), accumulated in FP64 starting from zero.  The inverse of a
+// diagonal block is computed from the stored (rounded) block.
 template <typename T>
-__global__ void k_galerkin(int64_t nc, const int32_t* __restrict__ csl, const int32_t* __restrict__ ccol,
-                           T* __restrict__ cval, T* __restrict__ cdinv, const int32_t* __restrict__ mptr,
-                           const int32_t* __restrict__ mem, const int32_t* __restrict__ fsl,
-                           const int32_t* __restrict__ fcol, const T* __restrict__ fval,
-                           const int32_t* __restrict__ agg) {
-  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t ns = ceil_div(nc, SL);
-  if (I >= ns * SL) return;
-  const int64_t s = I / SL;
-  const int l = (int)(I - s * SL);
-  const int64_t cb = csl[s];
-  const int w = (int)((csl[s + 1] - cb) / SL);
-  if (I >= nc) return;
-  const int32_t q0 = mptr[I], q1 = mptr[I + 1];
-  for (int t = 0; t < w; ++t) {
-    const int32_t J = ccol[cb + (int64_t)t * SL + l];
-    if (J < 0) break;
-    double acc[9];
+__global__ void k_galerkin(int64_t nc, int64_t ns, const int32_t* __restrict__ csl,
+                           const int32_t* __restrict__ ccol, T* __restrict__ cval, T* __restrict__ cdinv,
+                           const int32_t* __restrict__ mptr, const int32_t* __restrict__ mem,
+                           const int32_t* __restrict__ fsl, const int32_t* __restrict__ fcol,
+                           const T* __restrict__ fval, const int32_t* __restrict__ agg) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= csl[ns]) return;
+  // slice of slot p: the last s with csl[s] <= p
+  int64_t lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (csl[mid] <= p)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int64_t s = lo, cb = csl[s];
+  const int t = (int)((p - cb) / SL), l = (int)((p - cb) % SL);
+  const int64_t I = s * SL + l;
+  const int32_t J = ccol[p];
+  if (J < 0 || I >= nc) return;
+  double acc[9];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) acc[e] = 0.0;
-    for (int32_t q = q0; q < q1; ++q) {
-      const int32_t i = mem[q];
-      const int64_t fs = i / SL;
-      const int fl = i - (int)(fs * SL);
-      const int64_t fb = fsl[fs];
-      const int fw = (int)((fsl[fs + 1] - fb) / SL);
-      for (int u = 0; u < fw; ++u) {
-        const int32_t j = fcol[fb + (int64_t)u * SL + fl];
-        if (j < 0) break;
-        if (agg[j] != J) continue;
-        const int64_t vb = fb * 9 + (int64_t)u * 9 * SL + fl;
+  for (int e = 0; e < 9; ++e) acc[e] = 0.0;
+  for (int32_t q = mptr[I]; q < mptr[I + 1]; ++q) {
+    const int32_t i = mem[q];
+    const int64_t fs = i / SL;
+    const int fl = i - (int)(fs * SL);
+    const int64_t fb = fsl[fs];
+    const int fw = (int)((fsl[fs + 1] - fb) / SL);
+    for (int u = 0; u < fw; ++u) {
+      const int32_t j = fcol[fb + (int64_t)u * SL + fl];
+      if (j < 0) break;
+      if (agg[j] != J) continue;
+      const int64_t vb = fb * 9 + (int64_t)u * 9 * SL + fl;
 #pragma unroll
-        for (int e = 0; e < 9; ++e) acc[e] += (double)fval[vb + e * SL];
-      }
+      for (int e = 0; e < 9; ++e) acc[e] += (double)fval[vb + e * SL];
     }
-    const int64_t vb = cb * 9 + (int64_t)t * 9 * SL + l;
-    T st[9];
+  }
+  const int64_t vb = cb * 9 + (int64_t)t * 9 * SL + l;
+  T st[9];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) {
-      st[e] = (T)acc[e];
-      cval[vb + e * SL] = st[e];
-    }
-    if (J == (int32_t)I) {
-      double D[9], Di[9];
+  for (int e = 0; e < 9; ++e) {
+    st[e] = (T)acc[e];
+    cval[vb + e * SL] = st[e];
+  }
+  if (J == (int32_t)I) {
+    double D[9], Di[9];
 #pragma unroll
-      for (int e = 0; e < 9; ++e) D[e] = (double)st[e];
-      inv3(D, Di);
-      const int64_t db = s * 9 * SL + l;
+    for (int e = 0; e < 9; ++e) D[e] = (double)st[e];
+    inv3(D, Di);
+    const int64_t db = s * 9 * SL + l;
 #pragma unroll
-      for (int e = 0; e < 9; ++e) cdinv[db + e * SL] = (T)Di[e];
-    }
+    for (int e = 0; e < 9; ++e) cdinv[db + e * SL] = (T)Di[e];
   }
 }
 
@@ -772,11 +808,14 @@ void launch_sell_cols(hipStream_t st, int64_t n, const int32_t* brp, const int32
 void launch_row_max(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gw, int32_t* mx) {
   if (n > 0) hipLaunchKernelGGL(k_row_max, dim3(nblk(n)), dim3(TPB), 0, st, n, grp, gw, mx);
 }
+void launch_node_rank(hipStream_t st, int64_t n, uint64_t salt, uint64_t* rank) {
+  if (n > 0) hipLaunchKernelGGL(k_node_rank, dim3(nblk(n)), dim3(TPB), 0, st, n, salt, rank);
+}
 void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci,
-                    const int32_t* gw, const int32_t* mx, const int32_t* mate, uint64_t salt,
-                    int32_t bnum, int32_t bden, int32_t* prop, int32_t* count) {
+                    const int32_t* gw, const int32_t* mx, const int32_t* mate, const uint64_t* rank,
+                    uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop, int32_t* count) {
   if (n > 0)
-    hipLaunchKernelGGL(k_propose, dim3(nblk(n)), dim3(TPB), 0, st, n, grp, gci, gw, mx, mate, salt,
+    hipLaunchKernelGGL(k_propose, dim3(nblk(n)), dim3(TPB), 0, st, n, grp, gci, gw, mx, mate, rank, salt,
                        bnum, bden, prop, count);
 }
 void launch_accept(hipStream_t st, int64_t n, const int32_t* prop, int32_t* mate) {
@@ -839,7 +878,7 @@ template <typename T>
 void launch_galerkin(hipStream_t st, Sell C, T* cval, T* cdinv, const int32_t* mptr,
                      const int32_t* mem, Sell F, const T* fval, const int32_t* agg) {
   if (C.n <= 0) return;
-  hipLaunchKernelGGL((k_galerkin<T>), dim3(nblk(C.nslices * SL)), dim3(TPB), 0, st, C.n, C.sl_ptr,
+  hipLaunchKernelGGL((k_galerkin<T>), dim3(nblk(C.nslots)), dim3(TPB), 0, st, C.n, C.nslices, C.sl_ptr,
                      C.col, cval, cdinv, mptr, mem, F.sl_ptr, F.col, fval, agg);
 }
 template void launch_galerkin<double>(hipStream_t, Sell, double*, double*, const int32_t*,

@@ -15,6 +15,11 @@ namespace llg {
 namespace {
 
 constexpr int TPB = 256;
+constexpr int MAXV_S = 32;  // largest FGMRES restart
+
+// sliced-ELL kernels: 256-thread blocks for large levels, one slice per block
+// for small ones so that the blocks spread over all CUs
+inline int tpb_rows(int64_t n) { return n >= 65536 ? 256 : 64; }
 
 inline unsigned nblk(int64_t n, int t = TPB) { return (unsigned)ceil_div(n > 0 ? n : 1, t); }
 
@@ -66,11 +71,43 @@ __device__ inline void blk_mv(const T* __restrict__ val, int64_t vb, V3<TV> v, T
   a2 += (TA)val[vb + 6 * SL] * x + (TA)val[vb + 7 * SL] * y + (TA)val[vb + 8 * SL] * z;
 }
 
+// Row i of a sliced-ELL matrix times x: the slot loop is unrolled by four so
+// that the column indices of four slots, then their values and x entries,
+// are in flight together (the loads of one slot depend on its column index).
+template <typename T, typename TA, typename XF>
+__device__ inline void sell_row_mv(const int32_t* __restrict__ col, const T* __restrict__ val, int64_t cb,
+                                   int w, int l, XF xf, TA& a0, TA& a1, TA& a2) {
+  for (int t = 0; t < w; t += 4) {
+    int32_t c[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) c[q] = (t + q < w) ? col[cb + (int64_t)(t + q) * SL + l] : -1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (c[q] >= 0) blk_mv(val, cb * 9 + (int64_t)(t + q) * 9 * SL + l, xf(c[q]), a0, a1, a2);
+  }
+}
+
 template <typename T>
 __device__ inline V3<T> dmv(const T* __restrict__ d, int64_t db, V3<T> v) {
   return V3<T>{d[db + 0 * SL] * v.x + d[db + 1 * SL] * v.y + d[db + 2 * SL] * v.z,
                d[db + 3 * SL] * v.x + d[db + 4 * SL] * v.y + d[db + 5 * SL] * v.z,
                d[db + 6 * SL] * v.x + d[db + 7 * SL] * v.y + d[db + 8 * SL] * v.z};
+}
+
+// row index of this thread (XCD-aware block order) and its slice position
+struct RowPos {
+  int64_t i, s, cb;
+  int l, w;
+};
+__device__ inline RowPos row_pos(const int32_t* __restrict__ sl) {
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  RowPos p;
+  p.i = (int64_t)blk * blockDim.x + threadIdx.x;
+  p.s = p.i / SL;
+  p.l = (int)(p.i - p.s * SL);
+  p.cb = 0;
+  p.w = 0;
+  return p;
 }
 
 // ------------------------------------------------------------- level kernels
@@ -91,27 +128,23 @@ template <typename T, int XMODE>
 __global__ void k_residual(int64_t n, const int32_t* __restrict__ sl, const int32_t* __restrict__ col,
                            const T* __restrict__ val, T omega, const T* __restrict__ b,
                            const T* __restrict__ x, T* __restrict__ r) {
-  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t s = i / SL;
-  const int l = (int)(i - s * SL);
-  const int64_t cb = sl[s];
-  const int w = (int)((sl[s + 1] - cb) / SL);
+  RowPos p = row_pos(sl);
+  if (p.i >= n) return;
+  const int64_t cb = sl[p.s];
+  const int w = (int)((sl[p.s + 1] - cb) / SL);
   T a0 = 0, a1 = 0, a2 = 0;
-  for (int t = 0; t < w; ++t) {
-    const int32_t c = col[cb + (int64_t)t * SL + l];
-    if (c < 0) break;
-    blk_mv(val, cb * 9 + (int64_t)t * 9 * SL + l, xval<T, XMODE>(x, b, omega, c), a0, a1, a2);
-  }
-  const V3<T> bi = ld3(b, i);
-  st3(r, i, V3<T>{bi.x - a0, bi.y - a1, bi.z - a2});
+  sell_row_mv(col, val, cb, w, p.l, [&](int32_t c) { return xval<T, XMODE>(x, b, omega, c); }, a0, a1, a2);
+  const V3<T> bi = ld3(b, p.i);
+  st3(r, p.i, V3<T>{bi.x - a0, bi.y - a1, bi.z - a2});
 }
 
-// bc_I = sum of r_i over the members of aggregate I, ascending
+// Restriction bc_I = sum of r_i over the members of aggregate I, ascending,
+// fused with the first pre-smoothing sweep of the coarse level,
+// xc_I = omega Dc_I^{-1} bc_I (when xc != NULL).
 template <typename T>
 __global__ void k_restrict(int64_t nc, const int32_t* __restrict__ mptr, const int32_t* __restrict__ mem,
-                           const T* __restrict__ r, T* __restrict__ bc) {
+                           const T* __restrict__ r, T* __restrict__ bc, const T* __restrict__ cdinv, T omega,
+                           T* __restrict__ xc) {
   const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nc) return;
   T a0 = 0, a1 = 0, a2 = 0;
@@ -122,6 +155,11 @@ __global__ void k_restrict(int64_t nc, const int32_t* __restrict__ mptr, const i
     a2 += v.z;
   }
   st3(bc, I, V3<T>{a0, a1, a2});
+  if (xc) {
+    const int64_t cs = I / SL;
+    const V3<T> d = dmv(cdinv, cs * 9 * SL + (I - cs * SL), V3<T>{a0, a1, a2});
+    st3(xc, I, V3<T>{omega * d.x, omega * d.y, omega * d.z});
+  }
 }
 
 // out_i = x'_i + omega D_i^{-1} (b_i - sum_j A_ij x'_j), x'_j = xbase_j + ec[agg_j]
@@ -131,17 +169,11 @@ __global__ void k_post_smooth(int64_t n, const int32_t* __restrict__ sl, const i
                               const T* __restrict__ b, const T* __restrict__ x,
                               const int32_t* __restrict__ agg, const T* __restrict__ ec,
                               T* __restrict__ out) {
-  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t s = i / SL;
-  const int l = (int)(i - s * SL);
-  const int64_t cb = sl[s];
-  const int w = (int)((sl[s + 1] - cb) / SL);
-  T a0 = 0, a1 = 0, a2 = 0;
-  for (int t = 0; t < w; ++t) {
-    const int32_t c = col[cb + (int64_t)t * SL + l];
-    if (c < 0) break;
+  RowPos p = row_pos(sl);
+  if (p.i >= n) return;
+  const int64_t cb = sl[p.s];
+  const int w = (int)((sl[p.s + 1] - cb) / SL);
+  auto xp = [&](int64_t c) {
     V3<T> xj = xval<T, XMODE>(x, b, omega, c);
     if (ec) {
       const V3<T> e = ld3(ec, (int64_t)agg[c]);
@@ -149,19 +181,15 @@ __global__ void k_post_smooth(int64_t n, const int32_t* __restrict__ sl, const i
       xj.y += e.y;
       xj.z += e.z;
     }
-    blk_mv(val, cb * 9 + (int64_t)t * 9 * SL + l, xj, a0, a1, a2);
-  }
-  V3<T> xi = xval<T, XMODE>(x, b, omega, i);
-  if (ec) {
-    const V3<T> e = ld3(ec, (int64_t)agg[i]);
-    xi.x += e.x;
-    xi.y += e.y;
-    xi.z += e.z;
-  }
-  const V3<T> bi = ld3(b, i);
+    return xj;
+  };
+  T a0 = 0, a1 = 0, a2 = 0;
+  sell_row_mv(col, val, cb, w, p.l, [&](int32_t c) { return xp(c); }, a0, a1, a2);
+  const V3<T> xi = xp(p.i);
+  const V3<T> bi = ld3(b, p.i);
   V3<T> res{bi.x - a0, bi.y - a1, bi.z - a2};
-  if (!UNIT) res = dmv(dinv, s * 9 * SL + l, res);
-  st3(out, i, V3<T>{xi.x + omega * res.x, xi.y + omega * res.y, xi.z + omega * res.z});
+  if (!UNIT) res = dmv(dinv, p.s * 9 * SL + p.l, res);
+  st3(out, p.i, V3<T>{xi.x + omega * res.x, xi.y + omega * res.y, xi.z + omega * res.z});
 }
 
 template <typename T, int XMODE>
@@ -192,34 +220,33 @@ template <typename TZ>
 __global__ void k_spmv_outer(int64_t n, const int32_t* __restrict__ sl, const int32_t* __restrict__ col,
                              const double* __restrict__ val, const TZ* __restrict__ z,
                              double* __restrict__ w) {
-  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t s = i / SL;
-  const int l = (int)(i - s * SL);
-  const int64_t cb = sl[s];
-  const int wd = (int)((sl[s + 1] - cb) / SL);
+  RowPos p = row_pos(sl);
+  if (p.i >= n) return;
+  const int64_t cb = sl[p.s];
+  const int wd = (int)((sl[p.s + 1] - cb) / SL);
   double a0 = 0, a1 = 0, a2 = 0;
-  for (int t = 0; t < wd; ++t) {
-    const int32_t c = col[cb + (int64_t)t * SL + l];
-    if (c < 0) break;
-    blk_mv(val, cb * 9 + (int64_t)t * 9 * SL + l, ld3(z, (int64_t)c), a0, a1, a2);
-  }
-  st3(w, i, V3<double>{a0, a1, a2});
+  sell_row_mv(col, val, cb, wd, p.l, [&](int32_t c) { return ld3(z, (int64_t)c); }, a0, a1, a2);
+  st3(w, p.i, V3<double>{a0, a1, a2});
 }
 
-// block sum of v over 256 threads, fixed tree; result valid in thread 0
-__device__ inline double block_sum(double v, double* sh) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) sh[wv] = v;
-  __syncthreads();
-  double r = 0;
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r += sh[k];
+// Sum of NS per-thread values over the workgroup in a fixed tree (wave
+// shuffles, then the waves in order); results land in out[0..NS) of thread 0.
+template <int NS>
+__device__ inline void block_sums(const double* v, double* sh, double* out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    double a = v[q];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+    if (lane == 0) sh[wv * NS + q] = a;
   }
   __syncthreads();
-  return r;
+  if (threadIdx.x < NS) {
+    double r = 0;
+    for (int k = 0; k < nw; ++k) r += sh[k * NS + threadIdx.x];
+    out[threadIdx.x] = r;
+  }
+  __syncthreads();
 }
 
 __global__ void k_resid_outer(int64_t n, const int32_t* __restrict__ sl, const int32_t* __restrict__ col,
@@ -227,6 +254,7 @@ __global__ void k_resid_outer(int64_t n, const int32_t* __restrict__ sl, const i
                               const double* __restrict__ u, double* __restrict__ r,
                               double* __restrict__ part) {
   __shared__ double sh[TPB / 64];
+  __shared__ double res[1];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double nrm = 0;
   if (i < n) {
@@ -235,101 +263,83 @@ __global__ void k_resid_outer(int64_t n, const int32_t* __restrict__ sl, const i
     const int64_t cb = sl[s];
     const int wd = (int)((sl[s + 1] - cb) / SL);
     double a0 = 0, a1 = 0, a2 = 0;
-    for (int t = 0; t < wd; ++t) {
-      const int32_t c = col[cb + (int64_t)t * SL + l];
-      if (c < 0) break;
-      blk_mv(val, cb * 9 + (int64_t)t * 9 * SL + l, ld3(u, (int64_t)c), a0, a1, a2);
-    }
+    sell_row_mv(col, val, cb, wd, l, [&](int32_t c) { return ld3(u, (int64_t)c); }, a0, a1, a2);
     const V3<double> bi = ld3(b, i);
     const V3<double> ri{bi.x - a0, bi.y - a1, bi.z - a2};
     st3(r, i, ri);
     nrm = (ri.x * ri.x + ri.y * ri.y) + ri.z * ri.z;
   }
-  const double t = block_sum(nrm, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  block_sums<1>(&nrm, sh, res);
+  if (threadIdx.x == 0) part[blockIdx.x] = res[0];
 }
 
 // partial sums of x.x over a fixed grid of RED_BLOCKS-bounded blocks
 __global__ void k_norm_part(int64_t m, const double* __restrict__ x, double* __restrict__ part) {
   __shared__ double sh[TPB / 64];
+  __shared__ double res[1];
   double a = 0;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x)
     a += x[k] * x[k];
-  const double t = block_sum(a, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  block_sums<1>(&a, sh, res);
+  if (threadIdx.x == 0) part[blockIdx.x] = res[0];
 }
 
-constexpr int MAXV = 33;  // restart <= 32, plus the squared norm
-
-// part[i][blk] = V_i . w (i < nv), part[nv][blk] = w . w; one sweep over w and V
-__global__ void __launch_bounds__(TPB) k_mdot(int64_t m, int nv, const double* __restrict__ V, int64_t ldv,
+// part[q][blk] = V_q . w (q < NV), part[NV][blk] = w . w; one sweep over w and V
+template <int NV>
+__global__ void __launch_bounds__(TPB) k_mdot(int64_t m, const double* __restrict__ V, int64_t ldv,
                                               const double* __restrict__ w, double* __restrict__ part) {
-  __shared__ double sh[TPB / 64];
+  __shared__ double sh[(TPB / 64) * (NV + 1)];
+  __shared__ double res[NV + 1];
   const int G = gridDim.x;
-  double acc[MAXV];
+  double acc[NV + 1];
 #pragma unroll
-  for (int q = 0; q < MAXV; ++q) acc[q] = 0.0;
+  for (int q = 0; q <= NV; ++q) acc[q] = 0.0;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)G * blockDim.x) {
     const double wk = w[k];
 #pragma unroll
-    for (int q = 0; q < MAXV; ++q) {
-      if (q < nv) acc[q] += V[q * ldv + k] * wk;
-    }
-    acc[MAXV - 1] += wk * wk;
+    for (int q = 0; q < NV; ++q) acc[q] += V[q * ldv + k] * wk;
+    acc[NV] += wk * wk;
   }
-  for (int q = 0; q < nv; ++q) {
-    double t = 0;
-#pragma unroll
-    for (int r = 0; r < MAXV - 1; ++r)
-      if (r == q) t = acc[r];
-    t = block_sum(t, sh);
-    if (threadIdx.x == 0) part[(int64_t)q * G + blockIdx.x] = t;
-  }
-  const double t = block_sum(acc[MAXV - 1], sh);
-  if (threadIdx.x == 0) part[(int64_t)nv * G + blockIdx.x] = t;
+  block_sums<NV + 1>(acc, sh, res);
+  if (threadIdx.x <= NV) part[(int64_t)threadIdx.x * G + blockIdx.x] = res[threadIdx.x];
 }
 
-// w -= sum_i h_i V_i, then (same sweep, V_i still in registers)
-// part[i][blk] = V_i . w_new when want_dots, part[nv][blk] = w_new . w_new
-__global__ void __launch_bounds__(TPB) k_mupdate_dot(int64_t m, int nv, const double* __restrict__ V,
-                                                     int64_t ldv, const double* __restrict__ h,
-                                                     double* __restrict__ w, double* __restrict__ part,
-                                                     int want_dots) {
-  __shared__ double sh[TPB / 64];
-  __shared__ double hs[MAXV];
-  if (threadIdx.x < MAXV) hs[threadIdx.x] = (int)threadIdx.x < nv ? h[threadIdx.x] : 0.0;
-  __syncthreads();
-  const int G = gridDim.x;
-  double acc[MAXV];
+// w -= sum_q h_q V_q; in the same sweep (V_q still in registers)
+// part[q][blk] = V_q . w_new when want_dots, and part[NV][blk] = w_new . w_new.
+// skip: when non-NULL and *skip == 0 the pass is not needed and returns.
+template <int NV>
+__global__ void __launch_bounds__(TPB) k_mupdate_dot(int64_t m, const double* __restrict__ V, int64_t ldv,
+                                                     const double* __restrict__ h, double* __restrict__ w,
+                                                     double* __restrict__ part, int want_dots,
+                                                     const double* __restrict__ skip) {
+  if (skip && skip[0] == 0.0) return;
+  __shared__ double sh[(TPB / 64) * (NV + 1)];
+  __shared__ double res[NV + 1];
+  double hs[NV];
 #pragma unroll
-  for (int q = 0; q < MAXV; ++q) acc[q] = 0.0;
+  for (int q = 0; q < NV; ++q) hs[q] = h[q];
+  const int G = gridDim.x;
+  double acc[NV + 1];
+#pragma unroll
+  for (int q = 0; q <= NV; ++q) acc[q] = 0.0;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)G * blockDim.x) {
-    double v[MAXV - 1];
+    double v[NV];
     double wk = w[k];
 #pragma unroll
-    for (int q = 0; q < MAXV - 1; ++q) {
-      v[q] = q < nv ? V[q * ldv + k] : 0.0;
+    for (int q = 0; q < NV; ++q) {
+      v[q] = V[q * ldv + k];
       wk -= hs[q] * v[q];
     }
     w[k] = wk;
     if (want_dots) {
 #pragma unroll
-      for (int q = 0; q < MAXV - 1; ++q) acc[q] += v[q] * wk;
+      for (int q = 0; q < NV; ++q) acc[q] += v[q] * wk;
     }
-    acc[MAXV - 1] += wk * wk;
+    acc[NV] += wk * wk;
   }
-  if (want_dots) {
-    for (int q = 0; q < nv; ++q) {
-      double t = 0;
-#pragma unroll
-      for (int r = 0; r < MAXV - 1; ++r)
-        if (r == q) t = acc[r];
-      t = block_sum(t, sh);
-      if (threadIdx.x == 0) part[(int64_t)q * G + blockIdx.x] = t;
-    }
-  }
-  const double t = block_sum(acc[MAXV - 1], sh);
-  if (threadIdx.x == 0) part[(int64_t)nv * G + blockIdx.x] = t;
+  block_sums<NV + 1>(acc, sh, res);
+  if (threadIdx.x <= NV && (want_dots || threadIdx.x == NV))
+    part[(int64_t)threadIdx.x * G + blockIdx.x] = res[threadIdx.x];
 }
 
 template <typename TS, typename TD>
@@ -370,25 +380,24 @@ __global__ void k_project(int64_t n, const double* __restrict__ u, double* __res
 }
 
 // ------------------------------------------------------------- scalar work
-// Sum of nparts partials in a fixed order: strided per-thread sums, then a
-// fixed tree over the workgroup.
-__device__ inline double wg_sum(const double* part, int64_t nparts, double* sh) {
-  double a = 0;
-  for (int64_t k = threadIdx.x; k < nparts; k += blockDim.x) a += part[k];
-  sh[threadIdx.x] = a;
-  __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-    __syncthreads();
+// One wavefront sums nparts partials in a fixed order (lane-strided sums,
+// four independent accumulators, then a shuffle tree); valid in lane 0.
+__device__ inline double wave_sum(const double* __restrict__ part, int64_t nparts) {
+  const int lane = threadIdx.x & 63;
+  double a[4] = {0, 0, 0, 0};
+  int64_t k = lane;
+  for (; k + 192 < nparts; k += 256) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] += part[k + 64 * u];
   }
-  const double r = sh[0];
-  __syncthreads();
+  for (int u = 0; k < nparts; k += 64, ++u) a[u & 3] += part[k];
+  double r = (a[0] + a[1]) + (a[2] + a[3]);
+  for (int off = 32; off > 0; off >>= 1) r += __shfl_down(r, off, 64);
   return r;
 }
 
 __global__ void k_norm_finish(const double* part, int64_t nparts, int slot, double* sc, double* host) {
-  __shared__ double sh[TPB];
-  const double s = wg_sum(part, nparts, sh);
+  const double s = wave_sum(part, nparts);
   if (threadIdx.x == 0) {
     const double v = sqrt(s);
     sc[slot] = v;
@@ -397,54 +406,90 @@ __global__ void k_norm_finish(const double* part, int64_t nparts, int slot, doub
   }
 }
 
-__global__ void k_dots_finish(const double* part, int64_t nparts, int nv, double* hcol, double* delta,
-                              int accumulate, double* normsq) {
-  __shared__ double sh[TPB];
-  for (int i = 0; i <= nv; ++i) {
-    const double s = wg_sum(part + (int64_t)i * nparts, nparts, sh);
-    if (threadIdx.x == 0) {
-      if (i == nv) {
-        if (normsq) *normsq = s;
-      } else if (accumulate) {
-        delta[i] = s;
-        hcol[i] += s;
-      } else {
-        hcol[i] = s;
-      }
+// Pass-1 sums: hcol[q] = sum part[q] (q < nv), sc[5] = ||w||^2 (entry nv).
+__global__ void k_dots_finish(const double* part, int64_t nparts, int nv, double* hcol, double* sc) {
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int q = wv; q <= nv; q += nw) {
+    const double s = wave_sum(part + (int64_t)q * nparts, nparts);
+    if ((threadIdx.x & 63) == 0) {
+      if (q < nv)
+        hcol[q] = s;
+      else
+        sc[5] = s;
     }
   }
 }
 
+// Pass-2 sums and the reorthogonalization test: the first classical
+// Gram-Schmidt pass is kept when ||w'|| >= ||w|| / sqrt(2) (Kahan-Parlett
+// "twice is enough"); otherwise the second-pass coefficients go to delta,
+// are added to hcol, and sc[7] = 1 asks for the second update.
+__global__ void k_reorth_finish(const double* part, int64_t nparts, int nv, double* hcol, double* delta,
+                                double* sc) {
+  __shared__ double s[MAXV_S + 1];
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int q = wv; q <= nv; q += nw) {
+    const double v = wave_sum(part + (int64_t)q * nparts, nparts);
+    if ((threadIdx.x & 63) == 0) s[q] = v;
+  }
+  __syncthreads();
+  const bool again = !(s[nv] >= 0.5 * sc[5]);
+  for (int q = threadIdx.x; q < nv; q += blockDim.x) {
+    if (again) {
+      delta[q] = s[q];
+      hcol[q] += s[q];
+    } else {
+      delta[q] = 0.0;
+    }
+  }
+  if (threadIdx.x == 0) sc[7] = again ? 1.0 : 0.0;
+}
+
+// New Hessenberg column, previous Givens rotations, the new rotation and the
+// residual estimate.  The column and the rotations are staged in LDS so the
+// serial part runs on one lane without global-memory round trips.
 __global__ void k_arnoldi_finish(const double* part, int64_t nparts, int j, int R, KrylovScalars ks,
                                  double* host) {
-  __shared__ double sh[TPB];
-  const double s = wg_sum(part + (int64_t)(j + 1) * nparts, nparts, sh);
-  if (threadIdx.x != 0) return;
-  double* H = ks.H;
-  const double hn = sqrt(s);
-  for (int i = 0; i <= j; ++i) H[i * R + j] = ks.hcol[i];
-  H[(j + 1) * R + j] = hn;
-  const double wnorm0 = sqrt(ks.sc[5]);
-  const int breakdown = hn <= 1e-14 * wnorm0 ? 1 : 0;
-  for (int i = 0; i < j; ++i) {
-    const double a = H[i * R + j], c = H[(i + 1) * R + j];
-    H[i * R + j] = ks.cs[i] * a + ks.sn[i] * c;
-    H[(i + 1) * R + j] = -ks.sn[i] * a + ks.cs[i] * c;
+  __shared__ double col[MAXV_S + 2], c_s[MAXV_S], s_s[MAXV_S];
+  const double s = wave_sum(part + (int64_t)(j + 1) * nparts, nparts);
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+    col[i] = ks.hcol[i];
+    if (i < j) {
+      c_s[i] = ks.cs[i];
+      s_s[i] = ks.sn[i];
+    }
   }
-  const double a = H[j * R + j], c = H[(j + 1) * R + j];
-  const double rho = hypot(a, c);
-  ks.cs[j] = a / rho;
-  ks.sn[j] = c / rho;
-  H[j * R + j] = rho;
-  H[(j + 1) * R + j] = 0.0;
-  ks.g[j + 1] = -ks.sn[j] * ks.g[j];
-  ks.g[j] = ks.cs[j] * ks.g[j];
-  const double est = fabs(ks.g[j + 1]);
-  ks.sc[3] = est;
-  ks.sc[4] = hn;
-  ks.sc[1] = 1.0 / hn;
-  host[3] = est;
-  host[6] = (double)breakdown;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double hn = sqrt(s);
+    col[j + 1] = hn;
+    const double wnorm0 = sqrt(ks.sc[5]);
+    const int breakdown = hn <= 1e-14 * wnorm0 ? 1 : 0;
+    for (int i = 0; i < j; ++i) {
+      const double a = col[i], c = col[i + 1];
+      col[i] = c_s[i] * a + s_s[i] * c;
+      col[i + 1] = -s_s[i] * a + c_s[i] * c;
+    }
+    const double a = col[j], c = col[j + 1];
+    const double rho = hypot(a, c);
+    const double cj = a / rho, sj = c / rho;
+    ks.cs[j] = cj;
+    ks.sn[j] = sj;
+    col[j] = rho;
+    col[j + 1] = 0.0;
+    const double gj = ks.g[j];
+    ks.g[j + 1] = -sj * gj;
+    ks.g[j] = cj * gj;
+    const double est = fabs(sj * gj);
+    ks.sc[3] = est;
+    ks.sc[4] = hn;
+    ks.sc[1] = 1.0 / hn;
+    host[3] = est;
+    host[6] = (double)breakdown;
+    host[7] += ks.sc[7];  // second Gram-Schmidt passes in this solve
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) ks.H[i * R + j] = col[i];
 }
 
 __global__ void k_cycle_start(int R, KrylovScalars ks) {
@@ -478,7 +523,8 @@ template <typename T>
 void launch_residual(hipStream_t st, Sell A, const T* val, int xmode, double omega, const T* b,
                      const T* x, T* r) {
   if (A.n <= 0) return;
-  const dim3 g(nblk(A.n)), t(TPB);
+  const int tb = tpb_rows(A.n);
+  const dim3 g(nblk(A.n, tb)), t(tb);
   if (xmode == 0)
     hipLaunchKernelGGL((k_residual<T, 0>), g, t, 0, st, A.n, A.sl_ptr, A.col, val, (T)omega, b, x, r);
   else if (xmode == 1)
@@ -488,15 +534,20 @@ void launch_residual(hipStream_t st, Sell A, const T* val, int xmode, double ome
 }
 
 template <typename T>
-void launch_restrict(hipStream_t st, int64_t nc, const int32_t* mptr, const int32_t* mem, const T* r, T* bc) {
-  if (nc > 0) hipLaunchKernelGGL((k_restrict<T>), dim3(nblk(nc)), dim3(TPB), 0, st, nc, mptr, mem, r, bc);
+void launch_restrict(hipStream_t st, int64_t nc, const int32_t* mptr, const int32_t* mem, const T* r, T* bc,
+                     const T* cdinv, double omega, T* xc) {
+  const int tb = tpb_rows(nc);
+  if (nc > 0)
+    hipLaunchKernelGGL((k_restrict<T>), dim3(nblk(nc, tb)), dim3(tb), 0, st, nc, mptr, mem, r, bc, cdinv,
+                       (T)omega, xc);
 }
 
 template <typename T>
 void launch_post_smooth(hipStream_t st, Sell A, const T* val, const T* dinv, int unit, int xmode,
                         double omega, const T* b, const T* x, const int32_t* agg, const T* ec, T* out) {
   if (A.n <= 0) return;
-  const dim3 g(nblk(A.n)), t(TPB);
+  const int tb = tpb_rows(A.n);
+  const dim3 g(nblk(A.n, tb)), t(tb);
   const T om = (T)omega;
 #define LLG_PS(XM, U)                                                                                  \
   hipLaunchKernelGGL((k_post_smooth<T, XM, U>), g, t, 0, st, A.n, A.sl_ptr, A.col, val, dinv, om, b, x, \
@@ -517,7 +568,8 @@ template <typename T>
 void launch_prolong(hipStream_t st, int64_t n, int xmode, double omega, const T* b, const T* x,
                     const int32_t* agg, const T* ec, T* out) {
   if (n <= 0) return;
-  const dim3 g(nblk(n)), t(TPB);
+  const int tb = tpb_rows(n);
+  const dim3 g(nblk(n, tb)), t(tb);
   if (xmode == 0)
     hipLaunchKernelGGL((k_prolong<T, 0>), g, t, 0, st, n, (T)omega, b, x, agg, ec, out);
   else if (xmode == 1)
@@ -534,7 +586,8 @@ void launch_scale_in(hipStream_t st, int64_t n, const double* dinv0, int left_sc
 #define LLG_INST(T)                                                                                         \
   template void launch_smooth_first<T>(hipStream_t, Sell, const T*, double, const T*, T*);                  \
   template void launch_residual<T>(hipStream_t, Sell, const T*, int, double, const T*, const T*, T*);      \
-  template void launch_restrict<T>(hipStream_t, int64_t, const int32_t*, const int32_t*, const T*, T*);    \
+  template void launch_restrict<T>(hipStream_t, int64_t, const int32_t*, const int32_t*, const T*, T*,     \
+                                   const T*, double, T*);                                                   \
   template void launch_post_smooth<T>(hipStream_t, Sell, const T*, const T*, int, int, double, const T*,   \
                                       const T*, const int32_t*, const T*, T*);                              \
   template void launch_prolong<T>(hipStream_t, int64_t, int, double, const T*, const T*, const int32_t*,   \
@@ -546,8 +599,9 @@ LLG_INST(float)
 
 template <typename TZ>
 void launch_spmv_outer(hipStream_t st, Sell A, const double* val, const TZ* z, double* w) {
-  if (A.n > 0)
-    hipLaunchKernelGGL((k_spmv_outer<TZ>), dim3(nblk(A.n)), dim3(TPB), 0, st, A.n, A.sl_ptr, A.col, val, z, w);
+  if (A.n <= 0) return;
+  const int tb = tpb_rows(A.n);
+  hipLaunchKernelGGL((k_spmv_outer<TZ>), dim3(nblk(A.n, tb)), dim3(tb), 0, st, A.n, A.sl_ptr, A.col, val, z, w);
 }
 template void launch_spmv_outer<double>(hipStream_t, Sell, const double*, const double*, double*);
 template void launch_spmv_outer<float>(hipStream_t, Sell, const double*, const float*, double*);
@@ -562,15 +616,35 @@ int64_t red_blocks(int64_t m) { return std::max<int64_t>(1, std::min<int64_t>(RE
 void launch_norm_part(hipStream_t st, int64_t m, const double* x, double* part) {
   hipLaunchKernelGGL(k_norm_part, dim3((unsigned)red_blocks(m)), dim3(TPB), 0, st, m, x, part);
 }
+
+#define LLG_NV_CASES(X) \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) \
+  X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+
 void launch_mdot(hipStream_t st, int64_t m, int nv, const double* V, int64_t ldv, const double* w,
                  double* part) {
-  hipLaunchKernelGGL(k_mdot, dim3((unsigned)red_blocks(m)), dim3(TPB), 0, st, m, nv, V, ldv, w, part);
+  const dim3 g((unsigned)red_blocks(m)), t(TPB);
+  switch (nv) {
+#define X(K) \
+  case K: hipLaunchKernelGGL((k_mdot<K>), g, t, 0, st, m, V, ldv, w, part); break;
+    LLG_NV_CASES(X)
+#undef X
+    default: break;
+  }
 }
-void launch_mupdate_dot(hipStream_t st, int64_t m, int nv, const double* V, int64_t ldv,
-                        const double* h, double* w, double* part, int want_dots) {
-  hipLaunchKernelGGL(k_mupdate_dot, dim3((unsigned)red_blocks(m)), dim3(TPB), 0, st, m, nv, V, ldv, h, w,
-                     part, want_dots);
+
+void launch_mupdate_dot(hipStream_t st, int64_t m, int nv, const double* V, int64_t ldv, const double* h,
+                        double* w, double* part, int want_dots, const double* skip) {
+  const dim3 g((unsigned)red_blocks(m)), t(TPB);
+  switch (nv) {
+#define X(K) \
+  case K: hipLaunchKernelGGL((k_mupdate_dot<K>), g, t, 0, st, m, V, ldv, h, w, part, want_dots, skip); break;
+    LLG_NV_CASES(X)
+#undef X
+    default: break;
+  }
 }
+
 void launch_scale_vec(hipStream_t st, int64_t m, const double* x, const double* s, double* y) {
   if (m > 0) hipLaunchKernelGGL(k_scale_vec, dim3(nblk(m)), dim3(TPB), 0, st, m, x, s, y);
 }
@@ -594,16 +668,18 @@ void launch_project(hipStream_t st, int64_t n, const double* u, double* out, int
 
 void launch_norm_finish_n(hipStream_t st, const double* part, int64_t nparts, int slot, double* sc,
                           double* host) {
-  hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(TPB), 0, st, part, nparts, slot, sc, host);
+  hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(64), 0, st, part, nparts, slot, sc, host);
 }
-void launch_dots_finish_n(hipStream_t st, const double* part, int64_t nparts, int nv, double* hcol,
-                          double* delta, int accumulate, double* normsq) {
-  hipLaunchKernelGGL(k_dots_finish, dim3(1), dim3(TPB), 0, st, part, nparts, nv, hcol, delta, accumulate,
-                     normsq);
+void launch_dots_finish_n(hipStream_t st, const double* part, int64_t nparts, int nv, double* hcol, double* sc) {
+  hipLaunchKernelGGL(k_dots_finish, dim3(1), dim3(1024), 0, st, part, nparts, nv, hcol, sc);
+}
+void launch_reorth_finish_n(hipStream_t st, const double* part, int64_t nparts, int nv, double* hcol,
+                            double* delta, double* sc) {
+  hipLaunchKernelGGL(k_reorth_finish, dim3(1), dim3(1024), 0, st, part, nparts, nv, hcol, delta, sc);
 }
 void launch_arnoldi_finish_n(hipStream_t st, const double* part, int64_t nparts, int j, int R,
                              KrylovScalars ks, double* host) {
-  hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), dim3(TPB), 0, st, part, nparts, j, R, ks, host);
+  hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), dim3(64), 0, st, part, nparts, j, R, ks, host);
 }
 void launch_cycle_start(hipStream_t st, int R, KrylovScalars ks) {
   hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(64), 0, st, R, ks);

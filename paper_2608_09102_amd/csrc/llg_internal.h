@@ -60,9 +60,11 @@ void launch_sell_cols(hipStream_t st, int64_t n, const int32_t* brp, const int32
 
 // pairwise matching (one pass)
 void launch_row_max(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gw, int32_t* mx);
+void launch_node_rank(hipStream_t st, int64_t n, uint64_t salt, uint64_t* rank);
+// prop[i] = proposed partner or -1; *any is set non-zero when some node proposes
 void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci,
-                    const int32_t* gw, const int32_t* mx, const int32_t* mate, uint64_t salt,
-                    int32_t bnum, int32_t bden, int32_t* prop, int32_t* count);
+                    const int32_t* gw, const int32_t* mx, const int32_t* mate, const uint64_t* rank,
+                    uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop, int32_t* any);
 void launch_accept(hipStream_t st, int64_t n, const int32_t* prop, int32_t* mate);
 void launch_leader_flag(hipStream_t st, int64_t n, const int32_t* mate, int32_t* flag);
 void launch_assign(hipStream_t st, int64_t n, const int32_t* mate, const int32_t* id, int32_t* agg,
@@ -106,9 +108,11 @@ void launch_smooth_first(hipStream_t st, Sell A, const T* dinv, double omega, co
 template <typename T>
 void launch_residual(hipStream_t st, Sell A, const T* val, int xmode, double omega, const T* b,
                      const T* x, T* r);
+// bc = P^T r (members ascending); xc = omega Dc^{-1} bc when xc != NULL (the
+// first pre-smoothing sweep of the coarse level)
 template <typename T>
-void launch_restrict(hipStream_t st, int64_t nc, const int32_t* mptr, const int32_t* mem,
-                     const T* r, T* bc);
+void launch_restrict(hipStream_t st, int64_t nc, const int32_t* mptr, const int32_t* mem, const T* r, T* bc,
+                     const T* cdinv, double omega, T* xc);
 // out = x' + omega D^{-1} (b - A x') with x' = xbase + P ec (ec may be NULL)
 template <typename T>
 void launch_post_smooth(hipStream_t st, Sell A, const T* val, const T* dinv, int unit, int xmode,
@@ -131,8 +135,10 @@ void launch_resid_outer(hipStream_t st, Sell A, const double* val, const double*
 void launch_norm_part(hipStream_t st, int64_t m, const double* x, double* part);
 void launch_mdot(hipStream_t st, int64_t m, int nv, const double* V, int64_t ldv, const double* w,
                  double* part);
+// w -= sum_q h_q V_q and, in the same sweep, the dots of the new w (when
+// want_dots) and its squared norm; skipped when skip != NULL and *skip == 0
 void launch_mupdate_dot(hipStream_t st, int64_t m, int nv, const double* V, int64_t ldv,
-                        const double* h, double* w, double* part, int want_dots);
+                        const double* h, double* w, double* part, int want_dots, const double* skip);
 void launch_scale_vec(hipStream_t st, int64_t m, const double* x, const double* s, double* y);
 template <typename TS, typename TD>
 void launch_cast(hipStream_t st, int64_t m, const TS* x, TD* y);
@@ -154,10 +160,11 @@ struct KrylovScalars {
 int64_t red_blocks(int64_t m);  // partial-sum count of the grid reductions over m doubles
 void launch_norm_finish_n(hipStream_t st, const double* part, int64_t nparts, int slot, double* sc,
                           double* host);
-// sum the partial dots of one pass: entries i < nv go to hcol (assign) or to
-// delta and hcol (accumulate); entry nv (a squared norm) goes to *normsq
-void launch_dots_finish_n(hipStream_t st, const double* part, int64_t nparts, int nv, double* hcol,
-                          double* delta, int accumulate, double* normsq);
+// pass-1 sums: hcol[q] (q < nv) and sc[5] = ||w||^2
+void launch_dots_finish_n(hipStream_t st, const double* part, int64_t nparts, int nv, double* hcol, double* sc);
+// pass-2 sums and the reorthogonalization decision (sc[7]), delta = second coefficients
+void launch_reorth_finish_n(hipStream_t st, const double* part, int64_t nparts, int nv, double* hcol,
+                            double* delta, double* sc);
 void launch_arnoldi_finish_n(hipStream_t st, const double* part, int64_t nparts, int j, int R,
                              KrylovScalars ks, double* host);
 void launch_cycle_start(hipStream_t st, int R, KrylovScalars ks);
