@@ -36,6 +36,7 @@ def parse():
     p.add_argument("--workload", default="rough2d_1024")
     p.add_argument("--forms", default="fp64,fp32_amg", help="comma list; the first gives `value`")
     p.add_argument("--roofline-class", default="outer_spmv")
+    p.add_argument("--alpha", type=float, default=None, help="override the workload's alpha")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=1)
     p.add_argument("--serve", action="store_true",
@@ -86,16 +87,25 @@ def algorithmic_bytes(cls: str, st, N: int, precision: str) -> float:
     raise ValueError("no byte model for kernel class " + cls)
 
 
-def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str):
+def forcing_list(torch, w, total: int):
+    """Manufactured forcing F(t_{k+1}) for every step of the run, resident on
+    the device before the timed region (None when the workload has none)."""
+    if not w.forcing:
+        return [None] * total
+    import llg_inputs as I
+    return [torch.from_numpy(I.manufactured_forcing(w.dim, w.n, (k + 1) * w.dt, w.alpha)).cuda()
+            for k in range(total)]
+
+
+def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str, Fs):
     opts = llg.default_opts(rtol=w.rtol, precision=form)
     grid = llg.make_grid(w.dim, w.n)
     S = llg.Solver(grid, opts)
     m0 = torch.from_numpy(w.m0()).cuda()
     bufs = [m0.clone(), torch.empty_like(m0)]
-    F = None
     cur = 0
     for k in range(warmup):
-        _, s, st = S.step(bufs[cur], w.alpha, w.dt, forcing=F, out=bufs[1 - cur])
+        _, s, st = S.step(bufs[cur], w.alpha, w.dt, forcing=Fs[k], out=bufs[1 - cur])
         cur = 1 - cur
         log("  warmup %d: iters %d, %.1f ms" % (k, st.iters, st.ms_total))
     S.set_kernel_timing(cls)
@@ -105,7 +115,7 @@ def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        _, s, st = S.step(bufs[cur], w.alpha, w.dt, forcing=F, out=bufs[1 - cur])
+        _, s, st = S.step(bufs[cur], w.alpha, w.dt, forcing=Fs[warmup + k], out=bufs[1 - cur])
         cur = 1 - cur
         if s != llg.OK:
             raise RuntimeError("step %d: %s" % (k, llg.status_str(s)))
@@ -115,11 +125,22 @@ def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     S.set_kernel_timing("none")
+    final = bufs[cur]
+    err_exact = None
+    if w.forcing:
+        import llg_inputs as I
+        me = torch.from_numpy(I.exact_solution(w.dim, w.n, (warmup + steps) * w.dt)).cuda()
+        err_exact = float((final - me).abs().max())
     # single step from m0 for the cross-form comparison (outside the timed region)
-    one, _, _ = S.step(m0, w.alpha, w.dt)
-    return {"seconds": el, "iters": iters, "kernel_ms": kms, "kernel_launches": klaunch, "stats": st,
-            "one_step": one, "levels": st.levels, "level_nodes": list(st.level_nodes[:st.levels]),
-            "level_nnzb": list(st.level_nnzb[:st.levels])}
+    one, _, _ = S.step(m0, w.alpha, w.dt, forcing=Fs[0])
+    res = {"seconds": el, "iters": iters, "kernel_ms": kms, "kernel_launches": klaunch, "stats": st,
+           "one_step": one, "levels": st.levels, "level_nodes": list(st.level_nodes[:st.levels]),
+           "level_nnzb": list(st.level_nnzb[:st.levels]), "err_vs_exact": err_exact,
+           "workspace_GB": S.workspace_bytes / 1e9}
+    S.close()
+    del S
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(w, nsteps: int):
@@ -196,11 +217,14 @@ def main():
         serve_bench(a)
         return
     w = I.WORKLOADS[a.workload]
+    if a.alpha is not None:
+        w.alpha = a.alpha
     forms = [f for f in a.forms.split(",") if f]
+    Fs = forcing_list(torch, w, a.warmup + a.steps)
     res = {}
     for f in forms:
         log("[bench] %s %s: %d warmup + %d timed steps" % (w.name, f, a.warmup, a.steps))
-        res[f] = run_form(llg, torch, w, f, a.steps, a.warmup, a.roofline_class)
+        res[f] = run_form(llg, torch, w, f, a.steps, a.warmup, a.roofline_class, Fs)
         r = res[f]
         log("  %.3f s, %.2f ms/step, iters/step %.1f, %s kernel %.3f ms over %d launches"
             % (r["seconds"], 1e3 * r["seconds"] / a.steps, sum(r["iters"]) / len(r["iters"]),
@@ -232,7 +256,9 @@ def main():
                    "form": main_form, "hierarchy": "rebuilt every step", "krylov": "FGMRES(30)",
                    "preconditioner": "aggregation AMG V(1,1) block-Jacobi"},
         "iters_per_step": sum(r["iters"]) / len(r["iters"]),
+        "iters": r["iters"],
         "levels": r["levels"],
+        "workspace_GB": r["workspace_GB"],
         "level_nodes": r["level_nodes"],
         "roofline": {"bound": "hbm", "kernel": a.roofline_class, "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
@@ -244,8 +270,11 @@ def main():
         diff = float((rf["one_step"] - r["one_step"]).abs().max())
         out[f] = {"value": unknowns * a.steps / rf["seconds"], "ms_per_step": 1e3 * rf["seconds"] / a.steps,
                   "iters_per_step": sum(rf["iters"]) / len(rf["iters"]),
+                  "iters": rf["iters"], "err_vs_exact": rf["err_vs_exact"],
                   "speedup_vs_" + main_form: (unknowns * a.steps / rf["seconds"]) / value,
                   "max_abs_diff_one_step_vs_" + main_form: diff}
+    if r["err_vs_exact"] is not None:
+        out["err_vs_exact"] = r["err_vs_exact"]
     if not a.no_cpu_baseline:
         log("[bench] cpu baseline: oracle, %d step(s)" % a.cpu_steps)
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)

@@ -411,11 +411,35 @@ double dot(int64_t m, const double* x, const double* y) {
 
 double nrm2(int64_t m, const double* x) { return std::sqrt(dot(m, x, x)); }
 
-// ------------------------------------------------------ V-cycle (O7, O9, Sec. 3)
+// ------------------------------------------------------ V-cycle / K-cycle (Sec. 3, Sec. 3.1)
 // Multigrid = smoothing + coarse grid correction; damped block Jacobi with
 // nu_pre / nu_post sweeps, restriction P^T, prolongation P, exact solve at the
-// coarsest level.
-void vcycle(const Hier& H, size_t l, const double* b, double* x) {
+// coarsest level.  With kcycle_depth > 0 the coarse residual equation of
+// levels 1..depth is solved by two steps of minimal-residual (GCR)
+// acceleration preconditioned by the cycle of that level (the K-cycle that
+// Sec. 3.1 describes as Krylov acceleration at each level).
+void cycle(const Hier& H, size_t l, const double* b, double* x);
+
+void spmv_level(const Hier& H, size_t l, const double* x, double* y) { spmv(H.lv[l].A, x, y); }
+
+// e ~ A_lc^{-1} r: two GCR steps, search directions v1 = B r, v2 = B rho.
+void kcycle_correction(const Hier& H, size_t lc, const double* r, double* e) {
+  const int64_t m = 3 * H.lv[lc].A.n;
+  std::vector<double> v1(m), w1(m), rho(m), v2(m), w2(m), w2p(m);
+  cycle(H, lc, r, v1.data());
+  spmv_level(H, lc, v1.data(), w1.data());
+  const double a1 = dot(m, w1.data(), r) / dot(m, w1.data(), w1.data());
+  for (int64_t i = 0; i < m; ++i) rho[i] = r[i] - a1 * w1[i];
+  cycle(H, lc, rho.data(), v2.data());
+  spmv_level(H, lc, v2.data(), w2.data());
+  const double gamma = dot(m, w1.data(), w2.data()) / dot(m, w1.data(), w1.data());
+  for (int64_t i = 0; i < m; ++i) w2p[i] = w2[i] - gamma * w1[i];
+  const double a2 = dot(m, w2p.data(), rho.data()) / dot(m, w2p.data(), w2p.data());
+  // e = a1 v1 + a2 (v2 - gamma v1)
+  for (int64_t i = 0; i < m; ++i) e[i] = a1 * v1[i] + a2 * (v2[i] - gamma * v1[i]);
+}
+
+void cycle(const Hier& H, size_t l, const double* b, double* x) {
   const Level& L = H.lv[l];
   const int64_t n = L.A.n, m = 3 * n;
   if (l + 1 == H.lv.size()) {
@@ -437,7 +461,11 @@ void vcycle(const Hier& H, size_t l, const double* b, double* x) {
   std::vector<double> bc(3 * nc, 0.0), xc(3 * nc, 0.0);
   for (int64_t i = 0; i < n; ++i)  // restriction: P^T r
     for (int c = 0; c < 3; ++c) bc[3 * (int64_t)L.agg[i] + c] += r[3 * i + c];
-  vcycle(H, l + 1, bc.data(), xc.data());
+  const size_t lc = l + 1;
+  if (lc + 1 < H.lv.size() && (int)lc <= H.o.kcycle_depth)
+    kcycle_correction(H, lc, bc.data(), xc.data());
+  else
+    cycle(H, lc, bc.data(), xc.data());
   for (int64_t i = 0; i < n; ++i)  // prolongation: x += P e
     for (int c = 0; c < 3; ++c) x[3 * i + c] += xc[3 * (int64_t)L.agg[i] + c];
   for (int s = 0; s < H.o.nu_post; ++s) {
@@ -454,9 +482,9 @@ void precond(const Hier& H, const double* v, double* z) {
   if (H.o.left_scale) {
     std::vector<double> s(m);
     apply_blocks(H.dinv0, H.A.n, v, s.data());
-    vcycle(H, 0, s.data(), z);
+    cycle(H, 0, s.data(), z);
   } else {
-    vcycle(H, 0, v, z);
+    cycle(H, 0, v, z);
   }
 }
 
@@ -670,7 +698,7 @@ int build(Hier& H, const double* m_tilde, double alpha, double dt) {
 bool opts_ok(const llgo_opts* o) {
   return o && o->rtol >= 0 && o->restart >= 1 && o->max_iters >= 1 && o->nu_pre >= 0 &&
          o->nu_post >= 0 && o->npass >= 1 && o->beta_num >= 0 && o->beta_den >= 1 &&
-         o->max_coarse >= 1 && o->max_levels >= 1 && o->max_dense >= 1;
+         o->max_coarse >= 1 && o->max_levels >= 1 && o->max_dense >= 1 && o->kcycle_depth >= 0;
 }
 
 }  // namespace
@@ -696,6 +724,7 @@ void llgo_default_opts(llgo_opts* o) {
   o->x0_is_mn = 1;
   o->agg_salt = 0;
   o->krylov = 0;
+  o->kcycle_depth = 0;
 }
 
 uint64_t llgo_splitmix64(uint64_t x) { return splitmix64(x); }

@@ -65,6 +65,7 @@ typedef struct {
   int32_t x0_is_mn;     /* initial guess m^n (else zero) */
   uint64_t agg_salt;
   int32_t krylov;       /* 0 = FGMRES, 1 = GCR (Algorithm 1) */
+  int32_t kcycle_depth; /* coarse corrections of levels 1..depth by the K-cycle (0: V-cycle) */
 } llgo_opts;
 
 typedef struct {
