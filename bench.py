@@ -34,9 +34,11 @@ def parse():
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="rough2d_1024")
-    p.add_argument("--forms", default="fp64,fp32_amg", help="comma list; the first gives `value`")
+    p.add_argument("--forms", default="fp64:1,fp32_amg:1,fp64:0",
+                   help="comma list of precision:kcycle_depth (0 = V-cycle); the first gives `value`")
     p.add_argument("--roofline-class", default="outer_spmv")
     p.add_argument("--alpha", type=float, default=None, help="override the workload's alpha")
+    p.add_argument("--kdepth", type=int, default=None, help="override the K-cycle depth of every form")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=1)
     p.add_argument("--serve", action="store_true",
@@ -50,8 +52,10 @@ def parse():
 
 
 def source_sha() -> str:
+    """Hash of the sources the solve kernels are compiled from (the PMC
+    summary is only valid for the kernel source it was taken on)."""
     h = hashlib.sha256()
-    for f in ("k_solve.hip", "k_setup.hip", "engine.hip", "llg_internal.h"):
+    for f in ("k_solve.hip", "llg_internal.h"):
         with open(os.path.join(ROOT, "paper_2608_09102_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -97,8 +101,8 @@ def forcing_list(torch, w, total: int):
             for k in range(total)]
 
 
-def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str, Fs):
-    opts = llg.default_opts(rtol=w.rtol, precision=form)
+def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str, Fs, kdepth: int = 0):
+    opts = llg.default_opts(rtol=w.rtol, precision=form, kcycle_depth=kdepth)
     grid = llg.make_grid(w.dim, w.n)
     S = llg.Solver(grid, opts)
     m0 = torch.from_numpy(w.m0()).cuda()
@@ -219,18 +223,26 @@ def main():
     w = I.WORKLOADS[a.workload]
     if a.alpha is not None:
         w.alpha = a.alpha
-    forms = [f for f in a.forms.split(",") if f]
+    forms = []
+    for f in a.forms.split(","):
+        if not f:
+            continue
+        prec, _, kd = f.partition(":")
+        kd = int(kd) if kd else 0
+        if a.kdepth is not None:
+            kd = a.kdepth
+        forms.append((f, prec, kd))
     Fs = forcing_list(torch, w, a.warmup + a.steps)
     res = {}
-    for f in forms:
-        log("[bench] %s %s: %d warmup + %d timed steps" % (w.name, f, a.warmup, a.steps))
-        res[f] = run_form(llg, torch, w, f, a.steps, a.warmup, a.roofline_class, Fs)
-        r = res[f]
+    for key, prec, kd in forms:
+        log("[bench] %s %s kcycle_depth %d: %d warmup + %d timed steps" % (w.name, prec, kd, a.warmup, a.steps))
+        res[key] = run_form(llg, torch, w, prec, a.steps, a.warmup, a.roofline_class, Fs, kd)
+        r = res[key]
         log("  %.3f s, %.2f ms/step, iters/step %.1f, %s kernel %.3f ms over %d launches"
             % (r["seconds"], 1e3 * r["seconds"] / a.steps, sum(r["iters"]) / len(r["iters"]),
                a.roofline_class, r["kernel_ms"], r["kernel_launches"]))
-    main_form = forms[0]
-    r = res[main_form]
+    main_key, main_form, main_kd = forms[0]
+    r = res[main_key]
     unknowns = w.unknowns
     value = unknowns * a.steps / r["seconds"]
     # roofline of the timed kernel class
@@ -254,7 +266,8 @@ def main():
         "config": {"workload": w.name, "grid": "%dD %s" % (w.dim, "x".join([str(w.n)] * w.dim)),
                    "unknowns": unknowns, "alpha": w.alpha, "dt": w.dt, "rtol": w.rtol,
                    "form": main_form, "hierarchy": "rebuilt every step", "krylov": "FGMRES(30)",
-                   "preconditioner": "aggregation AMG V(1,1) block-Jacobi"},
+                   "preconditioner": "aggregation AMG, damped block-Jacobi (1,1), %s" % (
+                       "K-cycle on levels 1..%d" % main_kd if main_kd else "V-cycle")},
         "iters_per_step": sum(r["iters"]) / len(r["iters"]),
         "iters": r["iters"],
         "levels": r["levels"],
@@ -265,14 +278,15 @@ def main():
                      "traffic": traffic, "algorithmic_bytes_per_launch": lb,
                      "avg_launch_us": avg_s * 1e6, "launches": r["kernel_launches"]},
     }
-    for f in forms[1:]:
-        rf = res[f]
+    for key, prec, kd in forms[1:]:
+        rf = res[key]
         diff = float((rf["one_step"] - r["one_step"]).abs().max())
-        out[f] = {"value": unknowns * a.steps / rf["seconds"], "ms_per_step": 1e3 * rf["seconds"] / a.steps,
-                  "iters_per_step": sum(rf["iters"]) / len(rf["iters"]),
-                  "iters": rf["iters"], "err_vs_exact": rf["err_vs_exact"],
-                  "speedup_vs_" + main_form: (unknowns * a.steps / rf["seconds"]) / value,
-                  "max_abs_diff_one_step_vs_" + main_form: diff}
+        name = "%s_%s" % (prec, "k%d" % kd if kd else "vcycle")
+        out[name] = {"value": unknowns * a.steps / rf["seconds"], "ms_per_step": 1e3 * rf["seconds"] / a.steps,
+                     "iters_per_step": sum(rf["iters"]) / len(rf["iters"]), "iters": rf["iters"],
+                     "err_vs_exact": rf["err_vs_exact"], "kcycle_depth": kd,
+                     "speedup_vs_main": (unknowns * a.steps / rf["seconds"]) / value,
+                     "max_abs_diff_one_step_vs_main": diff}
     if r["err_vs_exact"] is not None:
         out["err_vs_exact"] = r["err_vs_exact"]
     if not a.no_cpu_baseline:

@@ -92,6 +92,10 @@ typedef struct {
   int32_t x0_is_mn;     /* initial guess m^n (else 0) */
   uint64_t agg_salt;    /* salt of the hashed matching order */
   int32_t rebuild_aggregates; /* 1: recompute the matching every step (default) */
+  int32_t kcycle_depth; /* coarse corrections of levels 1..depth by the K-cycle (two
+                           minimal-residual steps, Sec. 3.1); 0 = V-cycle; 0..8 */
+  int32_t graphs;       /* 1: replay the step's setup and each FGMRES iteration as HIP
+                           graphs captured once per context (default); 0: eager launches */
 } llg_opts;
 
 typedef struct {

@@ -46,7 +46,8 @@ class Opts(ctypes.Structure):
         ("beta_den", ctypes.c_int32), ("max_coarse", ctypes.c_int32), ("stagnation", ctypes.c_double),
         ("max_levels", ctypes.c_int32), ("max_dense", ctypes.c_int32), ("left_scale", ctypes.c_int32),
         ("project", ctypes.c_int32), ("x0_is_mn", ctypes.c_int32), ("agg_salt", ctypes.c_uint64),
-        ("rebuild_aggregates", ctypes.c_int32),
+        ("rebuild_aggregates", ctypes.c_int32), ("kcycle_depth", ctypes.c_int32),
+        ("graphs", ctypes.c_int32),
     ]
 
 

@@ -148,10 +148,13 @@ struct Level {
   void* dinv = nullptr;
   bool unit = false;
   void *b = nullptr, *x = nullptr, *r = nullptr, *e = nullptr, *xo = nullptr;
+  // K-cycle work vectors and coefficients (levels 1..kcycle_depth)
+  void *v1 = nullptr, *v2 = nullptr, *w1 = nullptr, *w2 = nullptr, *rho = nullptr;
+  double* kc = nullptr;
 };
 
 struct PlanKey {
-  std::tuple<int, int, int, int, int, int, int, int, double, int, int, uint64_t, int, int, int> k;
+  std::tuple<int, int, int, int, int, int, int, int, double, int, int, uint64_t, int, int, int, int> k;
   bool operator<(const PlanKey& o) const { return k < o.k; }
 };
 
@@ -162,7 +165,7 @@ PlanKey plan_key(const llg_grid& g, const llg_opts& o) {
   PlanKey k;
   k.k = std::make_tuple(g.dim, g.n[0], g.n[1], g.n[2], o.npass, o.beta_num, o.beta_den, o.max_coarse,
                         o.stagnation, o.max_levels, o.max_dense, o.agg_salt, o.precision, o.restart,
-                        o.left_scale);
+                        o.left_scale, o.kcycle_depth);
   return k;
 }
 
@@ -203,6 +206,18 @@ struct llg_ctx {
   double* host = nullptr;     // pinned scalars
   int32_t* hflags = nullptr;  // pinned flags
   bool setup_done = false;
+  // HIP graphs: the step's setup (two variants: without / with forcing) and
+  // one graph per FGMRES iteration index j, captured on a private stream
+  hipStream_t cap_st = nullptr;
+  bool capturing = false;
+  bool graphs_ok = true;
+  hipGraphExec_t setup_graph[2] = {nullptr, nullptr};
+  std::vector<hipGraphExec_t> pc_graph;  // preconditioner of iteration j
+  std::vector<hipGraphExec_t> it_graph;  // Gram-Schmidt of iteration j
+  double* prm = nullptr;          // device: alpha, dt
+  double* hprm = nullptr;         // pinned staging for prm
+  double* min = nullptr;          // device copy of m^n read by the setup graph
+  double* fin = nullptr;          // device copy of the forcing
   // timing of one kernel class
   int timed = LLG_KT_NONE;
   std::vector<hipEvent_t> ev;
@@ -218,7 +233,7 @@ namespace {
 struct KTimer {
   llg_ctx& c;
   bool on;
-  KTimer(llg_ctx& cc, int cls) : c(cc), on(cc.timed == cls) {
+  KTimer(llg_ctx& cc, int cls) : c(cc), on(cc.timed == cls && !cc.capturing) {
     if (!on) return;
     if (c.ev_used + 2 > c.ev.size()) {
       for (int k = 0; k < 2; ++k) {
@@ -433,6 +448,14 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
     L.r = ar.get(ts * 3 * n, true);
     L.e = ar.get(ts * 3 * n, true);
     L.xo = ar.get(ts * 3 * n, true);
+    if (l >= 1 && l <= c.opts.kcycle_depth && l + 1 < c.L) {
+      L.v1 = ar.get(ts * 3 * n, true);
+      L.v2 = ar.get(ts * 3 * n, true);
+      L.w1 = ar.get(ts * 3 * n, true);
+      L.w2 = ar.get(ts * 3 * n, true);
+      L.rho = ar.get(ts * 3 * n, true);
+      L.kc = ar.lazy<double>(8);
+    }
   }
   c.nd = 3 * c.lv[c.L - 1].A.n;
   c.dense = ar.lazy<double>(c.nd * c.nd);
@@ -447,7 +470,9 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   c.Z = ar.get(ts * (size_t)R * c.ld, true);
   c.npart_vec = red_blocks(m);
   c.npart_rows = ceil_div(c.N, 256);
-  c.part = ar.lazy<double>(std::max<int64_t>((R + 2) * c.npart_vec, c.npart_rows) + 64);
+  int64_t kparts = 0;
+  for (int l = 1; l < c.L; ++l) kparts = std::max<int64_t>(kparts, 3 * rows_blocks(c.lv[l].A.n));
+  c.part = ar.lazy<double>(std::max<int64_t>(std::max<int64_t>((R + 2) * c.npart_vec, c.npart_rows), kparts) + 64);
   c.ks.H = ar.lazy<double>((R + 1) * R);
   c.ks.cs = ar.lazy<double>(R);
   c.ks.sn = ar.lazy<double>(R);
@@ -456,6 +481,9 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   c.ks.y = ar.lazy<double>(R);
   c.ks.sc = ar.lazy<double>(16);
   c.delta = ar.lazy<double>(R + 2);
+  c.prm = ar.lazy<double>(4);
+  c.min = ar.lazy<double>(m);
+  c.fin = ar.lazy<double>(m);
 }
 
 bool grid_ok(const llg_grid* g) {
@@ -476,7 +504,7 @@ bool opts_ok(const llg_opts* o) {
          o->npass >= 1 && o->npass <= MAX_PASS && o->beta_num >= 0 && o->beta_den >= 1 &&
          o->max_coarse >= 1 && o->max_levels >= 1 && o->max_levels <= LLG_MAX_LEVELS && o->max_dense >= 1 &&
          (o->precision == LLG_PREC_FP64 || o->precision == LLG_PREC_FP32_AMG) && std::isfinite(o->omega) &&
-         std::isfinite(o->stagnation);
+         std::isfinite(o->stagnation) && o->kcycle_depth >= 0 && o->kcycle_depth <= 8;
 }
 
 // Plan for (grid, opts): cached; computed on the current device.
@@ -520,8 +548,11 @@ std::shared_ptr<Plan> get_plan(const llg_grid& g, const llg_opts& o) {
 }
 
 // ------------------------------------------------------------------ setup
+// Everything llg_step does before the Krylov solve: the structure rebuild
+// (replayed from the plan), assembly, Galerkin products and the coarsest
+// inverse.  alpha and dt are read from c.prm on the device.
 template <typename T>
-void setup_values(llg_ctx& c, const double* m, double alpha, double dt, const double* F) {
+void setup_values(llg_ctx& c, const double* m, const double* F) {
   hipStream_t st = c.st;
   const llg_grid& g = c.grid;
   if (c.opts.rebuild_aggregates) {
@@ -536,7 +567,7 @@ void setup_values(llg_ctx& c, const double* m, double alpha, double dt, const do
   Level& L0 = c.lv[0];
   {
     KTimer kt(c, LLG_KT_ASSEMBLE);
-    launch_assemble<T>(st, g.n[0], g.n[1], g.n[2], 1.0 / (g.h * g.h), dt, alpha, c.opts.left_scale,
+    launch_assemble<T>(st, g.n[0], g.n[1], g.n[2], 1.0 / (g.h * g.h), c.prm, c.opts.left_scale,
                        c.opts.x0_is_mn, m, F, L0.A, c.Aval, (T*)L0.val, c.dinv0, (T*)L0.dinv, c.b, c.u,
                        c.flags);
     LCHK();
@@ -552,10 +583,85 @@ void setup_values(llg_ctx& c, const double* m, double alpha, double dt, const do
   launch_dense_scatter<T>(st, C.A, (const T*)C.val, c.dense);
   launch_gauss_jordan(st, c.nd, c.dense, c.piv, c.flags);
   LCHK();
+}
+
+// Graphs are used unless switched off, or a kernel class other than the outer
+// SpMV is being timed (per-kernel events need eager launches).
+bool use_graphs(const llg_ctx& c) {
+  return c.graphs_ok && c.opts.graphs && (c.timed == LLG_KT_NONE || c.timed == LLG_KT_OUTER_SPMV);
+}
+
+template <typename Fn>
+hipGraphExec_t try_capture(llg_ctx& c, Fn body);
+
+// Capture the work `body` enqueues into a graph (on the private capture
+// stream) and instantiate it.
+template <typename Fn>
+hipGraphExec_t capture_graph(llg_ctx& c, Fn body) {
+  hipStream_t saved = c.st;
+  c.st = c.cap_st;
+  c.capturing = true;
+  HIPX(hipStreamBeginCapture(c.cap_st, hipStreamCaptureModeThreadLocal));
+  hipGraph_t g = nullptr;
+  try {
+    body();
+  } catch (...) {
+    (void)hipStreamEndCapture(c.cap_st, &g);
+    if (g) (void)hipGraphDestroy(g);
+    c.st = saved;
+    c.capturing = false;
+    throw;
+  }
+  const hipError_t e = hipStreamEndCapture(c.cap_st, &g);
+  c.st = saved;
+  c.capturing = false;
+  if (e != hipSuccess) throw DevError{std::string("graph capture: ") + hipGetErrorString(e)};
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e2 = hipGraphInstantiateWithFlags(&ex, g, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) throw DevError{std::string("graph instantiate: ") + hipGetErrorString(e2)};
+  return ex;
+}
+
+// Capture, or on failure switch the context to eager launches for good.
+template <typename Fn>
+hipGraphExec_t try_capture(llg_ctx& c, Fn body) {
+  try {
+    return capture_graph(c, body);
+  } catch (const DevError& e) {
+    c.graphs_ok = false;
+    (void)hipGetLastError();
+    return nullptr;
+  }
+}
+
+void write_params(llg_ctx& c, double alpha, double dt) {
+  c.hprm[0] = alpha;
+  c.hprm[1] = dt;
+  HIPX(hipMemcpyAsync(c.prm, c.hprm, 2 * sizeof(double), hipMemcpyHostToDevice, c.st));
+}
+
+// The setup of one step from the internal copies of m^n (and F).
+template <typename T>
+void run_setup(llg_ctx& c, bool forcing) {
+  const double* F = forcing ? c.fin : nullptr;
+  if (use_graphs(c)) {
+    hipGraphExec_t& gx = c.setup_graph[forcing ? 1 : 0];
+    if (!gx) gx = try_capture(c, [&]() { setup_values<T>(c, c.min, F); });
+    if (gx) {
+      HIPX(hipGraphLaunch(gx, c.st));
+      c.setup_done = true;
+      return;
+    }
+  }
+  setup_values<T>(c, c.min, F);
   c.setup_done = true;
 }
 
 // ------------------------------------------------------------------ V-cycle
+template <typename T>
+void kcorrection(llg_ctx& c, int lc);
+
 // V(l, b): pre-smoothing from x = 0, restriction of the residual, V(l+1) on
 // the coarse residual equation, prolongation of its correction fused with
 // post-smoothing; the exact (dense inverse) solve at the coarsest level
@@ -615,7 +721,10 @@ void vcycle(llg_ctx& c, int l, const T* b, T* out) {
                        pre_next ? (T*)Nx.x : nullptr);
     LCHK();
   }
-  vcycle<T>(c, l + 1, (const T*)Nx.b, (T*)Nx.e);
+  if (Nx.kc)
+    kcorrection<T>(c, l + 1);
+  else
+    vcycle<T>(c, l + 1, (const T*)Nx.b, (T*)Nx.e);
   const T* ec = (const T*)Nx.e;
   KTimer kt(c, LLG_KT_SMOOTH);
   if (o.nu_post == 0) {
@@ -638,6 +747,31 @@ void vcycle(llg_ctx& c, int l, const T* b, T* out) {
   }
 }
 
+// Coarse correction of level lc by the K-cycle (Sec. 3.1: Krylov acceleration
+// at each level): e minimizes ||r - A_c e|| over span{v1, v2}, v1 = C(r),
+// v2 = C(r - a1 A_c v1), C the cycle of level lc.  r is lv[lc].b, whose first
+// pre-smoothing sweep the restriction has already produced; e goes to lv[lc].e.
+template <typename T>
+void kcorrection(llg_ctx& c, int lc) {
+  hipStream_t st = c.st;
+  Level& C = c.lv[lc];
+  const T* val = (const T*)C.val;
+  const int64_t G = rows_blocks(C.A.n);
+  const bool pre = c.opts.nu_pre >= 1;
+  vcycle<T>(c, lc, (const T*)C.b, (T*)C.v1);
+  launch_spmv_dots<T>(st, C.A, val, (const T*)C.v1, (T*)C.w1, (const T*)C.b, nullptr, c.part);
+  launch_kc_coef(st, c.part, G, 1, C.kc);
+  launch_kc_update<T>(st, C.A.n, (const T*)C.b, (const T*)C.w1, C.kc, (T*)C.rho, (const T*)C.dinv, c.omega,
+                      pre ? (T*)C.x : nullptr, c.part);
+  launch_kc_coef(st, c.part, G, 2, C.kc);
+  LCHK();
+  vcycle<T>(c, lc, (const T*)C.rho, (T*)C.v2);
+  launch_spmv_dots<T>(st, C.A, val, (const T*)C.v2, (T*)C.w2, (const T*)C.w1, (const T*)C.rho, c.part);
+  launch_kc_coef(st, c.part, G, 3, C.kc);
+  launch_kc_combine<T>(st, C.A.n, (const T*)C.v1, (const T*)C.v2, C.kc, (T*)C.e);
+  LCHK();
+}
+
 template <typename T>
 void precond(llg_ctx& c, const double* v, T* z) {
   Level& L0 = c.lv[0];
@@ -652,6 +786,57 @@ struct SolveOut {
   bool converged = false;
   double est = 0, truer = 0;
 };
+
+// One FGMRES iteration with basis index j, in three parts: z_j = B v_j (the
+// preconditioner cycle), w = A z_j (the outer SpMV), and the two-pass
+// classical Gram-Schmidt against v_0..v_j with the Hessenberg column, Givens
+// update and v_{j+1} = w / h_{j+1,j}.  Parts 1 and 3 are replayed as graphs;
+// the outer SpMV is a single launch, timed with events on the stream.
+template <typename T>
+void iter_precond(llg_ctx& c, int j) {
+  precond<T>(c, c.V + (int64_t)j * c.ld, (T*)c.Z + (int64_t)j * c.ld);
+}
+
+template <typename T>
+void iter_spmv(llg_ctx& c, int j) {
+  KTimer kt(c, LLG_KT_OUTER_SPMV);
+  launch_spmv_outer<T>(c.st, c.lv[0].A, c.Aval, (const T*)c.Z + (int64_t)j * c.ld, c.w);
+  LCHK();
+}
+
+void iter_arnoldi(llg_ctx& c, int j) {
+  hipStream_t st = c.st;
+  const int R = c.opts.restart;
+  const int64_t m = 3 * c.N;
+  KTimer kt(c, LLG_KT_ARNOLDI);
+  // classical Gram-Schmidt; the second pass only when the first lost more
+  // than half of ||w||^2
+  launch_mdot(st, m, j + 1, c.V, c.ld, c.w, c.part);
+  launch_dots_finish_n(st, c.part, c.npart_vec, j + 1, c.ks.hcol, c.ks.sc);
+  launch_mupdate_dot(st, m, j + 1, c.V, c.ld, c.ks.hcol, c.w, c.part, 1, nullptr);
+  launch_reorth_finish_n(st, c.part, c.npart_vec, j + 1, c.ks.hcol, c.delta, c.ks.sc);
+  launch_mupdate_dot(st, m, j + 1, c.V, c.ld, c.delta, c.w, c.part, 0, c.ks.sc + 7);
+  launch_arnoldi_finish_n(st, c.part, c.npart_vec, j, R, c.ks, c.host);
+  launch_scale_vec(st, m, c.w, c.ks.sc + 1, c.V + (int64_t)(j + 1) * c.ld);
+  LCHK();
+}
+
+template <typename T>
+void iteration(llg_ctx& c, int j) {
+  if (use_graphs(c)) {
+    if (!c.pc_graph[j]) c.pc_graph[j] = try_capture(c, [&]() { iter_precond<T>(c, j); });
+    if (use_graphs(c) && !c.it_graph[j]) c.it_graph[j] = try_capture(c, [&]() { iter_arnoldi(c, j); });
+  }
+  if (use_graphs(c)) {
+    HIPX(hipGraphLaunch(c.pc_graph[j], c.st));
+    iter_spmv<T>(c, j);
+    HIPX(hipGraphLaunch(c.it_graph[j], c.st));
+  } else {
+    iter_precond<T>(c, j);
+    iter_spmv<T>(c, j);
+    iter_arnoldi(c, j);
+  }
+}
 
 template <typename T>
 SolveOut fgmres(llg_ctx& c) {
@@ -687,27 +872,7 @@ SolveOut fgmres(llg_ctx& c) {
     LCHK();
     int j = 0;
     for (; j < R && so.iters < c.opts.max_iters; ++j) {
-      const double* vj = c.V + (int64_t)j * c.ld;
-      T* zj = Z + (int64_t)j * c.ld;
-      precond<T>(c, vj, zj);
-      {
-        KTimer kt(c, LLG_KT_OUTER_SPMV);
-        launch_spmv_outer<T>(st, L0.A, c.Aval, zj, c.w);
-        LCHK();
-      }
-      {
-        KTimer kt(c, LLG_KT_ARNOLDI);
-        // classical Gram-Schmidt; the second pass only when the first lost
-        // more than half of ||w||^2
-        launch_mdot(st, m, j + 1, c.V, c.ld, c.w, c.part);
-        launch_dots_finish_n(st, c.part, c.npart_vec, j + 1, c.ks.hcol, c.ks.sc);
-        launch_mupdate_dot(st, m, j + 1, c.V, c.ld, c.ks.hcol, c.w, c.part, 1, nullptr);
-        launch_reorth_finish_n(st, c.part, c.npart_vec, j + 1, c.ks.hcol, c.delta, c.ks.sc);
-        launch_mupdate_dot(st, m, j + 1, c.V, c.ld, c.delta, c.w, c.part, 0, c.ks.sc + 7);
-        launch_arnoldi_finish_n(st, c.part, c.npart_vec, j, R, c.ks, H);
-        launch_scale_vec(st, m, c.w, c.ks.sc + 1, c.V + (int64_t)(j + 1) * c.ld);
-        LCHK();
-      }
+      iteration<T>(c, j);
       sync(c);
       ++so.iters;
       so.est = bnorm > 0 ? H[3] / bnorm : 0;
@@ -741,9 +906,13 @@ llg_status run_step(llg_ctx& c, const double* m_n, double alpha, double dt, cons
   c.kernel_ms = 0;
   c.launches = 0;
   c.ev_used = 0;
+  const int64_t fb = (int64_t)sizeof(double) * 3 * c.N;
+  HIPX(hipMemcpyAsync(c.min, m_n, fb, hipMemcpyDeviceToDevice, c.st));
+  if (F) HIPX(hipMemcpyAsync(c.fin, F, fb, hipMemcpyDeviceToDevice, c.st));
+  write_params(c, alpha, dt);
   launch_fill_i32(c.st, c.flags, 1, 0);
   LCHK();
-  setup_values<T>(c, m_n, alpha, dt, F);
+  run_setup<T>(c, F != nullptr);
   HIPX(hipStreamSynchronize(c.st));
   const double t_setup = ms_since(t0);
   SolveOut so = fgmres<T>(c);
@@ -830,6 +999,8 @@ void llg_default_opts(llg_opts* o) {
   o->x0_is_mn = 1;
   o->agg_salt = 0;
   o->rebuild_aggregates = 1;
+  o->kcycle_depth = 0;
+  o->graphs = 1;
 }
 
 llg_status llg_workspace_bytes(const llg_grid* grid, const llg_opts* opts, size_t* bytes) {
@@ -865,6 +1036,11 @@ llg_status llg_create(const llg_grid* grid, const llg_opts* opts, void* d_worksp
     c->omega = opts->omega > 0 ? opts->omega : (grid->dim == 2 ? 4.0 / 5.0 : 6.0 / 7.0);
     HIPX(hipHostMalloc((void**)&c->host, sizeof(double) * 16, hipHostMallocDefault));
     HIPX(hipHostMalloc((void**)&c->hflags, sizeof(int32_t) * 4, hipHostMallocDefault));
+    HIPX(hipHostMalloc((void**)&c->hprm, sizeof(double) * 4, hipHostMallocDefault));
+    HIPX(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
+    c->it_graph.assign(opts->restart, nullptr);
+    c->pc_graph.assign(opts->restart, nullptr);
+    init_kernel_attributes();
     Arena ar;
     ar.mode = Mode::REPLAY;
     ar.plan = plan.get();
@@ -880,8 +1056,7 @@ llg_status llg_create(const llg_grid* grid, const llg_opts* opts, void* d_worksp
     HIPX(hipStreamSynchronize(c->st));
     if (*c->hflags & F_PLAN) {
       set_err("hierarchy structure differs from the plan");
-      (void)hipHostFree(c->host);
-      (void)hipHostFree(c->hflags);
+      llg_destroy(c.release());
       return LLG_ERR_DEVICE;
     }
     *out = c.release();
@@ -906,11 +1081,13 @@ llg_status llg_setup(llg_ctx* ctx, const double* d_m_tilde, double alpha, double
       !std::isfinite(alpha))
     return LLG_ERR_INVALID_ARG;
   return guard([&]() -> llg_status {
+    HIPX(hipMemcpyAsync(ctx->min, d_m_tilde, sizeof(double) * 3 * ctx->N, hipMemcpyDeviceToDevice, ctx->st));
+    write_params(*ctx, alpha, dt);
     launch_fill_i32(ctx->st, ctx->flags, 1, 0);
     if (ctx->opts.precision == LLG_PREC_FP32_AMG)
-      setup_values<float>(*ctx, d_m_tilde, alpha, dt, nullptr);
+      run_setup<float>(*ctx, false);
     else
-      setup_values<double>(*ctx, d_m_tilde, alpha, dt, nullptr);
+      run_setup<double>(*ctx, false);
     HIPX(hipMemcpyAsync(ctx->hflags, ctx->flags, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->st));
     sync(*ctx);
     if (*ctx->hflags & F_PLAN) return LLG_ERR_DEVICE;
@@ -1051,8 +1228,16 @@ llg_status llg_destroy(llg_ctx* ctx) {
   if (!ctx) return LLG_ERR_INVALID_ARG;
   (void)hipStreamSynchronize(ctx->st);
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
-  (void)hipHostFree(ctx->host);
-  (void)hipHostFree(ctx->hflags);
+  for (hipGraphExec_t g : ctx->pc_graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  for (hipGraphExec_t g : ctx->it_graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  for (hipGraphExec_t g : ctx->setup_graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  if (ctx->cap_st) (void)hipStreamDestroy(ctx->cap_st);
+  if (ctx->host) (void)hipHostFree(ctx->host);
+  if (ctx->hflags) (void)hipHostFree(ctx->hflags);
+  if (ctx->hprm) (void)hipHostFree(ctx->hprm);
   delete ctx;
   return LLG_OK;
 }

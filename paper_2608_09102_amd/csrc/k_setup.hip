@@ -471,7 +471,7 @@ __device__ inline void inv3(const double* D, double* R) {
 // left scaling is on; D_p^{-1} kept for the preconditioner input; b and the
 // initial guess written alongside.
 template <typename T>
-__global__ void k_assemble(int nx, int ny, int nz, double inv_h2, double dt, double alpha,
+__global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* __restrict__ prm,
                            int left_scale, int x0_is_mn, const double* __restrict__ m,
                            const double* __restrict__ F, const int32_t* __restrict__ sl_ptr,
                            const int32_t* __restrict__ col, double* __restrict__ Aval,
@@ -480,6 +480,7 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, double dt, dou
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t N = (int64_t)nx * ny * nz;
   if (p >= N) return;
+  const double alpha = prm[0], dt = prm[1];
   const double m1 = m[3 * p], m2 = m[3 * p + 1], m3 = m[3 * p + 2];
   if (!isfinite(m1) || !isfinite(m2) || !isfinite(m3)) atomicOr(flag, 1);
   int64_t nb[6];
@@ -859,20 +860,28 @@ void launch_member_sort(hipStream_t st, int64_t nc, const int32_t* mptr, int32_t
 }
 
 template <typename T>
-void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, double dt, double alpha,
+void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, const double* prm,
                      int left_scale, int x0_is_mn, const double* m, const double* F, Sell A,
                      double* Aval, T* Lval, double* dinv0, T* ldinv, double* b, double* u,
                      int32_t* flag) {
   const int64_t N = (int64_t)nx * ny * nz;
-  hipLaunchKernelGGL((k_assemble<T>), dim3(nblk(N)), dim3(TPB), 0, st, nx, ny, nz, inv_h2, dt, alpha,
+  hipLaunchKernelGGL((k_assemble<T>), dim3(nblk(N)), dim3(TPB), 0, st, nx, ny, nz, inv_h2, prm,
                      left_scale, x0_is_mn, m, F, A.sl_ptr, A.col, Aval, Lval, dinv0, ldinv, b, u, flag);
 }
-template void launch_assemble<double>(hipStream_t, int, int, int, double, double, double, int, int,
+template void launch_assemble<double>(hipStream_t, int, int, int, double, const double*, int, int,
                                       const double*, const double*, Sell, double*, double*, double*,
                                       double*, double*, double*, int32_t*);
-template void launch_assemble<float>(hipStream_t, int, int, int, double, double, double, int, int,
+template void launch_assemble<float>(hipStream_t, int, int, int, double, const double*, int, int,
                                      const double*, const double*, Sell, double*, float*, double*,
                                      float*, double*, double*, int32_t*);
+
+void init_kernel_attributes() {
+  const size_t lds_max = (size_t)(GJ_LDS_MAX * GJ_LDS_MAX + GJ_LDS_MAX + GJ_T) * sizeof(double) +
+                         GJ_T * sizeof(int32_t);
+  (void)hipFuncSetAttribute((const void*)k_gauss_jordan_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds_max);
+  (void)hipGetLastError();
+}
 
 template <typename T>
 void launch_galerkin(hipStream_t st, Sell C, T* cval, T* cdinv, const int32_t* mptr,

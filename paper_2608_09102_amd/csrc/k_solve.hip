@@ -379,6 +379,81 @@ __global__ void k_project(int64_t n, const double* __restrict__ u, double* __res
   st3(out, i, V3<double>{v.x / nrm, v.y / nrm, v.z / nrm});
 }
 
+// ------------------------------------------------------------- K-cycle
+// Coarse correction of a Krylov-accelerated level: two minimal-residual (GCR)
+// steps on A_c e = r with directions v1 = B r and v2 = B rho.  The dot
+// products are reduced in a fixed order; the coefficients stay on the device
+// (kc[0] = a1, kc[1] = w1.w1, kc[4] = w1.rho, kc[2], kc[3] = final weights).
+
+// w = A v (level operator); part[q][blk]: q = 0 w.w, q = 1 w.d1, q = 2 w.d2
+template <typename T, int ND>
+__global__ void k_spmv_dots(int64_t n, const int32_t* __restrict__ sl, const int32_t* __restrict__ col,
+                            const T* __restrict__ val, const T* __restrict__ v, T* __restrict__ w,
+                            const T* __restrict__ d1, const T* __restrict__ d2, double* __restrict__ part) {
+  __shared__ double sh[(TPB / 64) * (ND + 1)];
+  __shared__ double res[ND + 1];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc[ND + 1];
+#pragma unroll
+  for (int q = 0; q <= ND; ++q) acc[q] = 0.0;
+  if (i < n) {
+    const int64_t s = i / SL;
+    const int l = (int)(i - s * SL);
+    const int64_t cb = sl[s];
+    const int wd = (int)((sl[s + 1] - cb) / SL);
+    T a0 = 0, a1 = 0, a2 = 0;
+    sell_row_mv(col, val, cb, wd, l, [&](int32_t c) { return ld3(v, (int64_t)c); }, a0, a1, a2);
+    st3(w, i, V3<T>{a0, a1, a2});
+    const double x0 = a0, x1 = a1, x2 = a2;
+    acc[0] = (x0 * x0 + x1 * x1) + x2 * x2;
+    if (ND >= 1) {
+      const V3<T> d = ld3(d1, i);
+      acc[1 % (ND + 1)] = (x0 * (double)d.x + x1 * (double)d.y) + x2 * (double)d.z;
+    }
+    if (ND >= 2) {
+      const V3<T> d = ld3(d2, i);
+      acc[2 % (ND + 1)] = (x0 * (double)d.x + x1 * (double)d.y) + x2 * (double)d.z;
+    }
+  }
+  block_sums<ND + 1>(acc, sh, res);
+  if (threadIdx.x <= ND) part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = res[threadIdx.x];
+}
+
+// rho = r - a1 w1, x = omega D^{-1} rho (first sweep of the second inner
+// cycle, when x != NULL); part[blk] = w1 . rho
+template <typename T>
+__global__ void k_kc_update(int64_t n, const T* __restrict__ r, const T* __restrict__ w1,
+                            const double* __restrict__ kc, T* __restrict__ rho, const T* __restrict__ dinv,
+                            T omega, T* __restrict__ x, double* __restrict__ part) {
+  __shared__ double sh[TPB / 64];
+  __shared__ double res[1];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (i < n) {
+    const T a1 = (T)kc[0];
+    const V3<T> ri = ld3(r, i), wi = ld3(w1, i);
+    const V3<T> p{ri.x - a1 * wi.x, ri.y - a1 * wi.y, ri.z - a1 * wi.z};
+    st3(rho, i, p);
+    acc = ((double)wi.x * p.x + (double)wi.y * p.y) + (double)wi.z * p.z;
+    if (x) {
+      const int64_t s = i / SL;
+      const V3<T> d = dmv(dinv, s * 9 * SL + (i - s * SL), p);
+      st3(x, i, V3<T>{omega * d.x, omega * d.y, omega * d.z});
+    }
+  }
+  block_sums<1>(&acc, sh, res);
+  if (threadIdx.x == 0) part[blockIdx.x] = res[0];
+}
+
+template <typename T>
+__global__ void k_kc_combine(int64_t n, const T* __restrict__ v1, const T* __restrict__ v2,
+                             const double* __restrict__ kc, T* __restrict__ e) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * n) return;
+  const T c1 = (T)kc[2], c2 = (T)kc[3];
+  e[i] = c1 * v1[i] + c2 * v2[i];
+}
+
 // ------------------------------------------------------------- scalar work
 // One wavefront sums nparts partials in a fixed order (lane-strided sums,
 // four independent accumulators, then a shuffle tree); valid in lane 0.
@@ -394,6 +469,35 @@ __device__ inline double wave_sum(const double* __restrict__ part, int64_t npart
   double r = (a[0] + a[1]) + (a[2] + a[3]);
   for (int off = 32; off > 0; off >>= 1) r += __shfl_down(r, off, 64);
   return r;
+}
+
+// stage 1: a1 = (w1.r)/(w1.w1); stage 2: w1.rho; stage 3: the weights of
+// e = a1 v1 + a2 (v2 - gamma v1), gamma = (w1.w2)/(w1.w1),
+// a2 = (w2'.rho)/(w2'.w2') with w2' = w2 - gamma w1
+__global__ void k_kc_coef(const double* part, int64_t G, int stage, double* kc) {
+  const int wv = threadIdx.x >> 6;
+  __shared__ double s[3];
+  const int nq = stage == 2 ? 1 : (stage == 1 ? 2 : 3);
+  if (wv < nq) {
+    const double v = wave_sum(part + (int64_t)wv * G, G);
+    if ((threadIdx.x & 63) == 0) s[wv] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  if (stage == 1) {
+    kc[1] = s[0];
+    kc[0] = s[1] / s[0];
+  } else if (stage == 2) {
+    kc[4] = s[0];
+  } else {
+    const double w11 = kc[1], w22 = s[0], w12 = s[1], w2r = s[2];
+    const double gamma = w12 / w11;
+    const double num = w2r - gamma * kc[4];
+    const double den = (w22 - 2.0 * gamma * w12) + gamma * gamma * w11;
+    const double a2 = num / den;
+    kc[2] = kc[0] - a2 * gamma;
+    kc[3] = a2;
+  }
 }
 
 __global__ void k_norm_finish(const double* part, int64_t nparts, int slot, double* sc, double* host) {
@@ -687,5 +791,37 @@ void launch_cycle_start(hipStream_t st, int R, KrylovScalars ks) {
 void launch_solve_y(hipStream_t st, int k, int R, KrylovScalars ks) {
   hipLaunchKernelGGL(k_solve_y, dim3(1), dim3(64), 0, st, k, R, ks);
 }
+
+template <typename T>
+void launch_spmv_dots(hipStream_t st, Sell A, const T* val, const T* v, T* w, const T* d1, const T* d2,
+                      double* part) {
+  const dim3 g(nblk(A.n)), t(TPB);
+  if (d2)
+    hipLaunchKernelGGL((k_spmv_dots<T, 2>), g, t, 0, st, A.n, A.sl_ptr, A.col, val, v, w, d1, d2, part);
+  else
+    hipLaunchKernelGGL((k_spmv_dots<T, 1>), g, t, 0, st, A.n, A.sl_ptr, A.col, val, v, w, d1, d2, part);
+}
+template <typename T>
+void launch_kc_update(hipStream_t st, int64_t n, const T* r, const T* w1, const double* kc, T* rho,
+                      const T* dinv, double omega, T* x, double* part) {
+  hipLaunchKernelGGL((k_kc_update<T>), dim3(nblk(n)), dim3(TPB), 0, st, n, r, w1, kc, rho, dinv, (T)omega, x,
+                     part);
+}
+template <typename T>
+void launch_kc_combine(hipStream_t st, int64_t n, const T* v1, const T* v2, const double* kc, T* e) {
+  hipLaunchKernelGGL((k_kc_combine<T>), dim3(nblk(3 * n)), dim3(TPB), 0, st, n, v1, v2, kc, e);
+}
+void launch_kc_coef(hipStream_t st, const double* part, int64_t G, int stage, double* kc) {
+  hipLaunchKernelGGL(k_kc_coef, dim3(1), dim3(192), 0, st, part, G, stage, kc);
+}
+int64_t rows_blocks(int64_t n) { return ceil_div(n > 0 ? n : 1, TPB); }
+#define LLG_INST_K(T)                                                                                    \
+  template void launch_spmv_dots<T>(hipStream_t, Sell, const T*, const T*, T*, const T*, const T*, double*); \
+  template void launch_kc_update<T>(hipStream_t, int64_t, const T*, const T*, const double*, T*, const T*, \
+                                    double, T*, double*);                                                 \
+  template void launch_kc_combine<T>(hipStream_t, int64_t, const T*, const T*, const double*, T*);
+LLG_INST_K(double)
+LLG_INST_K(float)
+#undef LLG_INST_K
 
 }  // namespace llg

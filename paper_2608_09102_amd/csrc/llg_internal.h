@@ -83,8 +83,9 @@ void launch_member_fill(hipStream_t st, int64_t n, const int32_t* agg, const int
 void launch_member_sort(hipStream_t st, int64_t nc, const int32_t* mptr, int32_t* mem);
 
 // assembly of the fine operator (FP64 A) and the scaled level-0 operator
+// prm[0] = alpha, prm[1] = dt (device memory, so captured graphs stay valid)
 template <typename T>
-void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, double dt, double alpha,
+void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, const double* prm,
                      int left_scale, int x0_is_mn, const double* m, const double* F, Sell A,
                      double* Aval, T* Lval, double* dinv0, T* ldinv, double* b, double* u,
                      int32_t* flag);
@@ -93,6 +94,9 @@ void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, doub
 template <typename T>
 void launch_galerkin(hipStream_t st, Sell C, T* cval, T* cdinv, const int32_t* mptr,
                      const int32_t* mem, Sell F, const T* fval, const int32_t* agg);
+
+// one-time kernel attribute setup (large dynamic LDS for the coarsest inverse)
+void init_kernel_attributes();
 
 // coarsest level: dense copy and in-place Gauss-Jordan inverse
 template <typename T>
@@ -126,6 +130,19 @@ void launch_prolong(hipStream_t st, int64_t n, int xmode, double omega, const T*
 template <typename T>
 void launch_scale_in(hipStream_t st, int64_t n, const double* dinv0, int left_scale, const double* v,
                      T* b0);
+
+// K-cycle coarse correction (two minimal-residual steps); partial sums over
+// rows_blocks(n) blocks, coefficients in kc (see k_solve.hip)
+int64_t rows_blocks(int64_t n);
+template <typename T>
+void launch_spmv_dots(hipStream_t st, Sell A, const T* val, const T* v, T* w, const T* d1, const T* d2,
+                      double* part);
+template <typename T>
+void launch_kc_update(hipStream_t st, int64_t n, const T* r, const T* w1, const double* kc, T* rho,
+                      const T* dinv, double omega, T* x, double* part);
+template <typename T>
+void launch_kc_combine(hipStream_t st, int64_t n, const T* v1, const T* v2, const double* kc, T* e);
+void launch_kc_coef(hipStream_t st, const double* part, int64_t G, int stage, double* kc);
 
 // outer Krylov kernels (FP64)
 template <typename TZ>

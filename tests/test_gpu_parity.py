@@ -79,12 +79,13 @@ def test_setup_bitwise(gpu, orc, case):
             assert np.array_equal(S.aggregates(l), R.agg), (name, l)
 
 
+@pytest.mark.parametrize("kdepth", [0, 2, 8])
 @pytest.mark.parametrize("case", CASES[:4], ids=[c[0] for c in CASES[:4]])
-def test_operator_and_vcycle(gpu, orc, case):
+def test_operator_and_vcycle(gpu, orc, case, kdepth):
     name, dim, n, h, alpha, dt, kind = case
-    say("[operator_and_vcycle]", name)
+    say("[operator_and_vcycle]", name, "kcycle_depth", kdepth)
     m = _field(dim, n, kind)
-    gg, go, og, oo = _both(gpu, orc, dim, n, h)
+    gg, go, og, oo = _both(gpu, orc, dim, n, h, opts_kw=dict(kcycle_depth=kdepth))
     S = gpu.Solver(gg, go)
     assert S.setup(_cuda(m), alpha, dt) == gpu.OK
     H = orc.Hierarchy(og, oo, m, alpha, dt)
@@ -128,6 +129,37 @@ def test_step_vortex64_trajectory(gpu, orc):
         m_gpu, m_orc = g1, o2
 
 
+@pytest.mark.parametrize("kdepth", [2, 8])
+def test_kcycle_steps(gpu, orc, kdepth):
+    """K-cycle preconditioner: steps of the 64x64 vortex workload and of an
+    evolved rough field match the oracle to 1e-8 with the same cycle."""
+    say("[kcycle_steps] depth", kdepth)
+    w = I.WORKLOADS["vortex64"]
+    S = gpu.Solver(gpu.make_grid(2, w.n), gpu.default_opts(rtol=1e-11, kcycle_depth=kdepth))
+    og = orc.make_grid(2, w.n)
+    oo = orc.default_opts(rtol=1e-11, kcycle_depth=kdepth)
+    m = w.m0()
+    for k in range(3):
+        out, s, st = S.step(_cuda(m), w.alpha, w.dt)
+        assert s == gpu.OK
+        rc, ref, ost = orc.step(og, oo, m, w.alpha, w.dt)
+        d = np.abs(out.cpu().numpy() - ref).max()
+        say("  vortex step %d iters gpu %d orc %d diff %.2e" % (k, st.iters, ost.iters, d))
+        assert d <= 1e-8 and abs(st.iters - ost.iters) <= 2
+        m = ref
+    n, c = 96, 104.9
+    m = I.smooth_unit_field(2, n, seed=2)
+    og = orc.make_grid(2, n)
+    for _ in range(6):
+        rc, m, _ = orc.step(og, orc.default_opts(rtol=1e-8), m, 0.02, c / n ** 2)
+    S = gpu.Solver(gpu.make_grid(2, n), gpu.default_opts(rtol=1e-11, kcycle_depth=kdepth))
+    out, s, st = S.step(_cuda(m), 0.02, c / n ** 2)
+    rc, ref, ost = orc.step(og, orc.default_opts(rtol=1e-11, kcycle_depth=kdepth), m, 0.02, c / n ** 2)
+    d = np.abs(out.cpu().numpy() - ref).max()
+    say("  evolved 96^2 iters gpu %d orc %d diff %.2e" % (st.iters, ost.iters, d))
+    assert s == gpu.OK and d <= 1e-8
+
+
 @pytest.mark.parametrize("alpha", [0.01, 0.1, 1.0])
 def test_fp32_amg_small_3d(gpu, orc, alpha):
     """FP32 hierarchy inside FP64 FGMRES reaches the FP64 outer tolerance."""
@@ -159,6 +191,24 @@ def test_determinism(gpu):
     S2 = gpu.Solver(gpu.make_grid(2, 96), gpu.default_opts(rtol=1e-9))
     c, _, _ = S2.step(_cuda(m), 0.05, 1e-3)
     assert bool((a == b).all()) and bool((a == c).all())
+
+
+@pytest.mark.parametrize("kdepth", [0, 2])
+def test_graphs_match_eager(gpu, kdepth):
+    """Replaying the captured HIP graphs gives bitwise the eager result."""
+    say("[graphs_match_eager] kdepth", kdepth)
+    m = I.smooth_unit_field(2, 80, seed=9)
+    outs = []
+    for graphs in (0, 1):
+        S = gpu.Solver(gpu.make_grid(2, 80), gpu.default_opts(rtol=1e-9, graphs=graphs, kcycle_depth=kdepth))
+        x = _cuda(m)
+        for _ in range(3):  # several steps: graphs are replayed, with new alpha/dt each time
+            x, s, st = S.step(x, 0.05, 2e-3)
+            assert s == gpu.OK
+        y, s, st2 = S.step(x, 0.2, 1e-3)
+        outs.append((y.cpu().numpy(), st2.iters))
+    assert outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][0], outs[1][0])
 
 
 def test_error_paths(gpu):
