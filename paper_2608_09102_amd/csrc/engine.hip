@@ -147,6 +147,7 @@ struct Level {
   void* val = nullptr;
   void* dinv = nullptr;
   bool unit = false;
+  int G = 1;  // lanes per row in the level's sliced-ELL kernels
   void *b = nullptr, *x = nullptr, *r = nullptr, *e = nullptr, *xo = nullptr;
   // K-cycle work vectors and coefficients (levels 1..kcycle_depth)
   void *v1 = nullptr, *v2 = nullptr, *w1 = nullptr, *w2 = nullptr, *rho = nullptr;
@@ -442,6 +443,7 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
     const int64_t n = L.A.n;
     L.val = ar.get(ts * 9 * L.A.nslots, true);
     L.unit = l == 0 && c.opts.left_scale;
+    L.G = n >= 32768 ? 1 : (c.grid.dim == 3 ? 16 : 8);
     L.dinv = ar.get(ts * 9 * L.A.nslices * SL, true);
     L.b = ar.get(ts * 3 * n, true);
     L.x = ar.get(ts * 3 * n, true);
@@ -471,7 +473,7 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   c.npart_vec = red_blocks(m);
   c.npart_rows = ceil_div(c.N, 256);
   int64_t kparts = 0;
-  for (int l = 1; l < c.L; ++l) kparts = std::max<int64_t>(kparts, 3 * rows_blocks(c.lv[l].A.n));
+  for (int l = 1; l < c.L; ++l) kparts = std::max<int64_t>(kparts, 3 * rows_blocks(c.lv[l].A.n, c.lv[l].G));
   c.part = ar.lazy<double>(std::max<int64_t>(std::max<int64_t>((R + 2) * c.npart_vec, c.npart_rows), kparts) + 64);
   c.ks.H = ar.lazy<double>((R + 1) * R);
   c.ks.cs = ar.lazy<double>(R);
@@ -703,7 +705,7 @@ void vcycle(llg_ctx& c, int l, const T* b, T* out) {
     }
     for (int s = 1; s < o.nu_pre; ++s) {
       T* dst = (xcur == X) ? XO : X;
-      launch_post_smooth<T>(st, L.A, val, dinv, L.unit, xmode, om, b, xcur, nullptr, nullptr, dst);
+      launch_post_smooth<T>(st, L.A, val, dinv, L.unit, xmode, om, b, xcur, nullptr, nullptr, dst, L.G);
       xmode = 0;
       xcur = dst;
     }
@@ -714,7 +716,7 @@ void vcycle(llg_ctx& c, int l, const T* b, T* out) {
     const bool pre_next = o.nu_pre >= 1 && l + 1 < c.L - 1;
     const T* rsrc = b;
     if (xmode != 2) {
-      launch_residual<T>(st, L.A, val, xmode, om, b, xcur, (T*)L.r);
+      launch_residual<T>(st, L.A, val, xmode, om, b, xcur, (T*)L.r, L.G);
       rsrc = (const T*)L.r;
     }
     launch_restrict<T>(st, L.nc, L.mptr, L.mem, rsrc, (T*)Nx.b, pre_next ? (const T*)Nx.dinv : nullptr, om,
@@ -738,9 +740,9 @@ void vcycle(llg_ctx& c, int l, const T* b, T* out) {
     const bool last = s == o.nu_post - 1;
     T* dst = last ? out : (xcur == XO ? X : XO);
     if (s == 0) {
-      launch_post_smooth<T>(st, L.A, val, dinv, L.unit, xmode, om, b, xcur, L.agg, ec, dst);
+      launch_post_smooth<T>(st, L.A, val, dinv, L.unit, xmode, om, b, xcur, L.agg, ec, dst, L.G);
     } else {
-      launch_post_smooth<T>(st, L.A, val, dinv, L.unit, 0, om, b, xcur, nullptr, nullptr, dst);
+      launch_post_smooth<T>(st, L.A, val, dinv, L.unit, 0, om, b, xcur, nullptr, nullptr, dst, L.G);
     }
     LCHK();
     xcur = dst;
@@ -756,17 +758,17 @@ void kcorrection(llg_ctx& c, int lc) {
   hipStream_t st = c.st;
   Level& C = c.lv[lc];
   const T* val = (const T*)C.val;
-  const int64_t G = rows_blocks(C.A.n);
+  const int64_t G = rows_blocks(C.A.n, C.G);
   const bool pre = c.opts.nu_pre >= 1;
   vcycle<T>(c, lc, (const T*)C.b, (T*)C.v1);
-  launch_spmv_dots<T>(st, C.A, val, (const T*)C.v1, (T*)C.w1, (const T*)C.b, nullptr, c.part);
+  launch_spmv_dots<T>(st, C.A, val, (const T*)C.v1, (T*)C.w1, (const T*)C.b, nullptr, c.part, C.G);
   launch_kc_coef(st, c.part, G, 1, C.kc);
   launch_kc_update<T>(st, C.A.n, (const T*)C.b, (const T*)C.w1, C.kc, (T*)C.rho, (const T*)C.dinv, c.omega,
                       pre ? (T*)C.x : nullptr, c.part);
-  launch_kc_coef(st, c.part, G, 2, C.kc);
+  launch_kc_coef(st, c.part, rows_blocks(C.A.n, 1), 2, C.kc);
   LCHK();
   vcycle<T>(c, lc, (const T*)C.rho, (T*)C.v2);
-  launch_spmv_dots<T>(st, C.A, val, (const T*)C.v2, (T*)C.w2, (const T*)C.w1, (const T*)C.rho, c.part);
+  launch_spmv_dots<T>(st, C.A, val, (const T*)C.v2, (T*)C.w2, (const T*)C.w1, (const T*)C.rho, c.part, C.G);
   launch_kc_coef(st, c.part, G, 3, C.kc);
   launch_kc_combine<T>(st, C.A.n, (const T*)C.v1, (const T*)C.v2, C.kc, (T*)C.e);
   LCHK();

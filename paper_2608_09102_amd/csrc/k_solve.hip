@@ -94,20 +94,45 @@ __device__ inline V3<T> dmv(const T* __restrict__ d, int64_t db, V3<T> v) {
                d[db + 6 * SL] * v.x + d[db + 7 * SL] * v.y + d[db + 8 * SL] * v.z};
 }
 
-// row index of this thread (XCD-aware block order) and its slice position
+// Row handled by this thread (XCD-aware block order).  With G > 1, G
+// consecutive lanes share one row (small levels: their rows are latency
+// bound, so the row's slots are spread over the lanes); sub is the lane's
+// index within its group.
 struct RowPos {
-  int64_t i, s, cb;
-  int l, w;
+  int64_t i, s;
+  int l, sub;
 };
-__device__ inline RowPos row_pos(const int32_t* __restrict__ sl) {
+template <int G>
+__device__ inline RowPos row_pos() {
   const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t t = (int64_t)blk * blockDim.x + threadIdx.x;
   RowPos p;
-  p.i = (int64_t)blk * blockDim.x + threadIdx.x;
+  p.i = t / G;
+  p.sub = (int)(t - p.i * G);
   p.s = p.i / SL;
   p.l = (int)(p.i - p.s * SL);
-  p.cb = 0;
-  p.w = 0;
   return p;
+}
+
+// Row product with the slots of the row split over the G lanes of a group,
+// then a butterfly sum inside the group (every lane ends with the total).
+template <int G, typename T, typename TA, typename XF>
+__device__ inline void sell_row_mv_g(const int32_t* __restrict__ col, const T* __restrict__ val, int64_t cb,
+                                     int w, int l, int sub, XF xf, TA& a0, TA& a1, TA& a2) {
+  if (G == 1) {
+    sell_row_mv(col, val, cb, w, l, xf, a0, a1, a2);
+    return;
+  }
+  for (int t = sub; t < w; t += G) {
+    const int32_t c = col[cb + (int64_t)t * SL + l];
+    if (c >= 0) blk_mv(val, cb * 9 + (int64_t)t * 9 * SL + l, xf(c), a0, a1, a2);
+  }
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) {
+    a0 += __shfl_xor(a0, off, G);
+    a1 += __shfl_xor(a1, off, G);
+    a2 += __shfl_xor(a2, off, G);
+  }
 }
 
 // ------------------------------------------------------------- level kernels
@@ -124,16 +149,18 @@ __global__ void k_smooth_first(int64_t n, const T* __restrict__ dinv, T omega, c
 }
 
 // r = b - A x
-template <typename T, int XMODE>
+template <typename T, int XMODE, int G>
 __global__ void k_residual(int64_t n, const int32_t* __restrict__ sl, const int32_t* __restrict__ col,
                            const T* __restrict__ val, T omega, const T* __restrict__ b,
                            const T* __restrict__ x, T* __restrict__ r) {
-  RowPos p = row_pos(sl);
+  const RowPos p = row_pos<G>();
   if (p.i >= n) return;
   const int64_t cb = sl[p.s];
   const int w = (int)((sl[p.s + 1] - cb) / SL);
   T a0 = 0, a1 = 0, a2 = 0;
-  sell_row_mv(col, val, cb, w, p.l, [&](int32_t c) { return xval<T, XMODE>(x, b, omega, c); }, a0, a1, a2);
+  sell_row_mv_g<G>(col, val, cb, w, p.l, p.sub, [&](int32_t c) { return xval<T, XMODE>(x, b, omega, c); }, a0,
+                   a1, a2);
+  if (p.sub != 0) return;
   const V3<T> bi = ld3(b, p.i);
   st3(r, p.i, V3<T>{bi.x - a0, bi.y - a1, bi.z - a2});
 }
@@ -163,13 +190,13 @@ __global__ void k_restrict(int64_t nc, const int32_t* __restrict__ mptr, const i
 }
 
 // out_i = x'_i + omega D_i^{-1} (b_i - sum_j A_ij x'_j), x'_j = xbase_j + ec[agg_j]
-template <typename T, int XMODE, bool UNIT>
+template <typename T, int XMODE, bool UNIT, int G>
 __global__ void k_post_smooth(int64_t n, const int32_t* __restrict__ sl, const int32_t* __restrict__ col,
                               const T* __restrict__ val, const T* __restrict__ dinv, T omega,
                               const T* __restrict__ b, const T* __restrict__ x,
                               const int32_t* __restrict__ agg, const T* __restrict__ ec,
                               T* __restrict__ out) {
-  RowPos p = row_pos(sl);
+  const RowPos p = row_pos<G>();
   if (p.i >= n) return;
   const int64_t cb = sl[p.s];
   const int w = (int)((sl[p.s + 1] - cb) / SL);
@@ -184,7 +211,8 @@ __global__ void k_post_smooth(int64_t n, const int32_t* __restrict__ sl, const i
     return xj;
   };
   T a0 = 0, a1 = 0, a2 = 0;
-  sell_row_mv(col, val, cb, w, p.l, [&](int32_t c) { return xp(c); }, a0, a1, a2);
+  sell_row_mv_g<G>(col, val, cb, w, p.l, p.sub, [&](int32_t c) { return xp(c); }, a0, a1, a2);
+  if (p.sub != 0) return;
   const V3<T> xi = xp(p.i);
   const V3<T> bi = ld3(b, p.i);
   V3<T> res{bi.x - a0, bi.y - a1, bi.z - a2};
@@ -220,7 +248,7 @@ template <typename TZ>
 __global__ void k_spmv_outer(int64_t n, const int32_t* __restrict__ sl, const int32_t* __restrict__ col,
                              const double* __restrict__ val, const TZ* __restrict__ z,
                              double* __restrict__ w) {
-  RowPos p = row_pos(sl);
+  const RowPos p = row_pos<1>();
   if (p.i >= n) return;
   const int64_t cb = sl[p.s];
   const int wd = (int)((sl[p.s + 1] - cb) / SL);
@@ -386,13 +414,15 @@ __global__ void k_project(int64_t n, const double* __restrict__ u, double* __res
 // (kc[0] = a1, kc[1] = w1.w1, kc[4] = w1.rho, kc[2], kc[3] = final weights).
 
 // w = A v (level operator); part[q][blk]: q = 0 w.w, q = 1 w.d1, q = 2 w.d2
-template <typename T, int ND>
+template <typename T, int ND, int G>
 __global__ void k_spmv_dots(int64_t n, const int32_t* __restrict__ sl, const int32_t* __restrict__ col,
                             const T* __restrict__ val, const T* __restrict__ v, T* __restrict__ w,
                             const T* __restrict__ d1, const T* __restrict__ d2, double* __restrict__ part) {
   __shared__ double sh[(TPB / 64) * (ND + 1)];
   __shared__ double res[ND + 1];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t / G;
+  const int sub = (int)(t - i * G);
   double acc[ND + 1];
 #pragma unroll
   for (int q = 0; q <= ND; ++q) acc[q] = 0.0;
@@ -402,17 +432,19 @@ __global__ void k_spmv_dots(int64_t n, const int32_t* __restrict__ sl, const int
     const int64_t cb = sl[s];
     const int wd = (int)((sl[s + 1] - cb) / SL);
     T a0 = 0, a1 = 0, a2 = 0;
-    sell_row_mv(col, val, cb, wd, l, [&](int32_t c) { return ld3(v, (int64_t)c); }, a0, a1, a2);
-    st3(w, i, V3<T>{a0, a1, a2});
-    const double x0 = a0, x1 = a1, x2 = a2;
-    acc[0] = (x0 * x0 + x1 * x1) + x2 * x2;
-    if (ND >= 1) {
-      const V3<T> d = ld3(d1, i);
-      acc[1 % (ND + 1)] = (x0 * (double)d.x + x1 * (double)d.y) + x2 * (double)d.z;
-    }
-    if (ND >= 2) {
-      const V3<T> d = ld3(d2, i);
-      acc[2 % (ND + 1)] = (x0 * (double)d.x + x1 * (double)d.y) + x2 * (double)d.z;
+    sell_row_mv_g<G>(col, val, cb, wd, l, sub, [&](int32_t c) { return ld3(v, (int64_t)c); }, a0, a1, a2);
+    if (sub == 0) {
+      st3(w, i, V3<T>{a0, a1, a2});
+      const double x0 = a0, x1 = a1, x2 = a2;
+      acc[0] = (x0 * x0 + x1 * x1) + x2 * x2;
+      if (ND >= 1) {
+        const V3<T> d = ld3(d1, i);
+        acc[1 % (ND + 1)] = (x0 * (double)d.x + x1 * (double)d.y) + x2 * (double)d.z;
+      }
+      if (ND >= 2) {
+        const V3<T> d = ld3(d2, i);
+        acc[2 % (ND + 1)] = (x0 * (double)d.x + x1 * (double)d.y) + x2 * (double)d.z;
+      }
     }
   }
   block_sums<ND + 1>(acc, sh, res);
@@ -625,16 +657,27 @@ void launch_smooth_first(hipStream_t st, Sell A, const T* dinv, double omega, co
 
 template <typename T>
 void launch_residual(hipStream_t st, Sell A, const T* val, int xmode, double omega, const T* b,
-                     const T* x, T* r) {
+                     const T* x, T* r, int G) {
   if (A.n <= 0) return;
+  const int64_t nt = A.n * G;
   const int tb = tpb_rows(A.n);
-  const dim3 g(nblk(A.n, tb)), t(tb);
-  if (xmode == 0)
-    hipLaunchKernelGGL((k_residual<T, 0>), g, t, 0, st, A.n, A.sl_ptr, A.col, val, (T)omega, b, x, r);
-  else if (xmode == 1)
-    hipLaunchKernelGGL((k_residual<T, 1>), g, t, 0, st, A.n, A.sl_ptr, A.col, val, (T)omega, b, x, r);
-  else
-    hipLaunchKernelGGL((k_residual<T, 2>), g, t, 0, st, A.n, A.sl_ptr, A.col, val, (T)omega, b, x, r);
+  const dim3 g(nblk(nt, tb)), t(tb);
+  const T om = (T)omega;
+#define LLG_RS(XM, GG) \
+  hipLaunchKernelGGL((k_residual<T, XM, GG>), g, t, 0, st, A.n, A.sl_ptr, A.col, val, om, b, x, r)
+#define LLG_RSG(GG)                      \
+  if (xmode == 0) LLG_RS(0, GG);         \
+  else if (xmode == 1) LLG_RS(1, GG);    \
+  else LLG_RS(2, GG);
+  if (G == 16) {
+    LLG_RSG(16)
+  } else if (G == 8) {
+    LLG_RSG(8)
+  } else {
+    LLG_RSG(1)
+  }
+#undef LLG_RSG
+#undef LLG_RS
 }
 
 template <typename T>
@@ -648,23 +691,33 @@ void launch_restrict(hipStream_t st, int64_t nc, const int32_t* mptr, const int3
 
 template <typename T>
 void launch_post_smooth(hipStream_t st, Sell A, const T* val, const T* dinv, int unit, int xmode,
-                        double omega, const T* b, const T* x, const int32_t* agg, const T* ec, T* out) {
+                        double omega, const T* b, const T* x, const int32_t* agg, const T* ec, T* out, int G) {
   if (A.n <= 0) return;
+  const int64_t nt = A.n * G;
   const int tb = tpb_rows(A.n);
-  const dim3 g(nblk(A.n, tb)), t(tb);
+  const dim3 g(nblk(nt, tb)), t(tb);
   const T om = (T)omega;
-#define LLG_PS(XM, U)                                                                                  \
-  hipLaunchKernelGGL((k_post_smooth<T, XM, U>), g, t, 0, st, A.n, A.sl_ptr, A.col, val, dinv, om, b, x, \
+#define LLG_PS(XM, U, GG)                                                                                   \
+  hipLaunchKernelGGL((k_post_smooth<T, XM, U, GG>), g, t, 0, st, A.n, A.sl_ptr, A.col, val, dinv, om, b, x, \
                      agg, ec, out)
-  if (unit) {
-    if (xmode == 0) LLG_PS(0, true);
-    else if (xmode == 1) LLG_PS(1, true);
-    else LLG_PS(2, true);
-  } else {
-    if (xmode == 0) LLG_PS(0, false);
-    else if (xmode == 1) LLG_PS(1, false);
-    else LLG_PS(2, false);
+#define LLG_PSG(GG)                                \
+  if (unit) {                                      \
+    if (xmode == 0) LLG_PS(0, true, GG);           \
+    else if (xmode == 1) LLG_PS(1, true, GG);      \
+    else LLG_PS(2, true, GG);                      \
+  } else {                                         \
+    if (xmode == 0) LLG_PS(0, false, GG);          \
+    else if (xmode == 1) LLG_PS(1, false, GG);     \
+    else LLG_PS(2, false, GG);                     \
   }
+  if (G == 16) {
+    LLG_PSG(16)
+  } else if (G == 8) {
+    LLG_PSG(8)
+  } else {
+    LLG_PSG(1)
+  }
+#undef LLG_PSG
 #undef LLG_PS
 }
 
@@ -689,11 +742,11 @@ void launch_scale_in(hipStream_t st, int64_t n, const double* dinv0, int left_sc
 
 #define LLG_INST(T)                                                                                         \
   template void launch_smooth_first<T>(hipStream_t, Sell, const T*, double, const T*, T*);                  \
-  template void launch_residual<T>(hipStream_t, Sell, const T*, int, double, const T*, const T*, T*);      \
+  template void launch_residual<T>(hipStream_t, Sell, const T*, int, double, const T*, const T*, T*, int); \
   template void launch_restrict<T>(hipStream_t, int64_t, const int32_t*, const int32_t*, const T*, T*,     \
                                    const T*, double, T*);                                                   \
   template void launch_post_smooth<T>(hipStream_t, Sell, const T*, const T*, int, int, double, const T*,   \
-                                      const T*, const int32_t*, const T*, T*);                              \
+                                      const T*, const int32_t*, const T*, T*, int);                         \
   template void launch_prolong<T>(hipStream_t, int64_t, int, double, const T*, const T*, const int32_t*,   \
                                   const T*, T*);                                                            \
   template void launch_scale_in<T>(hipStream_t, int64_t, const double*, int, const double*, T*);
@@ -794,12 +847,22 @@ void launch_solve_y(hipStream_t st, int k, int R, KrylovScalars ks) {
 
 template <typename T>
 void launch_spmv_dots(hipStream_t st, Sell A, const T* val, const T* v, T* w, const T* d1, const T* d2,
-                      double* part) {
-  const dim3 g(nblk(A.n)), t(TPB);
-  if (d2)
-    hipLaunchKernelGGL((k_spmv_dots<T, 2>), g, t, 0, st, A.n, A.sl_ptr, A.col, val, v, w, d1, d2, part);
-  else
-    hipLaunchKernelGGL((k_spmv_dots<T, 1>), g, t, 0, st, A.n, A.sl_ptr, A.col, val, v, w, d1, d2, part);
+                      double* part, int G) {
+  const dim3 g(nblk(A.n * G)), t(TPB);
+#define LLG_SD(ND, GG) \
+  hipLaunchKernelGGL((k_spmv_dots<T, ND, GG>), g, t, 0, st, A.n, A.sl_ptr, A.col, val, v, w, d1, d2, part)
+#define LLG_SDG(GG)     \
+  if (d2) LLG_SD(2, GG); \
+  else LLG_SD(1, GG);
+  if (G == 16) {
+    LLG_SDG(16)
+  } else if (G == 8) {
+    LLG_SDG(8)
+  } else {
+    LLG_SDG(1)
+  }
+#undef LLG_SDG
+#undef LLG_SD
 }
 template <typename T>
 void launch_kc_update(hipStream_t st, int64_t n, const T* r, const T* w1, const double* kc, T* rho,
@@ -814,9 +877,9 @@ void launch_kc_combine(hipStream_t st, int64_t n, const T* v1, const T* v2, cons
 void launch_kc_coef(hipStream_t st, const double* part, int64_t G, int stage, double* kc) {
   hipLaunchKernelGGL(k_kc_coef, dim3(1), dim3(192), 0, st, part, G, stage, kc);
 }
-int64_t rows_blocks(int64_t n) { return ceil_div(n > 0 ? n : 1, TPB); }
+int64_t rows_blocks(int64_t n, int G) { return ceil_div(n > 0 ? n * G : 1, TPB); }
 #define LLG_INST_K(T)                                                                                    \
-  template void launch_spmv_dots<T>(hipStream_t, Sell, const T*, const T*, T*, const T*, const T*, double*); \
+  template void launch_spmv_dots<T>(hipStream_t, Sell, const T*, const T*, T*, const T*, const T*, double*, int); \
   template void launch_kc_update<T>(hipStream_t, int64_t, const T*, const T*, const double*, T*, const T*, \
                                     double, T*, double*);                                                 \
   template void launch_kc_combine<T>(hipStream_t, int64_t, const T*, const T*, const double*, T*);

@@ -109,9 +109,10 @@ void launch_dense_apply(hipStream_t st, int64_t nd, const double* inv, const T* 
 // diagonal, first sweep from zero), 2 = x = 0.
 template <typename T>
 void launch_smooth_first(hipStream_t st, Sell A, const T* dinv, double omega, const T* b, T* x);
+// G = lanes per row (1, 8 or 16; more lanes for small, latency-bound levels)
 template <typename T>
 void launch_residual(hipStream_t st, Sell A, const T* val, int xmode, double omega, const T* b,
-                     const T* x, T* r);
+                     const T* x, T* r, int G);
 // bc = P^T r (members ascending); xc = omega Dc^{-1} bc when xc != NULL (the
 // first pre-smoothing sweep of the coarse level)
 template <typename T>
@@ -121,7 +122,7 @@ void launch_restrict(hipStream_t st, int64_t nc, const int32_t* mptr, const int3
 template <typename T>
 void launch_post_smooth(hipStream_t st, Sell A, const T* val, const T* dinv, int unit, int xmode,
                         double omega, const T* b, const T* x, const int32_t* agg, const T* ec,
-                        T* out);
+                        T* out, int G);
 // out = xbase + P ec
 template <typename T>
 void launch_prolong(hipStream_t st, int64_t n, int xmode, double omega, const T* b, const T* x,
@@ -133,10 +134,10 @@ void launch_scale_in(hipStream_t st, int64_t n, const double* dinv0, int left_sc
 
 // K-cycle coarse correction (two minimal-residual steps); partial sums over
 // rows_blocks(n) blocks, coefficients in kc (see k_solve.hip)
-int64_t rows_blocks(int64_t n);
+int64_t rows_blocks(int64_t n, int G);
 template <typename T>
 void launch_spmv_dots(hipStream_t st, Sell A, const T* val, const T* v, T* w, const T* d1, const T* d2,
-                      double* part);
+                      double* part, int G);
 template <typename T>
 void launch_kc_update(hipStream_t st, int64_t n, const T* r, const T* w1, const double* kc, T* rho,
                       const T* dinv, double omega, T* x, double* part);
