@@ -55,6 +55,7 @@ class Opts(ctypes.Structure):
         ("max_levels", ctypes.c_int32), ("max_dense", ctypes.c_int32),
         ("left_scale", ctypes.c_int32), ("project", ctypes.c_int32), ("x0_is_mn", ctypes.c_int32),
         ("agg_salt", ctypes.c_uint64), ("krylov", ctypes.c_int32), ("kcycle_depth", ctypes.c_int32),
+        ("smoother", ctypes.c_int32),
     ]
 
 
@@ -91,6 +92,7 @@ def lib() -> ctypes.CDLL:
         L.llgo_level_matrix.argtypes = [P, ctypes.c_int, P, P, P]
         L.llgo_level_dinv.argtypes = [P, ctypes.c_int, P]
         L.llgo_level_agg.argtypes = [P, ctypes.c_int, P]
+        L.llgo_level_colour.argtypes = [P, ctypes.c_int, P, P]
         L.llgo_apply_A.argtypes = [P, P, P]
         L.llgo_precond.argtypes = [P, P, P]
         L.llgo_solve.argtypes = [P, P, P, P, ctypes.POINTER(Stats)]
@@ -227,6 +229,18 @@ class Hierarchy:
             agg = np.empty(n.value, np.int32)
             assert L.llgo_level_agg(self._h, l, _p(agg)) == 0
         return LevelData(rp, ci, val, dinv, agg)
+
+    def colour(self, l: int):
+        """(colour class per node, number of classes) of level l, multicolour
+        Gauss-Seidel only."""
+        L = lib()
+        n = ctypes.c_int64(0)
+        nz = ctypes.c_int64(0)
+        assert L.llgo_level_info(self._h, l, ctypes.byref(n), ctypes.byref(nz)) == 0
+        col = np.empty(n.value, np.int32)
+        k = ctypes.c_int32(0)
+        assert L.llgo_level_colour(self._h, l, _p(col), ctypes.byref(k)) == 0
+        return col, int(k.value)
 
     def apply_A(self, x: np.ndarray) -> np.ndarray:
         x = np.ascontiguousarray(x, dtype=np.float64)

@@ -33,6 +33,8 @@ struct Level {
   std::vector<double> dinv;  // 9 per node: inverse of the diagonal block
   std::vector<int32_t> agg;  // node -> aggregate on the next level (empty at the coarsest)
   int64_t nc = 0;
+  std::vector<int32_t> colour;  // multicolour Gauss-Seidel: colour class of every node
+  int32_t ncol = 0;
 };
 
 struct Hier {
@@ -411,6 +413,70 @@ double dot(int64_t m, const double* x, const double* y) {
 
 double nrm2(int64_t m, const double* x) { return std::sqrt(dot(m, x, x)); }
 
+// ------------------------------------------------------ multicolour Gauss-Seidel (Sec. 3)
+// Colour classes are independent sets of the level's graph, so one block
+// Gauss-Seidel sweep taken class by class is the sequential sweep over the rows
+// sorted by class.
+// Level 0: the 5-/7-point grid graph is bipartite; the class is the parity of
+// i + j + k.
+void parity_colouring(const llgo_grid& g, std::vector<int32_t>& col, int32_t& ncol) {
+  const int64_t nx = g.n[0], ny = g.n[1], N = num_nodes(g);
+  col.assign(N, 0);
+  for (int64_t p = 0; p < N; ++p) {
+    const int64_t i = p % nx, j = (p / nx) % ny, k = p / (nx * ny);
+    col[p] = (int32_t)((i + j + k) & 1);
+  }
+  ncol = 2;
+}
+
+// Coarse levels: greedy colouring in priority order.  Nodes are taken by
+// ascending (node_rank(v, salt), v); each takes the smallest colour that no
+// already coloured neighbour has.
+void greedy_colouring(const Graph& G, uint64_t salt, std::vector<int32_t>& col, int32_t& ncol) {
+  const int64_t n = G.n;
+  std::vector<int64_t> order(n);
+  for (int64_t v = 0; v < n; ++v) order[v] = v;
+  std::vector<uint64_t> rk(n);
+  for (int64_t v = 0; v < n; ++v) rk[v] = node_rank(v, salt);
+  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    return rk[a] != rk[b] ? rk[a] < rk[b] : a < b;
+  });
+  col.assign(n, -1);
+  ncol = 0;
+  std::vector<char> used;
+  for (int64_t v : order) {
+    used.assign((size_t)ncol + 1, 0);
+    for (int64_t k = G.rp[v]; k < G.rp[v + 1]; ++k) {
+      const int32_t c = col[G.ci[k]];
+      if (c >= 0) used[c] = 1;
+    }
+    int32_t c = 0;
+    while (used[c]) ++c;
+    col[v] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+}
+
+// One block Gauss-Seidel sweep, class by class (ascending classes when
+// forward, descending otherwise): every row i of the class takes
+// x_i += D_i^{-1} (b_i - sum_j A_ij x_j) with the current x.
+void gs_sweep(const Level& L, const double* b, double* x, bool forward) {
+  for (int32_t q = 0; q < L.ncol; ++q) {
+    const int32_t c = forward ? q : L.ncol - 1 - q;
+    for (int64_t i = 0; i < L.A.n; ++i) {
+      if (L.colour[i] != c) continue;
+      double r[3] = {b[3 * i], b[3 * i + 1], b[3 * i + 2]};
+      for (int64_t k = L.A.rp[i]; k < L.A.rp[i + 1]; ++k) {
+        const double* blk = &L.A.v[9 * k];
+        const double* xj = x + 3 * (int64_t)L.A.ci[k];
+        for (int t = 0; t < 3; ++t) r[t] -= blk[3 * t] * xj[0] + blk[3 * t + 1] * xj[1] + blk[3 * t + 2] * xj[2];
+      }
+      const double* d = &L.dinv[9 * i];
+      for (int t = 0; t < 3; ++t) x[3 * i + t] += d[3 * t] * r[0] + d[3 * t + 1] * r[1] + d[3 * t + 2] * r[2];
+    }
+  }
+}
+
 // ------------------------------------------------------ V-cycle / K-cycle (Sec. 3, Sec. 3.1)
 // Multigrid = smoothing + coarse grid correction; damped block Jacobi with
 // nu_pre / nu_post sweeps, restriction P^T, prolongation P, exact solve at the
@@ -449,7 +515,12 @@ void cycle(const Hier& H, size_t l, const double* b, double* x) {
   }
   std::vector<double> r(m), t(m);
   std::fill(x, x + m, 0.0);
+  const bool gs = H.o.smoother == 1;
   for (int s = 0; s < H.o.nu_pre; ++s) {  // x += omega D^{-1} (b - A x)
+    if (gs) {
+      gs_sweep(L, b, x, true);
+      continue;
+    }
     spmv(L.A, x, t.data());
     for (int64_t i = 0; i < m; ++i) r[i] = b[i] - t[i];
     apply_blocks(L.dinv, n, r.data(), t.data());
@@ -469,6 +540,10 @@ void cycle(const Hier& H, size_t l, const double* b, double* x) {
   for (int64_t i = 0; i < n; ++i)  // prolongation: x += P e
     for (int c = 0; c < 3; ++c) x[3 * i + c] += xc[3 * (int64_t)L.agg[i] + c];
   for (int s = 0; s < H.o.nu_post; ++s) {
+    if (gs) {  // backward classes: the post-sweep mirrors the pre-sweep
+      gs_sweep(L, b, x, false);
+      continue;
+    }
     spmv(L.A, x, t.data());
     for (int64_t i = 0; i < m; ++i) r[i] = b[i] - t[i];
     apply_blocks(L.dinv, n, r.data(), t.data());
@@ -682,6 +757,12 @@ int build(Hier& H, const double* m_tilde, double alpha, double dt) {
     if ((double)nc > o.stagnation * (double)N) break;
     L.agg = agg;
     L.nc = nc;
+    if (o.smoother == 1) {
+      if (l == 0)
+        parity_colouring(g, L.colour, L.ncol);
+      else
+        greedy_colouring(G, o.agg_salt ^ (((uint64_t)l << 8) | 0x80u), L.colour, L.ncol);
+    }
     Level next;
     galerkin(L.A, L.agg, nc, next.A);
     H.lv.push_back(std::move(next));
@@ -698,7 +779,8 @@ int build(Hier& H, const double* m_tilde, double alpha, double dt) {
 bool opts_ok(const llgo_opts* o) {
   return o && o->rtol >= 0 && o->restart >= 1 && o->max_iters >= 1 && o->nu_pre >= 0 &&
          o->nu_post >= 0 && o->npass >= 1 && o->beta_num >= 0 && o->beta_den >= 1 &&
-         o->max_coarse >= 1 && o->max_levels >= 1 && o->max_dense >= 1 && o->kcycle_depth >= 0;
+         o->max_coarse >= 1 && o->max_levels >= 1 && o->max_dense >= 1 && o->kcycle_depth >= 0 &&
+         (o->smoother == 0 || o->smoother == 1);
 }
 
 }  // namespace
@@ -725,6 +807,7 @@ void llgo_default_opts(llgo_opts* o) {
   o->agg_salt = 0;
   o->krylov = 0;
   o->kcycle_depth = 0;
+  o->smoother = 0;
 }
 
 uint64_t llgo_splitmix64(uint64_t x) { return splitmix64(x); }
@@ -849,6 +932,16 @@ int llgo_level_agg(void* h, int level, int32_t* agg) {
   Hier* H = (Hier*)h;
   if (!H || !agg || level < 0 || level + 1 >= (int)H->lv.size()) return LLGO_ERR_ARG;
   std::copy(H->lv[level].agg.begin(), H->lv[level].agg.end(), agg);
+  return LLGO_OK;
+}
+
+int llgo_level_colour(void* h, int level, int32_t* colour, int32_t* ncol) {
+  Hier* H = (Hier*)h;
+  if (!H || level < 0 || level >= (int)H->lv.size() || !colour || !ncol) return LLGO_ERR_ARG;
+  const Level& L = H->lv[level];
+  if (L.colour.empty()) return LLGO_ERR_ARG;
+  std::copy(L.colour.begin(), L.colour.end(), colour);
+  *ncol = L.ncol;
   return LLGO_OK;
 }
 

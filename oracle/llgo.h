@@ -16,8 +16,9 @@
  *   - an aggregation AMG hierarchy (Sec. 3.1, Sec. 3.1.1): two passes of
  *     pairwise matching per level, Boolean prolongation (eq. Pagg), Galerkin
  *     coarse operators computed by block sums (eq. galerkin, eq. Ac_direct);
- *   - one V-cycle (damped block Jacobi smoothing, exact dense LU at the
- *     coarsest level, Sec. 3) as preconditioner of a restarted flexible GMRES,
+ *   - one V-cycle (damped block Jacobi smoothing, or multicolour block
+ *     Gauss-Seidel in the spirit of the Gauss-Seidel smoother of Sec. 3; exact
+ *     dense LU at the coarsest level) as preconditioner of a restarted flexible GMRES,
  *     or of the preconditioned GCR of Algorithm 1 (Sec. 3.1.2);
  *   - the projection m <- m/|m| (Sec. 4.3).
  *
@@ -66,6 +67,7 @@ typedef struct {
   uint64_t agg_salt;
   int32_t krylov;       /* 0 = FGMRES, 1 = GCR (Algorithm 1) */
   int32_t kcycle_depth; /* coarse corrections of levels 1..depth by the K-cycle (0: V-cycle) */
+  int32_t smoother;     /* 0: damped block Jacobi; 1: multicolour block Gauss-Seidel */
 } llgo_opts;
 
 typedef struct {
@@ -106,6 +108,9 @@ int llgo_level_info(void* h, int level, int64_t* n, int64_t* nnzb);
 int llgo_level_matrix(void* h, int level, int64_t* rp, int32_t* ci, double* val);
 int llgo_level_dinv(void* h, int level, double* dinv);
 int llgo_level_agg(void* h, int level, int32_t* agg);  /* map level -> level+1 */
+/* Colour of every node of a smoothed level (multicolour Gauss-Seidel only);
+ * *ncol receives the number of colours. */
+int llgo_level_colour(void* h, int level, int32_t* colour, int32_t* ncol);
 int llgo_apply_A(void* h, const double* x, double* y);
 int llgo_precond(void* h, const double* v, double* z);
 int llgo_solve(void* h, const double* b, const double* u0, double* u, llgo_stats* st);

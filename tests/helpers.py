@@ -2,6 +2,17 @@
 import numpy as np
 import scipy.sparse as sp
 
+MASK = (1 << 64) - 1
+GOLDEN = 0x9E3779B97F4A7C15
+
+
+def sm64(x):
+    """SplitMix64 output for state x (Steele, Lea, Flood, OOPSLA 2014)."""
+    z = (x + GOLDEN) & MASK
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK
+    return z ^ (z >> 31)
+
 
 def lap1d(n: int, h: float) -> sp.csr_matrix:
     """1D cell-centred Neumann Laplacian: mirrored ghost cells cancel the

@@ -14,18 +14,7 @@ import pytest
 import scipy.sparse as sp
 
 import llg_inputs as I
-from helpers import bsr_to_dense, bsr_to_scipy, grid_graph_csr
-
-MASK = (1 << 64) - 1
-GOLDEN = 0x9E3779B97F4A7C15
-
-
-def sm64(x):
-    """SplitMix64 output for state x (Steele, Lea, Flood, OOPSLA 2014)."""
-    z = (x + GOLDEN) & MASK
-    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK
-    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK
-    return z ^ (z >> 31)
+from helpers import GOLDEN, MASK, bsr_to_dense, bsr_to_scipy, grid_graph_csr, sm64
 
 
 def test_splitmix64_published_vectors(orc):
