@@ -35,7 +35,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="rough2d_1024")
     p.add_argument("--forms", default="fp64:1,fp32_amg:1,fp64:0",
-                   help="comma list of precision:kcycle_depth (0 = V-cycle); the first gives `value`")
+                   help="comma list of precision:kcycle_depth[:smoother] (depth 0 = V-cycle; smoother "
+                        "jacobi or mcgs, default jacobi); the first gives `value`")
     p.add_argument("--roofline-class", default="outer_spmv")
     p.add_argument("--alpha", type=float, default=None, help="override the workload's alpha")
     p.add_argument("--kdepth", type=int, default=None, help="override the K-cycle depth of every form")
@@ -101,8 +102,9 @@ def forcing_list(torch, w, total: int):
             for k in range(total)]
 
 
-def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str, Fs, kdepth: int = 0):
-    opts = llg.default_opts(rtol=w.rtol, precision=form, kcycle_depth=kdepth)
+def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str, Fs, kdepth: int = 0,
+             smoother: str = "jacobi"):
+    opts = llg.default_opts(rtol=w.rtol, precision=form, kcycle_depth=kdepth, smoother=smoother)
     grid = llg.make_grid(w.dim, w.n)
     S = llg.Solver(grid, opts)
     m0 = torch.from_numpy(w.m0()).cuda()
@@ -227,21 +229,24 @@ def main():
     for f in a.forms.split(","):
         if not f:
             continue
-        prec, _, kd = f.partition(":")
-        kd = int(kd) if kd else 0
+        parts = f.split(":")
+        prec = parts[0]
+        kd = int(parts[1]) if len(parts) > 1 and parts[1] else 0
+        sm = parts[2] if len(parts) > 2 and parts[2] else "jacobi"
         if a.kdepth is not None:
             kd = a.kdepth
-        forms.append((f, prec, kd))
+        forms.append((f, prec, kd, sm))
     Fs = forcing_list(torch, w, a.warmup + a.steps)
     res = {}
-    for key, prec, kd in forms:
-        log("[bench] %s %s kcycle_depth %d: %d warmup + %d timed steps" % (w.name, prec, kd, a.warmup, a.steps))
-        res[key] = run_form(llg, torch, w, prec, a.steps, a.warmup, a.roofline_class, Fs, kd)
+    for key, prec, kd, sm in forms:
+        log("[bench] %s %s kcycle_depth %d smoother %s: %d warmup + %d timed steps"
+            % (w.name, prec, kd, sm, a.warmup, a.steps))
+        res[key] = run_form(llg, torch, w, prec, a.steps, a.warmup, a.roofline_class, Fs, kd, sm)
         r = res[key]
         log("  %.3f s, %.2f ms/step, iters/step %.1f, %s kernel %.3f ms over %d launches"
             % (r["seconds"], 1e3 * r["seconds"] / a.steps, sum(r["iters"]) / len(r["iters"]),
                a.roofline_class, r["kernel_ms"], r["kernel_launches"]))
-    main_key, main_form, main_kd = forms[0]
+    main_key, main_form, main_kd, main_sm = forms[0]
     r = res[main_key]
     unknowns = w.unknowns
     value = unknowns * a.steps / r["seconds"]
@@ -266,7 +271,8 @@ def main():
         "config": {"workload": w.name, "grid": "%dD %s" % (w.dim, "x".join([str(w.n)] * w.dim)),
                    "unknowns": unknowns, "alpha": w.alpha, "dt": w.dt, "rtol": w.rtol,
                    "form": main_form, "hierarchy": "rebuilt every step", "krylov": "FGMRES(30)",
-                   "preconditioner": "aggregation AMG, damped block-Jacobi (1,1), %s" % (
+                   "preconditioner": "aggregation AMG, %s (1,1), %s" % (
+                       "damped block-Jacobi" if main_sm == "jacobi" else "multicolour block Gauss-Seidel",
                        "K-cycle on levels 1..%d" % main_kd if main_kd else "V-cycle")},
         "iters_per_step": sum(r["iters"]) / len(r["iters"]),
         "iters": r["iters"],
@@ -278,13 +284,13 @@ def main():
                      "traffic": traffic, "algorithmic_bytes_per_launch": lb,
                      "avg_launch_us": avg_s * 1e6, "launches": r["kernel_launches"]},
     }
-    for key, prec, kd in forms[1:]:
+    for key, prec, kd, sm in forms[1:]:
         rf = res[key]
         diff = float((rf["one_step"] - r["one_step"]).abs().max())
-        name = "%s_%s" % (prec, "k%d" % kd if kd else "vcycle")
+        name = "%s_%s%s" % (prec, "k%d" % kd if kd else "vcycle", "" if sm == "jacobi" else "_" + sm)
         out[name] = {"value": unknowns * a.steps / rf["seconds"], "ms_per_step": 1e3 * rf["seconds"] / a.steps,
                      "iters_per_step": sum(rf["iters"]) / len(rf["iters"]), "iters": rf["iters"],
-                     "err_vs_exact": rf["err_vs_exact"], "kcycle_depth": kd,
+                     "err_vs_exact": rf["err_vs_exact"], "kcycle_depth": kd, "smoother": sm,
                      "speedup_vs_main": (unknowns * a.steps / rf["seconds"]) / value,
                      "max_abs_diff_one_step_vs_main": diff}
     if r["err_vs_exact"] is not None:

@@ -67,6 +67,17 @@ typedef enum {
   LLG_PREC_FP32_AMG = 1  /* AMG hierarchy and V-cycle in FP32 inside FP64 FGMRES */
 } llg_precision;
 
+/* Smoother of every level but the coarsest.
+ * JACOBI: x += omega D^{-1} (b - A x), all rows at once.
+ * MCGS: block Gauss-Seidel, x_i += D_i^{-1} (b_i - sum_j A_ij x_j) with the
+ * current x, taken colour class by colour class (ascending before the coarse
+ * correction, descending after it).  The classes are independent sets of the
+ * level's graph: on level 0 the parity of i + j + k; on coarse levels the
+ * greedy colouring in the order of ascending (SplitMix64((v << 32 | v) ^ salt), v),
+ * salt = agg_salt ^ (level << 8 | 0x80), each node taking the smallest colour
+ * none of its earlier neighbours has.  At most 128 colours per level. */
+typedef enum { LLG_SMOOTHER_JACOBI = 0, LLG_SMOOTHER_MCGS = 1 } llg_smoother;
+
 typedef struct {
   int32_t dim;   /* 2 or 3 */
   int32_t n[3];  /* points per axis, each >= 2; n[2] == 1 when dim == 2 */
@@ -79,7 +90,7 @@ typedef struct {
   int32_t restart;      /* FGMRES basis size per cycle, 1..32 */
   int32_t max_iters;    /* total FGMRES iterations */
   int32_t precision;    /* llg_precision */
-  int32_t nu_pre, nu_post;  /* damped block-Jacobi sweeps, each 0..4 */
+  int32_t nu_pre, nu_post;  /* smoothing sweeps before / after the coarse correction, each 0..4 */
   double omega;         /* Jacobi damping; <= 0 selects 4/5 (2D) or 6/7 (3D) */
   int32_t npass;        /* pairwise matching passes per level, 1..3 */
   int32_t beta_num, beta_den;  /* strong coupling: den * w >= num * max_w */
@@ -96,6 +107,8 @@ typedef struct {
                            minimal-residual steps, Sec. 3.1); 0 = V-cycle; 0..8 */
   int32_t graphs;       /* 1: replay the step's setup and each FGMRES iteration as HIP
                            graphs captured once per context (default); 0: eager launches */
+  int32_t smoother;     /* llg_smoother: damped block Jacobi (default) or multicolour
+                           block Gauss-Seidel (Sec. 3 smooths by Gauss-Seidel) */
 } llg_opts;
 
 typedef struct {
@@ -170,6 +183,12 @@ llg_status llg_get_level(llg_ctx* ctx, int32_t level, int32_t* h_row_ptr, int32_
 /* Host copy of the aggregate map of `level` (node -> aggregate on level+1),
  * n entries.  Synchronizes the stream. */
 llg_status llg_get_aggregates(llg_ctx* ctx, int32_t level, int32_t* h_out, int64_t n);
+
+/* Host copy of the colour class of every node of `level` (multicolour
+ * Gauss-Seidel smoother only; not the coarsest level), n entries, and the
+ * number of classes in *h_ncol.  INVALID_ARG when the context smooths by
+ * Jacobi.  Synchronizes the stream. */
+llg_status llg_get_colours(llg_ctx* ctx, int32_t level, int32_t* h_out, int64_t n, int32_t* h_ncol);
 
 /* z = B v: one V-cycle applied to D^{-1} v (the FGMRES preconditioner), both
  * FP64 device vectors of 3N entries.  Requires a prior llg_setup/llg_step. */

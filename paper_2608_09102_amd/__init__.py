@@ -28,6 +28,7 @@ MAX_LEVELS = 40
 
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE, ERR_NOT_CONVERGED, ERR_NONFINITE = range(7)
 PREC_FP64, PREC_FP32_AMG = 0, 1
+SMOOTHER_JACOBI, SMOOTHER_MCGS = 0, 1
 KT_NONE, KT_OUTER_SPMV, KT_SMOOTH, KT_RESIDUAL, KT_ARNOLDI, KT_GALERKIN, KT_ASSEMBLE = range(7)
 KERNEL_CLASSES = {"none": 0, "outer_spmv": 1, "smooth": 2, "residual": 3, "arnoldi": 4, "galerkin": 5,
                   "assemble": 6}
@@ -47,7 +48,7 @@ class Opts(ctypes.Structure):
         ("max_levels", ctypes.c_int32), ("max_dense", ctypes.c_int32), ("left_scale", ctypes.c_int32),
         ("project", ctypes.c_int32), ("x0_is_mn", ctypes.c_int32), ("agg_salt", ctypes.c_uint64),
         ("rebuild_aggregates", ctypes.c_int32), ("kcycle_depth", ctypes.c_int32),
-        ("graphs", ctypes.c_int32),
+        ("graphs", ctypes.c_int32), ("smoother", ctypes.c_int32),
     ]
 
 
@@ -83,6 +84,7 @@ _lib.llg_num_levels.argtypes = [_P, ctypes.POINTER(_i32)]
 _lib.llg_level_info.argtypes = [_P, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
 _lib.llg_get_level.argtypes = [_P, _i32, _P, _P, _P, _i64]
 _lib.llg_get_aggregates.argtypes = [_P, _i32, _P, _i64]
+_lib.llg_get_colours.argtypes = [_P, _i32, _P, _i64, _P]
 _lib.llg_apply_precond.argtypes = [_P, _P, _P]
 _lib.llg_apply_A.argtypes = [_P, _P, _P]
 _lib.llg_set_kernel_timing.argtypes = [_P, _i32]
@@ -93,7 +95,7 @@ _lib.llg_status_str.restype = ctypes.c_char_p
 _lib.llg_last_error.argtypes = []
 _lib.llg_last_error.restype = ctypes.c_char_p
 for _f in ("llg_workspace_bytes", "llg_create", "llg_step", "llg_setup", "llg_num_levels", "llg_level_info",
-           "llg_get_level", "llg_get_aggregates", "llg_apply_precond", "llg_apply_A", "llg_set_kernel_timing",
+           "llg_get_level", "llg_get_aggregates", "llg_get_colours", "llg_apply_precond", "llg_apply_A", "llg_set_kernel_timing",
            "llg_ctx_bytes", "llg_destroy"):
     getattr(_lib, _f).restype = _i32
 
@@ -143,6 +145,8 @@ def default_opts(**kw) -> Opts:
             raise KeyError(k)
         if k == "precision" and isinstance(v, str):
             v = {"fp64": PREC_FP64, "fp32_amg": PREC_FP32_AMG}[v]
+        if k == "smoother" and isinstance(v, str):
+            v = {"jacobi": SMOOTHER_JACOBI, "mcgs": SMOOTHER_MCGS}[v]
         setattr(o, k, v)
     return o
 
@@ -266,6 +270,19 @@ class Solver:
         if s != OK:
             raise LLGError(s, "llg_get_aggregates")
         return a
+
+    def colours(self, level: int):
+        """(colour class of every node, number of classes) of a level smoothed
+        by multicolour Gauss-Seidel."""
+        import numpy as np
+        n, _ = self.level_info(level)
+        a = np.empty(n, np.int32)
+        k = ctypes.c_int32(0)
+        with torch.cuda.device(self.device):
+            s = _lib.llg_get_colours(self._ctx, level, a.ctypes.data_as(_P), n, ctypes.cast(ctypes.byref(k), _P))
+        if s != OK:
+            raise LLGError(s, "llg_get_colours")
+        return a, int(k.value)
 
     def precond(self, v):
         self._field(v, "v")

@@ -152,10 +152,19 @@ struct Level {
   // K-cycle work vectors and coefficients (levels 1..kcycle_depth)
   void *v1 = nullptr, *v2 = nullptr, *w1 = nullptr, *w2 = nullptr, *rho = nullptr;
   double* kc = nullptr;
+  // multicolour Gauss-Seidel: the colour of every node, the rows sorted by
+  // colour (class q is perm[coff[q] .. coff[q+1])), and every class as a
+  // sliced-ELL matrix with its own copy of the values and inverse diagonals
+  int32_t* colour = nullptr;
+  int32_t* perm = nullptr;
+  int ncol = 0;
+  std::vector<int64_t> coff;
+  std::vector<Sell> cls;
+  std::vector<void*> cval, cdinv;
 };
 
 struct PlanKey {
-  std::tuple<int, int, int, int, int, int, int, int, double, int, int, uint64_t, int, int, int, int> k;
+  std::tuple<int, int, int, int, int, int, int, int, double, int, int, uint64_t, int, int, int, int, int> k;
   bool operator<(const PlanKey& o) const { return k < o.k; }
 };
 
@@ -166,7 +175,7 @@ PlanKey plan_key(const llg_grid& g, const llg_opts& o) {
   PlanKey k;
   k.k = std::make_tuple(g.dim, g.n[0], g.n[1], g.n[2], o.npass, o.beta_num, o.beta_den, o.max_coarse,
                         o.stagnation, o.max_levels, o.max_dense, o.agg_salt, o.precision, o.restart,
-                        o.left_scale, o.kcycle_depth);
+                        o.left_scale, o.kcycle_depth, o.smoother);
   return k;
 }
 
@@ -280,7 +289,7 @@ void build_sell(Arena& ar, hipStream_t st, Level& L, int64_t n, int64_t gnnz) {
   launch_pattern_cols(st, n, L.grp, L.gci, L.brp, L.bci);
   LCHK();
   L.A.sl_ptr = ar.alloc<int32_t>(L.A.nslices + 1);
-  launch_slice_width(st, n, L.brp, L.A.sl_ptr);
+  launch_slice_width(st, n, nullptr, L.brp, L.A.sl_ptr);
   LCHK();
 }
 
@@ -289,8 +298,85 @@ void finish_sell(Arena& ar, hipStream_t st, Level& L, int32_t* scan_tmp) {
   LCHK();
   L.A.nslots = ar.count(L.A.sl_ptr + L.A.nslices);
   L.A.col = ar.alloc<int32_t>(L.A.nslots);
-  launch_sell_cols(st, L.A.n, L.brp, L.bci, L.A.sl_ptr, L.A.col);
+  launch_sell_cols(st, L.A.n, nullptr, L.brp, L.bci, L.A.sl_ptr, L.A.col);
   LCHK();
+}
+
+// Colour classes of level l for the multicolour Gauss-Seidel smoother: the
+// parity of i + j + k on level 0, Jones-Plassmann rounds on the level's graph
+// elsewhere (rounds logged like the matching rounds), a stable counting sort
+// of the rows by colour, and the sliced-ELL structure of every class.
+void build_colours(llg_ctx& c, Arena& ar, int l) {
+  hipStream_t st = c.st;
+  Level& L = c.lv[l];
+  const int64_t n = L.A.n;
+  L.colour = ar.alloc<int32_t>(n);
+  if (l == 0) {
+    launch_parity_colour(st, c.grid.n[0], c.grid.n[1], c.grid.n[2], L.colour);
+    LCHK();
+  } else {
+    const uint64_t salt = c.opts.agg_salt ^ (((uint64_t)l << 8) | 0x80u);
+    uint64_t* rank = ar.alloc<uint64_t>(n);
+    int32_t* cround = ar.alloc<int32_t>(n);
+    launch_node_rank(st, n, salt, rank);
+    launch_fill_i32(st, cround, n, INT32_MAX);
+    launch_fill_i32(st, L.colour, n, -1);
+    LCHK();
+    if (ar.mode == Mode::PLAN) {
+      int64_t rounds = 0;
+      for (;;) {
+        launch_fill_i32(st, c.count, 1, 0);
+        launch_jp_round(st, n, L.grp, L.gci, rank, (int32_t)rounds, cround, L.colour, c.count);
+        LCHK();
+        ++rounds;
+        HIPX(hipMemcpyAsync(ar.hcount, c.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPX(hipStreamSynchronize(st));
+        if (*ar.hcount == 0) break;
+        if (rounds > n + 2) throw DevError{"colouring did not terminate"};
+      }
+      ar.plan->counts.push_back(rounds);
+    } else {
+      const int64_t rounds = ar.plan->counts[ar.ci++];
+      launch_fill_i32(st, c.count, 1, 0);
+      for (int64_t r = 0; r < rounds; ++r)
+        launch_jp_round(st, n, L.grp, L.gci, rank, (int32_t)r, cround, L.colour,
+                        r + 1 == rounds ? c.count : c.count + 1);
+      launch_check_eq(st, c.count, 0, c.flags, F_PLAN);
+      LCHK();
+    }
+  }
+  launch_fill_i32(st, c.count + 2, 1, 0);
+  launch_colour_max(st, n, L.colour, c.count + 2);
+  LCHK();
+  const int64_t ncol = ar.count(c.count + 2);
+  if (ncol > MAX_COLOURS && ar.mode == Mode::PLAN) ar.plan->status = LLG_ERR_UNSUPPORTED;
+  L.ncol = (int)std::max<int64_t>(1, std::min<int64_t>(ncol, MAX_COLOURS));
+  const int64_t nb = colour_blocks(n);
+  int32_t* hist = ar.alloc<int32_t>(L.ncol * nb + 1);
+  launch_colour_hist(st, n, L.colour, L.ncol, hist);
+  launch_scan_excl(st, hist, hist, L.ncol * nb, hist + L.ncol * nb, c.scan_tmp);
+  L.perm = ar.alloc<int32_t>(n);
+  launch_fill_i32(st, L.perm, n, 0);
+  launch_colour_place(st, n, L.colour, L.ncol, hist, L.perm);
+  LCHK();
+  L.coff.assign(L.ncol + 1, 0);
+  for (int q = 1; q < L.ncol; ++q) L.coff[q] = ar.count(hist + (int64_t)q * nb);
+  L.coff[L.ncol] = n;
+  L.cls.assign(L.ncol, Sell{});
+  for (int q = 0; q < L.ncol; ++q) {
+    Sell& S = L.cls[q];
+    S.n = L.coff[q + 1] - L.coff[q];
+    S.nslices = ceil_div(S.n, SL);
+    S.sl_ptr = ar.alloc<int32_t>(S.nslices + 1);
+    const int32_t* rows = L.perm + L.coff[q];
+    launch_slice_width(st, S.n, rows, L.brp, S.sl_ptr);
+    launch_scan_excl(st, S.sl_ptr, S.sl_ptr, S.nslices, S.sl_ptr + S.nslices, c.scan_tmp);
+    LCHK();
+    S.nslots = ar.count(S.sl_ptr + S.nslices);
+    S.col = ar.alloc<int32_t>(S.nslots);
+    launch_sell_cols(st, S.n, rows, L.brp, L.bci, S.sl_ptr, S.col);
+    LCHK();
+  }
 }
 
 // Grid pattern, then per level: npass handshake-matching passes on the
@@ -304,7 +390,7 @@ int build_structure(llg_ctx& c, Arena& ar) {
   const int64_t N = (int64_t)nx * ny * nz;
   c.flags = ar.alloc<int32_t>(8);
   c.count = ar.alloc<int32_t>(8);
-  c.scan_tmp = ar.alloc<int32_t>(scan_tmp_ints(N + 1) + 64);
+  c.scan_tmp = ar.alloc<int32_t>(scan_tmp_ints(std::max<int64_t>(N + 1, MAX_COLOURS * colour_blocks(N) + 1)) + 64);
   if (ar.mode == Mode::PLAN || ar.first) {
     launch_fill_i32(st, c.flags, 8, 0);
     LCHK();
@@ -419,6 +505,7 @@ int build_structure(llg_ctx& c, Arena& ar) {
     L.mptr = mptr;
     L.mem = mem;
     L.nc = cn;
+    if (o.smoother == LLG_SMOOTHER_MCGS) build_colours(c, ar, l);
     Level& Nx = c.lv[l + 1];
     Nx.grp = crp;
     Nx.gci = cci;
@@ -450,6 +537,12 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
     L.r = ar.get(ts * 3 * n, true);
     L.e = ar.get(ts * 3 * n, true);
     L.xo = ar.get(ts * 3 * n, true);
+    L.cval.assign(L.ncol, nullptr);
+    L.cdinv.assign(L.ncol, nullptr);
+    for (int q = 0; q < L.ncol; ++q) {
+      L.cval[q] = ar.get(ts * 9 * L.cls[q].nslots, true);
+      if (!L.unit) L.cdinv[q] = ar.get(ts * 9 * L.cls[q].nslices * SL, true);
+    }
     if (l >= 1 && l <= c.opts.kcycle_depth && l + 1 < c.L) {
       L.v1 = ar.get(ts * 3 * n, true);
       L.v2 = ar.get(ts * 3 * n, true);
@@ -506,7 +599,8 @@ bool opts_ok(const llg_opts* o) {
          o->npass >= 1 && o->npass <= MAX_PASS && o->beta_num >= 0 && o->beta_den >= 1 &&
          o->max_coarse >= 1 && o->max_levels >= 1 && o->max_levels <= LLG_MAX_LEVELS && o->max_dense >= 1 &&
          (o->precision == LLG_PREC_FP64 || o->precision == LLG_PREC_FP32_AMG) && std::isfinite(o->omega) &&
-         std::isfinite(o->stagnation) && o->kcycle_depth >= 0 && o->kcycle_depth <= 8;
+         std::isfinite(o->stagnation) && o->kcycle_depth >= 0 && o->kcycle_depth <= 8 &&
+         (o->smoother == LLG_SMOOTHER_JACOBI || o->smoother == LLG_SMOOTHER_MCGS);
 }
 
 // Plan for (grid, opts): cached; computed on the current device.
@@ -581,6 +675,13 @@ void setup_values(llg_ctx& c, const double* m, const double* F) {
     launch_galerkin<T>(st, Nx.A, (T*)Nx.val, (T*)Nx.dinv, L.mptr, L.mem, L.A, (const T*)L.val, L.agg);
     LCHK();
   }
+  for (int l = 0; l + 1 < c.L; ++l) {  // colour-class copies for Gauss-Seidel
+    Level& L = c.lv[l];
+    for (int q = 0; q < L.ncol; ++q)
+      launch_cls_gather<T>(st, L.cls[q].n, L.perm + L.coff[q], L.A, (const T*)L.val,
+                           L.unit ? nullptr : (const T*)L.dinv, L.cls[q], (T*)L.cval[q], (T*)L.cdinv[q]);
+  }
+  LCHK();
   Level& C = c.lv[c.L - 1];
   launch_dense_scatter<T>(st, C.A, (const T*)C.val, c.dense);
   launch_gauss_jordan(st, c.nd, c.dense, c.piv, c.flags);
@@ -672,11 +773,18 @@ void kcorrection(llg_ctx& c, int lc);
 // and on the fine level with unit diagonal blocks it is x = omega b, never
 // stored, so each level costs one "down" and one "up" kernel.
 template <typename T>
+void vcycle_gs(llg_ctx& c, int l, const T* b, T* out);
+
+template <typename T>
 void vcycle(llg_ctx& c, int l, const T* b, T* out) {
   hipStream_t st = c.st;
   if (l == c.L - 1) {
     launch_dense_apply<T>(st, c.nd, c.dense, b, out);
     LCHK();
+    return;
+  }
+  if (c.opts.smoother == LLG_SMOOTHER_MCGS) {
+    vcycle_gs<T>(c, l, b, out);
     return;
   }
   Level& L = c.lv[l];
@@ -749,6 +857,53 @@ void vcycle(llg_ctx& c, int l, const T* b, T* out) {
   }
 }
 
+// One multicolour block Gauss-Seidel sweep of level L on x, classes in
+// ascending order (forward) or descending order; first: x is zero.
+template <typename T>
+void gs_sweeps(llg_ctx& c, Level& L, const T* b, T* x, bool forward, bool first) {
+  for (int q = 0; q < L.ncol; ++q) {
+    const int k = forward ? q : L.ncol - 1 - q;
+    launch_gs_sweep<T>(c.st, L.cls[k], L.perm + L.coff[k], (const T*)L.cval[k], (const T*)L.cdinv[k], L.unit,
+                       first && q == 0, b, x, L.G);
+  }
+}
+
+// V(l, b) with multicolour block Gauss-Seidel smoothing: forward sweeps from
+// x = 0, residual and restriction, the coarse correction, prolongation, then
+// backward sweeps (the post-smoother mirrors the pre-smoother).
+template <typename T>
+void vcycle_gs(llg_ctx& c, int l, const T* b, T* out) {
+  hipStream_t st = c.st;
+  Level& L = c.lv[l];
+  Level& Nx = c.lv[l + 1];
+  const llg_opts& o = c.opts;
+  T* X = (T*)L.x;
+  {
+    KTimer kt(c, LLG_KT_SMOOTH);
+    launch_fill<T>(st, X, 3 * L.A.n);
+    for (int s = 0; s < o.nu_pre; ++s) gs_sweeps<T>(c, L, b, X, true, s == 0);
+    LCHK();
+  }
+  {
+    KTimer kt(c, LLG_KT_RESIDUAL);
+    const T* rsrc = b;
+    if (o.nu_pre >= 1) {
+      launch_residual<T>(st, L.A, (const T*)L.val, 0, c.omega, b, X, (T*)L.r, L.G);
+      rsrc = (const T*)L.r;
+    }
+    launch_restrict<T>(st, L.nc, L.mptr, L.mem, rsrc, (T*)Nx.b, nullptr, c.omega, nullptr);
+    LCHK();
+  }
+  if (Nx.kc)
+    kcorrection<T>(c, l + 1);
+  else
+    vcycle<T>(c, l + 1, (const T*)Nx.b, (T*)Nx.e);
+  KTimer kt(c, LLG_KT_SMOOTH);
+  launch_prolong<T>(st, L.A.n, 0, c.omega, b, X, L.agg, (const T*)Nx.e, out);
+  for (int s = 0; s < o.nu_post; ++s) gs_sweeps<T>(c, L, b, out, false, false);
+  LCHK();
+}
+
 // Coarse correction of level lc by the K-cycle (Sec. 3.1: Krylov acceleration
 // at each level): e minimizes ||r - A_c e|| over span{v1, v2}, v1 = C(r),
 // v2 = C(r - a1 A_c v1), C the cycle of level lc.  r is lv[lc].b, whose first
@@ -759,7 +914,9 @@ void kcorrection(llg_ctx& c, int lc) {
   Level& C = c.lv[lc];
   const T* val = (const T*)C.val;
   const int64_t G = rows_blocks(C.A.n, C.G);
-  const bool pre = c.opts.nu_pre >= 1;
+  // with Jacobi smoothing the first sweep of the next cycle on rho is fused
+  // into the update of rho (Gauss-Seidel cycles start from x = 0 themselves)
+  const bool pre = c.opts.nu_pre >= 1 && c.opts.smoother == LLG_SMOOTHER_JACOBI;
   vcycle<T>(c, lc, (const T*)C.b, (T*)C.v1);
   launch_spmv_dots<T>(st, C.A, val, (const T*)C.v1, (T*)C.w1, (const T*)C.b, nullptr, c.part, C.G);
   launch_kc_coef(st, c.part, G, 1, C.kc);
@@ -1003,6 +1160,7 @@ void llg_default_opts(llg_opts* o) {
   o->rebuild_aggregates = 1;
   o->kcycle_depth = 0;
   o->graphs = 1;
+  o->smoother = LLG_SMOOTHER_JACOBI;
 }
 
 llg_status llg_workspace_bytes(const llg_grid* grid, const llg_opts* opts, size_t* bytes) {
@@ -1178,6 +1336,20 @@ llg_status llg_get_aggregates(llg_ctx* ctx, int32_t level, int32_t* h_out, int64
   return guard([&]() -> llg_status {
     HIPX(hipStreamSynchronize(ctx->st));
     HIPX(hipMemcpy(h_out, ctx->lv[level].agg, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    return LLG_OK;
+  });
+}
+
+llg_status llg_get_colours(llg_ctx* ctx, int32_t level, int32_t* h_out, int64_t n, int32_t* h_ncol) {
+  llg_status s = check_ctx(ctx);
+  if (s != LLG_OK) return s;
+  if (ctx->opts.smoother != LLG_SMOOTHER_MCGS || level < 0 || level + 1 >= ctx->L || !h_out || !h_ncol ||
+      n != ctx->lv[level].A.n)
+    return LLG_ERR_INVALID_ARG;
+  return guard([&]() -> llg_status {
+    HIPX(hipStreamSynchronize(ctx->st));
+    HIPX(hipMemcpy(h_out, ctx->lv[level].colour, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    *h_ncol = ctx->lv[level].ncol;
     return LLG_OK;
   });
 }

@@ -164,25 +164,31 @@ __global__ void k_pattern_cols(int64_t n, const int32_t* grp, const int32_t* gci
   if (!placed) bci[o++] = (int32_t)i;
 }
 
-__global__ void k_slice_width(int64_t n, const int32_t* brp, int32_t* wslots) {
+// Sliced-ELL structure of the rows rows[0..n) of a CSR pattern (rows == NULL:
+// rows 0..n).  Slice widths first, then the column slots.
+__global__ void k_slice_width(int64_t n, const int32_t* rows, const int32_t* brp, int32_t* wslots) {
   int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ns = ceil_div(n, SL);
   if (s >= ns) return;
   int32_t w = 0;
-  for (int64_t i = s * SL; i < (s + 1) * SL && i < n; ++i) w = max(w, brp[i + 1] - brp[i]);
+  for (int64_t k = s * SL; k < (s + 1) * SL && k < n; ++k) {
+    const int64_t i = rows ? rows[k] : k;
+    w = max(w, brp[i + 1] - brp[i]);
+  }
   wslots[s] = w * SL;
 }
 
-__global__ void k_sell_cols(int64_t n, const int32_t* brp, const int32_t* bci, const int32_t* sl_ptr,
-                            int32_t* col) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_sell_cols(int64_t n, const int32_t* rows, const int32_t* brp, const int32_t* bci,
+                            const int32_t* sl_ptr, int32_t* col) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ns = ceil_div(n, SL);
-  if (i >= ns * SL) return;
-  const int64_t s = i / SL;
-  const int l = (int)(i - s * SL);
+  if (k >= ns * SL) return;
+  const int64_t s = k / SL;
+  const int l = (int)(k - s * SL);
   const int32_t base = sl_ptr[s];
   const int w = (sl_ptr[s + 1] - base) / SL;
-  const int len = i < n ? brp[i + 1] - brp[i] : 0;
+  const int64_t i = k < n ? (rows ? rows[k] : k) : -1;
+  const int len = i >= 0 ? brp[i + 1] - brp[i] : 0;
   for (int t = 0; t < w; ++t) col[base + t * SL + l] = t < len ? bci[brp[i] + t] : -1;
 }
 
@@ -464,6 +470,116 @@ __device__ inline void inv3(const double* D, double* R) {
   const double rdet = 1.0 / det;
 #pragma unroll
   for (int k = 0; k < 9; ++k) R[k] = adj[k] * rdet;
+}
+
+// ---------------------------------------------------------------- colouring
+// Colour classes for the multicolour Gauss-Seidel smoother (Sec. 3).
+// Level 0: parity of i + j + k (the grid graph is bipartite).
+__global__ void k_parity_colour(int nx, int ny, int nz, int32_t* col) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = (int64_t)nx * ny * nz;
+  if (p >= N) return;
+  const int64_t i = p % nx, j = (p / nx) % ny, k = p / ((int64_t)nx * ny);
+  col[p] = (int32_t)((i + j + k) & 1);
+}
+
+// One Jones-Plassmann round r on a coarse level: a node whose earlier
+// neighbours (smaller (rank, id)) were all coloured in rounds before r takes
+// the smallest colour none of them has.  That is the greedy colouring in
+// ascending (rank, id) order: when a node is coloured, exactly its earlier
+// neighbours are.  cround[v] = round that coloured v (INT32_MAX: not yet);
+// a node coloured in this same round counts as not coloured, so the result
+// and the number of rounds do not depend on the order of the threads.
+// Colours >= 128 are not represented: such a node gets 128 (reported).
+__global__ void k_jp_round(int64_t n, const int32_t* __restrict__ grp, const int32_t* __restrict__ gci,
+                           const uint64_t* __restrict__ rank, int32_t r, int32_t* cround, int32_t* col,
+                           int32_t* pending) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool waiting = false;
+  if (i < n && cround[i] == INT32_MAX) {
+    const uint64_t ri = rank[i];
+    uint64_t used0 = 0, used1 = 0;
+    bool ready = true;
+    for (int32_t k = grp[i]; k < grp[i + 1]; ++k) {
+      const int32_t j = gci[k];
+      const uint64_t rj = rank[j];
+      if (!(rj < ri || (rj == ri && j < i))) continue;  // later neighbour
+      if (cround[j] >= r) {
+        ready = false;
+        break;
+      }
+      const int32_t cj = col[j];
+      if (cj < 64)
+        used0 |= 1ull << cj;
+      else if (cj < 128)
+        used1 |= 1ull << (cj - 64);
+    }
+    if (ready) {
+      int32_t c = used0 != ~0ull ? __builtin_ctzll(~used0) : (used1 != ~0ull ? 64 + __builtin_ctzll(~used1) : 128);
+      col[i] = c;
+      cround[i] = r;
+    } else {
+      waiting = true;
+    }
+  }
+  const unsigned long long ballot = __ballot(waiting);
+  if ((threadIdx.x & 63) == 0 && ballot && __atomic_load_n(pending, __ATOMIC_RELAXED) == 0) atomicOr(pending, 1);
+}
+
+// *ncol = 1 + largest colour (one atomic per wavefront)
+__global__ void k_colour_max(int64_t n, const int32_t* col, int32_t* ncol) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t c = i < n ? col[i] + 1 : 0;
+  for (int off = 32; off > 0; off >>= 1) c = max(c, __shfl_down(c, off, 64));
+  if ((threadIdx.x & 63) == 0 && c > 0) atomicMax(ncol, c);
+}
+
+// Counting sort of the nodes by colour, stable: hist[c * nb + b] = nodes of
+// colour c in block b (256 nodes per block); after an exclusive scan of hist,
+// a node's place is hist[c * nb + b] + (earlier nodes of its block with colour c).
+__global__ void k_colour_hist(int64_t n, const int32_t* col, int32_t ncol, int64_t nb, int32_t* hist) {
+  __shared__ int32_t h[128];
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) h[c] = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && col[i] >= 0 && col[i] < ncol) atomicAdd(&h[col[i]], 1);
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) hist[(int64_t)c * nb + blockIdx.x] = h[c];
+}
+
+__global__ void k_colour_place(int64_t n, const int32_t* col, int32_t ncol, int64_t nb, const int32_t* hist,
+                               int32_t* perm) {
+  __shared__ int32_t cs[TPB];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t c = i < n ? col[i] : -1;
+  cs[threadIdx.x] = c;
+  __syncthreads();
+  if (i >= n || c < 0 || c >= ncol) return;
+  int32_t before = 0;
+  for (int t = 0; t < (int)threadIdx.x; ++t) before += cs[t] == c;
+  perm[hist[(int64_t)c * nb + blockIdx.x] + before] = (int32_t)i;
+}
+
+// Values of one colour class: row k of the class is level row rows[k]; its
+// slot t holds the level's slot t of that row (same column).  The inverse
+// diagonal block follows when dinv != NULL.
+template <typename T>
+__global__ void k_cls_gather(int64_t n, const int32_t* __restrict__ rows, const int32_t* __restrict__ sl,
+                             const T* __restrict__ val, const T* __restrict__ dinv,
+                             const int32_t* __restrict__ csl, T* __restrict__ cval, T* __restrict__ cdinv) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t i = rows[k];
+  const int64_t s = i / SL, l = i - s * SL;
+  const int64_t cs = k / SL, cl = k - cs * SL;
+  const int64_t src = 9 * (int64_t)sl[s], dst = 9 * (int64_t)csl[cs];
+  const int w = (csl[cs + 1] - csl[cs]) / SL;
+  const int wsrc = (sl[s + 1] - sl[s]) / SL;
+  for (int t = 0; t < w; ++t)
+    for (int e = 0; e < 9; ++e)
+      cval[dst + (int64_t)SL * (9 * t + e) + cl] = t < wsrc ? val[src + (int64_t)SL * (9 * t + e) + l] : T(0);
+  if (dinv)
+    for (int e = 0; e < 9; ++e) cdinv[cs * 9 * SL + e * SL + cl] = dinv[s * 9 * SL + e * SL + l];
 }
 
 // One thread per node.  A_pq = dt L_pq M_p (+ I on the diagonal) in FP64;
@@ -796,15 +912,15 @@ void launch_pattern_cols(hipStream_t st, int64_t n, const int32_t* grp, const in
                          const int32_t* brp, int32_t* bci) {
   if (n > 0) hipLaunchKernelGGL(k_pattern_cols, dim3(nblk(n)), dim3(TPB), 0, st, n, grp, gci, brp, bci);
 }
-void launch_slice_width(hipStream_t st, int64_t n, const int32_t* brp, int32_t* wslots) {
+void launch_slice_width(hipStream_t st, int64_t n, const int32_t* rows, const int32_t* brp, int32_t* wslots) {
   const int64_t ns = ceil_div(n, SL);
-  if (ns > 0) hipLaunchKernelGGL(k_slice_width, dim3(nblk(ns)), dim3(TPB), 0, st, n, brp, wslots);
+  if (ns > 0) hipLaunchKernelGGL(k_slice_width, dim3(nblk(ns)), dim3(TPB), 0, st, n, rows, brp, wslots);
 }
-void launch_sell_cols(hipStream_t st, int64_t n, const int32_t* brp, const int32_t* bci,
+void launch_sell_cols(hipStream_t st, int64_t n, const int32_t* rows, const int32_t* brp, const int32_t* bci,
                       const int32_t* sl_ptr, int32_t* col) {
   const int64_t ns = ceil_div(n, SL);
   if (ns > 0)
-    hipLaunchKernelGGL(k_sell_cols, dim3(nblk(ns * SL)), dim3(TPB), 0, st, n, brp, bci, sl_ptr, col);
+    hipLaunchKernelGGL(k_sell_cols, dim3(nblk(ns * SL)), dim3(TPB), 0, st, n, rows, brp, bci, sl_ptr, col);
 }
 void launch_row_max(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gw, int32_t* mx) {
   if (n > 0) hipLaunchKernelGGL(k_row_max, dim3(nblk(n)), dim3(TPB), 0, st, n, grp, gw, mx);
@@ -905,6 +1021,40 @@ void launch_dense_scatter(hipStream_t st, Sell C, const T* cval, double* dense) 
 }
 template void launch_dense_scatter<double>(hipStream_t, Sell, const double*, double*);
 template void launch_dense_scatter<float>(hipStream_t, Sell, const float*, double*);
+
+void launch_parity_colour(hipStream_t st, int nx, int ny, int nz, int32_t* col) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  hipLaunchKernelGGL(k_parity_colour, dim3(nblk(N)), dim3(TPB), 0, st, nx, ny, nz, col);
+}
+void launch_jp_round(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci, const uint64_t* rank,
+                     int32_t r, int32_t* cround, int32_t* col, int32_t* pending) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_jp_round, dim3(nblk(n)), dim3(TPB), 0, st, n, grp, gci, rank, r, cround, col, pending);
+}
+void launch_colour_max(hipStream_t st, int64_t n, const int32_t* col, int32_t* ncol) {
+  if (n > 0) hipLaunchKernelGGL(k_colour_max, dim3(nblk(n)), dim3(TPB), 0, st, n, col, ncol);
+}
+int64_t colour_blocks(int64_t n) { return (int64_t)nblk(n); }
+void launch_colour_hist(hipStream_t st, int64_t n, const int32_t* col, int32_t ncol, int32_t* hist) {
+  const int64_t nb = colour_blocks(n);
+  hipLaunchKernelGGL(k_colour_hist, dim3((unsigned)nb), dim3(TPB), 0, st, n, col, ncol, nb, hist);
+}
+void launch_colour_place(hipStream_t st, int64_t n, const int32_t* col, int32_t ncol, const int32_t* hist,
+                         int32_t* perm) {
+  const int64_t nb = colour_blocks(n);
+  hipLaunchKernelGGL(k_colour_place, dim3((unsigned)nb), dim3(TPB), 0, st, n, col, ncol, nb, hist, perm);
+}
+template <typename T>
+void launch_cls_gather(hipStream_t st, int64_t n, const int32_t* rows, Sell A, const T* val, const T* dinv,
+                       Sell C, T* cval, T* cdinv) {
+  if (n > 0)
+    hipLaunchKernelGGL((k_cls_gather<T>), dim3(nblk(n)), dim3(TPB), 0, st, n, rows, A.sl_ptr, val, dinv, C.sl_ptr,
+                       cval, cdinv);
+}
+template void launch_cls_gather<double>(hipStream_t, int64_t, const int32_t*, Sell, const double*, const double*,
+                                        Sell, double*, double*);
+template void launch_cls_gather<float>(hipStream_t, int64_t, const int32_t*, Sell, const float*, const float*,
+                                       Sell, float*, float*);
 
 void launch_gauss_jordan(hipStream_t st, int64_t nd, double* dense, int32_t* piv, int32_t* flag) {
   static int lds_ok = -1;

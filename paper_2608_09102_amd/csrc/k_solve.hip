@@ -220,6 +220,42 @@ __global__ void k_post_smooth(int64_t n, const int32_t* __restrict__ sl, const i
   st3(out, p.i, V3<T>{xi.x + omega * res.x, xi.y + omega * res.y, xi.z + omega * res.z});
 }
 
+// One block Gauss-Seidel sweep over a colour class, in place.  The rows of a
+// class are not coupled to each other, so every row reads only rows of other
+// classes (settled by earlier launches) and its own entry.  FIRST: x = 0
+// everywhere before the sweep, so x_i = D_i^{-1} b_i without reading A.
+template <typename T, bool UNIT, bool FIRST, int G>
+__global__ void k_gs_sweep(int64_t n, const int32_t* __restrict__ rows, const int32_t* __restrict__ sl,
+                           const int32_t* __restrict__ col, const T* __restrict__ val, const T* __restrict__ dinv,
+                           const T* __restrict__ b, T* x) {
+  const RowPos p = row_pos<G>();
+  if (p.i >= n) return;
+  const int64_t i = rows[p.i];
+  T a0 = 0, a1 = 0, a2 = 0;
+  if (!FIRST) {
+    const int64_t cb = sl[p.s];
+    const int w = (int)((sl[p.s + 1] - cb) / SL);
+    sell_row_mv_g<G>(col, val, cb, w, p.l, p.sub, [&](int32_t c) { return ld3((const T*)x, (int64_t)c); }, a0,
+                     a1, a2);
+  }
+  if (p.sub != 0) return;
+  const V3<T> bi = ld3(b, i);
+  V3<T> res{bi.x - a0, bi.y - a1, bi.z - a2};
+  if (!UNIT) res = dmv(dinv, p.s * 9 * SL + p.l, res);
+  if (FIRST) {
+    st3(x, i, res);
+  } else {
+    const V3<T> xi = ld3((const T*)x, i);
+    st3(x, i, V3<T>{xi.x + res.x, xi.y + res.y, xi.z + res.z});
+  }
+}
+
+template <typename T>
+__global__ void k_fill_zero(T* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = T(0);
+}
+
 template <typename T, int XMODE>
 __global__ void k_prolong(int64_t n, T omega, const T* __restrict__ b, const T* __restrict__ x,
                           const int32_t* __restrict__ agg, const T* __restrict__ ec, T* __restrict__ out) {
@@ -736,6 +772,40 @@ void launch_prolong(hipStream_t st, int64_t n, int xmode, double omega, const T*
 }
 
 template <typename T>
+void launch_gs_sweep(hipStream_t st, Sell C, const int32_t* rows, const T* cval, const T* cdinv, int unit,
+                     int first, const T* b, T* x, int G) {
+  if (C.n <= 0) return;
+  if (first) G = 1;
+  const int64_t nt = C.n * G;
+  const int tb = tpb_rows(C.n);
+  const dim3 g(nblk(nt, tb)), t(tb);
+#define LLG_GS(U, F, GG) \
+  hipLaunchKernelGGL((k_gs_sweep<T, U, F, GG>), g, t, 0, st, C.n, rows, C.sl_ptr, C.col, cval, cdinv, b, x)
+#define LLG_GSG(GG)                 \
+  if (unit) {                       \
+    if (first) LLG_GS(true, true, GG); \
+    else LLG_GS(true, false, GG);   \
+  } else {                          \
+    if (first) LLG_GS(false, true, GG); \
+    else LLG_GS(false, false, GG);  \
+  }
+  if (G == 16) {
+    LLG_GSG(16)
+  } else if (G == 8) {
+    LLG_GSG(8)
+  } else {
+    LLG_GSG(1)
+  }
+#undef LLG_GSG
+#undef LLG_GS
+}
+
+template <typename T>
+void launch_fill(hipStream_t st, T* p, int64_t n) {
+  if (n > 0) hipLaunchKernelGGL((k_fill_zero<T>), dim3(nblk(n)), dim3(TPB), 0, st, p, n);
+}
+
+template <typename T>
 void launch_scale_in(hipStream_t st, int64_t n, const double* dinv0, int left_scale, const double* v, T* b0) {
   if (n > 0) hipLaunchKernelGGL((k_scale_in<T>), dim3(nblk(n)), dim3(TPB), 0, st, n, dinv0, left_scale, v, b0);
 }
@@ -749,7 +819,10 @@ void launch_scale_in(hipStream_t st, int64_t n, const double* dinv0, int left_sc
                                       const T*, const int32_t*, const T*, T*, int);                         \
   template void launch_prolong<T>(hipStream_t, int64_t, int, double, const T*, const T*, const int32_t*,   \
                                   const T*, T*);                                                            \
-  template void launch_scale_in<T>(hipStream_t, int64_t, const double*, int, const double*, T*);
+  template void launch_scale_in<T>(hipStream_t, int64_t, const double*, int, const double*, T*);           \
+  template void launch_gs_sweep<T>(hipStream_t, Sell, const int32_t*, const T*, const T*, int, int, const T*, \
+                                   T*, int);                                                                \
+  template void launch_fill<T>(hipStream_t, T*, int64_t);
 LLG_INST(double)
 LLG_INST(float)
 #undef LLG_INST

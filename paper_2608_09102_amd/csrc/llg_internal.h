@@ -54,9 +54,27 @@ void launch_grid_graph(hipStream_t st, int nx, int ny, int nz, const int32_t* gr
 void launch_pattern_rp(hipStream_t st, int64_t n, const int32_t* grp, int32_t* brp);
 void launch_pattern_cols(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci,
                          const int32_t* brp, int32_t* bci);
-void launch_slice_width(hipStream_t st, int64_t n, const int32_t* brp, int32_t* wslots);
-void launch_sell_cols(hipStream_t st, int64_t n, const int32_t* brp, const int32_t* bci,
+// sliced-ELL structure of rows[0..n) of a CSR pattern (rows == NULL: rows 0..n)
+void launch_slice_width(hipStream_t st, int64_t n, const int32_t* rows, const int32_t* brp, int32_t* wslots);
+void launch_sell_cols(hipStream_t st, int64_t n, const int32_t* rows, const int32_t* brp, const int32_t* bci,
                       const int32_t* sl_ptr, int32_t* col);
+
+// colour classes of the multicolour Gauss-Seidel smoother
+constexpr int MAX_COLOURS = 128;
+void launch_parity_colour(hipStream_t st, int nx, int ny, int nz, int32_t* col);
+// one Jones-Plassmann round; *pending is set non-zero when a node stays uncoloured
+void launch_jp_round(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci, const uint64_t* rank,
+                     int32_t r, int32_t* cround, int32_t* col, int32_t* pending);
+void launch_colour_max(hipStream_t st, int64_t n, const int32_t* col, int32_t* ncol);
+// counting sort by colour: hist has ncol * colour_blocks(n) entries (+1 for the total)
+int64_t colour_blocks(int64_t n);
+void launch_colour_hist(hipStream_t st, int64_t n, const int32_t* col, int32_t ncol, int32_t* hist);
+void launch_colour_place(hipStream_t st, int64_t n, const int32_t* col, int32_t ncol, const int32_t* hist,
+                         int32_t* perm);
+// values (and inverse diagonal blocks when dinv != NULL) of the class rows[0..n)
+template <typename T>
+void launch_cls_gather(hipStream_t st, int64_t n, const int32_t* rows, Sell A, const T* val, const T* dinv,
+                       Sell C, T* cval, T* cdinv);
 
 // pairwise matching (one pass)
 void launch_row_max(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gw, int32_t* mx);
@@ -123,6 +141,14 @@ template <typename T>
 void launch_post_smooth(hipStream_t st, Sell A, const T* val, const T* dinv, int unit, int xmode,
                         double omega, const T* b, const T* x, const int32_t* agg, const T* ec,
                         T* out, int G);
+// One block Gauss-Seidel sweep over a colour class (C: the class as a
+// sliced-ELL matrix, rows: its level rows): x_i += D_i^{-1} (b_i - sum_j A_ij x_j),
+// in place.  first: x is zero everywhere, so x_i = D_i^{-1} b_i.
+template <typename T>
+void launch_gs_sweep(hipStream_t st, Sell C, const int32_t* rows, const T* cval, const T* cdinv, int unit,
+                     int first, const T* b, T* x, int G);
+template <typename T>
+void launch_fill(hipStream_t st, T* p, int64_t n);
 // out = xbase + P ec
 template <typename T>
 void launch_prolong(hipStream_t st, int64_t n, int xmode, double omega, const T* b, const T* x,
