@@ -98,6 +98,8 @@ def lib() -> ctypes.CDLL:
         L.llgo_solve.argtypes = [P, P, P, P, ctypes.POINTER(Stats)]
         L.llgo_step.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), P, ctypes.c_double,
                                 ctypes.c_double, P, P, ctypes.POINTER(Stats)]
+        L.llgo_step2.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), P, P, ctypes.c_double,
+                                 ctypes.c_double, P, P, ctypes.POINTER(Stats)]
         _lib = L
     return _lib
 
@@ -275,4 +277,21 @@ def step(grid: Grid, opts: Opts, m_n: np.ndarray, alpha: float, dt: float, F: np
         Fp = _p(F)
     rc = lib().llgo_step(ctypes.byref(grid), ctypes.byref(opts), _p(m_n), alpha, dt, Fp, _p(out),
                          ctypes.byref(st))
+    return rc, out, st
+
+
+def step2(grid: Grid, opts: Opts, m_n: np.ndarray, m_nm1: np.ndarray, alpha: float, dt: float,
+          F: np.ndarray | None = None):
+    """One oracle BDF2 step from (m^n, m^{n-1}); returns (status, m_np1[N,3], Stats)."""
+    N = grid.n[0] * grid.n[1] * grid.n[2]
+    m_n = np.ascontiguousarray(m_n, dtype=np.float64).reshape(N, 3)
+    m_nm1 = np.ascontiguousarray(m_nm1, dtype=np.float64).reshape(N, 3)
+    out = np.empty_like(m_n)
+    st = Stats()
+    Fp = None
+    if F is not None:
+        F = np.ascontiguousarray(F, dtype=np.float64).reshape(N, 3)
+        Fp = _p(F)
+    rc = lib().llgo_step2(ctypes.byref(grid), ctypes.byref(opts), _p(m_n), _p(m_nm1), alpha, dt, Fp, _p(out),
+                          ctypes.byref(st))
     return rc, out, st

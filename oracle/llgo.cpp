@@ -965,18 +965,20 @@ int llgo_solve(void* h, const double* b, const double* u0, double* u, llgo_stats
 
 // One semi-implicit step (Sec. 2.1): m~ = m^n, b = m^n + dt F, solve, project
 // (Sec. 4.3).
-int llgo_step(const llgo_grid* g, const llgo_opts* o, const double* m_n, double alpha, double dt,
-              const double* F, double* m_np1, llgo_stats* st) {
-  if (!grid_ok(g) || !opts_ok(o) || !m_n || !m_np1) return LLGO_ERR_ARG;
+}  // extern "C"
+
+namespace {
+// Solve the system frozen at m_tilde with time-step factor dt_eff for the
+// right-hand side b, starting from m_tilde (x0_is_mn) or zero, then project
+// (Sec. 4.3) or copy.
+int solve_and_project(const llgo_grid* g, const llgo_opts* o, const double* m_tilde, double alpha,
+                      double dt_eff, const std::vector<double>& b, double* m_np1, llgo_stats* st) {
   const int64_t N = num_nodes(*g), m = 3 * N;
-  for (int64_t i = 0; i < m; ++i)
-    if (!std::isfinite(m_n[i])) return LLGO_ERR_NONFINITE;
   int s = LLGO_OK;
-  Hier* H = (Hier*)llgo_setup(g, o, m_n, alpha, dt, &s);
+  Hier* H = (Hier*)llgo_setup(g, o, m_tilde, alpha, dt_eff, &s);
   if (!H) return s;
-  std::vector<double> b(m), u0(m, 0.0), u(m);
-  for (int64_t i = 0; i < m; ++i) b[i] = F ? m_n[i] + dt * F[i] : m_n[i];
-  if (o->x0_is_mn) std::copy(m_n, m_n + m, u0.begin());
+  std::vector<double> u0(m, 0.0), u(m);
+  if (o->x0_is_mn) std::copy(m_tilde, m_tilde + m, u0.begin());
   s = llgo_solve(H, b.data(), u0.data(), u.data(), st);
   delete H;
   if (s != LLGO_OK && s != LLGO_ERR_NOT_CONVERGED) return s;
@@ -991,6 +993,42 @@ int llgo_step(const llgo_grid* g, const llgo_opts* o, const double* m_n, double 
     std::copy(u.begin(), u.end(), m_np1);
   }
   return s;
+}
+}  // namespace
+
+extern "C" {
+
+// BDF1 (Sec. 2.1): u + dt m^n x Delta_h u + alpha dt m^n x (m^n x Delta_h u)
+// = m^n (+ dt F), m^{n+1} = u / |u|.
+int llgo_step(const llgo_grid* g, const llgo_opts* o, const double* m_n, double alpha, double dt,
+              const double* F, double* m_np1, llgo_stats* st) {
+  if (!grid_ok(g) || !opts_ok(o) || !m_n || !m_np1) return LLGO_ERR_ARG;
+  const int64_t N = num_nodes(*g), m = 3 * N;
+  for (int64_t i = 0; i < m; ++i)
+    if (!std::isfinite(m_n[i])) return LLGO_ERR_NONFINITE;
+  std::vector<double> b(m);
+  for (int64_t i = 0; i < m; ++i) b[i] = F ? m_n[i] + dt * F[i] : m_n[i];
+  return solve_and_project(g, o, m_n, alpha, dt, b, m_np1, st);
+}
+
+// BDF2 with second-order extrapolation: (3 u - 4 m^n + m^{n-1}) / (2 dt)
+// = -m~ x Delta_h u - alpha m~ x (m~ x Delta_h u) + F, m~ = 2 m^n - m^{n-1}.
+// Times 2 dt / 3 this is the BDF1 system frozen at m~ (not of unit length)
+// with dt' = 2 dt / 3 and right-hand side (4 m^n - m^{n-1}) / 3 + dt' F.
+int llgo_step2(const llgo_grid* g, const llgo_opts* o, const double* m_n, const double* m_nm1, double alpha,
+               double dt, const double* F, double* m_np1, llgo_stats* st) {
+  if (!grid_ok(g) || !opts_ok(o) || !m_n || !m_nm1 || !m_np1) return LLGO_ERR_ARG;
+  const int64_t N = num_nodes(*g), m = 3 * N;
+  for (int64_t i = 0; i < m; ++i)
+    if (!std::isfinite(m_n[i]) || !std::isfinite(m_nm1[i])) return LLGO_ERR_NONFINITE;
+  const double dtp = (2.0 * dt) / 3.0;
+  std::vector<double> mt(m), b(m);
+  for (int64_t i = 0; i < m; ++i) {
+    mt[i] = 2.0 * m_n[i] - m_nm1[i];
+    b[i] = (4.0 * m_n[i] - m_nm1[i]) / 3.0;
+    if (F) b[i] = b[i] + dtp * F[i];
+  }
+  return solve_and_project(g, o, mt.data(), alpha, dtp, b, m_np1, st);
 }
 
 }  // extern "C"

@@ -119,6 +119,11 @@ int llgo_solve(void* h, const double* b, const double* u0, double* u, llgo_stats
 int llgo_step(const llgo_grid* g, const llgo_opts* o, const double* m_n, double alpha,
               double dt, const double* F, double* m_np1, llgo_stats* st);
 
+/* One BDF2 step with m~ = 2 m^n - m^{n-1}: the system of llgo_step frozen at
+ * m~ with dt' = 2 dt / 3 and right-hand side (4 m^n - m^{n-1}) / 3 + dt' F. */
+int llgo_step2(const llgo_grid* g, const llgo_opts* o, const double* m_n, const double* m_nm1,
+               double alpha, double dt, const double* F, double* m_np1, llgo_stats* st);
+
 #ifdef __cplusplus
 }
 #endif
