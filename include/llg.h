@@ -78,6 +78,10 @@ typedef enum {
  * none of its earlier neighbours has.  At most 128 colours per level. */
 typedef enum { LLG_SMOOTHER_JACOBI = 0, LLG_SMOOTHER_MCGS = 1 } llg_smoother;
 
+/* Time discretization: first-order backward differentiation with the field
+ * frozen at m^n (Sec. 2.1), or second order with m~ = 2 m^n - m^{n-1}. */
+typedef enum { LLG_SCHEME_BDF1 = 0, LLG_SCHEME_BDF2 = 1 } llg_scheme;
+
 typedef struct {
   int32_t dim;   /* 2 or 3 */
   int32_t n[3];  /* points per axis, each >= 2; n[2] == 1 when dim == 2 */
@@ -100,7 +104,7 @@ typedef struct {
   int32_t max_dense;    /* largest coarsest level (nodes) for the dense solve */
   int32_t left_scale;   /* build the hierarchy on D^{-1} A (block-diagonal scaling) */
   int32_t project;      /* normalize u node by node */
-  int32_t x0_is_mn;     /* initial guess m^n (else 0) */
+  int32_t x0_is_mn;     /* initial guess m~ (m^n for BDF1; else 0) */
   uint64_t agg_salt;    /* salt of the hashed matching order */
   int32_t rebuild_aggregates; /* 1: recompute the matching every step (default) */
   int32_t kcycle_depth; /* coarse corrections of levels 1..depth by the K-cycle (two
@@ -109,6 +113,7 @@ typedef struct {
                            graphs captured once per context (default); 0: eager launches */
   int32_t smoother;     /* llg_smoother: damped block Jacobi (default) or multicolour
                            block Gauss-Seidel (Sec. 3 smooths by Gauss-Seidel) */
+  int32_t scheme;       /* llg_scheme: BDF1 (default) or BDF2, see llg_step */
 } llg_opts;
 
 typedef struct {
@@ -155,11 +160,17 @@ llg_status llg_workspace_bytes(const llg_grid* grid, const llg_opts* opts, size_
 llg_status llg_create(const llg_grid* grid, const llg_opts* opts, void* d_workspace,
                       size_t bytes, void* hip_stream, llg_ctx** out);
 
-/* One time step.  d_m_n: m^n (N x 3); d_m_nm1: m^{n-1}, accepted and unused by
- * BDF1 (may be NULL); alpha >= 0 and dt > 0 finite; d_forcing: F (N x 3) or
- * NULL, giving b = m^n + dt F; d_m_np1: output m^{n+1}, must not overlap
- * d_m_n.  stats may be NULL.  NOT_CONVERGED still writes d_m_np1 (the
- * projected last iterate) and stats. */
+/* One time step.  d_m_n: m^n (N x 3); alpha >= 0 and dt > 0 finite;
+ * d_forcing: F (N x 3) or NULL; d_m_np1: output m^{n+1}, must not overlap
+ * d_m_n or d_m_nm1.  stats may be NULL.  NOT_CONVERGED still writes d_m_np1
+ * (the projected last iterate) and stats.
+ * BDF1 (Sec. 2.1): the system frozen at m~ = m^n, b = m^n + dt F; d_m_nm1 is
+ * not read (may be NULL).
+ * BDF2 (opts.scheme): (3 u - 4 m^n + m^{n-1}) / (2 dt) = -m~ x Lap u
+ * - alpha m~ x (m~ x Lap u) + F with m~ = 2 m^n - m^{n-1}, i.e. the BDF1
+ * operator frozen at m~ with dt' = 2 dt / 3 and b = (4 m^n - m^{n-1}) / 3
+ * + dt' F.  d_m_nm1 = m^{n-1} (N x 3); when it is NULL the step is a BDF1
+ * step (the usual start of a BDF2 run).  The initial guess is m~. */
 llg_status llg_step(llg_ctx* ctx, const double* d_m_n, const double* d_m_nm1, double alpha,
                     double dt, const double* d_forcing, double* d_m_np1, llg_stats* stats);
 

@@ -29,6 +29,7 @@ MAX_LEVELS = 40
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE, ERR_NOT_CONVERGED, ERR_NONFINITE = range(7)
 PREC_FP64, PREC_FP32_AMG = 0, 1
 SMOOTHER_JACOBI, SMOOTHER_MCGS = 0, 1
+SCHEME_BDF1, SCHEME_BDF2 = 0, 1
 KT_NONE, KT_OUTER_SPMV, KT_SMOOTH, KT_RESIDUAL, KT_ARNOLDI, KT_GALERKIN, KT_ASSEMBLE = range(7)
 KERNEL_CLASSES = {"none": 0, "outer_spmv": 1, "smooth": 2, "residual": 3, "arnoldi": 4, "galerkin": 5,
                   "assemble": 6}
@@ -48,7 +49,7 @@ class Opts(ctypes.Structure):
         ("max_levels", ctypes.c_int32), ("max_dense", ctypes.c_int32), ("left_scale", ctypes.c_int32),
         ("project", ctypes.c_int32), ("x0_is_mn", ctypes.c_int32), ("agg_salt", ctypes.c_uint64),
         ("rebuild_aggregates", ctypes.c_int32), ("kcycle_depth", ctypes.c_int32),
-        ("graphs", ctypes.c_int32), ("smoother", ctypes.c_int32),
+        ("graphs", ctypes.c_int32), ("smoother", ctypes.c_int32), ("scheme", ctypes.c_int32),
     ]
 
 
@@ -147,6 +148,8 @@ def default_opts(**kw) -> Opts:
             v = {"fp64": PREC_FP64, "fp32_amg": PREC_FP32_AMG}[v]
         if k == "smoother" and isinstance(v, str):
             v = {"jacobi": SMOOTHER_JACOBI, "mcgs": SMOOTHER_MCGS}[v]
+        if k == "scheme" and isinstance(v, str):
+            v = {"bdf1": SCHEME_BDF1, "bdf2": SCHEME_BDF2}[v]
         setattr(o, k, v)
     return o
 
@@ -212,8 +215,11 @@ class Solver:
         return x
 
     def step(self, m_n, alpha: float, dt: float, forcing=None, out=None, m_nm1=None, check: bool = True):
-        """One time step; returns (m_np1, status, Stats)."""
+        """One time step; returns (m_np1, status, Stats).  m_nm1 (m^{n-1}) is
+        read by BDF2 contexts; without it their step is a BDF1 step."""
         self._field(m_n, "m_n")
+        if m_nm1 is not None:
+            self._field(m_nm1, "m_nm1")
         if forcing is not None:
             self._field(forcing, "forcing")
         if out is None:

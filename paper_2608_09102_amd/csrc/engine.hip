@@ -164,7 +164,7 @@ struct Level {
 };
 
 struct PlanKey {
-  std::tuple<int, int, int, int, int, int, int, int, double, int, int, uint64_t, int, int, int, int, int> k;
+  std::tuple<int, int, int, int, int, int, int, int, double, int, int, uint64_t, int, int, int, int, int, int> k;
   bool operator<(const PlanKey& o) const { return k < o.k; }
 };
 
@@ -175,7 +175,7 @@ PlanKey plan_key(const llg_grid& g, const llg_opts& o) {
   PlanKey k;
   k.k = std::make_tuple(g.dim, g.n[0], g.n[1], g.n[2], o.npass, o.beta_num, o.beta_den, o.max_coarse,
                         o.stagnation, o.max_levels, o.max_dense, o.agg_salt, o.precision, o.restart,
-                        o.left_scale, o.kcycle_depth, o.smoother);
+                        o.left_scale, o.kcycle_depth, o.smoother, o.scheme);
   return k;
 }
 
@@ -221,13 +221,14 @@ struct llg_ctx {
   hipStream_t cap_st = nullptr;
   bool capturing = false;
   bool graphs_ok = true;
-  hipGraphExec_t setup_graph[2] = {nullptr, nullptr};
+  hipGraphExec_t setup_graph[4] = {nullptr, nullptr, nullptr, nullptr};  // [forcing + 2 * bdf2]
   std::vector<hipGraphExec_t> pc_graph;  // preconditioner of iteration j
   std::vector<hipGraphExec_t> it_graph;  // Gram-Schmidt of iteration j
   double* prm = nullptr;          // device: alpha, dt
   double* hprm = nullptr;         // pinned staging for prm
   double* min = nullptr;          // device copy of m^n read by the setup graph
   double* fin = nullptr;          // device copy of the forcing
+  double* mprv = nullptr;         // device copy of m^{n-1} (BDF2)
   // timing of one kernel class
   int timed = LLG_KT_NONE;
   std::vector<hipEvent_t> ev;
@@ -579,6 +580,7 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   c.prm = ar.lazy<double>(4);
   c.min = ar.lazy<double>(m);
   c.fin = ar.lazy<double>(m);
+  if (c.opts.scheme == LLG_SCHEME_BDF2) c.mprv = ar.lazy<double>(m);
 }
 
 bool grid_ok(const llg_grid* g) {
@@ -600,7 +602,8 @@ bool opts_ok(const llg_opts* o) {
          o->max_coarse >= 1 && o->max_levels >= 1 && o->max_levels <= LLG_MAX_LEVELS && o->max_dense >= 1 &&
          (o->precision == LLG_PREC_FP64 || o->precision == LLG_PREC_FP32_AMG) && std::isfinite(o->omega) &&
          std::isfinite(o->stagnation) && o->kcycle_depth >= 0 && o->kcycle_depth <= 8 &&
-         (o->smoother == LLG_SMOOTHER_JACOBI || o->smoother == LLG_SMOOTHER_MCGS);
+         (o->smoother == LLG_SMOOTHER_JACOBI || o->smoother == LLG_SMOOTHER_MCGS) &&
+         (o->scheme == LLG_SCHEME_BDF1 || o->scheme == LLG_SCHEME_BDF2);
 }
 
 // Plan for (grid, opts): cached; computed on the current device.
@@ -648,7 +651,7 @@ std::shared_ptr<Plan> get_plan(const llg_grid& g, const llg_opts& o) {
 // (replayed from the plan), assembly, Galerkin products and the coarsest
 // inverse.  alpha and dt are read from c.prm on the device.
 template <typename T>
-void setup_values(llg_ctx& c, const double* m, const double* F) {
+void setup_values(llg_ctx& c, const double* m, const double* mprev, const double* F) {
   hipStream_t st = c.st;
   const llg_grid& g = c.grid;
   if (c.opts.rebuild_aggregates) {
@@ -664,7 +667,7 @@ void setup_values(llg_ctx& c, const double* m, const double* F) {
   {
     KTimer kt(c, LLG_KT_ASSEMBLE);
     launch_assemble<T>(st, g.n[0], g.n[1], g.n[2], 1.0 / (g.h * g.h), c.prm, c.opts.left_scale,
-                       c.opts.x0_is_mn, m, F, L0.A, c.Aval, (T*)L0.val, c.dinv0, (T*)L0.dinv, c.b, c.u,
+                       c.opts.x0_is_mn, m, mprev, F, L0.A, c.Aval, (T*)L0.val, c.dinv0, (T*)L0.dinv, c.b, c.u,
                        c.flags);
     LCHK();
   }
@@ -738,26 +741,28 @@ hipGraphExec_t try_capture(llg_ctx& c, Fn body) {
   }
 }
 
-void write_params(llg_ctx& c, double alpha, double dt) {
+// alpha and the time-step factor of the system: dt (BDF1) or 2 dt / 3 (BDF2)
+void write_params(llg_ctx& c, double alpha, double dt, bool bdf2 = false) {
   c.hprm[0] = alpha;
-  c.hprm[1] = dt;
+  c.hprm[1] = bdf2 ? (2.0 * dt) / 3.0 : dt;
   HIPX(hipMemcpyAsync(c.prm, c.hprm, 2 * sizeof(double), hipMemcpyHostToDevice, c.st));
 }
 
 // The setup of one step from the internal copies of m^n (and F).
 template <typename T>
-void run_setup(llg_ctx& c, bool forcing) {
+void run_setup(llg_ctx& c, bool forcing, bool bdf2 = false) {
   const double* F = forcing ? c.fin : nullptr;
+  const double* mp = bdf2 ? c.mprv : nullptr;
   if (use_graphs(c)) {
-    hipGraphExec_t& gx = c.setup_graph[forcing ? 1 : 0];
-    if (!gx) gx = try_capture(c, [&]() { setup_values<T>(c, c.min, F); });
+    hipGraphExec_t& gx = c.setup_graph[(forcing ? 1 : 0) + (bdf2 ? 2 : 0)];
+    if (!gx) gx = try_capture(c, [&]() { setup_values<T>(c, c.min, mp, F); });
     if (gx) {
       HIPX(hipGraphLaunch(gx, c.st));
       c.setup_done = true;
       return;
     }
   }
-  setup_values<T>(c, c.min, F);
+  setup_values<T>(c, c.min, mp, F);
   c.setup_done = true;
 }
 
@@ -1059,19 +1064,21 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 }
 
 template <typename T>
-llg_status run_step(llg_ctx& c, const double* m_n, double alpha, double dt, const double* F, double* m_np1,
-                    llg_stats* stats) {
+llg_status run_step(llg_ctx& c, const double* m_n, const double* m_nm1, double alpha, double dt, const double* F,
+                    double* m_np1, llg_stats* stats) {
   const auto t0 = std::chrono::steady_clock::now();
   c.kernel_ms = 0;
   c.launches = 0;
   c.ev_used = 0;
   const int64_t fb = (int64_t)sizeof(double) * 3 * c.N;
+  const bool bdf2 = c.opts.scheme == LLG_SCHEME_BDF2 && m_nm1 != nullptr;
   HIPX(hipMemcpyAsync(c.min, m_n, fb, hipMemcpyDeviceToDevice, c.st));
   if (F) HIPX(hipMemcpyAsync(c.fin, F, fb, hipMemcpyDeviceToDevice, c.st));
-  write_params(c, alpha, dt);
+  if (bdf2) HIPX(hipMemcpyAsync(c.mprv, m_nm1, fb, hipMemcpyDeviceToDevice, c.st));
+  write_params(c, alpha, dt, bdf2);
   launch_fill_i32(c.st, c.flags, 1, 0);
   LCHK();
-  run_setup<T>(c, F != nullptr);
+  run_setup<T>(c, F != nullptr, bdf2);
   HIPX(hipStreamSynchronize(c.st));
   const double t_setup = ms_since(t0);
   SolveOut so = fgmres<T>(c);
@@ -1161,6 +1168,7 @@ void llg_default_opts(llg_opts* o) {
   o->kcycle_depth = 0;
   o->graphs = 1;
   o->smoother = LLG_SMOOTHER_JACOBI;
+  o->scheme = LLG_SCHEME_BDF1;
 }
 
 llg_status llg_workspace_bytes(const llg_grid* grid, const llg_opts* opts, size_t* bytes) {
@@ -1258,20 +1266,24 @@ llg_status llg_setup(llg_ctx* ctx, const double* d_m_tilde, double alpha, double
 
 llg_status llg_step(llg_ctx* ctx, const double* d_m_n, const double* d_m_nm1, double alpha, double dt,
                     const double* d_forcing, double* d_m_np1, llg_stats* stats) {
-  (void)d_m_nm1;
   llg_status s = check_ctx(ctx);
   if (s != LLG_OK) return s;
   if (!d_m_n || !d_m_np1 || !aligned8(d_m_n) || !aligned8(d_m_np1) || (d_forcing && !aligned8(d_forcing)))
     return LLG_ERR_INVALID_ARG;
   if (!(dt > 0) || !std::isfinite(dt) || !(alpha >= 0) || !std::isfinite(alpha)) return LLG_ERR_INVALID_ARG;
   const size_t fb = sizeof(double) * 3 * (size_t)ctx->N;
-  const char* a0 = (const char*)d_m_n;
-  const char* b0 = (const char*)d_m_np1;
-  if (a0 < b0 + fb && b0 < a0 + fb) return LLG_ERR_INVALID_ARG;
+  auto overlap = [fb](const void* x, const void* y) {
+    const char* a0 = (const char*)x;
+    const char* b0 = (const char*)y;
+    return a0 < b0 + fb && b0 < a0 + fb;
+  };
+  if (overlap(d_m_n, d_m_np1)) return LLG_ERR_INVALID_ARG;
+  const double* prev = ctx->opts.scheme == LLG_SCHEME_BDF2 ? d_m_nm1 : nullptr;
+  if (prev && (!aligned8(prev) || overlap(prev, d_m_np1))) return LLG_ERR_INVALID_ARG;
   return guard([&]() -> llg_status {
     if (ctx->opts.precision == LLG_PREC_FP32_AMG)
-      return run_step<float>(*ctx, d_m_n, alpha, dt, d_forcing, d_m_np1, stats);
-    return run_step<double>(*ctx, d_m_n, alpha, dt, d_forcing, d_m_np1, stats);
+      return run_step<float>(*ctx, d_m_n, prev, alpha, dt, d_forcing, d_m_np1, stats);
+    return run_step<double>(*ctx, d_m_n, prev, alpha, dt, d_forcing, d_m_np1, stats);
   });
 }
 

@@ -588,8 +588,9 @@ __global__ void k_cls_gather(int64_t n, const int32_t* __restrict__ rows, const 
 // initial guess written alongside.
 template <typename T>
 __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* __restrict__ prm,
-                           int left_scale, int x0_is_mn, const double* __restrict__ m,
-                           const double* __restrict__ F, const int32_t* __restrict__ sl_ptr,
+                           int left_scale, int x0_is_mn, const double* __restrict__ mn,
+                           const double* __restrict__ mprev, const double* __restrict__ F,
+                           const int32_t* __restrict__ sl_ptr,
                            const int32_t* __restrict__ col, double* __restrict__ Aval,
                            T* __restrict__ Lval, double* __restrict__ dinv0, T* __restrict__ ldinv,
                            double* __restrict__ b, double* __restrict__ u, int32_t* flag) {
@@ -597,8 +598,25 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
   const int64_t N = (int64_t)nx * ny * nz;
   if (p >= N) return;
   const double alpha = prm[0], dt = prm[1];
-  const double m1 = m[3 * p], m2 = m[3 * p + 1], m3 = m[3 * p + 2];
-  if (!isfinite(m1) || !isfinite(m2) || !isfinite(m3)) atomicOr(flag, 1);
+  // frozen field: m^n (BDF1) or 2 m^n - m^{n-1} (BDF2, mprev != NULL)
+  double mt[3], bb[3];
+  bool fin = true;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double a = mn[3 * p + c];
+    fin = fin && isfinite(a);
+    if (mprev) {
+      const double q = mprev[3 * p + c];
+      fin = fin && isfinite(q);
+      mt[c] = 2.0 * a - q;
+      bb[c] = (4.0 * a - q) / 3.0;
+    } else {
+      mt[c] = a;
+      bb[c] = a;
+    }
+  }
+  if (!fin) atomicOr(flag, 1);
+  const double m1 = mt[0], m2 = mt[1], m3 = mt[2];
   int64_t nb[6];
   const int deg = grid_nbrs(nx, ny, nz, p, nb);
   double M[9];
@@ -661,9 +679,8 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double mc = m[3 * p + c];
-    b[3 * p + c] = F ? mc + dt * F[3 * p + c] : mc;
-    u[3 * p + c] = x0_is_mn ? mc : 0.0;
+    b[3 * p + c] = F ? bb[c] + dt * F[3 * p + c] : bb[c];
+    u[3 * p + c] = x0_is_mn ? mt[c] : 0.0;
   }
 }
 
@@ -977,19 +994,19 @@ void launch_member_sort(hipStream_t st, int64_t nc, const int32_t* mptr, int32_t
 
 template <typename T>
 void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, const double* prm,
-                     int left_scale, int x0_is_mn, const double* m, const double* F, Sell A,
-                     double* Aval, T* Lval, double* dinv0, T* ldinv, double* b, double* u,
+                     int left_scale, int x0_is_mn, const double* m, const double* mprev, const double* F,
+                     Sell A, double* Aval, T* Lval, double* dinv0, T* ldinv, double* b, double* u,
                      int32_t* flag) {
   const int64_t N = (int64_t)nx * ny * nz;
   hipLaunchKernelGGL((k_assemble<T>), dim3(nblk(N)), dim3(TPB), 0, st, nx, ny, nz, inv_h2, prm,
-                     left_scale, x0_is_mn, m, F, A.sl_ptr, A.col, Aval, Lval, dinv0, ldinv, b, u, flag);
+                     left_scale, x0_is_mn, m, mprev, F, A.sl_ptr, A.col, Aval, Lval, dinv0, ldinv, b, u, flag);
 }
 template void launch_assemble<double>(hipStream_t, int, int, int, double, const double*, int, int,
-                                      const double*, const double*, Sell, double*, double*, double*,
-                                      double*, double*, double*, int32_t*);
+                                      const double*, const double*, const double*, Sell, double*, double*,
+                                      double*, double*, double*, double*, int32_t*);
 template void launch_assemble<float>(hipStream_t, int, int, int, double, const double*, int, int,
-                                     const double*, const double*, Sell, double*, float*, double*,
-                                     float*, double*, double*, int32_t*);
+                                     const double*, const double*, const double*, Sell, double*, float*,
+                                     double*, float*, double*, double*, int32_t*);
 
 void init_kernel_attributes() {
   const size_t lds_max = (size_t)(GJ_LDS_MAX * GJ_LDS_MAX + GJ_LDS_MAX + GJ_T) * sizeof(double) +

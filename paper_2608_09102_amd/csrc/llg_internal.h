@@ -100,12 +100,15 @@ void launch_member_fill(hipStream_t st, int64_t n, const int32_t* agg, const int
                         int32_t* cursor, int32_t* mem);
 void launch_member_sort(hipStream_t st, int64_t nc, const int32_t* mptr, int32_t* mem);
 
-// assembly of the fine operator (FP64 A) and the scaled level-0 operator
-// prm[0] = alpha, prm[1] = dt (device memory, so captured graphs stay valid)
+// assembly of the fine operator (FP64 A) and the scaled level-0 operator,
+// the right-hand side b and the initial guess u; the frozen field is m
+// (mprev == NULL) or 2 m - mprev (BDF2, b = (4 m - mprev) / 3 + dt F).
+// prm[0] = alpha, prm[1] = the time-step factor (device memory, so captured
+// graphs stay valid)
 template <typename T>
 void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, const double* prm,
-                     int left_scale, int x0_is_mn, const double* m, const double* F, Sell A,
-                     double* Aval, T* Lval, double* dinv0, T* ldinv, double* b, double* u,
+                     int left_scale, int x0_is_mn, const double* m, const double* mprev, const double* F,
+                     Sell A, double* Aval, T* Lval, double* dinv0, T* ldinv, double* b, double* u,
                      int32_t* flag);
 
 // Galerkin block sums P^T A P and the inverse diagonal blocks of the result
