@@ -150,22 +150,29 @@ def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str, Fs, kd
 
 
 def cpu_baseline(w, nsteps: int):
+    """The oracle timed on `nsteps` steps of the workload from m0 (forcing of
+    the first steps when the workload has one); also returns its first step."""
     import numpy as np
     import oracle
+    import llg_inputs as I
     g = oracle.make_grid(w.dim, w.n)
     o = oracle.default_opts(rtol=w.rtol)
     m = w.m0()
     t0 = time.perf_counter()
     iters = []
-    for _ in range(nsteps):
-        rc, m, st = oracle.step(g, o, m, w.alpha, w.dt)
+    first = None
+    for k in range(nsteps):
+        F = I.manufactured_forcing(w.dim, w.n, (k + 1) * w.dt, w.alpha) if w.forcing else None
+        rc, m, st = oracle.step(g, o, m, w.alpha, w.dt, F)
         iters.append(st.iters)
+        if first is None:
+            first = m.copy()
     el = time.perf_counter() - t0
     return {"value": 3.0 * w.nodes * nsteps / el, "unit": "unknowns*steps/s", "cores": 1, "kind": "oracle",
             "sample": "%d step(s) of the %s workload (assembly, hierarchy, FGMRES to rtol %g, projection), "
                       "single-threaded C++ oracle, %.1f s, %s FGMRES iterations"
                       % (nsteps, w.name, w.rtol, el, iters),
-            "host_threads_available": os.cpu_count()}
+            "host_threads_available": os.cpu_count()}, first
 
 
 def serve_bench(a):
@@ -297,7 +304,13 @@ def main():
         out["err_vs_exact"] = r["err_vs_exact"]
     if not a.no_cpu_baseline:
         log("[bench] cpu baseline: oracle, %d step(s)" % a.cpu_steps)
-        out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
+        out["cpu_baseline"], ref = cpu_baseline(w, a.cpu_steps)
+        # error of every form's first step against the FP64 oracle's (both at the workload's rtol)
+        import numpy as np
+        out["err_vs_oracle"] = float(np.abs(r["one_step"].cpu().numpy() - ref).max())
+        for key, prec, kd, sm in forms[1:]:
+            name = "%s_%s%s" % (prec, "k%d" % kd if kd else "vcycle", "" if sm == "jacobi" else "_" + sm)
+            out[name]["err_vs_oracle"] = float(np.abs(res[key]["one_step"].cpu().numpy() - ref).max())
     print(json.dumps(out), flush=True)
 
 
