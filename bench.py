@@ -35,8 +35,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="rough2d_1024")
     p.add_argument("--forms", default="fp64:1,fp32_amg:1,fp64:0",
-                   help="comma list of precision:kcycle_depth[:smoother] (depth 0 = V-cycle; smoother "
-                        "jacobi or mcgs, default jacobi); the first gives `value`")
+                   help="comma list of precision:kcycle_depth[:smoother[:operator]] (depth 0 = V-cycle; "
+                        "smoother jacobi or mcgs, default jacobi; grid-level operator bsr or factored, "
+                        "default bsr); the first gives `value`")
     p.add_argument("--roofline-class", default="outer_spmv")
     p.add_argument("--alpha", type=float, default=None, help="override the workload's alpha")
     p.add_argument("--kdepth", type=int, default=None, help="override the K-cycle depth of every form")
@@ -62,9 +63,10 @@ def source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel: str, workload: str, launch_bytes: float):
+def read_traffic(kernel: str, workload: str, precision: str, operator: str):
     """HBM bytes per launch from the committed PMC summary, or None when the
-    summary is missing or was taken on a different kernel source."""
+    summary is missing, was taken on another form or on a different kernel
+    source."""
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (kernel, workload))
     if not os.path.exists(path):
         return None
@@ -76,18 +78,22 @@ def read_traffic(kernel: str, workload: str, launch_bytes: float):
                 kv[k.strip()] = v.strip()
     if kv.get("source_sha") != source_sha():
         return None
+    if kv.get("precision", "fp64") != precision or kv.get("grid_operator", "bsr") != operator:
+        return None
     try:
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
 
-def algorithmic_bytes(cls: str, st, N: int, precision: str) -> float:
+def algorithmic_bytes(cls: str, st, N: int, precision: str, operator: str = "bsr") -> float:
     """Bytes one launch of the kernel class must move at minimum (values,
     indices, input vector read once, output written once)."""
     nnzb0 = st.level_nnzb[0]
     if cls == "outer_spmv":
         zb = 4 if precision == "fp32_amg" else 8
+        if operator == "factored":  # one FP64 block per node, neighbours from the grid
+            return 72.0 * N + 3.0 * zb * N + 24.0 * N
         return 72.0 * nnzb0 + 4.0 * nnzb0 + 3.0 * zb * N + 24.0 * N
     raise ValueError("no byte model for kernel class " + cls)
 
@@ -103,8 +109,9 @@ def forcing_list(torch, w, total: int):
 
 
 def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str, Fs, kdepth: int = 0,
-             smoother: str = "jacobi"):
-    opts = llg.default_opts(rtol=w.rtol, precision=form, kcycle_depth=kdepth, smoother=smoother)
+             smoother: str = "jacobi", operator: str = "bsr"):
+    opts = llg.default_opts(rtol=w.rtol, precision=form, kcycle_depth=kdepth, smoother=smoother,
+                            fine_operator=operator)
     grid = llg.make_grid(w.dim, w.n)
     S = llg.Solver(grid, opts)
     m0 = torch.from_numpy(w.m0()).cuda()
@@ -240,28 +247,29 @@ def main():
         prec = parts[0]
         kd = int(parts[1]) if len(parts) > 1 and parts[1] else 0
         sm = parts[2] if len(parts) > 2 and parts[2] else "jacobi"
+        op = parts[3] if len(parts) > 3 and parts[3] else "bsr"
         if a.kdepth is not None:
             kd = a.kdepth
-        forms.append((f, prec, kd, sm))
+        forms.append((f, prec, kd, sm, op))
     Fs = forcing_list(torch, w, a.warmup + a.steps)
     res = {}
-    for key, prec, kd, sm in forms:
-        log("[bench] %s %s kcycle_depth %d smoother %s: %d warmup + %d timed steps"
-            % (w.name, prec, kd, sm, a.warmup, a.steps))
-        res[key] = run_form(llg, torch, w, prec, a.steps, a.warmup, a.roofline_class, Fs, kd, sm)
+    for key, prec, kd, sm, op in forms:
+        log("[bench] %s %s kcycle_depth %d smoother %s operator %s: %d warmup + %d timed steps"
+            % (w.name, prec, kd, sm, op, a.warmup, a.steps))
+        res[key] = run_form(llg, torch, w, prec, a.steps, a.warmup, a.roofline_class, Fs, kd, sm, op)
         r = res[key]
         log("  %.3f s, %.2f ms/step, iters/step %.1f, %s kernel %.3f ms over %d launches"
             % (r["seconds"], 1e3 * r["seconds"] / a.steps, sum(r["iters"]) / len(r["iters"]),
                a.roofline_class, r["kernel_ms"], r["kernel_launches"]))
-    main_key, main_form, main_kd, main_sm = forms[0]
+    main_key, main_form, main_kd, main_sm, main_op = forms[0]
     r = res[main_key]
     unknowns = w.unknowns
     value = unknowns * a.steps / r["seconds"]
     # roofline of the timed kernel class
-    lb = algorithmic_bytes(a.roofline_class, r["stats"], w.nodes, main_form)
+    lb = algorithmic_bytes(a.roofline_class, r["stats"], w.nodes, main_form, main_op)
     avg_s = r["kernel_ms"] / 1e3 / max(1, r["kernel_launches"])
     achieved = lb / avg_s / 1e9 if avg_s > 0 else 0.0
-    traffic = read_traffic(a.roofline_class, w.name, lb)
+    traffic = read_traffic(a.roofline_class, w.name, main_form, main_op)
     out = {
         "metric": "unknowns*steps/s (FP64 AMG-FGMRES, rel.res 1e-8)",
         "value": value,
@@ -280,7 +288,8 @@ def main():
                    "form": main_form, "hierarchy": "rebuilt every step", "krylov": "FGMRES(30)",
                    "preconditioner": "aggregation AMG, %s (1,1), %s" % (
                        "damped block-Jacobi" if main_sm == "jacobi" else "multicolour block Gauss-Seidel",
-                       "K-cycle on levels 1..%d" % main_kd if main_kd else "V-cycle")},
+                       "K-cycle on levels 1..%d" % main_kd if main_kd else "V-cycle"),
+                   "grid_operator": "3x3-block sliced ELL" if main_op == "bsr" else "factored (one block per node)"},
         "iters_per_step": sum(r["iters"]) / len(r["iters"]),
         "iters": r["iters"],
         "levels": r["levels"],
@@ -291,13 +300,17 @@ def main():
                      "traffic": traffic, "algorithmic_bytes_per_launch": lb,
                      "avg_launch_us": avg_s * 1e6, "launches": r["kernel_launches"]},
     }
-    for key, prec, kd, sm in forms[1:]:
+    def form_name(prec, kd, sm, op):
+        return "%s_%s%s%s" % (prec, "k%d" % kd if kd else "vcycle", "" if sm == "jacobi" else "_" + sm,
+                              "" if op == "bsr" else "_" + op)
+
+    for key, prec, kd, sm, op in forms[1:]:
         rf = res[key]
         diff = float((rf["one_step"] - r["one_step"]).abs().max())
-        name = "%s_%s%s" % (prec, "k%d" % kd if kd else "vcycle", "" if sm == "jacobi" else "_" + sm)
+        name = form_name(prec, kd, sm, op)
         out[name] = {"value": unknowns * a.steps / rf["seconds"], "ms_per_step": 1e3 * rf["seconds"] / a.steps,
                      "iters_per_step": sum(rf["iters"]) / len(rf["iters"]), "iters": rf["iters"],
-                     "err_vs_exact": rf["err_vs_exact"], "kcycle_depth": kd, "smoother": sm,
+                     "err_vs_exact": rf["err_vs_exact"], "kcycle_depth": kd, "smoother": sm, "grid_operator": op,
                      "speedup_vs_main": (unknowns * a.steps / rf["seconds"]) / value,
                      "max_abs_diff_one_step_vs_main": diff}
     if r["err_vs_exact"] is not None:
@@ -308,8 +321,8 @@ def main():
         # error of every form's first step against the FP64 oracle's (both at the workload's rtol)
         import numpy as np
         out["err_vs_oracle"] = float(np.abs(r["one_step"].cpu().numpy() - ref).max())
-        for key, prec, kd, sm in forms[1:]:
-            name = "%s_%s%s" % (prec, "k%d" % kd if kd else "vcycle", "" if sm == "jacobi" else "_" + sm)
+        for key, prec, kd, sm, op in forms[1:]:
+            name = form_name(prec, kd, sm, op)
             out[name]["err_vs_oracle"] = float(np.abs(res[key]["one_step"].cpu().numpy() - ref).max())
     print(json.dumps(out), flush=True)
 

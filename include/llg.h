@@ -82,6 +82,18 @@ typedef enum { LLG_SMOOTHER_JACOBI = 0, LLG_SMOOTHER_MCGS = 1 } llg_smoother;
  * frozen at m^n (Sec. 2.1), or second order with m~ = 2 m^n - m^{n-1}. */
 typedef enum { LLG_SCHEME_BDF1 = 0, LLG_SCHEME_BDF2 = 1 } llg_scheme;
 
+/* Storage of the grid-level operators A and D^{-1} A.
+ * BSR: 3x3-block sliced ELL, one block per stored (row, column) (default).
+ * FACTORED: on the grid every off-diagonal block of row p is the same block,
+ * Mh_p = (dt/h^2) M_p in A and K_p = D_p^{-1} Mh_p in D^{-1} A (whose diagonal
+ * blocks are the identity), so one block per node is stored and the
+ * neighbours come from the grid: (A z)_p = z_p + Mh_p (sum_q z_q - deg_p z_p),
+ * (D^{-1} A x)_p = x_p + K_p sum_q x_q.  The coarse levels are identical in
+ * both forms; the grid-level products differ by rounding.  Requires
+ * left_scale (else UNSUPPORTED); a grid whose first level is already the
+ * coarsest is stored as BSR. */
+typedef enum { LLG_FINE_BSR = 0, LLG_FINE_FACTORED = 1 } llg_fine_operator;
+
 typedef struct {
   int32_t dim;   /* 2 or 3 */
   int32_t n[3];  /* points per axis, each >= 2; n[2] == 1 when dim == 2 */
@@ -114,6 +126,7 @@ typedef struct {
   int32_t smoother;     /* llg_smoother: damped block Jacobi (default) or multicolour
                            block Gauss-Seidel (Sec. 3 smooths by Gauss-Seidel) */
   int32_t scheme;       /* llg_scheme: BDF1 (default) or BDF2, see llg_step */
+  int32_t fine_operator; /* llg_fine_operator: storage of the grid level, see below */
 } llg_opts;
 
 typedef struct {
@@ -186,7 +199,9 @@ llg_status llg_num_levels(llg_ctx* ctx, int32_t* levels);
 llg_status llg_level_info(llg_ctx* ctx, int32_t level, int64_t* n, int64_t* nnzb);
 
 /* Host copy of a level in BSR form: h_row_ptr[n+1], h_col[nnzb] ascending per
- * row, h_vals[nnzb][3][3] row-major (FP32 levels are widened to double).
+ * row, h_vals[nnzb][3][3] row-major (FP32 levels are widened to double).  A
+ * factored grid level is expanded to the blocks its products apply (the
+ * diagonal block of level -1 is then I - deg_p Mh_p).
  * cap_nnzb is the capacity of h_col (blocks).  Synchronizes the stream. */
 llg_status llg_get_level(llg_ctx* ctx, int32_t level, int32_t* h_row_ptr, int32_t* h_col,
                          double* h_vals, int64_t cap_nnzb);

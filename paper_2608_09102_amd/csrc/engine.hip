@@ -161,10 +161,11 @@ struct Level {
   std::vector<int64_t> coff;
   std::vector<Sell> cls;
   std::vector<void*> cval, cdinv;
+  void* kf = nullptr;  // factored grid level: K_p per node ([slice][9][64])
 };
 
 struct PlanKey {
-  std::tuple<int, int, int, int, int, int, int, int, double, int, int, uint64_t, int, int, int, int, int, int> k;
+  std::tuple<int, int, int, int, int, int, int, int, double, int, int, uint64_t, int, int, int, int, int, int, int> k;
   bool operator<(const PlanKey& o) const { return k < o.k; }
 };
 
@@ -175,7 +176,7 @@ PlanKey plan_key(const llg_grid& g, const llg_opts& o) {
   PlanKey k;
   k.k = std::make_tuple(g.dim, g.n[0], g.n[1], g.n[2], o.npass, o.beta_num, o.beta_den, o.max_coarse,
                         o.stagnation, o.max_levels, o.max_dense, o.agg_salt, o.precision, o.restart,
-                        o.left_scale, o.kcycle_depth, o.smoother, o.scheme);
+                        o.left_scale, o.kcycle_depth, o.smoother, o.scheme, o.fine_operator);
   return k;
 }
 
@@ -195,9 +196,12 @@ struct llg_ctx {
   llg::Level lv[LLG_MAX_LEVELS];
   double omega = 0;
   int64_t N = 0;
-  // fine operator (FP64) and its inverse diagonal blocks
+  // fine operator (FP64) and its inverse diagonal blocks; in the factored
+  // form the per-node off-diagonal block Mh replaces the sliced-ELL values
   double* Aval = nullptr;
   double* dinv0 = nullptr;
+  bool fact = false;
+  double* Mh = nullptr;
   // coarsest
   int64_t nd = 0;
   double* dense = nullptr;
@@ -524,12 +528,19 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   const size_t ts = f32 ? sizeof(float) : sizeof(double);
   const int R = c.opts.restart;
   Level& L0 = c.lv[0];
-  c.Aval = ar.lazy<double>(9 * L0.A.nslots);
+  // the factored grid level needs a coarse level (the coarsest is stored as BSR)
+  c.fact = c.opts.fine_operator == LLG_FINE_FACTORED && c.L > 1;
+  if (c.fact) {
+    c.Mh = ar.lazy<double>(9 * L0.A.nslices * SL);
+    L0.kf = ar.get(ts * 9 * L0.A.nslices * SL, true);
+  } else {
+    c.Aval = ar.lazy<double>(9 * L0.A.nslots);
+  }
   c.dinv0 = ar.lazy<double>(9 * L0.A.nslices * SL);
   for (int l = 0; l < c.L; ++l) {
     Level& L = c.lv[l];
     const int64_t n = L.A.n;
-    L.val = ar.get(ts * 9 * L.A.nslots, true);
+    if (!(l == 0 && c.fact)) L.val = ar.get(ts * 9 * L.A.nslots, true);
     L.unit = l == 0 && c.opts.left_scale;
     L.G = n >= 32768 ? 1 : (c.grid.dim == 3 ? 16 : 8);
     L.dinv = ar.get(ts * 9 * L.A.nslices * SL, true);
@@ -603,7 +614,8 @@ bool opts_ok(const llg_opts* o) {
          (o->precision == LLG_PREC_FP64 || o->precision == LLG_PREC_FP32_AMG) && std::isfinite(o->omega) &&
          std::isfinite(o->stagnation) && o->kcycle_depth >= 0 && o->kcycle_depth <= 8 &&
          (o->smoother == LLG_SMOOTHER_JACOBI || o->smoother == LLG_SMOOTHER_MCGS) &&
-         (o->scheme == LLG_SCHEME_BDF1 || o->scheme == LLG_SCHEME_BDF2);
+         (o->scheme == LLG_SCHEME_BDF1 || o->scheme == LLG_SCHEME_BDF2) &&
+         (o->fine_operator == LLG_FINE_BSR || o->fine_operator == LLG_FINE_FACTORED);
 }
 
 // Plan for (grid, opts): cached; computed on the current device.
@@ -668,21 +680,23 @@ void setup_values(llg_ctx& c, const double* m, const double* mprev, const double
     KTimer kt(c, LLG_KT_ASSEMBLE);
     launch_assemble<T>(st, g.n[0], g.n[1], g.n[2], 1.0 / (g.h * g.h), c.prm, c.opts.left_scale,
                        c.opts.x0_is_mn, m, mprev, F, L0.A, c.Aval, (T*)L0.val, c.dinv0, (T*)L0.dinv, c.b, c.u,
-                       c.flags);
+                       c.flags, c.Mh, (T*)L0.kf);
     LCHK();
   }
   for (int l = 0; l + 1 < c.L; ++l) {
     Level& L = c.lv[l];
     Level& Nx = c.lv[l + 1];
     KTimer kt(c, LLG_KT_GALERKIN);
-    launch_galerkin<T>(st, Nx.A, (T*)Nx.val, (T*)Nx.dinv, L.mptr, L.mem, L.A, (const T*)L.val, L.agg);
+    launch_galerkin<T>(st, Nx.A, (T*)Nx.val, (T*)Nx.dinv, L.mptr, L.mem, L.A, (const T*)L.val, L.agg,
+                       (const T*)L.kf);
     LCHK();
   }
   for (int l = 0; l + 1 < c.L; ++l) {  // colour-class copies for Gauss-Seidel
     Level& L = c.lv[l];
     for (int q = 0; q < L.ncol; ++q)
       launch_cls_gather<T>(st, L.cls[q].n, L.perm + L.coff[q], L.A, (const T*)L.val,
-                           L.unit ? nullptr : (const T*)L.dinv, L.cls[q], (T*)L.cval[q], (T*)L.cdinv[q]);
+                           L.unit ? nullptr : (const T*)L.dinv, L.cls[q], (T*)L.cval[q], (T*)L.cdinv[q],
+                           (const T*)L.kf);
   }
   LCHK();
   Level& C = c.lv[c.L - 1];
@@ -766,6 +780,47 @@ void run_setup(llg_ctx& c, bool forcing, bool bdf2 = false) {
   c.setup_done = true;
 }
 
+// ------------------------------------------------------------------ products
+// Level and outer products, dispatched to the factored kernels on the grid
+// level when the context stores it in factored form.
+GridDims gdims(const llg_ctx& c) { return GridDims{c.grid.n[0], c.grid.n[1], c.grid.n[2]}; }
+
+template <typename T>
+void lvl_residual(llg_ctx& c, int l, int xmode, const T* b, const T* x, T* r) {
+  Level& L = c.lv[l];
+  if (l == 0 && c.fact)
+    launch_fact_residual<T>(c.st, gdims(c), (const T*)L.kf, xmode, c.omega, b, x, r);
+  else
+    launch_residual<T>(c.st, L.A, (const T*)L.val, xmode, c.omega, b, x, r, L.G);
+}
+
+template <typename T>
+void lvl_post_smooth(llg_ctx& c, int l, int xmode, const T* b, const T* x, const int32_t* agg, const T* ec,
+                     T* out) {
+  Level& L = c.lv[l];
+  if (l == 0 && c.fact)
+    launch_fact_post_smooth<T>(c.st, gdims(c), (const T*)L.kf, xmode, c.omega, b, x, agg, ec, out);
+  else
+    launch_post_smooth<T>(c.st, L.A, (const T*)L.val, (const T*)L.dinv, L.unit, xmode, c.omega, b, x, agg, ec, out,
+                          L.G);
+}
+
+template <typename TZ>
+void outer_spmv(llg_ctx& c, const TZ* z, double* w) {
+  if (c.fact)
+    launch_fact_outer<TZ>(c.st, gdims(c), c.Mh, z, w);
+  else
+    launch_spmv_outer<TZ>(c.st, c.lv[0].A, c.Aval, z, w);
+}
+
+// r = b - A u and the partial sums of |r|^2
+void outer_resid(llg_ctx& c) {
+  if (c.fact)
+    launch_fact_resid_outer(c.st, gdims(c), c.Mh, c.b, c.u, c.r, c.part);
+  else
+    launch_resid_outer(c.st, c.lv[0].A, c.Aval, c.b, c.u, c.r, c.part);
+}
+
 // ------------------------------------------------------------------ V-cycle
 template <typename T>
 void kcorrection(llg_ctx& c, int lc);
@@ -818,7 +873,7 @@ void vcycle(llg_ctx& c, int l, const T* b, T* out) {
     }
     for (int s = 1; s < o.nu_pre; ++s) {
       T* dst = (xcur == X) ? XO : X;
-      launch_post_smooth<T>(st, L.A, val, dinv, L.unit, xmode, om, b, xcur, nullptr, nullptr, dst, L.G);
+      lvl_post_smooth<T>(c, l, xmode, b, xcur, nullptr, nullptr, dst);
       xmode = 0;
       xcur = dst;
     }
@@ -829,7 +884,7 @@ void vcycle(llg_ctx& c, int l, const T* b, T* out) {
     const bool pre_next = o.nu_pre >= 1 && l + 1 < c.L - 1;
     const T* rsrc = b;
     if (xmode != 2) {
-      launch_residual<T>(st, L.A, val, xmode, om, b, xcur, (T*)L.r, L.G);
+      lvl_residual<T>(c, l, xmode, b, xcur, (T*)L.r);
       rsrc = (const T*)L.r;
     }
     launch_restrict<T>(st, L.nc, L.mptr, L.mem, rsrc, (T*)Nx.b, pre_next ? (const T*)Nx.dinv : nullptr, om,
@@ -853,9 +908,9 @@ void vcycle(llg_ctx& c, int l, const T* b, T* out) {
     const bool last = s == o.nu_post - 1;
     T* dst = last ? out : (xcur == XO ? X : XO);
     if (s == 0) {
-      launch_post_smooth<T>(st, L.A, val, dinv, L.unit, xmode, om, b, xcur, L.agg, ec, dst, L.G);
+      lvl_post_smooth<T>(c, l, xmode, b, xcur, L.agg, ec, dst);
     } else {
-      launch_post_smooth<T>(st, L.A, val, dinv, L.unit, 0, om, b, xcur, nullptr, nullptr, dst, L.G);
+      lvl_post_smooth<T>(c, l, 0, b, xcur, nullptr, nullptr, dst);
     }
     LCHK();
     xcur = dst;
@@ -893,7 +948,7 @@ void vcycle_gs(llg_ctx& c, int l, const T* b, T* out) {
     KTimer kt(c, LLG_KT_RESIDUAL);
     const T* rsrc = b;
     if (o.nu_pre >= 1) {
-      launch_residual<T>(st, L.A, (const T*)L.val, 0, c.omega, b, X, (T*)L.r, L.G);
+      lvl_residual<T>(c, l, 0, b, X, (T*)L.r);
       rsrc = (const T*)L.r;
     }
     launch_restrict<T>(st, L.nc, L.mptr, L.mem, rsrc, (T*)Nx.b, nullptr, c.omega, nullptr);
@@ -964,7 +1019,7 @@ void iter_precond(llg_ctx& c, int j) {
 template <typename T>
 void iter_spmv(llg_ctx& c, int j) {
   KTimer kt(c, LLG_KT_OUTER_SPMV);
-  launch_spmv_outer<T>(c.st, c.lv[0].A, c.Aval, (const T*)c.Z + (int64_t)j * c.ld, c.w);
+  outer_spmv<T>(c, (const T*)c.Z + (int64_t)j * c.ld, c.w);
   LCHK();
 }
 
@@ -1015,7 +1070,7 @@ SolveOut fgmres(llg_ctx& c) {
   // ||b|| and r = b - A u
   launch_norm_part(st, m, c.b, c.part);
   launch_norm_finish_n(st, c.part, c.npart_vec, 2, c.ks.sc, H);
-  launch_resid_outer(st, L0.A, c.Aval, c.b, c.u, c.r, c.part);
+  outer_resid(c);
   launch_norm_finish_n(st, c.part, c.npart_rows, 0, c.ks.sc, H);
   LCHK();
   HIPX(hipMemcpyAsync(c.hflags, c.flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -1047,7 +1102,7 @@ SolveOut fgmres(llg_ctx& c) {
     }
     launch_solve_y(st, j, R, c.ks);
     launch_zy<T>(st, m, j, Z, c.ld, c.ks.y, c.u);
-    launch_resid_outer(st, L0.A, c.Aval, c.b, c.u, c.r, c.part);
+    outer_resid(c);
     launch_norm_finish_n(st, c.part, c.npart_rows, 0, c.ks.sc, H);
     LCHK();
     sync(c);
@@ -1169,11 +1224,19 @@ void llg_default_opts(llg_opts* o) {
   o->graphs = 1;
   o->smoother = LLG_SMOOTHER_JACOBI;
   o->scheme = LLG_SCHEME_BDF1;
+  o->fine_operator = LLG_FINE_BSR;
+}
+
+// combinations the library does not implement
+static bool supported(const llg_grid* grid, const llg_opts* opts) {
+  if (grid->bc != LLG_BC_NEUMANN) return false;
+  if (opts->fine_operator == LLG_FINE_FACTORED && !opts->left_scale) return false;
+  return true;
 }
 
 llg_status llg_workspace_bytes(const llg_grid* grid, const llg_opts* opts, size_t* bytes) {
   if (!grid_ok(grid) || !opts_ok(opts) || !bytes) return LLG_ERR_INVALID_ARG;
-  if (grid->bc != LLG_BC_NEUMANN) return LLG_ERR_UNSUPPORTED;
+  if (!supported(grid, opts)) return LLG_ERR_UNSUPPORTED;
   return guard([&]() -> llg_status {
     auto plan = get_plan(*grid, *opts);
     if (plan->status != LLG_OK) return (llg_status)plan->status;
@@ -1186,7 +1249,7 @@ llg_status llg_create(const llg_grid* grid, const llg_opts* opts, void* d_worksp
                       void* hip_stream, llg_ctx** out) {
   if (!grid_ok(grid) || !opts_ok(opts) || !out || !d_workspace) return LLG_ERR_INVALID_ARG;
   if (((uintptr_t)d_workspace & (ALIGN - 1)) != 0) return LLG_ERR_INVALID_ARG;
-  if (grid->bc != LLG_BC_NEUMANN) return LLG_ERR_UNSUPPORTED;
+  if (!supported(grid, opts)) return LLG_ERR_UNSUPPORTED;
   *out = nullptr;
   return guard([&]() -> llg_status {
     auto plan = get_plan(*grid, *opts);
@@ -1316,24 +1379,41 @@ llg_status llg_get_level(llg_ctx* ctx, int32_t level, int32_t* h_row_ptr, int32_
   return guard([&]() -> llg_status {
     const bool f32 = level >= 0 && ctx->opts.precision == LLG_PREC_FP32_AMG;
     const size_t ts = f32 ? 4 : 8;
-    const void* val = level < 0 ? (const void*)ctx->Aval : L.val;
+    const bool fact = level <= 0 && ctx->fact;
+    const void* val = fact ? (level < 0 ? (const void*)ctx->Mh : L.kf) : (level < 0 ? (const void*)ctx->Aval : L.val);
     std::vector<int32_t> sl(L.A.nslices + 1), col(L.A.nslots);
-    std::vector<char> v(ts * 9 * (size_t)L.A.nslots);
+    std::vector<char> v(ts * 9 * (size_t)(fact ? L.A.nslices * SL : L.A.nslots));
     HIPX(hipStreamSynchronize(ctx->st));
     HIPX(hipMemcpy(h_row_ptr, L.brp, sizeof(int32_t) * (L.A.n + 1), hipMemcpyDeviceToHost));
     HIPX(hipMemcpy(sl.data(), L.A.sl_ptr, sizeof(int32_t) * sl.size(), hipMemcpyDeviceToHost));
     HIPX(hipMemcpy(col.data(), L.A.col, sizeof(int32_t) * col.size(), hipMemcpyDeviceToHost));
     HIPX(hipMemcpy(v.data(), val, v.size(), hipMemcpyDeviceToHost));
+    auto rd = [&](int64_t vi) {
+      return f32 ? (double)((const float*)v.data())[vi] : ((const double*)v.data())[vi];
+    };
     for (int64_t i = 0; i < L.A.n; ++i) {
       const int64_t sidx = i / SL, lane = i % SL;
       const int64_t cb = sl[sidx];
       const int64_t len = h_row_ptr[i + 1] - h_row_ptr[i];
       for (int64_t t = 0; t < len; ++t) {
         const int64_t o = h_row_ptr[i] + t;
-        h_col[o] = col[cb + t * SL + lane];
+        const int32_t j = col[cb + t * SL + lane];
+        h_col[o] = j;
         for (int e = 0; e < 9; ++e) {
-          const int64_t vi = cb * 9 + (t * 9 + e) * SL + lane;
-          h_vals[9 * o + e] = f32 ? (double)((const float*)v.data())[vi] : ((const double*)v.data())[vi];
+          double x;
+          if (fact) {
+            // the blocks the factored products apply: off the diagonal the
+            // stored block, on it I (scaled level) or I - deg Mh (level -1)
+            const double id = (e == 0 || e == 4 || e == 8) ? 1.0 : 0.0;
+            const double blk = rd(sidx * 9 * SL + e * SL + lane);
+            if (j != (int32_t)i)
+              x = blk;
+            else
+              x = level < 0 ? id + (-(double)(len - 1)) * blk : id;
+          } else {
+            x = rd(cb * 9 + (t * 9 + e) * SL + lane);
+          }
+          h_vals[9 * o + e] = x;
         }
       }
     }
@@ -1389,7 +1469,7 @@ llg_status llg_apply_A(llg_ctx* ctx, const double* d_x, double* d_y) {
   if (s != LLG_OK) return s;
   if (!d_x || !d_y || !aligned8(d_x) || !aligned8(d_y) || !ctx->setup_done) return LLG_ERR_INVALID_ARG;
   return guard([&]() -> llg_status {
-    launch_spmv_outer<double>(ctx->st, ctx->lv[0].A, ctx->Aval, d_x, d_y);
+    outer_spmv<double>(*ctx, d_x, d_y);
     LCHK();
     sync(*ctx);
     return LLG_OK;

@@ -565,8 +565,9 @@ __global__ void k_colour_place(int64_t n, const int32_t* col, int32_t ncol, int6
 // diagonal block follows when dinv != NULL.
 template <typename T>
 __global__ void k_cls_gather(int64_t n, const int32_t* __restrict__ rows, const int32_t* __restrict__ sl,
-                             const T* __restrict__ val, const T* __restrict__ dinv,
-                             const int32_t* __restrict__ csl, T* __restrict__ cval, T* __restrict__ cdinv) {
+                             const int32_t* __restrict__ col, const T* __restrict__ val, const T* __restrict__ dinv,
+                             const int32_t* __restrict__ csl, T* __restrict__ cval, T* __restrict__ cdinv,
+                             const T* __restrict__ fk) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int64_t i = rows[k];
@@ -575,9 +576,17 @@ __global__ void k_cls_gather(int64_t n, const int32_t* __restrict__ rows, const 
   const int64_t src = 9 * (int64_t)sl[s], dst = 9 * (int64_t)csl[cs];
   const int w = (csl[cs + 1] - csl[cs]) / SL;
   const int wsrc = (sl[s + 1] - sl[s]) / SL;
-  for (int t = 0; t < w; ++t)
+  for (int t = 0; t < w; ++t) {
+    if (fk) {  // factored grid level: identity on the diagonal, fk_i elsewhere
+      const int32_t j = t < wsrc ? col[sl[s] + (int64_t)t * SL + l] : -1;
+      for (int e = 0; e < 9; ++e)
+        cval[dst + (int64_t)SL * (9 * t + e) + cl] =
+            j < 0 ? T(0) : (j == i ? T((e == 0 || e == 4 || e == 8) ? 1 : 0) : fk[s * 9 * SL + e * SL + l]);
+      continue;
+    }
     for (int e = 0; e < 9; ++e)
       cval[dst + (int64_t)SL * (9 * t + e) + cl] = t < wsrc ? val[src + (int64_t)SL * (9 * t + e) + l] : T(0);
+  }
   if (dinv)
     for (int e = 0; e < 9; ++e) cdinv[cs * 9 * SL + e * SL + cl] = dinv[s * 9 * SL + e * SL + l];
 }
@@ -593,7 +602,8 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
                            const int32_t* __restrict__ sl_ptr,
                            const int32_t* __restrict__ col, double* __restrict__ Aval,
                            T* __restrict__ Lval, double* __restrict__ dinv0, T* __restrict__ ldinv,
-                           double* __restrict__ b, double* __restrict__ u, int32_t* flag) {
+                           double* __restrict__ b, double* __restrict__ u, int32_t* flag,
+                           double* __restrict__ Mh, T* __restrict__ K) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t N = (int64_t)nx * ny * nz;
   if (p >= N) return;
@@ -634,7 +644,25 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
   const int64_t s = p / SL;
   const int l = (int)(p - s * SL);
   const int64_t cb = sl_ptr[s];
-  const int w = (int)((sl_ptr[s + 1] - cb) / SL);
+  const int w = Mh ? 0 : (int)((sl_ptr[s + 1] - cb) / SL);
+  if (Mh) {
+    // factored form: the off-diagonal block of the row and its scaled form,
+    // the same values the sliced-ELL slots would hold
+    double blk[9], sb[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) blk[e] = s_off * M[e];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        sb[3 * r + q] = (Di[3 * r] * blk[q] + Di[3 * r + 1] * blk[3 + q]) + Di[3 * r + 2] * blk[6 + q];
+    const int64_t fb = s * 9 * SL + l;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      Mh[fb + e * SL] = blk[e];
+      K[fb + e * SL] = (T)sb[e];
+    }
+  }
   for (int t = 0; t < w; ++t) {
     const int32_t c = col[cb + (int64_t)t * SL + l];
     if (c < 0) break;
@@ -695,7 +723,8 @@ __global__ void k_galerkin(int64_t nc, int64_t ns, const int32_t* __restrict__ c
                            const int32_t* __restrict__ ccol, T* __restrict__ cval, T* __restrict__ cdinv,
                            const int32_t* __restrict__ mptr, const int32_t* __restrict__ mem,
                            const int32_t* __restrict__ fsl, const int32_t* __restrict__ fcol,
-                           const T* __restrict__ fval, const int32_t* __restrict__ agg) {
+                           const T* __restrict__ fval, const int32_t* __restrict__ agg,
+                           const T* __restrict__ fk) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= csl[ns]) return;
   // slice of slot p: the last s with csl[s] <= p
@@ -725,6 +754,13 @@ __global__ void k_galerkin(int64_t nc, int64_t ns, const int32_t* __restrict__ c
       const int32_t j = fcol[fb + (int64_t)u * SL + fl];
       if (j < 0) break;
       if (agg[j] != J) continue;
+      if (fk) {
+        const int64_t kb = fs * 9 * SL + fl;
+#pragma unroll
+        for (int e = 0; e < 9; ++e)
+          acc[e] += j == i ? ((e == 0 || e == 4 || e == 8) ? 1.0 : 0.0) : (double)fk[kb + e * SL];
+        continue;
+      }
       const int64_t vb = fb * 9 + (int64_t)u * 9 * SL + fl;
 #pragma unroll
       for (int e = 0; e < 9; ++e) acc[e] += (double)fval[vb + e * SL];
@@ -996,17 +1032,18 @@ template <typename T>
 void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, const double* prm,
                      int left_scale, int x0_is_mn, const double* m, const double* mprev, const double* F,
                      Sell A, double* Aval, T* Lval, double* dinv0, T* ldinv, double* b, double* u,
-                     int32_t* flag) {
+                     int32_t* flag, double* Mh, T* K) {
   const int64_t N = (int64_t)nx * ny * nz;
   hipLaunchKernelGGL((k_assemble<T>), dim3(nblk(N)), dim3(TPB), 0, st, nx, ny, nz, inv_h2, prm,
-                     left_scale, x0_is_mn, m, mprev, F, A.sl_ptr, A.col, Aval, Lval, dinv0, ldinv, b, u, flag);
+                     left_scale, x0_is_mn, m, mprev, F, A.sl_ptr, A.col, Aval, Lval, dinv0, ldinv, b, u, flag, Mh,
+                     K);
 }
 template void launch_assemble<double>(hipStream_t, int, int, int, double, const double*, int, int,
                                       const double*, const double*, const double*, Sell, double*, double*,
-                                      double*, double*, double*, double*, int32_t*);
+                                      double*, double*, double*, double*, int32_t*, double*, double*);
 template void launch_assemble<float>(hipStream_t, int, int, int, double, const double*, int, int,
                                      const double*, const double*, const double*, Sell, double*, float*,
-                                     double*, float*, double*, double*, int32_t*);
+                                     double*, float*, double*, double*, int32_t*, double*, float*);
 
 void init_kernel_attributes() {
   const size_t lds_max = (size_t)(GJ_LDS_MAX * GJ_LDS_MAX + GJ_LDS_MAX + GJ_T) * sizeof(double) +
@@ -1018,15 +1055,15 @@ void init_kernel_attributes() {
 
 template <typename T>
 void launch_galerkin(hipStream_t st, Sell C, T* cval, T* cdinv, const int32_t* mptr,
-                     const int32_t* mem, Sell F, const T* fval, const int32_t* agg) {
+                     const int32_t* mem, Sell F, const T* fval, const int32_t* agg, const T* fk) {
   if (C.n <= 0) return;
   hipLaunchKernelGGL((k_galerkin<T>), dim3(nblk(C.nslots)), dim3(TPB), 0, st, C.n, C.nslices, C.sl_ptr,
-                     C.col, cval, cdinv, mptr, mem, F.sl_ptr, F.col, fval, agg);
+                     C.col, cval, cdinv, mptr, mem, F.sl_ptr, F.col, fval, agg, fk);
 }
 template void launch_galerkin<double>(hipStream_t, Sell, double*, double*, const int32_t*,
-                                      const int32_t*, Sell, const double*, const int32_t*);
+                                      const int32_t*, Sell, const double*, const int32_t*, const double*);
 template void launch_galerkin<float>(hipStream_t, Sell, float*, float*, const int32_t*,
-                                     const int32_t*, Sell, const float*, const int32_t*);
+                                     const int32_t*, Sell, const float*, const int32_t*, const float*);
 
 template <typename T>
 void launch_dense_scatter(hipStream_t st, Sell C, const T* cval, double* dense) {
@@ -1063,15 +1100,15 @@ void launch_colour_place(hipStream_t st, int64_t n, const int32_t* col, int32_t 
 }
 template <typename T>
 void launch_cls_gather(hipStream_t st, int64_t n, const int32_t* rows, Sell A, const T* val, const T* dinv,
-                       Sell C, T* cval, T* cdinv) {
+                       Sell C, T* cval, T* cdinv, const T* fk) {
   if (n > 0)
-    hipLaunchKernelGGL((k_cls_gather<T>), dim3(nblk(n)), dim3(TPB), 0, st, n, rows, A.sl_ptr, val, dinv, C.sl_ptr,
-                       cval, cdinv);
+    hipLaunchKernelGGL((k_cls_gather<T>), dim3(nblk(n)), dim3(TPB), 0, st, n, rows, A.sl_ptr, A.col, val, dinv,
+                       C.sl_ptr, cval, cdinv, fk);
 }
 template void launch_cls_gather<double>(hipStream_t, int64_t, const int32_t*, Sell, const double*, const double*,
-                                        Sell, double*, double*);
+                                        Sell, double*, double*, const double*);
 template void launch_cls_gather<float>(hipStream_t, int64_t, const int32_t*, Sell, const float*, const float*,
-                                       Sell, float*, float*);
+                                       Sell, float*, float*, const float*);
 
 void launch_gauss_jordan(hipStream_t st, int64_t nd, double* dense, int32_t* piv, int32_t* flag) {
   static int lds_ok = -1;

@@ -337,6 +337,215 @@ __global__ void k_resid_outer(int64_t n, const int32_t* __restrict__ sl, const i
   if (threadIdx.x == 0) part[blockIdx.x] = res[0];
 }
 
+// ------------------------------------------------------- factored fine level
+// On the grid level every off-diagonal block of row p is one 3x3 block:
+// A_pq = Mh_p = (dt/h^2) M_p for each in-grid neighbour q, A_pp = I + s_pp M_p
+// with s_pp = -deg_p dt/h^2 = -deg_p (dt/h^2); the left-scaled operator has
+// Atilde_pq = K_p = D_p^{-1} Mh_p and Atilde_pp = I.  One block per node in
+// the [slice][9][64] layout, neighbours from the grid:
+//   (A z)_p = z_p + Mh_p (sum_q z_q - deg_p z_p),   (Atilde x)_p = x_p + K_p sum_q x_q.
+struct GridPos {
+  int64_t p, s;
+  int l;
+};
+__device__ inline GridPos grid_pos() {  // launched with TPB threads per block
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  GridPos g;
+  g.p = (int64_t)blk * TPB + threadIdx.x;
+  g.s = g.p / SL;
+  g.l = (int)(g.p - g.s * SL);
+  return g;
+}
+
+// In-grid neighbours of p in ascending index order (k-1, j-1, i-1, i+1,
+// j+1, k+1): h[t] tells whether neighbour t exists, q[t] is its index or p
+// itself when it does not (so that every load can be issued without a branch).
+template <int DIM>
+struct Nbrs {
+  bool h[6];
+  int64_t q[6];
+};
+template <int DIM>
+__device__ inline Nbrs<DIM> nbrs(int nx, int ny, int nz, int64_t p) {
+  const uint32_t up = (uint32_t)p, unx = (uint32_t)nx, uny = (uint32_t)ny;
+  uint32_t i, j, k = 0;
+  if (DIM == 3) {
+    const uint32_t nxy = unx * uny;
+    k = up / nxy;
+    const uint32_t rem = up - k * nxy;
+    j = rem / unx;
+    i = rem - j * unx;
+  } else {
+    j = up / unx;
+    i = up - j * unx;
+  }
+  const int64_t sxy = (int64_t)nx * ny;
+  Nbrs<DIM> n;
+  n.h[0] = DIM == 3 && k > 0;
+  n.h[1] = j > 0;
+  n.h[2] = i > 0;
+  n.h[3] = i + 1 < unx;
+  n.h[4] = j + 1 < uny;
+  n.h[5] = DIM == 3 && k + 1 < (uint32_t)nz;
+  const int64_t off[6] = {-sxy, -(int64_t)nx, -1, 1, (int64_t)nx, sxy};
+#pragma unroll
+  for (int t = 0; t < 6; ++t) n.q[t] = n.h[t] ? p + off[t] : p;
+  return n;
+}
+__device__ constexpr bool nbr_used(int dim, int t) { return dim == 3 || (t != 0 && t != 5); }
+
+// Sum of f(q) over the in-grid neighbours (missing ones contribute zero);
+// deg receives their number.
+template <int DIM, typename T, typename XF>
+__device__ inline V3<T> nbr_sum(int nx, int ny, int nz, int64_t p, XF f, int& deg) {
+  const Nbrs<DIM> n = nbrs<DIM>(nx, ny, nz, p);
+  V3<T> v[6];
+#pragma unroll
+  for (int t = 0; t < 6; ++t)
+    if (nbr_used(DIM, t)) v[t] = f(n.q[t]);
+  V3<T> a{T(0), T(0), T(0)};
+  int d = 0;
+#pragma unroll
+  for (int t = 0; t < 6; ++t)
+    if (nbr_used(DIM, t)) {
+      a.x += n.h[t] ? v[t].x : T(0);
+      a.y += n.h[t] ? v[t].y : T(0);
+      a.z += n.h[t] ? v[t].z : T(0);
+      d += n.h[t] ? 1 : 0;
+    }
+  deg = d;
+  return a;
+}
+
+// the nine entries of a per-node block ([slice][9][64] layout)
+template <typename T>
+struct B9 {
+  T e[9];
+};
+template <typename T>
+__device__ inline B9<T> ld9(const T* __restrict__ d, int64_t db) {
+  B9<T> b;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) b.e[q] = d[db + q * SL];
+  return b;
+}
+template <typename T, typename TV>
+__device__ inline V3<TV> mv9(const B9<T>& b, V3<TV> v) {
+  return V3<TV>{(TV)b.e[0] * v.x + (TV)b.e[1] * v.y + (TV)b.e[2] * v.z,
+                (TV)b.e[3] * v.x + (TV)b.e[4] * v.y + (TV)b.e[5] * v.z,
+                (TV)b.e[6] * v.x + (TV)b.e[7] * v.y + (TV)b.e[8] * v.z};
+}
+
+template <int DIM, typename TZ>
+__global__ void k_fact_outer(int nx, int ny, int nz, const double* __restrict__ Mh, const TZ* __restrict__ z,
+                             double* __restrict__ w) {
+  const GridPos g = grid_pos();
+  const int64_t N = (int64_t)nx * ny * nz;
+  if (g.p >= N) return;
+  const B9<double> m = ld9(Mh, g.s * 9 * SL + g.l);
+  auto zd = [&](int64_t q) {
+    const V3<TZ> t = ld3(z, q);
+    return V3<double>{(double)t.x, (double)t.y, (double)t.z};
+  };
+  int deg;
+  const V3<double> sz = nbr_sum<DIM, double>(nx, ny, nz, g.p, zd, deg);
+  const V3<double> zp = zd(g.p);
+  const double dg = (double)deg;
+  const V3<double> md = mv9(m, V3<double>{sz.x - dg * zp.x, sz.y - dg * zp.y, sz.z - dg * zp.z});
+  st3(w, g.p, V3<double>{zp.x + md.x, zp.y + md.y, zp.z + md.z});
+}
+
+// r = b - A u with the partial sums of |r|^2 per workgroup
+template <int DIM>
+__global__ void k_fact_resid_outer(int nx, int ny, int nz, const double* __restrict__ Mh,
+                                   const double* __restrict__ b, const double* __restrict__ u,
+                                   double* __restrict__ r, double* __restrict__ part) {
+  __shared__ double sh[TPB / 64];
+  __shared__ double res[1];
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = (int64_t)nx * ny * nz;
+  double nrm = 0;
+  if (p < N) {
+    const int64_t s = p / SL;
+    const B9<double> m = ld9(Mh, s * 9 * SL + (p - s * SL));
+    int deg;
+    const V3<double> su = nbr_sum<DIM, double>(nx, ny, nz, p, [&](int64_t q) { return ld3(u, q); }, deg);
+    const V3<double> up = ld3(u, p);
+    const double dg = (double)deg;
+    const V3<double> md = mv9(m, V3<double>{su.x - dg * up.x, su.y - dg * up.y, su.z - dg * up.z});
+    const V3<double> bi = ld3(b, p);
+    const V3<double> ri{bi.x - (up.x + md.x), bi.y - (up.y + md.y), bi.z - (up.z + md.z)};
+    st3(r, p, ri);
+    nrm = (ri.x * ri.x + ri.y * ri.y) + ri.z * ri.z;
+  }
+  block_sums<1>(&nrm, sh, res);
+  if (threadIdx.x == 0) part[blockIdx.x] = res[0];
+}
+
+// r = b - Atilde x on the grid level
+template <int DIM, typename T, int XMODE>
+__global__ void k_fact_residual(int nx, int ny, int nz, const T* __restrict__ K, T omega, const T* __restrict__ b,
+                                const T* __restrict__ x, T* __restrict__ r) {
+  const GridPos g = grid_pos();
+  const int64_t N = (int64_t)nx * ny * nz;
+  if (g.p >= N) return;
+  const B9<T> kb = ld9(K, g.s * 9 * SL + g.l);
+  int deg;
+  const V3<T> sx =
+      nbr_sum<DIM, T>(nx, ny, nz, g.p, [&](int64_t q) { return xval<T, XMODE>(x, b, omega, q); }, deg);
+  const V3<T> kx = mv9(kb, sx);
+  const V3<T> xp = xval<T, XMODE>(x, b, omega, g.p);
+  const V3<T> bi = ld3(b, g.p);
+  st3(r, g.p, V3<T>{bi.x - (xp.x + kx.x), bi.y - (xp.y + kx.y), bi.z - (xp.z + kx.z)});
+}
+
+// out = x' + omega (b - Atilde x'), x'_q = xbase_q + ec[agg_q] (EC) or xbase_q.
+// The aggregate numbers of the row's nodes are loaded first, then all the
+// x and ec entries together.
+template <int DIM, typename T, int XMODE, bool EC>
+__global__ void k_fact_post_smooth(int nx, int ny, int nz, const T* __restrict__ K, T omega,
+                                   const T* __restrict__ b, const T* __restrict__ x,
+                                   const int32_t* __restrict__ agg, const T* __restrict__ ec, T* __restrict__ out) {
+  const GridPos g = grid_pos();
+  const int64_t N = (int64_t)nx * ny * nz;
+  if (g.p >= N) return;
+  const B9<T> kb = ld9(K, g.s * 9 * SL + g.l);
+  const Nbrs<DIM> n = nbrs<DIM>(nx, ny, nz, g.p);
+  int32_t a[7];
+  if (EC) {
+#pragma unroll
+    for (int t = 0; t < 6; ++t)
+      if (nbr_used(DIM, t)) a[t] = agg[n.q[t]];
+    a[6] = agg[g.p];
+  }
+  V3<T> v[7];
+#pragma unroll
+  for (int t = 0; t < 7; ++t) {
+    if (t < 6 && !nbr_used(DIM, t)) continue;
+    const int64_t q = t < 6 ? n.q[t] : g.p;
+    v[t] = xval<T, XMODE>(x, b, omega, q);
+    if (EC) {
+      const V3<T> e = ld3(ec, (int64_t)a[t]);
+      v[t].x += e.x;
+      v[t].y += e.y;
+      v[t].z += e.z;
+    }
+  }
+  V3<T> sx{T(0), T(0), T(0)};
+#pragma unroll
+  for (int t = 0; t < 6; ++t)
+    if (nbr_used(DIM, t)) {
+      sx.x += n.h[t] ? v[t].x : T(0);
+      sx.y += n.h[t] ? v[t].y : T(0);
+      sx.z += n.h[t] ? v[t].z : T(0);
+    }
+  const V3<T> kx = mv9(kb, sx);
+  const V3<T> xi = v[6];
+  const V3<T> bi = ld3(b, g.p);
+  const V3<T> res{bi.x - (xi.x + kx.x), bi.y - (xi.y + kx.y), bi.z - (xi.z + kx.z)};
+  st3(out, g.p, V3<T>{xi.x + omega * res.x, xi.y + omega * res.y, xi.z + omega * res.z});
+}
+
 // partial sums of x.x over a fixed grid of RED_BLOCKS-bounded blocks
 __global__ void k_norm_part(int64_t m, const double* __restrict__ x, double* __restrict__ part) {
   __shared__ double sh[TPB / 64];
@@ -840,6 +1049,85 @@ void launch_resid_outer(hipStream_t st, Sell A, const double* val, const double*
                         double* r, double* part) {
   hipLaunchKernelGGL(k_resid_outer, dim3(nblk(A.n)), dim3(TPB), 0, st, A.n, A.sl_ptr, A.col, val, b, u, r, part);
 }
+
+template <typename TZ>
+void launch_fact_outer(hipStream_t st, GridDims g, const double* Mh, const TZ* z, double* w) {
+  const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+  if (g.nz > 1)
+    hipLaunchKernelGGL((k_fact_outer<3, TZ>), dim3(nblk(N)), dim3(TPB), 0, st, g.nx, g.ny, g.nz, Mh, z, w);
+  else
+    hipLaunchKernelGGL((k_fact_outer<2, TZ>), dim3(nblk(N)), dim3(TPB), 0, st, g.nx, g.ny, g.nz, Mh, z, w);
+}
+template void launch_fact_outer<double>(hipStream_t, GridDims, const double*, const double*, double*);
+template void launch_fact_outer<float>(hipStream_t, GridDims, const double*, const float*, double*);
+
+void launch_fact_resid_outer(hipStream_t st, GridDims g, const double* Mh, const double* b, const double* u,
+                             double* r, double* part) {
+  const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+  if (g.nz > 1)
+    hipLaunchKernelGGL(k_fact_resid_outer<3>, dim3(nblk(N)), dim3(TPB), 0, st, g.nx, g.ny, g.nz, Mh, b, u, r, part);
+  else
+    hipLaunchKernelGGL(k_fact_resid_outer<2>, dim3(nblk(N)), dim3(TPB), 0, st, g.nx, g.ny, g.nz, Mh, b, u, r, part);
+}
+
+template <typename T>
+void launch_fact_residual(hipStream_t st, GridDims g, const T* K, int xmode, double omega, const T* b, const T* x,
+                          T* r) {
+  const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+  const dim3 gr(nblk(N)), t(TPB);
+#define LLG_FR(D, XM) \
+  hipLaunchKernelGGL((k_fact_residual<D, T, XM>), gr, t, 0, st, g.nx, g.ny, g.nz, K, (T)omega, b, x, r)
+#define LLG_FRD(D)        \
+  if (xmode == 0)         \
+    LLG_FR(D, 0);         \
+  else if (xmode == 1)    \
+    LLG_FR(D, 1);         \
+  else                    \
+    LLG_FR(D, 2);
+  if (g.nz > 1) {
+    LLG_FRD(3)
+  } else {
+    LLG_FRD(2)
+  }
+#undef LLG_FRD
+#undef LLG_FR
+}
+
+template <typename T>
+void launch_fact_post_smooth(hipStream_t st, GridDims g, const T* K, int xmode, double omega, const T* b,
+                             const T* x, const int32_t* agg, const T* ec, T* out) {
+  const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+  const dim3 gr(nblk(N)), t(TPB);
+#define LLG_FP(D, XM)                                                                                       \
+  if (ec)                                                                                                     \
+    hipLaunchKernelGGL((k_fact_post_smooth<D, T, XM, true>), gr, t, 0, st, g.nx, g.ny, g.nz, K, (T)omega, b, x, \
+                       agg, ec, out);                                                                         \
+  else                                                                                                        \
+    hipLaunchKernelGGL((k_fact_post_smooth<D, T, XM, false>), gr, t, 0, st, g.nx, g.ny, g.nz, K, (T)omega, b,   \
+                       x, agg, ec, out)
+#define LLG_FPD(D)        \
+  if (xmode == 0)         \
+    LLG_FP(D, 0);         \
+  else if (xmode == 1)    \
+    LLG_FP(D, 1);         \
+  else                    \
+    LLG_FP(D, 2);
+  if (g.nz > 1) {
+    LLG_FPD(3)
+  } else {
+    LLG_FPD(2)
+  }
+#undef LLG_FPD
+#undef LLG_FP
+}
+template void launch_fact_residual<double>(hipStream_t, GridDims, const double*, int, double, const double*,
+                                           const double*, double*);
+template void launch_fact_residual<float>(hipStream_t, GridDims, const float*, int, double, const float*,
+                                          const float*, float*);
+template void launch_fact_post_smooth<double>(hipStream_t, GridDims, const double*, int, double, const double*,
+                                              const double*, const int32_t*, const double*, double*);
+template void launch_fact_post_smooth<float>(hipStream_t, GridDims, const float*, int, double, const float*,
+                                             const float*, const int32_t*, const float*, float*);
 
 int64_t red_blocks(int64_t m) { return std::max<int64_t>(1, std::min<int64_t>(RED_BLOCKS, ceil_div(m, TPB * 4))); }
 

@@ -72,9 +72,10 @@ void launch_colour_hist(hipStream_t st, int64_t n, const int32_t* col, int32_t n
 void launch_colour_place(hipStream_t st, int64_t n, const int32_t* col, int32_t ncol, const int32_t* hist,
                          int32_t* perm);
 // values (and inverse diagonal blocks when dinv != NULL) of the class rows[0..n)
+// (fk != NULL: the level is the factored grid level, as in launch_galerkin)
 template <typename T>
 void launch_cls_gather(hipStream_t st, int64_t n, const int32_t* rows, Sell A, const T* val, const T* dinv,
-                       Sell C, T* cval, T* cdinv);
+                       Sell C, T* cval, T* cdinv, const T* fk);
 
 // pairwise matching (one pass)
 void launch_row_max(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gw, int32_t* mx);
@@ -105,16 +106,20 @@ void launch_member_sort(hipStream_t st, int64_t nc, const int32_t* mptr, int32_t
 // (mprev == NULL) or 2 m - mprev (BDF2, b = (4 m - mprev) / 3 + dt F).
 // prm[0] = alpha, prm[1] = the time-step factor (device memory, so captured
 // graphs stay valid)
+// Factored form (Mh != NULL): the per-node blocks Mh and K are written
+// instead of the sliced-ELL values Aval and Lval.
 template <typename T>
 void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, const double* prm,
                      int left_scale, int x0_is_mn, const double* m, const double* mprev, const double* F,
                      Sell A, double* Aval, T* Lval, double* dinv0, T* ldinv, double* b, double* u,
-                     int32_t* flag);
+                     int32_t* flag, double* Mh, T* K);
 
 // Galerkin block sums P^T A P and the inverse diagonal blocks of the result
+// fk != NULL: the fine level is the factored grid level, whose block in slot
+// (i, j) is the identity when j == i and fk_i otherwise (fval unused)
 template <typename T>
 void launch_galerkin(hipStream_t st, Sell C, T* cval, T* cdinv, const int32_t* mptr,
-                     const int32_t* mem, Sell F, const T* fval, const int32_t* agg);
+                     const int32_t* mem, Sell F, const T* fval, const int32_t* agg, const T* fk);
 
 // one-time kernel attribute setup (large dynamic LDS for the coarsest inverse)
 void init_kernel_attributes();
@@ -173,6 +178,23 @@ void launch_kc_update(hipStream_t st, int64_t n, const T* r, const T* w1, const 
 template <typename T>
 void launch_kc_combine(hipStream_t st, int64_t n, const T* v1, const T* v2, const double* kc, T* e);
 void launch_kc_coef(hipStream_t st, const double* part, int64_t G, int stage, double* kc);
+
+// Factored grid level (one 3x3 block per node, [slice][9][64]): Mh_p is
+// every off-diagonal block of row p of A (A_pp = I - deg_p Mh_p), K_p every
+// off-diagonal block of the left-scaled operator (unit diagonal).
+struct GridDims {
+  int nx, ny, nz;
+};
+template <typename TZ>
+void launch_fact_outer(hipStream_t st, GridDims g, const double* Mh, const TZ* z, double* w);
+void launch_fact_resid_outer(hipStream_t st, GridDims g, const double* Mh, const double* b, const double* u,
+                             double* r, double* part);
+template <typename T>
+void launch_fact_residual(hipStream_t st, GridDims g, const T* K, int xmode, double omega, const T* b, const T* x,
+                          T* r);
+template <typename T>
+void launch_fact_post_smooth(hipStream_t st, GridDims g, const T* K, int xmode, double omega, const T* b,
+                             const T* x, const int32_t* agg, const T* ec, T* out);
 
 // outer Krylov kernels (FP64)
 template <typename TZ>
