@@ -94,6 +94,17 @@ typedef enum { LLG_SCHEME_BDF1 = 0, LLG_SCHEME_BDF2 = 1 } llg_scheme;
  * coarsest is stored as BSR. */
 typedef enum { LLG_FINE_BSR = 0, LLG_FINE_FACTORED = 1 } llg_fine_operator;
 
+/* Orthogonalization of the FGMRES basis (all FP64).
+ * CGS2: classical Gram-Schmidt, a second pass when the first removes more
+ * than half of |w|^2 (three sweeps over the basis per iteration).
+ * DCGS2 (default): classical Gram-Schmidt with the second pass of each basis
+ * vector delayed to the next iteration (Swirydowicz, Langou, Ananthan, Yang,
+ * Thomas 2021): two sweeps per iteration; the Hessenberg column of an
+ * iteration is made final one iteration later, the residual estimate of the
+ * newest column uses its first-pass entries, and the last column of a cycle
+ * is made final before the least-squares solve. */
+typedef enum { LLG_ARNOLDI_CGS2 = 0, LLG_ARNOLDI_DCGS2 = 1 } llg_arnoldi;
+
 typedef struct {
   int32_t dim;   /* 2 or 3 */
   int32_t n[3];  /* points per axis, each >= 2; n[2] == 1 when dim == 2 */
@@ -127,6 +138,7 @@ typedef struct {
                            block Gauss-Seidel (Sec. 3 smooths by Gauss-Seidel) */
   int32_t scheme;       /* llg_scheme: BDF1 (default) or BDF2, see llg_step */
   int32_t fine_operator; /* llg_fine_operator: storage of the grid level, see below */
+  int32_t arnoldi;      /* llg_arnoldi: orthogonalization of the FGMRES basis, see below */
 } llg_opts;
 
 typedef struct {

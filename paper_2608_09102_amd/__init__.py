@@ -31,6 +31,7 @@ PREC_FP64, PREC_FP32_AMG = 0, 1
 SMOOTHER_JACOBI, SMOOTHER_MCGS = 0, 1
 SCHEME_BDF1, SCHEME_BDF2 = 0, 1
 FINE_BSR, FINE_FACTORED = 0, 1
+ARNOLDI_CGS2, ARNOLDI_DCGS2 = 0, 1
 KT_NONE, KT_OUTER_SPMV, KT_SMOOTH, KT_RESIDUAL, KT_ARNOLDI, KT_GALERKIN, KT_ASSEMBLE = range(7)
 KERNEL_CLASSES = {"none": 0, "outer_spmv": 1, "smooth": 2, "residual": 3, "arnoldi": 4, "galerkin": 5,
                   "assemble": 6}
@@ -51,7 +52,7 @@ class Opts(ctypes.Structure):
         ("project", ctypes.c_int32), ("x0_is_mn", ctypes.c_int32), ("agg_salt", ctypes.c_uint64),
         ("rebuild_aggregates", ctypes.c_int32), ("kcycle_depth", ctypes.c_int32),
         ("graphs", ctypes.c_int32), ("smoother", ctypes.c_int32), ("scheme", ctypes.c_int32),
-        ("fine_operator", ctypes.c_int32),
+        ("fine_operator", ctypes.c_int32), ("arnoldi", ctypes.c_int32),
     ]
 
 
@@ -154,6 +155,8 @@ def default_opts(**kw) -> Opts:
             v = {"bdf1": SCHEME_BDF1, "bdf2": SCHEME_BDF2}[v]
         if k == "fine_operator" and isinstance(v, str):
             v = {"bsr": FINE_BSR, "factored": FINE_FACTORED}[v]
+        if k == "arnoldi" and isinstance(v, str):
+            v = {"cgs2": ARNOLDI_CGS2, "dcgs2": ARNOLDI_DCGS2}[v]
         setattr(o, k, v)
     return o
 

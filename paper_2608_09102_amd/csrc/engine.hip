@@ -579,7 +579,8 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   c.npart_rows = ceil_div(c.N, 256);
   int64_t kparts = 0;
   for (int l = 1; l < c.L; ++l) kparts = std::max<int64_t>(kparts, 3 * rows_blocks(c.lv[l].A.n, c.lv[l].G));
-  c.part = ar.lazy<double>(std::max<int64_t>(std::max<int64_t>((R + 2) * c.npart_vec, c.npart_rows), kparts) + 64);
+  // partial sums: up to 2R+3 columns of the delayed Gram-Schmidt dots (R+2 for the two-pass form)
+  c.part = ar.lazy<double>(std::max<int64_t>(std::max<int64_t>((2 * R + 4) * c.npart_vec, c.npart_rows), kparts) + 64);
   c.ks.H = ar.lazy<double>((R + 1) * R);
   c.ks.cs = ar.lazy<double>(R);
   c.ks.sn = ar.lazy<double>(R);
@@ -587,6 +588,9 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   c.ks.hcol = ar.lazy<double>(R + 2);
   c.ks.y = ar.lazy<double>(R);
   c.ks.sc = ar.lazy<double>(16);
+  c.ks.hs = ar.lazy<double>(R + 2);
+  c.ks.hinv = ar.lazy<double>(R + 2);
+  c.ks.coef = ar.lazy<double>(2 * R + 4);
   c.delta = ar.lazy<double>(R + 2);
   c.prm = ar.lazy<double>(4);
   c.min = ar.lazy<double>(m);
@@ -615,7 +619,8 @@ bool opts_ok(const llg_opts* o) {
          std::isfinite(o->stagnation) && o->kcycle_depth >= 0 && o->kcycle_depth <= 8 &&
          (o->smoother == LLG_SMOOTHER_JACOBI || o->smoother == LLG_SMOOTHER_MCGS) &&
          (o->scheme == LLG_SCHEME_BDF1 || o->scheme == LLG_SCHEME_BDF2) &&
-         (o->fine_operator == LLG_FINE_BSR || o->fine_operator == LLG_FINE_FACTORED);
+         (o->fine_operator == LLG_FINE_BSR || o->fine_operator == LLG_FINE_FACTORED) &&
+         (o->arnoldi == LLG_ARNOLDI_CGS2 || o->arnoldi == LLG_ARNOLDI_DCGS2);
 }
 
 // Plan for (grid, opts): cached; computed on the current device.
@@ -992,9 +997,9 @@ void kcorrection(llg_ctx& c, int lc) {
 }
 
 template <typename T>
-void precond(llg_ctx& c, const double* v, T* z) {
+void precond(llg_ctx& c, const double* v, T* z, const double* vscale = nullptr) {
   Level& L0 = c.lv[0];
-  launch_scale_in<T>(c.st, c.N, c.dinv0, c.opts.left_scale, v, (T*)L0.b);
+  launch_scale_in<T>(c.st, c.N, c.dinv0, c.opts.left_scale, v, vscale, (T*)L0.b);
   LCHK();
   vcycle<T>(c, 0, (const T*)L0.b, z);
 }
@@ -1013,7 +1018,8 @@ struct SolveOut {
 // the outer SpMV is a single launch, timed with events on the stream.
 template <typename T>
 void iter_precond(llg_ctx& c, int j) {
-  precond<T>(c, c.V + (int64_t)j * c.ld, (T*)c.Z + (int64_t)j * c.ld);
+  const bool dcgs = c.opts.arnoldi == LLG_ARNOLDI_DCGS2;
+  precond<T>(c, c.V + (int64_t)j * c.ld, (T*)c.Z + (int64_t)j * c.ld, dcgs ? c.ks.hinv + j : nullptr);
 }
 
 template <typename T>
@@ -1028,6 +1034,16 @@ void iter_arnoldi(llg_ctx& c, int j) {
   const int R = c.opts.restart;
   const int64_t m = 3 * c.N;
   KTimer kt(c, LLG_KT_ARNOLDI);
+  if (c.opts.arnoldi == LLG_ARNOLDI_DCGS2) {
+    // delayed reorthogonalization: one sweep for the dots, one for v_j and w'
+    double* u = c.V + (int64_t)j * c.ld;
+    launch_dcgs_dots(st, m, j, c.V, c.ld, u, c.w, c.part);
+    launch_dcgs_finish1(st, c.part, c.npart_vec, j, R, c.ks, c.host);
+    launch_dcgs_update(st, m, j, c.V, c.ld, c.ks.coef, u, c.w, c.V + (int64_t)(j + 1) * c.ld, c.part);
+    launch_dcgs_finish2(st, c.part, c.npart_vec, j, R, c.ks, c.host);
+    LCHK();
+    return;
+  }
   // classical Gram-Schmidt; the second pass only when the first lost more
   // than half of ||w||^2
   launch_mdot(st, m, j + 1, c.V, c.ld, c.w, c.part);
@@ -1099,6 +1115,13 @@ SolveOut fgmres(llg_ctx& c) {
         ++j;
         break;
       }
+    }
+    if (c.opts.arnoldi == LLG_ARNOLDI_DCGS2) {
+      // the last column is final once slot j is orthogonalized against v_0..v_{j-1}
+      double* u = c.V + (int64_t)j * c.ld;
+      launch_dcgs_dots(st, m, j, c.V, c.ld, u, u, c.part);
+      launch_dcgs_last(st, c.part, c.npart_vec, j, R, c.ks, H);
+      LCHK();
     }
     launch_solve_y(st, j, R, c.ks);
     launch_zy<T>(st, m, j, Z, c.ld, c.ks.y, c.u);
@@ -1225,6 +1248,7 @@ void llg_default_opts(llg_opts* o) {
   o->smoother = LLG_SMOOTHER_JACOBI;
   o->scheme = LLG_SCHEME_BDF1;
   o->fine_operator = LLG_FINE_BSR;
+  o->arnoldi = LLG_ARNOLDI_DCGS2;
 }
 
 // combinations the library does not implement

@@ -268,10 +268,14 @@ __global__ void k_prolong(int64_t n, T omega, const T* __restrict__ b, const T* 
 
 template <typename T>
 __global__ void k_scale_in(int64_t n, const double* __restrict__ dinv0, int left_scale,
-                           const double* __restrict__ v, T* __restrict__ b0) {
+                           const double* __restrict__ v, const double* __restrict__ vs, T* __restrict__ b0) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   V3<double> x = ld3(v, i);
+  if (vs) {
+    const double f = vs[0];
+    x = V3<double>{x.x * f, x.y * f, x.z * f};
+  }
   if (left_scale) {
     const int64_t s = i / SL;
     x = dmv(dinv0, s * 9 * SL + (i - s * SL), x);
@@ -615,6 +619,75 @@ __global__ void __launch_bounds__(TPB) k_mupdate_dot(int64_t m, const double* __
     part[(int64_t)threadIdx.x * G + blockIdx.x] = res[threadIdx.x];
 }
 
+// Delayed reorthogonalization (classical Gram-Schmidt with the second pass of
+// v_j lagged into the next iteration, after Swirydowicz, Langou, Ananthan,
+// Yang and Thomas 2021).  Slot j of V holds u = h_j v~_j: the once
+// orthogonalized vector times its norm h_j.  One sweep gives all the dots of
+// the iteration, a second sweep finishes v_j and forms the next w'.
+// part[q] = V_q . u and part[NV + q] = V_q . w (q < NV), part[2NV] = u.u,
+// part[2NV + 1] = u.w, part[2NV + 2] = w.w, one column per workgroup.
+template <int NV>
+__global__ void __launch_bounds__(TPB) k_dcgs_dots(int64_t m, const double* __restrict__ V, int64_t ldv,
+                                                   const double* __restrict__ u, const double* __restrict__ w,
+                                                   double* __restrict__ part) {
+  constexpr int NS = 2 * NV + 3;
+  __shared__ double sh[(TPB / 64) * NS];
+  __shared__ double res[NS];
+  const int G = gridDim.x;
+  double acc[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) acc[q] = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)G * blockDim.x) {
+    const double uk = u[k], wk = w[k];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const double v = V[q * ldv + k];
+      acc[q] += v * uk;
+      acc[NV + q] += v * wk;
+    }
+    acc[2 * NV] += uk * uk;
+    acc[2 * NV + 1] += uk * wk;
+    acc[2 * NV + 2] += wk * wk;
+  }
+  block_sums<NS>(acc, sh, res);
+  if (threadIdx.x < NS) part[(int64_t)threadIdx.x * G + blockIdx.x] = res[threadIdx.x];
+}
+
+// v_j = du u - sum_q d_q V_q (over u, in place) and w' = w - sum_q c_q V_q - cu u
+// (into wo), with part[blk] = w'.w'.  coef = d_0..d_{NV-1}, c_0..c_{NV-1}, du, cu.
+template <int NV>
+__global__ void __launch_bounds__(TPB) k_dcgs_update(int64_t m, const double* __restrict__ V, int64_t ldv,
+                                                     const double* __restrict__ coef, double* __restrict__ u,
+                                                     const double* __restrict__ w, double* __restrict__ wo,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[TPB / 64];
+  __shared__ double res[1];
+  double d[NV > 0 ? NV : 1], cc[NV > 0 ? NV : 1];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    d[q] = coef[q];
+    cc[q] = coef[NV + q];
+  }
+  const double du = coef[2 * NV], cu = coef[2 * NV + 1];
+  const int G = gridDim.x;
+  double acc = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)G * blockDim.x) {
+    const double uk = u[k], wk = w[k];
+    double vj = du * uk, wp = wk - cu * uk;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const double v = V[q * ldv + k];
+      vj -= d[q] * v;
+      wp -= cc[q] * v;
+    }
+    u[k] = vj;
+    wo[k] = wp;
+    acc += wp * wp;
+  }
+  block_sums<1>(&acc, sh, res);
+  if (threadIdx.x == 0) part[blockIdx.x] = res[0];
+}
+
 template <typename TS, typename TD>
 __global__ void k_cast(int64_t m, const TS* __restrict__ x, TD* __restrict__ y) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -873,12 +946,157 @@ __global__ void k_arnoldi_finish(const double* part, int64_t nparts, int j, int 
   for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) ks.H[i * R + j] = col[i];
 }
 
+// Final column `col` (unrotated, rows 0..jj+1) of the Hessenberg matrix:
+// the previous rotations, a new one, the rotated column into H and the
+// right-hand side g updated.  Returns the residual estimate |g_{jj+1}|.
+// One thread.
+__device__ inline double givens_column(double* col, int jj, int R, KrylovScalars ks) {
+  for (int i = 0; i < jj; ++i) {
+    const double a = col[i], c = col[i + 1];
+    col[i] = ks.cs[i] * a + ks.sn[i] * c;
+    col[i + 1] = -ks.sn[i] * a + ks.cs[i] * c;
+  }
+  const double a = col[jj], c = col[jj + 1];
+  const double rho = hypot(a, c);
+  const double cj = a / rho, sj = c / rho;
+  ks.cs[jj] = cj;
+  ks.sn[jj] = sj;
+  col[jj] = rho;
+  col[jj + 1] = 0.0;
+  const double gj = ks.g[jj];
+  ks.g[jj + 1] = -sj * gj;
+  ks.g[jj] = cj * gj;
+  for (int i = 0; i <= jj + 1; ++i) ks.H[i * R + jj] = col[i];
+  return fabs(sj * gj);
+}
+
+// After the dots sweep of iteration j: s = V^T v~_j, nu = |v~_j - V s| (by
+// Pythagoras), the coefficients of w against the final v_0..v_j, the final
+// column j-1 (its last entries change with v~_j = V s + nu v_j), and the
+// coefficients of the update sweep.
+__global__ void k_dcgs_finish1(const double* part, int64_t nparts, int j, int R, KrylovScalars ks, double* host) {
+  __shared__ double a[MAXV_S + 1], b[MAXV_S + 1], e3[3], col[MAXV_S + 2];
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int ns = 2 * j + 3;
+  for (int q = wv; q < ns; q += nw) {
+    const double v = wave_sum(part + (int64_t)q * nparts, nparts);
+    if ((threadIdx.x & 63) == 0) {
+      if (q < j)
+        a[q] = v;
+      else if (q < 2 * j)
+        b[q - j] = v;
+      else
+        e3[q - 2 * j] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double h = ks.hs[j];
+  double nu = 1.0, ss = 0.0;
+  if (j > 0) {
+    for (int q = 0; q < j; ++q) {
+      a[q] /= h;  // s_q
+      ss += a[q] * a[q];
+    }
+    const double nu2 = e3[0] / (h * h) - ss;
+    nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+  }
+  double st = 0.0;
+  for (int q = 0; q < j; ++q) st += a[q] * b[q];
+  const double hjj = nu > 0.0 ? (e3[1] / h - st) / nu : 0.0;
+  if (j > 0) {  // column j-1 is final now
+    for (int q = 0; q < j; ++q) col[q] = ks.hcol[q] + h * a[q];
+    col[j] = h * nu;
+    ks.sc[3] = givens_column(col, j - 1, R, ks);
+    host[7] += 1.0;  // delayed second passes in this solve
+  }
+  for (int q = 0; q < j; ++q) ks.hcol[q] = b[q];
+  ks.hcol[j] = hjj;
+  // update sweep: v_j = u / (h nu) - V s / nu, w' = w - V (t - s hjj / nu) - u hjj / (h nu)
+  const double inv = nu > 0.0 ? 1.0 / nu : 0.0;
+  for (int q = 0; q < j; ++q) {
+    ks.coef[q] = a[q] * inv;
+    ks.coef[j + q] = b[q] - a[q] * hjj * inv;
+  }
+  ks.coef[2 * j] = inv / h;
+  ks.coef[2 * j + 1] = hjj * inv / h;
+  ks.sc[5] = e3[2];  // ||w||^2
+  ks.sc[8] = nu > 0.0 ? 0.0 : 1.0;
+}
+
+// After the update sweep: h_{j+1} = |w'|, the provisional column j (its
+// first-pass entries) rotated by the final rotations for the residual
+// estimate, and the breakdown test.
+__global__ void k_dcgs_finish2(const double* part, int64_t nparts, int j, int R, KrylovScalars ks, double* host) {
+  const double s = wave_sum(part, nparts);
+  if (threadIdx.x != 0) return;
+  const double hn = sqrt(s);
+  ks.hs[j + 1] = hn;
+  ks.hinv[j + 1] = 1.0 / hn;  // slot j+1 times this is the next preconditioner input
+  ks.sc[4] = hn;
+  double col[MAXV_S + 2];
+  for (int i = 0; i <= j; ++i) col[i] = ks.hcol[i];
+  col[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double a = col[i], c = col[i + 1];
+    col[i] = ks.cs[i] * a + ks.sn[i] * c;
+    col[i + 1] = -ks.sn[i] * a + ks.cs[i] * c;
+  }
+  const double rho = hypot(col[j], col[j + 1]);
+  const double est = fabs(col[j + 1] / rho * ks.g[j]);
+  const int breakdown = (hn <= 1e-14 * sqrt(ks.sc[5]) || ks.sc[8] != 0.0) ? 1 : 0;
+  ks.sc[9] = (double)breakdown;
+  host[3] = est;
+  host[6] = (double)breakdown;
+}
+
+// End of a cycle after k iterations: the last column (k-1) made final with
+// the dots of slot k against v_0..v_{k-1} (part from k_dcgs_dots<k> with
+// u = w = slot k); without correction after a breakdown.
+__global__ void k_dcgs_last(const double* part, int64_t nparts, int k, int R, KrylovScalars ks, double* host) {
+  __shared__ double a[MAXV_S + 1], uu[1], col[MAXV_S + 2];
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int q = wv; q <= k; q += nw) {
+    const int idx = q < k ? q : 2 * k;
+    const double v = wave_sum(part + (int64_t)idx * nparts, nparts);
+    if ((threadIdx.x & 63) == 0) {
+      if (q < k)
+        a[q] = v;
+      else
+        uu[0] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double h = ks.hs[k];
+  const int j = k - 1;
+  if (ks.sc[9] != 0.0 || !(h > 0.0)) {
+    for (int q = 0; q <= j; ++q) col[q] = ks.hcol[q];
+    col[j + 1] = h;
+  } else {
+    double ss = 0.0;
+    for (int q = 0; q < k; ++q) {
+      a[q] /= h;
+      ss += a[q] * a[q];
+    }
+    const double nu2 = uu[0] / (h * h) - ss;
+    for (int q = 0; q <= j; ++q) col[q] = ks.hcol[q] + h * a[q];
+    col[j + 1] = h * (nu2 > 0.0 ? sqrt(nu2) : 0.0);
+    host[7] += 1.0;
+  }
+  ks.sc[3] = givens_column(col, j, R, ks);
+  host[3] = ks.sc[3];
+}
+
 __global__ void k_cycle_start(int R, KrylovScalars ks) {
   for (int i = threadIdx.x; i <= R; i += blockDim.x) ks.g[i] = 0.0;
   __syncthreads();
   if (threadIdx.x == 0) {
     ks.g[0] = ks.sc[0];
     ks.sc[1] = 1.0 / ks.sc[0];
+    ks.hs[0] = 1.0;  // v_0 = r / beta is final
+    ks.hinv[0] = 1.0;
+    ks.sc[9] = 0.0;
   }
 }
 
@@ -1015,8 +1233,10 @@ void launch_fill(hipStream_t st, T* p, int64_t n) {
 }
 
 template <typename T>
-void launch_scale_in(hipStream_t st, int64_t n, const double* dinv0, int left_scale, const double* v, T* b0) {
-  if (n > 0) hipLaunchKernelGGL((k_scale_in<T>), dim3(nblk(n)), dim3(TPB), 0, st, n, dinv0, left_scale, v, b0);
+void launch_scale_in(hipStream_t st, int64_t n, const double* dinv0, int left_scale, const double* v,
+                     const double* vs, T* b0) {
+  if (n > 0)
+    hipLaunchKernelGGL((k_scale_in<T>), dim3(nblk(n)), dim3(TPB), 0, st, n, dinv0, left_scale, v, vs, b0);
 }
 
 #define LLG_INST(T)                                                                                         \
@@ -1028,7 +1248,8 @@ void launch_scale_in(hipStream_t st, int64_t n, const double* dinv0, int left_sc
                                       const T*, const int32_t*, const T*, T*, int);                         \
   template void launch_prolong<T>(hipStream_t, int64_t, int, double, const T*, const T*, const int32_t*,   \
                                   const T*, T*);                                                            \
-  template void launch_scale_in<T>(hipStream_t, int64_t, const double*, int, const double*, T*);           \
+  template void launch_scale_in<T>(hipStream_t, int64_t, const double*, int, const double*, const double*, \
+                                   T*);                                                                     \
   template void launch_gs_sweep<T>(hipStream_t, Sell, const int32_t*, const T*, const T*, int, int, const T*, \
                                    T*, int);                                                                \
   template void launch_fill<T>(hipStream_t, T*, int64_t);
@@ -1161,6 +1382,45 @@ void launch_mupdate_dot(hipStream_t st, int64_t m, int nv, const double* V, int6
 #undef X
     default: break;
   }
+}
+
+#define LLG_NV0_CASES(X) X(0) LLG_NV_CASES(X)
+
+void launch_dcgs_dots(hipStream_t st, int64_t m, int nv, const double* V, int64_t ldv, const double* u,
+                      const double* w, double* part) {
+  const dim3 g((unsigned)red_blocks(m)), t(TPB);
+  switch (nv) {
+#define X(K) \
+  case K: hipLaunchKernelGGL((k_dcgs_dots<K>), g, t, 0, st, m, V, ldv, u, w, part); break;
+    LLG_NV0_CASES(X)
+#undef X
+    default: break;
+  }
+}
+
+void launch_dcgs_update(hipStream_t st, int64_t m, int nv, const double* V, int64_t ldv, const double* coef,
+                        double* u, const double* w, double* wo, double* part) {
+  const dim3 g((unsigned)red_blocks(m)), t(TPB);
+  switch (nv) {
+#define X(K) \
+  case K: hipLaunchKernelGGL((k_dcgs_update<K>), g, t, 0, st, m, V, ldv, coef, u, w, wo, part); break;
+    LLG_NV0_CASES(X)
+#undef X
+    default: break;
+  }
+}
+
+void launch_dcgs_finish1(hipStream_t st, const double* part, int64_t nparts, int j, int R, KrylovScalars ks,
+                         double* host) {
+  hipLaunchKernelGGL(k_dcgs_finish1, dim3(1), dim3(1024), 0, st, part, nparts, j, R, ks, host);
+}
+void launch_dcgs_finish2(hipStream_t st, const double* part, int64_t nparts, int j, int R, KrylovScalars ks,
+                         double* host) {
+  hipLaunchKernelGGL(k_dcgs_finish2, dim3(1), dim3(64), 0, st, part, nparts, j, R, ks, host);
+}
+void launch_dcgs_last(hipStream_t st, const double* part, int64_t nparts, int k, int R, KrylovScalars ks,
+                      double* host) {
+  hipLaunchKernelGGL(k_dcgs_last, dim3(1), dim3(1024), 0, st, part, nparts, k, R, ks, host);
 }
 
 void launch_scale_vec(hipStream_t st, int64_t m, const double* x, const double* s, double* y) {

@@ -161,10 +161,10 @@ void launch_fill(hipStream_t st, T* p, int64_t n);
 template <typename T>
 void launch_prolong(hipStream_t st, int64_t n, int xmode, double omega, const T* b, const T* x,
                     const int32_t* agg, const T* ec, T* out);
-// b0 = D0^{-1} v (or v), cast to T
+// b0 = D0^{-1} (v vs[0]) (or v vs[0]; vs NULL: 1), cast to T
 template <typename T>
 void launch_scale_in(hipStream_t st, int64_t n, const double* dinv0, int left_scale, const double* v,
-                     T* b0);
+                     const double* vs, T* b0);
 
 // K-cycle coarse correction (two minimal-residual steps); partial sums over
 // rows_blocks(n) blocks, coefficients in kc (see k_solve.hip)
@@ -224,7 +224,11 @@ struct KrylovScalars {
   double* g;      // R+1
   double* hcol;   // R+1 (dots of the current pass)
   double* y;      // R
-  double* sc;     // scalars: [0] beta, [1] 1/beta or 1/h, [2] bnorm, [3] est, [4] hn, [5] wnorm0
+  double* sc;     // scalars: [0] beta, [1] 1/beta or 1/h, [2] bnorm, [3] est, [4] hn, [5] wnorm0,
+                  // [7] second pass asked (two-pass form), [8] [9] breakdown flags (delayed form)
+  double* hs;     // R+2: delayed form, slot j of V holds hs[j] times the once-orthogonalized v~_j
+  double* hinv;   // R+2: the scale of slot j for the preconditioner input
+  double* coef;   // 2R+4: coefficients of the update sweep
 };
 int64_t red_blocks(int64_t m);  // partial-sum count of the grid reductions over m doubles
 void launch_norm_finish_n(hipStream_t st, const double* part, int64_t nparts, int slot, double* sc,
@@ -237,6 +241,20 @@ void launch_reorth_finish_n(hipStream_t st, const double* part, int64_t nparts, 
 void launch_arnoldi_finish_n(hipStream_t st, const double* part, int64_t nparts, int j, int R,
                              KrylovScalars ks, double* host);
 void launch_cycle_start(hipStream_t st, int R, KrylovScalars ks);
+// Delayed reorthogonalization: the dots sweep (u = slot j, w = A z_j, nv = j),
+// its scalar step, the update sweep (v_j over u, w' into wo = slot j+1), its
+// scalar step; and at the end of a cycle of k iterations the dots of slot k
+// (u = w = slot k, nv = k) and the final last column.
+void launch_dcgs_dots(hipStream_t st, int64_t m, int nv, const double* V, int64_t ldv, const double* u,
+                      const double* w, double* part);
+void launch_dcgs_finish1(hipStream_t st, const double* part, int64_t nparts, int j, int R, KrylovScalars ks,
+                         double* host);
+void launch_dcgs_update(hipStream_t st, int64_t m, int nv, const double* V, int64_t ldv, const double* coef,
+                        double* u, const double* w, double* wo, double* part);
+void launch_dcgs_finish2(hipStream_t st, const double* part, int64_t nparts, int j, int R, KrylovScalars ks,
+                         double* host);
+void launch_dcgs_last(hipStream_t st, const double* part, int64_t nparts, int k, int R, KrylovScalars ks,
+                      double* host);
 void launch_solve_y(hipStream_t st, int k, int R, KrylovScalars ks);
 
 }  // namespace llg
