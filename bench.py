@@ -34,7 +34,7 @@ def parse():
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="rough2d_1024")
-    p.add_argument("--forms", default="fp64:1,fp32_amg:1,fp64:0",
+    p.add_argument("--forms", default="fp64:1,fp32_amg:1,fp64:0,fp64:1:jacobi:factored,fp32_amg:1:jacobi:factored",
                    help="comma list of precision:kcycle_depth[:smoother[:operator]] (depth 0 = V-cycle; "
                         "smoother jacobi or mcgs, default jacobi; grid-level operator bsr or factored, "
                         "default bsr); the first gives `value`")
@@ -67,7 +67,7 @@ def read_traffic(kernel: str, workload: str, precision: str, operator: str):
     """HBM bytes per launch from the committed PMC summary, or None when the
     summary is missing, was taken on another form or on a different kernel
     source."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (kernel, workload))
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s_%s_%s.txt" % (kernel, workload, precision, operator))
     if not os.path.exists(path):
         return None
     kv = {}
@@ -156,14 +156,15 @@ def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str, Fs, kd
     return res
 
 
-def cpu_baseline(w, nsteps: int):
+def cpu_baseline(w, nsteps: int, kdepth: int = 0, smoother: str = "jacobi"):
     """The oracle timed on `nsteps` steps of the workload from m0 (forcing of
-    the first steps when the workload has one); also returns its first step."""
+    the first steps when the workload has one), with the cycle and smoother of
+    the main form; also returns its first step."""
     import numpy as np
     import oracle
     import llg_inputs as I
     g = oracle.make_grid(w.dim, w.n)
-    o = oracle.default_opts(rtol=w.rtol)
+    o = oracle.default_opts(rtol=w.rtol, kcycle_depth=kdepth, smoother=1 if smoother == "mcgs" else 0)
     m = w.m0()
     t0 = time.perf_counter()
     iters = []
@@ -176,9 +177,10 @@ def cpu_baseline(w, nsteps: int):
             first = m.copy()
     el = time.perf_counter() - t0
     return {"value": 3.0 * w.nodes * nsteps / el, "unit": "unknowns*steps/s", "cores": 1, "kind": "oracle",
-            "sample": "%d step(s) of the %s workload (assembly, hierarchy, FGMRES to rtol %g, projection), "
-                      "single-threaded C++ oracle, %.1f s, %s FGMRES iterations"
-                      % (nsteps, w.name, w.rtol, el, iters),
+            "sample": "%d step(s) of the %s workload (assembly, hierarchy, FGMRES to rtol %g with the %s, "
+                      "projection), single-threaded C++ oracle, %.1f s, %s FGMRES iterations"
+                      % (nsteps, w.name, w.rtol, "K-cycle on levels 1..%d" % kdepth if kdepth else "V-cycle",
+                         el, iters),
             "host_threads_available": os.cpu_count()}, first
 
 
@@ -317,7 +319,7 @@ def main():
         out["err_vs_exact"] = r["err_vs_exact"]
     if not a.no_cpu_baseline:
         log("[bench] cpu baseline: oracle, %d step(s)" % a.cpu_steps)
-        out["cpu_baseline"], ref = cpu_baseline(w, a.cpu_steps)
+        out["cpu_baseline"], ref = cpu_baseline(w, a.cpu_steps, main_kd, main_sm)
         # error of every form's first step against the FP64 oracle's (both at the workload's rtol)
         import numpy as np
         out["err_vs_oracle"] = float(np.abs(r["one_step"].cpu().numpy() - ref).max())
