@@ -594,7 +594,10 @@ int fgmres(const Hier& H, const double* b, const double* u0, double* u, llgo_sta
     for (; j < R && total < H.o.max_iters; ++j) {
       double* vj = &V[(size_t)j * m];
       double* zj = &Z[(size_t)j * m];
-      precond(H, vj, zj);
+      if (H.o.krylov == 2)  // unpreconditioned GMRES: z_j = v_j
+        std::copy(vj, vj + m, zj);
+      else
+        precond(H, vj, zj);
       spmv(H.A, zj, w.data());
       const double wnorm0 = nrm2(m, w.data());
       for (int i = 0; i <= j; ++i) {
@@ -717,7 +720,139 @@ int gcr(const Hier& H, const double* b, const double* u0, double* u, llgo_stats*
   return converged ? LLGO_OK : LLGO_ERR_NOT_CONVERGED;
 }
 
-// ------------------------------------------------------ setup
+// ------------------------------------------------------ Krylov baselines
+// The unpreconditioned solvers the paper compares against (GMRES above with
+// z_j = v_j; BiCGstab; TFQMR), on the unscaled operator A.  Converged when
+// the true residual satisfies ||b - A u|| <= rtol ||b||; when the recurrence
+// says so and the true residual does not, or on a breakdown, the method
+// restarts from the current iterate.  Iterations count matrix-vector pairs
+// (two products each).
+
+// Bi-CGSTAB (van der Vorst 1992), shadow vector r^ = r_0 of each start.
+int bicgstab(const Hier& H, const double* b, const double* u0, double* u, llgo_stats* st) {
+  const int64_t m = 3 * H.A.n;
+  std::copy(u0, u0 + m, u);
+  std::vector<double> r(m), rh(m), p(m), v(m), s(m), t(m);
+  const double bnorm = nrm2(m, b);
+  const double target = H.o.rtol * bnorm;
+  int total = 0, restarts = 0;
+  double rn = 0, est = 0;
+  bool converged = false;
+  for (;;) {
+    spmv(H.A, u, v.data());
+    for (int64_t i = 0; i < m; ++i) r[i] = b[i] - v[i];
+    rn = nrm2(m, r.data());
+    if (bnorm == 0.0 || rn <= target) {
+      converged = true;
+      break;
+    }
+    if (total >= H.o.max_iters) break;
+    std::copy(r.begin(), r.end(), rh.begin());
+    std::copy(r.begin(), r.end(), p.begin());
+    double rho = dot(m, r.data(), rh.data());
+    const int before = total;
+    while (total < H.o.max_iters) {
+      spmv(H.A, p.data(), v.data());
+      const double vr = dot(m, v.data(), rh.data());
+      const double alpha = rho / vr;
+      if (vr == 0.0 || !std::isfinite(alpha)) break;  // breakdown: restart
+      for (int64_t i = 0; i < m; ++i) s[i] = r[i] - alpha * v[i];
+      spmv(H.A, s.data(), t.data());
+      const double tt = dot(m, t.data(), t.data());
+      const double omega = tt > 0.0 ? dot(m, t.data(), s.data()) / tt : 0.0;
+      if (!std::isfinite(omega)) break;
+      for (int64_t i = 0; i < m; ++i) u[i] += alpha * p[i] + omega * s[i];
+      for (int64_t i = 0; i < m; ++i) r[i] = s[i] - omega * t[i];
+      ++total;
+      est = nrm2(m, r.data());
+      if (est <= target || omega == 0.0) break;
+      const double rho1 = dot(m, r.data(), rh.data());
+      const double beta = (rho1 / rho) * (alpha / omega);
+      if (rho1 == 0.0 || !std::isfinite(beta)) break;
+      rho = rho1;
+      for (int64_t i = 0; i < m; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+    }
+    if (total == before) break;  // no progress from this start
+    ++restarts;
+  }
+  if (st) *st = llgo_stats{total, restarts, (int32_t)H.lv.size(), converged ? 1 : 0, bnorm > 0 ? est / bnorm : 0,
+                           bnorm > 0 ? rn / bnorm : 0};
+  return converged ? LLGO_OK : LLGO_ERR_NOT_CONVERGED;
+}
+
+// TFQMR (Freund 1993), in the two half-steps per iteration of its usual
+// statement: the quasi-residual bound tau sqrt(m + 1) decides when the true
+// residual is checked.
+int tfqmr(const Hier& H, const double* b, const double* u0, double* u, llgo_stats* st) {
+  const int64_t m = 3 * H.A.n;
+  std::copy(u0, u0 + m, u);
+  std::vector<double> r(m), rs(m), w(m), ue(m), uo(m), v(m), d(m), aue(m), auo(m);
+  const double bnorm = nrm2(m, b);
+  const double target = H.o.rtol * bnorm;
+  int total = 0, restarts = 0;
+  double rn = 0, est = 0;
+  bool converged = false;
+  for (;;) {
+    spmv(H.A, u, v.data());
+    for (int64_t i = 0; i < m; ++i) r[i] = b[i] - v[i];
+    rn = nrm2(m, r.data());
+    if (bnorm == 0.0 || rn <= target) {
+      converged = true;
+      break;
+    }
+    if (total >= H.o.max_iters) break;
+    // w = u_even = r_0, A u_even, v = A u_even, d = 0, tau = |r_0|, theta = eta = 0
+    std::copy(r.begin(), r.end(), rs.begin());
+    std::copy(r.begin(), r.end(), w.begin());
+    std::copy(r.begin(), r.end(), ue.begin());
+    spmv(H.A, ue.data(), aue.data());
+    std::copy(aue.begin(), aue.end(), v.begin());
+    std::fill(d.begin(), d.end(), 0.0);
+    double tau = rn, theta = 0.0, eta = 0.0;
+    double rho = dot(m, r.data(), rs.data());
+    int half = 0;
+    const int before = total;
+    while (total < H.o.max_iters) {
+      const double vr = dot(m, v.data(), rs.data());
+      const double alpha = rho / vr;
+      if (vr == 0.0 || rho == 0.0 || !std::isfinite(alpha)) break;  // breakdown: restart
+      for (int64_t i = 0; i < m; ++i) uo[i] = ue[i] - alpha * v[i];
+      spmv(H.A, uo.data(), auo.data());
+      bool check = false;
+      for (int step = 0; step < 2; ++step) {  // the even half-step uses u_even, the odd one u_odd
+        const double* um = step == 0 ? ue.data() : uo.data();
+        const double* aum = step == 0 ? aue.data() : auo.data();
+        for (int64_t i = 0; i < m; ++i) w[i] -= alpha * aum[i];
+        const double f = (theta * theta / alpha) * eta;
+        for (int64_t i = 0; i < m; ++i) d[i] = um[i] + f * d[i];
+        theta = nrm2(m, w.data()) / tau;
+        const double c = 1.0 / std::sqrt(1.0 + theta * theta);
+        tau = tau * theta * c;
+        eta = c * c * alpha;
+        for (int64_t i = 0; i < m; ++i) u[i] += eta * d[i];
+        ++half;
+        if (tau * std::sqrt((double)half + 1.0) <= target) check = true;
+      }
+      ++total;
+      est = tau;
+      if (check) break;
+      const double rho1 = dot(m, w.data(), rs.data());
+      const double beta = rho1 / rho;
+      if (!std::isfinite(beta)) break;
+      rho = rho1;
+      for (int64_t i = 0; i < m; ++i) ue[i] = w[i] + beta * uo[i];
+      spmv(H.A, ue.data(), aue.data());
+      for (int64_t i = 0; i < m; ++i) v[i] = aue[i] + beta * (auo[i] + beta * v[i]);
+    }
+    if (total == before) break;  // no progress from this start
+    ++restarts;
+  }
+  if (st) *st = llgo_stats{total, restarts, (int32_t)H.lv.size(), converged ? 1 : 0, bnorm > 0 ? est / bnorm : 0,
+                           bnorm > 0 ? rn / bnorm : 0};
+  return converged ? LLGO_OK : LLGO_ERR_NOT_CONVERGED;
+}
+
+// ------------------------------------------------------ setup// ------------------------------------------------------ setup
 int build(Hier& H, const double* m_tilde, double alpha, double dt) {
   const llgo_grid& g = H.g;
   const llgo_opts& o = H.o;
@@ -780,7 +915,7 @@ bool opts_ok(const llgo_opts* o) {
   return o && o->rtol >= 0 && o->restart >= 1 && o->max_iters >= 1 && o->nu_pre >= 0 &&
          o->nu_post >= 0 && o->npass >= 1 && o->beta_num >= 0 && o->beta_den >= 1 &&
          o->max_coarse >= 1 && o->max_levels >= 1 && o->max_dense >= 1 && o->kcycle_depth >= 0 &&
-         (o->smoother == 0 || o->smoother == 1);
+         (o->smoother == 0 || o->smoother == 1) && o->krylov >= 0 && o->krylov <= 4;
 }
 
 }  // namespace
@@ -960,7 +1095,12 @@ int llgo_precond(void* h, const double* v, double* z) {
 int llgo_solve(void* h, const double* b, const double* u0, double* u, llgo_stats* st) {
   if (!h || !b || !u0 || !u) return LLGO_ERR_ARG;
   Hier* H = (Hier*)h;
-  return H->o.krylov == 1 ? gcr(*H, b, u0, u, st) : fgmres(*H, b, u0, u, st);
+  switch (H->o.krylov) {
+    case 1: return gcr(*H, b, u0, u, st);
+    case 3: return bicgstab(*H, b, u0, u, st);
+    case 4: return tfqmr(*H, b, u0, u, st);
+    default: return fgmres(*H, b, u0, u, st);  // 0: AMG-preconditioned, 2: unpreconditioned
+  }
 }
 
 // One semi-implicit step (Sec. 2.1): m~ = m^n, b = m^n + dt F, solve, project

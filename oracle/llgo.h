@@ -65,7 +65,8 @@ typedef struct {
   int32_t project;      /* normalize the solution node by node */
   int32_t x0_is_mn;     /* initial guess m^n (else zero) */
   uint64_t agg_salt;
-  int32_t krylov;       /* 0 = FGMRES, 1 = GCR (Algorithm 1) */
+  int32_t krylov;       /* 0 = FGMRES + AMG, 1 = GCR + AMG (Algorithm 1); baselines without
+                           preconditioner: 2 = GMRES(restart), 3 = BiCGstab, 4 = TFQMR */
   int32_t kcycle_depth; /* coarse corrections of levels 1..depth by the K-cycle (0: V-cycle) */
   int32_t smoother;     /* 0: damped block Jacobi; 1: multicolour block Gauss-Seidel */
 } llgo_opts;
