@@ -48,6 +48,9 @@ def parse():
     p.add_argument("--requests", type=int, default=32)
     p.add_argument("--workers", type=int, default=4)
     p.add_argument("--serve-steps", type=int, default=20)
+    p.add_argument("--baselines", action="store_true",
+                   help="compare the unpreconditioned Krylov solvers the paper uses (GMRES, BiCGstab, TFQMR, "
+                        "max 1000 iterations) with the AMG-preconditioned FGMRES on the workload")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain device copy of known size (for the PMC byte counters)")
     return p.parse_args()
@@ -184,6 +187,39 @@ def cpu_baseline(w, nsteps: int, kdepth: int = 0, smoother: str = "jacobi"):
             "host_threads_available": os.cpu_count()}, first
 
 
+def baselines_bench(a, llg, torch, w):
+    """Per solver: ms/step, iterations/step, steps that converged and the last
+    true relative residual, over `steps` steps after one warm-up step; FP64,
+    iteration cap 1000 for the baselines (as in the paper's tables)."""
+    forms = [("fgmres_amg_k1", dict(kcycle_depth=1)), ("fgmres_amg_v", dict(kcycle_depth=0)),
+             ("gmres", dict(krylov="gmres", max_iters=1000)), ("bicgstab", dict(krylov="bicgstab", max_iters=1000)),
+             ("tfqmr", dict(krylov="tfqmr", max_iters=1000))]
+    Fs = forcing_list(torch, w, a.steps + 1)
+    out = {"metric": "Krylov baselines vs AMG-FGMRES", "workload": w.name, "unknowns": w.unknowns,
+           "rtol": w.rtol, "steps": a.steps, "solvers": {}}
+    for name, kw in forms:
+        S = llg.Solver(llg.make_grid(w.dim, w.n), llg.default_opts(rtol=w.rtol, **kw))
+        m = torch.from_numpy(w.m0()).cuda()
+        nxt = torch.empty_like(m)
+        m, nxt = S.step(m, w.alpha, w.dt, forcing=Fs[0], out=nxt, check=False)[0], m
+        its, conv, rel = [], 0, None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(a.steps):
+            o, s, st = S.step(m, w.alpha, w.dt, forcing=Fs[k + 1], out=nxt, check=False)
+            m, nxt = o, m
+            its.append(st.iters)
+            conv += int(s == llg.OK)
+            rel = st.relres_true
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out["solvers"][name] = {"ms_per_step": 1e3 * el / a.steps, "iters_per_step": sum(its) / len(its),
+                                "iters": its, "converged_steps": conv, "relres_true_last": rel}
+        log("  %-14s %9.2f ms/step  %7.1f its/step  converged %d/%d  relres %.1e"
+            % (name, 1e3 * el / a.steps, sum(its) / len(its), conv, a.steps, rel))
+    print(json.dumps(out), flush=True)
+
+
 def serve_bench(a):
     """Serving workload: Poisson arrivals (8/s) of 20-step simulations, 2D n in
     128..2048 or 3D n in 32..192, FP32-AMG, admission by device footprint."""
@@ -241,6 +277,9 @@ def main():
     w = I.WORKLOADS[a.workload]
     if a.alpha is not None:
         w.alpha = a.alpha
+    if a.baselines:
+        baselines_bench(a, llg, torch, w)
+        return
     forms = []
     for f in a.forms.split(","):
         if not f:

@@ -105,6 +105,21 @@ typedef enum { LLG_FINE_BSR = 0, LLG_FINE_FACTORED = 1 } llg_fine_operator;
  * is made final before the least-squares solve. */
 typedef enum { LLG_ARNOLDI_CGS2 = 0, LLG_ARNOLDI_DCGS2 = 1 } llg_arnoldi;
 
+/* The solver of the linear system.  FGMRES_AMG is the method (FGMRES(restart)
+ * preconditioned by the AMG cycle).  The others are the unpreconditioned
+ * Krylov solvers the paper compares against (Sec. 4): GMRES(restart), BiCGstab
+ * (van der Vorst 1992) and TFQMR (Freund 1993) on A itself, FP64 only (else
+ * UNSUPPORTED); no AMG hierarchy is built for them.  BiCGstab and TFQMR count
+ * an iteration per two products with A and restart from the current iterate
+ * after a breakdown or when their recurrence meets rtol and the true
+ * residual does not. */
+typedef enum {
+  LLG_KRYLOV_FGMRES_AMG = 0,
+  LLG_KRYLOV_GMRES = 2,
+  LLG_KRYLOV_BICGSTAB = 3,
+  LLG_KRYLOV_TFQMR = 4
+} llg_krylov;
+
 typedef struct {
   int32_t dim;   /* 2 or 3 */
   int32_t n[3];  /* points per axis, each >= 2; n[2] == 1 when dim == 2 */
@@ -139,6 +154,7 @@ typedef struct {
   int32_t scheme;       /* llg_scheme: BDF1 (default) or BDF2, see llg_step */
   int32_t fine_operator; /* llg_fine_operator: storage of the grid level, see below */
   int32_t arnoldi;      /* llg_arnoldi: orthogonalization of the FGMRES basis, see below */
+  int32_t krylov;       /* llg_krylov: the solver; the default is FGMRES with the AMG cycle */
 } llg_opts;
 
 typedef struct {

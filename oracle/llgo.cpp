@@ -737,7 +737,7 @@ int bicgstab(const Hier& H, const double* b, const double* u0, double* u, llgo_s
   const double target = H.o.rtol * bnorm;
   int total = 0, restarts = 0;
   double rn = 0, est = 0;
-  bool converged = false;
+  bool converged = false, restarting = false;
   for (;;) {
     spmv(H.A, u, v.data());
     for (int64_t i = 0; i < m; ++i) r[i] = b[i] - v[i];
@@ -747,6 +747,7 @@ int bicgstab(const Hier& H, const double* b, const double* u0, double* u, llgo_s
       break;
     }
     if (total >= H.o.max_iters) break;
+    if (restarting) ++restarts;
     std::copy(r.begin(), r.end(), rh.begin());
     std::copy(r.begin(), r.end(), p.begin());
     double rho = dot(m, r.data(), rh.data());
@@ -773,7 +774,7 @@ int bicgstab(const Hier& H, const double* b, const double* u0, double* u, llgo_s
       for (int64_t i = 0; i < m; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
     }
     if (total == before) break;  // no progress from this start
-    ++restarts;
+    restarting = true;
   }
   if (st) *st = llgo_stats{total, restarts, (int32_t)H.lv.size(), converged ? 1 : 0, bnorm > 0 ? est / bnorm : 0,
                            bnorm > 0 ? rn / bnorm : 0};
@@ -791,7 +792,7 @@ int tfqmr(const Hier& H, const double* b, const double* u0, double* u, llgo_stat
   const double target = H.o.rtol * bnorm;
   int total = 0, restarts = 0;
   double rn = 0, est = 0;
-  bool converged = false;
+  bool converged = false, restarting = false;
   for (;;) {
     spmv(H.A, u, v.data());
     for (int64_t i = 0; i < m; ++i) r[i] = b[i] - v[i];
@@ -801,6 +802,7 @@ int tfqmr(const Hier& H, const double* b, const double* u0, double* u, llgo_stat
       break;
     }
     if (total >= H.o.max_iters) break;
+    if (restarting) ++restarts;
     // w = u_even = r_0, A u_even, v = A u_even, d = 0, tau = |r_0|, theta = eta = 0
     std::copy(r.begin(), r.end(), rs.begin());
     std::copy(r.begin(), r.end(), w.begin());
@@ -845,7 +847,7 @@ int tfqmr(const Hier& H, const double* b, const double* u0, double* u, llgo_stat
       for (int64_t i = 0; i < m; ++i) v[i] = aue[i] + beta * (auo[i] + beta * v[i]);
     }
     if (total == before) break;  // no progress from this start
-    ++restarts;
+    restarting = true;
   }
   if (st) *st = llgo_stats{total, restarts, (int32_t)H.lv.size(), converged ? 1 : 0, bnorm > 0 ? est / bnorm : 0,
                            bnorm > 0 ? rn / bnorm : 0};

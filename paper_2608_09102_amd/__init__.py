@@ -32,6 +32,7 @@ SMOOTHER_JACOBI, SMOOTHER_MCGS = 0, 1
 SCHEME_BDF1, SCHEME_BDF2 = 0, 1
 FINE_BSR, FINE_FACTORED = 0, 1
 ARNOLDI_CGS2, ARNOLDI_DCGS2 = 0, 1
+KRYLOV_FGMRES_AMG, KRYLOV_GMRES, KRYLOV_BICGSTAB, KRYLOV_TFQMR = 0, 2, 3, 4
 KT_NONE, KT_OUTER_SPMV, KT_SMOOTH, KT_RESIDUAL, KT_ARNOLDI, KT_GALERKIN, KT_ASSEMBLE = range(7)
 KERNEL_CLASSES = {"none": 0, "outer_spmv": 1, "smooth": 2, "residual": 3, "arnoldi": 4, "galerkin": 5,
                   "assemble": 6}
@@ -52,7 +53,7 @@ class Opts(ctypes.Structure):
         ("project", ctypes.c_int32), ("x0_is_mn", ctypes.c_int32), ("agg_salt", ctypes.c_uint64),
         ("rebuild_aggregates", ctypes.c_int32), ("kcycle_depth", ctypes.c_int32),
         ("graphs", ctypes.c_int32), ("smoother", ctypes.c_int32), ("scheme", ctypes.c_int32),
-        ("fine_operator", ctypes.c_int32), ("arnoldi", ctypes.c_int32),
+        ("fine_operator", ctypes.c_int32), ("arnoldi", ctypes.c_int32), ("krylov", ctypes.c_int32),
     ]
 
 
@@ -157,6 +158,9 @@ def default_opts(**kw) -> Opts:
             v = {"bsr": FINE_BSR, "factored": FINE_FACTORED}[v]
         if k == "arnoldi" and isinstance(v, str):
             v = {"cgs2": ARNOLDI_CGS2, "dcgs2": ARNOLDI_DCGS2}[v]
+        if k == "krylov" and isinstance(v, str):
+            v = {"fgmres_amg": KRYLOV_FGMRES_AMG, "gmres": KRYLOV_GMRES, "bicgstab": KRYLOV_BICGSTAB,
+                 "tfqmr": KRYLOV_TFQMR}[v]
         setattr(o, k, v)
     return o
 

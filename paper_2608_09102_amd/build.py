@@ -19,6 +19,7 @@ COMMON = ["-std=c++17", "-O3", "-fPIC", "--offload-arch=" + ARCH, "-I" + os.path
 SOURCES = {
     "k_setup.hip": ["-ffp-contract=off"],
     "k_solve.hip": [],
+    "k_krylov.hip": [],
     "engine.hip": [],
 }
 

@@ -165,7 +165,9 @@ struct Level {
 };
 
 struct PlanKey {
-  std::tuple<int, int, int, int, int, int, int, int, double, int, int, uint64_t, int, int, int, int, int, int, int> k;
+  std::tuple<int, int, int, int, int, int, int, int, double, int, int, uint64_t, int, int, int, int, int, int, int,
+             int>
+      k;
   bool operator<(const PlanKey& o) const { return k < o.k; }
 };
 
@@ -176,7 +178,7 @@ PlanKey plan_key(const llg_grid& g, const llg_opts& o) {
   PlanKey k;
   k.k = std::make_tuple(g.dim, g.n[0], g.n[1], g.n[2], o.npass, o.beta_num, o.beta_den, o.max_coarse,
                         o.stagnation, o.max_levels, o.max_dense, o.agg_salt, o.precision, o.restart,
-                        o.left_scale, o.kcycle_depth, o.smoother, o.scheme, o.fine_operator);
+                        o.left_scale, o.kcycle_depth, o.smoother, o.scheme, o.fine_operator, o.krylov);
   return k;
 }
 
@@ -226,6 +228,8 @@ struct llg_ctx {
   bool capturing = false;
   bool graphs_ok = true;
   hipGraphExec_t setup_graph[4] = {nullptr, nullptr, nullptr, nullptr};  // [forcing + 2 * bdf2]
+  hipGraphExec_t kb_graph = nullptr;  // one iteration of a Krylov baseline
+  double* kb = nullptr;                // device scalars of the Krylov baselines
   std::vector<hipGraphExec_t> pc_graph;  // preconditioner of iteration j
   std::vector<hipGraphExec_t> it_graph;  // Gram-Schmidt of iteration j
   double* prm = nullptr;          // device: alpha, dt
@@ -573,7 +577,11 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   c.b = ar.lazy<double>(m);
   c.r = ar.lazy<double>(m);
   c.w = ar.lazy<double>(m);
-  c.V = ar.lazy<double>((R + 1) * c.ld);
+  // the baselines keep their work vectors in the basis slots
+  const int slots = c.opts.krylov == LLG_KRYLOV_BICGSTAB || c.opts.krylov == LLG_KRYLOV_TFQMR ? std::max(R + 1, 10)
+                                                                                             : R + 1;
+  c.V = ar.lazy<double>(slots * c.ld);
+  c.kb = ar.lazy<double>(KB_SIZE);
   c.Z = ar.get(ts * (size_t)R * c.ld, true);
   c.npart_vec = red_blocks(m);
   c.npart_rows = ceil_div(c.N, 256);
@@ -620,7 +628,9 @@ bool opts_ok(const llg_opts* o) {
          (o->smoother == LLG_SMOOTHER_JACOBI || o->smoother == LLG_SMOOTHER_MCGS) &&
          (o->scheme == LLG_SCHEME_BDF1 || o->scheme == LLG_SCHEME_BDF2) &&
          (o->fine_operator == LLG_FINE_BSR || o->fine_operator == LLG_FINE_FACTORED) &&
-         (o->arnoldi == LLG_ARNOLDI_CGS2 || o->arnoldi == LLG_ARNOLDI_DCGS2);
+         (o->arnoldi == LLG_ARNOLDI_CGS2 || o->arnoldi == LLG_ARNOLDI_DCGS2) &&
+         (o->krylov == LLG_KRYLOV_FGMRES_AMG || o->krylov == LLG_KRYLOV_GMRES || o->krylov == LLG_KRYLOV_BICGSTAB ||
+          o->krylov == LLG_KRYLOV_TFQMR);
 }
 
 // Plan for (grid, opts): cached; computed on the current device.
@@ -671,7 +681,8 @@ template <typename T>
 void setup_values(llg_ctx& c, const double* m, const double* mprev, const double* F) {
   hipStream_t st = c.st;
   const llg_grid& g = c.grid;
-  if (c.opts.rebuild_aggregates) {
+  const bool amg = c.opts.krylov == LLG_KRYLOV_FGMRES_AMG;  // the baselines need only A, b and u0
+  if (amg && c.opts.rebuild_aggregates) {
     Arena ar;
     ar.mode = Mode::REPLAY;
     ar.plan = c.plan.get();
@@ -688,6 +699,7 @@ void setup_values(llg_ctx& c, const double* m, const double* mprev, const double
                        c.flags, c.Mh, (T*)L0.kf);
     LCHK();
   }
+  if (!amg) return;
   for (int l = 0; l + 1 < c.L; ++l) {
     Level& L = c.lv[l];
     Level& Nx = c.lv[l + 1];
@@ -1019,6 +1031,12 @@ struct SolveOut {
 template <typename T>
 void iter_precond(llg_ctx& c, int j) {
   const bool dcgs = c.opts.arnoldi == LLG_ARNOLDI_DCGS2;
+  if (c.opts.krylov == LLG_KRYLOV_GMRES) {  // unpreconditioned: z_j = v_j
+    launch_scale_copy(c.st, 3 * c.N, c.V + (int64_t)j * c.ld, dcgs ? c.ks.hinv + j : nullptr,
+                      (double*)c.Z + (int64_t)j * c.ld);
+    LCHK();
+    return;
+  }
   precond<T>(c, c.V + (int64_t)j * c.ld, (T*)c.Z + (int64_t)j * c.ld, dcgs ? c.ks.hinv + j : nullptr);
 }
 
@@ -1137,6 +1155,139 @@ SolveOut fgmres(llg_ctx& c) {
   return so;
 }
 
+// ------------------------------------------------------------------ baselines
+// r = b - A u, its norm to the host (H[0]); synchronizes.
+double true_residual(llg_ctx& c) {
+  outer_resid(c);
+  launch_norm_finish_n(c.st, c.part, c.npart_rows, 0, c.ks.sc, c.host);
+  LCHK();
+  sync(c);
+  return c.host[0];
+}
+
+// Shared loop of the baselines: `start` begins a cycle from r, `body` is one
+// iteration (replayed as a graph); a cycle ends on a breakdown flag or when
+// the recurrence's residual estimate meets the target, and the true residual
+// decides; otherwise the method restarts from the current iterate.
+template <typename Start, typename Body>
+SolveOut baseline_loop(llg_ctx& c, Start start, Body body) {
+  hipStream_t st = c.st;
+  const int64_t m = 3 * c.N;
+  double* H = c.host;
+  SolveOut so;
+  H[7] = 0.0;
+  launch_norm_part(st, m, c.b, c.part);
+  launch_norm_finish_n(st, c.part, c.npart_vec, 2, c.ks.sc, H);
+  LCHK();
+  double rn = true_residual(c);
+  const double bnorm = H[2];
+  const double target = c.opts.rtol * bnorm;
+  so.truer = so.est = bnorm > 0 ? rn / bnorm : 0;
+  if (bnorm == 0.0 || rn <= target) {
+    so.converged = true;
+    return so;
+  }
+  while (so.iters < c.opts.max_iters) {
+    start();
+    LCHK();
+    const int before = so.iters;
+    while (so.iters < c.opts.max_iters) {
+      if (use_graphs(c) && !c.kb_graph) c.kb_graph = try_capture(c, [&]() { body(); });
+      if (use_graphs(c) && c.kb_graph)
+        HIPX(hipGraphLaunch(c.kb_graph, st));
+      else
+        body();
+      sync(c);
+      ++so.iters;
+      so.est = bnorm > 0 ? H[3] / bnorm : 0;
+      if (H[6] != 0.0 || H[3] <= target) break;
+    }
+    rn = true_residual(c);
+    so.truer = rn / bnorm;
+    so.converged = rn <= target;
+    if (so.converged || so.iters == before) break;
+    ++so.restarts;
+  }
+  return so;
+}
+
+// Bi-CGSTAB (van der Vorst 1992) on A, without preconditioner; the shadow
+// vector of each start is its residual.
+SolveOut bicgstab(llg_ctx& c) {
+  // launches go to c.st as read at call time (the capture stream while a
+  // graph is recorded)
+  const int64_t m = 3 * c.N, ld = c.ld, np = c.npart_vec;
+  double *rh = c.V, *p = c.V + ld, *v = c.V + 2 * ld, *s = c.V + 3 * ld, *t = c.V + 4 * ld;
+  double* kb = c.kb;
+  const KTerm none{nullptr, nullptr, 0.0};
+  auto start = [&]() {
+    launch_copy(c.st, m, c.r, rh);
+    launch_copy(c.st, m, c.r, p);
+    launch_dot2(c.st, m, c.r, rh, c.r, c.r, c.part);
+    launch_kb_step(c.st, c.part, np, KB_START, kb, c.host);
+  };
+  auto body = [&]() {
+    outer_spmv<double>(c, p, v);
+    launch_dot2(c.st, m, v, rh, nullptr, nullptr, c.part);
+    launch_kb_step(c.st, c.part, np, KB_ALPHA, kb, c.host);
+    launch_lin3(c.st, m, KTerm{c.r, nullptr, 1.0}, KTerm{v, kb + KB_ALPHA, -1.0}, none, s, nullptr, nullptr, c.part);
+    outer_spmv<double>(c, s, t);
+    launch_dot2(c.st, m, t, s, t, t, c.part);
+    launch_kb_step(c.st, c.part, np, KB_OMEGA, kb, c.host);
+    launch_lin3(c.st, m, KTerm{c.u, nullptr, 1.0}, KTerm{p, kb + KB_ALPHA, 1.0}, KTerm{s, kb + KB_OMEGA, 1.0}, c.u,
+                nullptr, nullptr, c.part);
+    launch_lin3(c.st, m, KTerm{s, nullptr, 1.0}, KTerm{t, kb + KB_OMEGA, -1.0}, none, c.r, rh, nullptr, c.part);
+    launch_kb_step(c.st, c.part, np, KB_BICG_END, kb, c.host);
+    launch_lin3(c.st, m, KTerm{c.r, nullptr, 1.0}, KTerm{p, kb + KB_BETA, 1.0}, KTerm{v, kb + KB_BW, -1.0}, p,
+                nullptr, nullptr, c.part);
+  };
+  return baseline_loop(c, start, body);
+}
+
+// TFQMR (Freund 1993) on A, without preconditioner: one iteration is the two
+// half-steps of a pair, u_even then u_odd.
+SolveOut tfqmr(llg_ctx& c) {
+  // launches go to c.st as read at call time (the capture stream while a
+  // graph is recorded)
+  const int64_t m = 3 * c.N, ld = c.ld, np = c.npart_vec;
+  double *rs = c.V, *w = c.V + ld, *ue = c.V + 2 * ld, *uo = c.V + 3 * ld, *v = c.V + 4 * ld;
+  double *d = c.V + 5 * ld, *aue = c.V + 6 * ld, *auo = c.V + 7 * ld;
+  double* kb = c.kb;
+  const KTerm none{nullptr, nullptr, 0.0};
+  auto start = [&]() {
+    launch_copy(c.st, m, c.r, rs);
+    launch_copy(c.st, m, c.r, w);
+    launch_copy(c.st, m, c.r, ue);
+    outer_spmv<double>(c, ue, aue);
+    launch_copy(c.st, m, aue, v);
+    launch_lin3(c.st, m, KTerm{ue, nullptr, 0.0}, none, none, d, nullptr, nullptr, c.part);
+    launch_dot2(c.st, m, c.r, rs, c.r, c.r, c.part);
+    launch_kb_step(c.st, c.part, np, KB_START, kb, c.host);
+  };
+  auto half = [&](const double* um, const double* aum) {
+    launch_kb_step(c.st, c.part, np, KB_TF_F, kb, c.host);
+    launch_lin3(c.st, m, KTerm{w, nullptr, 1.0}, KTerm{aum, kb + KB_ALPHA, -1.0}, none, w, nullptr, nullptr, c.part);
+    launch_kb_step(c.st, c.part, np, KB_TF_HALF, kb, c.host);
+    launch_lin3(c.st, m, KTerm{um, nullptr, 1.0}, KTerm{d, kb + KB_F, 1.0}, none, d, nullptr, nullptr, c.part);
+    launch_lin3(c.st, m, KTerm{c.u, nullptr, 1.0}, KTerm{d, kb + KB_ETA, 1.0}, none, c.u, nullptr, nullptr, c.part);
+  };
+  auto body = [&]() {
+    launch_dot2(c.st, m, v, rs, nullptr, nullptr, c.part);
+    launch_kb_step(c.st, c.part, np, KB_ALPHA, kb, c.host);
+    launch_lin3(c.st, m, KTerm{ue, nullptr, 1.0}, KTerm{v, kb + KB_ALPHA, -1.0}, none, uo, nullptr, nullptr, c.part);
+    outer_spmv<double>(c, uo, auo);
+    half(ue, aue);
+    half(uo, auo);
+    launch_dot2(c.st, m, w, rs, nullptr, nullptr, c.part);
+    launch_kb_step(c.st, c.part, np, KB_TF_END, kb, c.host);
+    launch_lin3(c.st, m, KTerm{w, nullptr, 1.0}, KTerm{uo, kb + KB_BETA, 1.0}, none, ue, nullptr, nullptr, c.part);
+    outer_spmv<double>(c, ue, aue);
+    launch_lin3(c.st, m, KTerm{aue, nullptr, 1.0}, KTerm{auo, kb + KB_BETA, 1.0}, KTerm{v, kb + KB_B2, 1.0}, v, nullptr,
+                nullptr, c.part);
+  };
+  return baseline_loop(c, start, body);
+}
+
 double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -1159,7 +1310,9 @@ llg_status run_step(llg_ctx& c, const double* m_n, const double* m_nm1, double a
   run_setup<T>(c, F != nullptr, bdf2);
   HIPX(hipStreamSynchronize(c.st));
   const double t_setup = ms_since(t0);
-  SolveOut so = fgmres<T>(c);
+  SolveOut so = c.opts.krylov == LLG_KRYLOV_BICGSTAB ? bicgstab(c)
+                : c.opts.krylov == LLG_KRYLOV_TFQMR  ? tfqmr(c)
+                                                     : fgmres<T>(c);
   launch_project(c.st, c.N, c.u, m_np1, c.opts.project, c.flags);
   LCHK();
   HIPX(hipMemcpyAsync(c.hflags, c.flags, sizeof(int32_t), hipMemcpyDeviceToHost, c.st));
@@ -1249,12 +1402,14 @@ void llg_default_opts(llg_opts* o) {
   o->scheme = LLG_SCHEME_BDF1;
   o->fine_operator = LLG_FINE_BSR;
   o->arnoldi = LLG_ARNOLDI_DCGS2;
+  o->krylov = LLG_KRYLOV_FGMRES_AMG;
 }
 
 // combinations the library does not implement
 static bool supported(const llg_grid* grid, const llg_opts* opts) {
   if (grid->bc != LLG_BC_NEUMANN) return false;
   if (opts->fine_operator == LLG_FINE_FACTORED && !opts->left_scale) return false;
+  if (opts->krylov != LLG_KRYLOV_FGMRES_AMG && opts->precision != LLG_PREC_FP64) return false;
   return true;
 }
 
@@ -1522,6 +1677,7 @@ llg_status llg_destroy(llg_ctx* ctx) {
     if (g) (void)hipGraphExecDestroy(g);
   for (hipGraphExec_t g : ctx->it_graph)
     if (g) (void)hipGraphExecDestroy(g);
+  if (ctx->kb_graph) (void)hipGraphExecDestroy(ctx->kb_graph);
   for (hipGraphExec_t g : ctx->setup_graph)
     if (g) (void)hipGraphExecDestroy(g);
   if (ctx->cap_st) (void)hipStreamDestroy(ctx->cap_st);

@@ -196,6 +196,28 @@ template <typename T>
 void launch_fact_post_smooth(hipStream_t st, GridDims g, const T* K, int xmode, double omega, const T* b,
                              const T* x, const int32_t* agg, const T* ec, T* out);
 
+// Krylov baselines (BiCGstab, TFQMR): a term s c x of a linear combination
+// (c: device scalar or NULL for 1), the combination with its dots, plain
+// copies, and the scalar steps on the state kb.
+struct KTerm {
+  const double* x;
+  const double* c;
+  double s;
+};
+enum {
+  KB_RHO = 0, KB_ALPHA, KB_OMEGA, KB_BETA, KB_BW, KB_TAU, KB_THETA, KB_ETA, KB_F, KB_HALF, KB_FLAG, KB_B2,
+  KB_MINB, KB_SIZE = 16
+};
+enum { KB_START = 0, KB_BICG_END = 3, KB_TF_F = 4, KB_TF_HALF = 5, KB_TF_END = 6 };
+// (op codes KB_ALPHA and KB_OMEGA reuse the state indices of their results)
+void launch_lin3(hipStream_t st, int64_t m, KTerm t0, KTerm t1, KTerm t2, double* y, const double* d0,
+                 const double* d1, double* part);
+void launch_dot2(hipStream_t st, int64_t m, const double* x0, const double* y0, const double* x1,
+                 const double* y1, double* part);
+void launch_copy(hipStream_t st, int64_t m, const double* x, double* y);
+void launch_scale_copy(hipStream_t st, int64_t m, const double* x, const double* s, double* y);
+void launch_kb_step(hipStream_t st, const double* part, int64_t nparts, int op, double* kb, double* host);
+
 // outer Krylov kernels (FP64)
 template <typename TZ>
 void launch_spmv_outer(hipStream_t st, Sell A, const double* val, const TZ* z, double* w);
