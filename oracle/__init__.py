@@ -59,6 +59,19 @@ class Opts(ctypes.Structure):
     ]
 
 
+class Field(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("q", ctypes.c_double), ("h_ext", ctypes.c_double * 3),
+                ("stray", ctypes.c_int32)]
+
+
+def make_field(eps=1.0, q=0.0, h_ext=(0.0, 0.0, 0.0), stray=0) -> Field:
+    f = Field()
+    f.eps, f.q = eps, q
+    f.h_ext[0], f.h_ext[1], f.h_ext[2] = h_ext
+    f.stray = int(stray)
+    return f
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("converged", ctypes.c_int32), ("relres_est", ctypes.c_double),
@@ -100,6 +113,10 @@ def lib() -> ctypes.CDLL:
                                 ctypes.c_double, P, P, ctypes.POINTER(Stats)]
         L.llgo_step2.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), P, P, ctypes.c_double,
                                  ctypes.c_double, P, P, ctypes.POINTER(Stats)]
+        L.llgo_demag_tensor.argtypes = [ctypes.c_double] * 6 + [P]
+        L.llgo_stray_field.argtypes = [ctypes.POINTER(Grid), P, P]
+        L.llgo_step_field.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), P, P, ctypes.c_double,
+                                      ctypes.c_double, ctypes.POINTER(Field), P, P, ctypes.POINTER(Stats)]
         _lib = L
     return _lib
 
@@ -294,4 +311,39 @@ def step2(grid: Grid, opts: Opts, m_n: np.ndarray, m_nm1: np.ndarray, alpha: flo
         Fp = _p(F)
     rc = lib().llgo_step2(ctypes.byref(grid), ctypes.byref(opts), _p(m_n), _p(m_nm1), alpha, dt, Fp, _p(out),
                           ctypes.byref(st))
+    return rc, out, st
+
+
+def demag_tensor(X, Y, Z, dx, dy, dz) -> np.ndarray:
+    """[xx, yy, zz, xy, xz, yz] of the cell-averaged demagnetizing tensor."""
+    N = np.empty(6, np.float64)
+    lib().llgo_demag_tensor(X, Y, Z, dx, dy, dz, _p(N))
+    return N
+
+
+def stray_field(grid: Grid, m: np.ndarray) -> np.ndarray:
+    N = grid.n[0] * grid.n[1] * grid.n[2]
+    m = np.ascontiguousarray(m, dtype=np.float64).reshape(N, 3)
+    h = np.empty_like(m)
+    assert lib().llgo_stray_field(ctypes.byref(grid), _p(m), _p(h)) == 0
+    return h
+
+
+def step_field(grid: Grid, opts: Opts, m_n: np.ndarray, alpha: float, dt: float, field: Field,
+               m_nm1: np.ndarray | None = None, F: np.ndarray | None = None):
+    """One step of the full model (BDF1, or BDF2 with m_nm1); returns (status, m_np1, Stats)."""
+    N = grid.n[0] * grid.n[1] * grid.n[2]
+    m_n = np.ascontiguousarray(m_n, dtype=np.float64).reshape(N, 3)
+    prev = None
+    if m_nm1 is not None:
+        m_nm1 = np.ascontiguousarray(m_nm1, dtype=np.float64).reshape(N, 3)
+        prev = _p(m_nm1)
+    Fp = None
+    if F is not None:
+        F = np.ascontiguousarray(F, dtype=np.float64).reshape(N, 3)
+        Fp = _p(F)
+    out = np.empty_like(m_n)
+    st = Stats()
+    rc = lib().llgo_step_field(ctypes.byref(grid), ctypes.byref(opts), _p(m_n), prev, alpha, dt, ctypes.byref(field),
+                               Fp, _p(out), ctypes.byref(st))
     return rc, out, st

@@ -1174,3 +1174,144 @@ int llgo_step2(const llgo_grid* g, const llgo_opts* o, const double* m_n, const 
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------ full field (Sec. 2)
+namespace {
+// Newell, Williams and Dunlop (1993): the generating functions of the
+// diagonal (f) and off-diagonal (g) cell-averaged demagnetizing tensor.
+// Terms whose prefactor vanishes are dropped (their limits are zero).
+double newell_f(double x, double y, double z) {
+  x = std::fabs(x);
+  y = std::fabs(y);
+  z = std::fabs(z);
+  const double x2 = x * x, y2 = y * y, z2 = z * z;
+  const double R = std::sqrt(x2 + y2 + z2);
+  if (R == 0.0) return 0.0;
+  double r = 0.0;
+  if (y > 0.0 && z2 != x2) r += 0.5 * y * (z2 - x2) * std::asinh(y / std::sqrt(x2 + z2));
+  if (z > 0.0 && y2 != x2) r += 0.5 * z * (y2 - x2) * std::asinh(z / std::sqrt(x2 + y2));
+  if (x > 0.0 && y > 0.0 && z > 0.0) r -= x * y * z * std::atan(y * z / (x * R));
+  r += (2.0 * x2 - y2 - z2) * R / 6.0;
+  return r;
+}
+
+double newell_g(double x, double y, double z) {
+  const double sgn = (x > 0 ? 1.0 : (x < 0 ? -1.0 : 0.0)) * (y > 0 ? 1.0 : (y < 0 ? -1.0 : 0.0));
+  if (sgn == 0.0) return 0.0;
+  x = std::fabs(x);
+  y = std::fabs(y);
+  z = std::fabs(z);
+  const double x2 = x * x, y2 = y * y, z2 = z * z;
+  const double R = std::sqrt(x2 + y2 + z2);
+  double r = 0.0;
+  if (z > 0.0) r += x * y * z * std::asinh(z / std::sqrt(x2 + y2));
+  r += (y / 6.0) * (3.0 * z2 - y2) * std::asinh(x / std::sqrt(y2 + z2));
+  r += (x / 6.0) * (3.0 * z2 - x2) * std::asinh(y / std::sqrt(x2 + z2));
+  if (z > 0.0) {
+    r -= (z2 * z / 6.0) * std::atan(x * y / (z * R));
+    r -= (z * y2 / 2.0) * std::atan(x * z / (y * R));
+    r -= (z * x2 / 2.0) * std::atan(y * z / (x * R));
+  }
+  r -= x * y * R / 3.0;
+  return sgn * r;
+}
+
+// the 27-point second difference (weights 2 at 0, -1 at +-1 per axis) of fun
+// around (X, Y, Z) with spacings (a, b, c), over 4 pi a b c
+template <typename Fn>
+double newell_sum(Fn fun, double X, double Y, double Z, double a, double b, double c) {
+  const double w[3] = {-1.0, 2.0, -1.0};
+  double acc = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k)
+        acc += w[i] * w[j] * w[k] * fun(X + (i - 1) * a, Y + (j - 1) * b, Z + (k - 1) * c);
+  return acc / (4.0 * M_PI * a * b * c);
+}
+
+void demag(double X, double Y, double Z, double dx, double dy, double dz, double* N) {
+  const double far = std::max(std::fabs(X) / dx, std::max(std::fabs(Y) / dy, std::fabs(Z) / dz));
+  if (far > 16.0) {
+    const double r2 = X * X + Y * Y + Z * Z, r = std::sqrt(r2);
+    const double k = -(dx * dy * dz) / (4.0 * M_PI * r2 * r);
+    N[0] = k * (3.0 * X * X / r2 - 1.0);
+    N[1] = k * (3.0 * Y * Y / r2 - 1.0);
+    N[2] = k * (3.0 * Z * Z / r2 - 1.0);
+    N[3] = k * 3.0 * X * Y / r2;
+    N[4] = k * 3.0 * X * Z / r2;
+    N[5] = k * 3.0 * Y * Z / r2;
+    return;
+  }
+  N[0] = newell_sum(newell_f, X, Y, Z, dx, dy, dz);
+  N[1] = newell_sum(newell_f, Y, X, Z, dy, dx, dz);
+  N[2] = newell_sum(newell_f, Z, Y, X, dz, dy, dx);
+  N[3] = newell_sum(newell_g, X, Y, Z, dx, dy, dz);
+  N[4] = newell_sum(newell_g, X, Z, Y, dx, dz, dy);
+  N[5] = newell_sum(newell_g, Y, Z, X, dy, dz, dx);
+}
+
+// h_i = -sum_j N(x_i - x_j) m_j, the tensor tabulated once per offset
+void stray(const llgo_grid& g, const double* m, double* h) {
+  const int64_t nx = g.n[0], ny = g.n[1], nz = g.n[2], N = num_nodes(g);
+  const int64_t ox = 2 * nx - 1, oy = 2 * ny - 1, oz = 2 * nz - 1;
+  std::vector<double> T((size_t)(ox * oy * oz) * 6);
+  for (int64_t c = 0; c < oz; ++c)
+    for (int64_t b = 0; b < oy; ++b)
+      for (int64_t a = 0; a < ox; ++a)
+        demag((double)(a - (nx - 1)) * g.h, (double)(b - (ny - 1)) * g.h, (double)(c - (nz - 1)) * g.h, g.h, g.h,
+              g.h, &T[6 * (size_t)(a + ox * (b + oy * c))]);
+  for (int64_t p = 0; p < N; ++p) {
+    const int64_t i = p % nx, j = (p / nx) % ny, k = p / (nx * ny);
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t q = 0; q < N; ++q) {
+      const int64_t i2 = q % nx, j2 = (q / nx) % ny, k2 = q / (nx * ny);
+      const double* t = &T[6 * (size_t)((i - i2 + nx - 1) + ox * ((j - j2 + ny - 1) + oy * (k - k2 + nz - 1)))];
+      const double* mq = m + 3 * q;
+      s[0] += t[0] * mq[0] + t[3] * mq[1] + t[4] * mq[2];
+      s[1] += t[3] * mq[0] + t[1] * mq[1] + t[5] * mq[2];
+      s[2] += t[4] * mq[0] + t[5] * mq[1] + t[2] * mq[2];
+    }
+    for (int c = 0; c < 3; ++c) h[3 * p + c] = -s[c];
+  }
+}
+}  // namespace
+
+extern "C" {
+
+void llgo_demag_tensor(double X, double Y, double Z, double dx, double dy, double dz, double* N) {
+  demag(X, Y, Z, dx, dy, dz, N);
+}
+
+int llgo_stray_field(const llgo_grid* g, const double* m, double* h) {
+  if (!grid_ok(g) || !m || !h) return LLGO_ERR_ARG;
+  stray(*g, m, h);
+  return LLGO_OK;
+}
+
+int llgo_step_field(const llgo_grid* g, const llgo_opts* o, const double* m_n, const double* m_nm1, double alpha,
+                    double dt, const llgo_field* fld, const double* F, double* m_np1, llgo_stats* st) {
+  if (!grid_ok(g) || !opts_ok(o) || !m_n || !m_np1 || !fld) return LLGO_ERR_ARG;
+  const int64_t N = num_nodes(*g), m = 3 * N;
+  for (int64_t i = 0; i < m; ++i)
+    if (!std::isfinite(m_n[i]) || (m_nm1 && !std::isfinite(m_nm1[i]))) return LLGO_ERR_NONFINITE;
+  const double dtp = m_nm1 ? (2.0 * dt) / 3.0 : dt;
+  std::vector<double> mt(m), b(m), f(m, 0.0);
+  for (int64_t i = 0; i < m; ++i) {
+    mt[i] = m_nm1 ? 2.0 * m_n[i] - m_nm1[i] : m_n[i];
+    b[i] = m_nm1 ? (4.0 * m_n[i] - m_nm1[i]) / 3.0 : m_n[i];
+    if (F) b[i] = b[i] + dtp * F[i];
+  }
+  if (fld->stray) stray(*g, mt.data(), f.data());
+  for (int64_t p = 0; p < N; ++p) {
+    const double* x = &mt[3 * p];
+    double fp[3] = {f[3 * p] + fld->h_ext[0], (f[3 * p + 1] + fld->h_ext[1]) - fld->q * x[1],
+                    (f[3 * p + 2] + fld->h_ext[2]) - fld->q * x[2]};
+    // c1 = m~ x f, c2 = m~ x c1, b -= dt' (c1 + alpha c2)
+    const double c1[3] = {x[1] * fp[2] - x[2] * fp[1], x[2] * fp[0] - x[0] * fp[2], x[0] * fp[1] - x[1] * fp[0]};
+    const double c2[3] = {x[1] * c1[2] - x[2] * c1[1], x[2] * c1[0] - x[0] * c1[2], x[0] * c1[1] - x[1] * c1[0]};
+    for (int c = 0; c < 3; ++c) b[3 * p + c] = b[3 * p + c] - dtp * (c1[c] + alpha * c2[c]);
+  }
+  return solve_and_project(g, o, mt.data(), alpha, dtp * fld->eps, b, m_np1, st);
+}
+
+}  // extern "C"

@@ -125,6 +125,33 @@ int llgo_step(const llgo_grid* g, const llgo_opts* o, const double* m_n, double 
 int llgo_step2(const llgo_grid* g, const llgo_opts* o, const double* m_n, const double* m_nm1,
                double alpha, double dt, const double* F, double* m_np1, llgo_stats* st);
 
+/* Full field of the nondimensional model (Sec. 2): exchange coefficient eps,
+ * uniaxial anisotropy q along e1, uniform external field h_ext, and the stray
+ * field of the magnetization (stray != 0). */
+typedef struct {
+  double eps;
+  double q;
+  double h_ext[3];
+  int32_t stray;
+} llgo_field;
+
+/* Cell-averaged demagnetizing tensor between two cuboid cells dx x dy x dz
+ * whose centres differ by (X, Y, Z): N[0..5] = xx, yy, zz, xy, xz, yz.  Newell,
+ * Williams and Dunlop (1993) when max(|X|/dx, |Y|/dy, |Z|/dz) <= 16, the
+ * point-dipole tensor -(V / 4 pi)(3 r r^T / r^2 - I) / r^3 beyond. */
+void llgo_demag_tensor(double X, double Y, double Z, double dx, double dy, double dz, double* N);
+
+/* Stray field h = -sum_j N(x_i - x_j) m_j of a field on the grid (cubic cells
+ * of side h; a 2D grid is one layer of cells). */
+int llgo_stray_field(const llgo_grid* g, const double* m, double* h);
+
+/* One step of the full model: u + dt' eps (m~ x Lap u + alpha m~ x (m~ x Lap u))
+ * = b0 - dt' (m~ x f + alpha m~ x (m~ x f)), f = -q (0, m~2, m~3) + h_ext + h_s(m~),
+ * with BDF1 (m_nm1 NULL: m~ = m^n, b0 = m^n, dt' = dt) or BDF2 (m~ = 2 m^n - m^{n-1},
+ * b0 = (4 m^n - m^{n-1}) / 3, dt' = 2 dt / 3); F adds dt' F to b0. */
+int llgo_step_field(const llgo_grid* g, const llgo_opts* o, const double* m_n, const double* m_nm1, double alpha,
+                    double dt, const llgo_field* fld, const double* F, double* m_np1, llgo_stats* st);
+
 #ifdef __cplusplus
 }
 #endif
