@@ -155,6 +155,9 @@ typedef struct {
   int32_t fine_operator; /* llg_fine_operator: storage of the grid level, see below */
   int32_t arnoldi;      /* llg_arnoldi: orthogonalization of the FGMRES basis, see below */
   int32_t krylov;       /* llg_krylov: the solver; the default is FGMRES with the AMG cycle */
+  int32_t stray_field;  /* 1: reserve the stray-field workspace (zero-padded FFT grids and the
+                           transformed demagnetizing tensor) for llg_step_field; 2*n-1 padded to a
+                           power of two must stay <= 4096 per axis (else UNSUPPORTED) */
 } llg_opts;
 
 typedef struct {
@@ -214,6 +217,34 @@ llg_status llg_create(const llg_grid* grid, const llg_opts* opts, void* d_worksp
  * step (the usual start of a BDF2 run).  The initial guess is m~. */
 llg_status llg_step(llg_ctx* ctx, const double* d_m_n, const double* d_m_nm1, double alpha,
                     double dt, const double* d_forcing, double* d_m_np1, llg_stats* stats);
+
+/* The field of the full model (Sec. 2): m_t = -m x (eps Lap m + f) - alpha m x (m x (eps Lap m + f)),
+ * f = -q (m2 e2 + m3 e3) + h_s + h_ext.  eps > 0 scales the Laplacian; q is the
+ * uniaxial anisotropy along e1; h_ext a uniform external field; stray = 1 adds
+ * the stray field h_s = -N * m of the magnetization, the convolution with the
+ * cell-averaged demagnetizing tensor of the grid's cubic cells of side h
+ * (Newell, Williams and Dunlop 1993; beyond 16 cells the point-dipole tensor;
+ * a 2D grid is one layer of cells).  f is explicit, taken at m~. */
+typedef struct {
+  double eps;
+  double q;
+  double h_ext[3];
+  int32_t stray;
+} llg_field;
+
+/* One step of the full model: the operator of llg_step with dt' eps in place
+ * of dt' (dt' = dt for BDF1, 2 dt / 3 for BDF2) and the right-hand side
+ * b - dt' (m~ x f + alpha m~ x (m~ x f)).  field NULL: llg_step.  stray = 1
+ * needs a context created with opts.stray_field (else INVALID_ARG); the
+ * tensor is transformed on the first such call.  Other arguments and errors
+ * as llg_step. */
+llg_status llg_step_field(llg_ctx* ctx, const double* d_m_n, const double* d_m_nm1, double alpha, double dt,
+                          const llg_field* field, const double* d_forcing, double* d_m_np1, llg_stats* stats);
+
+/* d_h = h_s(d_m), the stray field of a device field (N x 3 each), for a
+ * context created with opts.stray_field (else INVALID_ARG).  Synchronizes the
+ * stream. */
+llg_status llg_stray_field(llg_ctx* ctx, const double* d_m, double* d_h);
 
 /* Assemble the operator for the frozen field d_m_tilde and build the AMG
  * hierarchy values (what llg_step does before the Krylov solve).  Used with

@@ -54,7 +54,21 @@ class Opts(ctypes.Structure):
         ("rebuild_aggregates", ctypes.c_int32), ("kcycle_depth", ctypes.c_int32),
         ("graphs", ctypes.c_int32), ("smoother", ctypes.c_int32), ("scheme", ctypes.c_int32),
         ("fine_operator", ctypes.c_int32), ("arnoldi", ctypes.c_int32), ("krylov", ctypes.c_int32),
+        ("stray_field", ctypes.c_int32),
     ]
+
+
+class Field(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("q", ctypes.c_double), ("h_ext", ctypes.c_double * 3),
+                ("stray", ctypes.c_int32)]
+
+
+def make_field(eps=1.0, q=0.0, h_ext=(0.0, 0.0, 0.0), stray=0) -> Field:
+    f = Field()
+    f.eps, f.q = float(eps), float(q)
+    f.h_ext[0], f.h_ext[1], f.h_ext[2] = (float(v) for v in h_ext)
+    f.stray = int(stray)
+    return f
 
 
 class Stats(ctypes.Structure):
@@ -90,6 +104,9 @@ _lib.llg_level_info.argtypes = [_P, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_
 _lib.llg_get_level.argtypes = [_P, _i32, _P, _P, _P, _i64]
 _lib.llg_get_aggregates.argtypes = [_P, _i32, _P, _i64]
 _lib.llg_get_colours.argtypes = [_P, _i32, _P, _i64, _P]
+_lib.llg_step_field.argtypes = [_P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.POINTER(Field), _P, _P,
+                                ctypes.POINTER(Stats)]
+_lib.llg_stray_field.argtypes = [_P, _P, _P]
 _lib.llg_apply_precond.argtypes = [_P, _P, _P]
 _lib.llg_apply_A.argtypes = [_P, _P, _P]
 _lib.llg_set_kernel_timing.argtypes = [_P, _i32]
@@ -100,7 +117,8 @@ _lib.llg_status_str.restype = ctypes.c_char_p
 _lib.llg_last_error.argtypes = []
 _lib.llg_last_error.restype = ctypes.c_char_p
 for _f in ("llg_workspace_bytes", "llg_create", "llg_step", "llg_setup", "llg_num_levels", "llg_level_info",
-           "llg_get_level", "llg_get_aggregates", "llg_get_colours", "llg_apply_precond", "llg_apply_A", "llg_set_kernel_timing",
+           "llg_get_level", "llg_get_aggregates", "llg_get_colours", "llg_step_field", "llg_stray_field",
+           "llg_apply_precond", "llg_apply_A", "llg_set_kernel_timing",
            "llg_ctx_bytes", "llg_destroy"):
     getattr(_lib, _f).restype = _i32
 
@@ -243,6 +261,34 @@ class Solver:
         if check and s not in (OK, ERR_NOT_CONVERGED):
             raise LLGError(s, "llg_step")
         return out, s, st
+
+    def step_field(self, m_n, alpha: float, dt: float, field: "Field", forcing=None, out=None, m_nm1=None,
+                   check: bool = True):
+        """One step of the full model (anisotropy, external and stray field)."""
+        self._field(m_n, "m_n")
+        if m_nm1 is not None:
+            self._field(m_nm1, "m_nm1")
+        if forcing is not None:
+            self._field(forcing, "forcing")
+        if out is None:
+            out = torch.empty_like(m_n)
+        self._field(out, "out")
+        st = Stats()
+        with torch.cuda.device(self.device):
+            s = _lib.llg_step_field(self._ctx, _ptr(m_n), _ptr(m_nm1), float(alpha), float(dt), ctypes.byref(field),
+                                    _ptr(forcing), _ptr(out), ctypes.byref(st))
+        if check and s not in (OK, ERR_NOT_CONVERGED):
+            raise LLGError(s, "llg_step_field")
+        return out, s, st
+
+    def stray_field(self, m):
+        self._field(m, "m")
+        h = torch.empty_like(m)
+        with torch.cuda.device(self.device):
+            s = _lib.llg_stray_field(self._ctx, _ptr(m), _ptr(h))
+        if s != OK:
+            raise LLGError(s, "llg_stray_field")
+        return h
 
     def setup(self, m_tilde, alpha: float, dt: float) -> int:
         self._field(m_tilde, "m_tilde")

@@ -20,6 +20,7 @@ SOURCES = {
     "k_setup.hip": ["-ffp-contract=off"],
     "k_solve.hip": [],
     "k_krylov.hip": [],
+    "k_field.hip": ["-ffp-contract=off"],
     "engine.hip": [],
 }
 

@@ -166,7 +166,7 @@ struct Level {
 
 struct PlanKey {
   std::tuple<int, int, int, int, int, int, int, int, double, int, int, uint64_t, int, int, int, int, int, int, int,
-             int>
+             int, int>
       k;
   bool operator<(const PlanKey& o) const { return k < o.k; }
 };
@@ -178,7 +178,8 @@ PlanKey plan_key(const llg_grid& g, const llg_opts& o) {
   PlanKey k;
   k.k = std::make_tuple(g.dim, g.n[0], g.n[1], g.n[2], o.npass, o.beta_num, o.beta_den, o.max_coarse,
                         o.stagnation, o.max_levels, o.max_dense, o.agg_salt, o.precision, o.restart,
-                        o.left_scale, o.kcycle_depth, o.smoother, o.scheme, o.fine_operator, o.krylov);
+                        o.left_scale, o.kcycle_depth, o.smoother, o.scheme, o.fine_operator, o.krylov,
+                        o.stray_field);
   return k;
 }
 
@@ -227,7 +228,7 @@ struct llg_ctx {
   hipStream_t cap_st = nullptr;
   bool capturing = false;
   bool graphs_ok = true;
-  hipGraphExec_t setup_graph[4] = {nullptr, nullptr, nullptr, nullptr};  // [forcing + 2 * bdf2]
+  hipGraphExec_t setup_graph[16] = {};  // [forcing + 2 bdf2 + 4 field + 8 stray]
   hipGraphExec_t kb_graph = nullptr;  // one iteration of a Krylov baseline
   double* kb = nullptr;                // device scalars of the Krylov baselines
   std::vector<hipGraphExec_t> pc_graph;  // preconditioner of iteration j
@@ -237,6 +238,11 @@ struct llg_ctx {
   double* min = nullptr;          // device copy of m^n read by the setup graph
   double* fin = nullptr;          // device copy of the forcing
   double* mprv = nullptr;         // device copy of m^{n-1} (BDF2)
+  // stray field: padded grid, transformed tensor (once per context) and work
+  llg::FieldDims fd;
+  double* nhat = nullptr;
+  double2* fwork = nullptr;
+  bool demag_ready = false;
   // timing of one kernel class
   int timed = LLG_KT_NONE;
   std::vector<hipEvent_t> ev;
@@ -600,7 +606,13 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   c.ks.hinv = ar.lazy<double>(R + 2);
   c.ks.coef = ar.lazy<double>(2 * R + 4);
   c.delta = ar.lazy<double>(R + 2);
-  c.prm = ar.lazy<double>(4);
+  c.prm = ar.lazy<double>(8);
+  if (c.opts.stray_field) {
+    c.fd = field_dims(c.grid.n[0], c.grid.n[1], c.grid.n[2]);
+    const int64_t P = c.fd.px * c.fd.py * c.fd.pz;
+    c.nhat = ar.lazy<double>(6 * P);
+    c.fwork = (double2*)ar.lazy<double>(6 * P);
+  }
   c.min = ar.lazy<double>(m);
   c.fin = ar.lazy<double>(m);
   if (c.opts.scheme == LLG_SCHEME_BDF2) c.mprv = ar.lazy<double>(m);
@@ -630,7 +642,8 @@ bool opts_ok(const llg_opts* o) {
          (o->fine_operator == LLG_FINE_BSR || o->fine_operator == LLG_FINE_FACTORED) &&
          (o->arnoldi == LLG_ARNOLDI_CGS2 || o->arnoldi == LLG_ARNOLDI_DCGS2) &&
          (o->krylov == LLG_KRYLOV_FGMRES_AMG || o->krylov == LLG_KRYLOV_GMRES || o->krylov == LLG_KRYLOV_BICGSTAB ||
-          o->krylov == LLG_KRYLOV_TFQMR);
+          o->krylov == LLG_KRYLOV_TFQMR) &&
+         (o->stray_field == 0 || o->stray_field == 1);
 }
 
 // Plan for (grid, opts): cached; computed on the current device.
@@ -678,7 +691,7 @@ std::shared_ptr<Plan> get_plan(const llg_grid& g, const llg_opts& o) {
 // (replayed from the plan), assembly, Galerkin products and the coarsest
 // inverse.  alpha and dt are read from c.prm on the device.
 template <typename T>
-void setup_values(llg_ctx& c, const double* m, const double* mprev, const double* F) {
+void setup_values(llg_ctx& c, const double* m, const double* mprev, const double* F, int field = 0) {
   hipStream_t st = c.st;
   const llg_grid& g = c.grid;
   const bool amg = c.opts.krylov == LLG_KRYLOV_FGMRES_AMG;  // the baselines need only A, b and u0
@@ -697,6 +710,11 @@ void setup_values(llg_ctx& c, const double* m, const double* mprev, const double
     launch_assemble<T>(st, g.n[0], g.n[1], g.n[2], 1.0 / (g.h * g.h), c.prm, c.opts.left_scale,
                        c.opts.x0_is_mn, m, mprev, F, L0.A, c.Aval, (T*)L0.val, c.dinv0, (T*)L0.dinv, c.b, c.u,
                        c.flags, c.Mh, (T*)L0.kf);
+    LCHK();
+  }
+  if (field) {  // explicit field terms of the right-hand side (field 2: with the stray field)
+    if (field == 2) launch_stray(st, c.fd, m, mprev, c.nhat, c.fwork);
+    launch_field_rhs(st, c.N, c.prm, m, mprev, c.fd, field == 2 ? c.fwork : nullptr, c.b);
     LCHK();
   }
   if (!amg) return;
@@ -772,29 +790,43 @@ hipGraphExec_t try_capture(llg_ctx& c, Fn body) {
   }
 }
 
-// alpha and the time-step factor of the system: dt (BDF1) or 2 dt / 3 (BDF2)
-void write_params(llg_ctx& c, double alpha, double dt, bool bdf2 = false) {
+// alpha, the time-step factors dt' = dt (BDF1) or 2 dt / 3 (BDF2) of the
+// right-hand side and dt' eps of the operator, and the field parameters
+void write_params(llg_ctx& c, double alpha, double dt, bool bdf2 = false, const llg_field* fld = nullptr) {
+  const double dtp = bdf2 ? (2.0 * dt) / 3.0 : dt;
   c.hprm[0] = alpha;
-  c.hprm[1] = bdf2 ? (2.0 * dt) / 3.0 : dt;
-  HIPX(hipMemcpyAsync(c.prm, c.hprm, 2 * sizeof(double), hipMemcpyHostToDevice, c.st));
+  c.hprm[1] = fld ? dtp * fld->eps : dtp;
+  c.hprm[2] = dtp;
+  c.hprm[3] = fld ? fld->q : 0.0;
+  for (int k = 0; k < 3; ++k) c.hprm[4 + k] = fld ? fld->h_ext[k] : 0.0;
+  c.hprm[7] = 0.0;
+  HIPX(hipMemcpyAsync(c.prm, c.hprm, 8 * sizeof(double), hipMemcpyHostToDevice, c.st));
 }
 
 // The setup of one step from the internal copies of m^n (and F).
 template <typename T>
-void run_setup(llg_ctx& c, bool forcing, bool bdf2 = false) {
+void run_setup(llg_ctx& c, bool forcing, bool bdf2 = false, int field = 0) {
   const double* F = forcing ? c.fin : nullptr;
   const double* mp = bdf2 ? c.mprv : nullptr;
   if (use_graphs(c)) {
-    hipGraphExec_t& gx = c.setup_graph[(forcing ? 1 : 0) + (bdf2 ? 2 : 0)];
-    if (!gx) gx = try_capture(c, [&]() { setup_values<T>(c, c.min, mp, F); });
+    hipGraphExec_t& gx = c.setup_graph[(forcing ? 1 : 0) + (bdf2 ? 2 : 0) + (field ? 4 : 0) + (field == 2 ? 8 : 0)];
+    if (!gx) gx = try_capture(c, [&]() { setup_values<T>(c, c.min, mp, F, field); });
     if (gx) {
       HIPX(hipGraphLaunch(gx, c.st));
       c.setup_done = true;
       return;
     }
   }
-  setup_values<T>(c, c.min, mp, F);
+  setup_values<T>(c, c.min, mp, F, field);
   c.setup_done = true;
+}
+
+// the transformed demagnetizing tensor, once per context (eager)
+void demag_prepare(llg_ctx& c) {
+  if (c.demag_ready) return;
+  launch_demag_setup(c.st, c.fd, c.grid.h, c.fwork, c.nhat);
+  LCHK();
+  c.demag_ready = true;
 }
 
 // ------------------------------------------------------------------ products
@@ -1294,7 +1326,7 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 
 template <typename T>
 llg_status run_step(llg_ctx& c, const double* m_n, const double* m_nm1, double alpha, double dt, const double* F,
-                    double* m_np1, llg_stats* stats) {
+                    double* m_np1, llg_stats* stats, const llg_field* fld = nullptr) {
   const auto t0 = std::chrono::steady_clock::now();
   c.kernel_ms = 0;
   c.launches = 0;
@@ -1304,10 +1336,12 @@ llg_status run_step(llg_ctx& c, const double* m_n, const double* m_nm1, double a
   HIPX(hipMemcpyAsync(c.min, m_n, fb, hipMemcpyDeviceToDevice, c.st));
   if (F) HIPX(hipMemcpyAsync(c.fin, F, fb, hipMemcpyDeviceToDevice, c.st));
   if (bdf2) HIPX(hipMemcpyAsync(c.mprv, m_nm1, fb, hipMemcpyDeviceToDevice, c.st));
-  write_params(c, alpha, dt, bdf2);
+  write_params(c, alpha, dt, bdf2, fld);
   launch_fill_i32(c.st, c.flags, 1, 0);
   LCHK();
-  run_setup<T>(c, F != nullptr, bdf2);
+  const int field = fld ? (fld->stray ? 2 : 1) : 0;
+  if (field == 2) demag_prepare(c);
+  run_setup<T>(c, F != nullptr, bdf2, field);
   HIPX(hipStreamSynchronize(c.st));
   const double t_setup = ms_since(t0);
   SolveOut so = c.opts.krylov == LLG_KRYLOV_BICGSTAB ? bicgstab(c)
@@ -1403,6 +1437,7 @@ void llg_default_opts(llg_opts* o) {
   o->fine_operator = LLG_FINE_BSR;
   o->arnoldi = LLG_ARNOLDI_DCGS2;
   o->krylov = LLG_KRYLOV_FGMRES_AMG;
+  o->stray_field = 0;
 }
 
 // combinations the library does not implement
@@ -1410,6 +1445,10 @@ static bool supported(const llg_grid* grid, const llg_opts* opts) {
   if (grid->bc != LLG_BC_NEUMANN) return false;
   if (opts->fine_operator == LLG_FINE_FACTORED && !opts->left_scale) return false;
   if (opts->krylov != LLG_KRYLOV_FGMRES_AMG && opts->precision != LLG_PREC_FP64) return false;
+  if (opts->stray_field) {  // padded FFT lengths within the one-workgroup transform
+    const FieldDims f = field_dims(grid->n[0], grid->n[1], grid->n[2]);
+    if (std::max(f.px, std::max(f.py, f.pz)) > FFT_MAX_LEN) return false;
+  }
   return true;
 }
 
@@ -1446,11 +1485,12 @@ llg_status llg_create(const llg_grid* grid, const llg_opts* opts, void* d_worksp
     c->omega = opts->omega > 0 ? opts->omega : (grid->dim == 2 ? 4.0 / 5.0 : 6.0 / 7.0);
     HIPX(hipHostMalloc((void**)&c->host, sizeof(double) * 16, hipHostMallocDefault));
     HIPX(hipHostMalloc((void**)&c->hflags, sizeof(int32_t) * 4, hipHostMallocDefault));
-    HIPX(hipHostMalloc((void**)&c->hprm, sizeof(double) * 4, hipHostMallocDefault));
+    HIPX(hipHostMalloc((void**)&c->hprm, sizeof(double) * 8, hipHostMallocDefault));
     HIPX(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
     c->it_graph.assign(opts->restart, nullptr);
     c->pc_graph.assign(opts->restart, nullptr);
     init_kernel_attributes();
+    init_field_attributes();
     Arena ar;
     ar.mode = Mode::REPLAY;
     ar.plan = plan.get();
@@ -1526,6 +1566,48 @@ llg_status llg_step(llg_ctx* ctx, const double* d_m_n, const double* d_m_nm1, do
     if (ctx->opts.precision == LLG_PREC_FP32_AMG)
       return run_step<float>(*ctx, d_m_n, prev, alpha, dt, d_forcing, d_m_np1, stats);
     return run_step<double>(*ctx, d_m_n, prev, alpha, dt, d_forcing, d_m_np1, stats);
+  });
+}
+
+llg_status llg_step_field(llg_ctx* ctx, const double* d_m_n, const double* d_m_nm1, double alpha, double dt,
+                          const llg_field* field, const double* d_forcing, double* d_m_np1, llg_stats* stats) {
+  if (!field) return llg_step(ctx, d_m_n, d_m_nm1, alpha, dt, d_forcing, d_m_np1, stats);
+  llg_status s = check_ctx(ctx);
+  if (s != LLG_OK) return s;
+  if (!(field->eps > 0) || !std::isfinite(field->eps) || !std::isfinite(field->q) ||
+      !std::isfinite(field->h_ext[0]) || !std::isfinite(field->h_ext[1]) || !std::isfinite(field->h_ext[2]) ||
+      (field->stray && !ctx->opts.stray_field))
+    return LLG_ERR_INVALID_ARG;
+  if (!d_m_n || !d_m_np1 || !aligned8(d_m_n) || !aligned8(d_m_np1) || (d_forcing && !aligned8(d_forcing)))
+    return LLG_ERR_INVALID_ARG;
+  if (!(dt > 0) || !std::isfinite(dt) || !(alpha >= 0) || !std::isfinite(alpha)) return LLG_ERR_INVALID_ARG;
+  const size_t fb = sizeof(double) * 3 * (size_t)ctx->N;
+  auto overlap = [fb](const void* x, const void* y) {
+    const char* a0 = (const char*)x;
+    const char* b0 = (const char*)y;
+    return a0 < b0 + fb && b0 < a0 + fb;
+  };
+  if (overlap(d_m_n, d_m_np1)) return LLG_ERR_INVALID_ARG;
+  const double* prev = ctx->opts.scheme == LLG_SCHEME_BDF2 ? d_m_nm1 : nullptr;
+  if (prev && (!aligned8(prev) || overlap(prev, d_m_np1))) return LLG_ERR_INVALID_ARG;
+  return guard([&]() -> llg_status {
+    if (ctx->opts.precision == LLG_PREC_FP32_AMG)
+      return run_step<float>(*ctx, d_m_n, prev, alpha, dt, d_forcing, d_m_np1, stats, field);
+    return run_step<double>(*ctx, d_m_n, prev, alpha, dt, d_forcing, d_m_np1, stats, field);
+  });
+}
+
+llg_status llg_stray_field(llg_ctx* ctx, const double* d_m, double* d_h) {
+  llg_status s = check_ctx(ctx);
+  if (s != LLG_OK) return s;
+  if (!ctx->opts.stray_field || !d_m || !d_h || !aligned8(d_m) || !aligned8(d_h)) return LLG_ERR_INVALID_ARG;
+  return guard([&]() -> llg_status {
+    demag_prepare(*ctx);
+    launch_stray(ctx->st, ctx->fd, d_m, nullptr, ctx->nhat, ctx->fwork);
+    launch_stray_out(ctx->st, ctx->fd, ctx->fwork, d_h);
+    LCHK();
+    HIPX(hipStreamSynchronize(ctx->st));
+    return LLG_OK;
   });
 }
 

@@ -707,7 +707,7 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    b[3 * p + c] = F ? bb[c] + dt * F[3 * p + c] : bb[c];
+    b[3 * p + c] = F ? bb[c] + prm[2] * F[3 * p + c] : bb[c];
     u[3 * p + c] = x0_is_mn ? mt[c] : 0.0;
   }
 }

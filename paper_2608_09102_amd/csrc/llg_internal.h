@@ -104,8 +104,9 @@ void launch_member_sort(hipStream_t st, int64_t nc, const int32_t* mptr, int32_t
 // assembly of the fine operator (FP64 A) and the scaled level-0 operator,
 // the right-hand side b and the initial guess u; the frozen field is m
 // (mprev == NULL) or 2 m - mprev (BDF2, b = (4 m - mprev) / 3 + dt F).
-// prm[0] = alpha, prm[1] = the time-step factor (device memory, so captured
-// graphs stay valid)
+// prm[0] = alpha, prm[1] = the time-step factor of the operator, prm[2] = the
+// factor of the forcing and of the explicit field terms (device memory, so
+// captured graphs stay valid)
 // Factored form (Mh != NULL): the per-node blocks Mh and K are written
 // instead of the sliced-ELL values Aval and Lval.
 template <typename T>
@@ -217,6 +218,26 @@ void launch_dot2(hipStream_t st, int64_t m, const double* x0, const double* y0, 
 void launch_copy(hipStream_t st, int64_t m, const double* x, double* y);
 void launch_scale_copy(hipStream_t st, int64_t m, const double* x, const double* s, double* y);
 void launch_kb_step(hipStream_t st, const double* part, int64_t nparts, int op, double* kb, double* host);
+
+// Full field (anisotropy, external and stray field).  The stray field is a
+// cyclic convolution on the grid zero-padded to P = pow2 >= 2n - 1 per axis
+// (P = 1 along z for a 2D grid); work holds three complex P-arrays, nhat the
+// six real transformed tensor components.
+constexpr int64_t FFT_MAX_LEN = 4096;
+struct FieldDims {
+  int64_t nx = 0, ny = 0, nz = 0, px = 0, py = 0, pz = 0;
+};
+int64_t next_pow2(int64_t v);
+FieldDims field_dims(int nx, int ny, int nz);
+void init_field_attributes();
+void launch_demag_setup(hipStream_t st, FieldDims f, double h, double2* work, double* nhat);
+// work = the transformed-back product N^ M^ of m~ (m, or 2 m - mprev)
+void launch_stray(hipStream_t st, FieldDims f, const double* m, const double* mprev, const double* nhat,
+                  double2* work);
+void launch_stray_out(hipStream_t st, FieldDims f, const double2* work, double* h);
+// b -= dt' (m~ x f + alpha m~ x (m~ x f)); work NULL: no stray field
+void launch_field_rhs(hipStream_t st, int64_t N, const double* prm, const double* m, const double* mprev,
+                      FieldDims f, const double2* work, double* b);
 
 // outer Krylov kernels (FP64)
 template <typename TZ>
