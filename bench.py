@@ -14,6 +14,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -51,6 +52,8 @@ def parse():
     p.add_argument("--baselines", action="store_true",
                    help="compare the unpreconditioned Krylov solvers the paper uses (GMRES, BiCGstab, TFQMR, "
                         "max 1000 iterations) with the AMG-preconditioned FGMRES on the workload")
+    p.add_argument("--field", action="store_true",
+                   help="full model: exchange only vs Permalloy-like anisotropy, external and stray field")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain device copy of known size (for the PMC byte counters)")
     return p.parse_args()
@@ -220,6 +223,82 @@ def baselines_bench(a, llg, torch, w):
     print(json.dumps(out), flush=True)
 
 
+# reduced Permalloy parameters for a 1 um body (exchange constant 1.3e-11 J/m,
+# anisotropy 100 J/m^3, saturation 8e5 A/m) and a weak in-plane external field
+MU0_MS2 = 4e-7 * math.pi * 8.0e5 ** 2
+PERMALLOY = dict(eps=1.3e-11 / (MU0_MS2 * 1e-12), q=100.0 / MU0_MS2, h_ext=(0.01, 0.0, 0.0))
+
+
+def stray_bytes(dim: int, N: int, P: int) -> float:
+    """Algorithmic HBM bytes of one stray-field evaluation: padding (read m,
+    write 3 complex planes), a read and a write of the 3 planes per FFT pass
+    (dim forward + dim inverse passes), the pointwise product (read the 6 real
+    tensor planes, read and write the 3 planes), and the cropped output."""
+    planes = 3 * 16.0 * P
+    return (24.0 * N + planes) + 2 * dim * 2 * planes + (48.0 * P + 2 * planes) + (planes * N / P + 24.0 * N)
+
+
+def field_bench(a, llg, torch, w, form: str, kdepth: int):
+    """Per variant of the model: ms/step and iterations/step over `steps` steps
+    after `warmup` steps, same main form; then the stray-field evaluation
+    alone (host-timed calls, each synchronizing)."""
+    variants = [("exchange_only", None), ("anisotropy_external", dict(PERMALLOY, stray=0)),
+                ("anisotropy_external_stray", dict(PERMALLOY, stray=1))]
+    out = {"metric": "full-model step time, %s" % form, "workload": w.name, "unknowns": w.unknowns,
+           "rtol": w.rtol, "steps": a.steps, "warmup": a.warmup, "field": dict(PERMALLOY), "variants": {}}
+    for name, kw in variants:
+        S = llg.Solver(llg.make_grid(w.dim, w.n), llg.default_opts(rtol=w.rtol, precision=form,
+                                                                  kcycle_depth=kdepth, stray_field=1))
+        fld = llg.make_field(**kw) if kw else None
+        bufs = [torch.from_numpy(w.m0()).cuda(), None]
+        bufs[1] = torch.empty_like(bufs[0])
+        cur = 0
+
+        def one():
+            nonlocal cur
+            if fld is None:
+                _, s, st = S.step(bufs[cur], w.alpha, w.dt, out=bufs[1 - cur])
+            else:
+                _, s, st = S.step_field(bufs[cur], w.alpha, w.dt, fld, out=bufs[1 - cur])
+            if s != llg.OK:
+                raise RuntimeError("%s: %s" % (name, llg.status_str(s)))
+            cur = 1 - cur
+            return st
+        for _ in range(a.warmup):
+            one()
+        its = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            its.append(one().iters)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out["variants"][name] = {"ms_per_step": 1e3 * el / a.steps, "iters_per_step": sum(its) / len(its),
+                                 "iters": its}
+        log("  %-26s %8.2f ms/step %6.1f its/step" % (name, 1e3 * el / a.steps, sum(its) / len(its)))
+        if name == "anisotropy_external_stray":
+            m = bufs[cur]
+            for _ in range(3):
+                S.stray_field(m)
+            reps = 20
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                S.stray_field(m)
+            ms = 1e3 * (time.perf_counter() - t0) / reps
+            P = 1
+            for n in ([w.n] * w.dim):
+                P *= 1 << (2 * n - 2).bit_length()
+            nb = stray_bytes(w.dim, w.nodes, P)
+            out["stray_field"] = {"ms_per_call": ms, "padded_cells": P, "algorithmic_bytes": nb,
+                                  "GBps_host_timed": nb / ms / 1e6}
+            log("  stray field alone: %.3f ms/call, %.0f GB/s host-timed over %.2f GB" % (ms, nb / ms / 1e6, nb / 1e9))
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def serve_bench(a):
     """Serving workload: Poisson arrivals (8/s) of 20-step simulations, 2D n in
     128..2048 or 3D n in 32..192, FP32-AMG, admission by device footprint."""
@@ -279,6 +358,10 @@ def main():
         w.alpha = a.alpha
     if a.baselines:
         baselines_bench(a, llg, torch, w)
+        return
+    if a.field:
+        f0 = a.forms.split(",")[0].split(":")
+        field_bench(a, llg, torch, w, f0[0], int(f0[1]) if len(f0) > 1 and f0[1] else 0)
         return
     forms = []
     for f in a.forms.split(","):

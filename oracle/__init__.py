@@ -115,6 +115,7 @@ def lib() -> ctypes.CDLL:
                                  ctypes.c_double, P, P, ctypes.POINTER(Stats)]
         L.llgo_demag_tensor.argtypes = [ctypes.c_double] * 6 + [P]
         L.llgo_stray_field.argtypes = [ctypes.POINTER(Grid), P, P]
+        L.llgo_stray_field_at.argtypes = [ctypes.POINTER(Grid), P, P, ctypes.c_int64, P]
         L.llgo_step_field.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), P, P, ctypes.c_double,
                                       ctypes.c_double, ctypes.POINTER(Field), P, P, ctypes.POINTER(Stats)]
         _lib = L
@@ -326,6 +327,16 @@ def stray_field(grid: Grid, m: np.ndarray) -> np.ndarray:
     m = np.ascontiguousarray(m, dtype=np.float64).reshape(N, 3)
     h = np.empty_like(m)
     assert lib().llgo_stray_field(ctypes.byref(grid), _p(m), _p(h)) == 0
+    return h
+
+
+def stray_field_at(grid: Grid, m: np.ndarray, cells) -> np.ndarray:
+    """Stray field at the given cell indices only, [len(cells), 3]."""
+    N = grid.n[0] * grid.n[1] * grid.n[2]
+    m = np.ascontiguousarray(m, dtype=np.float64).reshape(N, 3)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    h = np.empty((len(cells), 3), np.float64)
+    assert lib().llgo_stray_field_at(ctypes.byref(grid), _p(m), _p(cells), len(cells), _p(h)) == 0
     return h
 
 

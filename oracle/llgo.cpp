@@ -1288,6 +1288,27 @@ int llgo_stray_field(const llgo_grid* g, const double* m, double* h) {
   return LLGO_OK;
 }
 
+int llgo_stray_field_at(const llgo_grid* g, const double* m, const int64_t* cells, int64_t count, double* h) {
+  if (!grid_ok(g) || !m || (count > 0 && (!cells || !h)) || count < 0) return LLGO_ERR_ARG;
+  const int64_t nx = g->n[0], ny = g->n[1], N = num_nodes(*g);
+  for (int64_t s = 0; s < count; ++s) {
+    const int64_t p = cells[s];
+    if (p < 0 || p >= N) return LLGO_ERR_ARG;
+    const int64_t i = p % nx, j = (p / nx) % ny, k = p / (nx * ny);
+    double acc[3] = {0.0, 0.0, 0.0}, t[6];
+    for (int64_t q = 0; q < N; ++q) {
+      const int64_t i2 = q % nx, j2 = (q / nx) % ny, k2 = q / (nx * ny);
+      demag((double)(i - i2) * g->h, (double)(j - j2) * g->h, (double)(k - k2) * g->h, g->h, g->h, g->h, t);
+      const double* mq = m + 3 * q;
+      acc[0] += t[0] * mq[0] + t[3] * mq[1] + t[4] * mq[2];
+      acc[1] += t[3] * mq[0] + t[1] * mq[1] + t[5] * mq[2];
+      acc[2] += t[4] * mq[0] + t[5] * mq[1] + t[2] * mq[2];
+    }
+    for (int c = 0; c < 3; ++c) h[3 * s + c] = -acc[c];
+  }
+  return LLGO_OK;
+}
+
 int llgo_step_field(const llgo_grid* g, const llgo_opts* o, const double* m_n, const double* m_nm1, double alpha,
                     double dt, const llgo_field* fld, const double* F, double* m_np1, llgo_stats* st) {
   if (!grid_ok(g) || !opts_ok(o) || !m_n || !m_np1 || !fld) return LLGO_ERR_ARG;

@@ -145,6 +145,11 @@ void llgo_demag_tensor(double X, double Y, double Z, double dx, double dy, doubl
  * of side h; a 2D grid is one layer of cells). */
 int llgo_stray_field(const llgo_grid* g, const double* m, double* h);
 
+/* The same sum at `count` cells only (h[count][3]): each cell's field summed
+ * directly over every cell of the grid, for grids too large for the full
+ * O(N^2) form. */
+int llgo_stray_field_at(const llgo_grid* g, const double* m, const int64_t* cells, int64_t count, double* h);
+
 /* One step of the full model: u + dt' eps (m~ x Lap u + alpha m~ x (m~ x Lap u))
  * = b0 - dt' (m~ x f + alpha m~ x (m~ x f)), f = -q (0, m~2, m~3) + h_ext + h_s(m~),
  * with BDF1 (m_nm1 NULL: m~ = m^n, b0 = m^n, dt' = dt) or BDF2 (m~ = 2 m^n - m^{n-1},

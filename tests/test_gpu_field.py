@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import llg_inputs as I
+from helpers import laplacian
 
 pytestmark = pytest.mark.gpu
 
@@ -127,3 +128,68 @@ def test_default_field_is_plain_step(gpu):
     b, s2, _ = S.step_field(_cuda(m), alpha, dt, gpu.make_field())
     assert s1 == s2 == gpu.OK
     assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+# Permalloy-like reduced parameters of the model (exchange length over a 1 um
+# body, anisotropy over the demagnetizing energy density) and a weak in-plane
+# external field
+PERMALLOY = dict(eps=1.3e-11 / (4e-7 * np.pi * 8.0e5 ** 2 * 1e-12), q=100.0 / (4e-7 * np.pi * 8.0e5 ** 2),
+                 h_ext=(0.01, 0.0, 0.0))
+
+
+def _samples(n, N, count, seed):
+    """Corner, edge and face cells, then seeded random cells."""
+    nx, ny = n[0], n[1]
+    fixed = [0, nx - 1, nx * (ny - 1), N - 1, nx // 2, (ny // 2) * nx, N // 2]
+    rng = np.random.default_rng(seed)
+    return np.array(fixed + list(rng.integers(0, N, count - len(fixed))), dtype=np.int64)
+
+
+@pytest.mark.parametrize("name", ["rough2d_1024", "rough3d_128"])
+def test_stray_field_full_size_sampled(gpu, orc, name):
+    """At the workloads' full sizes: the FFT stray field of m0 at sampled cells
+    against the oracle's direct sum over every cell."""
+    w = I.WORKLOADS[name]
+    n = (w.n, w.n, w.n if w.dim == 3 else 1)
+    N = int(np.prod(n))
+    say("[stray_field_full_size]", name)
+    m = w.m0()
+    S = gpu.Solver(gpu.make_grid(w.dim, w.n), gpu.default_opts(stray_field=1))
+    h = S.stray_field(_cuda(m)).cpu().numpy()
+    cells = _samples(n, N, 24 if w.dim == 2 else 12, seed=7)
+    ref = orc.stray_field_at(orc.make_grid(w.dim, w.n), m, cells)
+    d = np.abs(h[cells] - ref).max()
+    say("  max|h| %.3e diff %.2e" % (np.abs(ref).max(), d))
+    assert d <= 1e-10 * np.abs(ref).max()
+
+
+def test_step_field_full_size_residual(gpu, orc):
+    """At 1024 x 1024 with the Permalloy-like field and the stray field: the
+    unprojected GPU step solves the scheme with the full field (scipy
+    Laplacian, numpy cross products, the stray field checked above): the
+    relative residual ||b - A u|| / ||b|| is within 100 x the solver's
+    tolerance (its test is on the block-scaled residual), and the same u
+    leaves a large residual in the scheme without the field terms."""
+    w = I.WORKLOADS["rough2d_1024"]
+    m = w.m0()
+    rtol = 1e-10
+    S = gpu.Solver(gpu.make_grid(2, w.n), gpu.default_opts(rtol=rtol, project=0, stray_field=1))
+    out, s, st = S.step_field(_cuda(m), w.alpha, w.dt, gpu.make_field(stray=1, **PERMALLOY))
+    assert s == gpu.OK
+    u = out.cpu().numpy()
+    hs = S.stray_field(_cuda(m)).cpu().numpy()
+    eps, dt, alpha = PERMALLOY["eps"], w.dt, w.alpha
+    f = np.array(PERMALLOY["h_ext"]) - PERMALLOY["q"] * np.stack([0 * m[:, 0], m[:, 1], m[:, 2]], 1) + hs
+    L = laplacian(2, w.n, 1.0 / w.n)
+
+    def rel(eps, f):
+        Lu = L @ u
+        c1 = np.cross(m, eps * Lu)
+        Au = u + dt * (c1 + alpha * np.cross(m, c1))
+        c2 = np.cross(m, f)
+        b = m - dt * (c2 + alpha * np.cross(m, c2))
+        return np.linalg.norm(b - Au) / np.linalg.norm(b)
+
+    r_field, r_plain = rel(eps, f), rel(1.0, 0.0 * f)
+    say("  iters %d, relative residual %.2e (without the field terms %.2e)" % (st.iters, r_field, r_plain))
+    assert r_field <= 100 * rtol and r_plain >= 1e-3

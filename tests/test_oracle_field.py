@@ -124,3 +124,18 @@ def test_field_scheme_identity(orc, bdf2):
     lhs = (3 * u - 4 * m + mp) / (2 * dt) if bdf2 else (u - m) / dt
     rhs = -np.cross(mt, hx) - alpha * np.cross(mt, np.cross(mt, hx))
     assert np.abs(lhs - rhs).max() <= 1e-9 * (np.abs(lhs).max() + np.abs(rhs).max())
+
+
+@pytest.mark.parametrize("dim,n", [(2, (13, 9)), (3, (5, 4, 6))])
+def test_stray_field_at_is_the_full_sum(orc, dim, n):
+    """The pointwise form sums the same terms in the same order as the full
+    form: equal to the bit at every cell, so the pins of the full form carry
+    over to the sampled one used at sizes the full form cannot reach."""
+    N = int(np.prod(n))
+    rng = np.random.default_rng(5)
+    m = rng.standard_normal((N, 3))
+    g = orc.make_grid(dim, n)
+    full = orc.stray_field(g, m)
+    cells = np.array([0, N - 1, N // 2, 1, n[0] - 1] + list(rng.integers(0, N, 5)))
+    assert np.array_equal(orc.stray_field_at(g, m, cells), full[cells])
+    assert orc.stray_field_at(g, m, []).shape == (0, 3)
