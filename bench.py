@@ -229,13 +229,21 @@ MU0_MS2 = 4e-7 * math.pi * 8.0e5 ** 2
 PERMALLOY = dict(eps=1.3e-11 / (MU0_MS2 * 1e-12), q=100.0 / MU0_MS2, h_ext=(0.01, 0.0, 0.0))
 
 
-def stray_bytes(dim: int, N: int, P: int) -> float:
-    """Algorithmic HBM bytes of one stray-field evaluation: padding (read m,
-    write 3 complex planes), a read and a write of the 3 planes per FFT pass
-    (dim forward + dim inverse passes), the pointwise product (read the 6 real
-    tensor planes, read and write the 3 planes), and the cropped output."""
-    planes = 3 * 16.0 * P
-    return (24.0 * N + planes) + 2 * dim * 2 * planes + (48.0 * P + 2 * planes) + (planes * N / P + 24.0 * N)
+def stray_bytes(n, pdims) -> float:
+    """Algorithmic HBM bytes of one stray-field evaluation as the library does
+    it: m~ packed into two complex planes on the n-box; forward line passes
+    that read only lines holding data and write the padded extent; the
+    product with the 6 real tensor planes (read 2 planes, write 2 planes);
+    inverse passes that write only the n-box; the cropped output."""
+    nx, ny, nz = n
+    px, py, pz = pdims
+    N, P = nx * ny * nz, px * py * pz
+    c = 16.0 * 2  # one complex value in each of the two planes
+    passes = [(N, px * ny * nz), (px * ny * nz, px * py * nz)]  # forward x, y: (read, write)
+    if pz > 1:
+        passes.append((px * py * nz, P))
+    fwd = sum(r + w for r, w in passes)
+    return (24.0 * N + c * N) + 2 * c * fwd + (c * P + 48.0 * P + c * P) + (c * N + 24.0 * N)
 
 
 def field_bench(a, llg, torch, w, form: str, kdepth: int):
@@ -286,10 +294,10 @@ def field_bench(a, llg, torch, w, form: str, kdepth: int):
             for _ in range(reps):
                 S.stray_field(m)
             ms = 1e3 * (time.perf_counter() - t0) / reps
-            P = 1
-            for n in ([w.n] * w.dim):
-                P *= 1 << (2 * n - 2).bit_length()
-            nb = stray_bytes(w.dim, w.nodes, P)
+            n3 = (w.n, w.n, w.n if w.dim == 3 else 1)
+            pd = tuple(1 << (2 * k - 2).bit_length() if k > 1 else 1 for k in n3)
+            P = pd[0] * pd[1] * pd[2]
+            nb = stray_bytes(n3, pd)
             out["stray_field"] = {"ms_per_call": ms, "padded_cells": P, "algorithmic_bytes": nb,
                                   "GBps_host_timed": nb / ms / 1e6}
             log("  stray field alone: %.3f ms/call, %.0f GB/s host-timed over %.2f GB" % (ms, nb / ms / 1e6, nb / 1e9))

@@ -611,7 +611,7 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
     c.fd = field_dims(c.grid.n[0], c.grid.n[1], c.grid.n[2]);
     const int64_t P = c.fd.px * c.fd.py * c.fd.pz;
     c.nhat = ar.lazy<double>(6 * P);
-    c.fwork = (double2*)ar.lazy<double>(6 * P);
+    c.fwork = (double2*)ar.lazy<double>(4 * P);  // two packed complex planes
   }
   c.min = ar.lazy<double>(m);
   c.fin = ar.lazy<double>(m);
