@@ -35,7 +35,8 @@ def parse():
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="rough2d_1024")
-    p.add_argument("--forms", default="fp64:1,fp32_amg:1,fp64:0,fp64:1:jacobi:factored,fp32_amg:1:jacobi:factored",
+    p.add_argument("--forms", default="fp64:1:jacobi:factored,fp32_amg:1:jacobi:factored,fp64:1,fp32_amg:1,"
+                                      "fp64:0:jacobi:factored",
                    help="comma list of precision:kcycle_depth[:smoother[:operator]] (depth 0 = V-cycle; "
                         "smoother jacobi or mcgs, default jacobi; grid-level operator bsr or factored, "
                         "default bsr); the first gives `value`")

@@ -82,6 +82,51 @@ __global__ void k_scan_top(int32_t* bsum, int64_t nb, int32_t* total) {
   if (threadIdx.x == 0) *total = carry;
 }
 
+// Whole scan in one workgroup of 1024 threads for short arrays (n <= 16384):
+// each thread sums its run of up to 16 items, the runs are scanned by wave
+// shuffles and the 16 wave totals in LDS, then each thread writes its run.
+// In place is fine: every thread reads its items before any are written.
+constexpr int SCAN1_T = 1024, SCAN1_ITEMS = 16;
+__global__ void __launch_bounds__(SCAN1_T) k_scan_single(const int32_t* in, int32_t* out, int64_t n,
+                                                          int32_t* total) {
+  __shared__ int32_t wsum[SCAN1_T / 64];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t per = (n + SCAN1_T - 1) / SCAN1_T;
+  const int64_t base = (int64_t)t * per;
+  int32_t v[SCAN1_ITEMS];
+  int32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN1_ITEMS; ++k) {
+    v[k] = (k < per && base + k < n) ? in[base + k] : 0;
+    sum += v[k];
+  }
+  int32_t incl = sum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  if (wv == 0) {
+    int32_t x = lane < SCAN1_T / 64 ? wsum[lane] : 0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane < SCAN1_T / 64) wsum[lane] = x;  // inclusive over waves
+  }
+  __syncthreads();
+  int32_t ex = incl - sum + (wv > 0 ? wsum[wv - 1] : 0);
+#pragma unroll
+  for (int k = 0; k < SCAN1_ITEMS; ++k) {
+    if (k < per && base + k < n) out[base + k] = ex;
+    ex += v[k];
+  }
+  if (t == SCAN1_T - 1) *total = ex;
+}
+
 __global__ void k_scan_down(const int32_t* in, int32_t* out, int64_t n, const int32_t* bsum) {
   __shared__ int32_t sh[SCAN_T];
   const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
@@ -344,7 +389,67 @@ __global__ void k_cg_count(int64_t nc, const int32_t* lead, const int32_t* mate,
 }
 
 // Coarse graph row I: (agg(j), w) over the rows of the (one or two) members,
-// sorted by coarse column, duplicates summed, the diagonal dropped.
+// sorted by coarse column, duplicates summed, the diagonal dropped.  Rows of
+// up to 32 candidates are sorted in registers by a bitonic network (their
+// padding sorts last); longer rows by insertion into their output range.
+template <int CM>
+__device__ inline int32_t cg_row_small(int32_t I, int32_t c, int32_t ka, int32_t na, int32_t kb,
+                                       const int32_t* __restrict__ gci, const int32_t* __restrict__ gw,
+                                       const int32_t* __restrict__ agg, int32_t* cj, int32_t* cw, int32_t o) {
+  int32_t J[CM], W[CM];
+#pragma unroll
+  for (int e = 0; e < CM; ++e) {
+    J[e] = 0x7fffffff;
+    W[e] = 0;
+    if (e < c) {
+      const int32_t k = e < na ? ka + e : kb + (e - na);
+      J[e] = agg[gci[k]];
+      W[e] = gw[k];
+    }
+  }
+#pragma unroll
+  for (int k = 2; k <= CM; k <<= 1) {
+#pragma unroll
+    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+#pragma unroll
+      for (int e = 0; e < CM; ++e) {
+        const int f = e ^ jj;
+        if (f > e) {
+          const bool up = (e & k) == 0;
+          const bool sw = up ? (J[e] > J[f]) : (J[e] < J[f]);
+          const int32_t j0 = J[e], j1 = J[f], w0 = W[e], w1 = W[f];
+          J[e] = sw ? j1 : j0;
+          J[f] = sw ? j0 : j1;
+          W[e] = sw ? w1 : w0;
+          W[f] = sw ? w0 : w1;
+        }
+      }
+    }
+  }
+  int32_t u = 0, cur = -1, sum = 0;
+#pragma unroll
+  for (int e = 0; e < CM; ++e) {
+    if (e < c && J[e] != I) {
+      if (u > 0 && J[e] == cur) {
+        sum += W[e];
+      } else {
+        if (u > 0) {
+          cj[o + u - 1] = cur;
+          cw[o + u - 1] = sum;
+        }
+        cur = J[e];
+        sum = W[e];
+        ++u;
+      }
+    }
+  }
+  if (u > 0) {
+    cj[o + u - 1] = cur;
+    cw[o + u - 1] = sum;
+  }
+  return u;
+}
+
 __global__ void k_cg_fill(int64_t nc, const int32_t* lead, const int32_t* mate, const int32_t* grp,
                           const int32_t* gci, const int32_t* gw, const int32_t* agg,
                           const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt) {
@@ -352,6 +457,21 @@ __global__ void k_cg_fill(int64_t nc, const int32_t* lead, const int32_t* mate, 
   if (I >= nc) return;
   const int32_t a = lead[I], b = mate[a];
   const int32_t o = cptr[I];
+  const int32_t ka = grp[a], na = grp[a + 1] - ka;
+  const int32_t kb = b >= 0 ? grp[b] : 0, nb = b >= 0 ? grp[b + 1] - kb : 0;
+  const int32_t nall = na + nb;
+  if (nall <= 8) {
+    ucnt[I] = cg_row_small<8>((int32_t)I, nall, ka, na, kb, gci, gw, agg, cj, cw, o);
+    return;
+  }
+  if (nall <= 16) {
+    ucnt[I] = cg_row_small<16>((int32_t)I, nall, ka, na, kb, gci, gw, agg, cj, cw, o);
+    return;
+  }
+  if (nall <= 32) {
+    ucnt[I] = cg_row_small<32>((int32_t)I, nall, ka, na, kb, gci, gw, agg, cj, cw, o);
+    return;
+  }
   int32_t c = 0;
   for (int mem = 0; mem < 2; ++mem) {
     const int32_t v = mem == 0 ? a : b;
@@ -713,13 +833,78 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
 }
 
 // ---------------------------------------------------------------- Galerkin
-// One thread per coarse block slot (I, J).  The block is the sum, over the
+// Large coarse levels: one workgroup per slice of the coarse matrix; its
+// threads take the block slots (row l, slot t) of the slice, 256 at a time.  Block (I, J) is the
+// sum, over the members i of aggregate I in ascending order and over the
+// stored blocks (i, j) of row i in ascending j with agg(j) = J, of the fine
+// block a_ij (eq. Ac_direct), accumulated in FP64 starting from zero.  The
+// inverse of a diagonal block is computed from the stored (rounded) block.
+template <typename T>
+__global__ void k_galerkin_slices(int64_t nc, const int32_t* __restrict__ csl, const int32_t* __restrict__ ccol,
+                           T* __restrict__ cval, T* __restrict__ cdinv, const int32_t* __restrict__ mptr,
+                           const int32_t* __restrict__ mem, const int32_t* __restrict__ fsl,
+                           const int32_t* __restrict__ fcol, const T* __restrict__ fval,
+                           const int32_t* __restrict__ agg, const T* __restrict__ fk) {
+  const int64_t s = blockIdx.x;
+  const int64_t cb = csl[s];
+  const int64_t nslot = csl[s + 1] - cb;
+  for (int64_t k = threadIdx.x; k < nslot; k += blockDim.x) {
+    const int t = (int)(k / SL), l = (int)(k - (int64_t)t * SL);
+    const int64_t I = s * SL + l;
+    const int32_t J = ccol[cb + k];
+    if (J < 0 || I >= nc) continue;
+    double acc[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) acc[e] = 0.0;
+    for (int32_t q = mptr[I]; q < mptr[I + 1]; ++q) {
+      const int32_t i = mem[q];
+      const int64_t fs = i / SL;
+      const int fl = i - (int)(fs * SL);
+      const int64_t fb = fsl[fs];
+      const int fw = (int)((fsl[fs + 1] - fb) / SL);
+      for (int u = 0; u < fw; ++u) {
+        const int32_t j = fcol[fb + (int64_t)u * SL + fl];
+        if (j < 0) break;
+        if (agg[j] != J) continue;
+        if (fk) {
+          const int64_t kb = fs * 9 * SL + fl;
+#pragma unroll
+          for (int e = 0; e < 9; ++e)
+            acc[e] += j == i ? ((e == 0 || e == 4 || e == 8) ? 1.0 : 0.0) : (double)fk[kb + e * SL];
+          continue;
+        }
+        const int64_t vb = fb * 9 + (int64_t)u * 9 * SL + fl;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) acc[e] += (double)fval[vb + e * SL];
+      }
+    }
+    const int64_t vb = cb * 9 + (int64_t)t * 9 * SL + l;
+    T stv[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      stv[e] = (T)acc[e];
+      cval[vb + e * SL] = stv[e];
+    }
+    if (J == (int32_t)I) {
+      double D[9], Di[9];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) D[e] = (double)stv[e];
+      inv3(D, Di);
+      const int64_t db = s * 9 * SL + l;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) cdinv[db + e * SL] = (T)Di[e];
+    }
+  }
+}
+
+// Small coarse levels (few slices): one thread per block slot (I, J), its
+// slice found by bisection.  The block is the sum, over the
 // members i of aggregate I in ascending order and over the stored blocks
 // (i, j) of row i in ascending j with agg(j) = J, of the fine block a_ij
 // (eq. Ac_direct), accumulated in FP64 starting from zero.  The inverse of a
 // diagonal block is computed from the stored (rounded) block.
 template <typename T>
-__global__ void k_galerkin(int64_t nc, int64_t ns, const int32_t* __restrict__ csl,
+__global__ void k_galerkin_slots(int64_t nc, int64_t ns, const int32_t* __restrict__ csl,
                            const int32_t* __restrict__ ccol, T* __restrict__ cval, T* __restrict__ cdinv,
                            const int32_t* __restrict__ mptr, const int32_t* __restrict__ mem,
                            const int32_t* __restrict__ fsl, const int32_t* __restrict__ fcol,
@@ -940,6 +1125,10 @@ void launch_scan_excl(hipStream_t st, const int32_t* in, int32_t* out, int64_t n
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, st, total, 1, 0);
     return;
   }
+  if (n <= (int64_t)SCAN1_T * SCAN1_ITEMS) {
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SCAN1_T), 0, st, in, out, n, total);
+    return;
+  }
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, st, in, n, tmp);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_T), 0, st, tmp, nb, total);
   hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_T), 0, st, in, out, n, tmp);
@@ -1057,8 +1246,12 @@ template <typename T>
 void launch_galerkin(hipStream_t st, Sell C, T* cval, T* cdinv, const int32_t* mptr,
                      const int32_t* mem, Sell F, const T* fval, const int32_t* agg, const T* fk) {
   if (C.n <= 0) return;
-  hipLaunchKernelGGL((k_galerkin<T>), dim3(nblk(C.nslots)), dim3(TPB), 0, st, C.n, C.nslices, C.sl_ptr,
-                     C.col, cval, cdinv, mptr, mem, F.sl_ptr, F.col, fval, agg, fk);
+  if (C.nslices >= 1024)
+    hipLaunchKernelGGL((k_galerkin_slices<T>), dim3((unsigned)C.nslices), dim3(TPB), 0, st, C.n, C.sl_ptr, C.col,
+                       cval, cdinv, mptr, mem, F.sl_ptr, F.col, fval, agg, fk);
+  else
+    hipLaunchKernelGGL((k_galerkin_slots<T>), dim3(nblk(C.nslots)), dim3(TPB), 0, st, C.n, C.nslices, C.sl_ptr,
+                       C.col, cval, cdinv, mptr, mem, F.sl_ptr, F.col, fval, agg, fk);
 }
 template void launch_galerkin<double>(hipStream_t, Sell, double*, double*, const int32_t*,
                                       const int32_t*, Sell, const double*, const int32_t*, const double*);
