@@ -276,6 +276,23 @@ struct KTimer {
   }
 };
 
+// A pair of timing events for one launch of class cls that stamps them
+// itself (both null when cls is not timed or the stream is being captured).
+void kernel_events(llg_ctx& c, int cls, hipEvent_t& e0, hipEvent_t& e1) {
+  e0 = e1 = nullptr;
+  if (c.timed != cls || c.capturing) return;
+  if (c.ev_used + 2 > c.ev.size()) {
+    for (int k = 0; k < 2; ++k) {
+      hipEvent_t e;
+      HIPX(hipEventCreate(&e));
+      c.ev.push_back(e);
+    }
+  }
+  e0 = c.ev[c.ev_used];
+  e1 = c.ev[c.ev_used + 1];
+  c.ev_used += 2;
+}
+
 // after a stream synchronization: add up the recorded kernel intervals
 void harvest(llg_ctx& c) {
   for (size_t k = 0; k + 1 < c.ev_used; k += 2) {
@@ -854,12 +871,13 @@ void lvl_post_smooth(llg_ctx& c, int l, int xmode, const T* b, const T* x, const
                           L.G);
 }
 
+// e0, e1: events the launch itself stamps at the kernel's start and end
 template <typename TZ>
-void outer_spmv(llg_ctx& c, const TZ* z, double* w) {
+void outer_spmv(llg_ctx& c, const TZ* z, double* w, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   if (c.fact)
-    launch_fact_outer<TZ>(c.st, gdims(c), c.Mh, z, w);
+    launch_fact_outer<TZ>(c.st, gdims(c), c.Mh, z, w, e0, e1);
   else
-    launch_spmv_outer<TZ>(c.st, c.lv[0].A, c.Aval, z, w);
+    launch_spmv_outer<TZ>(c.st, c.lv[0].A, c.Aval, z, w, e0, e1);
 }
 
 // r = b - A u and the partial sums of |r|^2
@@ -1072,10 +1090,13 @@ void iter_precond(llg_ctx& c, int j) {
   precond<T>(c, c.V + (int64_t)j * c.ld, (T*)c.Z + (int64_t)j * c.ld, dcgs ? c.ks.hinv + j : nullptr);
 }
 
+// The outer product is timed by the kernel's own start and end stamps (a
+// launch with events), so the figure is the kernel's duration alone.
 template <typename T>
 void iter_spmv(llg_ctx& c, int j) {
-  KTimer kt(c, LLG_KT_OUTER_SPMV);
-  outer_spmv<T>(c, (const T*)c.Z + (int64_t)j * c.ld, c.w);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  kernel_events(c, LLG_KT_OUTER_SPMV, e0, e1);
+  outer_spmv<T>(c, (const T*)c.Z + (int64_t)j * c.ld, c.w, e0, e1);
   LCHK();
 }
 

@@ -4,6 +4,7 @@
 // and the projection.  All of them are bound by HBM bandwidth: one thread per
 // block row, one wavefront per 64-row slice, coalesced slot-major loads, and
 // reductions in a fixed tree so results are bitwise reproducible.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1258,13 +1259,20 @@ LLG_INST(float)
 #undef LLG_INST
 
 template <typename TZ>
-void launch_spmv_outer(hipStream_t st, Sell A, const double* val, const TZ* z, double* w) {
+void launch_spmv_outer(hipStream_t st, Sell A, const double* val, const TZ* z, double* w, hipEvent_t e0,
+                       hipEvent_t e1) {
   if (A.n <= 0) return;
   const int tb = tpb_rows(A.n);
-  hipLaunchKernelGGL((k_spmv_outer<TZ>), dim3(nblk(A.n, tb)), dim3(tb), 0, st, A.n, A.sl_ptr, A.col, val, z, w);
+  if (e0)
+    hipExtLaunchKernelGGL((k_spmv_outer<TZ>), dim3(nblk(A.n, tb)), dim3(tb), 0, st, e0, e1, 0, A.n, A.sl_ptr, A.col,
+                          val, z, w);
+  else
+    hipLaunchKernelGGL((k_spmv_outer<TZ>), dim3(nblk(A.n, tb)), dim3(tb), 0, st, A.n, A.sl_ptr, A.col, val, z, w);
 }
-template void launch_spmv_outer<double>(hipStream_t, Sell, const double*, const double*, double*);
-template void launch_spmv_outer<float>(hipStream_t, Sell, const double*, const float*, double*);
+template void launch_spmv_outer<double>(hipStream_t, Sell, const double*, const double*, double*, hipEvent_t,
+                                        hipEvent_t);
+template void launch_spmv_outer<float>(hipStream_t, Sell, const double*, const float*, double*, hipEvent_t,
+                                       hipEvent_t);
 
 void launch_resid_outer(hipStream_t st, Sell A, const double* val, const double* b, const double* u,
                         double* r, double* part) {
@@ -1272,15 +1280,24 @@ void launch_resid_outer(hipStream_t st, Sell A, const double* val, const double*
 }
 
 template <typename TZ>
-void launch_fact_outer(hipStream_t st, GridDims g, const double* Mh, const TZ* z, double* w) {
+void launch_fact_outer(hipStream_t st, GridDims g, const double* Mh, const TZ* z, double* w, hipEvent_t e0,
+                       hipEvent_t e1) {
   const int64_t N = (int64_t)g.nx * g.ny * g.nz;
-  if (g.nz > 1)
+  if (e0 && g.nz > 1)
+    hipExtLaunchKernelGGL((k_fact_outer<3, TZ>), dim3(nblk(N)), dim3(TPB), 0, st, e0, e1, 0, g.nx, g.ny, g.nz, Mh, z,
+                          w);
+  else if (e0)
+    hipExtLaunchKernelGGL((k_fact_outer<2, TZ>), dim3(nblk(N)), dim3(TPB), 0, st, e0, e1, 0, g.nx, g.ny, g.nz, Mh, z,
+                          w);
+  else if (g.nz > 1)
     hipLaunchKernelGGL((k_fact_outer<3, TZ>), dim3(nblk(N)), dim3(TPB), 0, st, g.nx, g.ny, g.nz, Mh, z, w);
   else
     hipLaunchKernelGGL((k_fact_outer<2, TZ>), dim3(nblk(N)), dim3(TPB), 0, st, g.nx, g.ny, g.nz, Mh, z, w);
 }
-template void launch_fact_outer<double>(hipStream_t, GridDims, const double*, const double*, double*);
-template void launch_fact_outer<float>(hipStream_t, GridDims, const double*, const float*, double*);
+template void launch_fact_outer<double>(hipStream_t, GridDims, const double*, const double*, double*, hipEvent_t,
+                                        hipEvent_t);
+template void launch_fact_outer<float>(hipStream_t, GridDims, const double*, const float*, double*, hipEvent_t,
+                                       hipEvent_t);
 
 void launch_fact_resid_outer(hipStream_t st, GridDims g, const double* Mh, const double* b, const double* u,
                              double* r, double* part) {

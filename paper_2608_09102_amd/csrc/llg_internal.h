@@ -187,7 +187,8 @@ struct GridDims {
   int nx, ny, nz;
 };
 template <typename TZ>
-void launch_fact_outer(hipStream_t st, GridDims g, const double* Mh, const TZ* z, double* w);
+void launch_fact_outer(hipStream_t st, GridDims g, const double* Mh, const TZ* z, double* w,
+                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_fact_resid_outer(hipStream_t st, GridDims g, const double* Mh, const double* b, const double* u,
                              double* r, double* part);
 template <typename T>
@@ -241,7 +242,8 @@ void launch_field_rhs(hipStream_t st, int64_t N, const double* prm, const double
 
 // outer Krylov kernels (FP64)
 template <typename TZ>
-void launch_spmv_outer(hipStream_t st, Sell A, const double* val, const TZ* z, double* w);
+void launch_spmv_outer(hipStream_t st, Sell A, const double* val, const TZ* z, double* w,
+                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_resid_outer(hipStream_t st, Sell A, const double* val, const double* b, const double* u,
                         double* r, double* part);
 void launch_norm_part(hipStream_t st, int64_t m, const double* x, double* part);
