@@ -287,6 +287,57 @@ def test_full_size_rough2d_1024(gpu, orc):
     say("  rtol 1e-8: iters %d, true relres (oracle operator) %.2e, |m - tight| %.2e"
         % (st8.iters, res, np.abs(proj - ref).max()))
     assert res <= 1e-8
+    # the forms bench.py times: K-cycle on level 1, grid level stored per node, FP64 and FP32-AMG
+    for prec in ("fp64", "fp32_amg"):
+        kw = dict(kcycle_depth=1, fine_operator="factored", precision=prec)
+        Sf = gpu.Solver(gg, gpu.default_opts(rtol=1e-11, **kw))
+        out_f, s, stf = Sf.step(_cuda(m), w.alpha, w.dt)
+        assert s == gpu.OK
+        df = np.abs(out_f.cpu().numpy() - ref).max()
+        Sf8 = gpu.Solver(gg, gpu.default_opts(rtol=w.rtol, project=0, **kw))
+        uf, s, stf8 = Sf8.step(_cuda(m), w.alpha, w.dt)
+        assert s == gpu.OK
+        uf = uf.cpu().numpy()
+        resf = np.linalg.norm(m.ravel() - H.apply_A(uf).ravel()) / np.linalg.norm(m.ravel())
+        say("  %s:1 factored: rtol 1e-11 iters %d diff %.2e; rtol 1e-8 iters %d true relres %.2e"
+            % (prec, stf.iters, df, stf8.iters, resf))
+        assert df <= 1e-8 and resf <= 1e-8
+        Sf.close()
+        Sf8.close()
+
+
+def test_full_size_rough3d_128(gpu, orc):
+    """The 128^3 workload (alpha = 0.1) at full size, in the forms bench.py
+    times for it (K-cycle on level 1, grid level per node, FP32-AMG and FP64):
+    aggregates bitwise at every level against the oracle's hierarchy, and the
+    unprojected solution at rtol 1e-8 checked through its true residual with
+    the oracle's operator (the oracle's own step takes about a minute here)."""
+    w = I.WORKLOADS["rough3d_128"]
+    alpha = 0.1
+    say("[full_size_rough3d_128] generating")
+    m = w.m0()
+    gg = gpu.make_grid(3, w.n)
+    og = orc.make_grid(3, w.n)
+    say("  oracle hierarchy")
+    H = orc.Hierarchy(og, orc.default_opts(), m, alpha, w.dt)
+    outs = {}
+    for prec in ("fp32_amg", "fp64"):
+        S = gpu.Solver(gg, gpu.default_opts(rtol=w.rtol, project=0, kcycle_depth=1, fine_operator="factored",
+                                            precision=prec))
+        u, s, st = S.step(_cuda(m), alpha, w.dt)
+        assert s == gpu.OK
+        assert S.num_levels == H.num_levels
+        for l in range(H.num_levels - 1):
+            assert np.array_equal(S.aggregates(l), H.level(l).agg), l
+        u = u.cpu().numpy()
+        res = np.linalg.norm(m.ravel() - H.apply_A(u).ravel()) / np.linalg.norm(m.ravel())
+        say("  %s: iters %d levels %d true relres (oracle operator) %.2e" % (prec, st.iters, st.levels, res))
+        assert res <= 1e-8
+        outs[prec] = u
+        S.close()
+    d = np.abs(outs["fp32_amg"] - outs["fp64"]).max()
+    say("  |fp32_amg - fp64| = %.2e" % d)
+    assert d <= 1e-6
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_amg"])
