@@ -72,9 +72,16 @@ __device__ inline void blk_mv(const T* __restrict__ val, int64_t vb, V3<TV> v, T
   a2 += (TA)val[vb + 6 * SL] * x + (TA)val[vb + 7 * SL] * y + (TA)val[vb + 8 * SL] * z;
 }
 
+// Nine zero entries per lane at the slot stride: the block that padding slots
+// of the lane-group row product read instead of their own (never stored)
+// values.
+__device__ double g_zero_block[9 * SL];
+
 // Row i of a sliced-ELL matrix times x: the slot loop is unrolled by four so
-// that the column indices of four slots, then their values and x entries,
-// are in flight together (the loads of one slot depend on its column index).
+// that the column indices of four slots are loaded together; a slot's values
+// and x entries are loaded only for a stored block (padding slots cost no
+// memory traffic, which matters on the large levels where rows run about
+// 1.4 times shorter than their slice).
 template <typename T, typename TA, typename XF>
 __device__ inline void sell_row_mv(const int32_t* __restrict__ col, const T* __restrict__ val, int64_t cb,
                                    int w, int l, XF xf, TA& a0, TA& a1, TA& a2) {
@@ -117,6 +124,8 @@ __device__ inline RowPos row_pos() {
 
 // Row product with the slots of the row split over the G lanes of a group,
 // then a butterfly sum inside the group (every lane ends with the total).
+// These levels are latency bound, so two slots per lane are loaded with no
+// branch between them: a padding slot reads the zero block and x of node 0.
 template <int G, typename T, typename TA, typename XF>
 __device__ inline void sell_row_mv_g(const int32_t* __restrict__ col, const T* __restrict__ val, int64_t cb,
                                      int w, int l, int sub, XF xf, TA& a0, TA& a1, TA& a2) {
@@ -124,9 +133,15 @@ __device__ inline void sell_row_mv_g(const int32_t* __restrict__ col, const T* _
     sell_row_mv(col, val, cb, w, l, xf, a0, a1, a2);
     return;
   }
-  for (int t = sub; t < w; t += G) {
-    const int32_t c = col[cb + (int64_t)t * SL + l];
-    if (c >= 0) blk_mv(val, cb * 9 + (int64_t)t * 9 * SL + l, xf(c), a0, a1, a2);
+  const T* zero = (const T*)g_zero_block + l;
+  for (int t = sub; t < w; t += 2 * G) {
+    const int32_t c0 = col[cb + (int64_t)t * SL + l];
+    const int32_t c1 = t + G < w ? col[cb + (int64_t)(t + G) * SL + l] : -1;
+    const bool ok0 = c0 >= 0, ok1 = c1 >= 0;
+    const T* v0 = ok0 ? val + cb * 9 + (int64_t)t * 9 * SL + l : zero;
+    const T* v1 = ok1 ? val + cb * 9 + (int64_t)(t + G) * 9 * SL + l : zero;
+    blk_mv(v0, 0, xf(ok0 ? c0 : 0), a0, a1, a2);
+    blk_mv(v1, 0, xf(ok1 ? c1 : 0), a0, a1, a2);
   }
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) {
