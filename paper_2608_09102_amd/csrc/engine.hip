@@ -946,22 +946,29 @@ void vcycle(llg_ctx& c, int l, const T* b, T* out) {
     }
     LCHK();
   }
+  const bool coarsest_next = l + 1 == c.L - 1;
   {
     KTimer kt(c, LLG_KT_RESIDUAL);
-    const bool pre_next = o.nu_pre >= 1 && l + 1 < c.L - 1;
+    const bool pre_next = o.nu_pre >= 1 && !coarsest_next;
     const T* rsrc = b;
     if (xmode != 2) {
       lvl_residual<T>(c, l, xmode, b, xcur, (T*)L.r);
       rsrc = (const T*)L.r;
     }
-    launch_restrict<T>(st, L.nc, L.mptr, L.mem, rsrc, (T*)Nx.b, pre_next ? (const T*)Nx.dinv : nullptr, om,
-                       pre_next ? (T*)Nx.x : nullptr);
+    if (coarsest_next)  // restriction and the exact coarsest solve in one launch
+      launch_restrict_dense<T>(st, L.nc, L.mptr, L.mem, rsrc, c.dense, (T*)Nx.e);
+    else
+      launch_restrict<T>(st, L.nc, L.mptr, L.mem, rsrc, (T*)Nx.b, pre_next ? (const T*)Nx.dinv : nullptr, om,
+                         pre_next ? (T*)Nx.x : nullptr);
     LCHK();
   }
-  if (Nx.kc)
+  if (coarsest_next) {
+    // Nx.e holds the coarse correction
+  } else if (Nx.kc) {
     kcorrection<T>(c, l + 1);
-  else
+  } else {
     vcycle<T>(c, l + 1, (const T*)Nx.b, (T*)Nx.e);
+  }
   const T* ec = (const T*)Nx.e;
   KTimer kt(c, LLG_KT_SMOOTH);
   if (o.nu_post == 0) {

@@ -1106,6 +1106,36 @@ __global__ void k_dense_apply(int64_t nd, const double* __restrict__ inv, const 
   }
 }
 
+// The restriction to the coarsest level and its exact solve in one
+// workgroup: bc_I = sum of r_i over the members of aggregate I (ascending, in
+// the level's precision, as the restriction does), then x = A_c^{-1} bc.
+template <typename T>
+__global__ void k_restrict_dense(int64_t nc, const int32_t* __restrict__ mptr, const int32_t* __restrict__ mem,
+                                 const T* __restrict__ r, const double* __restrict__ inv, T* __restrict__ x) {
+  extern __shared__ double sb[];
+  for (int64_t I = threadIdx.x; I < nc; I += blockDim.x) {
+    T a0 = 0, a1 = 0, a2 = 0;
+    for (int32_t q = mptr[I]; q < mptr[I + 1]; ++q) {
+      const int64_t i = mem[q];
+      a0 += r[3 * i];
+      a1 += r[3 * i + 1];
+      a2 += r[3 * i + 2];
+    }
+    sb[3 * I] = (double)a0;
+    sb[3 * I + 1] = (double)a1;
+    sb[3 * I + 2] = (double)a2;
+  }
+  __syncthreads();
+  const int64_t nd = 3 * nc;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int64_t row = wv; row < nd; row += nw) {
+    double s = 0.0;
+    for (int64_t c = lane; c < nd; c += 64) s += inv[row * nd + c] * sb[c];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) x[row] = (T)s;
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -1329,5 +1359,17 @@ void launch_dense_apply(hipStream_t st, int64_t nd, const double* inv, const T* 
 }
 template void launch_dense_apply<double>(hipStream_t, int64_t, const double*, const double*, double*);
 template void launch_dense_apply<float>(hipStream_t, int64_t, const double*, const float*, float*);
+
+template <typename T>
+void launch_restrict_dense(hipStream_t st, int64_t nc, const int32_t* mptr, const int32_t* mem, const T* r,
+                           const double* inv, T* x) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL((k_restrict_dense<T>), dim3(1), dim3(1024), 3 * nc * sizeof(double), st, nc, mptr, mem, r, inv,
+                     x);
+}
+template void launch_restrict_dense<double>(hipStream_t, int64_t, const int32_t*, const int32_t*, const double*,
+                                            const double*, double*);
+template void launch_restrict_dense<float>(hipStream_t, int64_t, const int32_t*, const int32_t*, const float*,
+                                           const double*, float*);
 
 }  // namespace llg

@@ -131,6 +131,10 @@ void launch_dense_scatter(hipStream_t st, Sell C, const T* cval, double* dense);
 void launch_gauss_jordan(hipStream_t st, int64_t nd, double* dense, int32_t* piv, int32_t* flag);
 template <typename T>
 void launch_dense_apply(hipStream_t st, int64_t nd, const double* inv, const T* b, T* x);
+// restriction of r onto the coarsest level (nc nodes) and x = A_c^{-1} P^T r
+template <typename T>
+void launch_restrict_dense(hipStream_t st, int64_t nc, const int32_t* mptr, const int32_t* mem, const T* r,
+                           const double* inv, T* x);
 
 // V-cycle level kernels.  xmode: 0 = x stored, 1 = x = omega b (unit
 // diagonal, first sweep from zero), 2 = x = 0.
