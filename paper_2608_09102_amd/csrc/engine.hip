@@ -162,6 +162,7 @@ struct Level {
   std::vector<Sell> cls;
   std::vector<void*> cval, cdinv;
   void* kf = nullptr;  // factored grid level: K_p per node ([slice][9][64])
+  void* kfm = nullptr;  // the same blocks in member order of the level-1 aggregates (K_mem[q])
 };
 
 struct PlanKey {
@@ -204,6 +205,7 @@ struct llg_ctx {
   double* Aval = nullptr;
   double* dinv0 = nullptr;
   bool fact = false;
+  bool f1 = false;  // level-1 products from the grid level's per-node blocks
   double* Mh = nullptr;
   // coarsest
   int64_t nd = 0;
@@ -610,6 +612,12 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   c.npart_rows = ceil_div(c.N, 256);
   int64_t kparts = 0;
   for (int l = 1; l < c.L; ++l) kparts = std::max<int64_t>(kparts, 3 * rows_blocks(c.lv[l].A.n, c.lv[l].G));
+  // level 1 (not the coarsest, one lane per row) applied through the grid level's blocks
+  c.f1 = c.fact && c.L > 2 && c.lv[1].G == 1 && c.opts.smoother == LLG_SMOOTHER_JACOBI;
+  if (c.f1) {
+    kparts = std::max<int64_t>(kparts, 3 * rows_blocks(c.lv[1].A.n, L1_LANES));
+    c.lv[0].kfm = ar.get(ts * 9 * c.lv[0].A.nslices * SL, true);
+  }
   // partial sums: up to 2R+3 columns of the delayed Gram-Schmidt dots (R+2 for the two-pass form)
   c.part = ar.lazy<double>(std::max<int64_t>(std::max<int64_t>((2 * R + 4) * c.npart_vec, c.npart_rows), kparts) + 64);
   c.ks.H = ar.lazy<double>((R + 1) * R);
@@ -727,6 +735,7 @@ void setup_values(llg_ctx& c, const double* m, const double* mprev, const double
     launch_assemble<T>(st, g.n[0], g.n[1], g.n[2], 1.0 / (g.h * g.h), c.prm, c.opts.left_scale,
                        c.opts.x0_is_mn, m, mprev, F, L0.A, c.Aval, (T*)L0.val, c.dinv0, (T*)L0.dinv, c.b, c.u,
                        c.flags, c.Mh, (T*)L0.kf);
+    if (c.f1) launch_member_blocks<T>(st, L0.A.n, L0.mem, (const T*)L0.kf, (T*)L0.kfm);
     LCHK();
   }
   if (field) {  // explicit field terms of the right-hand side (field 2: with the stray field)
@@ -854,6 +863,12 @@ GridDims gdims(const llg_ctx& c) { return GridDims{c.grid.n[0], c.grid.n[1], c.g
 template <typename T>
 void lvl_residual(llg_ctx& c, int l, int xmode, const T* b, const T* x, T* r) {
   Level& L = c.lv[l];
+  if (l == 1 && c.f1 && xmode == 0) {
+    const Level& L0 = c.lv[0];
+    launch_l1<T>(c.st, gdims(c), 0, 0, L.A.n, L0.mptr, L0.mem, L0.agg, (const T*)L0.kfm, x, b, nullptr, nullptr,
+                 nullptr, c.omega, r, nullptr, nullptr, nullptr);
+    return;
+  }
   if (l == 0 && c.fact)
     launch_fact_residual<T>(c.st, gdims(c), (const T*)L.kf, xmode, c.omega, b, x, r);
   else
@@ -864,6 +879,12 @@ template <typename T>
 void lvl_post_smooth(llg_ctx& c, int l, int xmode, const T* b, const T* x, const int32_t* agg, const T* ec,
                      T* out) {
   Level& L = c.lv[l];
+  if (l == 1 && c.f1 && (xmode == 0 || xmode == 2)) {
+    const Level& L0 = c.lv[0];
+    launch_l1<T>(c.st, gdims(c), 1, xmode == 2, L.A.n, L0.mptr, L0.mem, L0.agg, (const T*)L0.kfm, x, b,
+                 (const T*)L.dinv, agg, ec, c.omega, out, nullptr, nullptr, nullptr);
+    return;
+  }
   if (l == 0 && c.fact)
     launch_fact_post_smooth<T>(c.st, gdims(c), (const T*)L.kf, xmode, c.omega, b, x, agg, ec, out);
   else
@@ -1047,19 +1068,29 @@ void kcorrection(llg_ctx& c, int lc) {
   hipStream_t st = c.st;
   Level& C = c.lv[lc];
   const T* val = (const T*)C.val;
-  const int64_t G = rows_blocks(C.A.n, C.G);
   // with Jacobi smoothing the first sweep of the next cycle on rho is fused
   // into the update of rho (Gauss-Seidel cycles start from x = 0 themselves)
   const bool pre = c.opts.nu_pre >= 1 && c.opts.smoother == LLG_SMOOTHER_JACOBI;
   vcycle<T>(c, lc, (const T*)C.b, (T*)C.v1);
-  launch_spmv_dots<T>(st, C.A, val, (const T*)C.v1, (T*)C.w1, (const T*)C.b, nullptr, c.part, C.G);
+  const Level& L0 = c.lv[0];
+  const bool f1 = lc == 1 && c.f1;
+  const int64_t G = f1 ? rows_blocks(C.A.n, L1_LANES) : rows_blocks(C.A.n, C.G);  // partial sums per column
+  if (f1)
+    launch_l1<T>(st, gdims(c), 2, 0, C.A.n, L0.mptr, L0.mem, L0.agg, (const T*)L0.kfm, (const T*)C.v1, nullptr,
+                 nullptr, nullptr, nullptr, c.omega, (T*)C.w1, (const T*)C.b, nullptr, c.part);
+  else
+    launch_spmv_dots<T>(st, C.A, val, (const T*)C.v1, (T*)C.w1, (const T*)C.b, nullptr, c.part, C.G);
   launch_kc_coef(st, c.part, G, 1, C.kc);
   launch_kc_update<T>(st, C.A.n, (const T*)C.b, (const T*)C.w1, C.kc, (T*)C.rho, (const T*)C.dinv, c.omega,
                       pre ? (T*)C.x : nullptr, c.part);
   launch_kc_coef(st, c.part, rows_blocks(C.A.n, 1), 2, C.kc);
   LCHK();
   vcycle<T>(c, lc, (const T*)C.rho, (T*)C.v2);
-  launch_spmv_dots<T>(st, C.A, val, (const T*)C.v2, (T*)C.w2, (const T*)C.w1, (const T*)C.rho, c.part, C.G);
+  if (f1)
+    launch_l1<T>(st, gdims(c), 2, 0, C.A.n, L0.mptr, L0.mem, L0.agg, (const T*)L0.kfm, (const T*)C.v2, nullptr,
+                 nullptr, nullptr, nullptr, c.omega, (T*)C.w2, (const T*)C.w1, (const T*)C.rho, c.part);
+  else
+    launch_spmv_dots<T>(st, C.A, val, (const T*)C.v2, (T*)C.w2, (const T*)C.w1, (const T*)C.rho, c.part, C.G);
   launch_kc_coef(st, c.part, G, 3, C.kc);
   launch_kc_combine<T>(st, C.A.n, (const T*)C.v1, (const T*)C.v2, C.kc, (T*)C.e);
   LCHK();

@@ -814,6 +814,141 @@ __global__ void k_spmv_dots(int64_t n, const int32_t* __restrict__ sl, const int
   if (threadIdx.x <= ND) part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = res[threadIdx.x];
 }
 
+// ------------------------------------------------ level 1 from the grid level
+// Over a grid level stored per node (Atilde_ii = I, Atilde_ij = K_i for each
+// grid neighbour j), the Galerkin block (I, J) of level 1 is
+// [I = J] |I| I3 + sum over members i of I of n_iJ K_i, where n_iJ counts
+// the grid neighbours of i in aggregate J.  So
+//   (A1 x)_I = |I| x_I + sum_{i in I} K_i sum_{j ~ i} x_agg(j),
+// which reads 72 B (FP64) per grid node instead of the stored level-1 blocks
+// (about 150 B per grid node).  The stored blocks are still formed (for the
+// next Galerkin product and the diagonal inverse D1); only the products use
+// this form, so they differ from the stored-block products by rounding.
+// K holds the grid blocks in member order (K[q] = K_mem[q]), so that the
+// lanes of a wavefront read consecutive blocks.
+// MODE 0: r = b - A1 x.  MODE 1: out = x' + omega D1^{-1} (b - A1 x') with
+// x'_J = x_J + ec[agg2_J] (ec may be NULL; XZ: x = 0).  MODE 2: w = A1 v with
+// the K-cycle's partial sums (q = 0 w.w, 1 w.d1, 2 w.d2).  Four lanes per
+// aggregate, one member each (an aggregate of two matching passes has at
+// most four), summed by a butterfly over the four lanes.
+constexpr int L1_G = L1_LANES;
+template <int DIM, typename T, int MODE, bool XZ, int ND>
+__global__ void k_l1(int nx, int ny, int nz, int64_t n1, const int32_t* __restrict__ mptr,
+                     const int32_t* __restrict__ mem, const int32_t* __restrict__ agg1, const T* __restrict__ K,
+                     const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ dinv1,
+                     const int32_t* __restrict__ agg2, const T* __restrict__ ec, T omega, T* __restrict__ out,
+                     const T* __restrict__ d1, const T* __restrict__ d2, double* __restrict__ part) {
+  __shared__ double sh[(TPB / 64) * (ND + 1)];
+  __shared__ double res[ND + 1];
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t I = t / L1_G;
+  const int sub = (int)(t - I * L1_G);
+  double dots[ND + 1];
+#pragma unroll
+  for (int q = 0; q <= ND; ++q) dots[q] = 0.0;
+  V3<T> acc{T(0), T(0), T(0)};
+  if (I < n1) {
+    auto xv = [&](int64_t J) {
+      V3<T> v = XZ ? V3<T>{T(0), T(0), T(0)} : ld3(x, J);
+      if (MODE == 1 && ec) {
+        const V3<T> e = ld3(ec, (int64_t)agg2[J]);
+        v.x += e.x;
+        v.y += e.y;
+        v.z += e.z;
+      }
+      return v;
+    };
+    const int32_t q0 = mptr[I], q1 = mptr[I + 1];
+    for (int32_t q = q0 + sub; q < q1; q += L1_G) {
+      const int64_t i = mem[q];
+      const int64_t sq = q / SL;
+      const B9<T> kb = ld9(K, sq * 9 * SL + (q - sq * SL));  // blocks in member order
+      const Nbrs<DIM> nb = nbrs<DIM>(nx, ny, nz, i);
+      int32_t a[6];
+#pragma unroll
+      for (int u = 0; u < 6; ++u)
+        if (nbr_used(DIM, u)) a[u] = agg1[nb.q[u]];
+      V3<T> v[6];
+#pragma unroll
+      for (int u = 0; u < 6; ++u)
+        if (nbr_used(DIM, u)) v[u] = xv((int64_t)a[u]);
+      V3<T> sx{T(0), T(0), T(0)};
+#pragma unroll
+      for (int u = 0; u < 6; ++u)
+        if (nbr_used(DIM, u)) {
+          sx.x += nb.h[u] ? v[u].x : T(0);
+          sx.y += nb.h[u] ? v[u].y : T(0);
+          sx.z += nb.h[u] ? v[u].z : T(0);
+        }
+      const V3<T> kx = mv9(kb, sx);
+      acc.x += kx.x;
+      acc.y += kx.y;
+      acc.z += kx.z;
+    }
+#pragma unroll
+    for (int off = L1_G / 2; off > 0; off >>= 1) {
+      acc.x += __shfl_xor(acc.x, off, L1_G);
+      acc.y += __shfl_xor(acc.y, off, L1_G);
+      acc.z += __shfl_xor(acc.z, off, L1_G);
+    }
+  }
+  if (I < n1 && sub == 0) {
+    auto xv = [&](int64_t J) {
+      V3<T> v = XZ ? V3<T>{T(0), T(0), T(0)} : ld3(x, J);
+      if (MODE == 1 && ec) {
+        const V3<T> e = ld3(ec, (int64_t)agg2[J]);
+        v.x += e.x;
+        v.y += e.y;
+        v.z += e.z;
+      }
+      return v;
+    };
+    const int32_t q0 = mptr[I], q1 = mptr[I + 1];
+    const V3<T> xI = xv(I);
+    const T m = (T)(q1 - q0);
+    const V3<T> ax{m * xI.x + acc.x, m * xI.y + acc.y, m * xI.z + acc.z};
+    if (MODE == 0) {
+      const V3<T> bi = ld3(b, I);
+      st3(out, I, V3<T>{bi.x - ax.x, bi.y - ax.y, bi.z - ax.z});
+    } else if (MODE == 1) {
+      const V3<T> bi = ld3(b, I);
+      const int64_t s1 = I / SL;
+      const V3<T> d = dmv(dinv1, s1 * 9 * SL + (I - s1 * SL), V3<T>{bi.x - ax.x, bi.y - ax.y, bi.z - ax.z});
+      st3(out, I, V3<T>{xI.x + omega * d.x, xI.y + omega * d.y, xI.z + omega * d.z});
+    } else {
+      st3(out, I, ax);
+      const double w0 = ax.x, w1 = ax.y, w2 = ax.z;
+      dots[0] = (w0 * w0 + w1 * w1) + w2 * w2;
+      if (ND >= 1) {
+        const V3<T> dd = ld3(d1, I);
+        dots[1 % (ND + 1)] = (w0 * (double)dd.x + w1 * (double)dd.y) + w2 * (double)dd.z;
+      }
+      if (ND >= 2) {
+        const V3<T> dd = ld3(d2, I);
+        dots[2 % (ND + 1)] = (w0 * (double)dd.x + w1 * (double)dd.y) + w2 * (double)dd.z;
+      }
+    }
+  }
+  if (MODE == 2) {
+    block_sums<ND + 1>(dots, sh, res);
+    if (threadIdx.x <= ND) part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = res[threadIdx.x];
+  }
+}
+
+// Kq[q] = K[mem[q]]: per-node blocks ([slice][9][64]) gathered into the
+// member order of the aggregates
+template <typename T>
+__global__ void k_member_blocks(int64_t n, const int32_t* __restrict__ mem, const T* __restrict__ K,
+                                T* __restrict__ Kq) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const int64_t i = mem[q];
+  const int64_t si = i / SL, sq = q / SL;
+  const int64_t a = si * 9 * SL + (i - si * SL), d = sq * 9 * SL + (q - sq * SL);
+#pragma unroll
+  for (int e = 0; e < 9; ++e) Kq[d + e * SL] = K[a + e * SL];
+}
+
 // rho = r - a1 w1, x = omega D^{-1} rho (first sweep of the second inner
 // cycle, when x != NULL); part[blk] = w1 . rho
 template <typename T>
@@ -1560,6 +1695,44 @@ void launch_kc_coef(hipStream_t st, const double* part, int64_t G, int stage, do
   hipLaunchKernelGGL(k_kc_coef, dim3(1), dim3(192), 0, st, part, G, stage, kc);
 }
 int64_t rows_blocks(int64_t n, int G) { return ceil_div(n > 0 ? n * G : 1, TPB); }
+
+template <typename T>
+void launch_member_blocks(hipStream_t st, int64_t n, const int32_t* mem, const T* K, T* Kq) {
+  if (n > 0) hipLaunchKernelGGL((k_member_blocks<T>), dim3(nblk(n)), dim3(TPB), 0, st, n, mem, K, Kq);
+}
+template void launch_member_blocks<double>(hipStream_t, int64_t, const int32_t*, const double*, double*);
+template void launch_member_blocks<float>(hipStream_t, int64_t, const int32_t*, const float*, float*);
+
+template <typename T>
+void launch_l1(hipStream_t st, GridDims g, int mode, int xzero, int64_t n1, const int32_t* mptr, const int32_t* mem,
+               const int32_t* agg1, const T* K, const T* x, const T* b, const T* dinv1, const int32_t* agg2,
+               const T* ec, double omega, T* out, const T* d1, const T* d2, double* part) {
+  if (n1 <= 0) return;
+  const dim3 gr(nblk(n1 * L1_G)), t(TPB);
+  const T om = (T)omega;
+#define LLG_L1(D, M, XZ, ND)                                                                                     \
+  hipLaunchKernelGGL((k_l1<D, T, M, XZ, ND>), gr, t, 0, st, g.nx, g.ny, g.nz, n1, mptr, mem, agg1, K, x, b, dinv1, \
+                     agg2, ec, om, out, d1, d2, part)
+#define LLG_L1D(D)                                 \
+  if (mode == 0) LLG_L1(D, 0, false, 0);           \
+  else if (mode == 1 && xzero) LLG_L1(D, 1, true, 0); \
+  else if (mode == 1) LLG_L1(D, 1, false, 0);      \
+  else if (d2) LLG_L1(D, 2, false, 2);             \
+  else LLG_L1(D, 2, false, 1);
+  if (g.nz > 1) {
+    LLG_L1D(3)
+  } else {
+    LLG_L1D(2)
+  }
+#undef LLG_L1D
+#undef LLG_L1
+}
+template void launch_l1<double>(hipStream_t, GridDims, int, int, int64_t, const int32_t*, const int32_t*,
+                                const int32_t*, const double*, const double*, const double*, const double*,
+                                const int32_t*, const double*, double, double*, const double*, const double*, double*);
+template void launch_l1<float>(hipStream_t, GridDims, int, int, int64_t, const int32_t*, const int32_t*,
+                               const int32_t*, const float*, const float*, const float*, const float*, const int32_t*,
+                               const float*, double, float*, const float*, const float*, double*);
 #define LLG_INST_K(T)                                                                                    \
   template void launch_spmv_dots<T>(hipStream_t, Sell, const T*, const T*, T*, const T*, const T*, double*, int); \
   template void launch_kc_update<T>(hipStream_t, int64_t, const T*, const T*, const double*, T*, const T*, \

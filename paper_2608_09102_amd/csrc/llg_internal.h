@@ -190,6 +190,18 @@ void launch_kc_coef(hipStream_t st, const double* part, int64_t G, int stage, do
 struct GridDims {
   int nx, ny, nz;
 };
+// Level-1 products from the grid level's per-node blocks K (see k_solve.hip):
+// mode 0 r = b - A1 x; mode 1 post-smoothing sweep (xzero: x = 0; ec, agg2
+// the coarse correction or NULL); mode 2 w = A1 x with the K-cycle partial
+// sums (d1, optional d2) over rows_blocks(n1, L1_LANES) workgroups of 256
+constexpr int L1_LANES = 4;
+// Kq[q] = K[mem[q]] for the n grid nodes (K in the level-1 member order)
+template <typename T>
+void launch_member_blocks(hipStream_t st, int64_t n, const int32_t* mem, const T* K, T* Kq);
+template <typename T>
+void launch_l1(hipStream_t st, GridDims g, int mode, int xzero, int64_t n1, const int32_t* mptr, const int32_t* mem,
+               const int32_t* agg1, const T* K, const T* x, const T* b, const T* dinv1, const int32_t* agg2,
+               const T* ec, double omega, T* out, const T* d1, const T* d2, double* part);
 template <typename TZ>
 void launch_fact_outer(hipStream_t st, GridDims g, const double* Mh, const TZ* z, double* w,
                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
