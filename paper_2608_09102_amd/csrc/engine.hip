@@ -163,6 +163,7 @@ struct Level {
   std::vector<void*> cval, cdinv;
   void* kf = nullptr;  // factored grid level: K_p per node ([slice][9][64])
   void* kfm = nullptr;  // the same blocks in member order of the level-1 aggregates (K_mem[q])
+  int32_t* nagg = nullptr;  // level-1 aggregates of each member's grid neighbours ([slice][6][64])
 };
 
 struct PlanKey {
@@ -617,6 +618,7 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   if (c.f1) {
     kparts = std::max<int64_t>(kparts, 3 * rows_blocks(c.lv[1].A.n, L1_LANES));
     c.lv[0].kfm = ar.get(ts * 9 * c.lv[0].A.nslices * SL, true);
+    c.lv[0].nagg = ar.lazy<int32_t>(6 * c.lv[0].A.nslices * SL);
   }
   // partial sums: up to 2R+3 columns of the delayed Gram-Schmidt dots (R+2 for the two-pass form)
   c.part = ar.lazy<double>(std::max<int64_t>(std::max<int64_t>((2 * R + 4) * c.npart_vec, c.npart_rows), kparts) + 64);
@@ -735,7 +737,10 @@ void setup_values(llg_ctx& c, const double* m, const double* mprev, const double
     launch_assemble<T>(st, g.n[0], g.n[1], g.n[2], 1.0 / (g.h * g.h), c.prm, c.opts.left_scale,
                        c.opts.x0_is_mn, m, mprev, F, L0.A, c.Aval, (T*)L0.val, c.dinv0, (T*)L0.dinv, c.b, c.u,
                        c.flags, c.Mh, (T*)L0.kf);
-    if (c.f1) launch_member_blocks<T>(st, L0.A.n, L0.mem, (const T*)L0.kf, (T*)L0.kfm);
+    if (c.f1) {
+      launch_member_nbr_aggs(st, GridDims{g.n[0], g.n[1], g.n[2]}, L0.mem, L0.agg, L0.nagg);
+      launch_member_blocks<T>(st, L0.A.n, L0.mem, (const T*)L0.kf, (T*)L0.kfm);
+    }
     LCHK();
   }
   if (field) {  // explicit field terms of the right-hand side (field 2: with the stray field)
@@ -865,7 +870,7 @@ void lvl_residual(llg_ctx& c, int l, int xmode, const T* b, const T* x, T* r) {
   Level& L = c.lv[l];
   if (l == 1 && c.f1 && xmode == 0) {
     const Level& L0 = c.lv[0];
-    launch_l1<T>(c.st, gdims(c), 0, 0, L.A.n, L0.mptr, L0.mem, L0.agg, (const T*)L0.kfm, x, b, nullptr, nullptr,
+    launch_l1<T>(c.st, gdims(c), 0, 0, L.A.n, L0.mptr, L0.nagg, (const T*)L0.kfm, x, b, nullptr, nullptr,
                  nullptr, c.omega, r, nullptr, nullptr, nullptr);
     return;
   }
@@ -881,7 +886,7 @@ void lvl_post_smooth(llg_ctx& c, int l, int xmode, const T* b, const T* x, const
   Level& L = c.lv[l];
   if (l == 1 && c.f1 && (xmode == 0 || xmode == 2)) {
     const Level& L0 = c.lv[0];
-    launch_l1<T>(c.st, gdims(c), 1, xmode == 2, L.A.n, L0.mptr, L0.mem, L0.agg, (const T*)L0.kfm, x, b,
+    launch_l1<T>(c.st, gdims(c), 1, xmode == 2, L.A.n, L0.mptr, L0.nagg, (const T*)L0.kfm, x, b,
                  (const T*)L.dinv, agg, ec, c.omega, out, nullptr, nullptr, nullptr);
     return;
   }
@@ -938,7 +943,6 @@ void vcycle(llg_ctx& c, int l, const T* b, T* out) {
   Level& L = c.lv[l];
   Level& Nx = c.lv[l + 1];
   const llg_opts& o = c.opts;
-  const T* val = (const T*)L.val;
   const T* dinv = (const T*)L.dinv;
   const double om = c.omega;
   T* X = (T*)L.x;
@@ -1076,7 +1080,7 @@ void kcorrection(llg_ctx& c, int lc) {
   const bool f1 = lc == 1 && c.f1;
   const int64_t G = f1 ? rows_blocks(C.A.n, L1_LANES) : rows_blocks(C.A.n, C.G);  // partial sums per column
   if (f1)
-    launch_l1<T>(st, gdims(c), 2, 0, C.A.n, L0.mptr, L0.mem, L0.agg, (const T*)L0.kfm, (const T*)C.v1, nullptr,
+    launch_l1<T>(st, gdims(c), 2, 0, C.A.n, L0.mptr, L0.nagg, (const T*)L0.kfm, (const T*)C.v1, nullptr,
                  nullptr, nullptr, nullptr, c.omega, (T*)C.w1, (const T*)C.b, nullptr, c.part);
   else
     launch_spmv_dots<T>(st, C.A, val, (const T*)C.v1, (T*)C.w1, (const T*)C.b, nullptr, c.part, C.G);
@@ -1087,7 +1091,7 @@ void kcorrection(llg_ctx& c, int lc) {
   LCHK();
   vcycle<T>(c, lc, (const T*)C.rho, (T*)C.v2);
   if (f1)
-    launch_l1<T>(st, gdims(c), 2, 0, C.A.n, L0.mptr, L0.mem, L0.agg, (const T*)L0.kfm, (const T*)C.v2, nullptr,
+    launch_l1<T>(st, gdims(c), 2, 0, C.A.n, L0.mptr, L0.nagg, (const T*)L0.kfm, (const T*)C.v2, nullptr,
                  nullptr, nullptr, nullptr, c.omega, (T*)C.w2, (const T*)C.w1, (const T*)C.rho, c.part);
   else
     launch_spmv_dots<T>(st, C.A, val, (const T*)C.v2, (T*)C.w2, (const T*)C.w1, (const T*)C.rho, c.part, C.G);
@@ -1187,7 +1191,6 @@ SolveOut fgmres(llg_ctx& c) {
   hipStream_t st = c.st;
   const int R = c.opts.restart;
   const int64_t m = 3 * c.N;
-  Level& L0 = c.lv[0];
   double* H = c.host;
   T* Z = (T*)c.Z;
   SolveOut so;

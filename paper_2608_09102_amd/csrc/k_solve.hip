@@ -824,8 +824,10 @@ __global__ void k_spmv_dots(int64_t n, const int32_t* __restrict__ sl, const int
 // (about 150 B per grid node).  The stored blocks are still formed (for the
 // next Galerkin product and the diagonal inverse D1); only the products use
 // this form, so they differ from the stored-block products by rounding.
-// K holds the grid blocks in member order (K[q] = K_mem[q]), so that the
-// lanes of a wavefront read consecutive blocks.
+// K holds the grid blocks in member order (K[q] = K_mem[q]) and nagg the
+// level-1 aggregates of their grid neighbours ([slice][6][64] by member, -1
+// where the neighbour is missing), so that the lanes of a wavefront read
+// consecutive entries and only the x gathers depend on loaded indices.
 // MODE 0: r = b - A1 x.  MODE 1: out = x' + omega D1^{-1} (b - A1 x') with
 // x'_J = x_J + ec[agg2_J] (ec may be NULL; XZ: x = 0).  MODE 2: w = A1 v with
 // the K-cycle's partial sums (q = 0 w.w, 1 w.d1, 2 w.d2).  Four lanes per
@@ -834,7 +836,7 @@ __global__ void k_spmv_dots(int64_t n, const int32_t* __restrict__ sl, const int
 constexpr int L1_G = L1_LANES;
 template <int DIM, typename T, int MODE, bool XZ, int ND>
 __global__ void k_l1(int nx, int ny, int nz, int64_t n1, const int32_t* __restrict__ mptr,
-                     const int32_t* __restrict__ mem, const int32_t* __restrict__ agg1, const T* __restrict__ K,
+                     const int32_t* __restrict__ nagg, const T* __restrict__ K,
                      const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ dinv1,
                      const int32_t* __restrict__ agg2, const T* __restrict__ ec, T omega, T* __restrict__ out,
                      const T* __restrict__ d1, const T* __restrict__ d2, double* __restrict__ part) {
@@ -860,26 +862,21 @@ __global__ void k_l1(int nx, int ny, int nz, int64_t n1, const int32_t* __restri
     };
     const int32_t q0 = mptr[I], q1 = mptr[I + 1];
     for (int32_t q = q0 + sub; q < q1; q += L1_G) {
-      const int64_t i = mem[q];
-      const int64_t sq = q / SL;
-      const B9<T> kb = ld9(K, sq * 9 * SL + (q - sq * SL));  // blocks in member order
-      const Nbrs<DIM> nb = nbrs<DIM>(nx, ny, nz, i);
+      const int64_t sq = q / SL, lq = q - sq * SL;
+      const B9<T> kb = ld9(K, sq * 9 * SL + lq);  // blocks in member order
       int32_t a[6];
 #pragma unroll
-      for (int u = 0; u < 6; ++u)
-        if (nbr_used(DIM, u)) a[u] = agg1[nb.q[u]];
+      for (int u = 0; u < 2 * DIM; ++u) a[u] = nagg[sq * 6 * SL + u * SL + lq];
       V3<T> v[6];
 #pragma unroll
-      for (int u = 0; u < 6; ++u)
-        if (nbr_used(DIM, u)) v[u] = xv((int64_t)a[u]);
+      for (int u = 0; u < 2 * DIM; ++u) v[u] = xv((int64_t)(a[u] >= 0 ? a[u] : 0));
       V3<T> sx{T(0), T(0), T(0)};
 #pragma unroll
-      for (int u = 0; u < 6; ++u)
-        if (nbr_used(DIM, u)) {
-          sx.x += nb.h[u] ? v[u].x : T(0);
-          sx.y += nb.h[u] ? v[u].y : T(0);
-          sx.z += nb.h[u] ? v[u].z : T(0);
-        }
+      for (int u = 0; u < 2 * DIM; ++u) {
+        sx.x += a[u] >= 0 ? v[u].x : T(0);
+        sx.y += a[u] >= 0 ? v[u].y : T(0);
+        sx.z += a[u] >= 0 ? v[u].z : T(0);
+      }
       const V3<T> kx = mv9(kb, sx);
       acc.x += kx.x;
       acc.y += kx.y;
@@ -933,6 +930,21 @@ __global__ void k_l1(int nx, int ny, int nz, int64_t n1, const int32_t* __restri
     block_sums<ND + 1>(dots, sh, res);
     if (threadIdx.x <= ND) part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = res[threadIdx.x];
   }
+}
+
+// nagg[q][t] = agg(t-th grid neighbour of mem[q]) or -1 ([slice][6][64])
+template <int DIM>
+__global__ void k_member_nbr_aggs(int nx, int ny, int nz, const int32_t* __restrict__ mem,
+                                  const int32_t* __restrict__ agg, int32_t* __restrict__ nagg) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = (int64_t)nx * ny * nz;
+  if (q >= N) return;
+  const Nbrs<DIM> nb = nbrs<DIM>(nx, ny, nz, mem[q]);
+  const int64_t sq = q / SL, lq = q - sq * SL;
+  int u = 0;
+#pragma unroll
+  for (int t = 0; t < 6; ++t)
+    if (nbr_used(DIM, t)) nagg[sq * 6 * SL + (u++) * SL + lq] = nb.h[t] ? agg[nb.q[t]] : -1;
 }
 
 // Kq[q] = K[mem[q]]: per-node blocks ([slice][9][64]) gathered into the
@@ -1696,6 +1708,14 @@ void launch_kc_coef(hipStream_t st, const double* part, int64_t G, int stage, do
 }
 int64_t rows_blocks(int64_t n, int G) { return ceil_div(n > 0 ? n * G : 1, TPB); }
 
+void launch_member_nbr_aggs(hipStream_t st, GridDims g, const int32_t* mem, const int32_t* agg, int32_t* nagg) {
+  const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+  if (g.nz > 1)
+    hipLaunchKernelGGL(k_member_nbr_aggs<3>, dim3(nblk(N)), dim3(TPB), 0, st, g.nx, g.ny, g.nz, mem, agg, nagg);
+  else
+    hipLaunchKernelGGL(k_member_nbr_aggs<2>, dim3(nblk(N)), dim3(TPB), 0, st, g.nx, g.ny, g.nz, mem, agg, nagg);
+}
+
 template <typename T>
 void launch_member_blocks(hipStream_t st, int64_t n, const int32_t* mem, const T* K, T* Kq) {
   if (n > 0) hipLaunchKernelGGL((k_member_blocks<T>), dim3(nblk(n)), dim3(TPB), 0, st, n, mem, K, Kq);
@@ -1704,15 +1724,15 @@ template void launch_member_blocks<double>(hipStream_t, int64_t, const int32_t*,
 template void launch_member_blocks<float>(hipStream_t, int64_t, const int32_t*, const float*, float*);
 
 template <typename T>
-void launch_l1(hipStream_t st, GridDims g, int mode, int xzero, int64_t n1, const int32_t* mptr, const int32_t* mem,
-               const int32_t* agg1, const T* K, const T* x, const T* b, const T* dinv1, const int32_t* agg2,
-               const T* ec, double omega, T* out, const T* d1, const T* d2, double* part) {
+void launch_l1(hipStream_t st, GridDims g, int mode, int xzero, int64_t n1, const int32_t* mptr, const int32_t* nagg,
+               const T* K, const T* x, const T* b, const T* dinv1, const int32_t* agg2, const T* ec, double omega,
+               T* out, const T* d1, const T* d2, double* part) {
   if (n1 <= 0) return;
   const dim3 gr(nblk(n1 * L1_G)), t(TPB);
   const T om = (T)omega;
 #define LLG_L1(D, M, XZ, ND)                                                                                     \
-  hipLaunchKernelGGL((k_l1<D, T, M, XZ, ND>), gr, t, 0, st, g.nx, g.ny, g.nz, n1, mptr, mem, agg1, K, x, b, dinv1, \
-                     agg2, ec, om, out, d1, d2, part)
+  hipLaunchKernelGGL((k_l1<D, T, M, XZ, ND>), gr, t, 0, st, g.nx, g.ny, g.nz, n1, mptr, nagg, K, x, b, dinv1, agg2, \
+                     ec, om, out, d1, d2, part)
 #define LLG_L1D(D)                                 \
   if (mode == 0) LLG_L1(D, 0, false, 0);           \
   else if (mode == 1 && xzero) LLG_L1(D, 1, true, 0); \
@@ -1728,11 +1748,11 @@ void launch_l1(hipStream_t st, GridDims g, int mode, int xzero, int64_t n1, cons
 #undef LLG_L1
 }
 template void launch_l1<double>(hipStream_t, GridDims, int, int, int64_t, const int32_t*, const int32_t*,
-                                const int32_t*, const double*, const double*, const double*, const double*,
-                                const int32_t*, const double*, double, double*, const double*, const double*, double*);
-template void launch_l1<float>(hipStream_t, GridDims, int, int, int64_t, const int32_t*, const int32_t*,
-                               const int32_t*, const float*, const float*, const float*, const float*, const int32_t*,
-                               const float*, double, float*, const float*, const float*, double*);
+                                const double*, const double*, const double*, const double*, const int32_t*,
+                                const double*, double, double*, const double*, const double*, double*);
+template void launch_l1<float>(hipStream_t, GridDims, int, int, int64_t, const int32_t*, const int32_t*, const float*,
+                               const float*, const float*, const float*, const int32_t*, const float*, double, float*,
+                               const float*, const float*, double*);
 #define LLG_INST_K(T)                                                                                    \
   template void launch_spmv_dots<T>(hipStream_t, Sell, const T*, const T*, T*, const T*, const T*, double*, int); \
   template void launch_kc_update<T>(hipStream_t, int64_t, const T*, const T*, const double*, T*, const T*, \

@@ -199,9 +199,11 @@ constexpr int L1_LANES = 4;
 template <typename T>
 void launch_member_blocks(hipStream_t st, int64_t n, const int32_t* mem, const T* K, T* Kq);
 template <typename T>
-void launch_l1(hipStream_t st, GridDims g, int mode, int xzero, int64_t n1, const int32_t* mptr, const int32_t* mem,
-               const int32_t* agg1, const T* K, const T* x, const T* b, const T* dinv1, const int32_t* agg2,
-               const T* ec, double omega, T* out, const T* d1, const T* d2, double* part);
+void launch_l1(hipStream_t st, GridDims g, int mode, int xzero, int64_t n1, const int32_t* mptr, const int32_t* nagg,
+               const T* K, const T* x, const T* b, const T* dinv1, const int32_t* agg2, const T* ec, double omega,
+               T* out, const T* d1, const T* d2, double* part);
+// nagg[q][t]: level-1 aggregate of the t-th grid neighbour of member q ([slice][6][64], -1 if missing)
+void launch_member_nbr_aggs(hipStream_t st, GridDims g, const int32_t* mem, const int32_t* agg, int32_t* nagg);
 template <typename TZ>
 void launch_fact_outer(hipStream_t st, GridDims g, const double* Mh, const TZ* z, double* w,
                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
