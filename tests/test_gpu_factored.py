@@ -88,6 +88,37 @@ def test_factored_levels_and_products(gpu, orc, case, precision):
             assert np.abs(z - zr).max() <= 1e-11 * np.abs(zr).max()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_amg"])
+@pytest.mark.parametrize("dim,n", [(2, 384), (3, 56)])
+def test_level1_products_from_grid_blocks(gpu, orc, dim, n, precision):
+    """Grids whose level 1 has at least 32768 nodes: there the factored form
+    applies level 1 through the grid level's blocks, (A1 x)_I = |I| x_I +
+    sum_i K_i sum_{j~i} x_agg(j), while the BSR form multiplies the stored
+    Galerkin blocks.  The K-cycle preconditioner (level 1 visited by the
+    residual, the post-smoothing sweep and the K-cycle products) agrees with
+    the BSR form's and with the oracle's to 1e-11 relative (FP64)."""
+    say("[level1_products_from_grid_blocks]", dim, n, precision)
+    nn = (n, n, n if dim == 3 else 1)
+    m = _rough(nn, seed=11)
+    alpha, dt = 0.1, 2e-4
+    g = gpu.make_grid(dim, n)
+    Sf = gpu.Solver(g, gpu.default_opts(fine_operator="factored", precision=precision, kcycle_depth=1))
+    Sb = gpu.Solver(g, gpu.default_opts(precision=precision, kcycle_depth=1))
+    assert Sf.setup(_cuda(m), alpha, dt) == gpu.OK and Sb.setup(_cuda(m), alpha, dt) == gpu.OK
+    assert Sf.level_info(1)[0] >= 32768 and Sf.num_levels > 2
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(m.shape)
+    z = Sf.precond(_cuda(v)).cpu().numpy()
+    zb = Sb.precond(_cuda(v)).cpu().numpy()
+    d = np.abs(z - zb).max() / np.abs(zb).max()
+    say("  level-1 nodes %d, |z - z_bsr| / |z| = %.2e" % (Sf.level_info(1)[0], d))
+    assert d <= (1e-11 if precision == "fp64" else 1e-4)
+    if precision == "fp64":
+        H = orc.Hierarchy(orc.make_grid(dim, n), orc.default_opts(kcycle_depth=1), m, alpha, dt)
+        zr = H.precond(v)
+        assert np.abs(z - zr).max() <= 1e-11 * np.abs(zr).max()
+
+
 def test_factored_steps(gpu, orc):
     """Vortex trajectory (rtol 1e-10 on the GPU, 1e-12 in the oracle) and an
     evolved rough field with the K-cycle (both at 1e-11): within 1e-8."""
