@@ -180,21 +180,27 @@ def device_field(dim: int, n: int, seed: int, device, sweeps: int = 20):
 
 class HipRunner:
     """Runs a request through libllg.so: one context per simulation on the
-    worker's stream, `steps` calls of llg_step, fields resident on the device."""
+    worker's stream, `steps` calls of llg_step, fields resident on the device.
+    opts_kw applies to every request; opts_by_dim[d] adds options for grids of
+    dimension d (e.g. the cycle that is fastest there)."""
 
-    def __init__(self, opts_kw=None, device: int = 0, workers: int = 4, keep_device: bool = False):
+    def __init__(self, opts_kw=None, device: int = 0, workers: int = 4, keep_device: bool = False,
+                 opts_by_dim=None):
         import torch
         import paper_2608_09102_amd as llg
         self.llg = llg
         self.torch = torch
         self.opts_kw = dict(opts_kw or {})
+        self.opts_by_dim = {int(k): dict(v) for k, v in (opts_by_dim or {}).items()}
         self.device = torch.device("cuda", device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(workers)]
         self._plan_lock = threading.Lock()
 
     def _grid_opts(self, r):
         llg = self.llg
-        return llg.make_grid(r.dim, r.n), llg.default_opts(**self.opts_kw)
+        kw = dict(self.opts_kw)
+        kw.update(self.opts_by_dim.get(r.dim, {}))
+        return llg.make_grid(r.dim, r.n), llg.default_opts(**kw)
 
     def footprint(self, r) -> int:
         g, o = self._grid_opts(r)
