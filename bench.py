@@ -99,8 +99,8 @@ def algorithmic_bytes(cls: str, st, N: int, precision: str, operator: str = "bsr
     nnzb0 = st.level_nnzb[0]
     if cls == "outer_spmv":
         zb = 4 if precision == "fp32_amg" else 8
-        if operator == "factored":  # one FP64 block per node, neighbours from the grid
-            return 72.0 * N + 3.0 * zb * N + 24.0 * N
+        if operator == "factored":  # block recomputed from the frozen field (24 B per node), neighbours from the grid
+            return 24.0 * N + 3.0 * zb * N + 24.0 * N
         return 72.0 * nnzb0 + 4.0 * nnzb0 + 3.0 * zb * N + 24.0 * N
     raise ValueError("no byte model for kernel class " + cls)
 

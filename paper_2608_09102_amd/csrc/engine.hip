@@ -162,7 +162,7 @@ struct Level {
   std::vector<Sell> cls;
   std::vector<void*> cval, cdinv;
   void* kf = nullptr;  // factored grid level: K_p per node ([slice][9][64])
-  void* kfm = nullptr;  // the same blocks in member order of the level-1 aggregates (K_mem[q])
+  double* mtq = nullptr;  // the frozen field in member order of the level-1 aggregates (mt[mem[q]])
   int32_t* nagg = nullptr;  // level-1 aggregates of each member's grid neighbours ([slice][6][64])
 };
 
@@ -208,6 +208,7 @@ struct llg_ctx {
   bool fact = false;
   bool f1 = false;  // level-1 products from the grid level's per-node blocks
   double* Mh = nullptr;
+  double* mt = nullptr;  // factored grid level: the frozen field, from which the solve kernels recompute blocks
   // coarsest
   int64_t nd = 0;
   double* dense = nullptr;
@@ -562,6 +563,7 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   c.fact = c.opts.fine_operator == LLG_FINE_FACTORED && c.L > 1;
   if (c.fact) {
     c.Mh = ar.lazy<double>(9 * L0.A.nslices * SL);
+    c.mt = ar.lazy<double>(3 * L0.A.n);
     L0.kf = ar.get(ts * 9 * L0.A.nslices * SL, true);
   } else {
     c.Aval = ar.lazy<double>(9 * L0.A.nslots);
@@ -617,7 +619,7 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   c.f1 = c.fact && c.L > 2 && c.lv[1].G == 1 && c.opts.smoother == LLG_SMOOTHER_JACOBI;
   if (c.f1) {
     kparts = std::max<int64_t>(kparts, 3 * rows_blocks(c.lv[1].A.n, L1_LANES));
-    c.lv[0].kfm = ar.get(ts * 9 * c.lv[0].A.nslices * SL, true);
+    c.lv[0].mtq = ar.lazy<double>(3 * c.lv[0].A.n);
     c.lv[0].nagg = ar.lazy<int32_t>(6 * c.lv[0].A.nslices * SL);
   }
   // partial sums: up to 2R+3 columns of the delayed Gram-Schmidt dots (R+2 for the two-pass form)
@@ -736,10 +738,10 @@ void setup_values(llg_ctx& c, const double* m, const double* mprev, const double
     KTimer kt(c, LLG_KT_ASSEMBLE);
     launch_assemble<T>(st, g.n[0], g.n[1], g.n[2], 1.0 / (g.h * g.h), c.prm, c.opts.left_scale,
                        c.opts.x0_is_mn, m, mprev, F, L0.A, c.Aval, (T*)L0.val, c.dinv0, (T*)L0.dinv, c.b, c.u,
-                       c.flags, c.Mh, (T*)L0.kf);
+                       c.flags, c.Mh, (T*)L0.kf, c.mt);
     if (c.f1) {
       launch_member_nbr_aggs(st, GridDims{g.n[0], g.n[1], g.n[2]}, L0.mem, L0.agg, L0.nagg);
-      launch_member_blocks<T>(st, L0.A.n, L0.mem, (const T*)L0.kf, (T*)L0.kfm);
+      launch_member_fields(st, L0.A.n, L0.mem, c.mt, L0.mtq);
     }
     LCHK();
   }
@@ -863,19 +865,25 @@ void demag_prepare(llg_ctx& c) {
 // ------------------------------------------------------------------ products
 // Level and outer products, dispatched to the factored kernels on the grid
 // level when the context stores it in factored form.
-GridDims gdims(const llg_ctx& c) { return GridDims{c.grid.n[0], c.grid.n[1], c.grid.n[2]}; }
+GridDims gdims(const llg_ctx& c) {
+  GridDims g{c.grid.n[0], c.grid.n[1], c.grid.n[2]};
+  g.mt = c.mt;
+  g.prm = c.prm;
+  g.inv_h2 = 1.0 / (c.grid.h * c.grid.h);
+  return g;
+}
 
 template <typename T>
 void lvl_residual(llg_ctx& c, int l, int xmode, const T* b, const T* x, T* r) {
   Level& L = c.lv[l];
   if (l == 1 && c.f1 && xmode == 0) {
     const Level& L0 = c.lv[0];
-    launch_l1<T>(c.st, gdims(c), 0, 0, L.A.n, L0.mptr, L0.nagg, (const T*)L0.kfm, x, b, nullptr, nullptr,
+    launch_l1<T>(c.st, gdims(c), 0, 0, L.A.n, L0.mptr, L0.nagg, L0.mtq, x, b, nullptr, nullptr,
                  nullptr, c.omega, r, nullptr, nullptr, nullptr);
     return;
   }
   if (l == 0 && c.fact)
-    launch_fact_residual<T>(c.st, gdims(c), (const T*)L.kf, xmode, c.omega, b, x, r);
+    launch_fact_residual<T>(c.st, gdims(c), xmode, c.omega, b, x, r);
   else
     launch_residual<T>(c.st, L.A, (const T*)L.val, xmode, c.omega, b, x, r, L.G);
 }
@@ -886,12 +894,12 @@ void lvl_post_smooth(llg_ctx& c, int l, int xmode, const T* b, const T* x, const
   Level& L = c.lv[l];
   if (l == 1 && c.f1 && (xmode == 0 || xmode == 2)) {
     const Level& L0 = c.lv[0];
-    launch_l1<T>(c.st, gdims(c), 1, xmode == 2, L.A.n, L0.mptr, L0.nagg, (const T*)L0.kfm, x, b,
+    launch_l1<T>(c.st, gdims(c), 1, xmode == 2, L.A.n, L0.mptr, L0.nagg, L0.mtq, x, b,
                  (const T*)L.dinv, agg, ec, c.omega, out, nullptr, nullptr, nullptr);
     return;
   }
   if (l == 0 && c.fact)
-    launch_fact_post_smooth<T>(c.st, gdims(c), (const T*)L.kf, xmode, c.omega, b, x, agg, ec, out);
+    launch_fact_post_smooth<T>(c.st, gdims(c), xmode, c.omega, b, x, agg, ec, out);
   else
     launch_post_smooth<T>(c.st, L.A, (const T*)L.val, (const T*)L.dinv, L.unit, xmode, c.omega, b, x, agg, ec, out,
                           L.G);
@@ -901,7 +909,7 @@ void lvl_post_smooth(llg_ctx& c, int l, int xmode, const T* b, const T* x, const
 template <typename TZ>
 void outer_spmv(llg_ctx& c, const TZ* z, double* w, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   if (c.fact)
-    launch_fact_outer<TZ>(c.st, gdims(c), c.Mh, z, w, e0, e1);
+    launch_fact_outer<TZ>(c.st, gdims(c), z, w, e0, e1);
   else
     launch_spmv_outer<TZ>(c.st, c.lv[0].A, c.Aval, z, w, e0, e1);
 }
@@ -909,7 +917,7 @@ void outer_spmv(llg_ctx& c, const TZ* z, double* w, hipEvent_t e0 = nullptr, hip
 // r = b - A u and the partial sums of |r|^2
 void outer_resid(llg_ctx& c) {
   if (c.fact)
-    launch_fact_resid_outer(c.st, gdims(c), c.Mh, c.b, c.u, c.r, c.part);
+    launch_fact_resid_outer(c.st, gdims(c), c.b, c.u, c.r, c.part);
   else
     launch_resid_outer(c.st, c.lv[0].A, c.Aval, c.b, c.u, c.r, c.part);
 }
@@ -1080,7 +1088,7 @@ void kcorrection(llg_ctx& c, int lc) {
   const bool f1 = lc == 1 && c.f1;
   const int64_t G = f1 ? rows_blocks(C.A.n, L1_LANES) : rows_blocks(C.A.n, C.G);  // partial sums per column
   if (f1)
-    launch_l1<T>(st, gdims(c), 2, 0, C.A.n, L0.mptr, L0.nagg, (const T*)L0.kfm, (const T*)C.v1, nullptr,
+    launch_l1<T>(st, gdims(c), 2, 0, C.A.n, L0.mptr, L0.nagg, L0.mtq, (const T*)C.v1, nullptr,
                  nullptr, nullptr, nullptr, c.omega, (T*)C.w1, (const T*)C.b, nullptr, c.part);
   else
     launch_spmv_dots<T>(st, C.A, val, (const T*)C.v1, (T*)C.w1, (const T*)C.b, nullptr, c.part, C.G);
@@ -1091,7 +1099,7 @@ void kcorrection(llg_ctx& c, int lc) {
   LCHK();
   vcycle<T>(c, lc, (const T*)C.rho, (T*)C.v2);
   if (f1)
-    launch_l1<T>(st, gdims(c), 2, 0, C.A.n, L0.mptr, L0.nagg, (const T*)L0.kfm, (const T*)C.v2, nullptr,
+    launch_l1<T>(st, gdims(c), 2, 0, C.A.n, L0.mptr, L0.nagg, L0.mtq, (const T*)C.v2, nullptr,
                  nullptr, nullptr, nullptr, c.omega, (T*)C.w2, (const T*)C.w1, (const T*)C.rho, c.part);
   else
     launch_spmv_dots<T>(st, C.A, val, (const T*)C.v2, (T*)C.w2, (const T*)C.w1, (const T*)C.rho, c.part, C.G);
@@ -1103,7 +1111,10 @@ void kcorrection(llg_ctx& c, int lc) {
 template <typename T>
 void precond(llg_ctx& c, const double* v, T* z, const double* vscale = nullptr) {
   Level& L0 = c.lv[0];
-  launch_scale_in<T>(c.st, c.N, c.dinv0, c.opts.left_scale, v, vscale, (T*)L0.b);
+  if (c.fact)
+    launch_scale_in_grid<T>(c.st, gdims(c), v, vscale, (T*)L0.b);
+  else
+    launch_scale_in<T>(c.st, c.N, c.dinv0, c.opts.left_scale, v, vscale, (T*)L0.b);
   LCHK();
   vcycle<T>(c, 0, (const T*)L0.b, z);
 }

@@ -553,45 +553,6 @@ __global__ void k_member_sort(int64_t nc, const int32_t* mptr, int32_t* mem) {
   }
 }
 
-// ---------------------------------------------------------------- assembly
-// Row r of M collects the coefficients of (Lap u1, Lap u2, Lap u3) in
-// equation r of the damped component-wise system (Sec. 2.1):
-//   M = [ -a(m2^2+m3^2)     -m3 + a m1 m2     m2 + a m1 m3 ]
-//       [  m3 + a m1 m2    -a(m1^2+m3^2)     -m1 + a m2 m3 ]
-//       [ -m2 + a m1 m3     m1 + a m2 m3    -a(m1^2+m2^2)  ]
-__device__ inline void block_M(double m1, double m2, double m3, double a, double* M) {
-  M[0] = -(a * (m2 * m2 + m3 * m3));
-  M[1] = -m3 + a * (m1 * m2);
-  M[2] = m2 + a * (m1 * m3);
-  M[3] = m3 + a * (m1 * m2);
-  M[4] = -(a * (m1 * m1 + m3 * m3));
-  M[5] = -m1 + a * (m2 * m3);
-  M[6] = -m2 + a * (m1 * m3);
-  M[7] = m1 + a * (m2 * m3);
-  M[8] = -(a * (m1 * m1 + m2 * m2));
-}
-
-// 3x3 inverse: adjugate times the reciprocal of the determinant (cofactor
-// expansion along the first row).
-__device__ inline void inv3(const double* D, double* R) {
-  const double a = D[0], b = D[1], c = D[2], d = D[3], e = D[4], f = D[5], g = D[6], h = D[7],
-               i = D[8];
-  double adj[9];
-  adj[0] = e * i - f * h;
-  adj[1] = c * h - b * i;
-  adj[2] = b * f - c * e;
-  adj[3] = f * g - d * i;
-  adj[4] = a * i - c * g;
-  adj[5] = c * d - a * f;
-  adj[6] = d * h - e * g;
-  adj[7] = b * g - a * h;
-  adj[8] = a * e - b * d;
-  const double det = (a * adj[0] + b * adj[3]) + c * adj[6];
-  const double rdet = 1.0 / det;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) R[k] = adj[k] * rdet;
-}
-
 // ---------------------------------------------------------------- colouring
 // Colour classes for the multicolour Gauss-Seidel smoother (Sec. 3).
 // Level 0: parity of i + j + k (the grid graph is bipartite).
@@ -723,7 +684,7 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
                            const int32_t* __restrict__ col, double* __restrict__ Aval,
                            T* __restrict__ Lval, double* __restrict__ dinv0, T* __restrict__ ldinv,
                            double* __restrict__ b, double* __restrict__ u, int32_t* flag,
-                           double* __restrict__ Mh, T* __restrict__ K) {
+                           double* __restrict__ Mh, T* __restrict__ K, double* __restrict__ mt_out) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t N = (int64_t)nx * ny * nz;
   if (p >= N) return;
@@ -746,6 +707,10 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
     }
   }
   if (!fin) atomicOr(flag, 1);
+  if (mt_out) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) mt_out[3 * p + c] = mt[c];
+  }
   const double m1 = mt[0], m2 = mt[1], m3 = mt[2];
   int64_t nb[6];
   const int deg = grid_nbrs(nx, ny, nz, p, nb);
@@ -1251,18 +1216,18 @@ template <typename T>
 void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, const double* prm,
                      int left_scale, int x0_is_mn, const double* m, const double* mprev, const double* F,
                      Sell A, double* Aval, T* Lval, double* dinv0, T* ldinv, double* b, double* u,
-                     int32_t* flag, double* Mh, T* K) {
+                     int32_t* flag, double* Mh, T* K, double* mt_out) {
   const int64_t N = (int64_t)nx * ny * nz;
   hipLaunchKernelGGL((k_assemble<T>), dim3(nblk(N)), dim3(TPB), 0, st, nx, ny, nz, inv_h2, prm,
                      left_scale, x0_is_mn, m, mprev, F, A.sl_ptr, A.col, Aval, Lval, dinv0, ldinv, b, u, flag, Mh,
-                     K);
+                     K, mt_out);
 }
 template void launch_assemble<double>(hipStream_t, int, int, int, double, const double*, int, int,
                                       const double*, const double*, const double*, Sell, double*, double*,
-                                      double*, double*, double*, double*, int32_t*, double*, double*);
+                                      double*, double*, double*, double*, int32_t*, double*, double*, double*);
 template void launch_assemble<float>(hipStream_t, int, int, int, double, const double*, int, int,
                                      const double*, const double*, const double*, Sell, double*, float*,
-                                     double*, float*, double*, double*, int32_t*, double*, float*);
+                                     double*, float*, double*, double*, int32_t*, double*, float*, double*);
 
 void init_kernel_attributes() {
   const size_t lds_max = (size_t)(GJ_LDS_MAX * GJ_LDS_MAX + GJ_LDS_MAX + GJ_T) * sizeof(double) +

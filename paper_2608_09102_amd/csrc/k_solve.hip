@@ -485,13 +485,60 @@ __device__ inline V3<TV> mv9(const B9<T>& b, V3<TV> v) {
                 (TV)b.e[6] * v.x + (TV)b.e[7] * v.y + (TV)b.e[8] * v.z};
 }
 
+// The blocks of node p recomputed from its frozen field (24 B instead of the
+// 72 B of a stored block; the same values, see grid_blocks).
+template <int DIM>
+__device__ inline int nbr_count(const Nbrs<DIM>& n) {
+  int d = 0;
+#pragma unroll
+  for (int t = 0; t < 6; ++t)
+    if (nbr_used(DIM, t)) d += n.h[t] ? 1 : 0;
+  return d;
+}
+__device__ inline B9<double> node_Mh(const GridDims& gd, int64_t p, int deg) {
+  double v[9];
+  grid_blocks(gd.mt + 3 * p, gd.prm[0], gd.prm[1], gd.inv_h2, deg, v, nullptr, nullptr);
+  B9<double> b;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) b.e[e] = v[e];
+  return b;
+}
+template <typename T>
+__device__ inline B9<T> node_K(const GridDims& gd, const double* mt, int deg) {
+  double v[9];
+  grid_blocks(mt, gd.prm[0], gd.prm[1], gd.inv_h2, deg, nullptr, nullptr, v);
+  B9<T> b;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) b.e[e] = (T)v[e];
+  return b;
+}
+
+// The same with D^{-1} recomputed from the frozen field (factored grid level)
+template <int DIM, typename T>
+__global__ void k_scale_in_grid(GridDims gd, const double* __restrict__ v, const double* __restrict__ vs,
+                                T* __restrict__ b0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)gd.nx * gd.ny * gd.nz) return;
+  V3<double> x = ld3(v, i);
+  if (vs) {
+    const double f = vs[0];
+    x = V3<double>{x.x * f, x.y * f, x.z * f};
+  }
+  double di[9];
+  grid_blocks(gd.mt + 3 * i, gd.prm[0], gd.prm[1], gd.inv_h2, nbr_count<DIM>(nbrs<DIM>(gd.nx, gd.ny, gd.nz, i)),
+              nullptr, di, nullptr);
+  const V3<double> y{(di[0] * x.x + di[1] * x.y) + di[2] * x.z, (di[3] * x.x + di[4] * x.y) + di[5] * x.z,
+                     (di[6] * x.x + di[7] * x.y) + di[8] * x.z};
+  st3(b0, i, V3<T>{(T)y.x, (T)y.y, (T)y.z});
+}
+
 template <int DIM, typename TZ>
-__global__ void k_fact_outer(int nx, int ny, int nz, const double* __restrict__ Mh, const TZ* __restrict__ z,
-                             double* __restrict__ w) {
+__global__ void k_fact_outer(GridDims gd, const TZ* __restrict__ z, double* __restrict__ w) {
+  const int nx = gd.nx, ny = gd.ny, nz = gd.nz;
   const GridPos g = grid_pos();
   const int64_t N = (int64_t)nx * ny * nz;
   if (g.p >= N) return;
-  const B9<double> m = ld9(Mh, g.s * 9 * SL + g.l);
+  const B9<double> m = node_Mh(gd, g.p, nbr_count<DIM>(nbrs<DIM>(nx, ny, nz, g.p)));
   auto zd = [&](int64_t q) {
     const V3<TZ> t = ld3(z, q);
     return V3<double>{(double)t.x, (double)t.y, (double)t.z};
@@ -506,17 +553,16 @@ __global__ void k_fact_outer(int nx, int ny, int nz, const double* __restrict__ 
 
 // r = b - A u with the partial sums of |r|^2 per workgroup
 template <int DIM>
-__global__ void k_fact_resid_outer(int nx, int ny, int nz, const double* __restrict__ Mh,
-                                   const double* __restrict__ b, const double* __restrict__ u,
+__global__ void k_fact_resid_outer(GridDims gd, const double* __restrict__ b, const double* __restrict__ u,
                                    double* __restrict__ r, double* __restrict__ part) {
+  const int nx = gd.nx, ny = gd.ny, nz = gd.nz;
   __shared__ double sh[TPB / 64];
   __shared__ double res[1];
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t N = (int64_t)nx * ny * nz;
   double nrm = 0;
   if (p < N) {
-    const int64_t s = p / SL;
-    const B9<double> m = ld9(Mh, s * 9 * SL + (p - s * SL));
+    const B9<double> m = node_Mh(gd, p, nbr_count<DIM>(nbrs<DIM>(nx, ny, nz, p)));
     int deg;
     const V3<double> su = nbr_sum<DIM, double>(nx, ny, nz, p, [&](int64_t q) { return ld3(u, q); }, deg);
     const V3<double> up = ld3(u, p);
@@ -533,12 +579,13 @@ __global__ void k_fact_resid_outer(int nx, int ny, int nz, const double* __restr
 
 // r = b - Atilde x on the grid level
 template <int DIM, typename T, int XMODE>
-__global__ void k_fact_residual(int nx, int ny, int nz, const T* __restrict__ K, T omega, const T* __restrict__ b,
-                                const T* __restrict__ x, T* __restrict__ r) {
+__global__ void k_fact_residual(GridDims gd, T omega, const T* __restrict__ b, const T* __restrict__ x,
+                                T* __restrict__ r) {
+  const int nx = gd.nx, ny = gd.ny, nz = gd.nz;
   const GridPos g = grid_pos();
   const int64_t N = (int64_t)nx * ny * nz;
   if (g.p >= N) return;
-  const B9<T> kb = ld9(K, g.s * 9 * SL + g.l);
+  const B9<T> kb = node_K<T>(gd, gd.mt + 3 * g.p, nbr_count<DIM>(nbrs<DIM>(nx, ny, nz, g.p)));
   int deg;
   const V3<T> sx =
       nbr_sum<DIM, T>(nx, ny, nz, g.p, [&](int64_t q) { return xval<T, XMODE>(x, b, omega, q); }, deg);
@@ -552,14 +599,14 @@ __global__ void k_fact_residual(int nx, int ny, int nz, const T* __restrict__ K,
 // The aggregate numbers of the row's nodes are loaded first, then all the
 // x and ec entries together.
 template <int DIM, typename T, int XMODE, bool EC>
-__global__ void k_fact_post_smooth(int nx, int ny, int nz, const T* __restrict__ K, T omega,
-                                   const T* __restrict__ b, const T* __restrict__ x,
+__global__ void k_fact_post_smooth(GridDims gd, T omega, const T* __restrict__ b, const T* __restrict__ x,
                                    const int32_t* __restrict__ agg, const T* __restrict__ ec, T* __restrict__ out) {
+  const int nx = gd.nx, ny = gd.ny, nz = gd.nz;
   const GridPos g = grid_pos();
   const int64_t N = (int64_t)nx * ny * nz;
   if (g.p >= N) return;
-  const B9<T> kb = ld9(K, g.s * 9 * SL + g.l);
   const Nbrs<DIM> n = nbrs<DIM>(nx, ny, nz, g.p);
+  const B9<T> kb = node_K<T>(gd, gd.mt + 3 * g.p, nbr_count<DIM>(n));
   int32_t a[7];
   if (EC) {
 #pragma unroll
@@ -824,10 +871,11 @@ __global__ void k_spmv_dots(int64_t n, const int32_t* __restrict__ sl, const int
 // (about 150 B per grid node).  The stored blocks are still formed (for the
 // next Galerkin product and the diagonal inverse D1); only the products use
 // this form, so they differ from the stored-block products by rounding.
-// K holds the grid blocks in member order (K[q] = K_mem[q]) and nagg the
-// level-1 aggregates of their grid neighbours ([slice][6][64] by member, -1
-// where the neighbour is missing), so that the lanes of a wavefront read
-// consecutive entries and only the x gathers depend on loaded indices.
+// mtq holds the frozen field in member order (mtq[q] = mt[mem[q]]; the
+// blocks K_i are recomputed from it) and nagg the level-1 aggregates of the
+// members' grid neighbours ([slice][6][64] by member, -1 where the neighbour
+// is missing), so that the lanes of a wavefront read consecutive entries and
+// only the x gathers depend on loaded indices.
 // MODE 0: r = b - A1 x.  MODE 1: out = x' + omega D1^{-1} (b - A1 x') with
 // x'_J = x_J + ec[agg2_J] (ec may be NULL; XZ: x = 0).  MODE 2: w = A1 v with
 // the K-cycle's partial sums (q = 0 w.w, 1 w.d1, 2 w.d2).  Four lanes per
@@ -835,8 +883,8 @@ __global__ void k_spmv_dots(int64_t n, const int32_t* __restrict__ sl, const int
 // most four), summed by a butterfly over the four lanes.
 constexpr int L1_G = L1_LANES;
 template <int DIM, typename T, int MODE, bool XZ, int ND>
-__global__ void k_l1(int nx, int ny, int nz, int64_t n1, const int32_t* __restrict__ mptr,
-                     const int32_t* __restrict__ nagg, const T* __restrict__ K,
+__global__ void k_l1(GridDims gd, int64_t n1, const int32_t* __restrict__ mptr, const int32_t* __restrict__ nagg,
+                     const double* __restrict__ mtq,
                      const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ dinv1,
                      const int32_t* __restrict__ agg2, const T* __restrict__ ec, T omega, T* __restrict__ out,
                      const T* __restrict__ d1, const T* __restrict__ d2, double* __restrict__ part) {
@@ -863,10 +911,14 @@ __global__ void k_l1(int nx, int ny, int nz, int64_t n1, const int32_t* __restri
     const int32_t q0 = mptr[I], q1 = mptr[I + 1];
     for (int32_t q = q0 + sub; q < q1; q += L1_G) {
       const int64_t sq = q / SL, lq = q - sq * SL;
-      const B9<T> kb = ld9(K, sq * 9 * SL + lq);  // blocks in member order
       int32_t a[6];
+      int deg = 0;
 #pragma unroll
-      for (int u = 0; u < 2 * DIM; ++u) a[u] = nagg[sq * 6 * SL + u * SL + lq];
+      for (int u = 0; u < 2 * DIM; ++u) {
+        a[u] = nagg[sq * 6 * SL + u * SL + lq];
+        deg += a[u] >= 0 ? 1 : 0;
+      }
+      const B9<T> kb = node_K<T>(gd, mtq + 3 * (int64_t)q, deg);  // field in member order
       V3<T> v[6];
 #pragma unroll
       for (int u = 0; u < 2 * DIM; ++u) v[u] = xv((int64_t)(a[u] >= 0 ? a[u] : 0));
@@ -947,18 +999,14 @@ __global__ void k_member_nbr_aggs(int nx, int ny, int nz, const int32_t* __restr
     if (nbr_used(DIM, t)) nagg[sq * 6 * SL + (u++) * SL + lq] = nb.h[t] ? agg[nb.q[t]] : -1;
 }
 
-// Kq[q] = K[mem[q]]: per-node blocks ([slice][9][64]) gathered into the
-// member order of the aggregates
-template <typename T>
-__global__ void k_member_blocks(int64_t n, const int32_t* __restrict__ mem, const T* __restrict__ K,
-                                T* __restrict__ Kq) {
+// mtq[q] = mt[mem[q]]: the frozen field in the member order of the aggregates
+__global__ void k_member_fields(int64_t n, const int32_t* __restrict__ mem, const double* __restrict__ mt,
+                                double* __restrict__ mtq) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   const int64_t i = mem[q];
-  const int64_t si = i / SL, sq = q / SL;
-  const int64_t a = si * 9 * SL + (i - si * SL), d = sq * 9 * SL + (q - sq * SL);
 #pragma unroll
-  for (int e = 0; e < 9; ++e) Kq[d + e * SL] = K[a + e * SL];
+  for (int c = 0; c < 3; ++c) mtq[3 * q + c] = mt[3 * i + c];
 }
 
 // rho = r - a1 w1, x = omega D^{-1} rho (first sweep of the second inner
@@ -1430,6 +1478,16 @@ void launch_scale_in(hipStream_t st, int64_t n, const double* dinv0, int left_sc
   if (n > 0)
     hipLaunchKernelGGL((k_scale_in<T>), dim3(nblk(n)), dim3(TPB), 0, st, n, dinv0, left_scale, v, vs, b0);
 }
+template <typename T>
+void launch_scale_in_grid(hipStream_t st, GridDims g, const double* v, const double* vs, T* b0) {
+  const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+  if (g.nz > 1)
+    hipLaunchKernelGGL((k_scale_in_grid<3, T>), dim3(nblk(N)), dim3(TPB), 0, st, g, v, vs, b0);
+  else
+    hipLaunchKernelGGL((k_scale_in_grid<2, T>), dim3(nblk(N)), dim3(TPB), 0, st, g, v, vs, b0);
+}
+template void launch_scale_in_grid<double>(hipStream_t, GridDims, const double*, const double*, double*);
+template void launch_scale_in_grid<float>(hipStream_t, GridDims, const double*, const double*, float*);
 
 #define LLG_INST(T)                                                                                         \
   template void launch_smooth_first<T>(hipStream_t, Sell, const T*, double, const T*, T*);                  \
@@ -1471,41 +1529,33 @@ void launch_resid_outer(hipStream_t st, Sell A, const double* val, const double*
 }
 
 template <typename TZ>
-void launch_fact_outer(hipStream_t st, GridDims g, const double* Mh, const TZ* z, double* w, hipEvent_t e0,
-                       hipEvent_t e1) {
+void launch_fact_outer(hipStream_t st, GridDims g, const TZ* z, double* w, hipEvent_t e0, hipEvent_t e1) {
   const int64_t N = (int64_t)g.nx * g.ny * g.nz;
   if (e0 && g.nz > 1)
-    hipExtLaunchKernelGGL((k_fact_outer<3, TZ>), dim3(nblk(N)), dim3(TPB), 0, st, e0, e1, 0, g.nx, g.ny, g.nz, Mh, z,
-                          w);
+    hipExtLaunchKernelGGL((k_fact_outer<3, TZ>), dim3(nblk(N)), dim3(TPB), 0, st, e0, e1, 0, g, z, w);
   else if (e0)
-    hipExtLaunchKernelGGL((k_fact_outer<2, TZ>), dim3(nblk(N)), dim3(TPB), 0, st, e0, e1, 0, g.nx, g.ny, g.nz, Mh, z,
-                          w);
+    hipExtLaunchKernelGGL((k_fact_outer<2, TZ>), dim3(nblk(N)), dim3(TPB), 0, st, e0, e1, 0, g, z, w);
   else if (g.nz > 1)
-    hipLaunchKernelGGL((k_fact_outer<3, TZ>), dim3(nblk(N)), dim3(TPB), 0, st, g.nx, g.ny, g.nz, Mh, z, w);
+    hipLaunchKernelGGL((k_fact_outer<3, TZ>), dim3(nblk(N)), dim3(TPB), 0, st, g, z, w);
   else
-    hipLaunchKernelGGL((k_fact_outer<2, TZ>), dim3(nblk(N)), dim3(TPB), 0, st, g.nx, g.ny, g.nz, Mh, z, w);
+    hipLaunchKernelGGL((k_fact_outer<2, TZ>), dim3(nblk(N)), dim3(TPB), 0, st, g, z, w);
 }
-template void launch_fact_outer<double>(hipStream_t, GridDims, const double*, const double*, double*, hipEvent_t,
-                                        hipEvent_t);
-template void launch_fact_outer<float>(hipStream_t, GridDims, const double*, const float*, double*, hipEvent_t,
-                                       hipEvent_t);
+template void launch_fact_outer<double>(hipStream_t, GridDims, const double*, double*, hipEvent_t, hipEvent_t);
+template void launch_fact_outer<float>(hipStream_t, GridDims, const float*, double*, hipEvent_t, hipEvent_t);
 
-void launch_fact_resid_outer(hipStream_t st, GridDims g, const double* Mh, const double* b, const double* u,
-                             double* r, double* part) {
+void launch_fact_resid_outer(hipStream_t st, GridDims g, const double* b, const double* u, double* r, double* part) {
   const int64_t N = (int64_t)g.nx * g.ny * g.nz;
   if (g.nz > 1)
-    hipLaunchKernelGGL(k_fact_resid_outer<3>, dim3(nblk(N)), dim3(TPB), 0, st, g.nx, g.ny, g.nz, Mh, b, u, r, part);
+    hipLaunchKernelGGL(k_fact_resid_outer<3>, dim3(nblk(N)), dim3(TPB), 0, st, g, b, u, r, part);
   else
-    hipLaunchKernelGGL(k_fact_resid_outer<2>, dim3(nblk(N)), dim3(TPB), 0, st, g.nx, g.ny, g.nz, Mh, b, u, r, part);
+    hipLaunchKernelGGL(k_fact_resid_outer<2>, dim3(nblk(N)), dim3(TPB), 0, st, g, b, u, r, part);
 }
 
 template <typename T>
-void launch_fact_residual(hipStream_t st, GridDims g, const T* K, int xmode, double omega, const T* b, const T* x,
-                          T* r) {
+void launch_fact_residual(hipStream_t st, GridDims g, int xmode, double omega, const T* b, const T* x, T* r) {
   const int64_t N = (int64_t)g.nx * g.ny * g.nz;
   const dim3 gr(nblk(N)), t(TPB);
-#define LLG_FR(D, XM) \
-  hipLaunchKernelGGL((k_fact_residual<D, T, XM>), gr, t, 0, st, g.nx, g.ny, g.nz, K, (T)omega, b, x, r)
+#define LLG_FR(D, XM) hipLaunchKernelGGL((k_fact_residual<D, T, XM>), gr, t, 0, st, g, (T)omega, b, x, r)
 #define LLG_FRD(D)        \
   if (xmode == 0)         \
     LLG_FR(D, 0);         \
@@ -1523,17 +1573,15 @@ void launch_fact_residual(hipStream_t st, GridDims g, const T* K, int xmode, dou
 }
 
 template <typename T>
-void launch_fact_post_smooth(hipStream_t st, GridDims g, const T* K, int xmode, double omega, const T* b,
-                             const T* x, const int32_t* agg, const T* ec, T* out) {
+void launch_fact_post_smooth(hipStream_t st, GridDims g, int xmode, double omega, const T* b, const T* x,
+                             const int32_t* agg, const T* ec, T* out) {
   const int64_t N = (int64_t)g.nx * g.ny * g.nz;
   const dim3 gr(nblk(N)), t(TPB);
-#define LLG_FP(D, XM)                                                                                       \
-  if (ec)                                                                                                     \
-    hipLaunchKernelGGL((k_fact_post_smooth<D, T, XM, true>), gr, t, 0, st, g.nx, g.ny, g.nz, K, (T)omega, b, x, \
-                       agg, ec, out);                                                                         \
-  else                                                                                                        \
-    hipLaunchKernelGGL((k_fact_post_smooth<D, T, XM, false>), gr, t, 0, st, g.nx, g.ny, g.nz, K, (T)omega, b,   \
-                       x, agg, ec, out)
+#define LLG_FP(D, XM)                                                                                          \
+  if (ec)                                                                                                        \
+    hipLaunchKernelGGL((k_fact_post_smooth<D, T, XM, true>), gr, t, 0, st, g, (T)omega, b, x, agg, ec, out);    \
+  else                                                                                                           \
+    hipLaunchKernelGGL((k_fact_post_smooth<D, T, XM, false>), gr, t, 0, st, g, (T)omega, b, x, agg, ec, out)
 #define LLG_FPD(D)        \
   if (xmode == 0)         \
     LLG_FP(D, 0);         \
@@ -1549,14 +1597,12 @@ void launch_fact_post_smooth(hipStream_t st, GridDims g, const T* K, int xmode, 
 #undef LLG_FPD
 #undef LLG_FP
 }
-template void launch_fact_residual<double>(hipStream_t, GridDims, const double*, int, double, const double*,
-                                           const double*, double*);
-template void launch_fact_residual<float>(hipStream_t, GridDims, const float*, int, double, const float*,
-                                          const float*, float*);
-template void launch_fact_post_smooth<double>(hipStream_t, GridDims, const double*, int, double, const double*,
-                                              const double*, const int32_t*, const double*, double*);
-template void launch_fact_post_smooth<float>(hipStream_t, GridDims, const float*, int, double, const float*,
-                                             const float*, const int32_t*, const float*, float*);
+template void launch_fact_residual<double>(hipStream_t, GridDims, int, double, const double*, const double*, double*);
+template void launch_fact_residual<float>(hipStream_t, GridDims, int, double, const float*, const float*, float*);
+template void launch_fact_post_smooth<double>(hipStream_t, GridDims, int, double, const double*, const double*,
+                                              const int32_t*, const double*, double*);
+template void launch_fact_post_smooth<float>(hipStream_t, GridDims, int, double, const float*, const float*,
+                                             const int32_t*, const float*, float*);
 
 int64_t red_blocks(int64_t m) { return std::max<int64_t>(1, std::min<int64_t>(RED_BLOCKS, ceil_div(m, TPB * 4))); }
 
@@ -1716,23 +1762,20 @@ void launch_member_nbr_aggs(hipStream_t st, GridDims g, const int32_t* mem, cons
     hipLaunchKernelGGL(k_member_nbr_aggs<2>, dim3(nblk(N)), dim3(TPB), 0, st, g.nx, g.ny, g.nz, mem, agg, nagg);
 }
 
-template <typename T>
-void launch_member_blocks(hipStream_t st, int64_t n, const int32_t* mem, const T* K, T* Kq) {
-  if (n > 0) hipLaunchKernelGGL((k_member_blocks<T>), dim3(nblk(n)), dim3(TPB), 0, st, n, mem, K, Kq);
+void launch_member_fields(hipStream_t st, int64_t n, const int32_t* mem, const double* mt, double* mtq) {
+  if (n > 0) hipLaunchKernelGGL(k_member_fields, dim3(nblk(n)), dim3(TPB), 0, st, n, mem, mt, mtq);
 }
-template void launch_member_blocks<double>(hipStream_t, int64_t, const int32_t*, const double*, double*);
-template void launch_member_blocks<float>(hipStream_t, int64_t, const int32_t*, const float*, float*);
 
 template <typename T>
 void launch_l1(hipStream_t st, GridDims g, int mode, int xzero, int64_t n1, const int32_t* mptr, const int32_t* nagg,
-               const T* K, const T* x, const T* b, const T* dinv1, const int32_t* agg2, const T* ec, double omega,
-               T* out, const T* d1, const T* d2, double* part) {
+               const double* mtq, const T* x, const T* b, const T* dinv1, const int32_t* agg2, const T* ec,
+               double omega, T* out, const T* d1, const T* d2, double* part) {
   if (n1 <= 0) return;
   const dim3 gr(nblk(n1 * L1_G)), t(TPB);
   const T om = (T)omega;
 #define LLG_L1(D, M, XZ, ND)                                                                                     \
-  hipLaunchKernelGGL((k_l1<D, T, M, XZ, ND>), gr, t, 0, st, g.nx, g.ny, g.nz, n1, mptr, nagg, K, x, b, dinv1, agg2, \
-                     ec, om, out, d1, d2, part)
+  hipLaunchKernelGGL((k_l1<D, T, M, XZ, ND>), gr, t, 0, st, g, n1, mptr, nagg, mtq, x, b, dinv1, agg2, ec, om, out, \
+                     d1, d2, part)
 #define LLG_L1D(D)                                 \
   if (mode == 0) LLG_L1(D, 0, false, 0);           \
   else if (mode == 1 && xzero) LLG_L1(D, 1, true, 0); \
@@ -1750,9 +1793,9 @@ void launch_l1(hipStream_t st, GridDims g, int mode, int xzero, int64_t n1, cons
 template void launch_l1<double>(hipStream_t, GridDims, int, int, int64_t, const int32_t*, const int32_t*,
                                 const double*, const double*, const double*, const double*, const int32_t*,
                                 const double*, double, double*, const double*, const double*, double*);
-template void launch_l1<float>(hipStream_t, GridDims, int, int, int64_t, const int32_t*, const int32_t*, const float*,
-                               const float*, const float*, const float*, const int32_t*, const float*, double, float*,
-                               const float*, const float*, double*);
+template void launch_l1<float>(hipStream_t, GridDims, int, int, int64_t, const int32_t*, const int32_t*,
+                               const double*, const float*, const float*, const float*, const int32_t*, const float*,
+                               double, float*, const float*, const float*, double*);
 #define LLG_INST_K(T)                                                                                    \
   template void launch_spmv_dots<T>(hipStream_t, Sell, const T*, const T*, T*, const T*, const T*, double*, int); \
   template void launch_kc_update<T>(hipStream_t, int64_t, const T*, const T*, const double*, T*, const T*, \

@@ -32,6 +32,96 @@ struct Sell {
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Grid sizes, and the source of the grid level's blocks for the solve
+// kernels: the frozen field mt (N x 3), prm[0] = alpha, prm[1] = dt' eps, and
+// 1/h^2 (the blocks are recomputed per node with grid_blocks).
+struct GridDims {
+  int nx, ny, nz;
+  const double* mt = nullptr;
+  const double* prm = nullptr;
+  double inv_h2 = 0.0;
+};
+
+// ---------------------------------------------------------- grid-level blocks
+// Row r of M collects the coefficients of (Lap u1, Lap u2, Lap u3) in
+// equation r of the damped component-wise system (Sec. 2.1):
+//   M = [ -a(m2^2+m3^2)     -m3 + a m1 m2     m2 + a m1 m3 ]
+//       [  m3 + a m1 m2    -a(m1^2+m3^2)     -m1 + a m2 m3 ]
+//       [ -m2 + a m1 m3     m1 + a m2 m3    -a(m1^2+m2^2)  ]
+// These functions are evaluated without contraction in every file, so that
+// the solve kernels recompute bit for bit the blocks the assembly stores.
+__device__ inline void block_M(double m1, double m2, double m3, double a, double* M) {
+#pragma clang fp contract(off)
+  M[0] = -(a * (m2 * m2 + m3 * m3));
+  M[1] = -m3 + a * (m1 * m2);
+  M[2] = m2 + a * (m1 * m3);
+  M[3] = m3 + a * (m1 * m2);
+  M[4] = -(a * (m1 * m1 + m3 * m3));
+  M[5] = -m1 + a * (m2 * m3);
+  M[6] = -m2 + a * (m1 * m3);
+  M[7] = m1 + a * (m2 * m3);
+  M[8] = -(a * (m1 * m1 + m2 * m2));
+}
+
+// 3x3 inverse: adjugate times the reciprocal of the determinant (cofactor
+// expansion along the first row).
+__device__ inline void inv3(const double* D, double* R) {
+#pragma clang fp contract(off)
+  const double a = D[0], b = D[1], c = D[2], d = D[3], e = D[4], f = D[5], g = D[6], h = D[7],
+               i = D[8];
+  double adj[9];
+  adj[0] = e * i - f * h;
+  adj[1] = c * h - b * i;
+  adj[2] = b * f - c * e;
+  adj[3] = f * g - d * i;
+  adj[4] = a * i - c * g;
+  adj[5] = c * d - a * f;
+  adj[6] = d * h - e * g;
+  adj[7] = b * g - a * h;
+  adj[8] = a * e - b * d;
+  const double det = (a * adj[0] + b * adj[3]) + c * adj[6];
+  const double rdet = 1.0 / det;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) R[k] = adj[k] * rdet;
+}
+
+// The grid level's blocks of a node with frozen field mt and deg in-grid
+// neighbours: Mh = s M (s = dt'/h^2, the off-diagonal block of A),
+// D = I + s_pp M (s_pp = -deg s, the diagonal block), Di = D^{-1} and
+// K = Di Mh (entry (r, q) summed over k = 0, 1, 2 in order; the off-diagonal
+// block of D^{-1} A).  Mh, Di or K may be NULL when not needed.
+__device__ inline void grid_blocks(const double* mt, double alpha, double dt, double inv_h2, int deg, double* Mh,
+                                   double* Di, double* K) {
+#pragma clang fp contract(off)
+  double M[9];
+  block_M(mt[0], mt[1], mt[2], alpha, M);
+  const double s_off = dt * inv_h2;
+  const double s_diag = dt * (-(double)deg * inv_h2);
+  double D[9], R[9], B[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    double v = s_diag * M[e];
+    if (e == 0 || e == 4 || e == 8) v = 1.0 + v;
+    D[e] = v;
+    B[e] = s_off * M[e];
+  }
+  inv3(D, R);
+  if (Mh) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) Mh[e] = B[e];
+  }
+  if (Di) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) Di[e] = R[e];
+  }
+  if (K) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) K[3 * r + q] = (R[3 * r] * B[q] + R[3 * r + 1] * B[3 + q]) + R[3 * r + 2] * B[6 + q];
+  }
+}
+
 // ----------------------------------------------------------------- launchers
 // Every launcher enqueues on `st` and returns nothing; launch errors are
 // collected by the caller with hipGetLastError().
@@ -113,7 +203,7 @@ template <typename T>
 void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, const double* prm,
                      int left_scale, int x0_is_mn, const double* m, const double* mprev, const double* F,
                      Sell A, double* Aval, T* Lval, double* dinv0, T* ldinv, double* b, double* u,
-                     int32_t* flag, double* Mh, T* K);
+                     int32_t* flag, double* Mh, T* K, double* mt_out);
 
 // Galerkin block sums P^T A P and the inverse diagonal blocks of the result
 // fk != NULL: the fine level is the factored grid level, whose block in slot
@@ -170,6 +260,9 @@ void launch_prolong(hipStream_t st, int64_t n, int xmode, double omega, const T*
 template <typename T>
 void launch_scale_in(hipStream_t st, int64_t n, const double* dinv0, int left_scale, const double* v,
                      const double* vs, T* b0);
+// the same with D^{-1} recomputed from the frozen field g.mt (factored grid level)
+template <typename T>
+void launch_scale_in_grid(hipStream_t st, GridDims g, const double* v, const double* vs, T* b0);
 
 // K-cycle coarse correction (two minimal-residual steps); partial sums over
 // rows_blocks(n) blocks, coefficients in kc (see k_solve.hip)
@@ -187,34 +280,28 @@ void launch_kc_coef(hipStream_t st, const double* part, int64_t G, int stage, do
 // Factored grid level (one 3x3 block per node, [slice][9][64]): Mh_p is
 // every off-diagonal block of row p of A (A_pp = I - deg_p Mh_p), K_p every
 // off-diagonal block of the left-scaled operator (unit diagonal).
-struct GridDims {
-  int nx, ny, nz;
-};
 // Level-1 products from the grid level's per-node blocks K (see k_solve.hip):
 // mode 0 r = b - A1 x; mode 1 post-smoothing sweep (xzero: x = 0; ec, agg2
 // the coarse correction or NULL); mode 2 w = A1 x with the K-cycle partial
 // sums (d1, optional d2) over rows_blocks(n1, L1_LANES) workgroups of 256
 constexpr int L1_LANES = 4;
-// Kq[q] = K[mem[q]] for the n grid nodes (K in the level-1 member order)
-template <typename T>
-void launch_member_blocks(hipStream_t st, int64_t n, const int32_t* mem, const T* K, T* Kq);
+// mtq[q] = mt[mem[q]] for the n grid nodes (the field in the level-1 member order)
+void launch_member_fields(hipStream_t st, int64_t n, const int32_t* mem, const double* mt, double* mtq);
 template <typename T>
 void launch_l1(hipStream_t st, GridDims g, int mode, int xzero, int64_t n1, const int32_t* mptr, const int32_t* nagg,
-               const T* K, const T* x, const T* b, const T* dinv1, const int32_t* agg2, const T* ec, double omega,
-               T* out, const T* d1, const T* d2, double* part);
+               const double* mtq, const T* x, const T* b, const T* dinv1, const int32_t* agg2, const T* ec,
+               double omega, T* out, const T* d1, const T* d2, double* part);
 // nagg[q][t]: level-1 aggregate of the t-th grid neighbour of member q ([slice][6][64], -1 if missing)
 void launch_member_nbr_aggs(hipStream_t st, GridDims g, const int32_t* mem, const int32_t* agg, int32_t* nagg);
 template <typename TZ>
-void launch_fact_outer(hipStream_t st, GridDims g, const double* Mh, const TZ* z, double* w,
-                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-void launch_fact_resid_outer(hipStream_t st, GridDims g, const double* Mh, const double* b, const double* u,
-                             double* r, double* part);
+void launch_fact_outer(hipStream_t st, GridDims g, const TZ* z, double* w, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr);
+void launch_fact_resid_outer(hipStream_t st, GridDims g, const double* b, const double* u, double* r, double* part);
 template <typename T>
-void launch_fact_residual(hipStream_t st, GridDims g, const T* K, int xmode, double omega, const T* b, const T* x,
-                          T* r);
+void launch_fact_residual(hipStream_t st, GridDims g, int xmode, double omega, const T* b, const T* x, T* r);
 template <typename T>
-void launch_fact_post_smooth(hipStream_t st, GridDims g, const T* K, int xmode, double omega, const T* b,
-                             const T* x, const int32_t* agg, const T* ec, T* out);
+void launch_fact_post_smooth(hipStream_t st, GridDims g, int xmode, double omega, const T* b, const T* x,
+                             const int32_t* agg, const T* ec, T* out);
 
 // Krylov baselines (BiCGstab, TFQMR): a term s c x of a linear combination
 // (c: device scalar or NULL for 1), the combination with its dots, plain
