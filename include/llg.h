@@ -148,7 +148,8 @@ typedef struct {
   int32_t kcycle_depth; /* coarse corrections of levels 1..depth by the K-cycle (two
                            minimal-residual steps, Sec. 3.1); 0 = V-cycle; 0..8 */
   int32_t graphs;       /* 1: replay the step's setup and each FGMRES iteration as HIP
-                           graphs captured once per context (default); 0: eager launches */
+                           graphs captured once per context; 0: eager launches (default:
+                           measured faster, the device stays ahead of the host either way) */
   int32_t smoother;     /* llg_smoother: damped block Jacobi (default) or multicolour
                            block Gauss-Seidel (Sec. 3 smooths by Gauss-Seidel) */
   int32_t scheme;       /* llg_scheme: BDF1 (default) or BDF2, see llg_step */
@@ -158,6 +159,14 @@ typedef struct {
   int32_t stray_field;  /* 1: reserve the stray-field workspace (zero-padded FFT grids and the
                            transformed demagnetizing tensor) for llg_step_field; 2*n-1 padded to a
                            power of two must stay <= 4096 per axis (else UNSUPPORTED) */
+  int32_t tail_nodes;   /* block-Jacobi cycles: the coarse levels below the K-cycle levels (and
+                           below level 1 when it is applied through the grid level), each of at
+                           most this many nodes, run their whole V-cycle in one workgroup with
+                           the level vectors on chip (same arithmetic, one launch instead of
+                           three per level); 0 switches it off */
+  int32_t pipeline;     /* 1: FGMRES enqueues the preconditioner and product of the next
+                           iteration before the host tests the current one's residual
+                           estimate (skipped where convergence is predicted); 0: off */
 } llg_opts;
 
 typedef struct {
@@ -172,6 +181,7 @@ typedef struct {
   double kernel_ms;
   int64_t kernel_launches;
   int32_t reorth_passes;  /* Arnoldi steps that needed a second Gram-Schmidt pass */
+  int32_t tail_level;     /* first level of the one-workgroup coarse cycle (opts.tail_nodes); 0 = none */
 } llg_stats;
 
 typedef struct llg_ctx llg_ctx;
@@ -189,7 +199,9 @@ typedef enum {
 
 /* Defaults: rtol 1e-10, restart 30, max_iters 1000, FP64, nu 1/1, omega by
  * dimension, npass 2, beta 1/4, max_coarse 40, stagnation 0.8, max_levels 40,
- * max_dense 512, left_scale 1, project 1, x0_is_mn 1, salt 0, rebuild 1. */
+ * max_dense 512, left_scale 1, project 1, x0_is_mn 1, salt 0, rebuild 1,
+ * K-cycle depth 0, graphs 0, Jacobi, BDF1, BSR grid level, DCGS2, FGMRES with
+ * the AMG cycle, no stray-field workspace, tail_nodes 128, pipeline 1. */
 void llg_default_opts(llg_opts* opts);
 
 /* Exact device bytes a context for (grid, opts) needs.  Runs the aggregation

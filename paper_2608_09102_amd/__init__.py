@@ -54,7 +54,8 @@ class Opts(ctypes.Structure):
         ("rebuild_aggregates", ctypes.c_int32), ("kcycle_depth", ctypes.c_int32),
         ("graphs", ctypes.c_int32), ("smoother", ctypes.c_int32), ("scheme", ctypes.c_int32),
         ("fine_operator", ctypes.c_int32), ("arnoldi", ctypes.c_int32), ("krylov", ctypes.c_int32),
-        ("stray_field", ctypes.c_int32),
+        ("stray_field", ctypes.c_int32), ("tail_nodes", ctypes.c_int32),
+        ("pipeline", ctypes.c_int32),
     ]
 
 
@@ -78,6 +79,7 @@ class Stats(ctypes.Structure):
         ("level_nodes", ctypes.c_int64 * MAX_LEVELS), ("level_nnzb", ctypes.c_int64 * MAX_LEVELS),
         ("ms_setup", ctypes.c_double), ("ms_solve", ctypes.c_double), ("ms_total", ctypes.c_double),
         ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int64), ("reorth_passes", ctypes.c_int32),
+        ("tail_level", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -87,7 +89,7 @@ class Stats(ctypes.Structure):
                 "level_nodes": list(self.level_nodes[:L]), "level_nnzb": list(self.level_nnzb[:L]),
                 "ms_setup": self.ms_setup, "ms_solve": self.ms_solve, "ms_total": self.ms_total,
                 "kernel_ms": self.kernel_ms, "kernel_launches": self.kernel_launches,
-                "reorth_passes": self.reorth_passes}
+                "reorth_passes": self.reorth_passes, "tail_level": self.tail_level}
 
 
 _P = ctypes.c_void_p

@@ -207,6 +207,11 @@ struct llg_ctx {
   double* dinv0 = nullptr;
   bool fact = false;
   bool f1 = false;  // level-1 products from the grid level's per-node blocks
+  // levels tail.. run their V-cycle in one workgroup (0: none)
+  int tail = 0;
+  bool tail_ok = false;
+  llg::TailArgs<double> ta64{};
+  llg::TailArgs<float> ta32{};
   double* Mh = nullptr;
   double* mt = nullptr;  // factored grid level: the frozen field, from which the solve kernels recompute blocks
   // coarsest
@@ -251,6 +256,7 @@ struct llg_ctx {
   int timed = LLG_KT_NONE;
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
+  hipEvent_t it_ev = nullptr;  // end of an FGMRES iteration's orthogonalization (pipelined loop)
   double kernel_ms = 0;
   int64_t launches = 0;
 };
@@ -298,14 +304,18 @@ void kernel_events(llg_ctx& c, int cls, hipEvent_t& e0, hipEvent_t& e1) {
 }
 
 // after a stream synchronization: add up the recorded kernel intervals
-void harvest(llg_ctx& c) {
-  for (size_t k = 0; k + 1 < c.ev_used; k += 2) {
+// Add up the timing pairs recorded before index `upto` (all by default, once
+// the stream is idle); later pairs move to the front of the pool.
+void harvest(llg_ctx& c, size_t upto = SIZE_MAX) {
+  upto = std::min(upto, c.ev_used);
+  for (size_t k = 0; k + 1 < upto; k += 2) {
     float ms = 0;
     HIPX(hipEventElapsedTime(&ms, c.ev[k], c.ev[k + 1]));
     c.kernel_ms += ms;
     c.launches += 1;
   }
-  c.ev_used = 0;
+  std::rotate(c.ev.begin(), c.ev.begin() + upto, c.ev.begin() + c.ev_used);
+  c.ev_used -= upto;
 }
 
 void sync(llg_ctx& c) {
@@ -553,6 +563,72 @@ int build_structure(llg_ctx& c, Arena& ar) {
   return l + 1;
 }
 
+// The levels from c.tail on run their V-cycle in one workgroup (k_tail):
+// block-Jacobi cycles only, below every K-cycle level and below level 1 when
+// it is applied through the grid level, each of at most opts.tail_nodes
+// nodes, at most TAIL_MAX of them, their vectors within the kernel's LDS.
+template <typename T>
+void plan_tail(llg_ctx& c, TailArgs<T>& a) {
+  const llg_opts& o = c.opts;
+  c.tail = 0;
+  if (o.tail_nodes <= 0 || o.smoother != LLG_SMOOTHER_JACOBI || c.L < 3 || !c.tail_ok) return;
+  int lo = std::max(1, o.kcycle_depth + 1);
+  if (c.f1) lo = std::max(lo, 2);
+  const int64_t ts = sizeof(T);
+  auto vb = [](int64_t n, int64_t sz) { return (3 * n * sz + 15) / 16 * 16; };
+  const int64_t nc = c.lv[c.L - 1].A.n;
+  int64_t bytes = vb(nc, 8) + vb(nc, ts);
+  int s = c.L - 1;
+  while (s - 1 >= lo && c.lv[s - 1].A.n <= o.tail_nodes && c.L - s <= TAIL_MAX) {
+    const int64_t add = 3 * vb(c.lv[s - 1].A.n, ts);
+    if (bytes + add > TAIL_LDS) break;
+    bytes += add;
+    --s;
+  }
+  if (s > c.L - 2) return;
+  a = TailArgs<T>{};
+  a.nlev = c.L - 1 - s;
+  int64_t off = 0;
+  for (int k = 0; k < a.nlev; ++k) {
+    const Level& L = c.lv[s + k];
+    TailLevel<T>& t = a.lv[k];
+    t.sl = L.A.sl_ptr;
+    t.col = L.A.col;
+    t.val = (const T*)L.val;
+    t.dinv = (const T*)L.dinv;
+    t.mptr = L.mptr;
+    t.mem = L.mem;
+    t.agg = L.agg;
+    t.n = (int32_t)L.A.n;
+    t.G = L.G;
+    t.ob = (int32_t)off;
+    t.ox = (int32_t)(off + vb(L.A.n, ts));
+    t.oy = (int32_t)(off + 2 * vb(L.A.n, ts));
+    off += 3 * vb(L.A.n, ts);
+  }
+  a.obd = (int32_t)off;
+  a.oe = (int32_t)(off + vb(nc, 8));
+  off += vb(nc, 8) + vb(nc, ts);
+  a.inv = c.dense;
+  a.nc = (int32_t)nc;
+  a.nu_pre = o.nu_pre;
+  a.nu_post = o.nu_post;
+  a.lds = (int32_t)off;
+  a.omega = (T)c.omega;
+  c.tail = s;
+}
+
+template <typename T>
+const TailArgs<T>& tail_args(const llg_ctx& c);
+template <>
+const TailArgs<double>& tail_args<double>(const llg_ctx& c) {
+  return c.ta64;
+}
+template <>
+const TailArgs<float>& tail_args<float>(const llg_ctx& c) {
+  return c.ta32;
+}
+
 // Values, vectors and Krylov storage (never materialized when planning).
 void allocate_numeric(llg_ctx& c, Arena& ar) {
   const bool f32 = c.opts.precision == LLG_PREC_FP32_AMG;
@@ -636,6 +712,10 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   c.ks.coef = ar.lazy<double>(2 * R + 4);
   c.delta = ar.lazy<double>(R + 2);
   c.prm = ar.lazy<double>(8);
+  if (f32)
+    plan_tail<float>(c, c.ta32);
+  else
+    plan_tail<double>(c, c.ta64);
   if (c.opts.stray_field) {
     c.fd = field_dims(c.grid.n[0], c.grid.n[1], c.grid.n[2]);
     const int64_t P = c.fd.px * c.fd.py * c.fd.pz;
@@ -672,7 +752,8 @@ bool opts_ok(const llg_opts* o) {
          (o->arnoldi == LLG_ARNOLDI_CGS2 || o->arnoldi == LLG_ARNOLDI_DCGS2) &&
          (o->krylov == LLG_KRYLOV_FGMRES_AMG || o->krylov == LLG_KRYLOV_GMRES || o->krylov == LLG_KRYLOV_BICGSTAB ||
           o->krylov == LLG_KRYLOV_TFQMR) &&
-         (o->stray_field == 0 || o->stray_field == 1);
+         (o->stray_field == 0 || o->stray_field == 1) && o->tail_nodes >= 0 &&
+         (o->pipeline == 0 || o->pipeline == 1);
 }
 
 // Plan for (grid, opts): cached; computed on the current device.
@@ -980,22 +1061,30 @@ void vcycle(llg_ctx& c, int l, const T* b, T* out) {
     LCHK();
   }
   const bool coarsest_next = l + 1 == c.L - 1;
+  const bool tail_next = c.tail > 0 && l + 1 == c.tail;  // the rest of the cycle in one workgroup
+  const T* rsrc = b;
   {
     KTimer kt(c, LLG_KT_RESIDUAL);
     const bool pre_next = o.nu_pre >= 1 && !coarsest_next;
-    const T* rsrc = b;
     if (xmode != 2) {
       lvl_residual<T>(c, l, xmode, b, xcur, (T*)L.r);
       rsrc = (const T*)L.r;
     }
-    if (coarsest_next)  // restriction and the exact coarsest solve in one launch
+    if (tail_next) {
+      // the fused cycle restricts rsrc itself
+    } else if (coarsest_next) {  // restriction and the exact coarsest solve in one launch
       launch_restrict_dense<T>(st, L.nc, L.mptr, L.mem, rsrc, c.dense, (T*)Nx.e);
-    else
+    } else {
       launch_restrict<T>(st, L.nc, L.mptr, L.mem, rsrc, (T*)Nx.b, pre_next ? (const T*)Nx.dinv : nullptr, om,
                          pre_next ? (T*)Nx.x : nullptr);
+    }
     LCHK();
   }
-  if (coarsest_next) {
+  if (tail_next) {
+    KTimer kt(c, LLG_KT_SMOOTH);
+    launch_tail<T>(st, tail_args<T>(c), rsrc, L.mptr, L.mem, (T*)Nx.e);
+    LCHK();
+  } else if (coarsest_next) {
     // Nx.e holds the coarse correction
   } else if (Nx.kc) {
     kcorrection<T>(c, l + 1);
@@ -1180,21 +1269,26 @@ void iter_arnoldi(llg_ctx& c, int j) {
   LCHK();
 }
 
+// The first two parts of iteration j (z_j = B v_j, w = A z_j): they write
+// only z_j and w, so they may run ahead of the convergence test of iteration
+// j - 1 (a finished solve never reads them).
 template <typename T>
-void iteration(llg_ctx& c, int j) {
-  if (use_graphs(c)) {
-    if (!c.pc_graph[j]) c.pc_graph[j] = try_capture(c, [&]() { iter_precond<T>(c, j); });
-    if (use_graphs(c) && !c.it_graph[j]) c.it_graph[j] = try_capture(c, [&]() { iter_arnoldi(c, j); });
-  }
-  if (use_graphs(c)) {
+void iteration_head(llg_ctx& c, int j) {
+  if (use_graphs(c) && !c.pc_graph[j]) c.pc_graph[j] = try_capture(c, [&]() { iter_precond<T>(c, j); });
+  if (use_graphs(c))
     HIPX(hipGraphLaunch(c.pc_graph[j], c.st));
-    iter_spmv<T>(c, j);
-    HIPX(hipGraphLaunch(c.it_graph[j], c.st));
-  } else {
+  else
     iter_precond<T>(c, j);
-    iter_spmv<T>(c, j);
+  iter_spmv<T>(c, j);
+}
+
+// The orthogonalization of iteration j (and the residual estimate to the host)
+void iteration_tail(llg_ctx& c, int j) {
+  if (use_graphs(c) && !c.it_graph[j]) c.it_graph[j] = try_capture(c, [&]() { iter_arnoldi(c, j); });
+  if (use_graphs(c))
+    HIPX(hipGraphLaunch(c.it_graph[j], c.st));
+  else
     iter_arnoldi(c, j);
-  }
 }
 
 template <typename T>
@@ -1228,12 +1322,34 @@ SolveOut fgmres(llg_ctx& c) {
     launch_cycle_start(st, R, c.ks);
     launch_scale_vec(st, m, c.r, c.ks.sc + 1, c.V);
     LCHK();
+    // Pipelined iterations: after enqueuing the orthogonalization of column
+    // j, the preconditioner and product of column j + 1 are enqueued before
+    // the host waits for the estimate of iteration j, so the device never
+    // idles during the host's test.  They are skipped when iteration j is
+    // predicted to converge (the estimate falls about geometrically: est_j ~
+    // est_{j-1}^2 / est_{j-2}), where they would be wasted work.
     int j = 0;
+    bool ahead = false;  // the head of iteration j is already enqueued
+    double e1 = -1.0, e2 = -1.0;  // the last two estimates (unscaled) of this cycle
     for (; j < R && so.iters < c.opts.max_iters; ++j) {
-      iteration<T>(c, j);
-      sync(c);
+      if (!ahead) iteration_head<T>(c, j);
+      iteration_tail(c, j);
+      bool next = c.opts.pipeline && j + 1 < R && so.iters + 1 < c.opts.max_iters;
+      if (next && e1 > 0 && e2 > 0) next = e1 * std::min(1.0, e1 / e2) > 3.0 * target;
+      if (next) {
+        HIPX(hipEventRecord(c.it_ev, st));
+        const size_t mark = c.ev_used;
+        iteration_head<T>(c, j + 1);
+        HIPX(hipEventSynchronize(c.it_ev));
+        harvest(c, mark);
+      } else {
+        sync(c);
+      }
+      ahead = next;
       ++so.iters;
       so.est = bnorm > 0 ? H[3] / bnorm : 0;
+      e2 = e1;
+      e1 = H[3];
       if (H[3] <= target || H[6] != 0.0) {
         ++j;
         break;
@@ -1442,6 +1558,7 @@ llg_status run_step(llg_ctx& c, const double* m_n, const double* m_nm1, double a
     stats->kernel_ms = c.kernel_ms;
     stats->kernel_launches = c.launches;
     stats->reorth_passes = (int32_t)c.host[7];
+    stats->tail_level = c.tail;
   }
   if (fl & F_PLAN) {
     set_err("device-side check of the hierarchy structure failed");
@@ -1504,13 +1621,15 @@ void llg_default_opts(llg_opts* o) {
   o->agg_salt = 0;
   o->rebuild_aggregates = 1;
   o->kcycle_depth = 0;
-  o->graphs = 1;
+  o->graphs = 0;
   o->smoother = LLG_SMOOTHER_JACOBI;
   o->scheme = LLG_SCHEME_BDF1;
   o->fine_operator = LLG_FINE_BSR;
   o->arnoldi = LLG_ARNOLDI_DCGS2;
   o->krylov = LLG_KRYLOV_FGMRES_AMG;
   o->stray_field = 0;
+  o->tail_nodes = 128;
+  o->pipeline = 1;
 }
 
 // combinations the library does not implement
@@ -1560,10 +1679,12 @@ llg_status llg_create(const llg_grid* grid, const llg_opts* opts, void* d_worksp
     HIPX(hipHostMalloc((void**)&c->hflags, sizeof(int32_t) * 4, hipHostMallocDefault));
     HIPX(hipHostMalloc((void**)&c->hprm, sizeof(double) * 8, hipHostMallocDefault));
     HIPX(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
+    HIPX(hipEventCreateWithFlags(&c->it_ev, hipEventDisableTiming));
     c->it_graph.assign(opts->restart, nullptr);
     c->pc_graph.assign(opts->restart, nullptr);
     init_kernel_attributes();
     init_field_attributes();
+    c->tail_ok = tail_prepare();
     Arena ar;
     ar.mode = Mode::REPLAY;
     ar.plan = plan.get();
@@ -1828,6 +1949,7 @@ llg_status llg_destroy(llg_ctx* ctx) {
   if (!ctx) return LLG_ERR_INVALID_ARG;
   (void)hipStreamSynchronize(ctx->st);
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  if (ctx->it_ev) (void)hipEventDestroy(ctx->it_ev);
   for (hipGraphExec_t g : ctx->pc_graph)
     if (g) (void)hipGraphExecDestroy(g);
   for (hipGraphExec_t g : ctx->it_graph)

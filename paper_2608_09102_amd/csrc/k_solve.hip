@@ -1350,6 +1350,170 @@ __global__ void k_solve_y(int k, int R, KrylovScalars ks) {
   }
 }
 
+// ------------------------------------------------------ fused coarse cycle
+// The rows of one level of the fused cycle, G lanes per row as in the level
+// kernels; f(i, s, l, a0, a1, a2) runs on the group's first lane with the row
+// product sum_j A_ij x_j, x in LDS.
+template <int G, typename T, typename F>
+__device__ inline void tail_rows_g(const TailLevel<T>& L, const T* x, F f) {
+  constexpr int R = TAIL_T / G;  // rows per pass
+  const int sub = (int)(threadIdx.x % G);
+  for (int i0 = 0; i0 < L.n; i0 += R) {
+    const int i = i0 + (int)(threadIdx.x / G);
+    if (i >= L.n) break;  // the lanes of a group share i
+    const int s = i / SL, l = i - s * SL;
+    const int64_t cb = L.sl[s];
+    const int w = (int)((L.sl[s + 1] - cb) / SL);
+    T a0 = 0, a1 = 0, a2 = 0;
+    sell_row_mv_g<G>(L.col, L.val, cb, w, l, sub, [&](int32_t c) { return ld3(x, (int64_t)c); }, a0, a1, a2);
+    if (sub == 0) f(i, s, l, a0, a1, a2);
+  }
+}
+template <typename T, typename F>
+__device__ inline void tail_rows(const TailLevel<T>& L, const T* x, F f) {
+  if (L.G == 16)
+    tail_rows_g<16>(L, x, f);
+  else if (L.G == 8)
+    tail_rows_g<8>(L, x, f);
+  else
+    tail_rows_g<1>(L, x, f);
+}
+
+// y = x + omega D^{-1} (b - A x), the damped block-Jacobi sweep
+template <typename T>
+__device__ inline void tail_sweep(const TailLevel<T>& L, const T* b, const T* x, T* y, T om) {
+  tail_rows(L, x, [&](int i, int s, int l, T a0, T a1, T a2) {
+    const V3<T> xi = ld3(x, (int64_t)i);
+    const V3<T> bi = ld3(b, (int64_t)i);
+    V3<T> res{bi.x - a0, bi.y - a1, bi.z - a2};
+    res = dmv(L.dinv, (int64_t)s * 9 * SL + l, res);
+    st3(y, (int64_t)i, V3<T>{xi.x + om * res.x, xi.y + om * res.y, xi.z + om * res.z});
+  });
+}
+
+// bc_I = sum of r_i over the members of aggregate I, ascending
+template <typename T>
+__device__ inline V3<T> tail_restrict_row(const int32_t* mptr, const int32_t* mem, const T* r, int I) {
+  T a0 = 0, a1 = 0, a2 = 0;
+  for (int32_t q = mptr[I]; q < mptr[I + 1]; ++q) {
+    const V3<T> v = ld3(r, (int64_t)mem[q]);
+    a0 += v.x;
+    a1 += v.y;
+    a2 += v.z;
+  }
+  return V3<T>{a0, a1, a2};
+}
+
+// The V-cycle of levels s..L-1 (Sec. 3) in one workgroup: restriction of the
+// residual of level s-1, then per level the first pre-smoothing sweep from
+// x = 0, further pre-sweeps, residual and restriction; the exact solve on the
+// coarsest level; per level upwards the prolongation of the correction and
+// the post-smoothing sweeps.  Between the steps a workgroup barrier stands
+// where the per-level path has a kernel boundary.
+template <typename T>
+__global__ void __launch_bounds__(TAIL_T) k_tail(const TailArgs<T> a, const T* __restrict__ rab,
+                                                 const int32_t* __restrict__ mptr, const int32_t* __restrict__ mem,
+                                                 T* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char tail_lds[];
+  auto vec = [&](int32_t off) { return (T*)(tail_lds + off); };
+  const int tid = (int)threadIdx.x;
+  const T om = a.omega;
+  const bool xz = a.nu_pre == 0;  // no pre-smoothing: x = 0
+  // after nu_pre - 1 further pre-sweeps x sits in the level's ox (even count) or oy
+  const bool xswap = a.nu_pre >= 2 && (a.nu_pre - 1) % 2 == 1;
+  {
+    T* B = vec(a.lv[0].ob);
+    for (int I = tid; I < a.lv[0].n; I += TAIL_T) st3(B, (int64_t)I, tail_restrict_row(mptr, mem, rab, I));
+  }
+  __syncthreads();
+  for (int k = 0; k < a.nlev; ++k) {
+    const TailLevel<T>& L = a.lv[k];
+    const T* B = vec(L.ob);
+    T* X = vec(L.ox);
+    T* Y = vec(L.oy);
+    if (!xz) {
+      for (int i = tid; i < L.n; i += TAIL_T) {
+        const int s = i / SL, l = i - s * SL;
+        const V3<T> d = dmv(L.dinv, (int64_t)s * 9 * SL + l, ld3(B, (int64_t)i));
+        st3(X, (int64_t)i, V3<T>{om * d.x, om * d.y, om * d.z});
+      }
+      __syncthreads();
+    }
+    for (int q = 1; q < a.nu_pre; ++q) {
+      tail_sweep(L, B, X, Y, om);
+      __syncthreads();
+      T* t = X;
+      X = Y;
+      Y = t;
+    }
+    const T* rs = B;
+    if (!xz) {
+      tail_rows(L, X, [&](int i, int, int, T a0, T a1, T a2) {
+        const V3<T> bi = ld3(B, (int64_t)i);
+        st3(Y, (int64_t)i, V3<T>{bi.x - a0, bi.y - a1, bi.z - a2});
+      });
+      __syncthreads();
+      rs = Y;
+    }
+    if (k + 1 < a.nlev) {
+      T* Bn = vec(a.lv[k + 1].ob);
+      for (int I = tid; I < a.lv[k + 1].n; I += TAIL_T) st3(Bn, (int64_t)I, tail_restrict_row(L.mptr, L.mem, rs, I));
+    } else {
+      double* bd = (double*)(tail_lds + a.obd);
+      for (int I = tid; I < a.nc; I += TAIL_T) {
+        const V3<T> v = tail_restrict_row(L.mptr, L.mem, rs, I);
+        bd[3 * I] = (double)v.x;
+        bd[3 * I + 1] = (double)v.y;
+        bd[3 * I + 2] = (double)v.z;
+      }
+    }
+    __syncthreads();
+  }
+  {
+    // coarsest: e = A_c^{-1} b, one wave per row, unfused multiply-add as in
+    // the standalone coarsest solve
+#pragma clang fp contract(off)
+    const double* bd = (const double*)(tail_lds + a.obd);
+    T* E = vec(a.oe);
+    const int nd = 3 * a.nc;
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int row = wv; row < nd; row += TAIL_T / 64) {
+      double s = 0.0;
+      for (int c = lane; c < nd; c += 64) s += a.inv[(int64_t)row * nd + c] * bd[c];
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+      if (lane == 0) E[row] = (T)s;
+    }
+  }
+  __syncthreads();
+  int32_t eo = a.oe;  // LDS offset of the correction of the level below
+  for (int k = a.nlev - 1; k >= 0; --k) {
+    const TailLevel<T>& L = a.lv[k];
+    const T* B = vec(L.ob);
+    T* X = vec(xswap ? L.oy : L.ox);
+    T* Y = vec(xswap ? L.ox : L.oy);
+    const T* ec = vec(eo);
+    for (int i = tid; i < L.n; i += TAIL_T) {
+      V3<T> xi = xz ? V3<T>{T(0), T(0), T(0)} : ld3((const T*)X, (int64_t)i);
+      const V3<T> e = ld3(ec, (int64_t)L.agg[i]);
+      xi.x += e.x;
+      xi.y += e.y;
+      xi.z += e.z;
+      st3(X, (int64_t)i, xi);
+    }
+    __syncthreads();
+    for (int q = 0; q < a.nu_post; ++q) {
+      tail_sweep(L, B, X, Y, om);
+      __syncthreads();
+      T* t = X;
+      X = Y;
+      Y = t;
+    }
+    eo = (int32_t)((unsigned char*)X - tail_lds);
+    if (k == 0)
+      for (int i = tid; i < 3 * L.n; i += TAIL_T) out[i] = X[i];
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- launchers
@@ -1436,6 +1600,25 @@ void launch_prolong(hipStream_t st, int64_t n, int xmode, double omega, const T*
     hipLaunchKernelGGL((k_prolong<T, 1>), g, t, 0, st, n, (T)omega, b, x, agg, ec, out);
   else
     hipLaunchKernelGGL((k_prolong<T, 2>), g, t, 0, st, n, (T)omega, b, x, agg, ec, out);
+}
+
+template <typename T>
+void launch_tail(hipStream_t st, const TailArgs<T>& a, const T* rabove, const int32_t* mptr, const int32_t* mem,
+                 T* out) {
+  hipLaunchKernelGGL((k_tail<T>), dim3(1), dim3(TAIL_T), (size_t)a.lds, st, a, rabove, mptr, mem, out);
+}
+template void launch_tail<double>(hipStream_t, const TailArgs<double>&, const double*, const int32_t*,
+                                  const int32_t*, double*);
+template void launch_tail<float>(hipStream_t, const TailArgs<float>&, const float*, const int32_t*, const int32_t*,
+                                 float*);
+
+bool tail_prepare() {
+  const bool ok = hipFuncSetAttribute((const void*)k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      TAIL_LDS) == hipSuccess &&
+                  hipFuncSetAttribute((const void*)k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      TAIL_LDS) == hipSuccess;
+  (void)hipGetLastError();
+  return ok;
 }
 
 template <typename T>

@@ -256,6 +256,44 @@ void launch_fill(hipStream_t st, T* p, int64_t n);
 template <typename T>
 void launch_prolong(hipStream_t st, int64_t n, int xmode, double omega, const T* b, const T* x,
                     const int32_t* agg, const T* ec, T* out);
+// The V-cycle of the small coarse levels s..L-1 in one workgroup (block
+// Jacobi smoothing): the level vectors live in LDS, the matrices are read
+// from global memory.  The launch takes the residual of level s-1 and the
+// aggregates of level s-1, and writes the coarse correction e_s; the
+// arithmetic of every step is that of the per-level kernels (same row
+// products, lane groups, summation orders), so the result is the same.
+constexpr int TAIL_T = 1024;    // threads of the workgroup
+constexpr int TAIL_MAX = 16;    // levels
+constexpr int TAIL_LDS = 152 * 1024;  // LDS budget (bytes)
+template <typename T>
+struct TailLevel {
+  const int32_t* sl;
+  const int32_t* col;
+  const T* val;
+  const T* dinv;
+  const int32_t* mptr;  // aggregates of this level (the next level's rows), members ascending
+  const int32_t* mem;
+  const int32_t* agg;   // node -> aggregate
+  int32_t n, G;         // rows; lanes per row (1, 8 or 16)
+  int32_t ob, ox, oy;   // LDS byte offsets of b, x and the third work vector (3 n each)
+};
+template <typename T>
+struct TailArgs {
+  TailLevel<T> lv[TAIL_MAX];  // smoothed levels s..L-2
+  const double* inv;          // coarsest level: dense inverse (nd x nd, nd = 3 nc)
+  int32_t nlev, nc;
+  int32_t obd, oe;            // LDS byte offsets: coarsest b (FP64) and its solution (T)
+  int32_t nu_pre, nu_post;
+  int32_t lds;                // LDS bytes
+  T omega;
+};
+// rabove: residual of level s-1; mptr/mem: its aggregates (the rows of level s)
+template <typename T>
+void launch_tail(hipStream_t st, const TailArgs<T>& a, const T* rabove, const int32_t* mptr, const int32_t* mem,
+                 T* out);
+// the tail kernel's LDS limit; false when the device refuses it
+bool tail_prepare();
+
 // b0 = D0^{-1} (v vs[0]) (or v vs[0]; vs NULL: 1), cast to T
 template <typename T>
 void launch_scale_in(hipStream_t st, int64_t n, const double* dinv0, int left_scale, const double* v,
