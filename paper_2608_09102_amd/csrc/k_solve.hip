@@ -1047,32 +1047,86 @@ __global__ void k_kc_combine(int64_t n, const T* __restrict__ v1, const T* __res
 // ------------------------------------------------------------- scalar work
 // One wavefront sums nparts partials in a fixed order (lane-strided sums,
 // four independent accumulators, then a shuffle tree); valid in lane 0.
+// Sum of nparts partial sums by one wave.  Sixteen loads per lane are in
+// flight at once (a vector reduction leaves 1024 partials: one round trip),
+// added in a fixed tree, so the result is reproducible.
 __device__ inline double wave_sum(const double* __restrict__ part, int64_t nparts) {
   const int lane = threadIdx.x & 63;
-  double a[4] = {0, 0, 0, 0};
-  int64_t k = lane;
-  for (; k + 192 < nparts; k += 256) {
+  double a[16];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] += part[k + 64 * u];
+  for (int u = 0; u < 16; ++u) a[u] = 0.0;
+  for (int64_t k0 = 0; k0 < nparts; k0 += 1024) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int64_t k = k0 + 64 * u + lane;
+      v[u] = k < nparts ? part[k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) a[u] += v[u];
   }
-  for (int u = 0; k < nparts; k += 64, ++u) a[u & 3] += part[k];
-  double r = (a[0] + a[1]) + (a[2] + a[3]);
+#pragma unroll
+  for (int w = 8; w > 0; w >>= 1)
+#pragma unroll
+    for (int u = 0; u < w; ++u) a[u] += a[u + w];
+  double r = a[0];
   for (int off = 32; off > 0; off >>= 1) r += __shfl_down(r, off, 64);
   return r;
+}
+
+// Sums of NQ columns of n partial sums each (column q at part + q ld) by the
+// whole workgroup (TPB-multiple size): every thread loads its entries of all
+// columns before the first add; lanes, then waves, are added in a fixed
+// tree.  The totals land in tot[0..NQ) (shared), valid after the call.
+template <int NQ>
+__device__ inline void group_sums(const double* __restrict__ part, int64_t ld, int64_t n, double* tot) {
+  __shared__ double ws[32][NQ];
+  const int nt = (int)blockDim.x, nw = nt >> 6, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double a[NQ][4];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[q][u] = 0.0;
+  for (int64_t k0 = 0; k0 < n; k0 += 4 * (int64_t)nt) {
+    double v[NQ][4];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t k = k0 + (int64_t)u * nt + threadIdx.x;
+        v[q][u] = k < n ? part[q * ld + k] : 0.0;
+      }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[q][u] += v[q][u];
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double r = (a[q][0] + a[q][1]) + (a[q][2] + a[q][3]);
+    for (int off = 32; off > 0; off >>= 1) r += __shfl_down(r, off, 64);
+    if (lane == 0) ws[wv][q] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < NQ) {
+    double r = 0.0;
+    for (int w = 0; w < nw; ++w) r += ws[w][threadIdx.x];
+    tot[threadIdx.x] = r;
+  }
+  __syncthreads();
 }
 
 // stage 1: a1 = (w1.r)/(w1.w1); stage 2: w1.rho; stage 3: the weights of
 // e = a1 v1 + a2 (v2 - gamma v1), gamma = (w1.w2)/(w1.w1),
 // a2 = (w2'.rho)/(w2'.w2') with w2' = w2 - gamma w1
 __global__ void k_kc_coef(const double* part, int64_t G, int stage, double* kc) {
-  const int wv = threadIdx.x >> 6;
   __shared__ double s[3];
-  const int nq = stage == 2 ? 1 : (stage == 1 ? 2 : 3);
-  if (wv < nq) {
-    const double v = wave_sum(part + (int64_t)wv * G, G);
-    if ((threadIdx.x & 63) == 0) s[wv] = v;
-  }
-  __syncthreads();
+  if (stage == 2)
+    group_sums<1>(part, G, G, s);
+  else if (stage == 1)
+    group_sums<2>(part, G, G, s);
+  else
+    group_sums<3>(part, G, G, s);
   if (threadIdx.x != 0) return;
   if (stage == 1) {
     kc[1] = s[0];
@@ -1274,16 +1328,13 @@ __global__ void k_dcgs_finish2(const double* part, int64_t nparts, int j, int R,
   ks.hs[j + 1] = hn;
   ks.hinv[j + 1] = 1.0 / hn;  // slot j+1 times this is the next preconditioner input
   ks.sc[4] = hn;
-  double col[MAXV_S + 2];
-  for (int i = 0; i <= j; ++i) col[i] = ks.hcol[i];
-  col[j + 1] = hn;
-  for (int i = 0; i < j; ++i) {
-    const double a = col[i], c = col[i + 1];
-    col[i] = ks.cs[i] * a + ks.sn[i] * c;
-    col[i + 1] = -ks.sn[i] * a + ks.cs[i] * c;
-  }
-  const double rho = hypot(col[j], col[j + 1]);
-  const double est = fabs(col[j + 1] / rho * ks.g[j]);
+  // rotation i changes entries i and i+1 of the column; only the running
+  // entry (i+1, the next rotation's input) is needed, and entry j+1 = hn is
+  // untouched by rotations 0..j-1
+  double t = ks.hcol[0];
+  for (int i = 0; i < j; ++i) t = -ks.sn[i] * t + ks.cs[i] * ks.hcol[i + 1];
+  const double rho = hypot(t, hn);
+  const double est = fabs(hn / rho * ks.g[j]);
   const int breakdown = (hn <= 1e-14 * sqrt(ks.sc[5]) || ks.sc[8] != 0.0) ? 1 : 0;
   ks.sc[9] = (double)breakdown;
   host[3] = est;
@@ -1933,7 +1984,7 @@ void launch_kc_combine(hipStream_t st, int64_t n, const T* v1, const T* v2, cons
   hipLaunchKernelGGL((k_kc_combine<T>), dim3(nblk(3 * n)), dim3(TPB), 0, st, n, v1, v2, kc, e);
 }
 void launch_kc_coef(hipStream_t st, const double* part, int64_t G, int stage, double* kc) {
-  hipLaunchKernelGGL(k_kc_coef, dim3(1), dim3(192), 0, st, part, G, stage, kc);
+  hipLaunchKernelGGL(k_kc_coef, dim3(1), dim3(1024), 0, st, part, G, stage, kc);
 }
 int64_t rows_blocks(int64_t n, int G) { return ceil_div(n > 0 ? n * G : 1, TPB); }
 
