@@ -692,7 +692,8 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   int64_t kparts = 0;
   for (int l = 1; l < c.L; ++l) kparts = std::max<int64_t>(kparts, 3 * rows_blocks(c.lv[l].A.n, c.lv[l].G));
   // level 1 (not the coarsest, one lane per row) applied through the grid level's blocks
-  c.f1 = c.fact && c.L > 2 && c.lv[1].G == 1 && c.opts.smoother == LLG_SMOOTHER_JACOBI;
+  // (at most two matching passes: k_l1 takes aggregates of at most four members)
+  c.f1 = c.fact && c.L > 2 && c.lv[1].G == 1 && c.opts.smoother == LLG_SMOOTHER_JACOBI && c.opts.npass <= 2;
   if (c.f1) {
     kparts = std::max<int64_t>(kparts, 3 * rows_blocks(c.lv[1].A.n, L1_LANES));
     c.lv[0].mtq = ar.lazy<double>(3 * c.lv[0].A.n);

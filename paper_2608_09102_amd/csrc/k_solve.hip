@@ -878,38 +878,56 @@ __global__ void k_spmv_dots(int64_t n, const int32_t* __restrict__ sl, const int
 // only the x gathers depend on loaded indices.
 // MODE 0: r = b - A1 x.  MODE 1: out = x' + omega D1^{-1} (b - A1 x') with
 // x'_J = x_J + ec[agg2_J] (ec may be NULL; XZ: x = 0).  MODE 2: w = A1 v with
-// the K-cycle's partial sums (q = 0 w.w, 1 w.d1, 2 w.d2).  Four lanes per
-// aggregate, one member each (an aggregate of two matching passes has at
-// most four), summed by a butterfly over the four lanes.
+// the K-cycle's partial sums (q = 0 w.w, 1 w.d1, 2 w.d2).  A workgroup
+// takes 64 consecutive aggregates and their members (an aggregate of two
+// matching passes has at most four, so at most 256): one thread per member
+// for the product, then one thread per aggregate sums its members' products
+// from LDS in the fixed order ((p0 + p2) + (p1 + p3)).
 constexpr int L1_G = L1_LANES;
+constexpr int L1_AGG = TPB / L1_G;  // aggregates per workgroup: their members fill at most TPB threads
 template <int DIM, typename T, int MODE, bool XZ, int ND>
-__global__ void k_l1(GridDims gd, int64_t n1, const int32_t* __restrict__ mptr, const int32_t* __restrict__ nagg,
-                     const double* __restrict__ mtq,
-                     const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ dinv1,
-                     const int32_t* __restrict__ agg2, const T* __restrict__ ec, T omega, T* __restrict__ out,
-                     const T* __restrict__ d1, const T* __restrict__ d2, double* __restrict__ part) {
+__global__ void __launch_bounds__(TPB) k_l1(GridDims gd, int64_t n1, const int32_t* __restrict__ mptr,
+                                            const int32_t* __restrict__ nagg, const double* __restrict__ mtq,
+                                            const T* __restrict__ x, const T* __restrict__ b,
+                                            const T* __restrict__ dinv1, const int32_t* __restrict__ agg2,
+                                            const T* __restrict__ ec, T omega, T* __restrict__ out,
+                                            const T* __restrict__ d1, const T* __restrict__ d2,
+                                            double* __restrict__ part) {
+  __shared__ T pm[3][TPB];  // member products, by member slot in the workgroup
   __shared__ double sh[(TPB / 64) * (ND + 1)];
   __shared__ double res[ND + 1];
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t I = t / L1_G;
-  const int sub = (int)(t - I * L1_G);
-  double dots[ND + 1];
-#pragma unroll
-  for (int q = 0; q <= ND; ++q) dots[q] = 0.0;
-  V3<T> acc{T(0), T(0), T(0)};
-  if (I < n1) {
-    auto xv = [&](int64_t J) {
-      V3<T> v = XZ ? V3<T>{T(0), T(0), T(0)} : ld3(x, J);
-      if (MODE == 1 && ec) {
-        const V3<T> e = ld3(ec, (int64_t)agg2[J]);
-        v.x += e.x;
-        v.y += e.y;
-        v.z += e.z;
-      }
-      return v;
-    };
-    const int32_t q0 = mptr[I], q1 = mptr[I + 1];
-    for (int32_t q = q0 + sub; q < q1; q += L1_G) {
+  const int64_t I0 = (int64_t)blockIdx.x * L1_AGG;
+  const int64_t I1 = min(I0 + (int64_t)L1_AGG, n1);
+  const int32_t qa = mptr[I0], qb = mptr[I1];  // the workgroup's members
+  const int tid = (int)threadIdx.x;
+  auto xv = [&](int64_t J) {
+    V3<T> v = XZ ? V3<T>{T(0), T(0), T(0)} : ld3(x, J);
+    if (MODE == 1 && ec) {
+      const V3<T> e = ld3(ec, (int64_t)agg2[J]);
+      v.x += e.x;
+      v.y += e.y;
+      v.z += e.z;
+    }
+    return v;
+  };
+  // the aggregate's own operands (threads 0..L1_AGG-1), issued before the member work
+  const int64_t I = I0 + tid;
+  const bool own = tid < L1_AGG && I < I1;
+  int32_t m0 = 0, m1 = 0;
+  V3<T> xI{T(0), T(0), T(0)}, bI{T(0), T(0), T(0)}, dd1{T(0), T(0), T(0)}, dd2{T(0), T(0), T(0)};
+  if (own) {
+    m0 = mptr[I];
+    m1 = mptr[I + 1];
+    xI = xv(I);
+    if (MODE != 2) bI = ld3(b, I);
+    if (MODE == 2 && ND >= 1) dd1 = ld3(d1, I);
+    if (MODE == 2 && ND >= 2) dd2 = ld3(d2, I);
+  }
+  // one member per thread: K_i sum_{j~i} x'_agg(j)
+  {
+    const int32_t q = qa + tid;
+    V3<T> kx{T(0), T(0), T(0)};
+    if (q < qb) {
       const int64_t sq = q / SL, lq = q - sq * SL;
       int32_t a[6];
       int deg = 0;
@@ -929,53 +947,42 @@ __global__ void k_l1(GridDims gd, int64_t n1, const int32_t* __restrict__ mptr, 
         sx.y += a[u] >= 0 ? v[u].y : T(0);
         sx.z += a[u] >= 0 ? v[u].z : T(0);
       }
-      const V3<T> kx = mv9(kb, sx);
-      acc.x += kx.x;
-      acc.y += kx.y;
-      acc.z += kx.z;
+      const V3<T> p = mv9(kb, sx);
+      kx = V3<T>{T(0) + p.x, T(0) + p.y, T(0) + p.z};
     }
-#pragma unroll
-    for (int off = L1_G / 2; off > 0; off >>= 1) {
-      acc.x += __shfl_xor(acc.x, off, L1_G);
-      acc.y += __shfl_xor(acc.y, off, L1_G);
-      acc.z += __shfl_xor(acc.z, off, L1_G);
-    }
+    pm[0][tid] = kx.x;
+    pm[1][tid] = kx.y;
+    pm[2][tid] = kx.z;
   }
-  if (I < n1 && sub == 0) {
-    auto xv = [&](int64_t J) {
-      V3<T> v = XZ ? V3<T>{T(0), T(0), T(0)} : ld3(x, J);
-      if (MODE == 1 && ec) {
-        const V3<T> e = ld3(ec, (int64_t)agg2[J]);
-        v.x += e.x;
-        v.y += e.y;
-        v.z += e.z;
-      }
-      return v;
-    };
-    const int32_t q0 = mptr[I], q1 = mptr[I + 1];
-    const V3<T> xI = xv(I);
-    const T m = (T)(q1 - q0);
+  __syncthreads();
+  double dots[ND + 1];
+#pragma unroll
+  for (int q = 0; q <= ND; ++q) dots[q] = 0.0;
+  if (own) {
+    // the member sums in the fixed order ((p0 + p2) + (p1 + p3)), absent members 0
+    V3<T> p[L1_G];
+#pragma unroll
+    for (int k = 0; k < L1_G; ++k) {
+      const bool h = m0 + k < m1;
+      const int sl = h ? m0 + k - qa : 0;
+      p[k] = h ? V3<T>{pm[0][sl], pm[1][sl], pm[2][sl]} : V3<T>{T(0), T(0), T(0)};
+    }
+    const V3<T> acc{(p[0].x + p[2].x) + (p[1].x + p[3].x), (p[0].y + p[2].y) + (p[1].y + p[3].y),
+                    (p[0].z + p[2].z) + (p[1].z + p[3].z)};
+    const T m = (T)(m1 - m0);
     const V3<T> ax{m * xI.x + acc.x, m * xI.y + acc.y, m * xI.z + acc.z};
     if (MODE == 0) {
-      const V3<T> bi = ld3(b, I);
-      st3(out, I, V3<T>{bi.x - ax.x, bi.y - ax.y, bi.z - ax.z});
+      st3(out, I, V3<T>{bI.x - ax.x, bI.y - ax.y, bI.z - ax.z});
     } else if (MODE == 1) {
-      const V3<T> bi = ld3(b, I);
       const int64_t s1 = I / SL;
-      const V3<T> d = dmv(dinv1, s1 * 9 * SL + (I - s1 * SL), V3<T>{bi.x - ax.x, bi.y - ax.y, bi.z - ax.z});
+      const V3<T> d = dmv(dinv1, s1 * 9 * SL + (I - s1 * SL), V3<T>{bI.x - ax.x, bI.y - ax.y, bI.z - ax.z});
       st3(out, I, V3<T>{xI.x + omega * d.x, xI.y + omega * d.y, xI.z + omega * d.z});
     } else {
       st3(out, I, ax);
       const double w0 = ax.x, w1 = ax.y, w2 = ax.z;
       dots[0] = (w0 * w0 + w1 * w1) + w2 * w2;
-      if (ND >= 1) {
-        const V3<T> dd = ld3(d1, I);
-        dots[1 % (ND + 1)] = (w0 * (double)dd.x + w1 * (double)dd.y) + w2 * (double)dd.z;
-      }
-      if (ND >= 2) {
-        const V3<T> dd = ld3(d2, I);
-        dots[2 % (ND + 1)] = (w0 * (double)dd.x + w1 * (double)dd.y) + w2 * (double)dd.z;
-      }
+      if (ND >= 1) dots[1 % (ND + 1)] = (w0 * (double)dd1.x + w1 * (double)dd1.y) + w2 * (double)dd1.z;
+      if (ND >= 2) dots[2 % (ND + 1)] = (w0 * (double)dd2.x + w1 * (double)dd2.y) + w2 * (double)dd2.z;
     }
   }
   if (MODE == 2) {
