@@ -520,7 +520,8 @@ int build_structure(llg_ctx& c, Arena& ar) {
       int32_t* cj = ar.alloc<int32_t>(ncand);
       int32_t* cwt = ar.alloc<int32_t>(ncand);
       int32_t* nrp = ar.alloc<int32_t>(nc + 1);
-      launch_cg_fill(st, nc, lead, mate, crp, cci, cw, aggp, cnt, cj, cwt, nrp);
+      // rows of the coarse levels of a 3D grid reach about 50 candidates
+      launch_cg_fill(st, nc, lead, mate, crp, cci, cw, aggp, cnt, cj, cwt, nrp, nz > 1 && l > 0);
       launch_scan_excl(st, nrp, nrp, nc, nrp + nc, c.scan_tmp);
       LCHK();
       const int64_t ng = ar.count(nrp + nc);

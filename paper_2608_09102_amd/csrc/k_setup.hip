@@ -390,10 +390,10 @@ __global__ void k_cg_count(int64_t nc, const int32_t* lead, const int32_t* mate,
 
 // Coarse graph row I: (agg(j), w) over the rows of the (one or two) members,
 // sorted by coarse column, duplicates summed, the diagonal dropped.  Rows of
-// up to 32 candidates are sorted in registers by a bitonic network (their
-// padding sorts last); longer rows by insertion into their output range.
+// up to 32 (or 64) candidates are sorted in registers by a bitonic network
+// (their padding sorts last); longer rows by insertion into their output range.
 template <int CM>
-__device__ inline int32_t cg_row_small(int32_t I, int32_t c, int32_t ka, int32_t na, int32_t kb,
+__device__ __forceinline__ int32_t cg_row_small(int32_t I, int32_t c, int32_t ka, int32_t na, int32_t kb,
                                        const int32_t* __restrict__ gci, const int32_t* __restrict__ gw,
                                        const int32_t* __restrict__ agg, int32_t* cj, int32_t* cw, int32_t o) {
   int32_t J[CM], W[CM];
@@ -450,11 +450,14 @@ __device__ inline int32_t cg_row_small(int32_t I, int32_t c, int32_t ka, int32_t
   return u;
 }
 
-__global__ void k_cg_fill(int64_t nc, const int32_t* lead, const int32_t* mate, const int32_t* grp,
-                          const int32_t* gci, const int32_t* gw, const int32_t* agg,
-                          const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt) {
-  int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nc) return;
+// CMAX: the widest register sort the kernel carries (32, or 64 for the coarse
+// levels of 3D grids, whose rows reach about 50 candidates; 64 costs twice
+// the registers, so the 2D levels and the 3D grid level keep 32).  Longer
+// rows fall back to insertion into their output range.
+template <int CMAX>
+__device__ __forceinline__ void cg_fill_row(int64_t I, const int32_t* lead, const int32_t* mate, const int32_t* grp,
+                                   const int32_t* gci, const int32_t* gw, const int32_t* agg,
+                                   const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt) {
   const int32_t a = lead[I], b = mate[a];
   const int32_t o = cptr[I];
   const int32_t ka = grp[a], na = grp[a + 1] - ka;
@@ -471,6 +474,12 @@ __global__ void k_cg_fill(int64_t nc, const int32_t* lead, const int32_t* mate, 
   if (nall <= 32) {
     ucnt[I] = cg_row_small<32>((int32_t)I, nall, ka, na, kb, gci, gw, agg, cj, cw, o);
     return;
+  }
+  if constexpr (CMAX >= 64) {
+    if (nall <= 64) {
+      ucnt[I] = cg_row_small<64>((int32_t)I, nall, ka, na, kb, gci, gw, agg, cj, cw, o);
+      return;
+    }
   }
   int32_t c = 0;
   for (int mem = 0; mem < 2; ++mem) {
@@ -504,6 +513,21 @@ __global__ void k_cg_fill(int64_t nc, const int32_t* lead, const int32_t* mate, 
     }
   }
   ucnt[I] = u;
+}
+__global__ void k_cg_fill(int64_t nc, const int32_t* lead, const int32_t* mate, const int32_t* grp,
+                          const int32_t* gci, const int32_t* gw, const int32_t* agg, const int32_t* cptr,
+                          int32_t* cj, int32_t* cw, int32_t* ucnt) {
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I < nc) cg_fill_row<32>(I, lead, mate, grp, gci, gw, agg, cptr, cj, cw, ucnt);
+}
+// the 64-wide sort needs about 256 registers: bounded to TPB threads so that
+// it has them without spilling
+__global__ void __launch_bounds__(TPB) k_cg_fill_wide(int64_t nc, const int32_t* lead, const int32_t* mate,
+                                                      const int32_t* grp, const int32_t* gci, const int32_t* gw,
+                                                      const int32_t* agg, const int32_t* cptr, int32_t* cj,
+                                                      int32_t* cw, int32_t* ucnt) {
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I < nc) cg_fill_row<64>(I, lead, mate, grp, gci, gw, agg, cptr, cj, cw, ucnt);
 }
 
 __global__ void k_cg_copy(int64_t nc, const int32_t* cptr, const int32_t* cj, const int32_t* cw,
@@ -1188,10 +1212,14 @@ void launch_cg_count(hipStream_t st, int64_t nc, const int32_t* lead, const int3
 }
 void launch_cg_fill(hipStream_t st, int64_t nc, const int32_t* lead, const int32_t* mate,
                     const int32_t* grp, const int32_t* gci, const int32_t* gw, const int32_t* agg,
-                    const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt) {
-  if (nc > 0)
-    hipLaunchKernelGGL(k_cg_fill, dim3(nblk(nc)), dim3(TPB), 0, st, nc, lead, mate, grp, gci, gw, agg,
-                       cptr, cj, cw, ucnt);
+                    const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt, int wide) {
+  if (nc <= 0) return;
+  if (wide)
+    hipLaunchKernelGGL(k_cg_fill_wide, dim3(nblk(nc)), dim3(TPB), 0, st, nc, lead, mate, grp, gci, gw, agg, cptr,
+                       cj, cw, ucnt);
+  else
+    hipLaunchKernelGGL(k_cg_fill, dim3(nblk(nc)), dim3(TPB), 0, st, nc, lead, mate, grp, gci, gw, agg, cptr,
+                       cj, cw, ucnt);
 }
 void launch_cg_copy(hipStream_t st, int64_t nc, const int32_t* cptr, const int32_t* cj,
                     const int32_t* cw, const int32_t* nrp, int32_t* nci, int32_t* nw) {

@@ -394,15 +394,33 @@ __global__ void k_resid_outer(int64_t n, const int32_t* __restrict__ sl, const i
 // the [slice][9][64] layout, neighbours from the grid:
 //   (A z)_p = z_p + Mh_p (sum_q z_q - deg_p z_p),   (Atilde x)_p = x_p + K_p sum_q x_q.
 struct GridPos {
-  int64_t p, s;
-  int l;
+  int64_t p;
+  bool ok;
 };
-__device__ inline GridPos grid_pos() {  // launched with TPB threads per block
-  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+// Node of this thread.  2D: XCD-aware block order over the node index.  3D:
+// XCD x (= blockIdx mod 8, the dispatch order of the chip) takes the y rows
+// [x ny/8, (x+1) ny/8) of every plane and walks them plane by plane.  The
+// planes k-1, k, k+1 that a stencil row reads then stay in that XCD's L2: a
+// contiguous z-slab per XCD keeps whole planes in flight, and at 256^3 their
+// three-plane reuse window (4.7 MB of FP64 vector) overflows the L2, so each
+// vector entry was fetched about three times.  Launched with grid_blocks().
+template <int DIM>
+__device__ inline GridPos grid_pos(const GridDims& gd) {
   GridPos g;
-  g.p = (int64_t)blk * TPB + threadIdx.x;
-  g.s = g.p / SL;
-  g.l = (int)(g.p - g.s * SL);
+  if (DIM == 2) {
+    g.p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+    g.ok = g.p < (int64_t)gd.nx * gd.ny;
+    return g;
+  }
+  const uint32_t x = blockIdx.x & 7u, k = blockIdx.x >> 3;
+  const uint32_t nx = (uint32_t)gd.nx, ny = (uint32_t)gd.ny;
+  const uint32_t j0 = (x * ny) >> 3, j1 = ((x + 1) * ny) >> 3;
+  const uint32_t row = (j1 - j0) * nx;  // nodes of the band in one plane
+  const uint32_t t = k * TPB + threadIdx.x;
+  g.ok = t < row * (uint32_t)gd.nz;
+  const uint32_t kz = g.ok ? t / row : 0, r = t - kz * row;
+  const uint32_t jj = r / nx, i = r - jj * nx;
+  g.p = ((int64_t)kz * ny + j0 + jj) * nx + i;
   return g;
 }
 
@@ -535,9 +553,8 @@ __global__ void k_scale_in_grid(GridDims gd, const double* __restrict__ v, const
 template <int DIM, typename TZ>
 __global__ void k_fact_outer(GridDims gd, const TZ* __restrict__ z, double* __restrict__ w) {
   const int nx = gd.nx, ny = gd.ny, nz = gd.nz;
-  const GridPos g = grid_pos();
-  const int64_t N = (int64_t)nx * ny * nz;
-  if (g.p >= N) return;
+  const GridPos g = grid_pos<DIM>(gd);
+  if (!g.ok) return;
   const B9<double> m = node_Mh(gd, g.p, nbr_count<DIM>(nbrs<DIM>(nx, ny, nz, g.p)));
   auto zd = [&](int64_t q) {
     const V3<TZ> t = ld3(z, q);
@@ -582,9 +599,8 @@ template <int DIM, typename T, int XMODE>
 __global__ void k_fact_residual(GridDims gd, T omega, const T* __restrict__ b, const T* __restrict__ x,
                                 T* __restrict__ r) {
   const int nx = gd.nx, ny = gd.ny, nz = gd.nz;
-  const GridPos g = grid_pos();
-  const int64_t N = (int64_t)nx * ny * nz;
-  if (g.p >= N) return;
+  const GridPos g = grid_pos<DIM>(gd);
+  if (!g.ok) return;
   const B9<T> kb = node_K<T>(gd, gd.mt + 3 * g.p, nbr_count<DIM>(nbrs<DIM>(nx, ny, nz, g.p)));
   int deg;
   const V3<T> sx =
@@ -602,9 +618,8 @@ template <int DIM, typename T, int XMODE, bool EC>
 __global__ void k_fact_post_smooth(GridDims gd, T omega, const T* __restrict__ b, const T* __restrict__ x,
                                    const int32_t* __restrict__ agg, const T* __restrict__ ec, T* __restrict__ out) {
   const int nx = gd.nx, ny = gd.ny, nz = gd.nz;
-  const GridPos g = grid_pos();
-  const int64_t N = (int64_t)nx * ny * nz;
-  if (g.p >= N) return;
+  const GridPos g = grid_pos<DIM>(gd);
+  if (!g.ok) return;
   const Nbrs<DIM> n = nbrs<DIM>(nx, ny, nz, g.p);
   const B9<T> kb = node_K<T>(gd, gd.mt + 3 * g.p, nbr_count<DIM>(n));
   int32_t a[7];
@@ -896,7 +911,11 @@ __global__ void __launch_bounds__(TPB) k_l1(GridDims gd, int64_t n1, const int32
   __shared__ T pm[3][TPB];  // member products, by member slot in the workgroup
   __shared__ double sh[(TPB / 64) * (ND + 1)];
   __shared__ double res[ND + 1];
-  const int64_t I0 = (int64_t)blockIdx.x * L1_AGG;
+  // XCD-contiguous aggregate ranges: the neighbour aggregates a member
+  // gathers (ids near its own, one grid row and one grid plane away) are then
+  // read by the same XCD, from its L2
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t I0 = (int64_t)blk * L1_AGG;
   const int64_t I1 = min(I0 + (int64_t)L1_AGG, n1);
   const int32_t qa = mptr[I0], qb = mptr[I1];  // the workgroup's members
   const int tid = (int)threadIdx.x;
@@ -987,7 +1006,7 @@ __global__ void __launch_bounds__(TPB) k_l1(GridDims gd, int64_t n1, const int32
   }
   if (MODE == 2) {
     block_sums<ND + 1>(dots, sh, res);
-    if (threadIdx.x <= ND) part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = res[threadIdx.x];
+    if (threadIdx.x <= ND) part[(int64_t)threadIdx.x * gridDim.x + blk] = res[threadIdx.x];
   }
 }
 
@@ -1769,17 +1788,22 @@ void launch_resid_outer(hipStream_t st, Sell A, const double* val, const double*
   hipLaunchKernelGGL(k_resid_outer, dim3(nblk(A.n)), dim3(TPB), 0, st, A.n, A.sl_ptr, A.col, val, b, u, r, part);
 }
 
+// workgroups of the grid-level stencil kernels (the node order of grid_pos)
+inline unsigned grid_blocks(const GridDims& g) {
+  if (g.nz <= 1) return nblk((int64_t)g.nx * g.ny);
+  return 8u * nblk((int64_t)((g.ny + 7) / 8) * g.nx * g.nz);
+}
+
 template <typename TZ>
 void launch_fact_outer(hipStream_t st, GridDims g, const TZ* z, double* w, hipEvent_t e0, hipEvent_t e1) {
-  const int64_t N = (int64_t)g.nx * g.ny * g.nz;
   if (e0 && g.nz > 1)
-    hipExtLaunchKernelGGL((k_fact_outer<3, TZ>), dim3(nblk(N)), dim3(TPB), 0, st, e0, e1, 0, g, z, w);
+    hipExtLaunchKernelGGL((k_fact_outer<3, TZ>), dim3(grid_blocks(g)), dim3(TPB), 0, st, e0, e1, 0, g, z, w);
   else if (e0)
-    hipExtLaunchKernelGGL((k_fact_outer<2, TZ>), dim3(nblk(N)), dim3(TPB), 0, st, e0, e1, 0, g, z, w);
+    hipExtLaunchKernelGGL((k_fact_outer<2, TZ>), dim3(grid_blocks(g)), dim3(TPB), 0, st, e0, e1, 0, g, z, w);
   else if (g.nz > 1)
-    hipLaunchKernelGGL((k_fact_outer<3, TZ>), dim3(nblk(N)), dim3(TPB), 0, st, g, z, w);
+    hipLaunchKernelGGL((k_fact_outer<3, TZ>), dim3(grid_blocks(g)), dim3(TPB), 0, st, g, z, w);
   else
-    hipLaunchKernelGGL((k_fact_outer<2, TZ>), dim3(nblk(N)), dim3(TPB), 0, st, g, z, w);
+    hipLaunchKernelGGL((k_fact_outer<2, TZ>), dim3(grid_blocks(g)), dim3(TPB), 0, st, g, z, w);
 }
 template void launch_fact_outer<double>(hipStream_t, GridDims, const double*, double*, hipEvent_t, hipEvent_t);
 template void launch_fact_outer<float>(hipStream_t, GridDims, const float*, double*, hipEvent_t, hipEvent_t);
@@ -1794,8 +1818,7 @@ void launch_fact_resid_outer(hipStream_t st, GridDims g, const double* b, const 
 
 template <typename T>
 void launch_fact_residual(hipStream_t st, GridDims g, int xmode, double omega, const T* b, const T* x, T* r) {
-  const int64_t N = (int64_t)g.nx * g.ny * g.nz;
-  const dim3 gr(nblk(N)), t(TPB);
+  const dim3 gr(grid_blocks(g)), t(TPB);
 #define LLG_FR(D, XM) hipLaunchKernelGGL((k_fact_residual<D, T, XM>), gr, t, 0, st, g, (T)omega, b, x, r)
 #define LLG_FRD(D)        \
   if (xmode == 0)         \
@@ -1816,8 +1839,7 @@ void launch_fact_residual(hipStream_t st, GridDims g, int xmode, double omega, c
 template <typename T>
 void launch_fact_post_smooth(hipStream_t st, GridDims g, int xmode, double omega, const T* b, const T* x,
                              const int32_t* agg, const T* ec, T* out) {
-  const int64_t N = (int64_t)g.nx * g.ny * g.nz;
-  const dim3 gr(nblk(N)), t(TPB);
+  const dim3 gr(grid_blocks(g)), t(TPB);
 #define LLG_FP(D, XM)                                                                                          \
   if (ec)                                                                                                        \
     hipLaunchKernelGGL((k_fact_post_smooth<D, T, XM, true>), gr, t, 0, st, g, (T)omega, b, x, agg, ec, out);    \

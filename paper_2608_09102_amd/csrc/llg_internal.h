@@ -182,7 +182,7 @@ void launch_cg_count(hipStream_t st, int64_t nc, const int32_t* lead, const int3
                      const int32_t* grp, int32_t* cnt);
 void launch_cg_fill(hipStream_t st, int64_t nc, const int32_t* lead, const int32_t* mate,
                     const int32_t* grp, const int32_t* gci, const int32_t* gw, const int32_t* agg,
-                    const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt);
+                    const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt, int wide);
 void launch_cg_copy(hipStream_t st, int64_t nc, const int32_t* cptr, const int32_t* cj,
                     const int32_t* cw, const int32_t* nrp, int32_t* nci, int32_t* nw);
 void launch_compose(hipStream_t st, int64_t n, int32_t* acc, const int32_t* aggp, int first);
