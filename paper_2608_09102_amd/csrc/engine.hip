@@ -477,6 +477,11 @@ int build_structure(llg_ctx& c, Arena& ar) {
       launch_row_max(st, cn, crp, cw, mx);
       launch_fill_i32(st, mate, cn, -1);
       LCHK();
+      // lanes per node in a proposal round: about two slots per lane on the
+      // coarse levels (latency bound), one lane on the grid-sized levels
+      int lanes = 1;
+      if (cn < (int64_t(1) << 20))
+        while (lanes < 16 && (int64_t)2 * lanes * cn < cg) lanes *= 2;
       // handshake rounds: PLAN runs until a round has no proposal and logs
       // the number of rounds; REPLAY runs that many and checks the extra
       // round proposes nothing
@@ -484,7 +489,7 @@ int build_structure(llg_ctx& c, Arena& ar) {
         int64_t rounds = 0;
         for (;;) {
           launch_fill_i32(st, c.count, 1, 0);
-          launch_propose(st, cn, crp, cci, cw, mx, mate, rank, salt, o.beta_num, o.beta_den, prop, c.count);
+          launch_propose(st, cn, crp, cci, cw, mx, mate, rank, salt, o.beta_num, o.beta_den, prop, c.count, lanes);
           LCHK();
           HIPX(hipMemcpyAsync(ar.hcount, c.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
           HIPX(hipStreamSynchronize(st));
@@ -499,11 +504,11 @@ int build_structure(llg_ctx& c, Arena& ar) {
         const int64_t rounds = ar.plan->counts[ar.ci++];
         launch_fill_i32(st, c.count + 1, 1, 0);
         for (int64_t r = 0; r < rounds; ++r) {
-          launch_propose(st, cn, crp, cci, cw, mx, mate, rank, salt, o.beta_num, o.beta_den, prop, c.count + 1);
+          launch_propose(st, cn, crp, cci, cw, mx, mate, rank, salt, o.beta_num, o.beta_den, prop, c.count + 1, lanes);
           launch_accept(st, cn, prop, mate);
         }
         launch_fill_i32(st, c.count, 1, 0);
-        launch_propose(st, cn, crp, cci, cw, mx, mate, rank, salt, o.beta_num, o.beta_den, prop, c.count);
+        launch_propose(st, cn, crp, cci, cw, mx, mate, rank, salt, o.beta_num, o.beta_den, prop, c.count, lanes);
         launch_check_eq(st, c.count, 0, c.flags, F_PLAN);
         LCHK();
       }

@@ -290,61 +290,82 @@ __global__ void k_row_max(int64_t n, const int32_t* grp, const int32_t* gw, int3
 // Handshake round: every free node proposes its best available edge (both
 // endpoints free, strong for the first-visited endpoint).  Neighbours are
 // examined four at a time so that their loads are in flight together.
-__global__ void k_propose(int64_t n, const int32_t* __restrict__ grp, const int32_t* __restrict__ gci,
-                          const int32_t* __restrict__ gw, const int32_t* __restrict__ mx,
-                          const int32_t* __restrict__ mate, const uint64_t* __restrict__ rank, uint64_t salt,
-                          int32_t bnum, int32_t bden, int32_t* __restrict__ prop, int32_t* count) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool proposed = false;
-  if (i < n) {
-    int32_t best = -1;
-    if (mate[i] < 0) {
-      const uint64_t ri = rank[i];
-      const int32_t mxi = mx[i];
-      const int32_t k1 = grp[i + 1];
-      EdgeKey bk{};
-      for (int32_t k0 = grp[i]; k0 < k1; k0 += 4) {
-        int32_t jj[4], ww[4];
+// One handshake round: every free node proposes its earliest candidate edge
+// (strong for its first-visited endpoint, other end free).  G lanes share a
+// node (coarse levels: their rows are long and the dependent loads of a row
+// walk are the round's latency); each lane walks every G-th slot, then a
+// butterfly keeps the earliest key.  The order is strict, so the result does
+// not depend on G.
+template <int G>
+__global__ void __launch_bounds__(TPB) k_propose(int64_t n, const int32_t* __restrict__ grp,
+                                                 const int32_t* __restrict__ gci, const int32_t* __restrict__ gw,
+                                                 const int32_t* __restrict__ mx, const int32_t* __restrict__ mate,
+                                                 const uint64_t* __restrict__ rank, uint64_t salt, int32_t bnum,
+                                                 int32_t bden, int32_t* __restrict__ prop, int32_t* count) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t / G;
+  const int sub = (int)(t - i * G);
+  int32_t best = -1;
+  EdgeKey bk{};
+  if (i < n && mate[i] < 0) {
+    const uint64_t ri = rank[i];
+    const int32_t mxi = mx[i];
+    const int32_t k1 = grp[i + 1];
+    for (int32_t k0 = grp[i] + sub; k0 < k1; k0 += 4 * G) {
+      int32_t jj[4], ww[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const bool ok = k0 + u < k1;
-          jj[u] = ok ? gci[k0 + u] : -1;
-          ww[u] = ok ? gw[k0 + u] : 0;
-        }
-        bool fr[4];
+      for (int u = 0; u < 4; ++u) {
+        const bool ok = k0 + u * G < k1;
+        jj[u] = ok ? gci[k0 + u * G] : -1;
+        ww[u] = ok ? gw[k0 + u * G] : 0;
+      }
+      bool fr[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) fr[u] = jj[u] >= 0 && mate[jj[u]] < 0;
-        uint64_t rr[4];
-        int32_t mj[4];
+      for (int u = 0; u < 4; ++u) fr[u] = jj[u] >= 0 && mate[jj[u]] < 0;
+      uint64_t rr[4];
+      int32_t mj[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          rr[u] = fr[u] ? rank[jj[u]] : 0;
-          mj[u] = fr[u] ? mx[jj[u]] : 0;
-        }
+      for (int u = 0; u < 4; ++u) {
+        rr[u] = fr[u] ? rank[jj[u]] : 0;
+        mj[u] = fr[u] ? mx[jj[u]] : 0;
+      }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (!fr[u]) continue;
-          const int32_t j = jj[u], w = ww[u];
-          const uint64_t rj = rr[u];
-          const bool ifirst = ri != rj ? ri < rj : i < j;
-          const int32_t mf = ifirst ? mxi : mj[u];
-          if ((int64_t)bden * w < (int64_t)bnum * mf) continue;
-          EdgeKey e;
-          e.rank = ifirst ? ri : rj;
-          e.first = ifirst ? (int32_t)i : j;
-          e.w = w;
-          e.lo = (int32_t)min((int64_t)j, i);
-          e.hi = (int32_t)max((int64_t)j, i);
-          if (best < 0 || key_before(e, bk, salt)) {
-            bk = e;
-            best = j;
-          }
+      for (int u = 0; u < 4; ++u) {
+        if (!fr[u]) continue;
+        const int32_t j = jj[u], w = ww[u];
+        const uint64_t rj = rr[u];
+        const bool ifirst = ri != rj ? ri < rj : i < j;
+        const int32_t mf = ifirst ? mxi : mj[u];
+        if ((int64_t)bden * w < (int64_t)bnum * mf) continue;
+        EdgeKey e;
+        e.rank = ifirst ? ri : rj;
+        e.first = ifirst ? (int32_t)i : j;
+        e.w = w;
+        e.lo = (int32_t)min((int64_t)j, i);
+        e.hi = (int32_t)max((int64_t)j, i);
+        if (best < 0 || key_before(e, bk, salt)) {
+          bk = e;
+          best = j;
         }
       }
     }
-    prop[i] = best;
-    proposed = best >= 0;
   }
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+    EdgeKey o;
+    const int32_t ob = __shfl_xor(best, off, G);
+    o.rank = __shfl_xor(bk.rank, off, G);
+    o.first = __shfl_xor(bk.first, off, G);
+    o.w = __shfl_xor(bk.w, off, G);
+    o.lo = __shfl_xor(bk.lo, off, G);
+    o.hi = __shfl_xor(bk.hi, off, G);
+    if (ob >= 0 && (best < 0 || key_before(o, bk, salt))) {
+      bk = o;
+      best = ob;
+    }
+  }
+  const bool proposed = i < n && sub == 0 && best >= 0;
+  if (i < n && sub == 0) prop[i] = best;
   // "some node proposed": set once; most wavefronts see the flag already set
   // and skip the atomic (same-address atomics from every wavefront serialize)
   const unsigned long long ballot = __ballot(proposed);
@@ -822,12 +843,15 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
 }
 
 // ---------------------------------------------------------------- Galerkin
-// Large coarse levels: one workgroup per slice of the coarse matrix; its
-// threads take the block slots (row l, slot t) of the slice, 256 at a time.  Block (I, J) is the
-// sum, over the members i of aggregate I in ascending order and over the
-// stored blocks (i, j) of row i in ascending j with agg(j) = J, of the fine
-// block a_ij (eq. Ac_direct), accumulated in FP64 starting from zero.  The
-// inverse of a diagonal block is computed from the stored (rounded) block.
+// Large coarse levels: one workgroup per slice of the coarse matrix; a thread
+// takes GC consecutive block slots (row l, slots t..t+GC-1) of the slice, so
+// that one walk over the fine rows of the members serves GC coarse blocks.
+// Block (I, J) is the sum, over the members i of aggregate I in ascending
+// order and over the stored blocks (i, j) of row i in ascending j with
+// agg(j) = J, of the fine block a_ij (eq. Ac_direct), accumulated in FP64
+// starting from zero.  The inverse of a diagonal block is computed from the
+// stored (rounded) block.
+constexpr int GC = 4;
 template <typename T>
 __global__ void k_galerkin_slices(int64_t nc, const int32_t* __restrict__ csl, const int32_t* __restrict__ ccol,
                            T* __restrict__ cval, T* __restrict__ cdinv, const int32_t* __restrict__ mptr,
@@ -836,15 +860,27 @@ __global__ void k_galerkin_slices(int64_t nc, const int32_t* __restrict__ csl, c
                            const int32_t* __restrict__ agg, const T* __restrict__ fk) {
   const int64_t s = blockIdx.x;
   const int64_t cb = csl[s];
-  const int64_t nslot = csl[s + 1] - cb;
-  for (int64_t k = threadIdx.x; k < nslot; k += blockDim.x) {
-    const int t = (int)(k / SL), l = (int)(k - (int64_t)t * SL);
+  const int width = (int)((csl[s + 1] - cb) / SL);
+  const int nchunk = (width + GC - 1) / GC;
+  for (int k = threadIdx.x; k < nchunk * SL; k += blockDim.x) {
+    const int c = k / SL, l = k - c * SL;
     const int64_t I = s * SL + l;
-    const int32_t J = ccol[cb + k];
-    if (J < 0 || I >= nc) continue;
-    double acc[9];
+    if (I >= nc) continue;
+    int32_t J[GC];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) acc[e] = 0.0;
+    for (int g = 0; g < GC; ++g) {
+      const int t = c * GC + g;
+      J[g] = t < width ? ccol[cb + (int64_t)t * SL + l] : -1;
+    }
+    bool any = false;
+#pragma unroll
+    for (int g = 0; g < GC; ++g) any = any || J[g] >= 0;
+    if (!any) continue;  // padding only
+    double acc[GC][9];
+#pragma unroll
+    for (int g = 0; g < GC; ++g)
+#pragma unroll
+      for (int e = 0; e < 9; ++e) acc[g][e] = 0.0;
     for (int32_t q = mptr[I]; q < mptr[I + 1]; ++q) {
       const int32_t i = mem[q];
       const int64_t fs = i / SL;
@@ -854,34 +890,48 @@ __global__ void k_galerkin_slices(int64_t nc, const int32_t* __restrict__ csl, c
       for (int u = 0; u < fw; ++u) {
         const int32_t j = fcol[fb + (int64_t)u * SL + fl];
         if (j < 0) break;
-        if (agg[j] != J) continue;
+        const int32_t aj = agg[j];
+        int hit = -1;
+#pragma unroll
+        for (int g = 0; g < GC; ++g) hit = aj == J[g] ? g : hit;
+        if (hit < 0) continue;
+        double f[9];
         if (fk) {
           const int64_t kb = fs * 9 * SL + fl;
 #pragma unroll
-          for (int e = 0; e < 9; ++e)
-            acc[e] += j == i ? ((e == 0 || e == 4 || e == 8) ? 1.0 : 0.0) : (double)fk[kb + e * SL];
-          continue;
-        }
-        const int64_t vb = fb * 9 + (int64_t)u * 9 * SL + fl;
+          for (int e = 0; e < 9; ++e) f[e] = j == i ? ((e == 0 || e == 4 || e == 8) ? 1.0 : 0.0) : (double)fk[kb + e * SL];
+        } else {
+          const int64_t vb = fb * 9 + (int64_t)u * 9 * SL + fl;
 #pragma unroll
-        for (int e = 0; e < 9; ++e) acc[e] += (double)fval[vb + e * SL];
+          for (int e = 0; e < 9; ++e) f[e] = (double)fval[vb + e * SL];
+        }
+#pragma unroll
+        for (int g = 0; g < GC; ++g)
+          if (g == hit)
+#pragma unroll
+            for (int e = 0; e < 9; ++e) acc[g][e] += f[e];
       }
     }
-    const int64_t vb = cb * 9 + (int64_t)t * 9 * SL + l;
-    T stv[9];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) {
-      stv[e] = (T)acc[e];
-      cval[vb + e * SL] = stv[e];
-    }
-    if (J == (int32_t)I) {
-      double D[9], Di[9];
+    for (int g = 0; g < GC; ++g) {
+      if (J[g] < 0) continue;
+      const int t = c * GC + g;
+      const int64_t vb = cb * 9 + (int64_t)t * 9 * SL + l;
+      T stv[9];
 #pragma unroll
-      for (int e = 0; e < 9; ++e) D[e] = (double)stv[e];
-      inv3(D, Di);
-      const int64_t db = s * 9 * SL + l;
+      for (int e = 0; e < 9; ++e) {
+        stv[e] = (T)acc[g][e];
+        cval[vb + e * SL] = stv[e];
+      }
+      if (J[g] == (int32_t)I) {
+        double D[9], Di[9];
 #pragma unroll
-      for (int e = 0; e < 9; ++e) cdinv[db + e * SL] = (T)Di[e];
+        for (int e = 0; e < 9; ++e) D[e] = (double)stv[e];
+        inv3(D, Di);
+        const int64_t db = s * 9 * SL + l;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) cdinv[db + e * SL] = (T)Di[e];
+      }
     }
   }
 }
@@ -1191,10 +1241,22 @@ void launch_node_rank(hipStream_t st, int64_t n, uint64_t salt, uint64_t* rank) 
 }
 void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci,
                     const int32_t* gw, const int32_t* mx, const int32_t* mate, const uint64_t* rank,
-                    uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop, int32_t* count) {
-  if (n > 0)
-    hipLaunchKernelGGL(k_propose, dim3(nblk(n)), dim3(TPB), 0, st, n, grp, gci, gw, mx, mate, rank, salt,
-                       bnum, bden, prop, count);
+                    uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop, int32_t* count, int G) {
+  if (n <= 0) return;
+#define LLG_PR(GG)                                                                                         \
+  hipLaunchKernelGGL((k_propose<GG>), dim3(nblk(n * GG)), dim3(TPB), 0, st, n, grp, gci, gw, mx, mate, rank, \
+                     salt, bnum, bden, prop, count)
+  if (G >= 16)
+    LLG_PR(16);
+  else if (G == 8)
+    LLG_PR(8);
+  else if (G == 4)
+    LLG_PR(4);
+  else if (G == 2)
+    LLG_PR(2);
+  else
+    LLG_PR(1);
+#undef LLG_PR
 }
 void launch_accept(hipStream_t st, int64_t n, const int32_t* prop, int32_t* mate) {
   if (n > 0) hipLaunchKernelGGL(k_accept, dim3(nblk(n)), dim3(TPB), 0, st, n, prop, mate);

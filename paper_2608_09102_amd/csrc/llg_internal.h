@@ -173,7 +173,7 @@ void launch_node_rank(hipStream_t st, int64_t n, uint64_t salt, uint64_t* rank);
 // prop[i] = proposed partner or -1; *any is set non-zero when some node proposes
 void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci,
                     const int32_t* gw, const int32_t* mx, const int32_t* mate, const uint64_t* rank,
-                    uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop, int32_t* any);
+                    uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop, int32_t* any, int lanes);
 void launch_accept(hipStream_t st, int64_t n, const int32_t* prop, int32_t* mate);
 void launch_leader_flag(hipStream_t st, int64_t n, const int32_t* mate, int32_t* flag);
 void launch_assign(hipStream_t st, int64_t n, const int32_t* mate, const int32_t* id, int32_t* agg,
