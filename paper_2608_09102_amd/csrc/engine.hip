@@ -466,16 +466,13 @@ int build_structure(llg_ctx& c, Arena& ar) {
     int32_t *crp = L.grp, *cci = L.gci, *cw = L.gw;
     for (int p = 0; p < o.npass; ++p) {
       const uint64_t salt = o.agg_salt ^ (((uint64_t)l << 8) | (uint64_t)p);
-      int32_t* mx = ar.alloc<int32_t>(cn);
+      NodeSt* ns = ar.alloc<NodeSt>(cn);
       int32_t* mate = ar.alloc<int32_t>(cn);
       int32_t* prop = ar.alloc<int32_t>(cn);
       int32_t* id = ar.alloc<int32_t>(cn + 1);
       int32_t* aggp = ar.alloc<int32_t>(cn);
       int32_t* lead = ar.alloc<int32_t>(cn);
-      uint64_t* rank = ar.alloc<uint64_t>(cn);
-      launch_node_rank(st, cn, salt, rank);
-      launch_row_max(st, cn, crp, cw, mx);
-      launch_fill_i32(st, mate, cn, -1);
+      launch_match_init(st, cn, crp, cw, salt, ns, mate);
       LCHK();
       // lanes per node in a proposal round: about two slots per lane on the
       // coarse levels (latency bound), one lane on the grid-sized levels
@@ -489,12 +486,12 @@ int build_structure(llg_ctx& c, Arena& ar) {
         int64_t rounds = 0;
         for (;;) {
           launch_fill_i32(st, c.count, 1, 0);
-          launch_propose(st, cn, crp, cci, cw, mx, mate, rank, salt, o.beta_num, o.beta_den, prop, c.count, lanes);
+          launch_propose(st, cn, crp, cci, cw, ns, salt, o.beta_num, o.beta_den, prop, c.count, lanes);
           LCHK();
           HIPX(hipMemcpyAsync(ar.hcount, c.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
           HIPX(hipStreamSynchronize(st));
           if (*ar.hcount == 0) break;
-          launch_accept(st, cn, prop, mate);
+          launch_accept(st, cn, prop, mate, ns);
           LCHK();
           ++rounds;
           if (rounds > cn + 2) throw DevError{"matching did not terminate"};
@@ -504,11 +501,11 @@ int build_structure(llg_ctx& c, Arena& ar) {
         const int64_t rounds = ar.plan->counts[ar.ci++];
         launch_fill_i32(st, c.count + 1, 1, 0);
         for (int64_t r = 0; r < rounds; ++r) {
-          launch_propose(st, cn, crp, cci, cw, mx, mate, rank, salt, o.beta_num, o.beta_den, prop, c.count + 1, lanes);
-          launch_accept(st, cn, prop, mate);
+          launch_propose(st, cn, crp, cci, cw, ns, salt, o.beta_num, o.beta_den, prop, c.count + 1, lanes);
+          launch_accept(st, cn, prop, mate, ns);
         }
         launch_fill_i32(st, c.count, 1, 0);
-        launch_propose(st, cn, crp, cci, cw, mx, mate, rank, salt, o.beta_num, o.beta_den, prop, c.count, lanes);
+        launch_propose(st, cn, crp, cci, cw, ns, salt, o.beta_num, o.beta_den, prop, c.count, lanes);
         launch_check_eq(st, c.count, 0, c.flags, F_PLAN);
         LCHK();
       }

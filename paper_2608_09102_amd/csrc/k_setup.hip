@@ -299,17 +299,19 @@ __global__ void k_row_max(int64_t n, const int32_t* grp, const int32_t* gw, int3
 template <int G>
 __global__ void __launch_bounds__(TPB) k_propose(int64_t n, const int32_t* __restrict__ grp,
                                                  const int32_t* __restrict__ gci, const int32_t* __restrict__ gw,
-                                                 const int32_t* __restrict__ mx, const int32_t* __restrict__ mate,
-                                                 const uint64_t* __restrict__ rank, uint64_t salt, int32_t bnum,
+                                                 const NodeSt* __restrict__ ns, uint64_t salt, int32_t bnum,
                                                  int32_t bden, int32_t* __restrict__ prop, int32_t* count) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // XCD-contiguous node ranges: the records of a row's neighbours are then
+  // mostly in the XCD's own L2
+  const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t i = t / G;
   const int sub = (int)(t - i * G);
   int32_t best = -1;
   EdgeKey bk{};
-  if (i < n && mate[i] < 0) {
-    const uint64_t ri = rank[i];
-    const int32_t mxi = mx[i];
+  const NodeSt si = i < n ? ns[i] : NodeSt{0, 0, 0};
+  if (i < n && si.mate < 0) {
+    const uint64_t ri = si.rank;
+    const int32_t mxi = si.mx;
     const int32_t k1 = grp[i + 1];
     for (int32_t k0 = grp[i] + sub; k0 < k1; k0 += 4 * G) {
       int32_t jj[4], ww[4];
@@ -319,15 +321,19 @@ __global__ void __launch_bounds__(TPB) k_propose(int64_t n, const int32_t* __res
         jj[u] = ok ? gci[k0 + u * G] : -1;
         ww[u] = ok ? gw[k0 + u * G] : 0;
       }
-      bool fr[4];
+      // the candidates' records, all four loads issued together (a padding
+      // slot reads node i's own record and is masked)
+      NodeSt sj[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) fr[u] = jj[u] >= 0 && mate[jj[u]] < 0;
+      for (int u = 0; u < 4; ++u) sj[u] = ns[jj[u] >= 0 ? jj[u] : i];
+      bool fr[4];
       uint64_t rr[4];
       int32_t mj[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        rr[u] = fr[u] ? rank[jj[u]] : 0;
-        mj[u] = fr[u] ? mx[jj[u]] : 0;
+        fr[u] = jj[u] >= 0 && sj[u].mate < 0;
+        rr[u] = sj[u].rank;
+        mj[u] = sj[u].mx;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -372,11 +378,28 @@ __global__ void __launch_bounds__(TPB) k_propose(int64_t n, const int32_t* __res
   if ((threadIdx.x & 63) == 0 && ballot && __atomic_load_n(count, __ATOMIC_RELAXED) == 0) atomicOr(count, 1);
 }
 
-__global__ void k_accept(int64_t n, const int32_t* prop, int32_t* mate) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_accept(int64_t n, const int32_t* prop, int32_t* mate, NodeSt* ns) {
+  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int32_t p = prop[i];
-  if (p >= 0 && prop[p] == (int32_t)i) mate[i] = p;
+  if (p >= 0 && prop[p] == (int32_t)i) {
+    mate[i] = p;
+    ns[i].mate = p;
+  }
+}
+
+__global__ void k_match_init(int64_t n, const int32_t* grp, const int32_t* gw, uint64_t salt, NodeSt* ns,
+                             int32_t* mate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t m = 0;
+  for (int32_t k = grp[i]; k < grp[i + 1]; ++k) m = max(m, gw[k]);
+  NodeSt r;
+  r.rank = node_rank(i, salt);
+  r.mx = m;
+  r.mate = -1;
+  ns[i] = r;
+  mate[i] = -1;
 }
 
 __global__ void k_leader_flag(int64_t n, const int32_t* mate, int32_t* flag) {
@@ -1239,13 +1262,13 @@ void launch_row_max(hipStream_t st, int64_t n, const int32_t* grp, const int32_t
 void launch_node_rank(hipStream_t st, int64_t n, uint64_t salt, uint64_t* rank) {
   if (n > 0) hipLaunchKernelGGL(k_node_rank, dim3(nblk(n)), dim3(TPB), 0, st, n, salt, rank);
 }
-void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci,
-                    const int32_t* gw, const int32_t* mx, const int32_t* mate, const uint64_t* rank,
-                    uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop, int32_t* count, int G) {
+void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci, const int32_t* gw,
+                    const NodeSt* ns, uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop, int32_t* count,
+                    int G) {
   if (n <= 0) return;
 #define LLG_PR(GG)                                                                                         \
-  hipLaunchKernelGGL((k_propose<GG>), dim3(nblk(n * GG)), dim3(TPB), 0, st, n, grp, gci, gw, mx, mate, rank, \
-                     salt, bnum, bden, prop, count)
+  hipLaunchKernelGGL((k_propose<GG>), dim3(nblk(n * GG)), dim3(TPB), 0, st, n, grp, gci, gw, ns, salt, bnum, \
+                     bden, prop, count)
   if (G >= 16)
     LLG_PR(16);
   else if (G == 8)
@@ -1258,8 +1281,12 @@ void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t
     LLG_PR(1);
 #undef LLG_PR
 }
-void launch_accept(hipStream_t st, int64_t n, const int32_t* prop, int32_t* mate) {
-  if (n > 0) hipLaunchKernelGGL(k_accept, dim3(nblk(n)), dim3(TPB), 0, st, n, prop, mate);
+void launch_accept(hipStream_t st, int64_t n, const int32_t* prop, int32_t* mate, NodeSt* ns) {
+  if (n > 0) hipLaunchKernelGGL(k_accept, dim3(nblk(n)), dim3(TPB), 0, st, n, prop, mate, ns);
+}
+void launch_match_init(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gw, uint64_t salt,
+                       NodeSt* ns, int32_t* mate) {
+  if (n > 0) hipLaunchKernelGGL(k_match_init, dim3(nblk(n)), dim3(TPB), 0, st, n, grp, gw, salt, ns, mate);
 }
 void launch_leader_flag(hipStream_t st, int64_t n, const int32_t* mate, int32_t* flag) {
   if (n > 0) hipLaunchKernelGGL(k_leader_flag, dim3(nblk(n)), dim3(TPB), 0, st, n, mate, flag);

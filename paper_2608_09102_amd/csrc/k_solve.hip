@@ -24,17 +24,6 @@ inline int tpb_rows(int64_t n) { return n >= 65536 ? 256 : 64; }
 
 inline unsigned nblk(int64_t n, int t = TPB) { return (unsigned)ceil_div(n > 0 ? n : 1, t); }
 
-// Workgroups are dispatched round-robin over the 8 XCDs of the chip; give each
-// XCD a contiguous range of slices so that neighbouring rows (which share x
-// entries) are served from the same L2.
-__device__ inline unsigned xcd_block(unsigned b, unsigned nb) {
-  const unsigned per = nb / 8, rem = nb % 8;
-  const unsigned xcd = b % 8, k = b / 8;
-  // blocks [0, 8*per) are spread evenly; the remainder keeps its index
-  if (b < 8 * per) return xcd * per + k;
-  (void)rem;
-  return b;
-}
 
 template <typename T>
 struct V3 {

@@ -32,6 +32,17 @@ struct Sell {
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip; give each
+// XCD a contiguous range of blocks so that neighbouring rows (which share
+// vector entries) are served from the same L2.  A bijection of [0, nb).
+__device__ inline unsigned xcd_block(unsigned b, unsigned nb) {
+  const unsigned per = nb / 8;
+  const unsigned xcd = b % 8, k = b / 8;
+  // blocks [0, 8*per) are spread evenly; the remainder keeps its index
+  if (b < 8 * per) return xcd * per + k;
+  return b;
+}
+
 // Grid sizes, and the source of the grid level's blocks for the solve
 // kernels: the frozen field mt (N x 3), prm[0] = alpha, prm[1] = dt' eps, and
 // 1/h^2 (the blocks are recomputed per node with grid_blocks).
@@ -171,10 +182,21 @@ void launch_cls_gather(hipStream_t st, int64_t n, const int32_t* rows, Sell A, c
 void launch_row_max(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gw, int32_t* mx);
 void launch_node_rank(hipStream_t st, int64_t n, uint64_t salt, uint64_t* rank);
 // prop[i] = proposed partner or -1; *any is set non-zero when some node proposes
-void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci,
-                    const int32_t* gw, const int32_t* mx, const int32_t* mate, const uint64_t* rank,
-                    uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop, int32_t* any, int lanes);
-void launch_accept(hipStream_t st, int64_t n, const int32_t* prop, int32_t* mate);
+// Matching state of a node, one 16-byte record so that a candidate costs one
+// load: its visiting rank, its largest edge weight, its mate (-1: free).
+struct alignas(16) NodeSt {
+  uint64_t rank;
+  int32_t mx;
+  int32_t mate;
+};
+// ns[i] = {rank of i, max_k w_ik, -1}; mate[i] = -1
+void launch_match_init(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gw, uint64_t salt,
+                       NodeSt* ns, int32_t* mate);
+void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci, const int32_t* gw,
+                    const NodeSt* ns, uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop, int32_t* any,
+                    int lanes);
+// mutual proposals are matched (mate and ns[].mate)
+void launch_accept(hipStream_t st, int64_t n, const int32_t* prop, int32_t* mate, NodeSt* ns);
 void launch_leader_flag(hipStream_t st, int64_t n, const int32_t* mate, int32_t* flag);
 void launch_assign(hipStream_t st, int64_t n, const int32_t* mate, const int32_t* id, int32_t* agg,
                    int32_t* lead);
