@@ -574,12 +574,17 @@ __global__ void __launch_bounds__(TPB) k_cg_fill_wide(int64_t nc, const int32_t*
   if (I < nc) cg_fill_row<64>(I, lead, mate, grp, gci, gw, agg, cptr, cj, cw, ucnt);
 }
 
+// The rows' entries moved to their final offsets; CG_L lanes share a row so
+// that the reads and writes of a row are contiguous across the lanes.
+constexpr int CG_L = 8;
 __global__ void k_cg_copy(int64_t nc, const int32_t* cptr, const int32_t* cj, const int32_t* cw,
                           const int32_t* nrp, int32_t* nci, int32_t* nw) {
-  int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t I = t / CG_L;
+  const int sub = (int)(t - I * CG_L);
   if (I >= nc) return;
   const int32_t o = cptr[I], d = nrp[I], len = nrp[I + 1] - nrp[I];
-  for (int32_t q = 0; q < len; ++q) {
+  for (int32_t q = sub; q < len; q += CG_L) {
     nci[d + q] = cj[o + q];
     nw[d + q] = cw[o + q];
   }
@@ -1313,7 +1318,7 @@ void launch_cg_fill(hipStream_t st, int64_t nc, const int32_t* lead, const int32
 void launch_cg_copy(hipStream_t st, int64_t nc, const int32_t* cptr, const int32_t* cj,
                     const int32_t* cw, const int32_t* nrp, int32_t* nci, int32_t* nw) {
   if (nc > 0)
-    hipLaunchKernelGGL(k_cg_copy, dim3(nblk(nc)), dim3(TPB), 0, st, nc, cptr, cj, cw, nrp, nci, nw);
+    hipLaunchKernelGGL(k_cg_copy, dim3(nblk(nc * CG_L)), dim3(TPB), 0, st, nc, cptr, cj, cw, nrp, nci, nw);
 }
 void launch_compose(hipStream_t st, int64_t n, int32_t* acc, const int32_t* aggp, int first) {
   if (n > 0) hipLaunchKernelGGL(k_compose, dim3(nblk(n)), dim3(TPB), 0, st, n, acc, aggp, first);
