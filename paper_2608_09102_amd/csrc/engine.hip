@@ -486,7 +486,7 @@ int build_structure(llg_ctx& c, Arena& ar) {
         int64_t rounds = 0;
         for (;;) {
           launch_fill_i32(st, c.count, 1, 0);
-          launch_propose(st, cn, crp, cci, cw, ns, salt, o.beta_num, o.beta_den, prop, c.count, lanes);
+          launch_propose(st, cn, crp, cci, cw, mate, ns, salt, o.beta_num, o.beta_den, prop, c.count, lanes);
           LCHK();
           HIPX(hipMemcpyAsync(ar.hcount, c.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
           HIPX(hipStreamSynchronize(st));
@@ -501,11 +501,11 @@ int build_structure(llg_ctx& c, Arena& ar) {
         const int64_t rounds = ar.plan->counts[ar.ci++];
         launch_fill_i32(st, c.count + 1, 1, 0);
         for (int64_t r = 0; r < rounds; ++r) {
-          launch_propose(st, cn, crp, cci, cw, ns, salt, o.beta_num, o.beta_den, prop, c.count + 1, lanes);
+          launch_propose(st, cn, crp, cci, cw, mate, ns, salt, o.beta_num, o.beta_den, prop, c.count + 1, lanes);
           launch_accept(st, cn, prop, mate, ns);
         }
         launch_fill_i32(st, c.count, 1, 0);
-        launch_propose(st, cn, crp, cci, cw, ns, salt, o.beta_num, o.beta_den, prop, c.count, lanes);
+        launch_propose(st, cn, crp, cci, cw, mate, ns, salt, o.beta_num, o.beta_den, prop, c.count, lanes);
         launch_check_eq(st, c.count, 0, c.flags, F_PLAN);
         LCHK();
       }

@@ -299,8 +299,9 @@ __global__ void k_row_max(int64_t n, const int32_t* grp, const int32_t* gw, int3
 template <int G>
 __global__ void __launch_bounds__(TPB) k_propose(int64_t n, const int32_t* __restrict__ grp,
                                                  const int32_t* __restrict__ gci, const int32_t* __restrict__ gw,
-                                                 const NodeSt* __restrict__ ns, uint64_t salt, int32_t bnum,
-                                                 int32_t bden, int32_t* __restrict__ prop, int32_t* count) {
+                                                 int32_t* __restrict__ mate, const NodeSt* __restrict__ ns,
+                                                 uint64_t salt, int32_t bnum, int32_t bden,
+                                                 int32_t* __restrict__ prop, int32_t* count) {
   // XCD-contiguous node ranges: the records of a row's neighbours are then
   // mostly in the XCD's own L2
   const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -308,8 +309,16 @@ __global__ void __launch_bounds__(TPB) k_propose(int64_t n, const int32_t* __res
   const int sub = (int)(t - i * G);
   int32_t best = -1;
   EdgeKey bk{};
-  const NodeSt si = i < n ? ns[i] : NodeSt{0, 0, 0};
-  if (i < n && si.mate < 0) {
+  // matched nodes (most of them after the first rounds) read only their
+  // 4-byte mate; a free node then reads its record.  A free node that finds
+  // no candidate is marked dead (mate -2): candidate edges are fixed and free
+  // nodes only get matched, so it will not find one later, and its row is
+  // not walked again.  Every reader of mate takes a negative value as
+  // unmatched; no neighbour can select a dead node (that edge would be a
+  // free candidate of the dead node).
+  const int32_t mi = i < n ? mate[i] : 0;
+  if (i < n && mi == -1) {
+    const NodeSt si = ns[i];
     const uint64_t ri = si.rank;
     const int32_t mxi = si.mx;
     const int32_t k1 = grp[i + 1];
@@ -371,7 +380,10 @@ __global__ void __launch_bounds__(TPB) k_propose(int64_t n, const int32_t* __res
     }
   }
   const bool proposed = i < n && sub == 0 && best >= 0;
-  if (i < n && sub == 0) prop[i] = best;
+  if (i < n && sub == 0) {
+    prop[i] = best;
+    if (mi == -1 && best < 0) mate[i] = -2;
+  }
   // "some node proposed": set once; most wavefronts see the flag already set
   // and skip the atomic (same-address atomics from every wavefront serialize)
   const unsigned long long ballot = __ballot(proposed);
@@ -561,7 +573,7 @@ __device__ __forceinline__ void cg_fill_row(int64_t I, const int32_t* lead, cons
 __global__ void k_cg_fill(int64_t nc, const int32_t* lead, const int32_t* mate, const int32_t* grp,
                           const int32_t* gci, const int32_t* gw, const int32_t* agg, const int32_t* cptr,
                           int32_t* cj, int32_t* cw, int32_t* ucnt) {
-  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t I = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (I < nc) cg_fill_row<32>(I, lead, mate, grp, gci, gw, agg, cptr, cj, cw, ucnt);
 }
 // the 64-wide sort needs about 256 registers: bounded to TPB threads so that
@@ -570,7 +582,7 @@ __global__ void __launch_bounds__(TPB) k_cg_fill_wide(int64_t nc, const int32_t*
                                                       const int32_t* grp, const int32_t* gci, const int32_t* gw,
                                                       const int32_t* agg, const int32_t* cptr, int32_t* cj,
                                                       int32_t* cw, int32_t* ucnt) {
-  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t I = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (I < nc) cg_fill_row<64>(I, lead, mate, grp, gci, gw, agg, cptr, cj, cw, ucnt);
 }
 
@@ -886,7 +898,8 @@ __global__ void k_galerkin_slices(int64_t nc, const int32_t* __restrict__ csl, c
                            const int32_t* __restrict__ mem, const int32_t* __restrict__ fsl,
                            const int32_t* __restrict__ fcol, const T* __restrict__ fval,
                            const int32_t* __restrict__ agg, const T* __restrict__ fk) {
-  const int64_t s = blockIdx.x;
+  // XCD-contiguous slices: neighbouring aggregates read the same fine rows
+  const int64_t s = xcd_block(blockIdx.x, gridDim.x);
   const int64_t cb = csl[s];
   const int width = (int)((csl[s + 1] - cb) / SL);
   const int nchunk = (width + GC - 1) / GC;
@@ -1268,12 +1281,12 @@ void launch_node_rank(hipStream_t st, int64_t n, uint64_t salt, uint64_t* rank) 
   if (n > 0) hipLaunchKernelGGL(k_node_rank, dim3(nblk(n)), dim3(TPB), 0, st, n, salt, rank);
 }
 void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci, const int32_t* gw,
-                    const NodeSt* ns, uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop, int32_t* count,
-                    int G) {
+                    int32_t* mate, const NodeSt* ns, uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop,
+                    int32_t* count, int G) {
   if (n <= 0) return;
 #define LLG_PR(GG)                                                                                         \
-  hipLaunchKernelGGL((k_propose<GG>), dim3(nblk(n * GG)), dim3(TPB), 0, st, n, grp, gci, gw, ns, salt, bnum, \
-                     bden, prop, count)
+  hipLaunchKernelGGL((k_propose<GG>), dim3(nblk(n * GG)), dim3(TPB), 0, st, n, grp, gci, gw, mate, ns, salt, \
+                     bnum, bden, prop, count)
   if (G >= 16)
     LLG_PR(16);
   else if (G == 8)

@@ -193,9 +193,10 @@ struct alignas(16) NodeSt {
 void launch_match_init(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gw, uint64_t salt,
                        NodeSt* ns, int32_t* mate);
 void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci, const int32_t* gw,
-                    const NodeSt* ns, uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop, int32_t* any,
-                    int lanes);
-// mutual proposals are matched (mate and ns[].mate)
+                    int32_t* mate, const NodeSt* ns, uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop,
+                    int32_t* any, int lanes);
+// mutual proposals are matched (mate and ns[].mate); propose marks a free
+// node without candidates dead (mate -2, unmatched for every reader)
 void launch_accept(hipStream_t st, int64_t n, const int32_t* prop, int32_t* mate, NodeSt* ns);
 void launch_leader_flag(hipStream_t st, int64_t n, const int32_t* mate, int32_t* flag);
 void launch_assign(hipStream_t st, int64_t n, const int32_t* mate, const int32_t* id, int32_t* agg,
