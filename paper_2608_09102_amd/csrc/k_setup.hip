@@ -928,29 +928,40 @@ __global__ void k_galerkin_slices(int64_t nc, const int32_t* __restrict__ csl, c
       const int fl = i - (int)(fs * SL);
       const int64_t fb = fsl[fs];
       const int fw = (int)((fsl[fs + 1] - fb) / SL);
-      for (int u = 0; u < fw; ++u) {
-        const int32_t j = fcol[fb + (int64_t)u * SL + fl];
-        if (j < 0) break;
-        const int32_t aj = agg[j];
-        int hit = -1;
+      // four slots of the row at a time: their column and aggregate loads
+      // are in flight together; the blocks are still added in slot order
+      // (a row's padding slots, column -1, follow its blocks)
+      for (int u0 = 0; u0 < fw; u0 += 4) {
+        int32_t jj[4], aa[4];
 #pragma unroll
-        for (int g = 0; g < GC; ++g) hit = aj == J[g] ? g : hit;
-        if (hit < 0) continue;
-        double f[9];
-        if (fk) {
-          const int64_t kb = fs * 9 * SL + fl;
+        for (int k = 0; k < 4; ++k) jj[k] = u0 + k < fw ? fcol[fb + (int64_t)(u0 + k) * SL + fl] : -1;
 #pragma unroll
-          for (int e = 0; e < 9; ++e) f[e] = j == i ? ((e == 0 || e == 4 || e == 8) ? 1.0 : 0.0) : (double)fk[kb + e * SL];
-        } else {
-          const int64_t vb = fb * 9 + (int64_t)u * 9 * SL + fl;
+        for (int k = 0; k < 4; ++k) aa[k] = jj[k] >= 0 ? agg[jj[k]] : -1;
 #pragma unroll
-          for (int e = 0; e < 9; ++e) f[e] = (double)fval[vb + e * SL];
+        for (int k = 0; k < 4; ++k) {
+          int hit = -1;
+#pragma unroll
+          for (int g = 0; g < GC; ++g) hit = aa[k] >= 0 && aa[k] == J[g] ? g : hit;
+          if (hit < 0) continue;
+          const int32_t j = jj[k];
+          double f[9];
+          if (fk) {
+            const int64_t kb = fs * 9 * SL + fl;
+#pragma unroll
+            for (int e = 0; e < 9; ++e)
+              f[e] = j == i ? ((e == 0 || e == 4 || e == 8) ? 1.0 : 0.0) : (double)fk[kb + e * SL];
+          } else {
+            const int64_t vb = fb * 9 + (int64_t)(u0 + k) * 9 * SL + fl;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) f[e] = (double)fval[vb + e * SL];
+          }
+#pragma unroll
+          for (int g = 0; g < GC; ++g)
+            if (g == hit)
+#pragma unroll
+              for (int e = 0; e < 9; ++e) acc[g][e] += f[e];
         }
-#pragma unroll
-        for (int g = 0; g < GC; ++g)
-          if (g == hit)
-#pragma unroll
-            for (int e = 0; e < 9; ++e) acc[g][e] += f[e];
+        if (jj[3] < 0) break;
       }
     }
 #pragma unroll
