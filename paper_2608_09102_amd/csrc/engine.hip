@@ -162,6 +162,7 @@ struct Level {
   std::vector<Sell> cls;
   std::vector<void*> cval, cdinv;
   void* kf = nullptr;  // factored grid level: K_p per node ([slice][9][64])
+  void* vt = nullptr;  // coarse levels feeding a Galerkin product: the blocks in slot order (9 per slot)
   double* mtq = nullptr;  // the frozen field in member order of the level-1 aggregates (mt[mem[q]])
   int32_t* nagg = nullptr;  // level-1 aggregates of each member's grid neighbours ([slice][6][64])
 };
@@ -652,6 +653,9 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
     Level& L = c.lv[l];
     const int64_t n = L.A.n;
     if (!(l == 0 && c.fact)) L.val = ar.get(ts * 9 * L.A.nslots, true);
+    // the next level's Galerkin product reads this level's blocks in slot
+    // order (the sliced-ELL layout spreads a block over nine cache lines)
+    if (l >= 1 && l + 1 < c.L) L.vt = ar.get(ts * 9 * L.A.nslots, true);
     L.unit = l == 0 && c.opts.left_scale;
     L.G = n >= 32768 ? 1 : (c.grid.dim == 3 ? 16 : 8);
     L.dinv = ar.get(ts * 9 * L.A.nslices * SL, true);
@@ -840,8 +844,20 @@ void setup_values(llg_ctx& c, const double* m, const double* mprev, const double
     Level& L = c.lv[l];
     Level& Nx = c.lv[l + 1];
     KTimer kt(c, LLG_KT_GALERKIN);
-    launch_galerkin<T>(st, Nx.A, (T*)Nx.val, (T*)Nx.dinv, L.mptr, L.mem, L.A, (const T*)L.val, L.agg,
-                       (const T*)L.kf);
+    GalSrc<T> src;
+    src.fval = (const T*)L.val;
+    src.fvt = (const T*)L.vt;
+    src.fk = (const T*)L.kf;
+    if (L.kf) {  // factored grid level: K_i from the frozen field
+      src.mt = c.mt;
+      src.prm = c.prm;
+      src.inv_h2 = 1.0 / (g.h * g.h);
+      src.nx = g.n[0];
+      src.ny = g.n[1];
+      src.nz = g.n[2];
+    }
+    src.cvt = (T*)Nx.vt;
+    launch_galerkin<T>(st, Nx.A, (T*)Nx.val, (T*)Nx.dinv, L.mptr, L.mem, L.A, L.agg, src);
     LCHK();
   }
   for (int l = 0; l + 1 < c.L; ++l) {  // colour-class copies for Gauss-Seidel

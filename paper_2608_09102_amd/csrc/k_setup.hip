@@ -883,6 +883,42 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
 }
 
 // ---------------------------------------------------------------- Galerkin
+// The fine block (i, j) of a Galerkin sum, in FP64.  Factored grid level: the
+// identity on the diagonal, else K_i, recomputed from the frozen field by the
+// contraction-free formulas the assembly used (bit for bit the stored K, read
+// as 24 contiguous bytes instead of nine slice-strided values) or read from
+// fk.  Other levels: the slot-ordered copy (nine contiguous values) when
+// there is one, else the sliced-ELL values.
+template <typename T, bool FACT>
+__device__ inline void fine_block(const GalSrc<T>& g, int32_t i, int32_t j, int64_t fs, int fl, int64_t fb, int u,
+                                  double* f) {
+  if (FACT) {
+    if (j == i) {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) f[e] = (e == 0 || e == 4 || e == 8) ? 1.0 : 0.0;
+    } else if (g.mt) {
+      int64_t nb[6];
+      const int deg = grid_nbrs(g.nx, g.ny, g.nz, i, nb);
+      double K[9];
+      grid_blocks(g.mt + 3 * (int64_t)i, g.prm[0], g.prm[1], g.inv_h2, deg, nullptr, nullptr, K);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) f[e] = (double)(T)K[e];
+    } else {
+      const int64_t kb = fs * 9 * SL + fl;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) f[e] = (double)g.fk[kb + e * SL];
+    }
+  } else if (g.fvt) {
+    const int64_t slot = fb + (int64_t)u * SL + fl;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) f[e] = (double)g.fvt[slot * 9 + e];
+  } else {
+    const int64_t vb = fb * 9 + (int64_t)u * 9 * SL + fl;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) f[e] = (double)g.fval[vb + e * SL];
+  }
+}
+
 // Large coarse levels: one workgroup per slice of the coarse matrix; a thread
 // takes GC consecutive block slots (row l, slots t..t+GC-1) of the slice, so
 // that one walk over the fine rows of the members serves GC coarse blocks.
@@ -892,12 +928,11 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
 // starting from zero.  The inverse of a diagonal block is computed from the
 // stored (rounded) block.
 constexpr int GC = 4;
-template <typename T>
-__global__ void k_galerkin_slices(int64_t nc, const int32_t* __restrict__ csl, const int32_t* __restrict__ ccol,
+template <typename T, bool FACT>
+__global__ void __launch_bounds__(TPB) k_galerkin_slices(int64_t nc, const int32_t* __restrict__ csl, const int32_t* __restrict__ ccol,
                            T* __restrict__ cval, T* __restrict__ cdinv, const int32_t* __restrict__ mptr,
                            const int32_t* __restrict__ mem, const int32_t* __restrict__ fsl,
-                           const int32_t* __restrict__ fcol, const T* __restrict__ fval,
-                           const int32_t* __restrict__ agg, const T* __restrict__ fk) {
+                           const int32_t* __restrict__ fcol, const int32_t* __restrict__ agg, const GalSrc<T> g) {
   // XCD-contiguous slices: neighbouring aggregates read the same fine rows
   const int64_t s = xcd_block(blockIdx.x, gridDim.x);
   const int64_t cb = csl[s];
@@ -909,19 +944,19 @@ __global__ void k_galerkin_slices(int64_t nc, const int32_t* __restrict__ csl, c
     if (I >= nc) continue;
     int32_t J[GC];
 #pragma unroll
-    for (int g = 0; g < GC; ++g) {
-      const int t = c * GC + g;
-      J[g] = t < width ? ccol[cb + (int64_t)t * SL + l] : -1;
+    for (int h = 0; h < GC; ++h) {
+      const int t = c * GC + h;
+      J[h] = t < width ? ccol[cb + (int64_t)t * SL + l] : -1;
     }
     bool any = false;
 #pragma unroll
-    for (int g = 0; g < GC; ++g) any = any || J[g] >= 0;
+    for (int h = 0; h < GC; ++h) any = any || J[h] >= 0;
     if (!any) continue;  // padding only
     double acc[GC][9];
 #pragma unroll
-    for (int g = 0; g < GC; ++g)
+    for (int h = 0; h < GC; ++h)
 #pragma unroll
-      for (int e = 0; e < 9; ++e) acc[g][e] = 0.0;
+      for (int e = 0; e < 9; ++e) acc[h][e] = 0.0;
     for (int32_t q = mptr[I]; q < mptr[I + 1]; ++q) {
       const int32_t i = mem[q];
       const int64_t fs = i / SL;
@@ -941,41 +976,38 @@ __global__ void k_galerkin_slices(int64_t nc, const int32_t* __restrict__ csl, c
         for (int k = 0; k < 4; ++k) {
           int hit = -1;
 #pragma unroll
-          for (int g = 0; g < GC; ++g) hit = aa[k] >= 0 && aa[k] == J[g] ? g : hit;
+          for (int h = 0; h < GC; ++h) hit = aa[k] >= 0 && aa[k] == J[h] ? h : hit;
           if (hit < 0) continue;
-          const int32_t j = jj[k];
           double f[9];
-          if (fk) {
-            const int64_t kb = fs * 9 * SL + fl;
+          fine_block<T, FACT>(g, i, jj[k], fs, fl, fb, u0 + k, f);
 #pragma unroll
-            for (int e = 0; e < 9; ++e)
-              f[e] = j == i ? ((e == 0 || e == 4 || e == 8) ? 1.0 : 0.0) : (double)fk[kb + e * SL];
-          } else {
-            const int64_t vb = fb * 9 + (int64_t)(u0 + k) * 9 * SL + fl;
+          for (int h = 0; h < GC; ++h)
+            if (h == hit)
 #pragma unroll
-            for (int e = 0; e < 9; ++e) f[e] = (double)fval[vb + e * SL];
-          }
-#pragma unroll
-          for (int g = 0; g < GC; ++g)
-            if (g == hit)
-#pragma unroll
-              for (int e = 0; e < 9; ++e) acc[g][e] += f[e];
+              for (int e = 0; e < 9; ++e) acc[h][e] += f[e];
         }
         if (jj[3] < 0) break;
       }
     }
 #pragma unroll
-    for (int g = 0; g < GC; ++g) {
-      if (J[g] < 0) continue;
-      const int t = c * GC + g;
+    for (int h = 0; h < GC; ++h) {
+      if (J[h] < 0) continue;
+      const int t = c * GC + h;
       const int64_t vb = cb * 9 + (int64_t)t * 9 * SL + l;
       T stv[9];
 #pragma unroll
       for (int e = 0; e < 9; ++e) {
-        stv[e] = (T)acc[g][e];
+        stv[e] = (T)acc[h][e];
         cval[vb + e * SL] = stv[e];
       }
-      if (J[g] == (int32_t)I) {
+      if (g.cvt) {
+        // slot-ordered copy for the next level's product (a wavefront's
+        // lanes hold consecutive slots: contiguous stores)
+        const int64_t slot = cb + (int64_t)t * SL + l;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) g.cvt[slot * 9 + e] = stv[e];
+      }
+      if (J[h] == (int32_t)I) {
         double D[9], Di[9];
 #pragma unroll
         for (int e = 0; e < 9; ++e) D[e] = (double)stv[e];
@@ -994,13 +1026,12 @@ __global__ void k_galerkin_slices(int64_t nc, const int32_t* __restrict__ csl, c
 // (i, j) of row i in ascending j with agg(j) = J, of the fine block a_ij
 // (eq. Ac_direct), accumulated in FP64 starting from zero.  The inverse of a
 // diagonal block is computed from the stored (rounded) block.
-template <typename T>
+template <typename T, bool FACT>
 __global__ void k_galerkin_slots(int64_t nc, int64_t ns, const int32_t* __restrict__ csl,
                            const int32_t* __restrict__ ccol, T* __restrict__ cval, T* __restrict__ cdinv,
                            const int32_t* __restrict__ mptr, const int32_t* __restrict__ mem,
                            const int32_t* __restrict__ fsl, const int32_t* __restrict__ fcol,
-                           const T* __restrict__ fval, const int32_t* __restrict__ agg,
-                           const T* __restrict__ fk) {
+                           const int32_t* __restrict__ agg, const GalSrc<T> g) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= csl[ns]) return;
   // slice of slot p: the last s with csl[s] <= p
@@ -1030,16 +1061,10 @@ __global__ void k_galerkin_slots(int64_t nc, int64_t ns, const int32_t* __restri
       const int32_t j = fcol[fb + (int64_t)u * SL + fl];
       if (j < 0) break;
       if (agg[j] != J) continue;
-      if (fk) {
-        const int64_t kb = fs * 9 * SL + fl;
+      double f[9];
+      fine_block<T, FACT>(g, i, j, fs, fl, fb, u, f);
 #pragma unroll
-        for (int e = 0; e < 9; ++e)
-          acc[e] += j == i ? ((e == 0 || e == 4 || e == 8) ? 1.0 : 0.0) : (double)fk[kb + e * SL];
-        continue;
-      }
-      const int64_t vb = fb * 9 + (int64_t)u * 9 * SL + fl;
-#pragma unroll
-      for (int e = 0; e < 9; ++e) acc[e] += (double)fval[vb + e * SL];
+      for (int e = 0; e < 9; ++e) acc[e] += f[e];
     }
   }
   const int64_t vb = cb * 9 + (int64_t)t * 9 * SL + l;
@@ -1048,6 +1073,10 @@ __global__ void k_galerkin_slots(int64_t nc, int64_t ns, const int32_t* __restri
   for (int e = 0; e < 9; ++e) {
     st[e] = (T)acc[e];
     cval[vb + e * SL] = st[e];
+  }
+  if (g.cvt) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) g.cvt[p * 9 + e] = st[e];
   }
   if (J == (int32_t)I) {
     double D[9], Di[9];
@@ -1384,20 +1413,27 @@ void init_kernel_attributes() {
 }
 
 template <typename T>
-void launch_galerkin(hipStream_t st, Sell C, T* cval, T* cdinv, const int32_t* mptr,
-                     const int32_t* mem, Sell F, const T* fval, const int32_t* agg, const T* fk) {
+void launch_galerkin(hipStream_t st, Sell C, T* cval, T* cdinv, const int32_t* mptr, const int32_t* mem, Sell F,
+                     const int32_t* agg, const GalSrc<T>& g) {
   if (C.n <= 0) return;
-  if (C.nslices >= 1024)
-    hipLaunchKernelGGL((k_galerkin_slices<T>), dim3((unsigned)C.nslices), dim3(TPB), 0, st, C.n, C.sl_ptr, C.col,
-                       cval, cdinv, mptr, mem, F.sl_ptr, F.col, fval, agg, fk);
-  else
-    hipLaunchKernelGGL((k_galerkin_slots<T>), dim3(nblk(C.nslots)), dim3(TPB), 0, st, C.n, C.nslices, C.sl_ptr,
-                       C.col, cval, cdinv, mptr, mem, F.sl_ptr, F.col, fval, agg, fk);
+#define LLG_GAL(FACT)                                                                                          \
+  if (C.nslices >= 1024)                                                                                       \
+    hipLaunchKernelGGL((k_galerkin_slices<T, FACT>), dim3((unsigned)C.nslices), dim3(TPB), 0, st, C.n, C.sl_ptr, \
+                       C.col, cval, cdinv, mptr, mem, F.sl_ptr, F.col, agg, g);                                  \
+  else                                                                                                         \
+    hipLaunchKernelGGL((k_galerkin_slots<T, FACT>), dim3(nblk(C.nslots)), dim3(TPB), 0, st, C.n, C.nslices,      \
+                       C.sl_ptr, C.col, cval, cdinv, mptr, mem, F.sl_ptr, F.col, agg, g)
+  if (g.fk) {
+    LLG_GAL(true);
+  } else {
+    LLG_GAL(false);
+  }
+#undef LLG_GAL
 }
-template void launch_galerkin<double>(hipStream_t, Sell, double*, double*, const int32_t*,
-                                      const int32_t*, Sell, const double*, const int32_t*, const double*);
-template void launch_galerkin<float>(hipStream_t, Sell, float*, float*, const int32_t*,
-                                     const int32_t*, Sell, const float*, const int32_t*, const float*);
+template void launch_galerkin<double>(hipStream_t, Sell, double*, double*, const int32_t*, const int32_t*, Sell,
+                                      const int32_t*, const GalSrc<double>&);
+template void launch_galerkin<float>(hipStream_t, Sell, float*, float*, const int32_t*, const int32_t*, Sell,
+                                     const int32_t*, const GalSrc<float>&);
 
 template <typename T>
 void launch_dense_scatter(hipStream_t st, Sell C, const T* cval, double* dense) {

@@ -228,12 +228,29 @@ void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, cons
                      Sell A, double* Aval, T* Lval, double* dinv0, T* ldinv, double* b, double* u,
                      int32_t* flag, double* Mh, T* K, double* mt_out);
 
-// Galerkin block sums P^T A P and the inverse diagonal blocks of the result
-// fk != NULL: the fine level is the factored grid level, whose block in slot
-// (i, j) is the identity when j == i and fk_i otherwise (fval unused)
+// Where a Galerkin product reads the fine blocks, and where it leaves a copy
+// of the coarse ones.  fk != NULL: the fine level is the factored grid level,
+// whose block (i, j) is the identity when j == i and K_i otherwise; K_i is
+// recomputed from mt (alpha, dt' in prm[0..1], inv_h2, grid nx, ny, nz) when
+// mt != NULL, else read from fk.  Otherwise the blocks are read from fvt (the
+// level's blocks in slot order, nine contiguous values per slot) when it is
+// not NULL, else from the sliced-ELL values fval.  cvt != NULL receives the
+// coarse blocks in slot order.
 template <typename T>
-void launch_galerkin(hipStream_t st, Sell C, T* cval, T* cdinv, const int32_t* mptr,
-                     const int32_t* mem, Sell F, const T* fval, const int32_t* agg, const T* fk);
+struct GalSrc {
+  const T* fval = nullptr;
+  const T* fvt = nullptr;
+  const T* fk = nullptr;
+  const double* mt = nullptr;
+  const double* prm = nullptr;
+  double inv_h2 = 0.0;
+  int nx = 0, ny = 0, nz = 0;
+  T* cvt = nullptr;
+};
+// Galerkin block sums P^T A P and the inverse diagonal blocks of the result
+template <typename T>
+void launch_galerkin(hipStream_t st, Sell C, T* cval, T* cdinv, const int32_t* mptr, const int32_t* mem, Sell F,
+                     const int32_t* agg, const GalSrc<T>& g);
 
 // one-time kernel attribute setup (large dynamic LDS for the coarsest inverse)
 void init_kernel_attributes();
