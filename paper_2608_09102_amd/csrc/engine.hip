@@ -163,6 +163,7 @@ struct Level {
   std::vector<void*> cval, cdinv;
   void* kf = nullptr;  // factored grid level: K_p per node ([slice][9][64])
   void* vt = nullptr;  // coarse levels feeding a Galerkin product: the blocks in slot order (9 per slot)
+  double* prho = nullptr;  // K-cycle levels: partial sums of w1.rho
   double* mtq = nullptr;  // the frozen field in member order of the level-1 aggregates (mt[mem[q]])
   int32_t* nagg = nullptr;  // level-1 aggregates of each member's grid neighbours ([slice][6][64])
 };
@@ -697,7 +698,12 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   c.npart_vec = red_blocks(m);
   c.npart_rows = ceil_div(c.N, 256);
   int64_t kparts = 0;
-  for (int l = 1; l < c.L; ++l) kparts = std::max<int64_t>(kparts, 3 * rows_blocks(c.lv[l].A.n, c.lv[l].G));
+  for (int l = 1; l < c.L; ++l) {
+    kparts = std::max<int64_t>(kparts, 3 * rows_blocks(c.lv[l].A.n, c.lv[l].G));
+    // K-cycle levels: the partials of w1.rho, kept apart from c.part until
+    // stage 3 sums them (a nested K-cycle reuses c.part in between)
+    if (l <= c.opts.kcycle_depth && l + 1 < c.L) c.lv[l].prho = ar.lazy<double>(rows_blocks(c.lv[l].A.n, 1));
+  }
   // level 1 (not the coarsest, one lane per row) applied through the grid level's blocks
   // (at most two matching passes: k_l1 takes aggregates of at most four members)
   c.f1 = c.fact && c.L > 2 && c.lv[1].G == 1 && c.opts.smoother == LLG_SMOOTHER_JACOBI && c.opts.npass <= 2;
@@ -1202,9 +1208,10 @@ void kcorrection(llg_ctx& c, int lc) {
   else
     launch_spmv_dots<T>(st, C.A, val, (const T*)C.v1, (T*)C.w1, (const T*)C.b, nullptr, c.part, C.G);
   launch_kc_coef(st, c.part, G, 1, C.kc);
+  // the partials of w1.rho wait in the level's own buffer until stage 3
+  double* part_rho = C.prho;
   launch_kc_update<T>(st, C.A.n, (const T*)C.b, (const T*)C.w1, C.kc, (T*)C.rho, (const T*)C.dinv, c.omega,
-                      pre ? (T*)C.x : nullptr, c.part);
-  launch_kc_coef(st, c.part, rows_blocks(C.A.n, 1), 2, C.kc);
+                      pre ? (T*)C.x : nullptr, part_rho);
   LCHK();
   vcycle<T>(c, lc, (const T*)C.rho, (T*)C.v2);
   if (f1)
@@ -1212,7 +1219,7 @@ void kcorrection(llg_ctx& c, int lc) {
                  nullptr, nullptr, nullptr, c.omega, (T*)C.w2, (const T*)C.w1, (const T*)C.rho, c.part);
   else
     launch_spmv_dots<T>(st, C.A, val, (const T*)C.v2, (T*)C.w2, (const T*)C.w1, (const T*)C.rho, c.part, C.G);
-  launch_kc_coef(st, c.part, G, 3, C.kc);
+  launch_kc_coef(st, c.part, G, 3, C.kc, part_rho, rows_blocks(C.A.n, 1));
   launch_kc_combine<T>(st, C.A.n, (const T*)C.v1, (const T*)C.v2, C.kc, (T*)C.e);
   LCHK();
 }

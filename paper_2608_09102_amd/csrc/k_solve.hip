@@ -1131,27 +1131,32 @@ __device__ inline void group_sums(const double* __restrict__ part, int64_t ld, i
   __syncthreads();
 }
 
-// stage 1: a1 = (w1.r)/(w1.w1); stage 2: w1.rho; stage 3: the weights of
+// K-cycle coefficients from the partial sums of one workgroup per block.
+// Stage 1: a1 = (w1.r)/(w1.w1) from w1.w1 and w1.r.  Stage 3: the weights of
 // e = a1 v1 + a2 (v2 - gamma v1), gamma = (w1.w2)/(w1.w1),
-// a2 = (w2'.rho)/(w2'.w2') with w2' = w2 - gamma w1
-__global__ void k_kc_coef(const double* part, int64_t G, int stage, double* kc) {
+// a2 = (w2'.rho)/(w2'.w2') with w2' = w2 - gamma w1, from w2.w2, w2.w1,
+// w2.rho (part, G per column) and w1.rho (part2, G2 partials that the update
+// of rho wrote; summed here rather than in a launch of its own).
+__global__ void k_kc_coef(const double* part, int64_t G, int stage, double* kc, const double* part2, int64_t G2) {
   __shared__ double s[3];
-  if (stage == 2)
-    group_sums<1>(part, G, G, s);
-  else if (stage == 1)
+  __shared__ double s2[1];
+  if (stage == 1) {
     group_sums<2>(part, G, G, s);
-  else
+  } else {
     group_sums<3>(part, G, G, s);
+    __syncthreads();
+    group_sums<1>(part2, G2, G2, s2);
+  }
   if (threadIdx.x != 0) return;
   if (stage == 1) {
     kc[1] = s[0];
     kc[0] = s[1] / s[0];
-  } else if (stage == 2) {
-    kc[4] = s[0];
   } else {
+    const double w1rho = s2[0];
+    kc[4] = w1rho;
     const double w11 = kc[1], w22 = s[0], w12 = s[1], w2r = s[2];
     const double gamma = w12 / w11;
-    const double num = w2r - gamma * kc[4];
+    const double num = w2r - gamma * w1rho;
     const double den = (w22 - 2.0 * gamma * w12) + gamma * gamma * w11;
     const double a2 = num / den;
     kc[2] = kc[0] - a2 * gamma;
@@ -2001,8 +2006,9 @@ template <typename T>
 void launch_kc_combine(hipStream_t st, int64_t n, const T* v1, const T* v2, const double* kc, T* e) {
   hipLaunchKernelGGL((k_kc_combine<T>), dim3(nblk(3 * n)), dim3(TPB), 0, st, n, v1, v2, kc, e);
 }
-void launch_kc_coef(hipStream_t st, const double* part, int64_t G, int stage, double* kc) {
-  hipLaunchKernelGGL(k_kc_coef, dim3(1), dim3(1024), 0, st, part, G, stage, kc);
+void launch_kc_coef(hipStream_t st, const double* part, int64_t G, int stage, double* kc, const double* part2,
+                    int64_t G2) {
+  hipLaunchKernelGGL(k_kc_coef, dim3(1), dim3(1024), 0, st, part, G, stage, kc, part2, G2);
 }
 int64_t rows_blocks(int64_t n, int G) { return ceil_div(n > 0 ? n * G : 1, TPB); }
 

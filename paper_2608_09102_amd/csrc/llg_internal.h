@@ -353,7 +353,8 @@ void launch_kc_update(hipStream_t st, int64_t n, const T* r, const T* w1, const 
                       const T* dinv, double omega, T* x, double* part);
 template <typename T>
 void launch_kc_combine(hipStream_t st, int64_t n, const T* v1, const T* v2, const double* kc, T* e);
-void launch_kc_coef(hipStream_t st, const double* part, int64_t G, int stage, double* kc);
+void launch_kc_coef(hipStream_t st, const double* part, int64_t G, int stage, double* kc,
+                    const double* part2 = nullptr, int64_t G2 = 0);
 
 // Factored grid level (one 3x3 block per node, [slice][9][64]): Mh_p is
 // every off-diagonal block of row p of A (A_pp = I - deg_p Mh_p), K_p every
