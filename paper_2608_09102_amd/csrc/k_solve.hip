@@ -1492,24 +1492,30 @@ __global__ void __launch_bounds__(TAIL_T) k_tail(const TailArgs<T> a, const T* _
   const bool xz = a.nu_pre == 0;  // no pre-smoothing: x = 0
   // after nu_pre - 1 further pre-sweeps x sits in the level's ox (even count) or oy
   const bool xswap = a.nu_pre >= 2 && (a.nu_pre - 1) % 2 == 1;
-  {
-    T* B = vec(a.lv[0].ob);
-    for (int I = tid; I < a.lv[0].n; I += TAIL_T) st3(B, (int64_t)I, tail_restrict_row(mptr, mem, rab, I));
-  }
+  // restriction onto tail level kn, with that level's first pre-smoothing
+  // sweep from x = 0, x = omega D^{-1} b, taken by the thread that formed b
+  // (as the per-level restriction kernel does)
+  auto restrict_to = [&](int kn, const int32_t* mp, const int32_t* me, const T* r) {
+    const TailLevel<T>& N = a.lv[kn];
+    T* Bn = vec(N.ob);
+    T* Xn = vec(N.ox);
+    for (int I = tid; I < N.n; I += TAIL_T) {
+      const V3<T> b = tail_restrict_row(mp, me, r, I);
+      st3(Bn, (int64_t)I, b);
+      if (!xz) {
+        const int s = I / SL, l = I - s * SL;
+        const V3<T> d = dmv(N.dinv, (int64_t)s * 9 * SL + l, b);
+        st3(Xn, (int64_t)I, V3<T>{om * d.x, om * d.y, om * d.z});
+      }
+    }
+  };
+  restrict_to(0, mptr, mem, rab);
   __syncthreads();
   for (int k = 0; k < a.nlev; ++k) {
     const TailLevel<T>& L = a.lv[k];
     const T* B = vec(L.ob);
     T* X = vec(L.ox);
     T* Y = vec(L.oy);
-    if (!xz) {
-      for (int i = tid; i < L.n; i += TAIL_T) {
-        const int s = i / SL, l = i - s * SL;
-        const V3<T> d = dmv(L.dinv, (int64_t)s * 9 * SL + l, ld3(B, (int64_t)i));
-        st3(X, (int64_t)i, V3<T>{om * d.x, om * d.y, om * d.z});
-      }
-      __syncthreads();
-    }
     for (int q = 1; q < a.nu_pre; ++q) {
       tail_sweep(L, B, X, Y, om);
       __syncthreads();
@@ -1527,8 +1533,7 @@ __global__ void __launch_bounds__(TAIL_T) k_tail(const TailArgs<T> a, const T* _
       rs = Y;
     }
     if (k + 1 < a.nlev) {
-      T* Bn = vec(a.lv[k + 1].ob);
-      for (int I = tid; I < a.lv[k + 1].n; I += TAIL_T) st3(Bn, (int64_t)I, tail_restrict_row(L.mptr, L.mem, rs, I));
+      restrict_to(k + 1, L.mptr, L.mem, rs);
     } else {
       double* bd = (double*)(tail_lds + a.obd);
       for (int I = tid; I < a.nc; I += TAIL_T) {
