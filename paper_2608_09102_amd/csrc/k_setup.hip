@@ -279,14 +279,6 @@ __device__ inline bool key_before(const EdgeKey& a, const EdgeKey& b, uint64_t s
   return a.hi < b.hi;
 }
 
-__global__ void k_row_max(int64_t n, const int32_t* grp, const int32_t* gw, int32_t* mx) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int32_t m = 0;
-  for (int32_t k = grp[i]; k < grp[i + 1]; ++k) m = max(m, gw[k]);
-  mx[i] = m;
-}
-
 // Handshake round: every free node proposes its best available edge (both
 // endpoints free, strong for the first-visited endpoint).  Neighbours are
 // examined four at a time so that their loads are in flight together.
@@ -1313,9 +1305,6 @@ void launch_sell_cols(hipStream_t st, int64_t n, const int32_t* rows, const int3
   const int64_t ns = ceil_div(n, SL);
   if (ns > 0)
     hipLaunchKernelGGL(k_sell_cols, dim3(nblk(ns * SL)), dim3(TPB), 0, st, n, rows, brp, bci, sl_ptr, col);
-}
-void launch_row_max(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gw, int32_t* mx) {
-  if (n > 0) hipLaunchKernelGGL(k_row_max, dim3(nblk(n)), dim3(TPB), 0, st, n, grp, gw, mx);
 }
 void launch_node_rank(hipStream_t st, int64_t n, uint64_t salt, uint64_t* rank) {
   if (n > 0) hipLaunchKernelGGL(k_node_rank, dim3(nblk(n)), dim3(TPB), 0, st, n, salt, rank);

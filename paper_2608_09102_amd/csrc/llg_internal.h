@@ -179,11 +179,12 @@ void launch_cls_gather(hipStream_t st, int64_t n, const int32_t* rows, Sell A, c
                        Sell C, T* cval, T* cdinv, const T* fk);
 
 // pairwise matching (one pass)
-void launch_row_max(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gw, int32_t* mx);
 void launch_node_rank(hipStream_t st, int64_t n, uint64_t salt, uint64_t* rank);
 // prop[i] = proposed partner or -1; *any is set non-zero when some node proposes
 // Matching state of a node, one 16-byte record so that a candidate costs one
-// load: its visiting rank, its largest edge weight, its mate (-1: free).
+// load: its visiting rank, its largest edge weight, its mate (-1 while
+// unmatched; the proposal rounds mark a free node without candidates -2 in
+// the mate array only, which the record does not need to know).
 struct alignas(16) NodeSt {
   uint64_t rank;
   int32_t mx;
