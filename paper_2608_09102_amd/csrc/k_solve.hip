@@ -767,7 +767,15 @@ __global__ void __launch_bounds__(TPB) k_dcgs_update(int64_t m, const double* __
   const double du = coef[2 * NV], cu = coef[2 * NV + 1];
   const int G = gridDim.x;
   double acc = 0.0;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)G * blockDim.x) {
+  // The grid-stride passes run from the last to the first: the dots sweep
+  // just before read the same vectors from the first pass to the last, so
+  // its last passes are the ones still in the Infinity Cache (the basis
+  // outgrows it); all lanes of a wavefront stay on one pass.
+  const int64_t stride = (int64_t)G * blockDim.x;
+  const int64_t k0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t r = (m - 1) / stride; r >= 0; --r) {
+    const int64_t k = r * stride + k0;
+    if (k >= m) continue;
     const double uk = u[k], wk = w[k];
     double vj = du * uk, wp = wk - cu * uk;
 #pragma unroll
