@@ -477,10 +477,12 @@ int build_structure(llg_ctx& c, Arena& ar) {
       launch_match_init(st, cn, crp, cw, salt, ns, mate);
       LCHK();
       // lanes per node in a proposal round: about two slots per lane on the
-      // coarse levels (latency bound), one lane on the grid-sized levels
+      // coarse levels (latency bound), one lane on the grid-sized levels.  A
+      // round launches lanes x cn threads whatever is left to match, and the
+      // late rounds (few free nodes) cost about their dispatch, so the lanes
+      // stop at about 1.25M threads (level 1 of a 128^3 grid: 2 instead of 8).
       int lanes = 1;
-      if (cn < (int64_t(1) << 20))
-        while (lanes < 16 && (int64_t)2 * lanes * cn < cg) lanes *= 2;
+      while (lanes < 16 && (int64_t)2 * lanes * cn < cg && (int64_t)2 * lanes * cn <= (int64_t(5) << 18)) lanes *= 2;
       // handshake rounds: PLAN runs until a round has no proposal and logs
       // the number of rounds; REPLAY runs that many and checks the extra
       // round proposes nothing
