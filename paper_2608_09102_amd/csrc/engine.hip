@@ -474,7 +474,7 @@ int build_structure(llg_ctx& c, Arena& ar) {
       int32_t* id = ar.alloc<int32_t>(cn + 1);
       int32_t* aggp = ar.alloc<int32_t>(cn);
       int32_t* lead = ar.alloc<int32_t>(cn);
-      launch_match_init(st, cn, crp, cw, salt, ns, mate);
+      launch_match_init(st, cn, crp, cw, salt, ns, mate, prop);
       LCHK();
       // lanes per node in a proposal round: about two slots per lane on the
       // coarse levels (latency bound), one lane on the grid-sized levels.  A

@@ -308,8 +308,22 @@ __global__ void __launch_bounds__(TPB) k_propose(int64_t n, const int32_t* __res
   // not walked again.  Every reader of mate takes a negative value as
   // unmatched; no neighbour can select a dead node (that edge would be a
   // free candidate of the dead node).
+  //
+  // A free node whose proposal of the last round is still free proposes it
+  // again without walking its row: the free nodes only shrink, so the
+  // earliest candidate of a set stays the earliest of any subset holding it.
+  // Only the nodes whose proposal got matched (and the first round, prop
+  // -1) walk their rows.  The decision is the same on the G lanes of a node.
   const int32_t mi = i < n ? mate[i] : 0;
+  bool walk = false;
   if (i < n && mi == -1) {
+    const int32_t pj = prop[i];
+    if (pj >= 0 && mate[pj] < 0)
+      best = pj;
+    else
+      walk = true;
+  }
+  if (walk) {
     const NodeSt si = ns[i];
     const uint64_t ri = si.rank;
     const int32_t mxi = si.mx;
@@ -359,6 +373,7 @@ __global__ void __launch_bounds__(TPB) k_propose(int64_t n, const int32_t* __res
   }
 #pragma unroll
   for (int off = 1; off < G; off <<= 1) {
+    if (!walk) break;  // uniform over the node's lanes
     EdgeKey o;
     const int32_t ob = __shfl_xor(best, off, G);
     o.rank = __shfl_xor(bk.rank, off, G);
@@ -393,7 +408,7 @@ __global__ void k_accept(int64_t n, const int32_t* prop, int32_t* mate, NodeSt* 
 }
 
 __global__ void k_match_init(int64_t n, const int32_t* grp, const int32_t* gw, uint64_t salt, NodeSt* ns,
-                             int32_t* mate) {
+                             int32_t* mate, int32_t* prop) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int32_t m = 0;
@@ -404,6 +419,7 @@ __global__ void k_match_init(int64_t n, const int32_t* grp, const int32_t* gw, u
   r.mate = -1;
   ns[i] = r;
   mate[i] = -1;
+  prop[i] = -1;
 }
 
 __global__ void k_leader_flag(int64_t n, const int32_t* mate, int32_t* flag) {
@@ -1332,8 +1348,8 @@ void launch_accept(hipStream_t st, int64_t n, const int32_t* prop, int32_t* mate
   if (n > 0) hipLaunchKernelGGL(k_accept, dim3(nblk(n)), dim3(TPB), 0, st, n, prop, mate, ns);
 }
 void launch_match_init(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gw, uint64_t salt,
-                       NodeSt* ns, int32_t* mate) {
-  if (n > 0) hipLaunchKernelGGL(k_match_init, dim3(nblk(n)), dim3(TPB), 0, st, n, grp, gw, salt, ns, mate);
+                       NodeSt* ns, int32_t* mate, int32_t* prop) {
+  if (n > 0) hipLaunchKernelGGL(k_match_init, dim3(nblk(n)), dim3(TPB), 0, st, n, grp, gw, salt, ns, mate, prop);
 }
 void launch_leader_flag(hipStream_t st, int64_t n, const int32_t* mate, int32_t* flag) {
   if (n > 0) hipLaunchKernelGGL(k_leader_flag, dim3(nblk(n)), dim3(TPB), 0, st, n, mate, flag);

@@ -190,9 +190,9 @@ struct alignas(16) NodeSt {
   int32_t mx;
   int32_t mate;
 };
-// ns[i] = {rank of i, max_k w_ik, -1}; mate[i] = -1
+// ns[i] = {rank of i, max_k w_ik, -1}; mate[i] = -1; prop[i] = -1 (no proposal yet)
 void launch_match_init(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gw, uint64_t salt,
-                       NodeSt* ns, int32_t* mate);
+                       NodeSt* ns, int32_t* mate, int32_t* prop);
 void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci, const int32_t* gw,
                     int32_t* mate, const NodeSt* ns, uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop,
                     int32_t* any, int lanes);
