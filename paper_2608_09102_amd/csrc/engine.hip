@@ -162,6 +162,7 @@ struct Level {
   std::vector<Sell> cls;
   std::vector<void*> cval, cdinv;
   void* kf = nullptr;  // factored grid level: K_p per node ([slice][9][64])
+  void* knm = nullptr;  // the same, node-major (9 contiguous values per node)
   void* vt = nullptr;  // coarse levels feeding a Galerkin product: the blocks in slot order (9 per slot)
   double* prho = nullptr;  // K-cycle levels: partial sums of w1.rho
   double* mtq = nullptr;  // the frozen field in member order of the level-1 aggregates (mt[mem[q]])
@@ -648,6 +649,7 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
     c.Mh = ar.lazy<double>(9 * L0.A.nslices * SL);
     c.mt = ar.lazy<double>(3 * L0.A.n);
     L0.kf = ar.get(ts * 9 * L0.A.nslices * SL, true);
+    L0.knm = ar.get(ts * 9 * L0.A.n, true);  // K node-major, read by level 1's Galerkin product
   } else {
     c.Aval = ar.lazy<double>(9 * L0.A.nslots);
   }
@@ -835,7 +837,7 @@ void setup_values(llg_ctx& c, const double* m, const double* mprev, const double
     KTimer kt(c, LLG_KT_ASSEMBLE);
     launch_assemble<T>(st, g.n[0], g.n[1], g.n[2], 1.0 / (g.h * g.h), c.prm, c.opts.left_scale,
                        c.opts.x0_is_mn, m, mprev, F, L0.A, c.Aval, (T*)L0.val, c.dinv0, (T*)L0.dinv, c.b, c.u,
-                       c.flags, c.Mh, (T*)L0.kf, c.mt);
+                       c.flags, c.Mh, (T*)L0.kf, (T*)L0.knm, c.mt);
     if (c.f1) {
       launch_member_nbr_aggs(st, GridDims{g.n[0], g.n[1], g.n[2]}, L0.mem, L0.agg, L0.nagg);
       launch_member_fields(st, L0.A.n, L0.mem, c.mt, L0.mtq);
@@ -856,14 +858,7 @@ void setup_values(llg_ctx& c, const double* m, const double* mprev, const double
     src.fval = (const T*)L.val;
     src.fvt = (const T*)L.vt;
     src.fk = (const T*)L.kf;
-    if (L.kf) {  // factored grid level: K_i from the frozen field
-      src.mt = c.mt;
-      src.prm = c.prm;
-      src.inv_h2 = 1.0 / (g.h * g.h);
-      src.nx = g.n[0];
-      src.ny = g.n[1];
-      src.nz = g.n[2];
-    }
+    src.knm = (const T*)L.knm;  // factored grid level: K node-major
     src.cvt = (T*)Nx.vt;
     launch_galerkin<T>(st, Nx.A, (T*)Nx.val, (T*)Nx.dinv, L.mptr, L.mem, L.A, L.agg, src);
     LCHK();

@@ -777,7 +777,8 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
                            const int32_t* __restrict__ col, double* __restrict__ Aval,
                            T* __restrict__ Lval, double* __restrict__ dinv0, T* __restrict__ ldinv,
                            double* __restrict__ b, double* __restrict__ u, int32_t* flag,
-                           double* __restrict__ Mh, T* __restrict__ K, double* __restrict__ mt_out) {
+                           double* __restrict__ Mh, T* __restrict__ K, T* __restrict__ Knm,
+                           double* __restrict__ mt_out) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t N = (int64_t)nx * ny * nz;
   if (p >= N) return;
@@ -839,6 +840,7 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
     for (int e = 0; e < 9; ++e) {
       Mh[fb + e * SL] = blk[e];
       K[fb + e * SL] = (T)sb[e];
+      if (Knm) Knm[9 * p + e] = (T)sb[e];  // node-major copy for the Galerkin product
     }
   }
   for (int t = 0; t < w; ++t) {
@@ -892,11 +894,10 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
 
 // ---------------------------------------------------------------- Galerkin
 // The fine block (i, j) of a Galerkin sum, in FP64.  Factored grid level: the
-// identity on the diagonal, else K_i, recomputed from the frozen field by the
-// contraction-free formulas the assembly used (bit for bit the stored K, read
-// as 24 contiguous bytes instead of nine slice-strided values) or read from
-// fk.  Other levels: the slot-ordered copy (nine contiguous values) when
-// there is one, else the sliced-ELL values.
+// identity on the diagonal, else K_i, read from the node-major copy the
+// assembly writes (nine contiguous values) or from fk.  Other levels: the
+// slot-ordered copy (nine contiguous values) when there is one, else the
+// sliced-ELL values.
 template <typename T, bool FACT>
 __device__ inline void fine_block(const GalSrc<T>& g, int32_t i, int32_t j, int64_t fs, int fl, int64_t fb, int u,
                                   double* f) {
@@ -904,13 +905,9 @@ __device__ inline void fine_block(const GalSrc<T>& g, int32_t i, int32_t j, int6
     if (j == i) {
 #pragma unroll
       for (int e = 0; e < 9; ++e) f[e] = (e == 0 || e == 4 || e == 8) ? 1.0 : 0.0;
-    } else if (g.mt) {
-      int64_t nb[6];
-      const int deg = grid_nbrs(g.nx, g.ny, g.nz, i, nb);
-      double K[9];
-      grid_blocks(g.mt + 3 * (int64_t)i, g.prm[0], g.prm[1], g.inv_h2, deg, nullptr, nullptr, K);
+    } else if (g.knm) {
 #pragma unroll
-      for (int e = 0; e < 9; ++e) f[e] = (double)(T)K[e];
+      for (int e = 0; e < 9; ++e) f[e] = (double)g.knm[9 * (int64_t)i + e];
     } else {
       const int64_t kb = fs * 9 * SL + fl;
 #pragma unroll
@@ -1396,18 +1393,20 @@ template <typename T>
 void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, const double* prm,
                      int left_scale, int x0_is_mn, const double* m, const double* mprev, const double* F,
                      Sell A, double* Aval, T* Lval, double* dinv0, T* ldinv, double* b, double* u,
-                     int32_t* flag, double* Mh, T* K, double* mt_out) {
+                     int32_t* flag, double* Mh, T* K, T* Knm, double* mt_out) {
   const int64_t N = (int64_t)nx * ny * nz;
   hipLaunchKernelGGL((k_assemble<T>), dim3(nblk(N)), dim3(TPB), 0, st, nx, ny, nz, inv_h2, prm,
                      left_scale, x0_is_mn, m, mprev, F, A.sl_ptr, A.col, Aval, Lval, dinv0, ldinv, b, u, flag, Mh,
-                     K, mt_out);
+                     K, Knm, mt_out);
 }
 template void launch_assemble<double>(hipStream_t, int, int, int, double, const double*, int, int,
                                       const double*, const double*, const double*, Sell, double*, double*,
-                                      double*, double*, double*, double*, int32_t*, double*, double*, double*);
+                                      double*, double*, double*, double*, int32_t*, double*, double*, double*,
+                                      double*);
 template void launch_assemble<float>(hipStream_t, int, int, int, double, const double*, int, int,
                                      const double*, const double*, const double*, Sell, double*, float*,
-                                     double*, float*, double*, double*, int32_t*, double*, float*, double*);
+                                     double*, float*, double*, double*, int32_t*, double*, float*, float*,
+                                     double*);
 
 void init_kernel_attributes() {
   const size_t lds_max = (size_t)(GJ_LDS_MAX * GJ_LDS_MAX + GJ_LDS_MAX + GJ_T) * sizeof(double) +

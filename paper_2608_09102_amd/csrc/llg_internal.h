@@ -222,30 +222,28 @@ void launch_member_sort(hipStream_t st, int64_t nc, const int32_t* mptr, int32_t
 // factor of the forcing and of the explicit field terms (device memory, so
 // captured graphs stay valid)
 // Factored form (Mh != NULL): the per-node blocks Mh and K are written
-// instead of the sliced-ELL values Aval and Lval.
+// instead of the sliced-ELL values Aval and Lval; Knm != NULL receives K
+// node-major as well (nine contiguous values per node).
 template <typename T>
 void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, const double* prm,
                      int left_scale, int x0_is_mn, const double* m, const double* mprev, const double* F,
                      Sell A, double* Aval, T* Lval, double* dinv0, T* ldinv, double* b, double* u,
-                     int32_t* flag, double* Mh, T* K, double* mt_out);
+                     int32_t* flag, double* Mh, T* K, T* Knm, double* mt_out);
 
 // Where a Galerkin product reads the fine blocks, and where it leaves a copy
 // of the coarse ones.  fk != NULL: the fine level is the factored grid level,
 // whose block (i, j) is the identity when j == i and K_i otherwise; K_i is
-// recomputed from mt (alpha, dt' in prm[0..1], inv_h2, grid nx, ny, nz) when
-// mt != NULL, else read from fk.  Otherwise the blocks are read from fvt (the
-// level's blocks in slot order, nine contiguous values per slot) when it is
-// not NULL, else from the sliced-ELL values fval.  cvt != NULL receives the
-// coarse blocks in slot order.
+// read from knm (node-major, nine contiguous values) when it is not NULL,
+// else from fk.  Otherwise the blocks are read from fvt (the level's blocks
+// in slot order, nine contiguous values per slot) when it is not NULL, else
+// from the sliced-ELL values fval.  cvt != NULL receives the coarse blocks
+// in slot order.
 template <typename T>
 struct GalSrc {
   const T* fval = nullptr;
   const T* fvt = nullptr;
   const T* fk = nullptr;
-  const double* mt = nullptr;
-  const double* prm = nullptr;
-  double inv_h2 = 0.0;
-  int nx = 0, ny = 0, nz = 0;
+  const T* knm = nullptr;
   T* cvt = nullptr;
 };
 // Galerkin block sums P^T A P and the inverse diagonal blocks of the result
