@@ -487,7 +487,12 @@ int build_structure(llg_ctx& c, Arena& ar) {
       // handshake rounds: PLAN runs until a round has no proposal and logs
       // the number of rounds; REPLAY runs that many and checks the extra
       // round proposes nothing
-      if (ar.mode == Mode::PLAN) {
+      if (cn <= MATCH_SMALL) {
+        // a small level: every round in one workgroup, in both modes
+        launch_match_small(st, cn, crp, cci, cw, mate, ns, salt, o.beta_num, o.beta_den, prop, c.flags, F_PLAN,
+                           lanes);
+        LCHK();
+      } else if (ar.mode == Mode::PLAN) {
         int64_t rounds = 0;
         for (;;) {
           launch_fill_i32(st, c.count, 1, 0);

@@ -288,17 +288,13 @@ __device__ inline bool key_before(const EdgeKey& a, const EdgeKey& b, uint64_t s
 // walk are the round's latency); each lane walks every G-th slot, then a
 // butterfly keeps the earliest key.  The order is strict, so the result does
 // not depend on G.
+// The proposal of node i (lanes sub = 0..G-1 of its group; i >= n: none) in
+// one handshake round; returns whether it proposed (on lane 0).
 template <int G>
-__global__ void __launch_bounds__(TPB) k_propose(int64_t n, const int32_t* __restrict__ grp,
-                                                 const int32_t* __restrict__ gci, const int32_t* __restrict__ gw,
-                                                 int32_t* __restrict__ mate, const NodeSt* __restrict__ ns,
-                                                 uint64_t salt, int32_t bnum, int32_t bden,
-                                                 int32_t* __restrict__ prop, int32_t* count) {
-  // XCD-contiguous node ranges: the records of a row's neighbours are then
-  // mostly in the XCD's own L2
-  const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  const int64_t i = t / G;
-  const int sub = (int)(t - i * G);
+__device__ inline bool propose_node(int64_t i, int sub, int64_t n, const int32_t* __restrict__ grp,
+                                    const int32_t* __restrict__ gci, const int32_t* __restrict__ gw,
+                                    int32_t* __restrict__ mate, const NodeSt* __restrict__ ns, uint64_t salt,
+                                    int32_t bnum, int32_t bden, int32_t* __restrict__ prop) {
   int32_t best = -1;
   EdgeKey bk{};
   // matched nodes (most of them after the first rounds) read only their
@@ -391,10 +387,69 @@ __global__ void __launch_bounds__(TPB) k_propose(int64_t n, const int32_t* __res
     prop[i] = best;
     if (mi == -1 && best < 0) mate[i] = -2;
   }
+  return proposed;
+}
+
+template <int G>
+__global__ void __launch_bounds__(TPB) k_propose(int64_t n, const int32_t* __restrict__ grp,
+                                                 const int32_t* __restrict__ gci, const int32_t* __restrict__ gw,
+                                                 int32_t* __restrict__ mate, const NodeSt* __restrict__ ns,
+                                                 uint64_t salt, int32_t bnum, int32_t bden,
+                                                 int32_t* __restrict__ prop, int32_t* count) {
+  // XCD-contiguous node ranges: the records of a row's neighbours are then
+  // mostly in the XCD's own L2
+  const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int64_t i = t / G;
+  const int sub = (int)(t - i * G);
+  const bool proposed = propose_node<G>(i, sub, n, grp, gci, gw, mate, ns, salt, bnum, bden, prop);
   // "some node proposed": set once; most wavefronts see the flag already set
   // and skip the atomic (same-address atomics from every wavefront serialize)
   const unsigned long long ballot = __ballot(proposed);
   if ((threadIdx.x & 63) == 0 && ballot && __atomic_load_n(count, __ATOMIC_RELAXED) == 0) atomicOr(count, 1);
+}
+
+// Every handshake round of a small level in one workgroup (MATCH_T threads,
+// G lanes per node): there the launches of the rounds cost more than their
+// work.  The rounds are those of k_propose / k_accept: within a round the
+// passes over the nodes read no state another pass of the round changes
+// (a dead mark only turns -1 into -2).  A round with a proposal matches at
+// least the earliest free candidate edge (both of its ends propose it), so
+// at most n/2 + 1 rounds run; past n rounds the flag bit is raised.
+constexpr int MATCH_T = 1024;
+template <int G>
+__global__ void __launch_bounds__(MATCH_T) k_match_small(int64_t n, const int32_t* __restrict__ grp,
+                                                         const int32_t* __restrict__ gci,
+                                                         const int32_t* __restrict__ gw, int32_t* __restrict__ mate,
+                                                         NodeSt* __restrict__ ns, uint64_t salt, int32_t bnum,
+                                                         int32_t bden, int32_t* __restrict__ prop, int32_t* flag,
+                                                         int32_t bit) {
+  __shared__ int32_t s_any;
+  const int tid = (int)threadIdx.x;
+  const int sub = tid % G;
+  for (int64_t r = 0;; ++r) {
+    if (tid == 0) s_any = 0;
+    __syncthreads();
+    bool any = false;
+    for (int64_t i0 = 0; i0 < n; i0 += MATCH_T / G) {
+      const bool pr = propose_node<G>(i0 + tid / G, sub, n, grp, gci, gw, mate, ns, salt, bnum, bden, prop);
+      any = any || pr;
+    }
+    if (any) s_any = 1;
+    __syncthreads();  // the round's proposals are visible to the workgroup
+    if (s_any == 0) break;
+    if (r > n) {
+      if (tid == 0) atomicOr(flag, bit);
+      break;
+    }
+    for (int64_t i = tid; i < n; i += MATCH_T) {
+      const int32_t pi = prop[i];
+      if (pi >= 0 && prop[pi] == (int32_t)i) {
+        mate[i] = pi;
+        ns[i].mate = pi;
+      }
+    }
+    __syncthreads();
+  }
 }
 
 __global__ void k_accept(int64_t n, const int32_t* prop, int32_t* mate, NodeSt* ns) {
@@ -1340,6 +1395,17 @@ void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t
   else
     LLG_PR(1);
 #undef LLG_PR
+}
+void launch_match_small(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci, const int32_t* gw,
+                        int32_t* mate, NodeSt* ns, uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop,
+                        int32_t* flag, int32_t bit, int G) {
+  if (n <= 0) return;
+  if (G >= 2)
+    hipLaunchKernelGGL(k_match_small<2>, dim3(1), dim3(MATCH_T), 0, st, n, grp, gci, gw, mate, ns, salt, bnum, bden,
+                       prop, flag, bit);
+  else
+    hipLaunchKernelGGL(k_match_small<1>, dim3(1), dim3(MATCH_T), 0, st, n, grp, gci, gw, mate, ns, salt, bnum, bden,
+                       prop, flag, bit);
 }
 void launch_accept(hipStream_t st, int64_t n, const int32_t* prop, int32_t* mate, NodeSt* ns) {
   if (n > 0) hipLaunchKernelGGL(k_accept, dim3(nblk(n)), dim3(TPB), 0, st, n, prop, mate, ns);

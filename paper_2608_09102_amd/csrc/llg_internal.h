@@ -196,6 +196,13 @@ void launch_match_init(hipStream_t st, int64_t n, const int32_t* grp, const int3
 void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci, const int32_t* gw,
                     int32_t* mate, const NodeSt* ns, uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop,
                     int32_t* any, int lanes);
+// Every round of the matching of a small level (n <= MATCH_SMALL) in one
+// workgroup, with 2 lanes per node (G >= 2) or 1; raises flag bit if it did
+// not end within n rounds.
+constexpr int64_t MATCH_SMALL = 512;
+void launch_match_small(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci, const int32_t* gw,
+                        int32_t* mate, NodeSt* ns, uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop,
+                        int32_t* flag, int32_t bit, int G);
 // mutual proposals are matched (mate and ns[].mate); propose marks a free
 // node without candidates dead (mate -2, unmatched for every reader)
 void launch_accept(hipStream_t st, int64_t n, const int32_t* prop, int32_t* mate, NodeSt* ns);
