@@ -116,7 +116,14 @@ struct Arena {
   X* lazy(int64_t n) { return (X*)get((size_t)std::max<int64_t>(n, 1) * sizeof(X), true); }
 
   // host-visible count stored at device address p
-  int64_t count(const int32_t* p) {
+  // REPLAY: the logged count replaces the read-back, and the device value is
+  // checked against it.  Counts in buffers that nothing overwrites during
+  // the step (defer) are checked together, CHECK_BATCH per launch, when the
+  // batch fills and at flush_checks(); a count in reused scratch is checked
+  // at once.
+  std::vector<const int32_t*> chk_p;
+  std::vector<int32_t> chk_v;
+  int64_t count(const int32_t* p, bool defer = true) {
     if (mode == Mode::PLAN) {
       HIPX(hipMemcpyAsync(hcount, p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
       HIPX(hipStreamSynchronize(st));
@@ -125,9 +132,22 @@ struct Arena {
     }
     if (ci >= plan->counts.size()) throw DevError{"count log exhausted"};
     const int64_t v = plan->counts[ci++];
-    launch_check_eq(st, p, (int32_t)v, flag, F_PLAN);
-    LCHK();
+    if (defer) {
+      chk_p.push_back(p);
+      chk_v.push_back((int32_t)v);
+      if ((int)chk_p.size() == CHECK_BATCH) flush_checks();
+    } else {
+      launch_check_eq(st, p, (int32_t)v, flag, F_PLAN);
+      LCHK();
+    }
     return v;
+  }
+  void flush_checks() {
+    if (chk_p.empty()) return;
+    launch_check_many(st, chk_p.data(), chk_v.data(), (int)chk_p.size(), flag, F_PLAN);
+    LCHK();
+    chk_p.clear();
+    chk_v.clear();
   }
   void release() {
     for (void* p : owned) (void)hipFree(p);
@@ -397,7 +417,7 @@ void build_colours(llg_ctx& c, Arena& ar, int l) {
   launch_fill_i32(st, c.count + 2, 1, 0);
   launch_colour_max(st, n, L.colour, c.count + 2);
   LCHK();
-  const int64_t ncol = ar.count(c.count + 2);
+  const int64_t ncol = ar.count(c.count + 2, false);  // c.count is reused scratch
   if (ncol > MAX_COLOURS && ar.mode == Mode::PLAN) ar.plan->status = LLG_ERR_UNSUPPORTED;
   L.ncol = (int)std::max<int64_t>(1, std::min<int64_t>(ncol, MAX_COLOURS));
   const int64_t nb = colour_blocks(n);
@@ -573,6 +593,7 @@ int build_structure(llg_ctx& c, Arena& ar) {
     build_sell(ar, st, Nx, cn, cg);
     finish_sell(ar, st, Nx, c.scan_tmp);
   }
+  ar.flush_checks();
   return l + 1;
 }
 

@@ -148,6 +148,16 @@ __global__ void k_check_eq(const int32_t* a, int32_t expect, int32_t* flag, int3
   if (threadIdx.x == 0 && blockIdx.x == 0 && a[0] != expect) atomicOr(flag, bit);
 }
 
+struct CountChecks {
+  const int32_t* p[CHECK_BATCH];
+  int32_t v[CHECK_BATCH];
+  int32_t n;
+};
+__global__ void k_check_many(const CountChecks c, int32_t* flag, int32_t bit) {
+  const int k = (int)threadIdx.x;
+  if (k < c.n && *c.p[k] != c.v[k]) atomicOr(flag, bit);
+}
+
 // ---------------------------------------------------------------- grid graph
 // Neighbours of node p in ascending index order: k-1, j-1, i-1, i+1, j+1, k+1
 // (homogeneous Neumann: missing neighbours are simply absent).
@@ -1346,6 +1356,15 @@ void launch_scan_excl(hipStream_t st, const int32_t* in, int32_t* out, int64_t n
 
 void launch_check_eq(hipStream_t st, const int32_t* a, int32_t expect, int32_t* flag, int32_t bit) {
   hipLaunchKernelGGL(k_check_eq, dim3(1), dim3(64), 0, st, a, expect, flag, bit);
+}
+void launch_check_many(hipStream_t st, const int32_t* const* p, const int32_t* v, int n, int32_t* flag, int32_t bit) {
+  CountChecks c{};
+  for (int k = 0; k < n && k < CHECK_BATCH; ++k) {
+    c.p[k] = p[k];
+    c.v[k] = v[k];
+  }
+  c.n = n < CHECK_BATCH ? n : CHECK_BATCH;
+  if (c.n > 0) hipLaunchKernelGGL(k_check_many, dim3(1), dim3(CHECK_BATCH), 0, st, c, flag, bit);
 }
 
 void launch_grid_degree(hipStream_t st, int nx, int ny, int nz, int32_t* deg) {

@@ -147,6 +147,9 @@ void launch_scan_excl(hipStream_t st, const int32_t* in, int32_t* out, int64_t n
                       int32_t* tmp);
 // device flag |= (a[0] != expect)
 void launch_check_eq(hipStream_t st, const int32_t* a, int32_t expect, int32_t* flag, int32_t bit);
+// *p[k] == v[k] for k < n (n <= CHECK_BATCH), in one launch; else flag |= bit
+constexpr int CHECK_BATCH = 64;
+void launch_check_many(hipStream_t st, const int32_t* const* p, const int32_t* v, int n, int32_t* flag, int32_t bit);
 
 // grid graph and patterns
 void launch_grid_degree(hipStream_t st, int nx, int ny, int nz, int32_t* deg);
