@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
         L.llgo_splitmix64.restype = ctypes.c_uint64
         L.llgo_match_pass.argtypes = [i64, P, P, P, ctypes.c_uint64, i32, i32, P, P, P]
         L.llgo_galerkin.argtypes = [i64, P, P, P, P, i64, P, P, P, P]
+        L.llgo_aggregate_levels.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), P, P, P, i64]
         L.llgo_assemble_nnzb.argtypes = [ctypes.POINTER(Grid), P]
         L.llgo_assemble.argtypes = [ctypes.POINTER(Grid), P, ctypes.c_double, ctypes.c_double, P, P, P]
         L.llgo_setup.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), P, ctypes.c_double,
@@ -166,6 +167,27 @@ def match_pass(rp, ci, w, salt: int, beta=(1, 4)):
                                _p(agg), _p(mate), ctypes.byref(nc))
     assert rc == 0
     return agg, mate, int(nc.value)
+
+
+def aggregate_levels(grid: Grid, opts: Opts):
+    """The aggregation hierarchy of the grid graph alone (no matrix values):
+    the list of level sizes and the aggregate map of every level but the
+    coarsest."""
+    N = int(grid.n[0]) * int(grid.n[1]) * int(grid.n[2])
+    cap = 2 * N  # the level sizes shrink by at least the stagnation factor
+    agg = np.empty(cap, np.int32)
+    sizes = np.zeros(max(int(opts.max_levels), 1) + 1, np.int64)
+    nl = ctypes.c_int32(0)
+    rc = lib().llgo_aggregate_levels(ctypes.byref(grid), ctypes.byref(opts), ctypes.byref(nl), _p(sizes), _p(agg),
+                                     cap)
+    assert rc == 0, rc
+    L = int(nl.value)
+    maps, off = [], 0
+    for l in range(L - 1):
+        n = int(sizes[l])
+        maps.append(agg[off:off + n].copy())
+        off += n
+    return [int(v) for v in sizes[:L]], maps
 
 
 def galerkin(rp, ci, val, agg, nc):

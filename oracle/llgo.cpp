@@ -855,25 +855,20 @@ int tfqmr(const Hier& H, const double* b, const double* u0, double* u, llgo_stat
 }
 
 // ------------------------------------------------------ setup// ------------------------------------------------------ setup
-int build(Hier& H, const double* m_tilde, double alpha, double dt) {
-  const llgo_grid& g = H.g;
-  const llgo_opts& o = H.o;
-  H.omega = o.omega > 0 ? o.omega : (g.dim == 2 ? 4.0 / 5.0 : 6.0 / 7.0);
-  assemble(g, m_tilde, alpha, dt, H.A);
-  diag_inverses(H.A, H.dinv0);
-  H.lv.clear();
-  H.lv.emplace_back();
-  if (o.left_scale)
-    left_scale(H.A, H.dinv0, H.lv[0].A);
-  else
-    H.lv[0].A = H.A;
+// The aggregation hierarchy of the grid graph (O5, Sec. 3.1.1), which does
+// not depend on the field: per level, npass passes of pairwise matching on
+// the current integer graph, the composite aggregate map, and the coarse
+// graph P^T G P.  Coarsening stops at <= max_coarse nodes, at max_levels, or
+// when a level would keep more than `stagnation` of its nodes.  visit(l, G,
+// agg, nc) is called for every level l that gets a next level, with G the
+// graph of level l.  Returns the number of levels.
+template <typename Visit>
+int aggregate_levels(const llgo_grid& g, const llgo_opts& o, Visit visit) {
   Graph G;
   grid_graph(g, G);
   for (int l = 0;; ++l) {
-    Level& L = H.lv[l];
-    diag_inverses(L.A, L.dinv);
-    const int64_t N = L.A.n;
-    if (N <= o.max_coarse || l + 1 >= o.max_levels) break;
+    const int64_t N = G.n;
+    if (N <= o.max_coarse || l + 1 >= o.max_levels) return l + 1;
     // npass passes of pairwise matching; the composite aggregate map is the
     // composition of the per-pass maps
     std::vector<int32_t> agg(N);
@@ -888,10 +883,29 @@ int build(Hier& H, const double* m_tilde, double alpha, double dt) {
       Graph nxt;
       coarse_graph(cur, a, c, nxt);
       for (int64_t i = 0; i < N; ++i) agg[i] = a[agg[i]];
-      cur = nxt;
+      cur = std::move(nxt);
       nc = c;
     }
-    if ((double)nc > o.stagnation * (double)N) break;
+    if ((double)nc > o.stagnation * (double)N) return l + 1;
+    visit(l, G, agg, nc);
+    G = std::move(cur);
+  }
+}
+
+int build(Hier& H, const double* m_tilde, double alpha, double dt) {
+  const llgo_grid& g = H.g;
+  const llgo_opts& o = H.o;
+  H.omega = o.omega > 0 ? o.omega : (g.dim == 2 ? 4.0 / 5.0 : 6.0 / 7.0);
+  assemble(g, m_tilde, alpha, dt, H.A);
+  diag_inverses(H.A, H.dinv0);
+  H.lv.clear();
+  H.lv.emplace_back();
+  if (o.left_scale)
+    left_scale(H.A, H.dinv0, H.lv[0].A);
+  else
+    H.lv[0].A = H.A;
+  aggregate_levels(g, o, [&](int l, const Graph& G, const std::vector<int32_t>& agg, int64_t nc) {
+    Level& L = H.lv[l];
     L.agg = agg;
     L.nc = nc;
     if (o.smoother == 1) {
@@ -903,8 +917,8 @@ int build(Hier& H, const double* m_tilde, double alpha, double dt) {
     Level next;
     galerkin(L.A, L.agg, nc, next.A);
     H.lv.push_back(std::move(next));
-    G = cur;
-  }
+  });
+  for (Level& L : H.lv) diag_inverses(L.A, L.dinv);
   const Level& C = H.lv.back();
   if (C.A.n > o.max_dense) return LLGO_ERR_UNSUPPORTED;
   H.nd = 3 * C.A.n;
@@ -945,6 +959,23 @@ void llgo_default_opts(llgo_opts* o) {
   o->krylov = 0;
   o->kcycle_depth = 0;
   o->smoother = 0;
+}
+
+int llgo_aggregate_levels(const llgo_grid* g, const llgo_opts* o, int32_t* levels, int64_t* level_nodes,
+                          int32_t* agg, int64_t cap) {
+  if (!grid_ok(g) || !opts_ok(o) || !levels || !level_nodes || cap < 0 || (cap > 0 && !agg)) return LLGO_ERR_ARG;
+  int64_t off = 0;
+  bool fits = true;
+  const int L = aggregate_levels(*g, *o, [&](int l, const Graph& G, const std::vector<int32_t>& a, int64_t nc) {
+    level_nodes[l] = G.n;
+    level_nodes[l + 1] = nc;
+    if (off + G.n > cap) fits = false;
+    if (fits) std::copy(a.begin(), a.end(), agg + off);
+    off += G.n;
+  });
+  if (L == 1) level_nodes[0] = num_nodes(*g);
+  *levels = L;
+  return fits ? LLGO_OK : LLGO_ERR_ARG;
 }
 
 uint64_t llgo_splitmix64(uint64_t x) { return splitmix64(x); }
@@ -1180,66 +1211,75 @@ namespace {
 // Newell, Williams and Dunlop (1993): the generating functions of the
 // diagonal (f) and off-diagonal (g) cell-averaged demagnetizing tensor.
 // Terms whose prefactor vanishes are dropped (their limits are zero).
-double newell_f(double x, double y, double z) {
+// The tensor is the 27-point second difference of f or g, whose terms grow
+// like |r|^3 while the tensor falls like |r|^-3: near the 16-cell switch to
+// the dipole the difference cancels about eight digits.  The functions and
+// the difference are therefore evaluated in long double (64-bit significand
+// on x86-64), which leaves the rounded double result within a few units of
+// the last place of the exact cell average.
+using ld = long double;
+const ld PI_L = 3.141592653589793238462643383279502884L;
+
+ld newell_f(ld x, ld y, ld z) {
   x = std::fabs(x);
   y = std::fabs(y);
   z = std::fabs(z);
-  const double x2 = x * x, y2 = y * y, z2 = z * z;
-  const double R = std::sqrt(x2 + y2 + z2);
-  if (R == 0.0) return 0.0;
-  double r = 0.0;
-  if (y > 0.0 && z2 != x2) r += 0.5 * y * (z2 - x2) * std::asinh(y / std::sqrt(x2 + z2));
-  if (z > 0.0 && y2 != x2) r += 0.5 * z * (y2 - x2) * std::asinh(z / std::sqrt(x2 + y2));
-  if (x > 0.0 && y > 0.0 && z > 0.0) r -= x * y * z * std::atan(y * z / (x * R));
-  r += (2.0 * x2 - y2 - z2) * R / 6.0;
+  const ld x2 = x * x, y2 = y * y, z2 = z * z;
+  const ld R = std::sqrt(x2 + y2 + z2);
+  if (R == 0.0L) return 0.0L;
+  ld r = 0.0L;
+  if (y > 0.0L && z2 != x2) r += 0.5L * y * (z2 - x2) * std::asinh(y / std::sqrt(x2 + z2));
+  if (z > 0.0L && y2 != x2) r += 0.5L * z * (y2 - x2) * std::asinh(z / std::sqrt(x2 + y2));
+  if (x > 0.0L && y > 0.0L && z > 0.0L) r -= x * y * z * std::atan(y * z / (x * R));
+  r += (2.0L * x2 - y2 - z2) * R / 6.0L;
   return r;
 }
 
-double newell_g(double x, double y, double z) {
-  const double sgn = (x > 0 ? 1.0 : (x < 0 ? -1.0 : 0.0)) * (y > 0 ? 1.0 : (y < 0 ? -1.0 : 0.0));
-  if (sgn == 0.0) return 0.0;
+ld newell_g(ld x, ld y, ld z) {
+  const ld sgn = (x > 0 ? 1.0L : (x < 0 ? -1.0L : 0.0L)) * (y > 0 ? 1.0L : (y < 0 ? -1.0L : 0.0L));
+  if (sgn == 0.0L) return 0.0L;
   x = std::fabs(x);
   y = std::fabs(y);
   z = std::fabs(z);
-  const double x2 = x * x, y2 = y * y, z2 = z * z;
-  const double R = std::sqrt(x2 + y2 + z2);
-  double r = 0.0;
-  if (z > 0.0) r += x * y * z * std::asinh(z / std::sqrt(x2 + y2));
-  r += (y / 6.0) * (3.0 * z2 - y2) * std::asinh(x / std::sqrt(y2 + z2));
-  r += (x / 6.0) * (3.0 * z2 - x2) * std::asinh(y / std::sqrt(x2 + z2));
-  if (z > 0.0) {
-    r -= (z2 * z / 6.0) * std::atan(x * y / (z * R));
-    r -= (z * y2 / 2.0) * std::atan(x * z / (y * R));
-    r -= (z * x2 / 2.0) * std::atan(y * z / (x * R));
+  const ld x2 = x * x, y2 = y * y, z2 = z * z;
+  const ld R = std::sqrt(x2 + y2 + z2);
+  ld r = 0.0L;
+  if (z > 0.0L) r += x * y * z * std::asinh(z / std::sqrt(x2 + y2));
+  r += (y / 6.0L) * (3.0L * z2 - y2) * std::asinh(x / std::sqrt(y2 + z2));
+  r += (x / 6.0L) * (3.0L * z2 - x2) * std::asinh(y / std::sqrt(x2 + z2));
+  if (z > 0.0L) {
+    r -= (z2 * z / 6.0L) * std::atan(x * y / (z * R));
+    r -= (z * y2 / 2.0L) * std::atan(x * z / (y * R));
+    r -= (z * x2 / 2.0L) * std::atan(y * z / (x * R));
   }
-  r -= x * y * R / 3.0;
+  r -= x * y * R / 3.0L;
   return sgn * r;
 }
 
 // the 27-point second difference (weights 2 at 0, -1 at +-1 per axis) of fun
 // around (X, Y, Z) with spacings (a, b, c), over 4 pi a b c
 template <typename Fn>
-double newell_sum(Fn fun, double X, double Y, double Z, double a, double b, double c) {
-  const double w[3] = {-1.0, 2.0, -1.0};
-  double acc = 0.0;
+double newell_sum(Fn fun, ld X, ld Y, ld Z, ld a, ld b, ld c) {
+  const ld w[3] = {-1.0L, 2.0L, -1.0L};
+  ld acc = 0.0L;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j)
       for (int k = 0; k < 3; ++k)
         acc += w[i] * w[j] * w[k] * fun(X + (i - 1) * a, Y + (j - 1) * b, Z + (k - 1) * c);
-  return acc / (4.0 * M_PI * a * b * c);
+  return (double)(acc / (4.0L * PI_L * a * b * c));
 }
 
 void demag(double X, double Y, double Z, double dx, double dy, double dz, double* N) {
   const double far = std::max(std::fabs(X) / dx, std::max(std::fabs(Y) / dy, std::fabs(Z) / dz));
   if (far > 16.0) {
-    const double r2 = X * X + Y * Y + Z * Z, r = std::sqrt(r2);
-    const double k = -(dx * dy * dz) / (4.0 * M_PI * r2 * r);
-    N[0] = k * (3.0 * X * X / r2 - 1.0);
-    N[1] = k * (3.0 * Y * Y / r2 - 1.0);
-    N[2] = k * (3.0 * Z * Z / r2 - 1.0);
-    N[3] = k * 3.0 * X * Y / r2;
-    N[4] = k * 3.0 * X * Z / r2;
-    N[5] = k * 3.0 * Y * Z / r2;
+    const ld x = X, y = Y, z = Z, r2 = x * x + y * y + z * z, r = std::sqrt(r2);
+    const ld k = -((ld)dx * dy * dz) / (4.0L * PI_L * r2 * r);
+    N[0] = (double)(k * (3.0L * x * x / r2 - 1.0L));
+    N[1] = (double)(k * (3.0L * y * y / r2 - 1.0L));
+    N[2] = (double)(k * (3.0L * z * z / r2 - 1.0L));
+    N[3] = (double)(k * 3.0L * x * y / r2);
+    N[4] = (double)(k * 3.0L * x * z / r2);
+    N[5] = (double)(k * 3.0L * y * z / r2);
     return;
   }
   N[0] = newell_sum(newell_f, X, Y, Z, dx, dy, dz);

@@ -90,6 +90,15 @@ int llgo_match_pass(int64_t n, const int64_t* rp, const int32_t* ci, const int64
 
 /* Galerkin product P^T A P of a 3x3 BSR matrix for Boolean P given by agg.
  * Call with out arrays NULL to get *nnzb_c; then call again with storage. */
+/* The field-independent aggregation hierarchy of the grid graph alone (the
+ * matching passes, coarse graphs and stopping rules of llgo_setup, without
+ * any matrix values): *levels levels, level_nodes[0..levels-1] (at least
+ * max_levels entries), and the aggregate maps of levels 0..levels-2
+ * concatenated in agg (node -> aggregate on the next level; cap entries;
+ * LLGO_ERR_ARG when it is too small). */
+int llgo_aggregate_levels(const llgo_grid* g, const llgo_opts* o, int32_t* levels, int64_t* level_nodes,
+                          int32_t* agg, int64_t cap);
+
 int llgo_galerkin(int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
                   const int32_t* agg, int64_t nc,
                   int64_t* nnzb_c, int64_t* rp_c, int32_t* ci_c, double* val_c);

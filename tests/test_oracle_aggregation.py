@@ -284,3 +284,19 @@ def test_coarsening_rate(orc):
     assert sizes[-1] <= 256
     for a, b in zip(sizes, sizes[1:]):
         assert 0.2 < b / a < 0.4
+
+
+@pytest.mark.parametrize("dim,n", [(2, 45), (3, 14)])
+def test_aggregate_levels_alone_equals_hierarchy(orc, dim, n):
+    """The graph-only hierarchy (used at sizes where the full oracle
+    hierarchy does not fit a test) gives the hierarchy's maps and sizes."""
+    g = orc.make_grid(dim, n)
+    o = orc.default_opts()
+    sizes, maps = orc.aggregate_levels(g, o)
+    m = I.smooth_unit_field(dim, n, seed=4)
+    H = orc.Hierarchy(g, o, m, 0.1, 1e-3)
+    assert len(sizes) == H.num_levels
+    for l in range(H.num_levels):
+        assert sizes[l] == len(H.level(l).rp) - 1
+    for l in range(H.num_levels - 1):
+        assert np.array_equal(maps[l], H.level(l).agg)
