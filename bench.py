@@ -1,13 +1,14 @@
 """Benchmark: semi-implicit Landau-Lifshitz time steps on one MI355X.
 
-One step = assemble the 3x3-block operator for m^n, rebuild the aggregation
-AMG hierarchy, solve with V-cycle-preconditioned FGMRES to rel. residual
-1e-8, project.  Default workload: 2D 1024x1024 Neumann grid (3,145,728
-unknowns), smoothed random unit field, alpha = 0.02, dt = 1e-4, FP64, the
-hierarchy rebuilt every step; the same run is repeated with the FP32-AMG form.
-Prints ONE JSON line (metric unknowns*steps/s).
+One step = assemble the 3x3-block operator for m^n (+ dt F), rebuild the
+aggregation AMG hierarchy, solve with AMG-preconditioned FGMRES to rel.
+residual 1e-8, project.  Default workload: the 3D 256^3 manufactured solution
+(50,331,648 unknowns, alpha = 0.1, dt = 1e-4, forcing F resident on the device),
+timed in the FP32-AMG form (`value`) and the FP64 form over the same steps;
+then, as secondary keys, the 2D 1024^2 rough-field forms and a short serving
+run.  Prints ONE JSON line (metric unknowns*steps/s).
 
-  python bench.py [--gpus 1] [--steps 50] [--warmup 3]
+  python bench.py [--gpus 1] [--steps 20] [--warmup 5]
 """
 from __future__ import annotations
 
@@ -24,6 +25,19 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 
+# forms timed per workload when --forms is not given (the first gives `value`):
+# the metric compares FP32-AMG with FP64, both at rel.res 1e-8
+DEFAULT_FORMS = {
+    "mms3d_256": "fp32_amg:1:jacobi:factored,fp64:1:jacobi:factored",
+    "rough3d_128": "fp32_amg:0:jacobi:factored,fp64:0:jacobi:factored",
+    "rough2d_1024": "fp32_amg:1:jacobi:factored,fp64:1:jacobi:factored",
+    "vortex64": "fp64:1:jacobi:factored,fp32_amg:1:jacobi:factored",
+}
+# the oracle runs one step of the workload when it takes about 10-30 s on one
+# host core; larger workloads are sampled on the same problem at half the grid
+# points per axis
+ORACLE_MAX_NODES = 2_200_000
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -32,14 +46,18 @@ def log(*a):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=50)
-    p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="rough2d_1024")
-    p.add_argument("--forms", default="fp64:1:jacobi:factored,fp32_amg:1:jacobi:factored,fp64:1,fp32_amg:1,"
-                                      "fp64:0:jacobi:factored",
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--workload", default="mms3d_256")
+    p.add_argument("--forms", default=None,
                    help="comma list of precision:kcycle_depth[:smoother[:operator]] (depth 0 = V-cycle; "
                         "smoother jacobi or mcgs, default jacobi; grid-level operator bsr or factored, "
-                        "default bsr); the first gives `value`")
+                        "default bsr); the first gives `value`.  Default: per workload (DEFAULT_FORMS)")
+    p.add_argument("--no-secondary", action="store_true",
+                   help="skip the secondary keys (the 1024^2 forms and the short serving run)")
+    p.add_argument("--secondary-workload", default="rough2d_1024")
+    p.add_argument("--serve-leg-requests", type=int, default=24,
+                   help="requests of the serving run reported as a secondary key")
     p.add_argument("--roofline-class", default="outer_spmv")
     p.add_argument("--alpha", type=float, default=None, help="override the workload's alpha")
     p.add_argument("--kdepth", type=int, default=None, help="override the K-cycle depth of every form")
@@ -106,13 +124,14 @@ def algorithmic_bytes(cls: str, st, N: int, precision: str, operator: str = "bsr
 
 
 def forcing_list(torch, w, total: int):
-    """Manufactured forcing F(t_{k+1}) for every step of the run, resident on
-    the device before the timed region (None when the workload has none)."""
+    """Manufactured forcing F(t_{k+1}) for every step of the run, generated on
+    the device and resident there before the timed region (None when the
+    workload has none)."""
     if not w.forcing:
         return [None] * total
     import llg_inputs as I
-    return [torch.from_numpy(I.manufactured_forcing(w.dim, w.n, (k + 1) * w.dt, w.alpha)).cuda()
-            for k in range(total)]
+    dev = torch.device("cuda")
+    return [I.manufactured_forcing(w.dim, w.n, (k + 1) * w.dt, w.alpha, xp=torch, device=dev) for k in range(total)]
 
 
 def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str, Fs, kdepth: int = 0,
@@ -120,7 +139,9 @@ def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str, Fs, kd
     opts = llg.default_opts(rtol=w.rtol, precision=form, kcycle_depth=kdepth, smoother=smoother,
                             fine_operator=operator)
     grid = llg.make_grid(w.dim, w.n)
+    t0 = time.perf_counter()
     S = llg.Solver(grid, opts)
+    t_create = time.perf_counter() - t0
     m0 = torch.from_numpy(w.m0()).cuda()
     bufs = [m0.clone(), torch.empty_like(m0)]
     cur = 0
@@ -149,46 +170,91 @@ def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str, Fs, kd
     err_exact = None
     if w.forcing:
         import llg_inputs as I
-        me = torch.from_numpy(I.exact_solution(w.dim, w.n, (warmup + steps) * w.dt)).cuda()
+        me = I.exact_solution(w.dim, w.n, (warmup + steps) * w.dt, xp=torch, device=final.device)
         err_exact = float((final - me).abs().max())
-    # single step from m0 for the cross-form comparison (outside the timed region)
-    one, _, _ = S.step(m0, w.alpha, w.dt, forcing=Fs[0])
+        del me
     res = {"seconds": el, "iters": iters, "kernel_ms": kms, "kernel_launches": klaunch, "stats": st,
-           "one_step": one, "levels": st.levels, "level_nodes": list(st.level_nodes[:st.levels]),
+           "levels": st.levels, "level_nodes": list(st.level_nodes[:st.levels]),
            "level_nnzb": list(st.level_nnzb[:st.levels]), "err_vs_exact": err_exact,
-           "workspace_GB": S.workspace_bytes / 1e9}
+           "workspace_GB": S.workspace_bytes / 1e9, "create_s": t_create,
+           "ms_setup_last": st.ms_setup, "ms_solve_last": st.ms_solve}
     S.close()
-    del S
+    del S, bufs, m0, final
     torch.cuda.empty_cache()
     return res
 
 
-def cpu_baseline(w, nsteps: int, kdepth: int = 0, smoother: str = "jacobi"):
-    """The oracle timed on `nsteps` steps of the workload from m0 (forcing of
-    the first steps when the workload has one), with the cycle and smoother of
-    the main form; also returns its first step."""
-    import numpy as np
-    import oracle
+def host_info() -> dict:
+    """CPU model, logical CPUs and memory of the host the oracle runs on."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    info["mem_GB"] = round(int(line.split()[1]) / 1e6, 1)
+                    break
+    except OSError:
+        pass
+    return info
+
+
+def sample_step(w, warmup: int):
+    """The step the CPU baseline times: the workload's own step after the
+    warm-up steps when the oracle takes it in about 10-30 s, else the same
+    problem at half the grid points per axis.  Forced workloads start from
+    the exact solution m_e(t_w) with the forcing F(t_w + dt); the others from
+    the workload's m0.  Returns (dim, n, m, F, label)."""
     import llg_inputs as I
-    g = oracle.make_grid(w.dim, w.n)
+    n = w.n if w.nodes <= ORACLE_MAX_NODES else w.n // 2
+    if w.forcing:
+        t = warmup * w.dt
+        m = I.exact_solution(w.dim, n, t)
+        F = I.manufactured_forcing(w.dim, n, t + w.dt, w.alpha)
+        label = "one step of the manufactured problem of the %s workload at %d^%d (alpha %g, dt %g, from the " \
+                "exact m_e(t) at t = %d dt, forcing F(t + dt))" % (w.name, n, w.dim, w.alpha, w.dt, warmup)
+    else:
+        m = I.smooth_unit_field(w.dim, n, w.seed) if n != w.n else w.m0()
+        F = None
+        label = "the first step of the %s workload at %d^%d" % (w.name, n, w.dim)
+    return w.dim, n, m, F, label
+
+
+def cpu_baseline(w, warmup: int, kdepth: int, smoother: str):
+    """The oracle (single-threaded C++, FP64) timed on sample_step, with the
+    workload's rtol and the main form's cycle and smoother."""
+    import oracle
+    dim, n, m, F, label = sample_step(w, warmup)
+    g = oracle.make_grid(dim, n)
     o = oracle.default_opts(rtol=w.rtol, kcycle_depth=kdepth, smoother=1 if smoother == "mcgs" else 0)
-    m = w.m0()
     t0 = time.perf_counter()
-    iters = []
-    first = None
-    for k in range(nsteps):
-        F = I.manufactured_forcing(w.dim, w.n, (k + 1) * w.dt, w.alpha) if w.forcing else None
-        rc, m, st = oracle.step(g, o, m, w.alpha, w.dt, F)
-        iters.append(st.iters)
-        if first is None:
-            first = m.copy()
+    rc, out, st = oracle.step(g, o, m, w.alpha, w.dt, F)
     el = time.perf_counter() - t0
-    return {"value": 3.0 * w.nodes * nsteps / el, "unit": "unknowns*steps/s", "cores": 1, "kind": "oracle",
-            "sample": "%d step(s) of the %s workload (assembly, hierarchy, FGMRES to rtol %g with the %s, "
-                      "projection), single-threaded C++ oracle, %.1f s, %s FGMRES iterations"
-                      % (nsteps, w.name, w.rtol, "K-cycle on levels 1..%d" % kdepth if kdepth else "V-cycle",
-                         el, iters),
-            "host_threads_available": os.cpu_count()}, first
+    unknowns = 3 * n ** dim
+    res = {"value": unknowns / el, "unit": "unknowns*steps/s", "cores": 1, "kind": "oracle",
+           "sample": "%s; assembly, hierarchy, FGMRES(30) to rtol %g with the %s, projection; %d FGMRES "
+                     "iterations; %.1f s on 1 host core (single-threaded C++, -O2)" % (
+                         label, w.rtol, "K-cycle on levels 1..%d" % kdepth if kdepth else "V-cycle", st.iters, el),
+           "seconds": el, "iters": st.iters, "host": host_info()}
+    return res, (dim, n, m, F, out, st.iters)
+
+
+def gpu_sample_error(llg, torch, w, sample, form: str, kdepth: int, smoother: str, operator: str):
+    """The GPU's step (the given form) of the CPU baseline's sample step, and
+    its max-norm difference from the oracle's."""
+    import numpy as np
+    dim, n, m, F, ref, _ = sample
+    S = llg.Solver(llg.make_grid(dim, n), llg.default_opts(rtol=w.rtol, precision=form, kcycle_depth=kdepth,
+                                                          smoother=smoother, fine_operator=operator))
+    out, s, st = S.step(torch.from_numpy(m).cuda(), w.alpha, w.dt,
+                        forcing=torch.from_numpy(F).cuda() if F is not None else None)
+    d = float(np.abs(out.cpu().numpy() - ref).max())
+    S.close()
+    return d, st.iters
 
 
 def baselines_bench(a, llg, torch, w):
@@ -308,30 +374,51 @@ def field_bench(a, llg, torch, w, form: str, kdepth: int):
     print(json.dumps(out), flush=True)
 
 
-def serve_bench(a):
-    """Serving workload: Poisson arrivals (8/s) of 20-step simulations, 2D n in
-    128..2048 or 3D n in 32..192, FP32-AMG, admission by device footprint."""
+SERVE_SOLVER = "FP32-AMG, factored grid level; K-cycle on level 1 (2D), V-cycle (3D)"
+
+
+def serve_inputs(count: int, steps: int):
+    """The request stream and its initial fields, generated on the host by a
+    process pool before anything touches the GPU."""
+    import llg_inputs as I
+    reqs = I.serving_requests(count=count, steps=steps)
+    log("[serve] generating the initial fields of %d requests" % len(reqs))
+    return reqs, I.serving_inputs(reqs)
+
+
+def serve_report(count: int, steps: int, workers: int, prepared=None) -> dict:
+    """The serving workload's request stream (Poisson arrivals at 8/s of
+    `steps`-step simulations, 2D n in 128..2048 or 3D n in 32..192, initial
+    fields from the input recipe with seed 5000 + r), served in FP32-AMG at
+    rel.res 1e-8 with admission by device footprint within 0.9 of the free
+    device memory."""
     import llg_inputs as I
     from paper_2608_09102_amd.serve import HipRunner, Server, default_budget
-    reqs = I.serving_requests(count=a.requests, steps=a.serve_steps)
-    budget = default_budget(0.8)
+    reqs, inputs = prepared if prepared is not None else serve_inputs(count, steps)
+    budget = default_budget(0.9)
     # FP32-AMG on the factored grid level; the K-cycle on level 1 in 2D, the
     # V-cycle in 3D (the faster cycle on each, as measured on the benchmark grids)
-    runner = HipRunner(opts_kw=dict(rtol=1e-8, precision="fp32_amg", fine_operator="factored"), workers=a.workers,
-                       opts_by_dim={2: dict(kcycle_depth=1), 3: dict(kcycle_depth=0)})
-    log("[serve] %d requests, %d workers, budget %.1f GB" % (len(reqs), a.workers, budget / 1e9))
-    rep = Server(runner, budget, a.workers).run(reqs, log=log)
+    runner = HipRunner(opts_kw=dict(rtol=1e-8, precision="fp32_amg", fine_operator="factored"), workers=workers,
+                       opts_by_dim={2: dict(kcycle_depth=1), 3: dict(kcycle_depth=0)}, inputs=inputs)
+    log("[serve] %d requests, %d workers, budget %.1f GB" % (len(reqs), workers, budget / 1e9))
+    rep = Server(runner, budget, workers).run(reqs, log=log)
     offered = sum(3 * r.nodes * r.steps for r in reqs) / max(r.arrival for r in reqs)
-    out = {"metric": "serving step latency and throughput (FP32-AMG, rel.res 1e-8)",
-           "value": rep["served_unknowns_steps_per_s"], "unit": "unknowns*steps/s", "n_gpus": 1,
-           "higher_is_better": True, "data": "synthetic",
-           "config": {"workload": "serving", "requests": len(reqs), "rate_per_s": 8, "steps": a.serve_steps,
-                      "workers": a.workers, "budget_bytes": budget,
-                      "solver": "FP32-AMG, factored grid level; K-cycle on level 1 (2D), V-cycle (3D)"},
-           "offered_unknowns_steps_per_s": offered}
+    out = {"requests": len(reqs), "rate_per_s": 8, "steps": steps, "workers": workers, "budget_bytes": budget,
+           "solver": SERVE_SOLVER, "offered_unknowns_steps_per_s": offered}
     for k, v in rep.items():
         if k != "outcomes":
             out[k] = v
+    return out
+
+
+def serve_bench(a, prepared=None):
+    rep = serve_report(a.requests, a.serve_steps, a.workers, prepared)
+    out = {"metric": "serving step latency and throughput (FP32-AMG, rel.res 1e-8)",
+           "value": rep["served_unknowns_steps_per_s"], "unit": "unknowns*steps/s", "n_gpus": 1,
+           "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": "serving", "requests": rep["requests"], "rate_per_s": 8, "steps": a.serve_steps,
+                      "workers": a.workers, "budget_bytes": rep["budget_bytes"], "solver": SERVE_SOLVER}}
+    out.update({k: v for k, v in rep.items() if k not in out["config"]})
     print(json.dumps(out), flush=True)
 
 
@@ -341,6 +428,11 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(requested --gpus %d)" % a.gpus, file=sys.stderr)
         sys.exit(2)
+    prepared = None
+    if a.serve:
+        prepared = serve_inputs(a.requests, a.serve_steps)
+    elif not a.no_secondary and a.serve_leg_requests > 0 and not (a.baselines or a.field or a.calibrate_copy):
+        prepared = serve_inputs(a.serve_leg_requests, a.serve_steps)
     import torch
     if a.calibrate_copy:
         # plain device copy of 1 GiB: the reference for the PMC byte counters
@@ -364,7 +456,7 @@ def main():
     import llg_inputs as I
     import paper_2608_09102_amd as llg
     if a.serve:
-        serve_bench(a)
+        serve_bench(a, prepared)
         return
     w = I.WORKLOADS[a.workload]
     if a.alpha is not None:
@@ -377,7 +469,7 @@ def main():
         field_bench(a, llg, torch, w, f0[0], int(f0[1]) if len(f0) > 1 and f0[1] else 0)
         return
     forms = []
-    for f in a.forms.split(","):
+    for f in (a.forms or DEFAULT_FORMS[w.name]).split(","):
         if not f:
             continue
         parts = f.split(":")
@@ -388,6 +480,7 @@ def main():
         if a.kdepth is not None:
             kd = a.kdepth
         forms.append((f, prec, kd, sm, op))
+    log("[bench] generating the forcing of %d steps on the device" % (a.warmup + a.steps) if w.forcing else "")
     Fs = forcing_list(torch, w, a.warmup + a.steps)
     res = {}
     for key, prec, kd, sm, op in forms:
@@ -395,9 +488,11 @@ def main():
             % (w.name, prec, kd, sm, op, a.warmup, a.steps))
         res[key] = run_form(llg, torch, w, prec, a.steps, a.warmup, a.roofline_class, Fs, kd, sm, op)
         r = res[key]
-        log("  %.3f s, %.2f ms/step, iters/step %.1f, %s kernel %.3f ms over %d launches"
+        log("  %.3f s, %.2f ms/step, iters/step %.1f, %s kernel %.3f ms over %d launches, create %.2f s"
             % (r["seconds"], 1e3 * r["seconds"] / a.steps, sum(r["iters"]) / len(r["iters"]),
-               a.roofline_class, r["kernel_ms"], r["kernel_launches"]))
+               a.roofline_class, r["kernel_ms"], r["kernel_launches"], r["create_s"]))
+    del Fs
+    torch.cuda.empty_cache()
     main_key, main_form, main_kd, main_sm, main_op = forms[0]
     r = res[main_key]
     unknowns = w.unknowns
@@ -407,8 +502,18 @@ def main():
     avg_s = r["kernel_ms"] / 1e3 / max(1, r["kernel_launches"])
     achieved = lb / avg_s / 1e9 if avg_s > 0 else 0.0
     traffic = read_traffic(a.roofline_class, w.name, main_form, main_op)
+
+    def form_name(prec, kd, sm, op):
+        return "%s_%s%s%s" % (prec, "k%d" % kd if kd else "vcycle", "" if sm == "jacobi" else "_" + sm,
+                              "" if op == "bsr" else "_" + op)
+
+    def cycle(kd, sm):
+        return "aggregation AMG, %s (1,1), %s" % ("damped block-Jacobi" if sm == "jacobi" else
+                                                  "multicolour block Gauss-Seidel",
+                                                  "K-cycle on levels 1..%d" % kd if kd else "V-cycle")
     out = {
-        "metric": "unknowns*steps/s (FP64 AMG-FGMRES, rel.res 1e-8)",
+        "metric": "unknowns*steps/s, FP32-AMG vs FP64 at rel.res 1e-8" if main_form == "fp32_amg"
+                  else "unknowns*steps/s (FP64 AMG-FGMRES, rel.res 1e-8)",
         "value": value,
         "unit": "unknowns*steps/s",
         "n_gpus": 1,
@@ -422,10 +527,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "grid": "%dD %s" % (w.dim, "x".join([str(w.n)] * w.dim)),
                    "unknowns": unknowns, "alpha": w.alpha, "dt": w.dt, "rtol": w.rtol,
-                   "form": main_form, "hierarchy": "rebuilt every step", "krylov": "FGMRES(30)",
-                   "preconditioner": "aggregation AMG, %s (1,1), %s" % (
-                       "damped block-Jacobi" if main_sm == "jacobi" else "multicolour block Gauss-Seidel",
-                       "K-cycle on levels 1..%d" % main_kd if main_kd else "V-cycle"),
+                   "forcing": "manufactured (resident on the device)" if w.forcing else None,
+                   "form": main_form, "hierarchy": "rebuilt every step", "krylov": "FGMRES(30), FP64",
+                   "preconditioner": cycle(main_kd, main_sm),
                    "grid_operator": "3x3-block sliced ELL" if main_op == "bsr" else "factored (one block per node)"},
         "iters_per_step": sum(r["iters"]) / len(r["iters"]),
         "iters": r["iters"],
@@ -437,30 +541,44 @@ def main():
                      "traffic": traffic, "algorithmic_bytes_per_launch": lb,
                      "avg_launch_us": avg_s * 1e6, "launches": r["kernel_launches"]},
     }
-    def form_name(prec, kd, sm, op):
-        return "%s_%s%s%s" % (prec, "k%d" % kd if kd else "vcycle", "" if sm == "jacobi" else "_" + sm,
-                              "" if op == "bsr" else "_" + op)
-
+    if r["err_vs_exact"] is not None:
+        out["err_vs_exact"] = r["err_vs_exact"]
+        out["err_vs_exact_note"] = ("max-norm distance from the manufactured m_e after warmup + steps steps; the "
+                                    "forcing uses the continuous Laplacian, so it holds the O(h^2) spatial error "
+                                    "besides the O(dt) temporal one")
     for key, prec, kd, sm, op in forms[1:]:
         rf = res[key]
-        diff = float((rf["one_step"] - r["one_step"]).abs().max())
         name = form_name(prec, kd, sm, op)
         out[name] = {"value": unknowns * a.steps / rf["seconds"], "ms_per_step": 1e3 * rf["seconds"] / a.steps,
                      "iters_per_step": sum(rf["iters"]) / len(rf["iters"]), "iters": rf["iters"],
                      "err_vs_exact": rf["err_vs_exact"], "kcycle_depth": kd, "smoother": sm, "grid_operator": op,
-                     "speedup_vs_main": (unknowns * a.steps / rf["seconds"]) / value,
-                     "max_abs_diff_one_step_vs_main": diff}
-    if r["err_vs_exact"] is not None:
-        out["err_vs_exact"] = r["err_vs_exact"]
+                     "value_ratio_main_over_this": value / (unknowns * a.steps / rf["seconds"])}
     if not a.no_cpu_baseline:
-        log("[bench] cpu baseline: oracle, %d step(s)" % a.cpu_steps)
-        out["cpu_baseline"], ref = cpu_baseline(w, a.cpu_steps, main_kd, main_sm)
-        # error of every form's first step against the FP64 oracle's (both at the workload's rtol)
-        import numpy as np
-        out["err_vs_oracle"] = float(np.abs(r["one_step"].cpu().numpy() - ref).max())
-        for key, prec, kd, sm, op in forms[1:]:
-            name = form_name(prec, kd, sm, op)
-            out[name]["err_vs_oracle"] = float(np.abs(res[key]["one_step"].cpu().numpy() - ref).max())
+        log("[bench] cpu baseline: the oracle on one step")
+        cb, sample = cpu_baseline(w, a.warmup, main_kd, main_sm)
+        out["cpu_baseline"] = cb
+        log("  %s" % cb["sample"])
+        # every form's step of the same sample against the oracle's (both at the workload's rtol)
+        errs = {}
+        for key, prec, kd, sm, op in forms:
+            d, its = gpu_sample_error(llg, torch, w, sample, prec, kd, sm, op)
+            errs[form_name(prec, kd, sm, op)] = {"max_abs_diff": d, "gpu_iters": its, "oracle_iters": sample[5]}
+        out["err_vs_oracle_sample"] = errs
+    if not a.no_secondary:
+        if a.secondary_workload and a.secondary_workload != w.name:
+            w2 = I.WORKLOADS[a.secondary_workload]
+            sec = {}
+            for f in DEFAULT_FORMS[w2.name].split(","):
+                prec, kd, sm, op = f.split(":")
+                log("[bench] secondary %s %s" % (w2.name, f))
+                rf = run_form(llg, torch, w2, prec, a.steps, a.warmup, "none", [None] * (a.warmup + a.steps),
+                              int(kd), sm, op)
+                sec[form_name(prec, int(kd), sm, op)] = {
+                    "value": w2.unknowns * a.steps / rf["seconds"], "ms_per_step": 1e3 * rf["seconds"] / a.steps,
+                    "iters_per_step": sum(rf["iters"]) / len(rf["iters"]), "preconditioner": cycle(int(kd), sm)}
+            out[w2.name] = sec
+        if a.serve_leg_requests > 0:
+            out["serving"] = serve_report(a.serve_leg_requests, a.serve_steps, a.workers, prepared)
     print(json.dumps(out), flush=True)
 
 

@@ -258,6 +258,19 @@ llg_status llg_step_field(llg_ctx* ctx, const double* d_m_n, const double* d_m_n
  * stream. */
 llg_status llg_stray_field(llg_ctx* ctx, const double* d_m, double* d_h);
 
+/* Host copy of the cell-averaged demagnetizing tensor the stray field uses
+ * (eq. stray_field with m constant on the cubic cells of side h; Newell,
+ * Williams and Dunlop 1993 for cells within one cell of each other, the
+ * cell average of the point-dipole kernel by quadrature up to 16 cells, the
+ * point dipole beyond), as the device computes it, for every cell offset
+ * k in [-(n_d - 1), n_d - 1] per axis: h_out[c][kz][ky][kx] with index
+ * kx + (n_x - 1) fastest, c = 0..5 for xx, yy, zz, xy, xz, yz;
+ * cap >= 6 (2 n_x - 1)(2 n_y - 1)(2 n_z - 1) doubles.  The entries do not
+ * depend on h.  Needs a context created with opts.stray_field (else
+ * INVALID_ARG).  Overwrites the stray-field work area (not the transformed
+ * tensor).  Synchronizes the stream.  For parity tests. */
+llg_status llg_get_demag_tensor(llg_ctx* ctx, double* h_out, int64_t cap);
+
 /* Assemble the operator for the frozen field d_m_tilde and build the AMG
  * hierarchy values (what llg_step does before the Krylov solve).  Used with
  * the inspection calls below. */

@@ -28,14 +28,25 @@ def normalize(m: np.ndarray) -> np.ndarray:
     return m / nrm
 
 
-def cell_centres(dim: int, n: int):
-    """Coordinates (x, y[, z]) of the cell centres, flattened in node order."""
-    c = (np.arange(n, dtype=np.float64) + 0.5) / n
-    if dim == 2:
-        y, x = np.meshgrid(c, c, indexing="ij")
-        return x.ravel(), y.ravel()
-    z, y, x = np.meshgrid(c, c, c, indexing="ij")
-    return x.ravel(), y.ravel(), z.ravel()
+def cell_centres(dim: int, n: int, xp=np, device=None):
+    """Coordinates (x, y[, z]) of the cell centres, flattened in node order.
+    xp is numpy (default) or torch (then on `device`)."""
+    if xp is np:
+        c = (np.arange(n, dtype=np.float64) + 0.5) / n
+        grids = np.meshgrid(*([c] * dim), indexing="ij")
+    else:
+        c = (xp.arange(n, dtype=xp.float64, device=device) + 0.5) / n
+        grids = xp.meshgrid(*([c] * dim), indexing="ij")
+    # the slowest index comes first: (y, x) in 2D, (z, y, x) in 3D
+    return tuple(g.reshape(-1) for g in reversed(grids))
+
+
+def _stack(xp, arrs):
+    return np.stack(arrs, axis=1) if xp is np else xp.stack(arrs, dim=1)
+
+
+def _cross(xp, a, b):
+    return np.cross(a, b) if xp is np else xp.linalg.cross(a, b, dim=1)
 
 
 def smooth_unit_field(dim: int, n: int, seed: int, sweeps: int = 20) -> np.ndarray:
@@ -77,12 +88,12 @@ def vortex_field(n: int, seed: int, sigma: float = 0.01) -> np.ndarray:
     return np.ascontiguousarray(normalize(m))
 
 
-def _xbar(dim: int, n: int):
+def _xbar(dim: int, n: int, xp=np, device=None):
     """xbar = sum_d x_d^2 (1 - x_d)^2 with its gradient norm^2 and Laplacian."""
-    cs = cell_centres(dim, n)
-    xb = np.zeros_like(cs[0])
-    grad2 = np.zeros_like(cs[0])
-    lap = np.zeros_like(cs[0])
+    cs = cell_centres(dim, n, xp, device)
+    xb = xp.zeros_like(cs[0])
+    grad2 = xp.zeros_like(cs[0])
+    lap = xp.zeros_like(cs[0])
     for c in cs:
         xb += c * c * (1 - c) * (1 - c)
         d1 = 2 * c * (1 - c) * (1 - 2 * c)
@@ -91,27 +102,33 @@ def _xbar(dim: int, n: int):
     return xb, grad2, lap
 
 
-def exact_solution(dim: int, n: int, t: float) -> np.ndarray:
-    """Manufactured m_e = (cos(xbar) sin t, sin(xbar) sin t, cos t), |m_e| = 1."""
-    xb, _, _ = _xbar(dim, n)
+def exact_solution(dim: int, n: int, t: float, xp=np, device=None):
+    """Manufactured m_e = (cos(xbar) sin t, sin(xbar) sin t, cos t), |m_e| = 1.
+    xp is numpy (default) or torch (then on `device`)."""
+    xb, _, _ = _xbar(dim, n, xp, device)
     s = math.sin(t)
-    return np.ascontiguousarray(np.stack([np.cos(xb) * s, np.sin(xb) * s, np.full_like(xb, math.cos(t))], axis=1))
+    m = _stack(xp, [xp.cos(xb) * s, xp.sin(xb) * s, xp.full_like(xb, math.cos(t))])
+    return np.ascontiguousarray(m) if xp is np else m.contiguous()
 
 
-def manufactured_forcing(dim: int, n: int, t: float, alpha: float) -> np.ndarray:
+def manufactured_forcing(dim: int, n: int, t: float, alpha: float, xp=np, device=None):
     """F = d/dt m_e + m_e x Lap m_e + alpha m_e x (m_e x Lap m_e), with the
     continuous Laplacian of m_e in closed form, so that m_e solves the damped
     equation of Sec. 2 with forcing F.  xbar has zero normal derivative on
-    the boundary, so m_e meets the Neumann condition."""
-    xb, g2, lap = _xbar(dim, n)
+    the boundary, so m_e meets the Neumann condition.  The discrete solution
+    therefore carries the O(h^2) error of the 5-/7-point Laplacian besides
+    the first-order error in time.  xp is numpy (default) or torch (then on
+    `device`)."""
+    xb, g2, lap = _xbar(dim, n, xp, device)
     s, c = math.sin(t), math.cos(t)
-    m = np.stack([np.cos(xb) * s, np.sin(xb) * s, np.full_like(xb, c)], axis=1)
-    dm = np.stack([np.cos(xb) * c, np.sin(xb) * c, np.full_like(xb, -s)], axis=1)
+    m = _stack(xp, [xp.cos(xb) * s, xp.sin(xb) * s, xp.full_like(xb, c)])
+    dm = _stack(xp, [xp.cos(xb) * c, xp.sin(xb) * c, xp.full_like(xb, -s)])
     # Lap cos(xbar) = -sin(xbar) Lap xbar - cos(xbar) |grad xbar|^2, same for sin
-    lm = np.stack([(-np.sin(xb) * lap - np.cos(xb) * g2) * s, (np.cos(xb) * lap - np.sin(xb) * g2) * s,
-                   np.zeros_like(xb)], axis=1)
-    mxl = np.cross(m, lm)
-    return np.ascontiguousarray(dm + mxl + alpha * np.cross(m, mxl))
+    lm = _stack(xp, [(-xp.sin(xb) * lap - xp.cos(xb) * g2) * s, (xp.cos(xb) * lap - xp.sin(xb) * g2) * s,
+                     xp.zeros_like(xb)])
+    mxl = _cross(xp, m, lm)
+    F = dm + mxl + alpha * _cross(xp, m, mxl)
+    return np.ascontiguousarray(F) if xp is np else F.contiguous()
 
 
 @dataclass
@@ -201,3 +218,25 @@ def serving_requests(count: int = 256, rate: float = 8.0, seed: int = 5, steps: 
         dt = float(rng.uniform(1e-4, 1e-3))
         out.append(Request(r, t, dim, n, alpha, dt, steps, 5000 + r))
     return out
+
+
+def _request_field(args):
+    dim, n, seed = args
+    return smooth_unit_field(dim, n, seed)
+
+
+def serving_inputs(requests, workers: int | None = None) -> dict:
+    """The initial field of every request (request r: seed 5000 + r), generated
+    on the host by a pool of `workers` processes (default: up to 16), as a
+    dict rid -> array."""
+    import multiprocessing as mp
+    import os
+    from concurrent.futures import ProcessPoolExecutor
+    workers = workers or max(1, min(16, os.cpu_count() or 1))
+    args = [(r.dim, r.n, r.seed) for r in requests]
+    if workers == 1 or len(args) <= 1:
+        fields = [_request_field(a) for a in args]
+    else:
+        with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+            fields = list(ex.map(_request_field, args))
+    return {r.rid: f for r, f in zip(requests, fields)}

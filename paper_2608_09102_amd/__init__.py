@@ -109,6 +109,7 @@ _lib.llg_get_colours.argtypes = [_P, _i32, _P, _i64, _P]
 _lib.llg_step_field.argtypes = [_P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.POINTER(Field), _P, _P,
                                 ctypes.POINTER(Stats)]
 _lib.llg_stray_field.argtypes = [_P, _P, _P]
+_lib.llg_get_demag_tensor.argtypes = [_P, _P, _i64]
 _lib.llg_apply_precond.argtypes = [_P, _P, _P]
 _lib.llg_apply_A.argtypes = [_P, _P, _P]
 _lib.llg_set_kernel_timing.argtypes = [_P, _i32]
@@ -120,6 +121,7 @@ _lib.llg_last_error.argtypes = []
 _lib.llg_last_error.restype = ctypes.c_char_p
 for _f in ("llg_workspace_bytes", "llg_create", "llg_step", "llg_setup", "llg_num_levels", "llg_level_info",
            "llg_get_level", "llg_get_aggregates", "llg_get_colours", "llg_step_field", "llg_stray_field",
+           "llg_get_demag_tensor",
            "llg_apply_precond", "llg_apply_A", "llg_set_kernel_timing",
            "llg_ctx_bytes", "llg_destroy"):
     getattr(_lib, _f).restype = _i32
@@ -291,6 +293,19 @@ class Solver:
         if s != OK:
             raise LLGError(s, "llg_stray_field")
         return h
+
+    def demag_tensor(self):
+        """The device's demagnetizing tensor for every cell offset, as a host
+        array [6][2nz-1][2ny-1][2nx-1] (xx, yy, zz, xy, xz, yz; offset k at
+        index k + n - 1 per axis)."""
+        import numpy as np
+        nx, ny, nz = (int(self.grid.n[0]), int(self.grid.n[1]), int(self.grid.n[2]))
+        out = np.zeros((6, 2 * nz - 1, 2 * ny - 1, 2 * nx - 1))
+        with torch.cuda.device(self.device):
+            s = _lib.llg_get_demag_tensor(self._ctx, out.ctypes.data, out.size)
+        if s != OK:
+            raise LLGError(s, "llg_get_demag_tensor")
+        return out
 
     def setup(self, m_tilde, alpha: float, dt: float) -> int:
         self._field(m_tilde, "m_tilde")

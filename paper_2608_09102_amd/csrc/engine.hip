@@ -987,7 +987,7 @@ void run_setup(llg_ctx& c, bool forcing, bool bdf2 = false, int field = 0) {
 // the transformed demagnetizing tensor, once per context (eager)
 void demag_prepare(llg_ctx& c) {
   if (c.demag_ready) return;
-  launch_demag_setup(c.st, c.fd, c.grid.h, c.fwork, c.nhat);
+  launch_demag_setup(c.st, c.fd, c.fwork, c.nhat);
   LCHK();
   c.demag_ready = true;
 }
@@ -1851,6 +1851,38 @@ llg_status llg_stray_field(llg_ctx* ctx, const double* d_m, double* d_h) {
     launch_stray_out(ctx->st, ctx->fd, ctx->fwork, d_h);
     LCHK();
     HIPX(hipStreamSynchronize(ctx->st));
+    return LLG_OK;
+  });
+}
+
+llg_status llg_get_demag_tensor(llg_ctx* ctx, double* h_out, int64_t cap) {
+  llg_status s = check_ctx(ctx);
+  if (s != LLG_OK) return s;
+  if (!ctx->opts.stray_field || !h_out) return LLG_ERR_INVALID_ARG;
+  const FieldDims& f = ctx->fd;
+  const int64_t ox = 2 * f.nx - 1, oy = 2 * f.ny - 1, oz = 2 * f.nz - 1, P = f.px * f.py * f.pz;
+  if (cap < 6 * ox * oy * oz) return LLG_ERR_INVALID_ARG;
+  return guard([&]() -> llg_status {
+    double* T = (double*)(ctx->fwork + P);
+    launch_demag_table(ctx->st, f, T);
+    std::vector<double2> host((size_t)P);
+    const int pairs[3][2] = {{0, 1}, {2, 3}, {4, 5}};
+    for (int r = 0; r < 3; ++r) {
+      launch_demag_pair(ctx->st, f, pairs[r][0], pairs[r][1], T, ctx->fwork);
+      LCHK();
+      HIPX(hipMemcpyAsync(host.data(), ctx->fwork, (size_t)P * sizeof(double2), hipMemcpyDeviceToHost, ctx->st));
+      HIPX(hipStreamSynchronize(ctx->st));
+      // offset (a, b, c) sits at padded index (a mod px, b mod py, c mod pz)
+      for (int64_t c = 0; c < oz; ++c)
+        for (int64_t b = 0; b < oy; ++b)
+          for (int64_t a = 0; a < ox; ++a) {
+            const int64_t X = a - (f.nx - 1), Y = b - (f.ny - 1), Z = c - (f.nz - 1);
+            const int64_t p = ((X + f.px) % f.px) + f.px * (((Y + f.py) % f.py) + f.py * ((Z + f.pz) % f.pz));
+            const int64_t o = a + ox * (b + oy * c);
+            h_out[pairs[r][0] * ox * oy * oz + o] = host[(size_t)p].x;
+            h_out[pairs[r][1] * ox * oy * oz + o] = host[(size_t)p].y;
+          }
+    }
     return LLG_OK;
   });
 }

@@ -28,78 +28,163 @@ constexpr int TPB = 256;
 inline unsigned nblk(int64_t n, int t = TPB) { return (unsigned)ceil_div(n > 0 ? n : 1, t); }
 
 // ------------------------------------------------------------ demag tensor
-__device__ double newell_f(double x, double y, double z) {
-  x = fabs(x);
-  y = fabs(y);
-  z = fabs(z);
-  const double x2 = x * x, y2 = y * y, z2 = z * z;
-  const double R = sqrt(x2 + y2 + z2);
-  if (R == 0.0) return 0.0;
-  double r = 0.0;
-  if (y > 0.0 && z2 != x2) r += 0.5 * y * (z2 - x2) * asinh(y / sqrt(x2 + z2));
-  if (z > 0.0 && y2 != x2) r += 0.5 * z * (y2 - x2) * asinh(z / sqrt(x2 + y2));
-  if (x > 0.0 && y > 0.0 && z > 0.0) r -= x * y * z * atan(y * z / (x * R));
-  r += (2.0 * x2 - y2 - z2) * R / 6.0;
-  return r;
-}
+// With m constant on the cubic cells of side h and the field averaged over
+// each cell, the stray field of eq. stray_field is h_i = -sum_j N(k_i - k_j) m_j,
+// where for the cell offset k (in cells, r = k h)
+//   N_ab(k) = -(1/4pi) int_{[-1,1]^3} prod_d (1 - |s_d|) K_ab(k + s) ds,
+//   K_ab(y) = d_a d_b (1/|y|) = (3 y_a y_b - delta_ab |y|^2) / |y|^5:
+// averaging the field of one uniformly magnetized cube over another is the
+// convolution of the point kernel with the autocorrelation of the cube, a tent
+// of half-width one cell along each axis.  N does not depend on h.  The offset
+// is handled by range (max norm of k):
+//  - |k| <= 1, cells that touch or coincide (the integrand is singular):
+//    closed form.  Along an axis where the kernel is differentiated twice the
+//    tent average is the second difference of the kernel; along an axis where
+//    it is not, the second difference of a second antiderivative.  So N is the
+//    27-point second difference (weights 2 at 0, -1 at +-1 per axis), over
+//    4 pi, of a generating function whose mixed derivatives give 1/|y| (Newell,
+//    Williams and Dunlop 1993); the six generating functions are evaluated
+//    together at each lattice point from the three logarithms and three
+//    arctangents they share (gen6).
+//  - 2 <= |k| <= 16: the integral above by Gauss-Legendre quadrature.  The
+//    nearest point of the other cell is a cell away, so the integrand is
+//    analytic on the domain; each axis is folded onto [0, 1], which leaves
+//    the tent as the weight (1 - s).  Twelve nodes per folded axis reproduce
+//    the closed form evaluated at 40 digits to about 1e-18 at |k| = 2, and
+//    better beyond.
+//  - |k| > 16: the point dipole -(1/4pi) K(k).
+// Entries: 0 xx, 1 yy, 2 zz, 3 xy, 4 xz, 5 yz.  The diagonal entries are even
+// in every coordinate of k; the xy entry is odd in k_x and k_y and even in
+// k_z, and so on, so the positive octant determines the tensor.
 
-__device__ double newell_g(double x, double y, double z) {
-  const double sgn = (x > 0 ? 1.0 : (x < 0 ? -1.0 : 0.0)) * (y > 0 ? 1.0 : (y < 0 ? -1.0 : 0.0));
-  if (sgn == 0.0) return 0.0;
+constexpr int DEMAG_NEAR = 1, DEMAG_FAR = 16, GL_NODES = 12, GL_AXIS = 2 * GL_NODES;
+
+// Nodes and weights of the folded rule on [0, 1] for the weight (1 - s).
+struct GlRule {
+  double t[GL_NODES], w[GL_NODES];
+};
+
+// The six generating values at a lattice point (coordinates taken by
+// absolute value; the off-diagonal ones are odd in their first two
+// arguments, applied by the caller).  With R = |y|, l_a = log((y_a + R) / rho_a)
+// (rho_a the distance to the a axis; set to 0 where rho_a = 0, where each of
+// its coefficients vanishes) and t_a = atan2(y_b y_c, y_a R):
+//   F_aa = y_b (y_c^2 - y_a^2) l_b / 2 + y_c (y_b^2 - y_a^2) l_c / 2
+//          - y_a y_b y_c t_a + (2 y_a^2 - y_b^2 - y_c^2) R / 6,
+//   F_ab = y_a y_b y_c l_c + y_b (3 y_c^2 - y_b^2) l_a / 6 + y_a (3 y_c^2 - y_a^2) l_b / 6
+//          - y_c^3 t_c / 6 - y_c y_b^2 t_b / 2 - y_c y_a^2 t_a / 2 - y_a y_b R / 3
+// for (a, b, c) a cyclic or the matching order of (x, y, z).
+__device__ void gen6(double x, double y, double z, double F[6]) {
   x = fabs(x);
   y = fabs(y);
   z = fabs(z);
-  const double x2 = x * x, y2 = y * y, z2 = z * z;
-  const double R = sqrt(x2 + y2 + z2);
-  double r = 0.0;
-  if (z > 0.0) r += x * y * z * asinh(z / sqrt(x2 + y2));
-  r += (y / 6.0) * (3.0 * z2 - y2) * asinh(x / sqrt(y2 + z2));
-  r += (x / 6.0) * (3.0 * z2 - x2) * asinh(y / sqrt(x2 + z2));
-  if (z > 0.0) {
-    r -= (z2 * z / 6.0) * atan(x * y / (z * R));
-    r -= (z * y2 / 2.0) * atan(x * z / (y * R));
-    r -= (z * x2 / 2.0) * atan(y * z / (x * R));
+  const double xx = x * x, yy = y * y, zz = z * z;
+  const double R = sqrt(xx + yy + zz);
+  if (R == 0.0) {
+    for (int c = 0; c < 6; ++c) F[c] = 0.0;
+    return;
   }
-  r -= x * y * R / 3.0;
-  return sgn * r;
+  const double ryz = sqrt(yy + zz), rxz = sqrt(xx + zz), rxy = sqrt(xx + yy);
+  const double lx = ryz > 0.0 ? log((x + R) / ryz) : 0.0;
+  const double ly = rxz > 0.0 ? log((y + R) / rxz) : 0.0;
+  const double lz = rxy > 0.0 ? log((z + R) / rxy) : 0.0;
+  const double tx = atan2(y * z, x * R), ty = atan2(x * z, y * R), tz = atan2(x * y, z * R);
+  const double xyz = x * y * z, R6 = R / 6.0;
+  F[0] = 0.5 * y * (zz - xx) * ly + 0.5 * z * (yy - xx) * lz - xyz * tx + (2.0 * xx - yy - zz) * R6;
+  F[1] = 0.5 * x * (zz - yy) * lx + 0.5 * z * (xx - yy) * lz - xyz * ty + (2.0 * yy - xx - zz) * R6;
+  F[2] = 0.5 * y * (xx - zz) * ly + 0.5 * x * (yy - zz) * lx - xyz * tz + (2.0 * zz - xx - yy) * R6;
+  F[3] = xyz * lz + y * (3.0 * zz - yy) * lx / 6.0 + x * (3.0 * zz - xx) * ly / 6.0 - z * zz * tz / 6.0 -
+         0.5 * z * yy * ty - 0.5 * z * xx * tx - x * y * R / 3.0;
+  F[4] = xyz * ly + z * (3.0 * yy - zz) * lx / 6.0 + x * (3.0 * yy - xx) * lz / 6.0 - y * yy * ty / 6.0 -
+         0.5 * y * zz * tz - 0.5 * y * xx * tx - x * z * R / 3.0;
+  F[5] = xyz * lx + z * (3.0 * xx - zz) * ly / 6.0 + y * (3.0 * xx - yy) * lz / 6.0 - x * xx * tx / 6.0 -
+         0.5 * x * zz * tz - 0.5 * x * yy * ty - y * z * R / 3.0;
 }
 
-// second difference over the 27 neighbouring corners, over 4 pi a b c
-template <bool OFF>
-__device__ double newell_sum(double X, double Y, double Z, double a, double b, double c) {
-  const double w[3] = {-1.0, 2.0, -1.0};
-  double acc = 0.0;
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j)
-      for (int k = 0; k < 3; ++k) {
-        const double x = X + (i - 1) * a, y = Y + (j - 1) * b, z = Z + (k - 1) * c;
-        acc += w[i] * w[j] * w[k] * (OFF ? newell_g(x, y, z) : newell_f(x, y, z));
+__device__ inline double sgn(int64_t v) { return v > 0 ? 1.0 : (v < 0 ? -1.0 : 0.0); }
+
+// closed form for |k| <= 1
+__device__ void demag_near(int64_t X, int64_t Y, int64_t Z, double t[6]) {
+  for (int c = 0; c < 6; ++c) t[c] = 0.0;
+  for (int k = -1; k <= 1; ++k)
+    for (int j = -1; j <= 1; ++j)
+      for (int i = -1; i <= 1; ++i) {
+        const double W = (i ? -1.0 : 2.0) * (j ? -1.0 : 2.0) * (k ? -1.0 : 2.0);
+        const int64_t a = X + i, b = Y + j, c = Z + k;
+        double F[6];
+        gen6((double)a, (double)b, (double)c, F);
+        const double sab = sgn(a) * sgn(b), sac = sgn(a) * sgn(c), sbc = sgn(b) * sgn(c);
+        t[0] += W * F[0];
+        t[1] += W * F[1];
+        t[2] += W * F[2];
+        t[3] += W * sab * F[3];
+        t[4] += W * sac * F[4];
+        t[5] += W * sbc * F[5];
       }
-  return acc / (4.0 * M_PI * a * b * c);
+  for (int c = 0; c < 6; ++c) t[c] = t[c] / (4.0 * M_PI);
 }
 
-// component comp (0..5: xx yy zz xy xz yz) between cells (X, Y, Z) apart
-__device__ double demag(int comp, double X, double Y, double Z, double d) {
-  const double far = fmax(fabs(X), fmax(fabs(Y), fabs(Z))) / d;
-  if (far > 16.0) {
-    const double r2 = X * X + Y * Y + Z * Z, r = sqrt(r2);
-    const double k = -(d * d * d) / (4.0 * M_PI * r2 * r);
-    switch (comp) {
-      case 0: return k * (3.0 * X * X / r2 - 1.0);
-      case 1: return k * (3.0 * Y * Y / r2 - 1.0);
-      case 2: return k * (3.0 * Z * Z / r2 - 1.0);
-      case 3: return k * 3.0 * X * Y / r2;
-      case 4: return k * 3.0 * X * Z / r2;
-      default: return k * 3.0 * Y * Z / r2;
-    }
+// -(1/4pi) K(y) (the point dipole; also the quadrature's integrand)
+__device__ inline void dipole(double x, double y, double z, double t[6]) {
+  const double r2 = x * x + y * y + z * z;
+  const double s = -1.0 / (4.0 * M_PI * r2 * r2 * sqrt(r2));
+  t[0] = s * (3.0 * x * x - r2);
+  t[1] = s * (3.0 * y * y - r2);
+  t[2] = s * (3.0 * z * z - r2);
+  t[3] = s * 3.0 * x * y;
+  t[4] = s * 3.0 * x * z;
+  t[5] = s * 3.0 * y * z;
+}
+
+// The positive octant of offsets, T[c][node] on the n-box: the near and far
+// ranges, one thread per offset (the quadrature range is k_demag_mid's).
+__global__ void k_demag_octant(FieldDims f, double* __restrict__ T) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = f.nx * f.ny * f.nz;
+  if (node >= N) return;
+  const int64_t X = node % f.nx, Y = (node / f.nx) % f.ny, Z = node / (f.nx * f.ny);
+  const int64_t far = X > Y ? (X > Z ? X : Z) : (Y > Z ? Y : Z);
+  double t[6];
+  if (far <= DEMAG_NEAR)
+    demag_near(X, Y, Z, t);
+  else if (far > DEMAG_FAR)
+    dipole((double)X, (double)Y, (double)Z, t);
+  else
+    return;
+  for (int c = 0; c < 6; ++c) T[c * N + node] = t[c];
+}
+
+// The quadrature range, one workgroup per offset of the box
+// [0, min(n, 17))^3; GL_AXIS^3 points (both halves of every folded axis).
+constexpr int MID_TPB = 256;
+__global__ __launch_bounds__(MID_TPB) void k_demag_mid(FieldDims f, GlRule q, double* __restrict__ T) {
+  const int64_t mx = f.nx < DEMAG_FAR + 1 ? f.nx : DEMAG_FAR + 1;
+  const int64_t my = f.ny < DEMAG_FAR + 1 ? f.ny : DEMAG_FAR + 1;
+  const int64_t X = blockIdx.x % mx, Y = (blockIdx.x / mx) % my, Z = blockIdx.x / (mx * my);
+  const int64_t far = X > Y ? (X > Z ? X : Z) : (Y > Z ? Y : Z);
+  if (far <= DEMAG_NEAR) return;
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int p = threadIdx.x; p < GL_AXIS * GL_AXIS * GL_AXIS; p += MID_TPB) {
+    const int a = p % GL_AXIS, b = (p / GL_AXIS) % GL_AXIS, c = p / (GL_AXIS * GL_AXIS);
+    const double sa = a < GL_NODES ? q.t[a] : -q.t[a - GL_NODES];
+    const double sb = b < GL_NODES ? q.t[b] : -q.t[b - GL_NODES];
+    const double sc = c < GL_NODES ? q.t[c] : -q.t[c - GL_NODES];
+    const double W = q.w[a % GL_NODES] * q.w[b % GL_NODES] * q.w[c % GL_NODES];
+    double t[6];
+    dipole((double)X + sa, (double)Y + sb, (double)Z + sc, t);
+    for (int k = 0; k < 6; ++k) acc[k] += W * t[k];
   }
-  switch (comp) {
-    case 0: return newell_sum<false>(X, Y, Z, d, d, d);
-    case 1: return newell_sum<false>(Y, X, Z, d, d, d);
-    case 2: return newell_sum<false>(Z, Y, X, d, d, d);
-    case 3: return newell_sum<true>(X, Y, Z, d, d, d);
-    case 4: return newell_sum<true>(X, Z, Y, d, d, d);
-    default: return newell_sum<true>(Y, Z, X, d, d, d);
+  __shared__ double red[6][MID_TPB];
+  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = MID_TPB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int64_t N = f.nx * f.ny * f.nz, node = X + f.nx * (Y + f.ny * Z);
+    for (int k = 0; k < 6; ++k) T[k * N + node] = red[k][0];
   }
 }
 
@@ -354,22 +439,32 @@ void fft_forward_full(hipStream_t st, FieldDims f, double2* w, int planes) {
   fft_axis(st, w, P, planes, f.pz, pxy, pxy, 1, 1, 0, f.pz, f.pz, -1, 1.0);
 }
 
-// Two tensor components packed as one complex plane, a + i b: both are real
-// and even up to rounding, so their transforms are real and the packed
-// transform's real and imaginary parts are the two transforms.
-__global__ void k_demag_grid2(FieldDims f, int c0, int c1, double h, double2* out) {
+// Two tensor components packed as one complex plane, a + i b, on the padded
+// grid (cyclic offsets), from the octant table by the parities of the
+// entries: both are real and even up to sign flips that the transform sees
+// as real, so the packed transform's real and imaginary parts are the two
+// transforms.
+__global__ void k_demag_pair(FieldDims f, int c0, int c1, const double* __restrict__ T, double2* out) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t P = f.px * f.py * f.pz;
   if (p >= P) return;
   const int64_t a = p % f.px, b = (p / f.px) % f.py, c = p / (f.px * f.py);
   int64_t X, Y, Z;
-  const bool in = wrap(a, f.nx, f.px, X) && wrap(b, f.ny, f.py, Y) && wrap(c, f.nz, f.pz, Z);
-  double v0 = 0.0, v1 = 0.0;
-  if (in) {
-    v0 = demag(c0, X * h, Y * h, Z * h, h);
-    v1 = demag(c1, X * h, Y * h, Z * h, h);
+  double v[2] = {0.0, 0.0};
+  if (wrap(a, f.nx, f.px, X) && wrap(b, f.ny, f.py, Y) && wrap(c, f.nz, f.pz, Z)) {
+    const int64_t N = f.nx * f.ny * f.nz;
+    const int64_t node = (X < 0 ? -X : X) + f.nx * ((Y < 0 ? -Y : Y) + f.ny * (Z < 0 ? -Z : Z));
+    const int cc[2] = {c0, c1};
+    for (int r = 0; r < 2; ++r) {
+      const int comp = cc[r];
+      double s = 1.0;
+      if (comp == 3) s = (X < 0 ? -1.0 : 1.0) * (Y < 0 ? -1.0 : 1.0);
+      if (comp == 4) s = (X < 0 ? -1.0 : 1.0) * (Z < 0 ? -1.0 : 1.0);
+      if (comp == 5) s = (Y < 0 ? -1.0 : 1.0) * (Z < 0 ? -1.0 : 1.0);
+      v[r] = s * T[comp * N + node];
+    }
   }
-  out[p] = make_double2(v0, v1);
+  out[p] = make_double2(v[0], v[1]);
 }
 
 __global__ void k_take_pair(int64_t P, int c0, int c1, const double2* in, double* nhat) {
@@ -491,11 +586,65 @@ FieldDims field_dims(int nx, int ny, int nz) {
 
 void init_field_attributes() {}
 
-void launch_demag_setup(hipStream_t st, FieldDims f, double h, double2* work, double* nhat) {
+// Gauss-Legendre nodes x_i and weights on [-1, 1] by Newton's method on the
+// Legendre polynomial (three-term recurrence), mapped to [0, 1] with the
+// weight (1 - s) folded into the weights.
+GlRule folded_rule() {
+  GlRule q;
+  const int n = GL_NODES;
+  for (int i = 0; i < n; ++i) {
+    double x = cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (fabs(dx) < 1e-17) break;
+    }
+    double p0 = 1.0, p1 = x;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (x * p1 - p0) / (x * x - 1.0);
+    const double w = 2.0 / ((1.0 - x * x) * dp * dp);
+    const double t = 0.5 * (x + 1.0);
+    q.t[i] = t;
+    q.w[i] = 0.5 * w * (1.0 - t);
+  }
+  return q;
+}
+
+// The octant table T[6][N] (N = nx ny nz doubles each) of the tensor.
+void launch_demag_table(hipStream_t st, FieldDims f, double* T) {
+  const int64_t N = f.nx * f.ny * f.nz;
+  hipLaunchKernelGGL(k_demag_octant, dim3(nblk(N)), dim3(TPB), 0, st, f, T);
+  const int64_t mx = std::min<int64_t>(f.nx, DEMAG_FAR + 1), my = std::min<int64_t>(f.ny, DEMAG_FAR + 1),
+                mz = std::min<int64_t>(f.nz, DEMAG_FAR + 1);
+  hipLaunchKernelGGL(k_demag_mid, dim3((unsigned)(mx * my * mz)), dim3(MID_TPB), 0, st, f, folded_rule(), T);
+}
+
+// Components c0 (real part) and c1 (imaginary part) on the padded grid.
+void launch_demag_pair(hipStream_t st, FieldDims f, int c0, int c1, const double* T, double2* out) {
   const int64_t P = f.px * f.py * f.pz;
+  hipLaunchKernelGGL(k_demag_pair, dim3(nblk(P)), dim3(TPB), 0, st, f, c0, c1, T, out);
+}
+
+// The octant table goes to the second work plane (16 P bytes >= 48 N: every
+// padded length is at least twice the grid's), the packed pairs to the first.
+void launch_demag_setup(hipStream_t st, FieldDims f, double2* work, double* nhat) {
+  const int64_t P = f.px * f.py * f.pz;
+  double* T = (double*)(work + P);
+  launch_demag_table(st, f, T);
   const int pairs[3][2] = {{0, 1}, {2, 3}, {4, 5}};
   for (int r = 0; r < 3; ++r) {
-    hipLaunchKernelGGL(k_demag_grid2, dim3(nblk(P)), dim3(TPB), 0, st, f, pairs[r][0], pairs[r][1], h, work);
+    launch_demag_pair(st, f, pairs[r][0], pairs[r][1], T, work);
     fft_forward_full(st, f, work, 1);
     hipLaunchKernelGGL(k_take_pair, dim3(nblk(P)), dim3(TPB), 0, st, P, pairs[r][0], pairs[r][1], work, nhat);
   }

@@ -424,7 +424,13 @@ struct FieldDims {
 int64_t next_pow2(int64_t v);
 FieldDims field_dims(int nx, int ny, int nz);
 void init_field_attributes();
-void launch_demag_setup(hipStream_t st, FieldDims f, double h, double2* work, double* nhat);
+// the transformed demagnetizing tensor (six real planes of P values) into
+// nhat, using both work planes
+void launch_demag_setup(hipStream_t st, FieldDims f, double2* work, double* nhat);
+// the tensor on the positive octant of offsets, T[6][nx ny nz]; components
+// c0 + i c1 on the padded grid (cyclic offsets) from it
+void launch_demag_table(hipStream_t st, FieldDims f, double* T);
+void launch_demag_pair(hipStream_t st, FieldDims f, int c0, int c1, const double* T, double2* out);
 // work = the transformed-back product N^ M^ of m~ (m, or 2 m - mprev)
 void launch_stray(hipStream_t st, FieldDims f, const double* m, const double* mprev, const double* nhat,
                   double2* work);

@@ -1,9 +1,13 @@
 """Serving loop: continuous batching of independent Landau-Lifshitz simulations.
 
-Requests (grid, alpha, dt, number of steps, seed) arrive over time.  A request
-is admitted when a worker slot is free and its exact device footprint
-(llg_workspace_bytes plus its two field buffers) fits in the HBM budget next to
-the simulations already running; admission is first-come first-served.  Each
+Requests (grid, alpha, dt, number of steps, initial field) arrive over time.
+When a request arrives its exact device footprint is planned
+(llg_workspace_bytes plus its two field buffers); it is admitted when a worker
+slot is free and the footprint fits in the HBM budget next to the simulations
+already running; admission is first-come first-served.  Planning runs the
+field-independent aggregation once per grid shape on the device, in temporary
+memory outside the budget (the budget is a fraction of the free memory that
+leaves room for it).  Each
 admitted simulation owns a context on the worker's own HIP stream, so its
 field, its AMG hierarchy and its Krylov state stay resident on the device
 between steps, and the steps of different simulations overlap on the GPU.  A
@@ -62,7 +66,7 @@ class Server:
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
         out = {r.rid: Outcome(r.rid, arrival=r.arrival * time_scale, unknowns=3 * r.nodes, steps=r.steps)
                for r in reqs}
-        foot = {r.rid: int(self.runner.footprint(r)) for r in reqs}
+        foot = {}  # each request's footprint, planned when it arrives
         cv = threading.Condition()
         state = {"used": 0, "free": list(range(self.workers)), "active": 0, "next": 0}
         pending = []
@@ -98,6 +102,7 @@ class Server:
                 while state["next"] < len(reqs) and reqs[state["next"]].arrival * time_scale <= t:
                     r = reqs[state["next"]]
                     state["next"] += 1
+                    foot[r.rid] = int(self.runner.footprint(r))
                     if foot[r.rid] > self.budget:
                         out[r.rid].status = "rejected"
                         out[r.rid].error = "footprint %d exceeds the budget %d" % (foot[r.rid], self.budget)
@@ -149,35 +154,6 @@ def report(outcomes, makespan: float) -> dict:
     }
 
 
-def device_field(dim: int, n: int, seed: int, device, sweeps: int = 20):
-    """Smoothed random unit field generated on the device (seeded torch
-    generator; deterministic for a given seed): random normal vectors,
-    normalized, `sweeps` rounds of 1/2 self + 1/2 mean of in-grid neighbours,
-    normalized.  Same recipe as llg_inputs.smooth_unit_field, device RNG."""
-    import torch
-    g = torch.Generator(device=device)
-    g.manual_seed(int(seed))
-    shape = (n, n, 3) if dim == 2 else (n, n, n, 3)
-    m = torch.randn(shape, generator=g, device=device, dtype=torch.float64)
-    m = m / m.norm(dim=-1, keepdim=True)
-    for _ in range(sweeps):
-        acc = torch.zeros_like(m)
-        cnt = torch.zeros(shape[:-1] + (1,), device=device, dtype=torch.float64)
-        for ax in range(dim):
-            lo = [slice(None)] * (dim + 1)
-            hi = [slice(None)] * (dim + 1)
-            lo[ax] = slice(0, n - 1)
-            hi[ax] = slice(1, n)
-            lo, hi = tuple(lo), tuple(hi)
-            acc[lo] += m[hi]
-            acc[hi] += m[lo]
-            cnt[lo] += 1.0
-            cnt[hi] += 1.0
-        m = 0.5 * m + 0.5 * (acc / cnt)
-    m = m / m.norm(dim=-1, keepdim=True)
-    return m.reshape(-1, 3).contiguous()
-
-
 class HipRunner:
     """Runs a request through libllg.so: one context per simulation on the
     worker's stream, `steps` calls of llg_step, fields resident on the device.
@@ -185,7 +161,7 @@ class HipRunner:
     dimension d (e.g. the cycle that is fastest there)."""
 
     def __init__(self, opts_kw=None, device: int = 0, workers: int = 4, keep_device: bool = False,
-                 opts_by_dim=None):
+                 opts_by_dim=None, inputs=None):
         import torch
         import paper_2608_09102_amd as llg
         self.llg = llg
@@ -195,6 +171,7 @@ class HipRunner:
         self.device = torch.device("cuda", device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(workers)]
         self._plan_lock = threading.Lock()
+        self.inputs = inputs  # rid -> initial field on the host (else generated from the request's recipe)
 
     def _grid_opts(self, r):
         llg = self.llg
@@ -208,7 +185,7 @@ class HipRunner:
             s, b = self.llg.workspace_bytes(g, o)
         if s != self.llg.OK:
             raise self.llg.LLGError(s, "llg_workspace_bytes")
-        return b + 2 * 24 * r.nodes  # workspace + m^n and m^{n+1}
+        return b + 2 * 24 * r.nodes  # workspace + m^n and m^{n+1} (the initial field is copied into m^n)
 
     def run(self, r, wid: int, on_step):
         torch, llg = self.torch, self.llg
@@ -216,7 +193,8 @@ class HipRunner:
         g, o = self._grid_opts(r)
         with torch.cuda.device(self.device), torch.cuda.stream(st):
             S = llg.Solver(g, o, stream=st)
-            m = device_field(r.dim, r.n, r.seed, self.device)
+            h = self.inputs[r.rid] if self.inputs is not None else r.m0()
+            m = torch.from_numpy(h).to(self.device)
             nxt = torch.empty_like(m)
             st.synchronize()
             for _ in range(r.steps):

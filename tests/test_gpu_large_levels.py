@@ -1,0 +1,85 @@
+"""Hierarchy values bit for bit on grids large enough for the setup kernels
+that only run on large levels (eq. galerkin, eq. Ac_direct, Sec. 3.1.1): the
+Galerkin product with one workgroup per coarse slice (levels of 65,536 nodes
+or more), the four-block walk of its threads, the coarse-graph rows of more
+than 32 candidates (3D coarse levels), the matching rounds over many
+workgroups, and, in the per-node grid form, the level-1 product that reads the
+grid blocks node-major.
+
+Bars: every level's pattern and FP64 values equal the oracle's (both sides add
+the same blocks in the same order without contraction); the aggregates equal
+the oracle's; FP32-AMG levels equal between the sliced-ELL and the per-node
+grid form.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    import paper_2608_09102_amd as llg
+    assert torch.cuda.is_available()
+    return llg
+
+
+def _cuda(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def _rough(N, seed=7):
+    rng = np.random.default_rng(seed)
+    m = rng.standard_normal((N, 3))
+    return m / np.linalg.norm(m, axis=1, keepdims=True)
+
+
+CASES = [("2d_512", 2, 512, 0.05, 2e-5), ("3d_64", 3, 64, 0.3, 1e-3)]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_large_levels_bitwise(gpu, orc, case):
+    name, dim, n, alpha, dt = case
+    say("[large_levels_bitwise]", name)
+    N = n ** dim
+    m = _rough(N)
+    H = orc.Hierarchy(orc.make_grid(dim, n), orc.default_opts(kcycle_depth=1), m, alpha, dt)
+    nl = H.num_levels
+    sizes = [len(H.level(l).rp) - 1 for l in range(nl)]
+    say("  oracle levels", sizes)
+    assert sizes[1] >= 65536  # level 1 is formed by the slice-parallel product
+    forms = {}
+    for op in ("bsr", "factored"):
+        for prec in ("fp64", "fp32_amg"):
+            S = gpu.Solver(gpu.make_grid(dim, n), gpu.default_opts(kcycle_depth=1, fine_operator=op, precision=prec))
+            assert S.setup(_cuda(m), alpha, dt) == gpu.OK
+            assert S.num_levels == nl
+            forms[(op, prec)] = [S.level(l) for l in range(nl)]
+            if prec == "fp64":
+                for l in range(nl - 1):
+                    assert np.array_equal(S.aggregates(l), H.level(l).agg), (op, l)
+            S.close()
+    for op in ("bsr", "factored"):
+        for l in range(nl):
+            rp, ci, val = forms[(op, "fp64")][l]
+            R = H.level(l)
+            assert np.array_equal(rp, R.rp) and np.array_equal(ci, R.ci), (op, l)
+            assert np.array_equal(val, R.val), (op, l, np.abs(val - R.val).max())
+    for l in range(nl):
+        a, b = forms[("bsr", "fp32_amg")][l], forms[("factored", "fp32_amg")][l]
+        assert all(np.array_equal(x, y) for x, y in zip(a, b)), l
+        # FP32-AMG levels are the FP64 ones rounded, up to the rounding of the
+        # coarse sums formed in FP32
+        rel = np.abs(a[2] - forms[("bsr", "fp64")][l][2]).max() / np.abs(forms[("bsr", "fp64")][l][2]).max()
+        assert rel <= 1e-5, (l, rel)
+    say("  %d levels equal" % nl)

@@ -367,3 +367,35 @@ def test_arnoldi_forms_agree(gpu, orc, precision, kdepth):
     assert outs["dcgs2"][2] >= 1
     for f in outs:
         assert np.abs(outs[f][0] - ref).max() <= 1e-8
+
+
+FORCED_FORMS = [dict(), dict(kcycle_depth=1, fine_operator="factored"),
+                dict(kcycle_depth=1, fine_operator="factored", precision="fp32_amg")]
+
+
+@pytest.mark.parametrize("form", FORCED_FORMS, ids=["bsr_v", "factored_k1", "factored_k1_fp32amg"])
+def test_forced_steps_vortex64(gpu, orc, form):
+    """BDF1 with a forcing term, b = m^n + dt F (the damped scheme of Sec. 2.1
+    with the forcing of Sec. 4.4): the 64^2 vortex field stepped twice with
+    the 2D manufactured forcing F(t_{k+1}); both sides at rtol 1e-11, every
+    step within 1e-8 of the oracle's from the same m^n, and the forcing
+    visibly changes the step."""
+    w = I.WORKLOADS["vortex64"]
+    say("[forced_steps_vortex64]", form)
+    S = gpu.Solver(gpu.make_grid(2, w.n), gpu.default_opts(rtol=1e-11, **form))
+    og = orc.make_grid(2, w.n)
+    oo = orc.default_opts(rtol=1e-11, kcycle_depth=form.get("kcycle_depth", 0))
+    m = w.m0()
+    for k in range(2):
+        F = I.manufactured_forcing(2, w.n, (k + 1) * w.dt, w.alpha)
+        out, s, st = S.step(_cuda(m), w.alpha, w.dt, forcing=_cuda(F))
+        assert s == gpu.OK
+        rc, ref, ost = orc.step(og, oo, m, w.alpha, w.dt, F)
+        assert rc == 0
+        rc, unforced, _ = orc.step(og, oo, m, w.alpha, w.dt)
+        d = np.abs(out.cpu().numpy() - ref).max()
+        say("  step %d iters gpu %d oracle %d diff %.2e (forcing moves the step by %.2e)"
+            % (k, st.iters, ost.iters, d, np.abs(ref - unforced).max()))
+        assert d <= 1e-8
+        assert np.abs(ref - unforced).max() >= 1e-4
+        m = ref

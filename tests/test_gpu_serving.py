@@ -31,11 +31,19 @@ def _requests():
     return out
 
 
+# the forms the serving run uses: FP32-AMG with the grid level stored per
+# node; the K-cycle on level 1 in 2D, the V-cycle in 3D
+SERVED = dict(precision="fp32_amg", fine_operator="factored")
+SERVED_BY_DIM = {2: dict(kcycle_depth=1), 3: dict(kcycle_depth=0)}
+
+
 def test_alone_equals_mix():
+    """The served forms at the serving tolerance: each request's final field
+    is bitwise the same alone and in the mix."""
     from paper_2608_09102_amd.serve import HipRunner, Server
     say("[serving alone vs mix]")
     reqs = _requests()
-    runner = HipRunner(opts_kw=dict(rtol=1e-8, precision="fp32_amg"), workers=4)
+    runner = HipRunner(opts_kw=dict(rtol=1e-8, **SERVED), workers=4, opts_by_dim=SERVED_BY_DIM)
     alone = {}
     for r in reqs:
         alone[r.rid] = runner.run(r, 0, lambda ms, it: None)
@@ -47,6 +55,30 @@ def test_alone_equals_mix():
         assert len(o.step_ms) == 5
         nrm = np.linalg.norm(o.result, axis=1)
         assert np.abs(nrm - 1).max() < 1e-12
+
+
+def test_served_requests_match_oracle(orc):
+    """The served forms through the serving loop, solved to rtol 1e-11: every
+    request's field after its 5 steps (from its recipe's initial field,
+    seed 5000 + r) within 1e-8 of the oracle's 5-step trajectory."""
+    from paper_2608_09102_amd.serve import HipRunner, Server
+    say("[served requests vs oracle]")
+    reqs = _requests()
+    runner = HipRunner(opts_kw=dict(rtol=1e-11, **SERVED), workers=4, opts_by_dim=SERVED_BY_DIM)
+    rep = Server(runner, budget_bytes=40 * 2 ** 30, workers=4).run(reqs, keep_results=True)
+    assert rep["done"] == len(reqs)
+    by = {r.rid: r for r in reqs}
+    for o in rep["outcomes"]:
+        r = by[o.rid]
+        g = orc.make_grid(r.dim, r.n)
+        oo = orc.default_opts(rtol=1e-11, kcycle_depth=SERVED_BY_DIM[r.dim]["kcycle_depth"])
+        m = r.m0()
+        for _ in range(r.steps):
+            rc, m, _ = orc.step(g, oo, m, r.alpha, r.dt)
+            assert rc == 0
+        d = np.abs(o.result - m).max()
+        say("  request %d (%dD n=%d): |gpu - oracle| = %.2e" % (o.rid, r.dim, r.n, d))
+        assert d <= 1e-8, (o.rid, d)
 
 
 def test_tight_budget_queues():
