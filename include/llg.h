@@ -258,6 +258,22 @@ llg_status llg_step_field(llg_ctx* ctx, const double* d_m_n, const double* d_m_n
  * stream. */
 llg_status llg_stray_field(llg_ctx* ctx, const double* d_m, double* d_h);
 
+/* The stray field without a context, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops that forbid allocation):
+ * d_h = h_s(d_m) on `grid` as llg_stray_field computes it, with the transformed
+ * tensor and the FFT work planes in a static device array of
+ * LLG_STRAY_NOALLOC_MAX_BYTES bytes that every device the library runs on
+ * holds until the process ends.  The call allocates nothing.  It needs
+ * 80 P bytes, P = the padded cell count (each axis of n > 1 cells padded to
+ * the power of two >= 2 n - 1): 2D grids up to 512 x 512 and 3D grids up to
+ * 64^3 fit; larger grids return UNSUPPORTED.  The array keeps the last call's
+ * contents (the tensor is recomputed only when the grid's dimensions change);
+ * calls that overlap on one device race.  All work runs on hip_stream (NULL =
+ * the default stream), which is synchronized before returning.  d_m and d_h:
+ * N x 3 doubles each.  Errors: INVALID_ARG, UNSUPPORTED, DEVICE. */
+#define LLG_STRAY_NOALLOC_MAX_BYTES ((size_t)176160768) /* 168 MiB */
+llg_status llg_stray_field_noalloc(const llg_grid* grid, const double* d_m, double* d_h, void* hip_stream);
+
 /* Host copy of the cell-averaged demagnetizing tensor the stray field uses
  * (eq. stray_field with m constant on the cubic cells of side h; Newell,
  * Williams and Dunlop 1993 for cells within one cell of each other, the

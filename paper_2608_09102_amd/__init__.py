@@ -110,6 +110,7 @@ _lib.llg_step_field.argtypes = [_P, _P, _P, ctypes.c_double, ctypes.c_double, ct
                                 ctypes.POINTER(Stats)]
 _lib.llg_stray_field.argtypes = [_P, _P, _P]
 _lib.llg_get_demag_tensor.argtypes = [_P, _P, _i64]
+_lib.llg_stray_field_noalloc.argtypes = [ctypes.POINTER(Grid), _P, _P, _P]
 _lib.llg_apply_precond.argtypes = [_P, _P, _P]
 _lib.llg_apply_A.argtypes = [_P, _P, _P]
 _lib.llg_set_kernel_timing.argtypes = [_P, _i32]
@@ -121,7 +122,7 @@ _lib.llg_last_error.argtypes = []
 _lib.llg_last_error.restype = ctypes.c_char_p
 for _f in ("llg_workspace_bytes", "llg_create", "llg_step", "llg_setup", "llg_num_levels", "llg_level_info",
            "llg_get_level", "llg_get_aggregates", "llg_get_colours", "llg_step_field", "llg_stray_field",
-           "llg_get_demag_tensor",
+           "llg_get_demag_tensor", "llg_stray_field_noalloc",
            "llg_apply_precond", "llg_apply_A", "llg_set_kernel_timing",
            "llg_ctx_bytes", "llg_destroy"):
     getattr(_lib, _f).restype = _i32
@@ -185,6 +186,18 @@ def default_opts(**kw) -> Opts:
                  "tfqmr": KRYLOV_TFQMR}[v]
         setattr(o, k, v)
     return o
+
+
+def stray_field_noalloc(grid: Grid, m, out=None, stream=None):
+    """h_s(m) without a context: the library's static device scratch holds
+    the tensor and work planes (llg_stray_field_noalloc); m and out are
+    (N, 3) float64 CUDA tensors.  Returns (out, status)."""
+    if out is None:
+        out = torch.empty_like(m)
+    st = stream if stream is not None else torch.cuda.current_stream(m.device)
+    with torch.cuda.device(m.device):
+        s = _lib.llg_stray_field_noalloc(ctypes.byref(grid), _ptr(m), _ptr(out), ctypes.c_void_p(st.cuda_stream))
+    return out, s
 
 
 def workspace_bytes(grid: Grid, opts: Opts) -> tuple:

@@ -1855,6 +1855,20 @@ llg_status llg_stray_field(llg_ctx* ctx, const double* d_m, double* d_h) {
   });
 }
 
+llg_status llg_stray_field_noalloc(const llg_grid* grid, const double* d_m, double* d_h, void* hip_stream) {
+  if (!grid_ok(grid) || !d_m || !d_h || !aligned8(d_m) || !aligned8(d_h)) return LLG_ERR_INVALID_ARG;
+  if (grid->bc != LLG_BC_NEUMANN) return LLG_ERR_UNSUPPORTED;
+  const FieldDims f = field_dims(grid->n[0], grid->n[1], grid->n[2]);
+  if (std::max(f.px, std::max(f.py, f.pz)) > FFT_MAX_LEN || stray_noalloc_bytes(f) > LLG_STRAY_NOALLOC_MAX_BYTES) {
+    set_err("padded grid exceeds the static stray-field scratch");
+    return LLG_ERR_UNSUPPORTED;
+  }
+  return guard([&]() -> llg_status {
+    HIPX(stray_noalloc(f, d_m, d_h, (hipStream_t)hip_stream));
+    return LLG_OK;
+  });
+}
+
 llg_status llg_get_demag_tensor(llg_ctx* ctx, double* h_out, int64_t cap) {
   llg_status s = check_ctx(ctx);
   if (s != LLG_OK) return s;

@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "llg.h"
 #include "llg_internal.h"
@@ -648,6 +649,59 @@ void launch_demag_setup(hipStream_t st, FieldDims f, double2* work, double* nhat
     fft_forward_full(st, f, work, 1);
     hipLaunchKernelGGL(k_take_pair, dim3(nblk(P)), dim3(TPB), 0, st, P, pairs[r][0], pairs[r][1], work, nhat);
   }
+}
+
+// ------------------------------------------------------------ no-allocation stray field
+// The stray field of a device field without a context: the transformed tensor
+// (6 P doubles) and the two work planes (4 P doubles) live in one static
+// device array, so the call allocates nothing.  Each device holds its own
+// copy of the array; its address is looked up once per device.  The array
+// keeps the last call's contents: the transformed tensor is reused when the
+// grid dimensions repeat.  Calls that overlap on one device race.
+constexpr size_t NOALLOC_BYTES = LLG_STRAY_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEV = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[NOALLOC_MAX_DEV] = {};
+int64_t g_noalloc_dims[NOALLOC_MAX_DEV][3] = {};
+}  // namespace
+
+size_t stray_noalloc_bytes(FieldDims f) { return (size_t)(f.px * f.py * f.pz) * 10 * sizeof(double); }
+
+hipError_t stray_noalloc(FieldDims f, const double* m, double* h, hipStream_t st) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEV) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_noalloc_ptr[dev] = p;
+  }
+  const int64_t P = f.px * f.py * f.pz;
+  double* nhat = (double*)g_noalloc_ptr[dev];
+  double2* work = (double2*)(nhat + 6 * P);
+  const bool same = g_noalloc_dims[dev][0] == f.nx && g_noalloc_dims[dev][1] == f.ny && g_noalloc_dims[dev][2] == f.nz;
+  if (!same) {
+    g_noalloc_dims[dev][0] = 0;  // invalid until the new tensor is in place
+    launch_demag_setup(st, f, work, nhat);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  launch_stray(st, f, m, nullptr, nhat, work);
+  launch_stray_out(st, f, work, h);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  g_noalloc_dims[dev][0] = f.nx;
+  g_noalloc_dims[dev][1] = f.ny;
+  g_noalloc_dims[dev][2] = f.nz;
+  return hipSuccess;
 }
 
 void launch_stray(hipStream_t st, FieldDims f, const double* m, const double* mprev, const double* nhat,

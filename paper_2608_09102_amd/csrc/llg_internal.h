@@ -435,6 +435,10 @@ void launch_demag_pair(hipStream_t st, FieldDims f, int c0, int c1, const double
 void launch_stray(hipStream_t st, FieldDims f, const double* m, const double* mprev, const double* nhat,
                   double2* work);
 void launch_stray_out(hipStream_t st, FieldDims f, const double2* work, double* h);
+// the stray field of a device field in the static device array (see
+// llg_stray_field_noalloc); bytes it needs for a padded grid
+size_t stray_noalloc_bytes(FieldDims f);
+hipError_t stray_noalloc(FieldDims f, const double* m, double* h, hipStream_t st);
 // b -= dt' (m~ x f + alpha m~ x (m~ x f)); work NULL: no stray field
 void launch_field_rhs(hipStream_t st, int64_t N, const double* prm, const double* m, const double* mprev,
                       FieldDims f, const double2* work, double* b);
