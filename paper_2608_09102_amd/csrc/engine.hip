@@ -184,6 +184,7 @@ struct Level {
   void* kf = nullptr;  // factored grid level: K_p per node ([slice][9][64])
   void* knm = nullptr;  // the same, node-major (9 contiguous values per node)
   void* vt = nullptr;  // coarse levels feeding a Galerkin product: the blocks in slot order (9 per slot)
+  void* xp = nullptr;  // level 1 applied through the grid blocks: x + P e_c before the post-smoothing sweep
   double* prho = nullptr;  // K-cycle levels: partial sums of w1.rho
   double* mtq = nullptr;  // the frozen field in member order of the level-1 aggregates (mt[mem[q]])
   int32_t* nagg = nullptr;  // level-1 aggregates of each member's grid neighbours ([slice][6][64])
@@ -741,6 +742,7 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
     kparts = std::max<int64_t>(kparts, 3 * rows_blocks(c.lv[1].A.n, L1_LANES));
     c.lv[0].mtq = ar.lazy<double>(3 * c.lv[0].A.n);
     c.lv[0].nagg = ar.lazy<int32_t>(6 * c.lv[0].A.nslices * SL);
+    c.lv[1].xp = ar.get(ts * 3 * c.lv[1].A.n, true);  // level-1 iterate with the prolonged correction
   }
   // partial sums: up to 2R+3 columns of the delayed Gram-Schmidt dots (R+2 for the two-pass form)
   c.part = ar.lazy<double>(std::max<int64_t>(std::max<int64_t>((2 * R + 4) * c.npart_vec, c.npart_rows), kparts) + 64);
@@ -1024,8 +1026,17 @@ void lvl_post_smooth(llg_ctx& c, int l, int xmode, const T* b, const T* x, const
   Level& L = c.lv[l];
   if (l == 1 && c.f1 && (xmode == 0 || xmode == 2)) {
     const Level& L0 = c.lv[0];
+    if (ec) {
+      // the prolongation first, x' = x + P e_c, in its own pass: fused into
+      // the level-1 sweep it puts a chain of two dependent gathers (the
+      // neighbour's coarse aggregate, then its correction) behind every
+      // neighbour load
+      launch_prolong<T>(c.st, L.A.n, xmode, c.omega, b, x, agg, ec, (T*)L.xp);
+      x = (const T*)L.xp;
+      xmode = 0;
+    }
     launch_l1<T>(c.st, gdims(c), 1, xmode == 2, L.A.n, L0.mptr, L0.nagg, L0.mtq, x, b,
-                 (const T*)L.dinv, agg, ec, c.omega, out, nullptr, nullptr, nullptr);
+                 (const T*)L.dinv, nullptr, nullptr, c.omega, out, nullptr, nullptr, nullptr);
     return;
   }
   if (l == 0 && c.fact)
