@@ -28,7 +28,9 @@
  *     llg_last_error() returns (thread-local).  Arguments are validated before
  *     any device work; on an argument error nothing is launched.
  *   - All device work of a context runs on the HIP stream given to
- *     llg_create().  llg_step() returns after that work is complete.  One
+ *     llg_create() (and, with opts.overlap_rebuild, on a second stream of
+ *     the context for the next step's structure rebuild).  llg_step() returns
+ *     after the step's work is complete.  One
  *     context must not be used from two threads at once; distinct contexts are
  *     independent and may run concurrently on distinct streams.
  *   - Device memory: llg_create() and llg_step() allocate no device memory;
@@ -167,6 +169,14 @@ typedef struct {
   int32_t pipeline;     /* 1: FGMRES enqueues the preconditioner and product of the next
                            iteration before the host tests the current one's residual
                            estimate (skipped where convergence is predicted); 0: off */
+  int32_t overlap_rebuild; /* 1 (with rebuild_aggregates, the AMG solver and graphs off): the
+                           field-independent hierarchy structure (matching, coarse graphs,
+                           patterns) is kept in two copies, and the copy the next step uses is
+                           rebuilt on a second HIP stream while the current step assembles
+                           and solves; the workspace holds the structure twice.  llg_step
+                           still returns when its own step is complete; the rebuild may still
+                           run then, and llg_destroy waits for it.  0: each step rebuilds
+                           the structure before its assembly, on the context's stream */
 } llg_opts;
 
 typedef struct {
@@ -201,7 +211,8 @@ typedef enum {
  * dimension, npass 2, beta 1/4, max_coarse 40, stagnation 0.8, max_levels 40,
  * max_dense 512, left_scale 1, project 1, x0_is_mn 1, salt 0, rebuild 1,
  * K-cycle depth 0, graphs 0, Jacobi, BDF1, BSR grid level, DCGS2, FGMRES with
- * the AMG cycle, no stray-field workspace, tail_nodes 128, pipeline 1. */
+ * the AMG cycle, no stray-field workspace, tail_nodes 128, pipeline 1,
+ * overlap_rebuild 1. */
 void llg_default_opts(llg_opts* opts);
 
 /* Exact device bytes a context for (grid, opts) needs.  Runs the aggregation

@@ -67,6 +67,8 @@ struct Plan {
   std::vector<uint8_t> lazy;     // request is not materialized in PLAN mode
   std::vector<int64_t> counts;   // every host-visible count, in order
   size_t total = 0;
+  size_t struct_bytes = 0;       // bytes of the structure's requests (the first ones)
+  bool dbl = false;              // a second copy of the structure (the overlapped rebuild)
   int status = LLG_OK;
 };
 
@@ -82,6 +84,7 @@ struct Arena {
   std::vector<void*> owned;       // PLAN: temporary allocations
   hipStream_t st = nullptr;
   int32_t* flag = nullptr;        // REPLAY: mismatch flag
+  int flag_word = 0;              // word of the flags the checks raise (1: a rebuild on the second stream)
   int32_t* hcount = nullptr;      // PLAN: pinned read-back slot
 
   void* get(size_t bytes, bool lazy) {
@@ -190,6 +193,28 @@ struct Level {
   int32_t* nagg = nullptr;  // level-1 aggregates of each member's grid neighbours ([slice][6][64])
 };
 
+// The parts of a level that the structure build writes (pattern, graph,
+// aggregates, members, colour classes); two copies of these exist when the
+// next step's structure is rebuilt on a second stream.
+struct LevelStruct {
+  Sell A;
+  int32_t *brp = nullptr, *bci = nullptr;
+  int64_t nnzb = 0;
+  int32_t *grp = nullptr, *gci = nullptr, *gw = nullptr;
+  int64_t gnnz = 0;
+  int32_t *agg = nullptr, *mptr = nullptr, *mem = nullptr;
+  int64_t nc = 0;
+  int32_t *colour = nullptr, *perm = nullptr;
+  int ncol = 0;
+  std::vector<int64_t> coff;
+  std::vector<Sell> cls;
+};
+struct StructSet {
+  LevelStruct lv[LLG_MAX_LEVELS];
+  int L = 0;
+  int32_t *flags = nullptr, *count = nullptr, *scan_tmp = nullptr;
+};
+
 struct PlanKey {
   std::tuple<int, int, int, int, int, int, int, int, double, int, int, uint64_t, int, int, int, int, int, int, int,
              int, int>
@@ -200,12 +225,18 @@ struct PlanKey {
 std::mutex g_plan_mu;
 std::map<PlanKey, std::shared_ptr<Plan>> g_plans;
 
+// the next step's structure is rebuilt on a second stream during the current
+// step (double-buffered): AMG solves that rebuild every step, without graphs
+bool overlapped_rebuild(const llg_opts& o) {
+  return o.overlap_rebuild && o.rebuild_aggregates && o.krylov == LLG_KRYLOV_FGMRES_AMG && !o.graphs;
+}
+
 PlanKey plan_key(const llg_grid& g, const llg_opts& o) {
   PlanKey k;
   k.k = std::make_tuple(g.dim, g.n[0], g.n[1], g.n[2], o.npass, o.beta_num, o.beta_den, o.max_coarse,
                         o.stagnation, o.max_levels, o.max_dense, o.agg_salt, o.precision, o.restart,
                         o.left_scale, o.kcycle_depth, o.smoother, o.scheme, o.fine_operator, o.krylov,
-                        o.stray_field);
+                        o.stray_field * 2 + (overlapped_rebuild(o) ? 1 : 0));
   return k;
 }
 
@@ -253,6 +284,16 @@ struct llg_ctx {
   int32_t* flags = nullptr;
   int32_t* count = nullptr;
   int32_t* scan_tmp = nullptr;
+  // overlapped rebuild: two structure sets, the one the current step uses
+  // (loaded into lv[], flags, count, scan_tmp) and the one being rebuilt on
+  // the second stream for the next step
+  bool dbl = false;
+  int set = 0;
+  llg::StructSet sets[2];
+  std::vector<void*> ptrs2;  // addresses of the second set's structure requests
+  hipStream_t aux = nullptr;
+  hipEvent_t built[2] = {nullptr, nullptr};
+  hipEvent_t main_ev = nullptr;
   double* host = nullptr;     // pinned scalars
   int32_t* hflags = nullptr;  // pinned flags
   bool setup_done = false;
@@ -411,7 +452,7 @@ void build_colours(llg_ctx& c, Arena& ar, int l) {
       for (int64_t r = 0; r < rounds; ++r)
         launch_jp_round(st, n, L.grp, L.gci, rank, (int32_t)r, cround, L.colour,
                         r + 1 == rounds ? c.count : c.count + 1);
-      launch_check_eq(st, c.count, 0, c.flags, F_PLAN);
+      launch_check_eq(st, c.count, 0, ar.flag, F_PLAN);
       LCHK();
     }
   }
@@ -465,7 +506,7 @@ int build_structure(llg_ctx& c, Arena& ar) {
     launch_fill_i32(st, c.flags, 8, 0);
     LCHK();
   }
-  ar.flag = c.flags;
+  ar.flag = c.flags + ar.flag_word;
   Level& L0 = c.lv[0];
   L0.grp = ar.alloc<int32_t>(N + 1);
   launch_grid_degree(st, nx, ny, nz, L0.grp);
@@ -510,7 +551,7 @@ int build_structure(llg_ctx& c, Arena& ar) {
       // round proposes nothing
       if (cn <= MATCH_SMALL) {
         // a small level: every round in one workgroup, in both modes
-        launch_match_small(st, cn, crp, cci, cw, mate, ns, salt, o.beta_num, o.beta_den, prop, c.flags, F_PLAN,
+        launch_match_small(st, cn, crp, cci, cw, mate, ns, salt, o.beta_num, o.beta_den, prop, ar.flag, F_PLAN,
                            lanes);
         LCHK();
       } else if (ar.mode == Mode::PLAN) {
@@ -537,7 +578,7 @@ int build_structure(llg_ctx& c, Arena& ar) {
         }
         launch_fill_i32(st, c.count, 1, 0);
         launch_propose(st, cn, crp, cci, cw, mate, ns, salt, o.beta_num, o.beta_den, prop, c.count, lanes);
-        launch_check_eq(st, c.count, 0, c.flags, F_PLAN);
+        launch_check_eq(st, c.count, 0, ar.flag, F_PLAN);
         LCHK();
       }
       launch_leader_flag(st, cn, mate, id);
@@ -662,6 +703,62 @@ const TailArgs<double>& tail_args<double>(const llg_ctx& c) {
 template <>
 const TailArgs<float>& tail_args<float>(const llg_ctx& c) {
   return c.ta32;
+}
+
+void save_struct(const llg_ctx& c, StructSet& S) {
+  S.L = c.L;
+  S.flags = c.flags;
+  S.count = c.count;
+  S.scan_tmp = c.scan_tmp;
+  for (int l = 0; l < LLG_MAX_LEVELS; ++l) {
+    const Level& L = c.lv[l];
+    LevelStruct& T = S.lv[l];
+    T.A = L.A;
+    T.brp = L.brp;
+    T.bci = L.bci;
+    T.nnzb = L.nnzb;
+    T.grp = L.grp;
+    T.gci = L.gci;
+    T.gw = L.gw;
+    T.gnnz = L.gnnz;
+    T.agg = L.agg;
+    T.mptr = L.mptr;
+    T.mem = L.mem;
+    T.nc = L.nc;
+    T.colour = L.colour;
+    T.perm = L.perm;
+    T.ncol = L.ncol;
+    T.coff = L.coff;
+    T.cls = L.cls;
+  }
+}
+
+void load_struct(llg_ctx& c, const StructSet& S) {
+  c.L = S.L;
+  c.flags = S.flags;
+  c.count = S.count;
+  c.scan_tmp = S.scan_tmp;
+  for (int l = 0; l < LLG_MAX_LEVELS; ++l) {
+    Level& L = c.lv[l];
+    const LevelStruct& T = S.lv[l];
+    L.A = T.A;
+    L.brp = T.brp;
+    L.bci = T.bci;
+    L.nnzb = T.nnzb;
+    L.grp = T.grp;
+    L.gci = T.gci;
+    L.gw = T.gw;
+    L.gnnz = T.gnnz;
+    L.agg = T.agg;
+    L.mptr = T.mptr;
+    L.mem = T.mem;
+    L.nc = T.nc;
+    L.colour = T.colour;
+    L.perm = T.perm;
+    L.ncol = T.ncol;
+    L.coff = T.coff;
+    L.cls = T.cls;
+  }
 }
 
 // Values, vectors and Krylov storage (never materialized when planning).
@@ -799,7 +896,7 @@ bool opts_ok(const llg_opts* o) {
          (o->krylov == LLG_KRYLOV_FGMRES_AMG || o->krylov == LLG_KRYLOV_GMRES || o->krylov == LLG_KRYLOV_BICGSTAB ||
           o->krylov == LLG_KRYLOV_TFQMR) &&
          (o->stray_field == 0 || o->stray_field == 1) && o->tail_nodes >= 0 &&
-         (o->pipeline == 0 || o->pipeline == 1);
+         (o->pipeline == 0 || o->pipeline == 1) && (o->overlap_rebuild == 0 || o->overlap_rebuild == 1);
 }
 
 // Plan for (grid, opts): cached; computed on the current device.
@@ -825,8 +922,13 @@ std::shared_ptr<Plan> get_plan(const llg_grid& g, const llg_opts& o) {
   ar.hcount = hc;
   try {
     c.L = build_structure(c, ar);
+    plan->struct_bytes = plan->total;
     if (c.lv[c.L - 1].A.n > o.max_dense) plan->status = LLG_ERR_UNSUPPORTED;
     allocate_numeric(c, ar);
+    if (overlapped_rebuild(o)) {  // the second structure set
+      plan->dbl = true;
+      plan->total += plan->struct_bytes;
+    }
     HIPX(hipStreamSynchronize(c.st));
   } catch (...) {
     ar.release();
@@ -843,6 +945,55 @@ std::shared_ptr<Plan> get_plan(const llg_grid& g, const llg_opts& o) {
 }
 
 // ------------------------------------------------------------------ setup
+void retarget_tail(llg_ctx& c) {
+  if (c.opts.precision == LLG_PREC_FP32_AMG)
+    plan_tail<float>(c, c.ta32);
+  else
+    plan_tail<double>(c, c.ta64);
+}
+
+// The overlapped rebuild.  The step uses the structure set built for it
+// during the previous step (or at creation) on the second stream: the main
+// stream waits for that build, takes its device-side check result as the
+// step's initial flags, and the set is loaded.  Then the other set (the one
+// the previous step used) is rebuilt on the second stream for the next step,
+// after the work already queued on the main stream.  Every step thus still
+// rebuilds a hierarchy structure; the rebuild runs beside the solve.
+void rebuild_overlapped(llg_ctx& c) {
+  const int cur = c.set, nxt = 1 - c.set;
+  HIPX(hipStreamWaitEvent(c.st, c.built[cur], 0));
+  load_struct(c, c.sets[cur]);
+  retarget_tail(c);
+  HIPX(hipMemcpyAsync(c.flags, c.flags + 1, sizeof(int32_t), hipMemcpyDeviceToDevice, c.st));
+  launch_fill_i32(c.st, c.flags + 1, 1, 0);
+  LCHK();
+  HIPX(hipEventRecord(c.main_ev, c.st));
+  HIPX(hipStreamWaitEvent(c.aux, c.main_ev, 0));
+  load_struct(c, c.sets[nxt]);
+  hipStream_t keep = c.st;
+  c.st = c.aux;
+  Arena ar;
+  ar.mode = Mode::REPLAY;
+  ar.plan = c.plan.get();
+  ar.first = false;
+  ar.ptrs = nxt == 0 ? &c.ptrs : &c.ptrs2;
+  ar.st = c.aux;
+  ar.flag_word = 1;
+  try {
+    (void)build_structure(c, ar);
+  } catch (...) {
+    c.st = keep;
+    load_struct(c, c.sets[cur]);
+    retarget_tail(c);
+    throw;
+  }
+  c.st = keep;
+  HIPX(hipEventRecord(c.built[nxt], c.aux));
+  load_struct(c, c.sets[cur]);
+  retarget_tail(c);
+  c.set = nxt;
+}
+
 // Everything llg_step does before the Krylov solve: the structure rebuild
 // (replayed from the plan), assembly, Galerkin products and the coarsest
 // inverse.  alpha and dt are read from c.prm on the device.
@@ -851,7 +1002,9 @@ void setup_values(llg_ctx& c, const double* m, const double* mprev, const double
   hipStream_t st = c.st;
   const llg_grid& g = c.grid;
   const bool amg = c.opts.krylov == LLG_KRYLOV_FGMRES_AMG;  // the baselines need only A, b and u0
-  if (amg && c.opts.rebuild_aggregates) {
+  if (amg && c.opts.rebuild_aggregates && c.dbl) {
+    rebuild_overlapped(c);
+  } else if (amg && c.opts.rebuild_aggregates) {
     Arena ar;
     ar.mode = Mode::REPLAY;
     ar.plan = c.plan.get();
@@ -1691,6 +1844,7 @@ void llg_default_opts(llg_opts* o) {
   o->stray_field = 0;
   o->tail_nodes = 128;
   o->pipeline = 1;
+  o->overlap_rebuild = 1;
 }
 
 // combinations the library does not implement
@@ -1757,9 +1911,36 @@ llg_status llg_create(const llg_grid* grid, const llg_opts* opts, void* d_worksp
     c->L = build_structure(*c, ar);
     allocate_numeric(*c, ar);
     c->used = ar.off;
+    int32_t fl1 = 0;
+    if (plan->dbl) {  // the second structure set, built here as well
+      c->dbl = true;
+      save_struct(*c, c->sets[0]);
+      Arena a2;
+      a2.mode = Mode::REPLAY;
+      a2.plan = plan.get();
+      a2.first = true;
+      a2.ptrs = &c->ptrs2;
+      a2.base = c->ws + c->used;
+      a2.cap = bytes - c->used;
+      a2.st = c->st;
+      (void)build_structure(*c, a2);
+      c->used += a2.off;
+      save_struct(*c, c->sets[1]);
+      HIPX(hipMemcpyAsync(c->hflags, c->flags, sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+      HIPX(hipStreamSynchronize(c->st));
+      fl1 = *c->hflags;
+      load_struct(*c, c->sets[0]);
+      retarget_tail(*c);
+      HIPX(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+      for (int k = 0; k < 2; ++k) {
+        HIPX(hipEventCreateWithFlags(&c->built[k], hipEventDisableTiming));
+        HIPX(hipEventRecord(c->built[k], c->st));  // both sets are complete on the main stream
+      }
+      HIPX(hipEventCreateWithFlags(&c->main_ev, hipEventDisableTiming));
+    }
     HIPX(hipMemcpyAsync(c->hflags, c->flags, sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
     HIPX(hipStreamSynchronize(c->st));
-    if (*c->hflags & F_PLAN) {
+    if ((*c->hflags | fl1) & F_PLAN) {
       set_err("hierarchy structure differs from the plan");
       llg_destroy(c.release());
       return LLG_ERR_DEVICE;
@@ -2054,7 +2235,12 @@ llg_status llg_ctx_bytes(llg_ctx* ctx, size_t* bytes) {
 
 llg_status llg_destroy(llg_ctx* ctx) {
   if (!ctx) return LLG_ERR_INVALID_ARG;
+  if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
   (void)hipStreamSynchronize(ctx->st);
+  if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+  for (hipEvent_t e : ctx->built)
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->main_ev) (void)hipEventDestroy(ctx->main_ev);
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   if (ctx->it_ev) (void)hipEventDestroy(ctx->it_ev);
   for (hipGraphExec_t g : ctx->pc_graph)

@@ -399,3 +399,31 @@ def test_forced_steps_vortex64(gpu, orc, form):
         assert d <= 1e-8
         assert np.abs(ref - unforced).max() >= 1e-4
         m = ref
+
+
+@pytest.mark.parametrize("form", [dict(), dict(kcycle_depth=1, fine_operator="factored", precision="fp32_amg")],
+                         ids=["bsr_v", "factored_k1_fp32amg"])
+def test_overlapped_rebuild_matches_serial(gpu, form):
+    """The hierarchy structure rebuilt for the next step on the second stream
+    (two structure copies used in turn) gives every step bit for bit the
+    result of the rebuild at the start of each step, over enough steps that
+    both copies are rebuilt and used several times; the aggregates of the
+    last step equal the serial ones."""
+    say("[overlapped_rebuild_matches_serial]", form)
+    n = 72
+    m0 = I.smooth_unit_field(2, n, seed=12)
+    outs, aggs = {}, {}
+    for ov in (0, 1):
+        S = gpu.Solver(gpu.make_grid(2, n), gpu.default_opts(rtol=1e-9, overlap_rebuild=ov, **form))
+        x = _cuda(m0)
+        res = []
+        for k in range(5):
+            x, s, st = S.step(x, 0.05, 1e-3)
+            assert s == gpu.OK
+            res.append((x.cpu().numpy(), st.iters))
+        outs[ov] = res
+        aggs[ov] = [S.aggregates(l) for l in range(S.num_levels - 1)]
+        S.close()
+    for (a, ia), (b, ib) in zip(outs[0], outs[1]):
+        assert ia == ib and np.array_equal(a, b)
+    assert all(np.array_equal(p, q) for p, q in zip(aggs[0], aggs[1]))
