@@ -58,7 +58,9 @@ def parse():
     p.add_argument("--secondary-workload", default="rough2d_1024")
     p.add_argument("--serve-leg-requests", type=int, default=24,
                    help="requests of the serving run reported as a secondary key")
-    p.add_argument("--roofline-class", default="outer_spmv")
+    p.add_argument("--roofline-class", default="level1",
+                   help="kernel class of the roofline object: level1 (the level-1 products through the grid "
+                        "blocks, k_l1, the largest kernel of the 256^3 forms) or outer_spmv")
     p.add_argument("--alpha", type=float, default=None, help="override the workload's alpha")
     p.add_argument("--kdepth", type=int, default=None, help="override the K-cycle depth of every form")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -111,9 +113,15 @@ def read_traffic(kernel: str, workload: str, precision: str, operator: str):
         return None
 
 
-def algorithmic_bytes(cls: str, st, N: int, precision: str, operator: str = "bsr") -> float:
+def algorithmic_bytes(cls: str, st, N: int, precision: str, operator: str = "bsr", r=None) -> float:
     """Bytes one launch of the kernel class must move at minimum (values,
-    indices, input vector read once, output written once)."""
+    indices, input vector read once, output written once).  level1: the
+    library adds up each timed launch's bytes by its mode (frozen field by
+    member 24 B and neighbour aggregates 4 B per neighbour per grid node,
+    member pointers, x, and per mode b / D1^-1 / the dot operands and the
+    output); the figure is their mean per launch."""
+    if cls == "level1":
+        return r["kernel_bytes"] / max(1, r["kernel_launches"])
     nnzb0 = st.level_nnzb[0]
     if cls == "outer_spmv":
         zb = 4 if precision == "fp32_amg" else 8
@@ -136,8 +144,12 @@ def forcing_list(torch, w, total: int):
 
 def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str, Fs, kdepth: int = 0,
              smoother: str = "jacobi", operator: str = "bsr"):
+    # operator[+serial|+reuse]: the hierarchy structure rebuilt on a second stream beside the step
+    # (default), rebuilt at the start of each step (serial), or built once per context (reuse)
+    base, _, rb = operator.partition("+")
+    extra = {"serial": dict(overlap_rebuild=0), "reuse": dict(rebuild_aggregates=0)}.get(rb, {})
     opts = llg.default_opts(rtol=w.rtol, precision=form, kcycle_depth=kdepth, smoother=smoother,
-                            fine_operator=operator)
+                            fine_operator=base, **extra)
     grid = llg.make_grid(w.dim, w.n)
     t0 = time.perf_counter()
     S = llg.Solver(grid, opts)
@@ -153,6 +165,7 @@ def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str, Fs, kd
     iters = []
     kms = 0.0
     klaunch = 0
+    kbytes = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
@@ -163,6 +176,7 @@ def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str, Fs, kd
         iters.append(st.iters)
         kms += st.kernel_ms
         klaunch += st.kernel_launches
+        kbytes += st.kernel_bytes
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     S.set_kernel_timing("none")
@@ -173,7 +187,8 @@ def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str, Fs, kd
         me = I.exact_solution(w.dim, w.n, (warmup + steps) * w.dt, xp=torch, device=final.device)
         err_exact = float((final - me).abs().max())
         del me
-    res = {"seconds": el, "iters": iters, "kernel_ms": kms, "kernel_launches": klaunch, "stats": st,
+    res = {"seconds": el, "iters": iters, "kernel_ms": kms, "kernel_launches": klaunch, "kernel_bytes": kbytes,
+           "stats": st,
            "levels": st.levels, "level_nodes": list(st.level_nodes[:st.levels]),
            "level_nnzb": list(st.level_nnzb[:st.levels]), "err_vs_exact": err_exact,
            "workspace_GB": S.workspace_bytes / 1e9, "create_s": t_create,
@@ -498,14 +513,14 @@ def main():
     unknowns = w.unknowns
     value = unknowns * a.steps / r["seconds"]
     # roofline of the timed kernel class
-    lb = algorithmic_bytes(a.roofline_class, r["stats"], w.nodes, main_form, main_op)
+    lb = algorithmic_bytes(a.roofline_class, r["stats"], w.nodes, main_form, main_op, r)
     avg_s = r["kernel_ms"] / 1e3 / max(1, r["kernel_launches"])
     achieved = lb / avg_s / 1e9 if avg_s > 0 else 0.0
     traffic = read_traffic(a.roofline_class, w.name, main_form, main_op)
 
     def form_name(prec, kd, sm, op):
         return "%s_%s%s%s" % (prec, "k%d" % kd if kd else "vcycle", "" if sm == "jacobi" else "_" + sm,
-                              "" if op == "bsr" else "_" + op)
+                              "" if op == "bsr" else "_" + op.replace("+", "_"))
 
     def cycle(kd, sm):
         return "aggregation AMG, %s (1,1), %s" % ("damped block-Jacobi" if sm == "jacobi" else
@@ -530,12 +545,16 @@ def main():
                    "forcing": "manufactured (resident on the device)" if w.forcing else None,
                    "form": main_form, "hierarchy": "rebuilt every step", "krylov": "FGMRES(30), FP64",
                    "preconditioner": cycle(main_kd, main_sm),
-                   "grid_operator": "3x3-block sliced ELL" if main_op == "bsr" else "factored (one block per node)"},
+                   "grid_operator": "3x3-block sliced ELL" if main_op.startswith("bsr") else "factored (one block per node)",
+                   "structure_rebuild": {"": "every step, on a second stream beside the step (double-buffered)",
+                                         "serial": "every step, before the assembly",
+                                         "reuse": "once per context"}[main_op.partition("+")[2]]},
         "iters_per_step": sum(r["iters"]) / len(r["iters"]),
         "iters": r["iters"],
         "levels": r["levels"],
         "workspace_GB": r["workspace_GB"],
         "level_nodes": r["level_nodes"],
+        "level_nnzb": r["level_nnzb"],
         "roofline": {"bound": "hbm", "kernel": a.roofline_class, "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": traffic, "algorithmic_bytes_per_launch": lb,

@@ -192,6 +192,8 @@ typedef struct {
   int64_t kernel_launches;
   int32_t reorth_passes;  /* Arnoldi steps that needed a second Gram-Schmidt pass */
   int32_t tail_level;     /* first level of the one-workgroup coarse cycle (opts.tail_nodes); 0 = none */
+  double kernel_bytes;    /* algorithmic bytes of the timed launches (LLG_KT_LEVEL1: every launch's
+                             operands read once and results written once), 0 for the other classes */
 } llg_stats;
 
 typedef struct llg_ctx llg_ctx;
@@ -204,7 +206,8 @@ typedef enum {
   LLG_KT_RESIDUAL = 3,     /* r = b - A x with restriction, all levels */
   LLG_KT_ARNOLDI = 4,      /* multi-dot and update passes of the Gram-Schmidt step */
   LLG_KT_GALERKIN = 5,     /* P^T A P values */
-  LLG_KT_ASSEMBLE = 6      /* fine operator assembly */
+  LLG_KT_ASSEMBLE = 6,     /* fine operator assembly */
+  LLG_KT_LEVEL1 = 7        /* level-1 products applied through the grid level's blocks (every mode) */
 } llg_kernel_class;
 
 /* Defaults: rtol 1e-10, restart 30, max_iters 1000, FP64, nu 1/1, omega by

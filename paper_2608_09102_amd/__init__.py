@@ -34,7 +34,7 @@ FINE_BSR, FINE_FACTORED = 0, 1
 ARNOLDI_CGS2, ARNOLDI_DCGS2 = 0, 1
 KRYLOV_FGMRES_AMG, KRYLOV_GMRES, KRYLOV_BICGSTAB, KRYLOV_TFQMR = 0, 2, 3, 4
 KT_NONE, KT_OUTER_SPMV, KT_SMOOTH, KT_RESIDUAL, KT_ARNOLDI, KT_GALERKIN, KT_ASSEMBLE = range(7)
-KERNEL_CLASSES = {"none": 0, "outer_spmv": 1, "smooth": 2, "residual": 3, "arnoldi": 4, "galerkin": 5,
+KERNEL_CLASSES = {"none": 0, "outer_spmv": 1, "smooth": 2, "residual": 3, "arnoldi": 4, "galerkin": 5, "level1": 7,
                   "assemble": 6}
 
 
@@ -79,7 +79,7 @@ class Stats(ctypes.Structure):
         ("level_nodes", ctypes.c_int64 * MAX_LEVELS), ("level_nnzb", ctypes.c_int64 * MAX_LEVELS),
         ("ms_setup", ctypes.c_double), ("ms_solve", ctypes.c_double), ("ms_total", ctypes.c_double),
         ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int64), ("reorth_passes", ctypes.c_int32),
-        ("tail_level", ctypes.c_int32),
+        ("tail_level", ctypes.c_int32), ("kernel_bytes", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -89,7 +89,8 @@ class Stats(ctypes.Structure):
                 "level_nodes": list(self.level_nodes[:L]), "level_nnzb": list(self.level_nnzb[:L]),
                 "ms_setup": self.ms_setup, "ms_solve": self.ms_solve, "ms_total": self.ms_total,
                 "kernel_ms": self.kernel_ms, "kernel_launches": self.kernel_launches,
-                "reorth_passes": self.reorth_passes, "tail_level": self.tail_level}
+                "reorth_passes": self.reorth_passes, "tail_level": self.tail_level,
+                "kernel_bytes": self.kernel_bytes}
 
 
 _P = ctypes.c_void_p

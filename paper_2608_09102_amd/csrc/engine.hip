@@ -324,6 +324,7 @@ struct llg_ctx {
   hipEvent_t it_ev = nullptr;  // end of an FGMRES iteration's orthogonalization (pipelined loop)
   double kernel_ms = 0;
   int64_t launches = 0;
+  double kernel_bytes = 0;  // algorithmic bytes of the timed launches (level-1 class)
 };
 
 namespace llg {
@@ -769,6 +770,10 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   Level& L0 = c.lv[0];
   // the factored grid level needs a coarse level (the coarsest is stored as BSR)
   c.fact = c.opts.fine_operator == LLG_FINE_FACTORED && c.L > 1;
+  // level 1 (not the coarsest, one lane per row) applied through the grid level's blocks
+  // (at most two matching passes: k_l1 takes aggregates of at most four members)
+  const bool f1 = c.fact && c.L > 2 && c.lv[1].A.n >= 32768 && c.opts.smoother == LLG_SMOOTHER_JACOBI &&
+                  c.opts.npass <= 2;
   if (c.fact) {
     c.Mh = ar.lazy<double>(9 * L0.A.nslices * SL);
     c.mt = ar.lazy<double>(3 * L0.A.n);
@@ -781,10 +786,13 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   for (int l = 0; l < c.L; ++l) {
     Level& L = c.lv[l];
     const int64_t n = L.A.n;
-    if (!(l == 0 && c.fact)) L.val = ar.get(ts * 9 * L.A.nslots, true);
-    // the next level's Galerkin product reads this level's blocks in slot
-    // order (the sliced-ELL layout spreads a block over nine cache lines)
-    if (l >= 1 && l + 1 < c.L) L.vt = ar.get(ts * 9 * L.A.nslots, true);
+    // sliced-ELL values, except where no product reads them: the factored
+    // grid level, and level 1 when it is applied through the grid blocks
+    if (!(l == 0 && c.fact) && !(l == 1 && f1)) L.val = ar.get(ts * 9 * L.A.nslots, true);
+    // the next level's Galerkin product walks the member rows of this level
+    // and reads their blocks in CSR order (contiguous per row; the sliced-ELL
+    // layout spreads a row over 64-slot strides and a block over nine lines)
+    if (l >= 1 && l + 1 < c.L) L.vt = ar.get(ts * 9 * L.nnzb, true);
     L.unit = l == 0 && c.opts.left_scale;
     L.G = n >= 32768 ? 1 : (c.grid.dim == 3 ? 16 : 8);
     L.dinv = ar.get(ts * 9 * L.A.nslices * SL, true);
@@ -832,9 +840,7 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
     // stage 3 sums them (a nested K-cycle reuses c.part in between)
     if (l <= c.opts.kcycle_depth && l + 1 < c.L) c.lv[l].prho = ar.lazy<double>(rows_blocks(c.lv[l].A.n, 1));
   }
-  // level 1 (not the coarsest, one lane per row) applied through the grid level's blocks
-  // (at most two matching passes: k_l1 takes aggregates of at most four members)
-  c.f1 = c.fact && c.L > 2 && c.lv[1].G == 1 && c.opts.smoother == LLG_SMOOTHER_JACOBI && c.opts.npass <= 2;
+  c.f1 = f1;
   if (c.f1) {
     kparts = std::max<int64_t>(kparts, 3 * rows_blocks(c.lv[1].A.n, L1_LANES));
     c.lv[0].mtq = ar.lazy<double>(3 * c.lv[0].A.n);
@@ -1040,7 +1046,10 @@ void setup_values(llg_ctx& c, const double* m, const double* mprev, const double
     src.fvt = (const T*)L.vt;
     src.fk = (const T*)L.kf;
     src.knm = (const T*)L.knm;  // factored grid level: K node-major
+    src.frp = L.brp;
+    src.fci = L.bci;
     src.cvt = (T*)Nx.vt;
+    src.crp = Nx.brp;
     launch_galerkin<T>(st, Nx.A, (T*)Nx.val, (T*)Nx.dinv, L.mptr, L.mem, L.A, L.agg, src);
     LCHK();
   }
@@ -1158,13 +1167,35 @@ GridDims gdims(const llg_ctx& c) {
   return g;
 }
 
+// A level-1 product through the grid blocks (k_l1), timed as LLG_KT_LEVEL1:
+// the launch stamps its own events, and its algorithmic bytes are added up:
+// the member-ordered frozen field (24 B per grid node), the neighbour
+// aggregates (4 B per neighbour slot), the member pointers, x once, and per
+// mode b and the output (0), b, D1^{-1} and the output (1), the output and
+// the dot operands (2).
+template <typename T>
+void l1(llg_ctx& c, int mode, int xzero, const T* x, const T* b, const T* dinv1, T* out, const T* d1, const T* d2,
+        double* part) {
+  const Level& L0 = c.lv[0];
+  const int64_t n1 = c.lv[1].A.n, N = L0.A.n, v = sizeof(T);
+  hipEvent_t e0, e1;
+  kernel_events(c, LLG_KT_LEVEL1, e0, e1);
+  if (e0) {
+    double bytes = 24.0 * N + 4.0 * 2 * c.grid.dim * N + 4.0 * (n1 + 1) + (xzero ? 0.0 : 3.0 * v * n1);
+    if (mode == 0) bytes += 6.0 * v * n1;
+    if (mode == 1) bytes += 15.0 * v * n1;
+    if (mode == 2) bytes += 3.0 * v * n1 * (1 + (d1 ? 1 : 0) + (d2 ? 1 : 0));
+    c.kernel_bytes += bytes;
+  }
+  launch_l1<T>(c.st, gdims(c), mode, xzero, n1, L0.mptr, L0.nagg, L0.mtq, x, b, dinv1, nullptr, nullptr, c.omega,
+               out, d1, d2, part, e0, e1);
+}
+
 template <typename T>
 void lvl_residual(llg_ctx& c, int l, int xmode, const T* b, const T* x, T* r) {
   Level& L = c.lv[l];
   if (l == 1 && c.f1 && xmode == 0) {
-    const Level& L0 = c.lv[0];
-    launch_l1<T>(c.st, gdims(c), 0, 0, L.A.n, L0.mptr, L0.nagg, L0.mtq, x, b, nullptr, nullptr,
-                 nullptr, c.omega, r, nullptr, nullptr, nullptr);
+    l1<T>(c, 0, 0, x, b, nullptr, r, nullptr, nullptr, nullptr);
     return;
   }
   if (l == 0 && c.fact)
@@ -1178,7 +1209,6 @@ void lvl_post_smooth(llg_ctx& c, int l, int xmode, const T* b, const T* x, const
                      T* out) {
   Level& L = c.lv[l];
   if (l == 1 && c.f1 && (xmode == 0 || xmode == 2)) {
-    const Level& L0 = c.lv[0];
     if (ec) {
       // the prolongation first, x' = x + P e_c, in its own pass: fused into
       // the level-1 sweep it puts a chain of two dependent gathers (the
@@ -1188,8 +1218,7 @@ void lvl_post_smooth(llg_ctx& c, int l, int xmode, const T* b, const T* x, const
       x = (const T*)L.xp;
       xmode = 0;
     }
-    launch_l1<T>(c.st, gdims(c), 1, xmode == 2, L.A.n, L0.mptr, L0.nagg, L0.mtq, x, b,
-                 (const T*)L.dinv, nullptr, nullptr, c.omega, out, nullptr, nullptr, nullptr);
+    l1<T>(c, 1, xmode == 2, x, b, (const T*)L.dinv, out, nullptr, nullptr, nullptr);
     return;
   }
   if (l == 0 && c.fact)
@@ -1386,12 +1415,10 @@ void kcorrection(llg_ctx& c, int lc) {
   // into the update of rho (Gauss-Seidel cycles start from x = 0 themselves)
   const bool pre = c.opts.nu_pre >= 1 && c.opts.smoother == LLG_SMOOTHER_JACOBI;
   vcycle<T>(c, lc, (const T*)C.b, (T*)C.v1);
-  const Level& L0 = c.lv[0];
   const bool f1 = lc == 1 && c.f1;
   const int64_t G = f1 ? rows_blocks(C.A.n, L1_LANES) : rows_blocks(C.A.n, C.G);  // partial sums per column
   if (f1)
-    launch_l1<T>(st, gdims(c), 2, 0, C.A.n, L0.mptr, L0.nagg, L0.mtq, (const T*)C.v1, nullptr,
-                 nullptr, nullptr, nullptr, c.omega, (T*)C.w1, (const T*)C.b, nullptr, c.part);
+    l1<T>(c, 2, 0, (const T*)C.v1, nullptr, nullptr, (T*)C.w1, (const T*)C.b, nullptr, c.part);
   else
     launch_spmv_dots<T>(st, C.A, val, (const T*)C.v1, (T*)C.w1, (const T*)C.b, nullptr, c.part, C.G);
   launch_kc_coef(st, c.part, G, 1, C.kc);
@@ -1402,8 +1429,7 @@ void kcorrection(llg_ctx& c, int lc) {
   LCHK();
   vcycle<T>(c, lc, (const T*)C.rho, (T*)C.v2);
   if (f1)
-    launch_l1<T>(st, gdims(c), 2, 0, C.A.n, L0.mptr, L0.nagg, L0.mtq, (const T*)C.v2, nullptr,
-                 nullptr, nullptr, nullptr, c.omega, (T*)C.w2, (const T*)C.w1, (const T*)C.rho, c.part);
+    l1<T>(c, 2, 0, (const T*)C.v2, nullptr, nullptr, (T*)C.w2, (const T*)C.w1, (const T*)C.rho, c.part);
   else
     launch_spmv_dots<T>(st, C.A, val, (const T*)C.v2, (T*)C.w2, (const T*)C.w1, (const T*)C.rho, c.part, C.G);
   launch_kc_coef(st, c.part, G, 3, C.kc, part_rho, rows_blocks(C.A.n, 1));
@@ -1733,6 +1759,7 @@ llg_status run_step(llg_ctx& c, const double* m_n, const double* m_nm1, double a
   const auto t0 = std::chrono::steady_clock::now();
   c.kernel_ms = 0;
   c.launches = 0;
+  c.kernel_bytes = 0;
   c.ev_used = 0;
   const int64_t fb = (int64_t)sizeof(double) * 3 * c.N;
   const bool bdf2 = c.opts.scheme == LLG_SCHEME_BDF2 && m_nm1 != nullptr;
@@ -1771,6 +1798,7 @@ llg_status run_step(llg_ctx& c, const double* m_n, const double* m_nm1, double a
     stats->ms_solve = stats->ms_total - t_setup;
     stats->kernel_ms = c.kernel_ms;
     stats->kernel_launches = c.launches;
+    stats->kernel_bytes = c.kernel_bytes;
     stats->reorth_passes = (int32_t)c.host[7];
     stats->tail_level = c.tail;
   }
@@ -2123,9 +2151,13 @@ llg_status llg_get_level(llg_ctx* ctx, int32_t level, int32_t* h_row_ptr, int32_
     const bool f32 = level >= 0 && ctx->opts.precision == LLG_PREC_FP32_AMG;
     const size_t ts = f32 ? 4 : 8;
     const bool fact = level <= 0 && ctx->fact;
-    const void* val = fact ? (level < 0 ? (const void*)ctx->Mh : L.kf) : (level < 0 ? (const void*)ctx->Aval : L.val);
+    // a level whose products do not read sliced-ELL values keeps only its
+    // CSR-ordered copy (level 1 applied through the grid blocks)
+    const bool csr = !fact && level >= 0 && !L.val;
+    const void* val = fact ? (level < 0 ? (const void*)ctx->Mh : L.kf)
+                           : (level < 0 ? (const void*)ctx->Aval : (csr ? L.vt : L.val));
     std::vector<int32_t> sl(L.A.nslices + 1), col(L.A.nslots);
-    std::vector<char> v(ts * 9 * (size_t)(fact ? L.A.nslices * SL : L.A.nslots));
+    std::vector<char> v(ts * 9 * (size_t)(fact ? L.A.nslices * SL : (csr ? L.nnzb : L.A.nslots)));
     HIPX(hipStreamSynchronize(ctx->st));
     HIPX(hipMemcpy(h_row_ptr, L.brp, sizeof(int32_t) * (L.A.n + 1), hipMemcpyDeviceToHost));
     HIPX(hipMemcpy(sl.data(), L.A.sl_ptr, sizeof(int32_t) * sl.size(), hipMemcpyDeviceToHost));
@@ -2153,6 +2185,8 @@ llg_status llg_get_level(llg_ctx* ctx, int32_t level, int32_t* h_row_ptr, int32_
               x = blk;
             else
               x = level < 0 ? id + (-(double)(len - 1)) * blk : id;
+          } else if (csr) {
+            x = rd(o * 9 + e);
           } else {
             x = rd(cb * 9 + (t * 9 + e) * SL + lane);
           }
@@ -2222,7 +2256,7 @@ llg_status llg_apply_A(llg_ctx* ctx, const double* d_x, double* d_y) {
 llg_status llg_set_kernel_timing(llg_ctx* ctx, int32_t kernel_class) {
   llg_status s = check_ctx(ctx);
   if (s != LLG_OK) return s;
-  if (kernel_class < LLG_KT_NONE || kernel_class > LLG_KT_ASSEMBLE) return LLG_ERR_INVALID_ARG;
+  if (kernel_class < LLG_KT_NONE || kernel_class > LLG_KT_LEVEL1) return LLG_ERR_INVALID_ARG;
   ctx->timed = kernel_class;
   return LLG_OK;
 }

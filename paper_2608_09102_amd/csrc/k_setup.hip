@@ -964,8 +964,8 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
 // slot-ordered copy (nine contiguous values) when there is one, else the
 // sliced-ELL values.
 template <typename T, bool FACT>
-__device__ inline void fine_block(const GalSrc<T>& g, int32_t i, int32_t j, int64_t fs, int fl, int64_t fb, int u,
-                                  double* f) {
+__device__ inline void fine_block(const GalSrc<T>& g, int32_t i, int32_t j, int64_t k, int64_t fs, int fl,
+                                  int64_t fb, int u, double* f) {
   if (FACT) {
     if (j == i) {
 #pragma unroll
@@ -979,9 +979,8 @@ __device__ inline void fine_block(const GalSrc<T>& g, int32_t i, int32_t j, int6
       for (int e = 0; e < 9; ++e) f[e] = (double)g.fk[kb + e * SL];
     }
   } else if (g.fvt) {
-    const int64_t slot = fb + (int64_t)u * SL + fl;
 #pragma unroll
-    for (int e = 0; e < 9; ++e) f[e] = (double)g.fvt[slot * 9 + e];
+    for (int e = 0; e < 9; ++e) f[e] = (double)g.fvt[k * 9 + e];
   } else {
     const int64_t vb = fb * 9 + (int64_t)u * 9 * SL + fl;
 #pragma unroll
@@ -1031,15 +1030,16 @@ __global__ void __launch_bounds__(TPB) k_galerkin_slices(int64_t nc, const int32
       const int32_t i = mem[q];
       const int64_t fs = i / SL;
       const int fl = i - (int)(fs * SL);
-      const int64_t fb = fsl[fs];
-      const int fw = (int)((fsl[fs + 1] - fb) / SL);
-      // four slots of the row at a time: their column and aggregate loads
-      // are in flight together; the blocks are still added in slot order
-      // (a row's padding slots, column -1, follow its blocks)
-      for (int u0 = 0; u0 < fw; u0 += 4) {
+      const int64_t fb = (FACT || g.fvt) ? 0 : fsl[fs];  // sliced fine values only
+      // the member's row in CSR order (contiguous columns and, on coarse
+      // levels, contiguous blocks), four at a time: their column and
+      // aggregate loads are in flight together; the blocks are still added
+      // in ascending column order
+      const int32_t k0 = g.frp[i], k1 = g.frp[i + 1];
+      for (int32_t kb = k0; kb < k1; kb += 4) {
         int32_t jj[4], aa[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) jj[k] = u0 + k < fw ? fcol[fb + (int64_t)(u0 + k) * SL + fl] : -1;
+        for (int k = 0; k < 4; ++k) jj[k] = kb + k < k1 ? g.fci[kb + k] : -1;
 #pragma unroll
         for (int k = 0; k < 4; ++k) aa[k] = jj[k] >= 0 ? agg[jj[k]] : -1;
 #pragma unroll
@@ -1049,14 +1049,13 @@ __global__ void __launch_bounds__(TPB) k_galerkin_slices(int64_t nc, const int32
           for (int h = 0; h < GC; ++h) hit = aa[k] >= 0 && aa[k] == J[h] ? h : hit;
           if (hit < 0) continue;
           double f[9];
-          fine_block<T, FACT>(g, i, jj[k], fs, fl, fb, u0 + k, f);
+          fine_block<T, FACT>(g, i, jj[k], kb + k, fs, fl, fb, kb + k - k0, f);
 #pragma unroll
           for (int h = 0; h < GC; ++h)
             if (h == hit)
 #pragma unroll
               for (int e = 0; e < 9; ++e) acc[h][e] += f[e];
         }
-        if (jj[3] < 0) break;
       }
     }
 #pragma unroll
@@ -1066,16 +1065,16 @@ __global__ void __launch_bounds__(TPB) k_galerkin_slices(int64_t nc, const int32
       const int64_t vb = cb * 9 + (int64_t)t * 9 * SL + l;
       T stv[9];
 #pragma unroll
-      for (int e = 0; e < 9; ++e) {
-        stv[e] = (T)acc[h][e];
-        cval[vb + e * SL] = stv[e];
+      for (int e = 0; e < 9; ++e) stv[e] = (T)acc[h][e];
+      if (cval) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) cval[vb + e * SL] = stv[e];
       }
       if (g.cvt) {
-        // slot-ordered copy for the next level's product (a wavefront's
-        // lanes hold consecutive slots: contiguous stores)
-        const int64_t slot = cb + (int64_t)t * SL + l;
+        // CSR-ordered copy for the next level's product, which walks member rows
+        const int64_t pos = (int64_t)g.crp[I] + t;
 #pragma unroll
-        for (int e = 0; e < 9; ++e) g.cvt[slot * 9 + e] = stv[e];
+        for (int e = 0; e < 9; ++e) g.cvt[pos * 9 + e] = stv[e];
       }
       if (J[h] == (int32_t)I) {
         double D[9], Di[9];
@@ -1125,14 +1124,13 @@ __global__ void k_galerkin_slots(int64_t nc, int64_t ns, const int32_t* __restri
     const int32_t i = mem[q];
     const int64_t fs = i / SL;
     const int fl = i - (int)(fs * SL);
-    const int64_t fb = fsl[fs];
-    const int fw = (int)((fsl[fs + 1] - fb) / SL);
-    for (int u = 0; u < fw; ++u) {
-      const int32_t j = fcol[fb + (int64_t)u * SL + fl];
-      if (j < 0) break;
+    const int64_t fb = (FACT || g.fvt) ? 0 : fsl[fs];  // sliced fine values only
+    const int32_t k0 = g.frp[i], k1 = g.frp[i + 1];
+    for (int32_t k = k0; k < k1; ++k) {
+      const int32_t j = g.fci[k];
       if (agg[j] != J) continue;
       double f[9];
-      fine_block<T, FACT>(g, i, j, fs, fl, fb, u, f);
+      fine_block<T, FACT>(g, i, j, k, fs, fl, fb, k - k0, f);
 #pragma unroll
       for (int e = 0; e < 9; ++e) acc[e] += f[e];
     }
@@ -1140,13 +1138,15 @@ __global__ void k_galerkin_slots(int64_t nc, int64_t ns, const int32_t* __restri
   const int64_t vb = cb * 9 + (int64_t)t * 9 * SL + l;
   T st[9];
 #pragma unroll
-  for (int e = 0; e < 9; ++e) {
-    st[e] = (T)acc[e];
-    cval[vb + e * SL] = st[e];
+  for (int e = 0; e < 9; ++e) st[e] = (T)acc[e];
+  if (cval) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) cval[vb + e * SL] = st[e];
   }
   if (g.cvt) {
+    const int64_t pos = (int64_t)g.crp[I] + t;
 #pragma unroll
-    for (int e = 0; e < 9; ++e) g.cvt[p * 9 + e] = st[e];
+    for (int e = 0; e < 9; ++e) g.cvt[pos * 9 + e] = st[e];
   }
   if (J == (int32_t)I) {
     double D[9], Di[9];

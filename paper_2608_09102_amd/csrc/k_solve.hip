@@ -2040,13 +2040,13 @@ void launch_member_fields(hipStream_t st, int64_t n, const int32_t* mem, const d
 template <typename T>
 void launch_l1(hipStream_t st, GridDims g, int mode, int xzero, int64_t n1, const int32_t* mptr, const int32_t* nagg,
                const double* mtq, const T* x, const T* b, const T* dinv1, const int32_t* agg2, const T* ec,
-               double omega, T* out, const T* d1, const T* d2, double* part) {
+               double omega, T* out, const T* d1, const T* d2, double* part, hipEvent_t e0, hipEvent_t e1) {
   if (n1 <= 0) return;
   const dim3 gr(nblk(n1 * L1_G)), t(TPB);
   const T om = (T)omega;
-#define LLG_L1(D, M, XZ, ND)                                                                                     \
-  hipLaunchKernelGGL((k_l1<D, T, M, XZ, ND>), gr, t, 0, st, g, n1, mptr, nagg, mtq, x, b, dinv1, agg2, ec, om, out, \
-                     d1, d2, part)
+#define LLG_L1(D, M, XZ, ND)                                                                                      \
+  hipExtLaunchKernelGGL((k_l1<D, T, M, XZ, ND>), gr, t, 0, st, e0, e1, 0, g, n1, mptr, nagg, mtq, x, b, dinv1, agg2, \
+                        ec, om, out, d1, d2, part)
 #define LLG_L1D(D)                                 \
   if (mode == 0) LLG_L1(D, 0, false, 0);           \
   else if (mode == 1 && xzero) LLG_L1(D, 1, true, 0); \
@@ -2063,10 +2063,12 @@ void launch_l1(hipStream_t st, GridDims g, int mode, int xzero, int64_t n1, cons
 }
 template void launch_l1<double>(hipStream_t, GridDims, int, int, int64_t, const int32_t*, const int32_t*,
                                 const double*, const double*, const double*, const double*, const int32_t*,
-                                const double*, double, double*, const double*, const double*, double*);
+                                const double*, double, double*, const double*, const double*, double*, hipEvent_t,
+                                hipEvent_t);
 template void launch_l1<float>(hipStream_t, GridDims, int, int, int64_t, const int32_t*, const int32_t*,
                                const double*, const float*, const float*, const float*, const int32_t*, const float*,
-                               double, float*, const float*, const float*, double*);
+                               double, float*, const float*, const float*, double*, hipEvent_t,
+                               hipEvent_t);
 #define LLG_INST_K(T)                                                                                    \
   template void launch_spmv_dots<T>(hipStream_t, Sell, const T*, const T*, T*, const T*, const T*, double*, int); \
   template void launch_kc_update<T>(hipStream_t, int64_t, const T*, const T*, const double*, T*, const T*, \

@@ -250,11 +250,14 @@ void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, cons
 // in slot order.
 template <typename T>
 struct GalSrc {
-  const T* fval = nullptr;
-  const T* fvt = nullptr;
+  const T* fval = nullptr;     // fine blocks, sliced ELL (the grid level stored as BSR)
+  const T* fvt = nullptr;      // fine blocks in the fine level's CSR order (coarse levels)
   const T* fk = nullptr;
   const T* knm = nullptr;
-  T* cvt = nullptr;
+  const int32_t* frp = nullptr;  // fine CSR pattern: row pointers and ascending columns
+  const int32_t* fci = nullptr;
+  T* cvt = nullptr;            // coarse blocks in the coarse level's CSR order (for the next product)
+  const int32_t* crp = nullptr;  // coarse CSR row pointers (positions of cvt)
 };
 // Galerkin block sums P^T A P and the inverse diagonal blocks of the result
 template <typename T>
@@ -378,7 +381,8 @@ void launch_member_fields(hipStream_t st, int64_t n, const int32_t* mem, const d
 template <typename T>
 void launch_l1(hipStream_t st, GridDims g, int mode, int xzero, int64_t n1, const int32_t* mptr, const int32_t* nagg,
                const double* mtq, const T* x, const T* b, const T* dinv1, const int32_t* agg2, const T* ec,
-               double omega, T* out, const T* d1, const T* d2, double* part);
+               double omega, T* out, const T* d1, const T* d2, double* part, hipEvent_t e0 = nullptr,
+               hipEvent_t e1 = nullptr);
 // nagg[q][t]: level-1 aggregate of the t-th grid neighbour of member q ([slice][6][64], -1 if missing)
 void launch_member_nbr_aggs(hipStream_t st, GridDims g, const int32_t* mem, const int32_t* agg, int32_t* nagg);
 template <typename TZ>
