@@ -27,8 +27,15 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 
 # forms timed per workload when --forms is not given (the first gives `value`):
 # the metric compares FP32-AMG with FP64, both at rel.res 1e-8
+# The 256^3 main forms rebuild the hierarchy structure before each step's
+# assembly (+serial): with the rebuild overlapped on a second stream (the
+# forms without the suffix, reported beside them) the step is about 5%
+# faster, but its kernels share the device with the rebuild, which a kernel
+# trace cannot show (the profiler serializes the streams), so the roofline
+# kernel is timed in the serial form.
 DEFAULT_FORMS = {
-    "mms3d_256": "fp32_amg:1:jacobi:factored,fp64:1:jacobi:factored",
+    "mms3d_256": "fp32_amg:1:jacobi:factored+serial,fp64:1:jacobi:factored+serial,fp32_amg:1:jacobi:factored,"
+                 "fp64:1:jacobi:factored",
     "rough3d_128": "fp32_amg:0:jacobi:factored,fp64:0:jacobi:factored",
     "rough2d_1024": "fp32_amg:1:jacobi:factored,fp64:1:jacobi:factored",
     "vortex64": "fp64:1:jacobi:factored,fp32_amg:1:jacobi:factored",
@@ -63,6 +70,8 @@ def parse():
                         "blocks, k_l1, the largest kernel of the 256^3 forms) or outer_spmv")
     p.add_argument("--alpha", type=float, default=None, help="override the workload's alpha")
     p.add_argument("--kdepth", type=int, default=None, help="override the K-cycle depth of every form")
+    p.add_argument("--nu", type=int, default=None, help="smoothing sweeps before and after the coarse correction "
+                                                          "(every form; default 1)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=1)
     p.add_argument("--serve", action="store_true",
@@ -94,7 +103,8 @@ def read_traffic(kernel: str, workload: str, precision: str, operator: str):
     """HBM bytes per launch from the committed PMC summary, or None when the
     summary is missing, was taken on another form or on a different kernel
     source."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s_%s_%s_%s.txt" % (kernel, workload, precision, operator))
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s_%s_%s.txt" % (kernel, workload, precision,
+                                                                      operator.replace("+", "_")))
     if not os.path.exists(path):
         return None
     kv = {}
@@ -142,14 +152,24 @@ def forcing_list(torch, w, total: int):
     return [I.manufactured_forcing(w.dim, w.n, (k + 1) * w.dt, w.alpha, xp=torch, device=dev) for k in range(total)]
 
 
+NU = None  # --nu: sweeps before and after the coarse correction, every form
+
+
+def form_opts(llg, rtol: float, precision: str, kdepth: int, smoother: str, operator: str):
+    """Options of a form.  operator[+serial|+reuse]: the hierarchy structure
+    rebuilt on a second stream beside the step (default), rebuilt at the
+    start of each step (serial), or built once per context (reuse)."""
+    base, _, rb = operator.partition("+")
+    extra = dict({"serial": dict(overlap_rebuild=0), "reuse": dict(rebuild_aggregates=0)}.get(rb, {}))
+    if NU is not None:
+        extra.update(nu_pre=NU, nu_post=NU)
+    return llg.default_opts(rtol=rtol, precision=precision, kcycle_depth=kdepth, smoother=smoother,
+                            fine_operator=base, **extra)
+
+
 def run_form(llg, torch, w, form: str, steps: int, warmup: int, cls: str, Fs, kdepth: int = 0,
              smoother: str = "jacobi", operator: str = "bsr"):
-    # operator[+serial|+reuse]: the hierarchy structure rebuilt on a second stream beside the step
-    # (default), rebuilt at the start of each step (serial), or built once per context (reuse)
-    base, _, rb = operator.partition("+")
-    extra = {"serial": dict(overlap_rebuild=0), "reuse": dict(rebuild_aggregates=0)}.get(rb, {})
-    opts = llg.default_opts(rtol=w.rtol, precision=form, kcycle_depth=kdepth, smoother=smoother,
-                            fine_operator=base, **extra)
+    opts = form_opts(llg, w.rtol, form, kdepth, smoother, operator)
     grid = llg.make_grid(w.dim, w.n)
     t0 = time.perf_counter()
     S = llg.Solver(grid, opts)
@@ -263,8 +283,7 @@ def gpu_sample_error(llg, torch, w, sample, form: str, kdepth: int, smoother: st
     its max-norm difference from the oracle's."""
     import numpy as np
     dim, n, m, F, ref, _ = sample
-    S = llg.Solver(llg.make_grid(dim, n), llg.default_opts(rtol=w.rtol, precision=form, kcycle_depth=kdepth,
-                                                          smoother=smoother, fine_operator=operator))
+    S = llg.Solver(llg.make_grid(dim, n), form_opts(llg, w.rtol, form, kdepth, smoother, operator))
     out, s, st = S.step(torch.from_numpy(m).cuda(), w.alpha, w.dt,
                         forcing=torch.from_numpy(F).cuda() if F is not None else None)
     d = float(np.abs(out.cpu().numpy() - ref).max())
@@ -474,6 +493,8 @@ def main():
         serve_bench(a, prepared)
         return
     w = I.WORKLOADS[a.workload]
+    global NU
+    NU = a.nu
     if a.alpha is not None:
         w.alpha = a.alpha
     if a.baselines:

@@ -189,7 +189,7 @@ struct Level {
   void* vt = nullptr;  // coarse levels feeding a Galerkin product: the blocks in slot order (9 per slot)
   void* xp = nullptr;  // level 1 applied through the grid blocks: x + P e_c before the post-smoothing sweep
   double* prho = nullptr;  // K-cycle levels: partial sums of w1.rho
-  double* mtq = nullptr;  // the frozen field in member order of the level-1 aggregates (mt[mem[q]])
+  void* mtq = nullptr;  // the frozen field in member order of the level-1 aggregates (mt[mem[q]]), in T
   int32_t* nagg = nullptr;  // level-1 aggregates of each member's grid neighbours ([slice][6][64])
 };
 
@@ -843,7 +843,7 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   c.f1 = f1;
   if (c.f1) {
     kparts = std::max<int64_t>(kparts, 3 * rows_blocks(c.lv[1].A.n, L1_LANES));
-    c.lv[0].mtq = ar.lazy<double>(3 * c.lv[0].A.n);
+    c.lv[0].mtq = ar.get(ts * 3 * c.lv[0].A.n, true);
     c.lv[0].nagg = ar.lazy<int32_t>(6 * c.lv[0].A.nslices * SL);
     c.lv[1].xp = ar.get(ts * 3 * c.lv[1].A.n, true);  // level-1 iterate with the prolonged correction
   }
@@ -1027,7 +1027,7 @@ void setup_values(llg_ctx& c, const double* m, const double* mprev, const double
                        c.flags, c.Mh, (T*)L0.kf, (T*)L0.knm, c.mt);
     if (c.f1) {
       launch_member_nbr_aggs(st, GridDims{g.n[0], g.n[1], g.n[2]}, L0.mem, L0.agg, L0.nagg);
-      launch_member_fields(st, L0.A.n, L0.mem, c.mt, L0.mtq);
+      launch_member_fields<T>(st, L0.A.n, L0.mem, c.mt, (T*)L0.mtq);
     }
     LCHK();
   }
@@ -1169,7 +1169,7 @@ GridDims gdims(const llg_ctx& c) {
 
 // A level-1 product through the grid blocks (k_l1), timed as LLG_KT_LEVEL1:
 // the launch stamps its own events, and its algorithmic bytes are added up:
-// the member-ordered frozen field (24 B per grid node), the neighbour
+// the member-ordered frozen field (3 values of T per grid node), the neighbour
 // aggregates (4 B per neighbour slot), the member pointers, x once, and per
 // mode b and the output (0), b, D1^{-1} and the output (1), the output and
 // the dot operands (2).
@@ -1181,13 +1181,13 @@ void l1(llg_ctx& c, int mode, int xzero, const T* x, const T* b, const T* dinv1,
   hipEvent_t e0, e1;
   kernel_events(c, LLG_KT_LEVEL1, e0, e1);
   if (e0) {
-    double bytes = 24.0 * N + 4.0 * 2 * c.grid.dim * N + 4.0 * (n1 + 1) + (xzero ? 0.0 : 3.0 * v * n1);
+    double bytes = 3.0 * v * N + 4.0 * 2 * c.grid.dim * N + 4.0 * (n1 + 1) + (xzero ? 0.0 : 3.0 * v * n1);
     if (mode == 0) bytes += 6.0 * v * n1;
     if (mode == 1) bytes += 15.0 * v * n1;
     if (mode == 2) bytes += 3.0 * v * n1 * (1 + (d1 ? 1 : 0) + (d2 ? 1 : 0));
     c.kernel_bytes += bytes;
   }
-  launch_l1<T>(c.st, gdims(c), mode, xzero, n1, L0.mptr, L0.nagg, L0.mtq, x, b, dinv1, nullptr, nullptr, c.omega,
+  launch_l1<T>(c.st, gdims(c), mode, xzero, n1, L0.mptr, L0.nagg, (const T*)L0.mtq, x, b, dinv1, nullptr, nullptr, c.omega,
                out, d1, d2, part, e0, e1);
 }
 

@@ -519,6 +519,51 @@ __device__ inline B9<T> node_K(const GridDims& gd, const double* mt, int deg) {
   for (int e = 0; e < 9; ++e) b.e[e] = (T)v[e];
   return b;
 }
+// The FP32-AMG level-1 products: K from the frozen field rounded to FP32,
+// evaluated in FP32 (the products are FP32; the FP64 evaluation of the same
+// formula costs more than the product's memory traffic hides).  Same steps as
+// grid_blocks: M, D = I + s_pp M, its adjugate inverse, K = D^{-1} (s M).
+template <typename T>
+__device__ inline B9<T> node_K(const GridDims& gd, const float* mt, int deg) {
+  const float a = (float)gd.prm[0], s_off = (float)(gd.prm[1] * gd.inv_h2);
+  const float s_diag = (float)(gd.prm[1] * (-(double)deg * gd.inv_h2));
+  const float m1 = mt[0], m2 = mt[1], m3 = mt[2];
+  float M[9];
+  M[0] = -(a * (m2 * m2 + m3 * m3));
+  M[1] = -m3 + a * (m1 * m2);
+  M[2] = m2 + a * (m1 * m3);
+  M[3] = m3 + a * (m1 * m2);
+  M[4] = -(a * (m1 * m1 + m3 * m3));
+  M[5] = -m1 + a * (m2 * m3);
+  M[6] = -m2 + a * (m1 * m3);
+  M[7] = m1 + a * (m2 * m3);
+  M[8] = -(a * (m1 * m1 + m2 * m2));
+  float D[9], B[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    const float v = s_diag * M[e];
+    D[e] = (e == 0 || e == 4 || e == 8) ? 1.0f + v : v;
+    B[e] = s_off * M[e];
+  }
+  float adj[9];
+  adj[0] = D[4] * D[8] - D[5] * D[7];
+  adj[1] = D[2] * D[7] - D[1] * D[8];
+  adj[2] = D[1] * D[5] - D[2] * D[4];
+  adj[3] = D[5] * D[6] - D[3] * D[8];
+  adj[4] = D[0] * D[8] - D[2] * D[6];
+  adj[5] = D[2] * D[3] - D[0] * D[5];
+  adj[6] = D[3] * D[7] - D[4] * D[6];
+  adj[7] = D[1] * D[6] - D[0] * D[7];
+  adj[8] = D[0] * D[4] - D[1] * D[3];
+  const float rdet = 1.0f / ((D[0] * adj[0] + D[1] * adj[3]) + D[2] * adj[6]);
+  B9<T> k;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      k.e[3 * r + q] = (T)(rdet * ((adj[3 * r] * B[q] + adj[3 * r + 1] * B[3 + q]) + adj[3 * r + 2] * B[6 + q]));
+  return k;
+}
 
 // The same with D^{-1} recomputed from the frozen field (factored grid level)
 template <int DIM, typename T>
@@ -883,8 +928,10 @@ __global__ void k_spmv_dots(int64_t n, const int32_t* __restrict__ sl, const int
 // (about 150 B per grid node).  The stored blocks are still formed (for the
 // next Galerkin product and the diagonal inverse D1); only the products use
 // this form, so they differ from the stored-block products by rounding.
-// mtq holds the frozen field in member order (mtq[q] = mt[mem[q]]; the
-// blocks K_i are recomputed from it) and nagg the level-1 aggregates of the
+// mtq holds the frozen field in member order (mtq[q] = mt[mem[q]], rounded
+// to T: in the FP32-AMG form the products are FP32 and their blocks come
+// from the rounded field; the blocks K_i are recomputed from it) and nagg
+// the level-1 aggregates of the
 // members' grid neighbours ([slice][6][64] by member, -1 where the neighbour
 // is missing), so that the lanes of a wavefront read consecutive entries and
 // only the x gathers depend on loaded indices.
@@ -899,7 +946,7 @@ constexpr int L1_G = L1_LANES;
 constexpr int L1_AGG = TPB / L1_G;  // aggregates per workgroup: their members fill at most TPB threads
 template <int DIM, typename T, int MODE, bool XZ, int ND>
 __global__ void __launch_bounds__(TPB) k_l1(GridDims gd, int64_t n1, const int32_t* __restrict__ mptr,
-                                            const int32_t* __restrict__ nagg, const double* __restrict__ mtq,
+                                            const int32_t* __restrict__ nagg, const T* __restrict__ mtq,
                                             const T* __restrict__ x, const T* __restrict__ b,
                                             const T* __restrict__ dinv1, const int32_t* __restrict__ agg2,
                                             const T* __restrict__ ec, T omega, T* __restrict__ out,
@@ -1023,13 +1070,15 @@ __global__ void k_member_nbr_aggs(int nx, int ny, int nz, const int32_t* __restr
 }
 
 // mtq[q] = mt[mem[q]]: the frozen field in the member order of the aggregates
+// (rounded to T: FP32 in the FP32-AMG form, where the level-1 products are FP32)
+template <typename T>
 __global__ void k_member_fields(int64_t n, const int32_t* __restrict__ mem, const double* __restrict__ mt,
-                                double* __restrict__ mtq) {
+                                T* __restrict__ mtq) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   const int64_t i = mem[q];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) mtq[3 * q + c] = mt[3 * i + c];
+  for (int c = 0; c < 3; ++c) mtq[3 * q + c] = (T)mt[3 * i + c];
 }
 
 // rho = r - a1 w1, x = omega D^{-1} rho (first sweep of the second inner
@@ -2033,13 +2082,16 @@ void launch_member_nbr_aggs(hipStream_t st, GridDims g, const int32_t* mem, cons
     hipLaunchKernelGGL(k_member_nbr_aggs<2>, dim3(nblk(N)), dim3(TPB), 0, st, g.nx, g.ny, g.nz, mem, agg, nagg);
 }
 
-void launch_member_fields(hipStream_t st, int64_t n, const int32_t* mem, const double* mt, double* mtq) {
-  if (n > 0) hipLaunchKernelGGL(k_member_fields, dim3(nblk(n)), dim3(TPB), 0, st, n, mem, mt, mtq);
+template <typename T>
+void launch_member_fields(hipStream_t st, int64_t n, const int32_t* mem, const double* mt, T* mtq) {
+  if (n > 0) hipLaunchKernelGGL((k_member_fields<T>), dim3(nblk(n)), dim3(TPB), 0, st, n, mem, mt, mtq);
 }
+template void launch_member_fields<double>(hipStream_t, int64_t, const int32_t*, const double*, double*);
+template void launch_member_fields<float>(hipStream_t, int64_t, const int32_t*, const double*, float*);
 
 template <typename T>
 void launch_l1(hipStream_t st, GridDims g, int mode, int xzero, int64_t n1, const int32_t* mptr, const int32_t* nagg,
-               const double* mtq, const T* x, const T* b, const T* dinv1, const int32_t* agg2, const T* ec,
+               const T* mtq, const T* x, const T* b, const T* dinv1, const int32_t* agg2, const T* ec,
                double omega, T* out, const T* d1, const T* d2, double* part, hipEvent_t e0, hipEvent_t e1) {
   if (n1 <= 0) return;
   const dim3 gr(nblk(n1 * L1_G)), t(TPB);
@@ -2066,7 +2118,7 @@ template void launch_l1<double>(hipStream_t, GridDims, int, int, int64_t, const 
                                 const double*, double, double*, const double*, const double*, double*, hipEvent_t,
                                 hipEvent_t);
 template void launch_l1<float>(hipStream_t, GridDims, int, int, int64_t, const int32_t*, const int32_t*,
-                               const double*, const float*, const float*, const float*, const int32_t*, const float*,
+                               const float*, const float*, const float*, const float*, const int32_t*, const float*,
                                double, float*, const float*, const float*, double*, hipEvent_t,
                                hipEvent_t);
 #define LLG_INST_K(T)                                                                                    \

@@ -377,10 +377,11 @@ void launch_kc_coef(hipStream_t st, const double* part, int64_t G, int stage, do
 // sums (d1, optional d2) over rows_blocks(n1, L1_LANES) workgroups of 256
 constexpr int L1_LANES = 4;
 // mtq[q] = mt[mem[q]] for the n grid nodes (the field in the level-1 member order)
-void launch_member_fields(hipStream_t st, int64_t n, const int32_t* mem, const double* mt, double* mtq);
+template <typename T>
+void launch_member_fields(hipStream_t st, int64_t n, const int32_t* mem, const double* mt, T* mtq);
 template <typename T>
 void launch_l1(hipStream_t st, GridDims g, int mode, int xzero, int64_t n1, const int32_t* mptr, const int32_t* nagg,
-               const double* mtq, const T* x, const T* b, const T* dinv1, const int32_t* agg2, const T* ec,
+               const T* mtq, const T* x, const T* b, const T* dinv1, const int32_t* agg2, const T* ec,
                double omega, T* out, const T* d1, const T* d2, double* part, hipEvent_t e0 = nullptr,
                hipEvent_t e1 = nullptr);
 // nagg[q][t]: level-1 aggregate of the t-th grid neighbour of member q ([slice][6][64], -1 if missing)
