@@ -85,6 +85,8 @@ struct Arena {
   hipStream_t st = nullptr;
   int32_t* flag = nullptr;        // REPLAY: mismatch flag
   int flag_word = 0;              // word of the flags the checks raise (1: a rebuild on the second stream)
+  bool keep_grid = false;         // REPLAY of a step: the grid graph and the grid level's pattern (field and
+                                  // aggregation independent) are already in place; skip their kernels
   int32_t* hcount = nullptr;      // PLAN: pinned read-back slot
 
   void* get(size_t bytes, bool lazy) {
@@ -390,27 +392,29 @@ void sync(llg_ctx& c) {
 }
 
 // ------------------------------------------------------------------ structure
-void build_sell(Arena& ar, hipStream_t st, Level& L, int64_t n, int64_t gnnz) {
+// build: false when the pattern is already in place (the grid level on a
+// step's replay): the buffers are requested and the counts taken, no kernel runs
+void build_sell(Arena& ar, hipStream_t st, Level& L, int64_t n, int64_t gnnz, bool build = true) {
   L.A.n = n;
   L.A.nslices = ceil_div(n, SL);
   L.brp = ar.alloc<int32_t>(n + 1);
-  launch_pattern_rp(st, n, L.grp, L.brp);
+  if (build) launch_pattern_rp(st, n, L.grp, L.brp);
   LCHK();
   L.nnzb = gnnz + n;
   L.bci = ar.alloc<int32_t>(L.nnzb);
-  launch_pattern_cols(st, n, L.grp, L.gci, L.brp, L.bci);
+  if (build) launch_pattern_cols(st, n, L.grp, L.gci, L.brp, L.bci);
   LCHK();
   L.A.sl_ptr = ar.alloc<int32_t>(L.A.nslices + 1);
-  launch_slice_width(st, n, nullptr, L.brp, L.A.sl_ptr);
+  if (build) launch_slice_width(st, n, nullptr, L.brp, L.A.sl_ptr);
   LCHK();
 }
 
-void finish_sell(Arena& ar, hipStream_t st, Level& L, int32_t* scan_tmp) {
-  launch_scan_excl(st, L.A.sl_ptr, L.A.sl_ptr, L.A.nslices, L.A.sl_ptr + L.A.nslices, scan_tmp);
+void finish_sell(Arena& ar, hipStream_t st, Level& L, int32_t* scan_tmp, bool build = true) {
+  if (build) launch_scan_excl(st, L.A.sl_ptr, L.A.sl_ptr, L.A.nslices, L.A.sl_ptr + L.A.nslices, scan_tmp);
   LCHK();
   L.A.nslots = ar.count(L.A.sl_ptr + L.A.nslices);
   L.A.col = ar.alloc<int32_t>(L.A.nslots);
-  launch_sell_cols(st, L.A.n, nullptr, L.brp, L.bci, L.A.sl_ptr, L.A.col);
+  if (build) launch_sell_cols(st, L.A.n, nullptr, L.brp, L.bci, L.A.sl_ptr, L.A.col);
   LCHK();
 }
 
@@ -509,18 +513,23 @@ int build_structure(llg_ctx& c, Arena& ar) {
   }
   ar.flag = c.flags + ar.flag_word;
   Level& L0 = c.lv[0];
+  const bool grid = !ar.keep_grid;  // build the grid graph and the grid level's pattern
   L0.grp = ar.alloc<int32_t>(N + 1);
-  launch_grid_degree(st, nx, ny, nz, L0.grp);
-  LCHK();
-  launch_scan_excl(st, L0.grp, L0.grp, N, L0.grp + N, c.scan_tmp);
-  LCHK();
+  if (grid) {
+    launch_grid_degree(st, nx, ny, nz, L0.grp);
+    LCHK();
+    launch_scan_excl(st, L0.grp, L0.grp, N, L0.grp + N, c.scan_tmp);
+    LCHK();
+  }
   L0.gnnz = ar.count(L0.grp + N);
   L0.gci = ar.alloc<int32_t>(L0.gnnz);
   L0.gw = ar.alloc<int32_t>(L0.gnnz);
-  launch_grid_graph(st, nx, ny, nz, L0.grp, L0.gci, L0.gw);
-  LCHK();
-  build_sell(ar, st, L0, N, L0.gnnz);
-  finish_sell(ar, st, L0, c.scan_tmp);
+  if (grid) {
+    launch_grid_graph(st, nx, ny, nz, L0.grp, L0.gci, L0.gw);
+    LCHK();
+  }
+  build_sell(ar, st, L0, N, L0.gnnz, grid);
+  finish_sell(ar, st, L0, c.scan_tmp, grid);
 
   int l = 0;
   for (;; ++l) {
@@ -985,6 +994,7 @@ void rebuild_overlapped(llg_ctx& c) {
   ar.ptrs = nxt == 0 ? &c.ptrs : &c.ptrs2;
   ar.st = c.aux;
   ar.flag_word = 1;
+  ar.keep_grid = true;
   try {
     (void)build_structure(c, ar);
   } catch (...) {
@@ -1017,6 +1027,7 @@ void setup_values(llg_ctx& c, const double* m, const double* mprev, const double
     ar.first = false;
     ar.ptrs = &c.ptrs;
     ar.st = st;
+    ar.keep_grid = true;
     (void)build_structure(c, ar);
   }
   Level& L0 = c.lv[0];
