@@ -156,11 +156,16 @@ NU = None  # --nu: sweeps before and after the coarse correction, every form
 
 
 def form_opts(llg, rtol: float, precision: str, kdepth: int, smoother: str, operator: str):
-    """Options of a form.  operator[+serial|+reuse]: the hierarchy structure
-    rebuilt on a second stream beside the step (default), rebuilt at the
-    start of each step (serial), or built once per context (reuse)."""
-    base, _, rb = operator.partition("+")
-    extra = dict({"serial": dict(overlap_rebuild=0), "reuse": dict(rebuild_aggregates=0)}.get(rb, {}))
+    """Options of a form.  operator[+serial|+reuse][+sliced]: the hierarchy
+    structure rebuilt on a second stream beside the step (default), rebuilt
+    at the start of each step (serial), or built once per context (reuse);
+    +sliced: the large coarse levels' products on sliced-ELL values instead
+    of the CSR-ordered blocks."""
+    base, *mods = operator.split("+")
+    extra = {}
+    for rb in mods:
+        extra.update({"serial": dict(overlap_rebuild=0), "reuse": dict(rebuild_aggregates=0),
+                      "sliced": dict(csr_levels=0)}[rb])
     if NU is not None:
         extra.update(nu_pre=NU, nu_post=NU)
     return llg.default_opts(rtol=rtol, precision=precision, kcycle_depth=kdepth, smoother=smoother,

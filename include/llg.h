@@ -177,6 +177,10 @@ typedef struct {
                            still returns when its own step is complete; the rebuild may still
                            run then, and llg_destroy waits for it.  0: each step rebuilds
                            the structure before its assembly, on the context's stream */
+  int32_t csr_levels;   /* 1: the row products of the large coarse levels (at least 32768 nodes,
+                           block-Jacobi cycles, below the K-cycle levels, not the coarsest) read
+                           the blocks in CSR order, the copy the next Galerkin product reads,
+                           and no sliced-ELL values are kept for them; 0: sliced-ELL values */
 } llg_opts;
 
 typedef struct {
@@ -215,7 +219,7 @@ typedef enum {
  * max_dense 512, left_scale 1, project 1, x0_is_mn 1, salt 0, rebuild 1,
  * K-cycle depth 0, graphs 0, Jacobi, BDF1, BSR grid level, DCGS2, FGMRES with
  * the AMG cycle, no stray-field workspace, tail_nodes 128, pipeline 1,
- * overlap_rebuild 1. */
+ * overlap_rebuild 1, csr_levels 1. */
 void llg_default_opts(llg_opts* opts);
 
 /* Exact device bytes a context for (grid, opts) needs.  Runs the aggregation

@@ -55,7 +55,7 @@ class Opts(ctypes.Structure):
         ("graphs", ctypes.c_int32), ("smoother", ctypes.c_int32), ("scheme", ctypes.c_int32),
         ("fine_operator", ctypes.c_int32), ("arnoldi", ctypes.c_int32), ("krylov", ctypes.c_int32),
         ("stray_field", ctypes.c_int32), ("tail_nodes", ctypes.c_int32),
-        ("pipeline", ctypes.c_int32), ("overlap_rebuild", ctypes.c_int32),
+        ("pipeline", ctypes.c_int32), ("overlap_rebuild", ctypes.c_int32), ("csr_levels", ctypes.c_int32),
     ]
 
 

@@ -173,6 +173,7 @@ struct Level {
   void* dinv = nullptr;
   bool unit = false;
   int G = 1;  // lanes per row in the level's sliced-ELL kernels
+  bool csr = false;  // row products on the CSR-ordered copy vt (no sliced-ELL values)
   void *b = nullptr, *x = nullptr, *r = nullptr, *e = nullptr, *xo = nullptr;
   // K-cycle work vectors and coefficients (levels 1..kcycle_depth)
   void *v1 = nullptr, *v2 = nullptr, *w1 = nullptr, *w2 = nullptr, *rho = nullptr;
@@ -238,7 +239,7 @@ PlanKey plan_key(const llg_grid& g, const llg_opts& o) {
   k.k = std::make_tuple(g.dim, g.n[0], g.n[1], g.n[2], o.npass, o.beta_num, o.beta_den, o.max_coarse,
                         o.stagnation, o.max_levels, o.max_dense, o.agg_salt, o.precision, o.restart,
                         o.left_scale, o.kcycle_depth, o.smoother, o.scheme, o.fine_operator, o.krylov,
-                        o.stray_field * 2 + (overlapped_rebuild(o) ? 1 : 0));
+                        o.stray_field * 4 + o.csr_levels * 2 + (overlapped_rebuild(o) ? 1 : 0));
   return k;
 }
 
@@ -795,9 +796,14 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   for (int l = 0; l < c.L; ++l) {
     Level& L = c.lv[l];
     const int64_t n = L.A.n;
+    // the large coarse levels below the K-cycle levels apply their rows from
+    // the CSR-ordered copy (block-Jacobi cycles; not the coarsest level)
+    L.csr = c.opts.csr_levels && l >= 1 && !(l == 1 && f1) && l > c.opts.kcycle_depth && l + 1 < c.L &&
+            n >= 32768 && c.opts.smoother == LLG_SMOOTHER_JACOBI;
     // sliced-ELL values, except where no product reads them: the factored
-    // grid level, and level 1 when it is applied through the grid blocks
-    if (!(l == 0 && c.fact) && !(l == 1 && f1)) L.val = ar.get(ts * 9 * L.A.nslots, true);
+    // grid level, level 1 when it is applied through the grid blocks, and
+    // the levels applied from the CSR-ordered copy
+    if (!(l == 0 && c.fact) && !(l == 1 && f1) && !L.csr) L.val = ar.get(ts * 9 * L.A.nslots, true);
     // the next level's Galerkin product walks the member rows of this level
     // and reads their blocks in CSR order (contiguous per row; the sliced-ELL
     // layout spreads a row over 64-slot strides and a block over nine lines)
@@ -810,6 +816,7 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
     L.r = ar.get(ts * 3 * n, true);
     L.e = ar.get(ts * 3 * n, true);
     L.xo = ar.get(ts * 3 * n, true);
+    if (L.csr) L.xp = ar.get(ts * 3 * n, true);  // the iterate with the prolonged correction
     L.cval.assign(L.ncol, nullptr);
     L.cdinv.assign(L.ncol, nullptr);
     for (int q = 0; q < L.ncol; ++q) {
@@ -911,7 +918,8 @@ bool opts_ok(const llg_opts* o) {
          (o->krylov == LLG_KRYLOV_FGMRES_AMG || o->krylov == LLG_KRYLOV_GMRES || o->krylov == LLG_KRYLOV_BICGSTAB ||
           o->krylov == LLG_KRYLOV_TFQMR) &&
          (o->stray_field == 0 || o->stray_field == 1) && o->tail_nodes >= 0 &&
-         (o->pipeline == 0 || o->pipeline == 1) && (o->overlap_rebuild == 0 || o->overlap_rebuild == 1);
+         (o->pipeline == 0 || o->pipeline == 1) && (o->overlap_rebuild == 0 || o->overlap_rebuild == 1) &&
+         (o->csr_levels == 0 || o->csr_levels == 1);
 }
 
 // Plan for (grid, opts): cached; computed on the current device.
@@ -1211,6 +1219,8 @@ void lvl_residual(llg_ctx& c, int l, int xmode, const T* b, const T* x, T* r) {
   }
   if (l == 0 && c.fact)
     launch_fact_residual<T>(c.st, gdims(c), xmode, c.omega, b, x, r);
+  else if (L.csr)
+    launch_residual_csr<T>(c.st, L.A.n, L.brp, L.bci, (const T*)L.vt, xmode, c.omega, b, x, r);
   else
     launch_residual<T>(c.st, L.A, (const T*)L.val, xmode, c.omega, b, x, r, L.G);
 }
@@ -1232,11 +1242,20 @@ void lvl_post_smooth(llg_ctx& c, int l, int xmode, const T* b, const T* x, const
     l1<T>(c, 1, xmode == 2, x, b, (const T*)L.dinv, out, nullptr, nullptr, nullptr);
     return;
   }
-  if (l == 0 && c.fact)
+  if (l == 0 && c.fact) {
     launch_fact_post_smooth<T>(c.st, gdims(c), xmode, c.omega, b, x, agg, ec, out);
-  else
+  } else if (L.csr) {
+    if (ec) {  // the prolongation in its own pass, as on level 1
+      launch_prolong<T>(c.st, L.A.n, xmode, c.omega, b, x, agg, ec, (T*)L.xp);
+      x = (const T*)L.xp;
+      xmode = 0;
+    }
+    launch_post_smooth_csr<T>(c.st, L.A.n, L.brp, L.bci, (const T*)L.vt, (const T*)L.dinv, xmode, c.omega, b, x,
+                              out);
+  } else {
     launch_post_smooth<T>(c.st, L.A, (const T*)L.val, (const T*)L.dinv, L.unit, xmode, c.omega, b, x, agg, ec, out,
                           L.G);
+  }
 }
 
 // e0, e1: events the launch itself stamps at the kernel's start and end
@@ -1884,6 +1903,7 @@ void llg_default_opts(llg_opts* o) {
   o->tail_nodes = 128;
   o->pipeline = 1;
   o->overlap_rebuild = 1;
+  o->csr_levels = 1;
 }
 
 // combinations the library does not implement

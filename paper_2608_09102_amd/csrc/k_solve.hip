@@ -254,6 +254,78 @@ __global__ void k_post_smooth(int64_t n, const int32_t* __restrict__ sl, const i
   st3(out, p.i, V3<T>{xi.x + omega * res.x, xi.y + omega * res.y, xi.z + omega * res.z});
 }
 
+// ------------------------------------------------ CSR-ordered large levels
+// A coarse level that feeds a Galerkin product also keeps its blocks in CSR
+// order (nine contiguous values per block, a row's blocks contiguous in
+// ascending column order).  The row products of the large coarse levels read
+// that copy: their rows vary in length, so their slices hold about 1.4 times
+// the stored blocks, and a slot line is fetched whole as soon as one row of
+// the slice reaches it.  G lanes share a row: lane sub takes the blocks
+// rp[i] + sub, + G, ..., two per pass with their loads in flight together,
+// and the group's partial sums are added by a butterfly (every lane ends with
+// the total).
+template <int G, typename T, typename XF>
+__device__ inline void csr_row_mv_g(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                    const T* __restrict__ vt, int64_t i, int sub, XF xf, T& a0, T& a1, T& a2) {
+  const int32_t k1 = rp[i + 1];
+  for (int32_t k = rp[i] + sub; k < k1; k += 2 * G) {
+    const bool two = k + G < k1;
+    const int32_t kb = two ? k + G : k;  // a missing second block re-reads the first
+    const int32_t c0 = ci[k], c1 = ci[kb];
+    T p[9], q[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) p[e] = vt[(int64_t)k * 9 + e];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) q[e] = vt[(int64_t)kb * 9 + e];
+    const V3<T> x0 = xf(c0), x1 = xf(c1);
+    a0 += p[0] * x0.x + p[1] * x0.y + p[2] * x0.z;
+    a1 += p[3] * x0.x + p[4] * x0.y + p[5] * x0.z;
+    a2 += p[6] * x0.x + p[7] * x0.y + p[8] * x0.z;
+    if (two) {
+      a0 += q[0] * x1.x + q[1] * x1.y + q[2] * x1.z;
+      a1 += q[3] * x1.x + q[4] * x1.y + q[5] * x1.z;
+      a2 += q[6] * x1.x + q[7] * x1.y + q[8] * x1.z;
+    }
+  }
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) {
+    a0 += __shfl_xor(a0, off, G);
+    a1 += __shfl_xor(a1, off, G);
+    a2 += __shfl_xor(a2, off, G);
+  }
+}
+
+// r = b - A x, A in CSR order
+template <typename T, int XMODE, int G>
+__global__ void k_residual_csr(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                               const T* __restrict__ vt, T omega, const T* __restrict__ b, const T* __restrict__ x,
+                               T* __restrict__ r) {
+  const RowPos p = row_pos<G>();
+  if (p.i >= n) return;  // the G lanes of a row leave together
+  T a0 = 0, a1 = 0, a2 = 0;
+  csr_row_mv_g<G>(rp, ci, vt, p.i, p.sub, [&](int32_t c) { return xval<T, XMODE>(x, b, omega, c); }, a0, a1, a2);
+  if (p.sub != 0) return;
+  const V3<T> bi = ld3(b, p.i);
+  st3(r, p.i, V3<T>{bi.x - a0, bi.y - a1, bi.z - a2});
+}
+
+// out_i = x_i + omega D_i^{-1} (b_i - sum_j A_ij x_j), A in CSR order (the
+// coarse correction is prolonged into x beforehand, in its own pass)
+template <typename T, int XMODE, int G>
+__global__ void k_post_smooth_csr(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                  const T* __restrict__ vt, const T* __restrict__ dinv, T omega,
+                                  const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ out) {
+  const RowPos p = row_pos<G>();
+  if (p.i >= n) return;
+  T a0 = 0, a1 = 0, a2 = 0;
+  csr_row_mv_g<G>(rp, ci, vt, p.i, p.sub, [&](int32_t c) { return xval<T, XMODE>(x, b, omega, c); }, a0, a1, a2);
+  if (p.sub != 0) return;
+  const V3<T> xi = xval<T, XMODE>(x, b, omega, p.i);
+  const V3<T> bi = ld3(b, p.i);
+  const V3<T> res = dmv(dinv, p.s * 9 * SL + p.l, V3<T>{bi.x - a0, bi.y - a1, bi.z - a2});
+  st3(out, p.i, V3<T>{xi.x + omega * res.x, xi.y + omega * res.y, xi.z + omega * res.z});
+}
+
 // One block Gauss-Seidel sweep over a colour class, in place.  The rows of a
 // class are not coupled to each other, so every row reads only rows of other
 // classes (settled by earlier launches) and its own entry.  FIRST: x = 0
@@ -1735,6 +1807,37 @@ void launch_prolong(hipStream_t st, int64_t n, int xmode, double omega, const T*
     hipLaunchKernelGGL((k_prolong<T, 2>), g, t, 0, st, n, (T)omega, b, x, agg, ec, out);
 }
 
+// the large-level products on the CSR-ordered copy: G = CSR_G lanes per row
+template <typename T>
+void launch_residual_csr(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci, const T* vt, int xmode,
+                         double omega, const T* b, const T* x, T* r) {
+  if (n <= 0) return;
+  const int tb = tpb_rows(n);
+  const dim3 g(nblk(n * CSR_G, tb)), t(tb);
+  const T om = (T)omega;
+  if (xmode == 0)
+    hipLaunchKernelGGL((k_residual_csr<T, 0, CSR_G>), g, t, 0, st, n, rp, ci, vt, om, b, x, r);
+  else if (xmode == 1)
+    hipLaunchKernelGGL((k_residual_csr<T, 1, CSR_G>), g, t, 0, st, n, rp, ci, vt, om, b, x, r);
+  else
+    hipLaunchKernelGGL((k_residual_csr<T, 2, CSR_G>), g, t, 0, st, n, rp, ci, vt, om, b, x, r);
+}
+
+template <typename T>
+void launch_post_smooth_csr(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci, const T* vt,
+                            const T* dinv, int xmode, double omega, const T* b, const T* x, T* out) {
+  if (n <= 0) return;
+  const int tb = tpb_rows(n);
+  const dim3 g(nblk(n * CSR_G, tb)), t(tb);
+  const T om = (T)omega;
+  if (xmode == 0)
+    hipLaunchKernelGGL((k_post_smooth_csr<T, 0, CSR_G>), g, t, 0, st, n, rp, ci, vt, dinv, om, b, x, out);
+  else if (xmode == 1)
+    hipLaunchKernelGGL((k_post_smooth_csr<T, 1, CSR_G>), g, t, 0, st, n, rp, ci, vt, dinv, om, b, x, out);
+  else
+    hipLaunchKernelGGL((k_post_smooth_csr<T, 2, CSR_G>), g, t, 0, st, n, rp, ci, vt, dinv, om, b, x, out);
+}
+
 template <typename T>
 void launch_tail(hipStream_t st, const TailArgs<T>& a, const T* rabove, const int32_t* mptr, const int32_t* mem,
                  T* out) {
@@ -1814,6 +1917,10 @@ template void launch_scale_in_grid<float>(hipStream_t, GridDims, const double*, 
                                       const T*, const int32_t*, const T*, T*, int);                         \
   template void launch_prolong<T>(hipStream_t, int64_t, int, double, const T*, const T*, const int32_t*,   \
                                   const T*, T*);                                                            \
+  template void launch_residual_csr<T>(hipStream_t, int64_t, const int32_t*, const int32_t*, const T*, int,  \
+                                       double, const T*, const T*, T*);                                     \
+  template void launch_post_smooth_csr<T>(hipStream_t, int64_t, const int32_t*, const int32_t*, const T*,   \
+                                          const T*, int, double, const T*, const T*, T*);                   \
   template void launch_scale_in<T>(hipStream_t, int64_t, const double*, int, const double*, const double*, \
                                    T*);                                                                     \
   template void launch_gs_sweep<T>(hipStream_t, Sell, const int32_t*, const T*, const T*, int, int, const T*, \

@@ -296,6 +296,18 @@ template <typename T>
 void launch_post_smooth(hipStream_t st, Sell A, const T* val, const T* dinv, int unit, int xmode,
                         double omega, const T* b, const T* x, const int32_t* agg, const T* ec,
                         T* out, int G);
+// The same two products on a level's CSR-ordered blocks (rp, ci: the level's
+// block pattern; vt: nine contiguous values per block, in pattern order),
+// CSR_G lanes per row; the post-smoothing sweep takes no coarse correction
+// (prolong it into x first).  CSR_G: lanes per row (the large coarse levels
+// hold about 15 blocks per row in 3D).
+constexpr int CSR_G = 4;
+template <typename T>
+void launch_residual_csr(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci, const T* vt, int xmode,
+                         double omega, const T* b, const T* x, T* r);
+template <typename T>
+void launch_post_smooth_csr(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci, const T* vt,
+                            const T* dinv, int xmode, double omega, const T* b, const T* x, T* out);
 // One block Gauss-Seidel sweep over a colour class (C: the class as a
 // sliced-ELL matrix, rows: its level rows): x_i += D_i^{-1} (b_i - sum_j A_ij x_j),
 // in place.  first: x is zero everywhere, so x_i = D_i^{-1} b_i.

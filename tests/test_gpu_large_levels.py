@@ -83,3 +83,48 @@ def test_large_levels_bitwise(gpu, orc, case):
         rel = np.abs(a[2] - forms[("bsr", "fp64")][l][2]).max() / np.abs(forms[("bsr", "fp64")][l][2]).max()
         assert rel <= 1e-5, (l, rel)
     say("  %d levels equal" % nl)
+
+
+# Large coarse levels applied from their CSR-ordered blocks (opts.csr_levels):
+# grids with a level of at least 32768 nodes below the K-cycle levels (and
+# below level 1 of the per-node grid form, which is applied through the grid
+# blocks) and above the coarsest.
+CSR_CASES = [
+    # name, dim, n, alpha, dt, grid-level storage, K-cycle depth
+    ("2d_512_bsr_v", 2, 512, 0.05, 2e-5, "bsr", 0),
+    ("3d_96_factored_k1", 3, 96, 0.3, 1e-3, "factored", 1),
+]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("case", CSR_CASES, ids=[c[0] for c in CSR_CASES])
+def test_csr_levels_cycle(gpu, orc, case):
+    """The cycle with the large levels' row products on the CSR-ordered copy
+    against the oracle's cycle (FP64, 1e-12 relative, the V-cycle bar of the
+    small grids) and against the sliced-ELL products (FP32-AMG: the two add a
+    row's blocks in different orders)."""
+    name, dim, n, alpha, dt, op, kd = case
+    say("[csr_levels_cycle]", name)
+    m = _rough(n ** dim)
+    H = orc.Hierarchy(orc.make_grid(dim, n), orc.default_opts(kcycle_depth=kd), m, alpha, dt)
+    sizes = [len(H.level(l).rp) - 1 for l in range(H.num_levels)]
+    say("  oracle levels", sizes)
+    first = max(2 if op == "factored" else 1, kd + 1)
+    assert any(s >= 32768 for s in sizes[first:-1])
+    v = np.random.default_rng(5).standard_normal(m.shape)
+    zr = H.precond(v)
+    out = {}
+    for csr in (1, 0):
+        for prec in ("fp64", "fp32_amg"):
+            S = gpu.Solver(gpu.make_grid(dim, n), gpu.default_opts(kcycle_depth=kd, fine_operator=op, precision=prec,
+                                                                   csr_levels=csr))
+            assert S.setup(_cuda(m), alpha, dt) == gpu.OK
+            out[(csr, prec)] = S.precond(_cuda(v)).cpu().numpy()
+            S.close()
+    for csr in (1, 0):
+        d = np.abs(out[(csr, "fp64")] - zr).max() / np.abs(zr).max()
+        say("  csr_levels %d: fp64 cycle vs oracle %.2e" % (csr, d))
+        assert d <= 1e-12, (csr, d)
+    d = np.abs(out[(1, "fp32_amg")] - out[(0, "fp32_amg")]).max() / np.abs(out[(0, "fp32_amg")]).max()
+    say("  fp32_amg cycle, CSR vs sliced products %.2e" % d)
+    assert d <= 1e-5, d
