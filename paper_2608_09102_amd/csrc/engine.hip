@@ -557,6 +557,15 @@ int build_structure(llg_ctx& c, Arena& ar) {
       // stop at about 1.25M threads (level 1 of a 128^3 grid: 2 instead of 8).
       int lanes = 1;
       while (lanes < 16 && (int64_t)2 * lanes * cn < cg && (int64_t)2 * lanes * cn <= (int64_t(5) << 18)) lanes *= 2;
+      // the first pass of the grid level matches on the grid graph itself,
+      // whose rows the proposal kernel computes instead of loading
+      const bool on_grid = l == 0 && p == 0;
+      auto propose = [&](int32_t* any) {
+        if (on_grid)
+          launch_propose_grid(st, nx, ny, nz, mate, salt, o.beta_num, o.beta_den, prop, any);
+        else
+          launch_propose(st, cn, crp, cci, cw, mate, ns, salt, o.beta_num, o.beta_den, prop, any, lanes);
+      };
       // handshake rounds: PLAN runs until a round has no proposal and logs
       // the number of rounds; REPLAY runs that many and checks the extra
       // round proposes nothing
@@ -569,7 +578,7 @@ int build_structure(llg_ctx& c, Arena& ar) {
         int64_t rounds = 0;
         for (;;) {
           launch_fill_i32(st, c.count, 1, 0);
-          launch_propose(st, cn, crp, cci, cw, mate, ns, salt, o.beta_num, o.beta_den, prop, c.count, lanes);
+          propose(c.count);
           LCHK();
           HIPX(hipMemcpyAsync(ar.hcount, c.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
           HIPX(hipStreamSynchronize(st));
@@ -584,11 +593,11 @@ int build_structure(llg_ctx& c, Arena& ar) {
         const int64_t rounds = ar.plan->counts[ar.ci++];
         launch_fill_i32(st, c.count + 1, 1, 0);
         for (int64_t r = 0; r < rounds; ++r) {
-          launch_propose(st, cn, crp, cci, cw, mate, ns, salt, o.beta_num, o.beta_den, prop, c.count + 1, lanes);
+          propose(c.count + 1);
           launch_accept(st, cn, prop, mate, ns);
         }
         launch_fill_i32(st, c.count, 1, 0);
-        launch_propose(st, cn, crp, cci, cw, mate, ns, salt, o.beta_num, o.beta_den, prop, c.count, lanes);
+        propose(c.count);
         launch_check_eq(st, c.count, 0, ar.flag, F_PLAN);
         LCHK();
       }

@@ -320,21 +320,28 @@ __device__ inline bool propose_node(int64_t i, int sub, int64_t n, const int32_t
   // earliest candidate of a set stays the earliest of any subset holding it.
   // Only the nodes whose proposal got matched (and the first round, prop
   // -1) walk their rows.  The decision is the same on the G lanes of a node.
+  //
+  // The loads go out in three waves: mate and the last proposal; then, for a
+  // free node, the proposal's mate together with the node's record and row
+  // bounds (read for nothing when it proposes again); then the row.
   const int32_t mi = i < n ? mate[i] : 0;
+  const int32_t pj = i < n ? prop[i] : -1;
   bool walk = false;
+  NodeSt si{};
+  int32_t kb = 0, k1 = 0;
   if (i < n && mi == -1) {
-    const int32_t pj = prop[i];
+    si = ns[i];
+    kb = grp[i];
+    k1 = grp[i + 1];
     if (pj >= 0 && mate[pj] < 0)
       best = pj;
     else
       walk = true;
   }
   if (walk) {
-    const NodeSt si = ns[i];
     const uint64_t ri = si.rank;
     const int32_t mxi = si.mx;
-    const int32_t k1 = grp[i + 1];
-    for (int32_t k0 = grp[i] + sub; k0 < k1; k0 += 4 * G) {
+    for (int32_t k0 = kb + sub; k0 < k1; k0 += 4 * G) {
       int32_t jj[4], ww[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -415,6 +422,71 @@ __global__ void __launch_bounds__(TPB) k_propose(int64_t n, const int32_t* __res
   // "some node proposed": set once; most wavefronts see the flag already set
   // and skip the atomic (same-address atomics from every wavefront serialize)
   const unsigned long long ballot = __ballot(proposed);
+  if ((threadIdx.x & 63) == 0 && ballot && __atomic_load_n(count, __ATOMIC_RELAXED) == 0) atomicOr(count, 1);
+}
+
+// The same round on the grid graph itself (the first pass of the grid level):
+// its rows are the grid neighbours in ascending order, every weight is 1, so
+// every node's largest weight is 1 (a grid of one node has no row), and a
+// node's visiting rank is node_rank of its index.  A walk then reads only
+// the neighbours' 4-byte mates: neighbours and ranks are computed, not
+// loaded.  mate stands in for the record's copy of it: the two differ only
+// where a dead node (no candidate) holds -2, and both are negative there.
+// The decisions are those of propose_node on the stored grid graph.
+__global__ void __launch_bounds__(TPB) k_propose_grid(int nx, int ny, int nz, int32_t* __restrict__ mate,
+                                                      uint64_t salt, int32_t bnum, int32_t bden,
+                                                      int32_t* __restrict__ prop, int32_t* count) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  int32_t best = -1;
+  // a node's last proposal is one of its neighbours, so the neighbours'
+  // mates, loaded once the node is known to be free, also tell whether that
+  // proposal is still free: two dependent loads per node
+  const int32_t mi = i < N ? mate[i] : 0;
+  const int32_t pj = i < N ? prop[i] : -1;
+  bool walk = false;
+  int64_t nb[6];
+  int32_t mj[6];
+  int c = 0;
+  if (i < N && mi == -1) {
+    c = grid_nbrs(nx, ny, nz, i, nb);
+#pragma unroll
+    for (int u = 0; u < 6; ++u) mj[u] = u < c ? mate[nb[u]] : 0;
+    bool again = false;
+#pragma unroll
+    for (int u = 0; u < 6; ++u) again = again || (u < c && nb[u] == pj && mj[u] < 0);
+    if (again)
+      best = pj;
+    else
+      walk = true;
+  }
+  if (walk) {
+    const uint64_t ri = node_rank(i, salt);
+    EdgeKey bk{};
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      if (u >= c || mj[u] >= 0) continue;
+      const int32_t j = (int32_t)nb[u];
+      const uint64_t rj = node_rank(j, salt);
+      const bool ifirst = ri != rj ? ri < rj : i < j;
+      if ((int64_t)bden < (int64_t)bnum) continue;  // weight 1 against the largest weight 1
+      EdgeKey e;
+      e.rank = ifirst ? ri : rj;
+      e.first = ifirst ? (int32_t)i : j;
+      e.w = 1;
+      e.lo = (int32_t)min((int64_t)j, i);
+      e.hi = (int32_t)max((int64_t)j, i);
+      if (best < 0 || key_before(e, bk, salt)) {
+        bk = e;
+        best = j;
+      }
+    }
+  }
+  if (i < N) {
+    prop[i] = best;
+    if (mi == -1 && best < 0) mate[i] = -2;
+  }
+  const unsigned long long ballot = __ballot(i < N && best >= 0);
   if ((threadIdx.x & 63) == 0 && ballot && __atomic_load_n(count, __ATOMIC_RELAXED) == 0) atomicOr(count, 1);
 }
 
@@ -1414,6 +1486,13 @@ void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t
   else
     LLG_PR(1);
 #undef LLG_PR
+}
+void launch_propose_grid(hipStream_t st, int nx, int ny, int nz, int32_t* mate, uint64_t salt, int32_t bnum,
+                         int32_t bden, int32_t* prop, int32_t* count) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  if (N > 0)
+    hipLaunchKernelGGL(k_propose_grid, dim3(nblk(N)), dim3(TPB), 0, st, nx, ny, nz, mate, salt, bnum, bden, prop,
+                       count);
 }
 void launch_match_small(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci, const int32_t* gw,
                         int32_t* mate, NodeSt* ns, uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop,
