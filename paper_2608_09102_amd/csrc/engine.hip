@@ -1078,6 +1078,7 @@ void setup_values(llg_ctx& c, const double* m, const double* mprev, const double
     src.fci = L.bci;
     src.cvt = (T*)Nx.vt;
     src.crp = Nx.brp;
+    src.cci = Nx.bci;
     launch_galerkin<T>(st, Nx.A, (T*)Nx.val, (T*)Nx.dinv, L.mptr, L.mem, L.A, L.agg, src);
     LCHK();
   }

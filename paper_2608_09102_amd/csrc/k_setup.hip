@@ -1161,6 +1161,100 @@ __global__ void __launch_bounds__(TPB) k_galerkin_slices(int64_t nc, const int32
   }
 }
 
+// Large coarse levels of a coarse level, row by row: GR_L lanes share a
+// coarse row I, lane t owning its slots t and t + GR_L (further passes for
+// rows of more than 2 GR_L blocks).  The group walks the fine rows of I's
+// members once: lane e loads entry e of a member row (its column's aggregate
+// and its nine values, contiguous in the fine level's CSR-ordered copy), and
+// the entries are handed round the group in row order; the lane owning the
+// entry's aggregate adds it.  So every block (I, J) is the sum, over the
+// members i of I in ascending order and over the stored blocks (i, j) of row i
+// in ascending j with agg(j) = J, of a_ij (eq. Ac_direct), accumulated in FP64
+// from zero, as in the other two kernels, while each fine row is read once per
+// coarse row (not once per group of slots) and with contiguous loads.
+constexpr int GR_L = 16;
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_galerkin_rows(int64_t nc, const int32_t* __restrict__ csl,
+                                                       T* __restrict__ cval, T* __restrict__ cdinv,
+                                                       const int32_t* __restrict__ mptr,
+                                                       const int32_t* __restrict__ mem,
+                                                       const int32_t* __restrict__ agg, const GalSrc<T> g) {
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t I = blk * (TPB / GR_L) + threadIdx.x / GR_L;
+  const int t = (int)(threadIdx.x % GR_L);
+  if (I >= nc) return;  // a whole group
+  const int32_t c0 = g.crp[I], w = g.crp[I + 1] - c0;
+  const int32_t q0 = mptr[I], q1 = mptr[I + 1];
+  const int64_t s = I / SL, l = I - s * SL;
+  for (int sp = 0; sp < w; sp += 2 * GR_L) {
+    const int s0 = sp + t, s1 = sp + GR_L + t;
+    const int32_t J0 = s0 < w ? g.cci[c0 + s0] : -1, J1 = s1 < w ? g.cci[c0 + s1] : -1;
+    double a0[9], a1[9];
+#pragma unroll
+    for (int x = 0; x < 9; ++x) a0[x] = a1[x] = 0.0;
+    for (int32_t q = q0; q < q1; ++q) {
+      const int32_t i = mem[q];
+      const int32_t k0 = g.frp[i], len = g.frp[i + 1] - k0;
+      for (int b = 0; b < len; b += GR_L) {
+        const int e = b + t;
+        int32_t a = -1;
+        T v[9];
+#pragma unroll
+        for (int x = 0; x < 9; ++x) v[x] = T(0);
+        if (e < len) {
+          a = agg[g.fci[k0 + e]];
+#pragma unroll
+          for (int x = 0; x < 9; ++x) v[x] = g.fvt[(int64_t)(k0 + e) * 9 + x];
+        }
+        const int n = min(GR_L, len - b);
+        for (int u = 0; u < n; ++u) {
+          const int32_t A = __shfl(a, u, GR_L);
+          double f[9];
+#pragma unroll
+          for (int x = 0; x < 9; ++x) f[x] = (double)__shfl(v[x], u, GR_L);
+          if (A == J0) {
+#pragma unroll
+            for (int x = 0; x < 9; ++x) a0[x] += f[x];
+          }
+          if (A == J1) {
+#pragma unroll
+            for (int x = 0; x < 9; ++x) a1[x] += f[x];
+          }
+        }
+      }
+    }
+    // slot s0 (then s1): stored in T, the inverse of a diagonal block from the stored block
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int32_t J = h ? J1 : J0;
+      if (J < 0) continue;
+      const int so = h ? s1 : s0;
+      T stv[9];
+#pragma unroll
+      for (int x = 0; x < 9; ++x) stv[x] = (T)(h ? a1[x] : a0[x]);
+      if (cval) {
+        const int64_t vb = (int64_t)csl[s] * 9 + (int64_t)so * 9 * SL + l;
+#pragma unroll
+        for (int x = 0; x < 9; ++x) cval[vb + x * SL] = stv[x];
+      }
+      if (g.cvt) {
+        const int64_t pos = (int64_t)c0 + so;
+#pragma unroll
+        for (int x = 0; x < 9; ++x) g.cvt[pos * 9 + x] = stv[x];
+      }
+      if (J == (int32_t)I) {
+        double D[9], Di[9];
+#pragma unroll
+        for (int x = 0; x < 9; ++x) D[x] = (double)stv[x];
+        inv3(D, Di);
+        const int64_t db = s * 9 * SL + l;
+#pragma unroll
+        for (int x = 0; x < 9; ++x) cdinv[db + x * SL] = (T)Di[x];
+      }
+    }
+  }
+}
+
 // Small coarse levels (few slices): one thread per block slot (I, J), its
 // slice found by bisection.  The block is the sum, over the
 // members i of aggregate I in ascending order and over the stored blocks
@@ -1591,7 +1685,15 @@ void launch_galerkin(hipStream_t st, Sell C, T* cval, T* cdinv, const int32_t* m
   else                                                                                                         \
     hipLaunchKernelGGL((k_galerkin_slots<T, FACT>), dim3(nblk(C.nslots)), dim3(TPB), 0, st, C.n, C.nslices,      \
                        C.sl_ptr, C.col, cval, cdinv, mptr, mem, F.sl_ptr, F.col, agg, g)
-  if (g.fk) {
+  // large coarse levels of a coarse level row by row, from its CSR-ordered
+  // copy.  (Level 1 of a grid level stored per node measured faster by slot
+  // groups: its blocks come from K_i, one load per member, and by slot groups
+  // 64 coarse rows share the FP64 adds of a wavefront, against 4 row by row.)
+  const bool rows = C.nslices >= 1024 && g.crp && g.cci && !g.fk && g.fvt != nullptr;
+  const dim3 rg(nblk(C.n, TPB / GR_L)), rt(TPB);
+  if (rows) {
+    hipLaunchKernelGGL((k_galerkin_rows<T>), rg, rt, 0, st, C.n, C.sl_ptr, cval, cdinv, mptr, mem, agg, g);
+  } else if (g.fk) {
     LLG_GAL(true);
   } else {
     LLG_GAL(false);

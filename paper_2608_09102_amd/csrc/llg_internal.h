@@ -262,6 +262,7 @@ struct GalSrc {
   const int32_t* fci = nullptr;
   T* cvt = nullptr;            // coarse blocks in the coarse level's CSR order (for the next product)
   const int32_t* crp = nullptr;  // coarse CSR row pointers (positions of cvt)
+  const int32_t* cci = nullptr;  // coarse CSR columns (ascending; the sliced-ELL slot order)
 };
 // Galerkin block sums P^T A P and the inverse diagonal blocks of the result
 template <typename T>

@@ -1,10 +1,10 @@
 """Hierarchy values bit for bit on grids large enough for the setup kernels
 that only run on large levels (eq. galerkin, eq. Ac_direct, Sec. 3.1.1): the
-Galerkin product with one workgroup per coarse slice (levels of 65,536 nodes
-or more), the four-block walk of its threads, the coarse-graph rows of more
-than 32 candidates (3D coarse levels), the matching rounds over many
-workgroups, and, in the per-node grid form, the level-1 product that reads the
-grid blocks node-major.
+Galerkin products of coarse levels of 65,536 nodes or more (one workgroup per
+coarse slice from the grid level, stored as sliced ELL or per node; row by
+row, a group of lanes per coarse row, from a coarse level's CSR-ordered copy),
+the coarse-graph rows of more than 32 candidates (3D coarse levels), and the
+matching rounds over many workgroups.
 
 Bars: every level's pattern and FP64 values equal the oracle's (both sides add
 the same blocks in the same order without contraction); the aggregates equal
@@ -43,7 +43,9 @@ def _rough(N, seed=7):
     return m / np.linalg.norm(m, axis=1, keepdims=True)
 
 
-CASES = [("2d_512", 2, 512, 0.05, 2e-5), ("3d_64", 3, 64, 0.3, 1e-3)]
+# 3d_96: level 2 (about 70,000 nodes) is formed row by row from level 1's
+# CSR-ordered blocks
+CASES = [("2d_512", 2, 512, 0.05, 2e-5), ("3d_64", 3, 64, 0.3, 1e-3), ("3d_96", 3, 96, 0.3, 1e-3)]
 
 
 @pytest.mark.timeout(900)
