@@ -1079,6 +1079,43 @@ __global__ void __launch_bounds__(TPB) k_galerkin_slices(int64_t nc, const int32
   const int64_t cb = csl[s];
   const int width = (int)((csl[s + 1] - cb) / SL);
   const int nchunk = (width + GC - 1) / GC;
+  // Grid level stored per node: the member rows of the slice's coarse rows
+  // (up to GM members per row) are staged in LDS once, their entries'
+  // aggregates, the diagonal's position and K_i, and every slot group of a
+  // coarse row reads them there (a row's slot groups would otherwise gather
+  // the same aggregates from L2 once each).
+  constexpr int GM = 4;
+  __shared__ int32_t s_aa[SL * GM * 8];
+  __shared__ int32_t s_dp[SL * GM];
+  __shared__ int32_t s_nm[SL];
+  __shared__ T s_k[SL * GM * 9];
+  if (FACT && g.knm) {
+    for (int tt = threadIdx.x; tt < SL * GM; tt += blockDim.x) {
+      const int lr = tt / GM, m = tt - lr * GM;
+      const int64_t I = s * SL + lr;
+      int32_t nm = 0;
+      if (I < nc) {
+        const int32_t q0 = mptr[I];
+        nm = mptr[I + 1] - q0;
+        if (m < nm && nm <= GM) {
+          const int32_t i = mem[q0 + m];
+          const int32_t k0 = g.frp[i], len = min(g.frp[i + 1] - k0, 8);
+          int dp = -1;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int32_t j = k < len ? g.fci[k0 + k] : -1;
+            s_aa[(lr * GM + m) * 8 + k] = j >= 0 ? agg[j] : -1;
+            dp = j == i ? k : dp;
+          }
+          s_dp[lr * GM + m] = dp;
+#pragma unroll
+          for (int e = 0; e < 9; ++e) s_k[(lr * GM + m) * 9 + e] = g.knm[9 * (int64_t)i + e];
+        }
+      }
+      if (m == 0) s_nm[lr] = nm;
+    }
+    __syncthreads();
+  }
   for (int k = threadIdx.x; k < nchunk * SL; k += blockDim.x) {
     const int c = k / SL, l = k - c * SL;
     const int64_t I = s * SL + l;
@@ -1098,35 +1135,87 @@ __global__ void __launch_bounds__(TPB) k_galerkin_slices(int64_t nc, const int32
     for (int h = 0; h < GC; ++h)
 #pragma unroll
       for (int e = 0; e < 9; ++e) acc[h][e] = 0.0;
-    for (int32_t q = mptr[I]; q < mptr[I + 1]; ++q) {
-      const int32_t i = mem[q];
-      const int64_t fs = i / SL;
-      const int fl = i - (int)(fs * SL);
-      const int64_t fb = (FACT || g.fvt) ? 0 : fsl[fs];  // sliced fine values only
-      // the member's row in CSR order (contiguous columns and, on coarse
-      // levels, contiguous blocks), four at a time: their column and
-      // aggregate loads are in flight together; the blocks are still added
-      // in ascending column order
-      const int32_t k0 = g.frp[i], k1 = g.frp[i + 1];
-      for (int32_t kb = k0; kb < k1; kb += 4) {
-        int32_t jj[4], aa[4];
+    if (FACT && g.knm) {
+      // Grid-level rows (at most 8 entries): every block of row i is K_i but
+      // the diagonal one, I.  So the entries of the row that fall into slot h
+      // are taken from a bit mask, in ascending order, and each costs one
+      // block addition; the FP64 sums are those of the walk below.
+      auto add_member = [&](const int32_t* aa, int dpos, const double* kd) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) jj[k] = kb + k < k1 ? g.fci[kb + k] : -1;
+        for (int h = 0; h < GC; ++h) {
+          unsigned m = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) aa[k] = jj[k] >= 0 ? agg[jj[k]] : -1;
+          for (int k = 0; k < 8; ++k) m |= (J[h] >= 0 && aa[k] == J[h]) ? 1u << k : 0u;
+          while (m) {
+            const int k = __ffs(m) - 1;
+            m &= m - 1;
+            const bool d = k == dpos;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          int hit = -1;
+            for (int e = 0; e < 9; ++e) acc[h][e] += d ? ((e == 0 || e == 4 || e == 8) ? 1.0 : 0.0) : kd[e];
+          }
+        }
+      };
+      const int nm = s_nm[l];
+      if (nm <= GM) {
+        for (int m = 0; m < nm; ++m) {
+          const int b = l * GM + m;
+          int32_t aa[8];
+          double kd[9];
 #pragma unroll
-          for (int h = 0; h < GC; ++h) hit = aa[k] >= 0 && aa[k] == J[h] ? h : hit;
-          if (hit < 0) continue;
-          double f[9];
-          fine_block<T, FACT>(g, i, jj[k], kb + k, fs, fl, fb, kb + k - k0, f);
+          for (int k = 0; k < 8; ++k) aa[k] = s_aa[b * 8 + k];
 #pragma unroll
-          for (int h = 0; h < GC; ++h)
-            if (h == hit)
+          for (int e = 0; e < 9; ++e) kd[e] = (double)s_k[b * 9 + e];
+          add_member(aa, s_dp[b], kd);
+        }
+      } else {
+        for (int32_t q = mptr[I]; q < mptr[I + 1]; ++q) {
+          const int32_t i = mem[q];
+          const int32_t k0 = g.frp[i], len = min(g.frp[i + 1] - k0, 8);
+          int32_t aa[8];
+          int dpos = -1;
 #pragma unroll
-              for (int e = 0; e < 9; ++e) acc[h][e] += f[e];
+          for (int k = 0; k < 8; ++k) {
+            const int32_t j = k < len ? g.fci[k0 + k] : -1;
+            aa[k] = j >= 0 ? agg[j] : -1;
+            dpos = j == i ? k : dpos;
+          }
+          double kd[9];
+#pragma unroll
+          for (int e = 0; e < 9; ++e) kd[e] = (double)g.knm[9 * (int64_t)i + e];
+          add_member(aa, dpos, kd);
+        }
+      }
+    } else {
+      for (int32_t q = mptr[I]; q < mptr[I + 1]; ++q) {
+        const int32_t i = mem[q];
+        const int64_t fs = i / SL;
+        const int fl = i - (int)(fs * SL);
+        const int64_t fb = (FACT || g.fvt) ? 0 : fsl[fs];  // sliced fine values only
+        // the member's row in CSR order (contiguous columns and, on coarse
+        // levels, contiguous blocks), four at a time: their column and
+        // aggregate loads are in flight together; the blocks are still added
+        // in ascending column order
+        const int32_t k0 = g.frp[i], k1 = g.frp[i + 1];
+        for (int32_t kb = k0; kb < k1; kb += 4) {
+          int32_t jj[4], aa[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) jj[k] = kb + k < k1 ? g.fci[kb + k] : -1;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) aa[k] = jj[k] >= 0 ? agg[jj[k]] : -1;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            int hit = -1;
+#pragma unroll
+            for (int h = 0; h < GC; ++h) hit = aa[k] >= 0 && aa[k] == J[h] ? h : hit;
+            if (hit < 0) continue;
+            double f[9];
+            fine_block<T, FACT>(g, i, jj[k], kb + k, fs, fl, fb, kb + k - k0, f);
+#pragma unroll
+            for (int h = 0; h < GC; ++h)
+              if (h == hit)
+#pragma unroll
+                for (int e = 0; e < 9; ++e) acc[h][e] += f[e];
+          }
         }
       }
     }
