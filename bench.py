@@ -33,11 +33,14 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # faster, but its kernels share the device with the rebuild, which a kernel
 # trace cannot show (the profiler serializes the streams), so the roofline
 # kernel is timed in the serial form.
+# +nuXY: X block-Jacobi sweeps before and Y after the coarse correction (the
+# library default is one and one); the counts are the measured cheapest per
+# workload (design notes, the smoothing study)
 DEFAULT_FORMS = {
-    "mms3d_256": "fp32_amg:1:jacobi:factored+serial,fp64:1:jacobi:factored+serial,fp32_amg:1:jacobi:factored,"
-                 "fp64:1:jacobi:factored",
-    "rough3d_128": "fp32_amg:0:jacobi:factored,fp64:0:jacobi:factored",
-    "rough2d_1024": "fp32_amg:1:jacobi:factored,fp64:1:jacobi:factored",
+    "mms3d_256": "fp32_amg:1:jacobi:factored+serial+nu03,fp64:1:jacobi:factored+serial+nu03,"
+                 "fp32_amg:1:jacobi:factored+nu03,fp64:1:jacobi:factored+nu03",
+    "rough3d_128": "fp32_amg:0:jacobi:factored+nu02,fp64:0:jacobi:factored+nu02",
+    "rough2d_1024": "fp32_amg:1:jacobi:factored+nu02,fp64:1:jacobi:factored+nu02",
     "vortex64": "fp64:1:jacobi:factored,fp32_amg:1:jacobi:factored",
 }
 # the oracle runs one step of the workload when it takes about 10-30 s on one
@@ -135,7 +138,7 @@ def algorithmic_bytes(cls: str, st, N: int, precision: str, operator: str = "bsr
     nnzb0 = st.level_nnzb[0]
     if cls == "outer_spmv":
         zb = 4 if precision == "fp32_amg" else 8
-        if operator == "factored":  # block recomputed from the frozen field (24 B per node), neighbours from the grid
+        if operator.split("+")[0] == "factored":  # block recomputed from the frozen field (24 B per node), neighbours from the grid
             return 24.0 * N + 3.0 * zb * N + 24.0 * N
         return 72.0 * nnzb0 + 4.0 * nnzb0 + 3.0 * zb * N + 24.0 * N
     raise ValueError("no byte model for kernel class " + cls)
@@ -156,14 +159,18 @@ NU = None  # --nu: sweeps before and after the coarse correction, every form
 
 
 def form_opts(llg, rtol: float, precision: str, kdepth: int, smoother: str, operator: str):
-    """Options of a form.  operator[+serial|+reuse][+sliced]: the hierarchy
-    structure rebuilt on a second stream beside the step (default), rebuilt
-    at the start of each step (serial), or built once per context (reuse);
-    +sliced: the large coarse levels' products on sliced-ELL values instead
-    of the CSR-ordered blocks."""
+    """Options of a form.  operator[+serial|+reuse][+sliced][+nuXY]: the
+    hierarchy structure rebuilt on a second stream beside the step (default),
+    rebuilt at the start of each step (serial), or built once per context
+    (reuse); +sliced: the large coarse levels' products on sliced-ELL values
+    instead of the CSR-ordered blocks; +nuXY: X smoothing sweeps before and Y
+    after the coarse correction (default one and one)."""
     base, *mods = operator.split("+")
     extra = {}
     for rb in mods:
+        if rb.startswith("nu"):
+            extra.update(nu_pre=int(rb[2]), nu_post=int(rb[3]))
+            continue
         extra.update({"serial": dict(overlap_rebuild=0), "reuse": dict(rebuild_aggregates=0),
                       "sliced": dict(csr_levels=0)}[rb])
     if NU is not None:
@@ -264,21 +271,32 @@ def sample_step(w, warmup: int):
     return w.dim, n, m, F, label
 
 
-def cpu_baseline(w, warmup: int, kdepth: int, smoother: str):
+def form_nu(operator: str):
+    """(sweeps before, sweeps after) of a form's operator string."""
+    nu = (NU, NU) if NU is not None else (1, 1)
+    for rb in operator.split("+")[1:]:
+        if rb.startswith("nu"):
+            nu = (int(rb[2]), int(rb[3]))
+    return nu
+
+
+def cpu_baseline(w, warmup: int, kdepth: int, smoother: str, nu=(1, 1)):
     """The oracle (single-threaded C++, FP64) timed on sample_step, with the
-    workload's rtol and the main form's cycle and smoother."""
+    workload's rtol and the main form's cycle, smoother and sweep counts."""
     import oracle
     dim, n, m, F, label = sample_step(w, warmup)
     g = oracle.make_grid(dim, n)
-    o = oracle.default_opts(rtol=w.rtol, kcycle_depth=kdepth, smoother=1 if smoother == "mcgs" else 0)
+    o = oracle.default_opts(rtol=w.rtol, kcycle_depth=kdepth, smoother=1 if smoother == "mcgs" else 0,
+                            nu_pre=nu[0], nu_post=nu[1])
     t0 = time.perf_counter()
     rc, out, st = oracle.step(g, o, m, w.alpha, w.dt, F)
     el = time.perf_counter() - t0
     unknowns = 3 * n ** dim
     res = {"value": unknowns / el, "unit": "unknowns*steps/s", "cores": 1, "kind": "oracle",
-           "sample": "%s; assembly, hierarchy, FGMRES(30) to rtol %g with the %s, projection; %d FGMRES "
-                     "iterations; %.1f s on 1 host core (single-threaded C++, -O2)" % (
-                         label, w.rtol, "K-cycle on levels 1..%d" % kdepth if kdepth else "V-cycle", st.iters, el),
+           "sample": "%s; assembly, hierarchy, FGMRES(30) to rtol %g with the %s, (%d,%d) smoothing sweeps, "
+                     "projection; %d FGMRES iterations; %.1f s on 1 host core (single-threaded C++, -O2)" % (
+                         label, w.rtol, "K-cycle on levels 1..%d" % kdepth if kdepth else "V-cycle", nu[0], nu[1],
+                         st.iters, el),
            "seconds": el, "iters": st.iters, "host": host_info()}
     return res, (dim, n, m, F, out, st.iters)
 
@@ -435,9 +453,11 @@ def serve_report(count: int, steps: int, workers: int, prepared=None) -> dict:
     from paper_2608_09102_amd.serve import HipRunner, Server, default_budget
     reqs, inputs = prepared if prepared is not None else serve_inputs(count, steps)
     budget = default_budget(0.9)
-    # FP32-AMG on the factored grid level; the K-cycle on level 1 in 2D, the
-    # V-cycle in 3D (the faster cycle on each, as measured on the benchmark grids)
-    runner = HipRunner(opts_kw=dict(rtol=1e-8, precision="fp32_amg", fine_operator="factored"), workers=workers,
+    # FP32-AMG on the factored grid level, no sweep before and two after the
+    # coarse correction; the K-cycle on level 1 in 2D, the V-cycle in 3D (the
+    # faster settings on each, as measured on the 1024^2 and 128^3 grids)
+    runner = HipRunner(opts_kw=dict(rtol=1e-8, precision="fp32_amg", fine_operator="factored", nu_pre=0,
+                                    nu_post=2), workers=workers,
                        opts_by_dim={2: dict(kcycle_depth=1), 3: dict(kcycle_depth=0)}, inputs=inputs)
     log("[serve] %d requests, %d workers, budget %.1f GB" % (len(reqs), workers, budget / 1e9))
     rep = Server(runner, budget, workers).run(reqs, log=log)
@@ -548,10 +568,10 @@ def main():
         return "%s_%s%s%s" % (prec, "k%d" % kd if kd else "vcycle", "" if sm == "jacobi" else "_" + sm,
                               "" if op == "bsr" else "_" + op.replace("+", "_"))
 
-    def cycle(kd, sm):
-        return "aggregation AMG, %s (1,1), %s" % ("damped block-Jacobi" if sm == "jacobi" else
-                                                  "multicolour block Gauss-Seidel",
-                                                  "K-cycle on levels 1..%d" % kd if kd else "V-cycle")
+    def cycle(kd, sm, op="bsr"):
+        return "aggregation AMG, %s (%d,%d), %s" % (("damped block-Jacobi" if sm == "jacobi" else
+                                                      "multicolour block Gauss-Seidel",) + form_nu(op) +
+                                                     ("K-cycle on levels 1..%d" % kd if kd else "V-cycle",))
     out = {
         "metric": "unknowns*steps/s, FP32-AMG vs FP64 at rel.res 1e-8" if main_form == "fp32_amg"
                   else "unknowns*steps/s (FP64 AMG-FGMRES, rel.res 1e-8)",
@@ -570,11 +590,12 @@ def main():
                    "unknowns": unknowns, "alpha": w.alpha, "dt": w.dt, "rtol": w.rtol,
                    "forcing": "manufactured (resident on the device)" if w.forcing else None,
                    "form": main_form, "hierarchy": "rebuilt every step", "krylov": "FGMRES(30), FP64",
-                   "preconditioner": cycle(main_kd, main_sm),
+                   "preconditioner": cycle(main_kd, main_sm, main_op),
                    "grid_operator": "3x3-block sliced ELL" if main_op.startswith("bsr") else "factored (one block per node)",
-                   "structure_rebuild": {"": "every step, on a second stream beside the step (double-buffered)",
-                                         "serial": "every step, before the assembly",
-                                         "reuse": "once per context"}[main_op.partition("+")[2]]},
+                   "structure_rebuild": ("once per context" if "reuse" in main_op.split("+") else
+                                         "every step, before the assembly" if "serial" in main_op.split("+") else
+                                         "every step, on a second stream beside the step (double-buffered)"),
+                   "large_coarse_levels": "sliced ELL" if "sliced" in main_op.split("+") else "CSR-ordered copy"},
         "iters_per_step": sum(r["iters"]) / len(r["iters"]),
         "iters": r["iters"],
         "levels": r["levels"],
@@ -600,7 +621,7 @@ def main():
                      "value_ratio_main_over_this": value / (unknowns * a.steps / rf["seconds"])}
     if not a.no_cpu_baseline:
         log("[bench] cpu baseline: the oracle on one step")
-        cb, sample = cpu_baseline(w, a.warmup, main_kd, main_sm)
+        cb, sample = cpu_baseline(w, a.warmup, main_kd, main_sm, form_nu(main_op))
         out["cpu_baseline"] = cb
         log("  %s" % cb["sample"])
         # every form's step of the same sample against the oracle's (both at the workload's rtol)
@@ -620,7 +641,7 @@ def main():
                               int(kd), sm, op)
                 sec[form_name(prec, int(kd), sm, op)] = {
                     "value": w2.unknowns * a.steps / rf["seconds"], "ms_per_step": 1e3 * rf["seconds"] / a.steps,
-                    "iters_per_step": sum(rf["iters"]) / len(rf["iters"]), "preconditioner": cycle(int(kd), sm)}
+                    "iters_per_step": sum(rf["iters"]) / len(rf["iters"]), "preconditioner": cycle(int(kd), sm, op)}
             out[w2.name] = sec
         if a.serve_leg_requests > 0:
             out["serving"] = serve_report(a.serve_leg_requests, a.serve_steps, a.workers, prepared)

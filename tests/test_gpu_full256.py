@@ -1,6 +1,7 @@
 """The 256^3 manufactured-solution workload at full size (50,331,648
 unknowns), in the forms the benchmark times (FP32-AMG and FP64; grid level
-stored per node; K-cycle on level 1).
+stored per node; K-cycle on level 1; no smoothing sweep before the coarse
+correction and three after it).
 
 Bars:
 - the aggregates of every level bit for bit against the oracle's aggregation
@@ -54,7 +55,8 @@ def test_full_size_mms3d_256(gpu, orc):
     for prec in ("fp32_amg", "fp64"):
         say("  %s: step" % prec)
         S = gpu.Solver(gpu.make_grid(3, w.n), gpu.default_opts(rtol=w.rtol, project=0, kcycle_depth=1,
-                                                              fine_operator="factored", precision=prec))
+                                                              fine_operator="factored", precision=prec,
+                                                              nu_pre=0, nu_post=3))
         u, s, st = S.step(torch.from_numpy(m).cuda(), w.alpha, w.dt, forcing=torch.from_numpy(F).cuda())
         assert s == gpu.OK
         assert S.num_levels == len(sizes), (S.num_levels, sizes)

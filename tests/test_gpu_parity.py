@@ -79,6 +79,34 @@ def test_setup_bitwise(gpu, orc, case):
             assert np.array_equal(S.aggregates(l), R.agg), (name, l)
 
 
+# smoothing sweeps (before, after) the coarse correction other than one and
+# one: no pre-smoothing (the cycle restricts b itself; the K-cycle's rho update
+# carries no first sweep) and more post-smoothing sweeps
+NU_CASES = [(0, 1), (0, 2), (0, 3), (2, 1), (1, 3)]
+
+
+@pytest.mark.parametrize("nu", NU_CASES, ids=["nu%d%d" % v for v in NU_CASES])
+@pytest.mark.parametrize("kdepth", [0, 1])
+@pytest.mark.parametrize("case", [CASES[0], CASES[3]], ids=[CASES[0][0], CASES[3][0]])
+def test_cycle_sweep_counts(gpu, orc, case, kdepth, nu):
+    """The cycle with other sweep counts, in both grid-level forms, against
+    the oracle's cycle with the same counts (1e-12 relative, the V-cycle bar)."""
+    name, dim, n, h, alpha, dt, kind = case
+    say("[cycle_sweep_counts]", name, "kcycle_depth", kdepth, "nu", nu)
+    m = _field(dim, n, kind)
+    kw = dict(kcycle_depth=kdepth, nu_pre=nu[0], nu_post=nu[1])
+    H = orc.Hierarchy(orc.make_grid(dim, n, h), orc.default_opts(**kw), m, alpha, dt)
+    v = np.random.default_rng(11).standard_normal(m.shape)
+    zr = H.precond(v)
+    for op in ("bsr", "factored"):
+        S = gpu.Solver(gpu.make_grid(dim, n, h), gpu.default_opts(fine_operator=op, **kw))
+        assert S.setup(_cuda(m), alpha, dt) == gpu.OK
+        z = S.precond(_cuda(v)).cpu().numpy()
+        S.close()
+        d = np.abs(z - zr).max() / np.abs(zr).max()
+        assert d <= 1e-12, (op, d)
+
+
 @pytest.mark.parametrize("kdepth", [0, 2, 8])
 @pytest.mark.parametrize("case", CASES[:4], ids=[c[0] for c in CASES[:4]])
 def test_operator_and_vcycle(gpu, orc, case, kdepth):

@@ -33,7 +33,7 @@ def _requests():
 
 # the forms the serving run uses: FP32-AMG with the grid level stored per
 # node; the K-cycle on level 1 in 2D, the V-cycle in 3D
-SERVED = dict(precision="fp32_amg", fine_operator="factored")
+SERVED = dict(precision="fp32_amg", fine_operator="factored", nu_pre=0, nu_post=2)
 SERVED_BY_DIM = {2: dict(kcycle_depth=1), 3: dict(kcycle_depth=0)}
 
 
@@ -71,7 +71,8 @@ def test_served_requests_match_oracle(orc):
     for o in rep["outcomes"]:
         r = by[o.rid]
         g = orc.make_grid(r.dim, r.n)
-        oo = orc.default_opts(rtol=1e-11, kcycle_depth=SERVED_BY_DIM[r.dim]["kcycle_depth"])
+        oo = orc.default_opts(rtol=1e-11, kcycle_depth=SERVED_BY_DIM[r.dim]["kcycle_depth"],
+                              nu_pre=SERVED["nu_pre"], nu_post=SERVED["nu_post"])
         m = r.m0()
         for _ in range(r.steps):
             rc, m, _ = orc.step(g, oo, m, r.alpha, r.dt)
