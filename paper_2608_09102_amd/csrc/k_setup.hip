@@ -202,21 +202,28 @@ __global__ void k_pattern_rp(int64_t n, const int32_t* grp, int32_t* brp) {
   if (i <= n) brp[i] = grp[i] + (int32_t)i;
 }
 
+// Row i of the block pattern: the graph row (ascending, no self loop) with the
+// diagonal inserted in column order.  PC_L lanes share a row: lane sub takes
+// the entries sub, sub + PC_L, ...; an entry past the diagonal moves one slot
+// right, and the lane holding the first such entry writes the diagonal in
+// front of it (lane 0 writes it last when every entry precedes it).  The
+// stores of a row's lanes are contiguous; one thread per row walked its row
+// with a load and a store per step.
+constexpr int PC_L = 8;
 __global__ void k_pattern_cols(int64_t n, const int32_t* grp, const int32_t* gci, const int32_t* brp,
                                int32_t* bci) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t / PC_L;
+  const int sub = (int)(t - i * PC_L);
   if (i >= n) return;
-  int32_t o = brp[i];
-  bool placed = false;
-  for (int32_t k = grp[i]; k < grp[i + 1]; ++k) {
-    int32_t c = gci[k];
-    if (!placed && c > i) {
-      bci[o++] = (int32_t)i;
-      placed = true;
-    }
-    bci[o++] = c;
+  const int32_t k0 = grp[i], k1 = grp[i + 1], o = brp[i];
+  for (int32_t k = k0 + sub; k < k1; k += PC_L) {
+    const int32_t c = gci[k];
+    const bool after = c > (int32_t)i;
+    bci[o + (k - k0) + (after ? 1 : 0)] = c;
+    if (after && (k == k0 || gci[k - 1] < (int32_t)i)) bci[o + (k - k0)] = (int32_t)i;
   }
-  if (!placed) bci[o++] = (int32_t)i;
+  if (sub == 0 && (k1 == k0 || gci[k1 - 1] < (int32_t)i)) bci[o + (k1 - k0)] = (int32_t)i;
 }
 
 // Sliced-ELL structure of the rows rows[0..n) of a CSR pattern (rows == NULL:
@@ -339,7 +346,7 @@ __device__ inline bool propose_node(int64_t i, int sub, int64_t n, const int32_t
       walk = true;
   }
   if (walk) {
-    const uint64_t ri = si.rank;
+    const uint64_t ri = node_rank(i, salt);
     const int32_t mxi = si.mx;
     for (int32_t k0 = kb + sub; k0 < k1; k0 += 4 * G) {
       int32_t jj[4], ww[4];
@@ -360,7 +367,7 @@ __device__ inline bool propose_node(int64_t i, int sub, int64_t n, const int32_t
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         fr[u] = jj[u] >= 0 && sj[u].mate < 0;
-        rr[u] = sj[u].rank;
+        rr[u] = node_rank(jj[u] >= 0 ? jj[u] : i, salt);
         mj[u] = sj[u].mx;
       }
 #pragma unroll
@@ -551,7 +558,6 @@ __global__ void k_match_init(int64_t n, const int32_t* grp, const int32_t* gw, u
   int32_t m = 0;
   for (int32_t k = grp[i]; k < grp[i + 1]; ++k) m = max(m, gw[k]);
   NodeSt r;
-  r.rank = node_rank(i, salt);
   r.mx = m;
   r.mate = -1;
   ns[i] = r;
@@ -1636,7 +1642,7 @@ void launch_pattern_rp(hipStream_t st, int64_t n, const int32_t* grp, int32_t* b
 }
 void launch_pattern_cols(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci,
                          const int32_t* brp, int32_t* bci) {
-  if (n > 0) hipLaunchKernelGGL(k_pattern_cols, dim3(nblk(n)), dim3(TPB), 0, st, n, grp, gci, brp, bci);
+  if (n > 0) hipLaunchKernelGGL(k_pattern_cols, dim3(nblk(n * PC_L)), dim3(TPB), 0, st, n, grp, gci, brp, bci);
 }
 void launch_slice_width(hipStream_t st, int64_t n, const int32_t* rows, const int32_t* brp, int32_t* wslots) {
   const int64_t ns = ceil_div(n, SL);
