@@ -484,7 +484,7 @@ def serve_bench(a, prepared=None):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(requested --gpus %d)" % a.gpus, file=sys.stderr)
         sys.exit(2)
     prepared = None
