@@ -1301,19 +1301,38 @@ __global__ void __launch_bounds__(TPB) k_galerkin_rows(int64_t nc, const int32_t
 #pragma unroll
           for (int x = 0; x < 9; ++x) v[x] = g.fvt[(int64_t)(k0 + e) * 9 + x];
         }
+        // the entries of this stretch that fall into each of the lane's two
+        // slots, as bit masks; then their blocks are fetched from their
+        // lanes in ascending order, as many passes as the wavefront's fullest
+        // mask (every lane takes part in each pass, so every source lane of
+        // a shuffle is active)
         const int n = min(GR_L, len - b);
+        unsigned m0 = 0, m1 = 0;
         for (int u = 0; u < n; ++u) {
           const int32_t A = __shfl(a, u, GR_L);
+          m0 |= (J0 >= 0 && A == J0) ? 1u << u : 0u;
+          m1 |= (J1 >= 0 && A == J1) ? 1u << u : 0u;
+        }
+        while (__any(m0 != 0)) {
+          const int u = m0 ? __ffs(m0) - 1 : 0;
           double f[9];
 #pragma unroll
           for (int x = 0; x < 9; ++x) f[x] = (double)__shfl(v[x], u, GR_L);
-          if (A == J0) {
+          if (m0) {
 #pragma unroll
             for (int x = 0; x < 9; ++x) a0[x] += f[x];
+            m0 &= m0 - 1;
           }
-          if (A == J1) {
+        }
+        while (__any(m1 != 0)) {
+          const int u = m1 ? __ffs(m1) - 1 : 0;
+          double f[9];
+#pragma unroll
+          for (int x = 0; x < 9; ++x) f[x] = (double)__shfl(v[x], u, GR_L);
+          if (m1) {
 #pragma unroll
             for (int x = 0; x < 9; ++x) a1[x] += f[x];
+            m1 &= m1 - 1;
           }
         }
       }
