@@ -1256,7 +1256,7 @@ __global__ void __launch_bounds__(TPB) k_galerkin_slices(int64_t nc, const int32
   }
 }
 
-// Large coarse levels of a coarse level, row by row: GR_L lanes share a
+// Coarse levels of a coarse level, row by row: GR_L lanes share a
 // coarse row I, lane t owning its slots t and t + GR_L (further passes for
 // rows of more than 2 GR_L blocks).  The group walks the fine rows of I's
 // members once: lane e loads entry e of a member row (its column's aggregate
@@ -1799,11 +1799,13 @@ void launch_galerkin(hipStream_t st, Sell C, T* cval, T* cdinv, const int32_t* m
   else                                                                                                         \
     hipLaunchKernelGGL((k_galerkin_slots<T, FACT>), dim3(nblk(C.nslots)), dim3(TPB), 0, st, C.n, C.nslices,      \
                        C.sl_ptr, C.col, cval, cdinv, mptr, mem, F.sl_ptr, F.col, agg, g)
-  // large coarse levels of a coarse level row by row, from its CSR-ordered
-  // copy.  (Level 1 of a grid level stored per node measured faster by slot
+  // the coarse levels of a coarse level row by row, from its CSR-ordered copy
+  // (also the small ones: 24-71 us against 50-310 us by slot, one thread and
+  // one slice bisection each, at 1,000-32,000 rows).  (Level 1 of a grid level
+  // stored per node measured faster by slot
   // groups: its blocks come from K_i, one load per member, and by slot groups
   // 64 coarse rows share the FP64 adds of a wavefront, against 4 row by row.)
-  const bool rows = C.nslices >= 1024 && g.crp && g.cci && !g.fk && g.fvt != nullptr;
+  const bool rows = g.crp && g.cci && !g.fk && g.fvt != nullptr;
   const dim3 rg(nblk(C.n, TPB / GR_L)), rt(TPB);
   if (rows) {
     hipLaunchKernelGGL((k_galerkin_rows<T>), rg, rt, 0, st, C.n, C.sl_ptr, cval, cdinv, mptr, mem, agg, g);
