@@ -542,13 +542,21 @@ int build_structure(llg_ctx& c, Arena& ar) {
     int32_t *crp = L.grp, *cci = L.gci, *cw = L.gw;
     for (int p = 0; p < o.npass; ++p) {
       const uint64_t salt = o.agg_salt ^ (((uint64_t)l << 8) | (uint64_t)p);
-      NodeSt* ns = ar.alloc<NodeSt>(cn);
+      // the first pass of the grid level matches on the grid graph itself,
+      // whose rows the proposal kernel computes instead of loading; it needs
+      // no records, and its first round sets mate and prop of every node
+      const bool on_grid = l == 0 && p == 0 && cn > MATCH_SMALL;
+      NodeSt* ns = on_grid ? nullptr : ar.alloc<NodeSt>(cn);
       int32_t* mate = ar.alloc<int32_t>(cn);
       int32_t* prop = ar.alloc<int32_t>(cn);
       int32_t* id = ar.alloc<int32_t>(cn + 1);
       int32_t* aggp = ar.alloc<int32_t>(cn);
       int32_t* lead = ar.alloc<int32_t>(cn);
-      launch_match_init(st, cn, crp, cw, salt, ns, mate, prop);
+      uint64_t* rank = on_grid ? ar.alloc<uint64_t>(cn) : nullptr;
+      if (on_grid)
+        launch_node_rank(st, cn, salt, rank);
+      else
+        launch_match_init(st, cn, crp, cw, salt, ns, mate, prop);
       LCHK();
       // lanes per node in a proposal round: about two slots per lane on the
       // coarse levels (latency bound), one lane on the grid-sized levels.  A
@@ -557,12 +565,9 @@ int build_structure(llg_ctx& c, Arena& ar) {
       // stop at about 1.25M threads (level 1 of a 128^3 grid: 2 instead of 8).
       int lanes = 1;
       while (lanes < 16 && (int64_t)2 * lanes * cn < cg && (int64_t)2 * lanes * cn <= (int64_t(5) << 18)) lanes *= 2;
-      // the first pass of the grid level matches on the grid graph itself,
-      // whose rows the proposal kernel computes instead of loading
-      const bool on_grid = l == 0 && p == 0;
-      auto propose = [&](int32_t* any) {
+      auto propose = [&](int32_t* any, bool first) {
         if (on_grid)
-          launch_propose_grid(st, nx, ny, nz, mate, salt, o.beta_num, o.beta_den, prop, any);
+          launch_propose_grid(st, nx, ny, nz, mate, rank, salt, o.beta_num, o.beta_den, prop, any, first);
         else
           launch_propose(st, cn, crp, cci, cw, mate, ns, salt, o.beta_num, o.beta_den, prop, any, lanes);
       };
@@ -578,7 +583,7 @@ int build_structure(llg_ctx& c, Arena& ar) {
         int64_t rounds = 0;
         for (;;) {
           launch_fill_i32(st, c.count, 1, 0);
-          propose(c.count);
+          propose(c.count, rounds == 0);
           LCHK();
           HIPX(hipMemcpyAsync(ar.hcount, c.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
           HIPX(hipStreamSynchronize(st));
@@ -593,11 +598,11 @@ int build_structure(llg_ctx& c, Arena& ar) {
         const int64_t rounds = ar.plan->counts[ar.ci++];
         launch_fill_i32(st, c.count + 1, 1, 0);
         for (int64_t r = 0; r < rounds; ++r) {
-          propose(c.count + 1);
+          propose(c.count + 1, r == 0);
           launch_accept(st, cn, prop, mate, ns);
         }
         launch_fill_i32(st, c.count, 1, 0);
-        propose(c.count);
+        propose(c.count, rounds == 0);
         launch_check_eq(st, c.count, 0, ar.flag, F_PLAN);
         LCHK();
       }

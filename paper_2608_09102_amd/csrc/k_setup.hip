@@ -296,9 +296,60 @@ __device__ inline bool key_before(const EdgeKey& a, const EdgeKey& b, uint64_t s
   return a.hi < b.hi;
 }
 
-// Handshake round: every free node proposes its best available edge (both
-// endpoints free, strong for the first-visited endpoint).  Neighbours are
-// examined four at a time so that their loads are in flight together.
+// The earliest candidate edge of node i (largest weight mxi) over the row
+// slots [kb, k1) that lane sub of its G lanes visits (every G-th slot); best
+// and bk are updated in place.  Neighbours are examined four at a time so
+// that their loads are in flight together.
+template <int G>
+__device__ inline void row_best(int64_t i, int sub, int32_t mxi, int32_t kb, int32_t k1,
+                                const int32_t* __restrict__ gci, const int32_t* __restrict__ gw,
+                                const NodeSt* __restrict__ ns, uint64_t salt, int32_t bnum, int32_t bden,
+                                int32_t& best, EdgeKey& bk) {
+  const uint64_t ri = node_rank(i, salt);
+  for (int32_t k0 = kb + sub; k0 < k1; k0 += 4 * G) {
+    int32_t jj[4], ww[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool ok = k0 + u * G < k1;
+      jj[u] = ok ? gci[k0 + u * G] : -1;
+      ww[u] = ok ? gw[k0 + u * G] : 0;
+    }
+    // the candidates' records, all four loads issued together (a padding
+    // slot reads node i's own record and is masked)
+    NodeSt sj[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) sj[u] = ns[jj[u] >= 0 ? jj[u] : i];
+    bool fr[4];
+    uint64_t rr[4];
+    int32_t mj[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      fr[u] = jj[u] >= 0 && sj[u].mate < 0;
+      rr[u] = node_rank(jj[u] >= 0 ? jj[u] : i, salt);
+      mj[u] = sj[u].mx;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (!fr[u]) continue;
+      const int32_t j = jj[u], w = ww[u];
+      const uint64_t rj = rr[u];
+      const bool ifirst = ri != rj ? ri < rj : i < j;
+      const int32_t mf = ifirst ? mxi : mj[u];
+      if ((int64_t)bden * w < (int64_t)bnum * mf) continue;
+      EdgeKey e;
+      e.rank = ifirst ? ri : rj;
+      e.first = ifirst ? (int32_t)i : j;
+      e.w = w;
+      e.lo = (int32_t)min((int64_t)j, i);
+      e.hi = (int32_t)max((int64_t)j, i);
+      if (best < 0 || key_before(e, bk, salt)) {
+        bk = e;
+        best = j;
+      }
+    }
+  }
+}
+
 // One handshake round: every free node proposes its earliest candidate edge
 // (strong for its first-visited endpoint, other end free).  G lanes share a
 // node (coarse levels: their rows are long and the dependent loads of a row
@@ -314,8 +365,8 @@ __device__ inline bool propose_node(int64_t i, int sub, int64_t n, const int32_t
                                     int32_t bnum, int32_t bden, int32_t* __restrict__ prop) {
   int32_t best = -1;
   EdgeKey bk{};
-  // matched nodes (most of them after the first rounds) read only their
-  // 4-byte mate; a free node then reads its record.  A free node that finds
+  // matched nodes (most of them after the first rounds) read only their mate
+  // and proposal; a free node then reads its record.  A free node that finds
   // no candidate is marked dead (mate -2): candidate edges are fixed and free
   // nodes only get matched, so it will not find one later, and its row is
   // not walked again.  Every reader of mate takes a negative value as
@@ -345,52 +396,7 @@ __device__ inline bool propose_node(int64_t i, int sub, int64_t n, const int32_t
     else
       walk = true;
   }
-  if (walk) {
-    const uint64_t ri = node_rank(i, salt);
-    const int32_t mxi = si.mx;
-    for (int32_t k0 = kb + sub; k0 < k1; k0 += 4 * G) {
-      int32_t jj[4], ww[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const bool ok = k0 + u * G < k1;
-        jj[u] = ok ? gci[k0 + u * G] : -1;
-        ww[u] = ok ? gw[k0 + u * G] : 0;
-      }
-      // the candidates' records, all four loads issued together (a padding
-      // slot reads node i's own record and is masked)
-      NodeSt sj[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) sj[u] = ns[jj[u] >= 0 ? jj[u] : i];
-      bool fr[4];
-      uint64_t rr[4];
-      int32_t mj[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        fr[u] = jj[u] >= 0 && sj[u].mate < 0;
-        rr[u] = node_rank(jj[u] >= 0 ? jj[u] : i, salt);
-        mj[u] = sj[u].mx;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (!fr[u]) continue;
-        const int32_t j = jj[u], w = ww[u];
-        const uint64_t rj = rr[u];
-        const bool ifirst = ri != rj ? ri < rj : i < j;
-        const int32_t mf = ifirst ? mxi : mj[u];
-        if ((int64_t)bden * w < (int64_t)bnum * mf) continue;
-        EdgeKey e;
-        e.rank = ifirst ? ri : rj;
-        e.first = ifirst ? (int32_t)i : j;
-        e.w = w;
-        e.lo = (int32_t)min((int64_t)j, i);
-        e.hi = (int32_t)max((int64_t)j, i);
-        if (best < 0 || key_before(e, bk, salt)) {
-          bk = e;
-          best = j;
-        }
-      }
-    }
-  }
+  if (walk) row_best<G>(i, sub, si.mx, kb, k1, gci, gw, ns, salt, bnum, bden, best, bk);
 #pragma unroll
   for (int off = 1; off < G; off <<= 1) {
     if (!walk) break;  // uniform over the node's lanes
@@ -406,11 +412,15 @@ __device__ inline bool propose_node(int64_t i, int sub, int64_t n, const int32_t
       best = ob;
     }
   }
+  // prop changes only where a node walks (a node proposing again finds its
+  // proposal there) and once where a node got matched: its proposal, which
+  // names its mate, is cleared so that the accept pass can skip it
   const bool proposed = i < n && sub == 0 && best >= 0;
-  if (i < n && sub == 0) {
+  if (walk && sub == 0) {
     prop[i] = best;
-    if (mi == -1 && best < 0) mate[i] = -2;
+    if (best < 0) mate[i] = -2;
   }
+  if (i < n && sub == 0 && mi >= 0 && pj >= 0) prop[i] = -1;
   return proposed;
 }
 
@@ -432,6 +442,49 @@ __global__ void __launch_bounds__(TPB) k_propose(int64_t n, const int32_t* __res
   if ((threadIdx.x & 63) == 0 && ballot && __atomic_load_n(count, __ATOMIC_RELAXED) == 0) atomicOr(count, 1);
 }
 
+// The round with one lane per node (the levels whose rows are short).  A
+// wavefront pays for a row walk when any of its lanes walks, which most do
+// for ten rounds while a fifth to a third of the nodes walk; so, as in
+// k_propose_grid, the workgroup lists its walkers in LDS (with the record
+// and row bounds loaded beside the last proposal's mate) and its first
+// threads walk them.  The decisions are those of propose_node.
+__global__ void __launch_bounds__(TPB) k_propose_packed(int64_t n, const int32_t* __restrict__ grp,
+                                                        const int32_t* __restrict__ gci,
+                                                        const int32_t* __restrict__ gw, int32_t* __restrict__ mate,
+                                                        const NodeSt* __restrict__ ns, uint64_t salt, int32_t bnum,
+                                                        int32_t bden, int32_t* __restrict__ prop, int32_t* count) {
+  __shared__ int4 s_walk[TPB];  // node, largest weight, row start, row end
+  __shared__ int s_nw;
+  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+  if (threadIdx.x == 0) s_nw = 0;
+  __syncthreads();
+  bool proposed = false;
+  if (i < n) {
+    const int32_t mi = mate[i], pj = prop[i];
+    if (mi >= 0 && pj >= 0) prop[i] = -1;  // matched in the last round
+    if (mi == -1) {
+      const NodeSt si = ns[i];
+      const int32_t kb = grp[i], k1 = grp[i + 1];
+      if (pj >= 0 && mate[pj] < 0)
+        proposed = true;
+      else
+        s_walk[atomicAdd(&s_nw, 1)] = make_int4((int32_t)i, si.mx, kb, k1);
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < s_nw) {
+    const int4 wk = s_walk[threadIdx.x];
+    int32_t best = -1;
+    EdgeKey bk{};
+    row_best<1>(wk.x, 0, wk.y, wk.z, wk.w, gci, gw, ns, salt, bnum, bden, best, bk);
+    prop[wk.x] = best;
+    if (best < 0) mate[wk.x] = -2;
+    proposed = proposed || best >= 0;
+  }
+  const unsigned long long ballot = __ballot(proposed);
+  if ((threadIdx.x & 63) == 0 && ballot && __atomic_load_n(count, __ATOMIC_RELAXED) == 0) atomicOr(count, 1);
+}
+
 // The same round on the grid graph itself (the first pass of the grid level):
 // its rows are the grid neighbours in ascending order, every weight is 1, so
 // every node's largest weight is 1 (a grid of one node has no row), and a
@@ -440,60 +493,99 @@ __global__ void __launch_bounds__(TPB) k_propose(int64_t n, const int32_t* __res
 // loaded.  mate stands in for the record's copy of it: the two differ only
 // where a dead node (no candidate) holds -2, and both are negative there.
 // The decisions are those of propose_node on the stored grid graph.
-__global__ void __launch_bounds__(TPB) k_propose_grid(int nx, int ny, int nz, int32_t* __restrict__ mate,
-                                                      uint64_t salt, int32_t bnum, int32_t bden,
-                                                      int32_t* __restrict__ prop, int32_t* count) {
-  const int64_t N = (int64_t)nx * ny * nz;
-  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  int32_t best = -1;
-  // a node's last proposal is one of its neighbours, so the neighbours'
-  // mates, loaded once the node is known to be free, also tell whether that
-  // proposal is still free: two dependent loads per node
-  const int32_t mi = i < N ? mate[i] : 0;
-  const int32_t pj = i < N ? prop[i] : -1;
-  bool walk = false;
-  int64_t nb[6];
-  int32_t mj[6];
+//
+// The walk is arithmetic (the coordinates, the key comparisons) and a
+// wavefront pays for it when any of its lanes walks, which most do for ten
+// rounds while only a fifth to a third of the nodes walk.  So the workgroup
+// first sorts its nodes out: matched and dead nodes stop, a node whose last
+// proposal is still free proposes it again (prop already holds it), and the
+// rest are listed in LDS and walked by the workgroup's first threads.  The
+// ranks are read from rank[] (node_rank of every node, written once per
+// pass): seven hashes per walk cost more than seven loads.
+// Round one (first != 0) finds every node free with nothing proposed, loads
+// no mates and writes both prop and mate of every node: no initialisation
+// pass is needed.
+__device__ inline int grid_nbrs32(unsigned nx, unsigned ny, unsigned nz, unsigned p, unsigned* nb) {
+  const unsigned nxy = nx * ny;
+  const unsigned k = p / nxy, r = p - k * nxy;
+  const unsigned j = r / nx, i = r - j * nx;
   int c = 0;
-  if (i < N && mi == -1) {
-    c = grid_nbrs(nx, ny, nz, i, nb);
-#pragma unroll
-    for (int u = 0; u < 6; ++u) mj[u] = u < c ? mate[nb[u]] : 0;
-    bool again = false;
-#pragma unroll
-    for (int u = 0; u < 6; ++u) again = again || (u < c && nb[u] == pj && mj[u] < 0);
-    if (again)
-      best = pj;
-    else
-      walk = true;
+  if (k > 0) nb[c++] = p - nxy;
+  if (j > 0) nb[c++] = p - nx;
+  if (i > 0) nb[c++] = p - 1;
+  if (i + 1 < nx) nb[c++] = p + 1;
+  if (j + 1 < ny) nb[c++] = p + nx;
+  if (k + 1 < nz) nb[c++] = p + nxy;
+  return c;
+}
+
+__global__ void __launch_bounds__(TPB) k_propose_grid(int nx, int ny, int nz, int32_t* __restrict__ mate,
+                                                      const uint64_t* __restrict__ rank, uint64_t salt,
+                                                      int32_t bnum, int32_t bden, int32_t* __restrict__ prop,
+                                                      int32_t* count, int first) {
+  __shared__ unsigned s_walk[TPB];
+  __shared__ int s_nw;
+  const unsigned N = (unsigned)nx * ny * nz;
+  const unsigned i = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+  if (threadIdx.x == 0) s_nw = 0;
+  __syncthreads();
+  bool proposed = false;
+  if (i < N) {
+    bool walk = first != 0;
+    if (!walk) {
+      const int32_t mi = mate[i], pj = prop[i];
+      if (mi >= 0 && pj >= 0) prop[i] = -1;  // matched in the last round
+      if (mi == -1) {
+        if (pj >= 0 && mate[pj] < 0)
+          proposed = true;
+        else
+          walk = true;
+      }
+    }
+    if (walk) s_walk[atomicAdd(&s_nw, 1)] = i;
   }
-  if (walk) {
-    const uint64_t ri = node_rank(i, salt);
+  __syncthreads();
+  const int nw = s_nw;
+  if ((int)threadIdx.x < nw) {
+    const unsigned w = s_walk[threadIdx.x];
+    unsigned nb[6];
+    const int c = grid_nbrs32(nx, ny, nz, w, nb);
+    int32_t mj[6];
+    uint64_t rr[6];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      mj[u] = (u < c && !first) ? mate[nb[u]] : -1;
+      rr[u] = rank[u < c ? nb[u] : w];
+    }
+    const uint64_t ri = rank[w];
+    int32_t best = -1;
     EdgeKey bk{};
 #pragma unroll
     for (int u = 0; u < 6; ++u) {
       if (u >= c || mj[u] >= 0) continue;
-      const int32_t j = (int32_t)nb[u];
-      const uint64_t rj = node_rank(j, salt);
-      const bool ifirst = ri != rj ? ri < rj : i < j;
       if ((int64_t)bden < (int64_t)bnum) continue;  // weight 1 against the largest weight 1
+      const int32_t j = (int32_t)nb[u];
+      const uint64_t rj = rr[u];
+      const bool wfirst = ri != rj ? ri < rj : w < (unsigned)j;
       EdgeKey e;
-      e.rank = ifirst ? ri : rj;
-      e.first = ifirst ? (int32_t)i : j;
+      e.rank = wfirst ? ri : rj;
+      e.first = wfirst ? (int32_t)w : j;
       e.w = 1;
-      e.lo = (int32_t)min((int64_t)j, i);
-      e.hi = (int32_t)max((int64_t)j, i);
+      e.lo = min((int32_t)w, j);
+      e.hi = max((int32_t)w, j);
       if (best < 0 || key_before(e, bk, salt)) {
         bk = e;
         best = j;
       }
     }
+    prop[w] = best;
+    if (best < 0)
+      mate[w] = -2;
+    else if (first)
+      mate[w] = -1;
+    proposed = proposed || best >= 0;
   }
-  if (i < N) {
-    prop[i] = best;
-    if (mi == -1 && best < 0) mate[i] = -2;
-  }
-  const unsigned long long ballot = __ballot(i < N && best >= 0);
+  const unsigned long long ballot = __ballot(proposed);
   if ((threadIdx.x & 63) == 0 && ballot && __atomic_load_n(count, __ATOMIC_RELAXED) == 0) atomicOr(count, 1);
 }
 
@@ -531,6 +623,7 @@ __global__ void __launch_bounds__(MATCH_T) k_match_small(int64_t n, const int32_
       break;
     }
     for (int64_t i = tid; i < n; i += MATCH_T) {
+      if (mate[i] != -1) continue;
       const int32_t pi = prop[i];
       if (pi >= 0 && prop[pi] == (int32_t)i) {
         mate[i] = pi;
@@ -541,13 +634,16 @@ __global__ void __launch_bounds__(MATCH_T) k_match_small(int64_t n, const int32_
   }
 }
 
+// Only prop is read: dead nodes hold -1 there, and the proposal round after
+// a match clears the matched nodes' proposals.  ns is null on the grid pass,
+// whose proposal rounds read no records.
 __global__ void k_accept(int64_t n, const int32_t* prop, int32_t* mate, NodeSt* ns) {
   const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int32_t p = prop[i];
   if (p >= 0 && prop[p] == (int32_t)i) {
     mate[i] = p;
-    ns[i].mate = p;
+    if (ns) ns[i].mate = p;
   }
 }
 
@@ -1692,15 +1788,16 @@ void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t
   else if (G == 2)
     LLG_PR(2);
   else
-    LLG_PR(1);
+    hipLaunchKernelGGL(k_propose_packed, dim3(nblk(n)), dim3(TPB), 0, st, n, grp, gci, gw, mate, ns, salt, bnum,
+                       bden, prop, count);
 #undef LLG_PR
 }
-void launch_propose_grid(hipStream_t st, int nx, int ny, int nz, int32_t* mate, uint64_t salt, int32_t bnum,
-                         int32_t bden, int32_t* prop, int32_t* count) {
+void launch_propose_grid(hipStream_t st, int nx, int ny, int nz, int32_t* mate, const uint64_t* rank,
+                         uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop, int32_t* count, bool first) {
   const int64_t N = (int64_t)nx * ny * nz;
   if (N > 0)
-    hipLaunchKernelGGL(k_propose_grid, dim3(nblk(N)), dim3(TPB), 0, st, nx, ny, nz, mate, salt, bnum, bden, prop,
-                       count);
+    hipLaunchKernelGGL(k_propose_grid, dim3(nblk(N)), dim3(TPB), 0, st, nx, ny, nz, mate, rank, salt, bnum, bden,
+                       prop, count, first ? 1 : 0);
 }
 void launch_match_small(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci, const int32_t* gw,
                         int32_t* mate, NodeSt* ns, uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop,

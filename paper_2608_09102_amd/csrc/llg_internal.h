@@ -201,9 +201,11 @@ void launch_propose(hipStream_t st, int64_t n, const int32_t* grp, const int32_t
                     int32_t* mate, const NodeSt* ns, uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop,
                     int32_t* any, int lanes);
 // The same round on the grid graph of an nx x ny x nz grid (weights 1): the
-// neighbours and visiting ranks are computed, the records are not read.
-void launch_propose_grid(hipStream_t st, int nx, int ny, int nz, int32_t* mate, uint64_t salt, int32_t bnum,
-                         int32_t bden, int32_t* prop, int32_t* any);
+// neighbours are computed, the visiting ranks read from rank (node_rank of
+// every node under salt), no records are read.  The first round (first)
+// also sets mate of every node; prop and mate need no initialisation.
+void launch_propose_grid(hipStream_t st, int nx, int ny, int nz, int32_t* mate, const uint64_t* rank,
+                         uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop, int32_t* any, bool first);
 // Every round of the matching of a small level (n <= MATCH_SMALL) in one
 // workgroup, with 2 lanes per node (G >= 2) or 1; raises flag bit if it did
 // not end within n rounds.
