@@ -692,98 +692,21 @@ __global__ void k_cg_count(int64_t nc, const int32_t* lead, const int32_t* mate,
 }
 
 // Coarse graph row I: (agg(j), w) over the rows of the (one or two) members,
-// sorted by coarse column, duplicates summed, the diagonal dropped.  Rows of
-// up to 32 (or 64) candidates are sorted in registers by a bitonic network
-// (their padding sorts last); longer rows by insertion into their output range.
-template <int CM>
-__device__ __forceinline__ int32_t cg_row_small(int32_t I, int32_t c, int32_t ka, int32_t na, int32_t kb,
-                                       const int32_t* __restrict__ gci, const int32_t* __restrict__ gw,
-                                       const int32_t* __restrict__ agg, int32_t* cj, int32_t* cw, int32_t o) {
-  int32_t J[CM], W[CM];
-#pragma unroll
-  for (int e = 0; e < CM; ++e) {
-    J[e] = 0x7fffffff;
-    W[e] = 0;
-    if (e < c) {
-      const int32_t k = e < na ? ka + e : kb + (e - na);
-      J[e] = agg[gci[k]];
-      W[e] = gw[k];
-    }
-  }
-#pragma unroll
-  for (int k = 2; k <= CM; k <<= 1) {
-#pragma unroll
-    for (int jj = k >> 1; jj > 0; jj >>= 1) {
-#pragma unroll
-      for (int e = 0; e < CM; ++e) {
-        const int f = e ^ jj;
-        if (f > e) {
-          const bool up = (e & k) == 0;
-          const bool sw = up ? (J[e] > J[f]) : (J[e] < J[f]);
-          const int32_t j0 = J[e], j1 = J[f], w0 = W[e], w1 = W[f];
-          J[e] = sw ? j1 : j0;
-          J[f] = sw ? j0 : j1;
-          W[e] = sw ? w1 : w0;
-          W[f] = sw ? w0 : w1;
-        }
-      }
-    }
-  }
-  int32_t u = 0, cur = -1, sum = 0;
-#pragma unroll
-  for (int e = 0; e < CM; ++e) {
-    if (e < c && J[e] != I) {
-      if (u > 0 && J[e] == cur) {
-        sum += W[e];
-      } else {
-        if (u > 0) {
-          cj[o + u - 1] = cur;
-          cw[o + u - 1] = sum;
-        }
-        cur = J[e];
-        sum = W[e];
-        ++u;
-      }
-    }
-  }
-  if (u > 0) {
-    cj[o + u - 1] = cur;
-    cw[o + u - 1] = sum;
-  }
-  return u;
-}
-
-// CMAX: the widest register sort the kernel carries (32, or 64 for the coarse
-// levels of 3D grids, whose rows reach about 50 candidates; 64 costs twice
-// the registers, so the 2D levels and the 3D grid level keep 32).  Longer
-// rows fall back to insertion into their output range.
-template <int CMAX>
-__device__ __forceinline__ void cg_fill_row(int64_t I, const int32_t* lead, const int32_t* mate, const int32_t* grp,
-                                   const int32_t* gci, const int32_t* gw, const int32_t* agg,
-                                   const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt) {
-  const int32_t a = lead[I], b = mate[a];
-  const int32_t o = cptr[I];
-  const int32_t ka = grp[a], na = grp[a + 1] - ka;
-  const int32_t kb = b >= 0 ? grp[b] : 0, nb = b >= 0 ? grp[b + 1] - kb : 0;
-  const int32_t nall = na + nb;
-  if (nall <= 8) {
-    ucnt[I] = cg_row_small<8>((int32_t)I, nall, ka, na, kb, gci, gw, agg, cj, cw, o);
-    return;
-  }
-  if (nall <= 16) {
-    ucnt[I] = cg_row_small<16>((int32_t)I, nall, ka, na, kb, gci, gw, agg, cj, cw, o);
-    return;
-  }
-  if (nall <= 32) {
-    ucnt[I] = cg_row_small<32>((int32_t)I, nall, ka, na, kb, gci, gw, agg, cj, cw, o);
-    return;
-  }
-  if constexpr (CMAX >= 64) {
-    if (nall <= 64) {
-      ucnt[I] = cg_row_small<64>((int32_t)I, nall, ka, na, kb, gci, gw, agg, cj, cw, o);
-      return;
-    }
-  }
+// sorted by coarse column, duplicates summed, the diagonal dropped, written
+// at cj/cw[cptr[I]...] (room for every candidate) with its length in
+// ucnt[I].
+//
+// G lanes take a row: they read the members' rows with contiguous loads and
+// insert the candidates into a hash table of T slots in LDS (open
+// addressing; equal columns meet in one slot, whose integer weight sums
+// them, so the order of the insertions does not matter).  The table's
+// entries are then compacted and each is written at its rank among them,
+// which sorts the row.  A row has 10-30 candidates and 8-27 entries on the
+// grid hierarchies; a row of more than T candidates (none on them) is built
+// by its first lane with insertion into its output range.
+__device__ int32_t cg_row_insert(int32_t I, int32_t a, int32_t b, const int32_t* __restrict__ grp,
+                                 const int32_t* __restrict__ gci, const int32_t* __restrict__ gw,
+                                 const int32_t* __restrict__ agg, int32_t* cj, int32_t* cw, int32_t o) {
   int32_t c = 0;
   for (int mem = 0; mem < 2; ++mem) {
     const int32_t v = mem == 0 ? a : b;
@@ -791,7 +714,6 @@ __device__ __forceinline__ void cg_fill_row(int64_t I, const int32_t* lead, cons
     for (int32_t k = grp[v]; k < grp[v + 1]; ++k) {
       const int32_t J = agg[gci[k]];
       const int32_t w = gw[k];
-      // insertion into the sorted prefix
       int32_t q = c;
       while (q > 0 && cj[o + q - 1] > J) {
         cj[o + q] = cj[o + q - 1];
@@ -806,7 +728,7 @@ __device__ __forceinline__ void cg_fill_row(int64_t I, const int32_t* lead, cons
   int32_t u = 0;
   for (int32_t q = 0; q < c; ++q) {
     const int32_t J = cj[o + q], w = cw[o + q];
-    if (J == (int32_t)I) continue;
+    if (J == I) continue;
     if (u > 0 && cj[o + u - 1] == J) {
       cw[o + u - 1] += w;
     } else {
@@ -815,22 +737,99 @@ __device__ __forceinline__ void cg_fill_row(int64_t I, const int32_t* lead, cons
       ++u;
     }
   }
-  ucnt[I] = u;
+  return u;
 }
-__global__ void k_cg_fill(int64_t nc, const int32_t* lead, const int32_t* mate, const int32_t* grp,
-                          const int32_t* gci, const int32_t* gw, const int32_t* agg, const int32_t* cptr,
-                          int32_t* cj, int32_t* cw, int32_t* ucnt) {
-  const int64_t I = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (I < nc) cg_fill_row<32>(I, lead, mate, grp, gci, gw, agg, cptr, cj, cw, ucnt);
-}
-// the 64-wide sort needs about 256 registers: bounded to TPB threads so that
-// it has them without spilling
-__global__ void __launch_bounds__(TPB) k_cg_fill_wide(int64_t nc, const int32_t* lead, const int32_t* mate,
-                                                      const int32_t* grp, const int32_t* gci, const int32_t* gw,
-                                                      const int32_t* agg, const int32_t* cptr, int32_t* cj,
-                                                      int32_t* cw, int32_t* ucnt) {
-  const int64_t I = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (I < nc) cg_fill_row<64>(I, lead, mate, grp, gci, gw, agg, cptr, cj, cw, ucnt);
+
+template <int G, int T>
+__global__ void __launch_bounds__(TPB) k_cg_fill(int64_t nc, const int32_t* __restrict__ lead,
+                                                 const int32_t* __restrict__ mate, const int32_t* __restrict__ grp,
+                                                 const int32_t* __restrict__ gci, const int32_t* __restrict__ gw,
+                                                 const int32_t* __restrict__ agg, const int32_t* __restrict__ cptr,
+                                                 int32_t* cj, int32_t* cw, int32_t* ucnt) {
+  static_assert(TPB % G == 0 && T % G == 0 && (T & (T - 1)) == 0, "table shape");
+  constexpr int R = TPB / G;   // rows per workgroup
+  constexpr int PS = T / G;    // table slots per lane
+  constexpr int TB = __builtin_ctz(T);
+  __shared__ int32_t s_key[R * T];
+  __shared__ int32_t s_wt[R * T];
+  __shared__ int2 s_ent[R * T];
+  const int r = (int)threadIdx.x / G, lane = (int)threadIdx.x % G;
+  const int64_t I = (int64_t)xcd_block(blockIdx.x, gridDim.x) * R + r;
+  int32_t* key = s_key + r * T;
+  int32_t* wt = s_wt + r * T;
+  int2* ent = s_ent + r * T;
+#pragma unroll
+  for (int q = 0; q < PS; ++q) {
+    key[lane * PS + q] = -1;
+    wt[lane * PS + q] = 0;
+  }
+  int32_t a = 0, b = -1, ka = 0, na = 0, kb = 0, nb = 0, o = 0;
+  if (I < nc) {
+    a = lead[I];
+    o = cptr[I];
+    b = mate[a];
+    ka = grp[a];
+    na = grp[a + 1] - ka;
+    if (b >= 0) {
+      kb = grp[b];
+      nb = grp[b + 1] - kb;
+    }
+  }
+  const int32_t c = na + nb;
+  const bool small = I < nc && c <= T;  // the same on the row's lanes
+  __syncthreads();
+  if (small) {
+    for (int32_t e = lane; e < c; e += G) {
+      const int32_t k = e < na ? ka + e : kb + (e - na);
+      const int32_t J = agg[gci[k]], w = gw[k];
+      if (J == (int32_t)I) continue;
+      unsigned h = ((unsigned)J * 0x9E3779B1u) >> (32 - TB);
+      // at most c <= T distinct columns: a free slot or J's own is found
+      for (;;) {
+        const int32_t old = atomicCAS(&key[h], -1, J);
+        if (old == -1 || old == J) {
+          atomicAdd(&wt[h], w);
+          break;
+        }
+        h = (h + 1) & (T - 1);
+      }
+    }
+  }
+  __syncthreads();
+  // compact the occupied slots (each lane holds PS consecutive ones)
+  int32_t kk[PS], ww[PS];
+  int cl = 0;
+#pragma unroll
+  for (int q = 0; q < PS; ++q) {
+    kk[q] = key[lane * PS + q];
+    ww[q] = wt[lane * PS + q];
+    cl += kk[q] != -1;
+  }
+  int incl = cl;
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+    const int v = __shfl_up(incl, off, G);
+    if (lane >= off) incl += v;
+  }
+  const int u = __shfl(incl, G - 1, G);
+  int pos = incl - cl;
+#pragma unroll
+  for (int q = 0; q < PS; ++q)
+    if (kk[q] != -1) ent[pos++] = make_int2(kk[q], ww[q]);
+  __syncthreads();
+  if (small) {
+    // columns are distinct: an entry's rank is its place in the sorted row
+    for (int t = lane; t < u; t += G) {
+      const int2 v = ent[t];
+      int rk = 0;
+      for (int x = 0; x < u; ++x) rk += ent[x].x < v.x;
+      cj[o + rk] = v.x;
+      cw[o + rk] = v.y;
+    }
+    if (lane == 0) ucnt[I] = u;
+  } else if (I < nc && lane == 0) {
+    ucnt[I] = cg_row_insert((int32_t)I, a, b, grp, gci, gw, agg, cj, cw, o);
+  }
 }
 
 // The rows' entries moved to their final offsets; CG_L lanes share a row so
@@ -1832,12 +1831,15 @@ void launch_cg_fill(hipStream_t st, int64_t nc, const int32_t* lead, const int32
                     const int32_t* grp, const int32_t* gci, const int32_t* gw, const int32_t* agg,
                     const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt, int wide) {
   if (nc <= 0) return;
+  // the grid level's rows, and all rows in 2D, have up to about 20
+  // candidates: eight lanes and 32 slots; the coarse levels of 3D grids up
+  // to about 50: sixteen lanes and 64 slots
   if (wide)
-    hipLaunchKernelGGL(k_cg_fill_wide, dim3(nblk(nc)), dim3(TPB), 0, st, nc, lead, mate, grp, gci, gw, agg, cptr,
-                       cj, cw, ucnt);
+    hipLaunchKernelGGL((k_cg_fill<16, 64>), dim3(nblk(nc, TPB / 16)), dim3(TPB), 0, st, nc, lead, mate, grp, gci,
+                       gw, agg, cptr, cj, cw, ucnt);
   else
-    hipLaunchKernelGGL(k_cg_fill, dim3(nblk(nc)), dim3(TPB), 0, st, nc, lead, mate, grp, gci, gw, agg, cptr,
-                       cj, cw, ucnt);
+    hipLaunchKernelGGL((k_cg_fill<8, 32>), dim3(nblk(nc, TPB / 8)), dim3(TPB), 0, st, nc, lead, mate, grp, gci, gw,
+                       agg, cptr, cj, cw, ucnt);
 }
 void launch_cg_copy(hipStream_t st, int64_t nc, const int32_t* cptr, const int32_t* cj,
                     const int32_t* cw, const int32_t* nrp, int32_t* nci, int32_t* nw) {
