@@ -538,6 +538,8 @@ int build_structure(llg_ctx& c, Arena& ar) {
     const int64_t n = L.A.n;
     if (n <= o.max_coarse || l + 1 >= o.max_levels) break;
     int32_t* acc = ar.alloc<int32_t>(n);
+    const int32_t* leads[MAX_PASS] = {};
+    const int32_t* mates[MAX_PASS] = {};
     int64_t cn = n, cg = L.gnnz;
     int32_t *crp = L.grp, *cci = L.gci, *cw = L.gw;
     for (int p = 0; p < o.npass; ++p) {
@@ -620,15 +622,18 @@ int build_structure(llg_ctx& c, Arena& ar) {
       int32_t* cwt = ar.alloc<int32_t>(ncand);
       int32_t* nrp = ar.alloc<int32_t>(nc + 1);
       // rows of the coarse levels of a 3D grid reach about 50 candidates
-      launch_cg_fill(st, nc, lead, mate, crp, cci, cw, aggp, cnt, cj, cwt, nrp, nz > 1 && l > 0);
+      const int gdims[3] = {nx, ny, nz};
+      launch_cg_fill(st, nc, lead, mate, crp, cci, cw, aggp, cnt, cj, cwt, nrp, nz > 1 && l > 0,
+                     l == 0 && p == 0 ? gdims : nullptr);
       launch_scan_excl(st, nrp, nrp, nc, nrp + nc, c.scan_tmp);
       LCHK();
       const int64_t ng = ar.count(nrp + nc);
       int32_t* nci = ar.alloc<int32_t>(ng);
       int32_t* nw = ar.alloc<int32_t>(ng);
       launch_cg_copy(st, nc, cnt, cj, cwt, nrp, nci, nw);
-      launch_compose(st, n, acc, aggp, p == 0);
       LCHK();
+      leads[p] = lead;
+      mates[p] = mate;
       cn = nc;
       cg = ng;
       crp = nrp;
@@ -636,16 +641,12 @@ int build_structure(llg_ctx& c, Arena& ar) {
       cw = nw;
     }
     if ((double)cn > o.stagnation * (double)n) break;
-    // members of the composite aggregates, ascending
+    // members of the composite aggregates, ascending, and the composite map
     int32_t* mptr = ar.alloc<int32_t>(cn + 1);
-    int32_t* cursor = ar.alloc<int32_t>(cn);
     int32_t* mem = ar.alloc<int32_t>(n);
-    launch_fill_i32(st, mptr, cn + 1, 0);
-    launch_fill_i32(st, cursor, cn, 0);
-    launch_member_count(st, n, acc, mptr);
+    launch_member_count(st, cn, o.npass, leads, mates, mptr);
     launch_scan_excl(st, mptr, mptr, cn, mptr + cn, c.scan_tmp);
-    launch_member_fill(st, n, acc, mptr, cursor, mem);
-    launch_member_sort(st, cn, mptr, mem);
+    launch_member_fill(st, cn, o.npass, leads, mates, mptr, mem, acc);
     LCHK();
     L.agg = acc;
     L.mptr = mptr;

@@ -740,12 +740,26 @@ __device__ int32_t cg_row_insert(int32_t I, int32_t a, int32_t b, const int32_t*
   return u;
 }
 
-template <int G, int T>
+// The t-th grid neighbour of node v, in the order of grid_nbrs32.
+__device__ inline unsigned grid_nbr_at(unsigned nx, unsigned ny, unsigned nz, unsigned v, int t) {
+  unsigned nb[6];
+  const int c = grid_nbrs32(nx, ny, nz, v, nb);
+  unsigned r = nb[0];
+#pragma unroll
+  for (int u = 1; u < 6; ++u)
+    if (u < c && u == t) r = nb[u];
+  return r;
+}
+
+// GRID: the first pass of the grid level, whose graph is the grid graph
+// (weights 1): the members' neighbours are computed from the grid sizes
+// instead of read from the stored rows.
+template <int G, int T, bool GRID>
 __global__ void __launch_bounds__(TPB) k_cg_fill(int64_t nc, const int32_t* __restrict__ lead,
                                                  const int32_t* __restrict__ mate, const int32_t* __restrict__ grp,
                                                  const int32_t* __restrict__ gci, const int32_t* __restrict__ gw,
                                                  const int32_t* __restrict__ agg, const int32_t* __restrict__ cptr,
-                                                 int32_t* cj, int32_t* cw, int32_t* ucnt) {
+                                                 int32_t* cj, int32_t* cw, int32_t* ucnt, int nx, int ny, int nz) {
   static_assert(TPB % G == 0 && T % G == 0 && (T & (T - 1)) == 0, "table shape");
   constexpr int R = TPB / G;   // rows per workgroup
   constexpr int PS = T / G;    // table slots per lane
@@ -780,8 +794,15 @@ __global__ void __launch_bounds__(TPB) k_cg_fill(int64_t nc, const int32_t* __re
   __syncthreads();
   if (small) {
     for (int32_t e = lane; e < c; e += G) {
-      const int32_t k = e < na ? ka + e : kb + (e - na);
-      const int32_t J = agg[gci[k]], w = gw[k];
+      int32_t J, w;
+      if constexpr (GRID) {
+        J = agg[grid_nbr_at(nx, ny, nz, e < na ? a : b, e < na ? e : e - na)];
+        w = 1;
+      } else {
+        const int32_t k = e < na ? ka + e : kb + (e - na);
+        J = agg[gci[k]];
+        w = gw[k];
+      }
       if (J == (int32_t)I) continue;
       unsigned h = ((unsigned)J * 0x9E3779B1u) >> (32 - TB);
       // at most c <= T distinct columns: a free slot or J's own is found
@@ -848,39 +869,84 @@ __global__ void k_cg_copy(int64_t nc, const int32_t* cptr, const int32_t* cj, co
   }
 }
 
-__global__ void k_compose(int64_t n, int32_t* acc, const int32_t* aggp, int first) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  acc[i] = first ? aggp[i] : aggp[acc[i]];
-}
+// Members of the composite aggregates, from the passes' own records: an
+// aggregate of pass p is its leader (a node, or an aggregate of pass p - 1)
+// and the leader's mate when it has one, so the fine nodes of a composite
+// aggregate I are found by expanding I through the passes, last to first.
+// The 2^NP slots of the expansion (absent members -1) are sorted, so the
+// members come out ascending; the fill also writes the composite map acc.
+struct PassMaps {
+  const int32_t* lead[MAX_PASS];
+  const int32_t* mate[MAX_PASS];
+};
 
-__global__ void k_member_count(int64_t n, const int32_t* agg, int32_t* cnt) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) atomicAdd(&cnt[agg[i]], 1);
-}
-
-__global__ void k_member_fill(int64_t n, const int32_t* agg, const int32_t* mptr, int32_t* cursor,
-                              int32_t* mem) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int32_t a = agg[i];
-  const int32_t pos = atomicAdd(&cursor[a], 1);
-  mem[mptr[a] + pos] = (int32_t)i;
-}
-
-// Members of each aggregate in ascending order (at most 2^npass of them).
-__global__ void k_member_sort(int64_t nc, const int32_t* mptr, int32_t* mem) {
-  int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nc) return;
-  const int32_t o = mptr[I], c = mptr[I + 1] - o;
-  for (int32_t a = 1; a < c; ++a) {
-    const int32_t v = mem[o + a];
-    int32_t q = a;
-    while (q > 0 && mem[o + q - 1] > v) {
-      mem[o + q] = mem[o + q - 1];
-      --q;
+template <int NP>
+__device__ inline int expand_members(int32_t I, const PassMaps& pm, int32_t (&m)[1 << NP]) {
+  m[0] = I;
+#pragma unroll
+  for (int q = NP - 1; q >= 0; --q) {
+    const int c = 1 << (NP - 1 - q);  // slots filled before pass q's expansion
+#pragma unroll
+    for (int x = (1 << NP) / 2 - 1; x >= 0; --x) {
+      if (x >= c) continue;
+      const int32_t A = m[x];
+      int32_t L = -1, M = -1;
+      if (A >= 0) {
+        L = pm.lead[q][A];
+        const int32_t mm = pm.mate[q][L];
+        M = mm >= 0 ? mm : -1;
+      }
+      m[2 * x] = L;
+      m[2 * x + 1] = M;
     }
-    mem[o + q] = v;
+  }
+  int cnt = 0;
+#pragma unroll
+  for (int x = 0; x < (1 << NP); ++x) {
+    cnt += m[x] >= 0;
+    if (m[x] < 0) m[x] = 0x7fffffff;
+  }
+#pragma unroll
+  for (int k = 2; k <= (1 << NP); k <<= 1) {
+#pragma unroll
+    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+#pragma unroll
+      for (int e = 0; e < (1 << NP); ++e) {
+        const int f = e ^ jj;
+        if (f > e) {
+          const bool up = (e & k) == 0;
+          const int32_t a = m[e], b = m[f];
+          const bool sw = up ? a > b : a < b;
+          m[e] = sw ? b : a;
+          m[f] = sw ? a : b;
+        }
+      }
+    }
+  }
+  return cnt;
+}
+
+template <int NP>
+__global__ void k_member_count(int64_t nc, PassMaps pm, int32_t* cnt) {
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  int32_t m[1 << NP];
+  cnt[I] = expand_members<NP>((int32_t)I, pm, m);
+}
+
+template <int NP>
+__global__ void k_member_fill(int64_t nc, PassMaps pm, const int32_t* mptr, int32_t* mem, int32_t* acc) {
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  int32_t m[1 << NP];
+  const int c = expand_members<NP>((int32_t)I, pm, m);
+  const int32_t o = mptr[I];
+#pragma unroll
+  for (int x = 0; x < (1 << NP); ++x) {
+    if (x < c) {
+      mem[o + x] = m[x];
+      acc[m[x]] = (int32_t)I;
+    }
   }
 }
 
@@ -1829,35 +1895,55 @@ void launch_cg_count(hipStream_t st, int64_t nc, const int32_t* lead, const int3
 }
 void launch_cg_fill(hipStream_t st, int64_t nc, const int32_t* lead, const int32_t* mate,
                     const int32_t* grp, const int32_t* gci, const int32_t* gw, const int32_t* agg,
-                    const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt, int wide) {
+                    const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt, int wide, const int* grid) {
   if (nc <= 0) return;
   // the grid level's rows, and all rows in 2D, have up to about 20
   // candidates: eight lanes and 32 slots; the coarse levels of 3D grids up
   // to about 50: sixteen lanes and 64 slots
   if (wide)
-    hipLaunchKernelGGL((k_cg_fill<16, 64>), dim3(nblk(nc, TPB / 16)), dim3(TPB), 0, st, nc, lead, mate, grp, gci,
-                       gw, agg, cptr, cj, cw, ucnt);
+    hipLaunchKernelGGL((k_cg_fill<16, 64, false>), dim3(nblk(nc, TPB / 16)), dim3(TPB), 0, st, nc, lead, mate, grp,
+                       gci, gw, agg, cptr, cj, cw, ucnt, 0, 0, 0);
+  else if (grid)
+    hipLaunchKernelGGL((k_cg_fill<8, 32, true>), dim3(nblk(nc, TPB / 8)), dim3(TPB), 0, st, nc, lead, mate, grp, gci,
+                       gw, agg, cptr, cj, cw, ucnt, grid[0], grid[1], grid[2]);
   else
-    hipLaunchKernelGGL((k_cg_fill<8, 32>), dim3(nblk(nc, TPB / 8)), dim3(TPB), 0, st, nc, lead, mate, grp, gci, gw,
-                       agg, cptr, cj, cw, ucnt);
+    hipLaunchKernelGGL((k_cg_fill<8, 32, false>), dim3(nblk(nc, TPB / 8)), dim3(TPB), 0, st, nc, lead, mate, grp,
+                       gci, gw, agg, cptr, cj, cw, ucnt, 0, 0, 0);
 }
 void launch_cg_copy(hipStream_t st, int64_t nc, const int32_t* cptr, const int32_t* cj,
                     const int32_t* cw, const int32_t* nrp, int32_t* nci, int32_t* nw) {
   if (nc > 0)
     hipLaunchKernelGGL(k_cg_copy, dim3(nblk(nc * CG_L)), dim3(TPB), 0, st, nc, cptr, cj, cw, nrp, nci, nw);
 }
-void launch_compose(hipStream_t st, int64_t n, int32_t* acc, const int32_t* aggp, int first) {
-  if (n > 0) hipLaunchKernelGGL(k_compose, dim3(nblk(n)), dim3(TPB), 0, st, n, acc, aggp, first);
+static PassMaps pass_maps(int np, const int32_t* const* lead, const int32_t* const* mate) {
+  PassMaps pm{};
+  for (int q = 0; q < np; ++q) {
+    pm.lead[q] = lead[q];
+    pm.mate[q] = mate[q];
+  }
+  return pm;
 }
-void launch_member_count(hipStream_t st, int64_t n, const int32_t* agg, int32_t* cnt) {
-  if (n > 0) hipLaunchKernelGGL(k_member_count, dim3(nblk(n)), dim3(TPB), 0, st, n, agg, cnt);
+void launch_member_count(hipStream_t st, int64_t nc, int np, const int32_t* const* lead,
+                         const int32_t* const* mate, int32_t* cnt) {
+  if (nc <= 0) return;
+  const PassMaps pm = pass_maps(np, lead, mate);
+  if (np == 1)
+    hipLaunchKernelGGL(k_member_count<1>, dim3(nblk(nc)), dim3(TPB), 0, st, nc, pm, cnt);
+  else if (np == 2)
+    hipLaunchKernelGGL(k_member_count<2>, dim3(nblk(nc)), dim3(TPB), 0, st, nc, pm, cnt);
+  else
+    hipLaunchKernelGGL(k_member_count<3>, dim3(nblk(nc)), dim3(TPB), 0, st, nc, pm, cnt);
 }
-void launch_member_fill(hipStream_t st, int64_t n, const int32_t* agg, const int32_t* mptr,
-                        int32_t* cursor, int32_t* mem) {
-  if (n > 0) hipLaunchKernelGGL(k_member_fill, dim3(nblk(n)), dim3(TPB), 0, st, n, agg, mptr, cursor, mem);
-}
-void launch_member_sort(hipStream_t st, int64_t nc, const int32_t* mptr, int32_t* mem) {
-  if (nc > 0) hipLaunchKernelGGL(k_member_sort, dim3(nblk(nc)), dim3(TPB), 0, st, nc, mptr, mem);
+void launch_member_fill(hipStream_t st, int64_t nc, int np, const int32_t* const* lead,
+                        const int32_t* const* mate, const int32_t* mptr, int32_t* mem, int32_t* acc) {
+  if (nc <= 0) return;
+  const PassMaps pm = pass_maps(np, lead, mate);
+  if (np == 1)
+    hipLaunchKernelGGL(k_member_fill<1>, dim3(nblk(nc)), dim3(TPB), 0, st, nc, pm, mptr, mem, acc);
+  else if (np == 2)
+    hipLaunchKernelGGL(k_member_fill<2>, dim3(nblk(nc)), dim3(TPB), 0, st, nc, pm, mptr, mem, acc);
+  else
+    hipLaunchKernelGGL(k_member_fill<3>, dim3(nblk(nc)), dim3(TPB), 0, st, nc, pm, mptr, mem, acc);
 }
 
 template <typename T>

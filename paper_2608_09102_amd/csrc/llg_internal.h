@@ -221,16 +221,25 @@ void launch_assign(hipStream_t st, int64_t n, const int32_t* mate, const int32_t
                    int32_t* lead);
 void launch_cg_count(hipStream_t st, int64_t nc, const int32_t* lead, const int32_t* mate,
                      const int32_t* grp, int32_t* cnt);
+// Coarse graph rows at the candidate offsets cptr (cj, cw; lengths ucnt).
+// wide: the coarse levels of a 3D grid (rows of up to about 50 candidates);
+// grid: {nx, ny, nz} when the graph is the grid graph itself (the grid
+// level's first pass; its rows are then computed), else null.
 void launch_cg_fill(hipStream_t st, int64_t nc, const int32_t* lead, const int32_t* mate,
                     const int32_t* grp, const int32_t* gci, const int32_t* gw, const int32_t* agg,
-                    const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt, int wide);
+                    const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt, int wide,
+                    const int* grid = nullptr);
 void launch_cg_copy(hipStream_t st, int64_t nc, const int32_t* cptr, const int32_t* cj,
                     const int32_t* cw, const int32_t* nrp, int32_t* nci, int32_t* nw);
-void launch_compose(hipStream_t st, int64_t n, int32_t* acc, const int32_t* aggp, int first);
-void launch_member_count(hipStream_t st, int64_t n, const int32_t* agg, int32_t* cnt);
-void launch_member_fill(hipStream_t st, int64_t n, const int32_t* agg, const int32_t* mptr,
-                        int32_t* cursor, int32_t* mem);
-void launch_member_sort(hipStream_t st, int64_t nc, const int32_t* mptr, int32_t* mem);
+// Members of the composite aggregates of a level after np passes, from each
+// pass's leaders (lead[q][a]: the leader of aggregate a of pass q, a node of
+// pass q's graph) and mates: cnt[I] = the number of fine nodes of aggregate
+// I; then, with mptr the exclusive scan of cnt, mem[mptr[I]..] = its fine
+// nodes ascending and acc[i] = the aggregate of fine node i.
+void launch_member_count(hipStream_t st, int64_t nc, int np, const int32_t* const* lead,
+                         const int32_t* const* mate, int32_t* cnt);
+void launch_member_fill(hipStream_t st, int64_t nc, int np, const int32_t* const* lead,
+                        const int32_t* const* mate, const int32_t* mptr, int32_t* mem, int32_t* acc);
 
 // assembly of the fine operator (FP64 A) and the scaled level-0 operator,
 // the right-hand side b and the initial guess u; the frozen field is m
