@@ -313,7 +313,6 @@ struct llg_ctx {
   double* prm = nullptr;          // device: alpha, dt
   double* hprm = nullptr;         // pinned staging for prm
   double* min = nullptr;          // device copy of m^n read by the setup graph
-  double* fin = nullptr;          // device copy of the forcing
   double* mprv = nullptr;         // device copy of m^{n-1} (BDF2)
   // stray field: padded grid, transformed tensor (once per context) and work
   llg::FieldDims fd;
@@ -533,6 +532,10 @@ int build_structure(llg_ctx& c, Arena& ar) {
   finish_sell(ar, st, L0, c.scan_tmp, grid);
 
   int l = 0;
+  // the matching state of the next pass's nodes, set by the coarse-graph
+  // fill of the pass before (null: set it here)
+  NodeSt* ns_next = nullptr;
+  int32_t *mate_next = nullptr, *prop_next = nullptr;
   for (;; ++l) {
     Level& L = c.lv[l];
     const int64_t n = L.A.n;
@@ -548,16 +551,18 @@ int build_structure(llg_ctx& c, Arena& ar) {
       // whose rows the proposal kernel computes instead of loading; it needs
       // no records, and its first round sets mate and prop of every node
       const bool on_grid = l == 0 && p == 0 && cn > MATCH_SMALL;
-      NodeSt* ns = on_grid ? nullptr : ar.alloc<NodeSt>(cn);
-      int32_t* mate = ar.alloc<int32_t>(cn);
-      int32_t* prop = ar.alloc<int32_t>(cn);
+      const bool preset = ns_next != nullptr;
+      NodeSt* ns = preset ? ns_next : on_grid ? nullptr : ar.alloc<NodeSt>(cn);
+      int32_t* mate = preset ? mate_next : ar.alloc<int32_t>(cn);
+      int32_t* prop = preset ? prop_next : ar.alloc<int32_t>(cn);
+      ns_next = nullptr;
       int32_t* id = ar.alloc<int32_t>(cn + 1);
       int32_t* aggp = ar.alloc<int32_t>(cn);
       int32_t* lead = ar.alloc<int32_t>(cn);
       uint64_t* rank = on_grid ? ar.alloc<uint64_t>(cn) : nullptr;
       if (on_grid)
         launch_node_rank(st, cn, salt, rank);
-      else
+      else if (!preset)
         launch_match_init(st, cn, crp, cw, salt, ns, mate, prop);
       LCHK();
       // lanes per node in a proposal round: about two slots per lane on the
@@ -623,8 +628,12 @@ int build_structure(llg_ctx& c, Arena& ar) {
       int32_t* nrp = ar.alloc<int32_t>(nc + 1);
       // rows of the coarse levels of a 3D grid reach about 50 candidates
       const int gdims[3] = {nx, ny, nz};
+      // the next pass (of this level or the next) starts from these nodes
+      ns_next = ar.alloc<NodeSt>(nc);
+      mate_next = ar.alloc<int32_t>(nc);
+      prop_next = ar.alloc<int32_t>(nc);
       launch_cg_fill(st, nc, lead, mate, crp, cci, cw, aggp, cnt, cj, cwt, nrp, nz > 1 && l > 0,
-                     l == 0 && p == 0 ? gdims : nullptr);
+                     l == 0 && p == 0 ? gdims : nullptr, ns_next, mate_next, prop_next);
       launch_scan_excl(st, nrp, nrp, nc, nrp + nc, c.scan_tmp);
       LCHK();
       const int64_t ng = ar.count(nrp + nc);
@@ -891,7 +900,7 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
   c.ks.hinv = ar.lazy<double>(R + 2);
   c.ks.coef = ar.lazy<double>(2 * R + 4);
   c.delta = ar.lazy<double>(R + 2);
-  c.prm = ar.lazy<double>(8);
+  c.prm = ar.lazy<double>(PRM_WORDS);
   if (f32)
     plan_tail<float>(c, c.ta32);
   else
@@ -902,8 +911,9 @@ void allocate_numeric(llg_ctx& c, Arena& ar) {
     c.nhat = ar.lazy<double>(6 * P);
     c.fwork = (double2*)ar.lazy<double>(4 * P);  // two packed complex planes
   }
+  // copies of m^n (and m^{n-1}) for the field terms of llg_step_field, whose
+  // captured kernels read them at fixed addresses
   c.min = ar.lazy<double>(m);
-  c.fin = ar.lazy<double>(m);
   if (c.opts.scheme == LLG_SCHEME_BDF2) c.mprv = ar.lazy<double>(m);
 }
 
@@ -1057,8 +1067,8 @@ void setup_values(llg_ctx& c, const double* m, const double* mprev, const double
   {
     KTimer kt(c, LLG_KT_ASSEMBLE);
     launch_assemble<T>(st, g.n[0], g.n[1], g.n[2], 1.0 / (g.h * g.h), c.prm, c.opts.left_scale,
-                       c.opts.x0_is_mn, m, mprev, F, L0.A, c.Aval, (T*)L0.val, c.dinv0, (T*)L0.dinv, c.b, c.u,
-                       c.flags, c.Mh, (T*)L0.kf, (T*)L0.knm, c.mt);
+                       c.opts.x0_is_mn, L0.A, c.Aval, (T*)L0.val, c.dinv0, (T*)L0.dinv, c.b, c.u, c.flags, c.Mh,
+                       (T*)L0.kf, (T*)L0.knm, c.mt);
     if (c.f1) {
       launch_member_nbr_aggs(st, GridDims{g.n[0], g.n[1], g.n[2]}, L0.mem, L0.agg, L0.nagg);
       launch_member_fields<T>(st, L0.A.n, L0.mem, c.mt, (T*)L0.mtq);
@@ -1154,7 +1164,10 @@ hipGraphExec_t try_capture(llg_ctx& c, Fn body) {
 
 // alpha, the time-step factors dt' = dt (BDF1) or 2 dt / 3 (BDF2) of the
 // right-hand side and dt' eps of the operator, and the field parameters
-void write_params(llg_ctx& c, double alpha, double dt, bool bdf2 = false, const llg_field* fld = nullptr) {
+// The step's parameters, and the device addresses of its inputs (bit
+// patterns in prm[8..10], read by the assembly kernel).
+void write_params(llg_ctx& c, double alpha, double dt, bool bdf2, const llg_field* fld, const double* m,
+                  const double* mprev, const double* F) {
   const double dtp = bdf2 ? (2.0 * dt) / 3.0 : dt;
   c.hprm[0] = alpha;
   c.hprm[1] = fld ? dtp * fld->eps : dtp;
@@ -1162,13 +1175,18 @@ void write_params(llg_ctx& c, double alpha, double dt, bool bdf2 = false, const 
   c.hprm[3] = fld ? fld->q : 0.0;
   for (int k = 0; k < 3; ++k) c.hprm[4 + k] = fld ? fld->h_ext[k] : 0.0;
   c.hprm[7] = 0.0;
-  HIPX(hipMemcpyAsync(c.prm, c.hprm, 8 * sizeof(double), hipMemcpyHostToDevice, c.st));
+  const double* in[3] = {m, mprev, F};
+  for (int k = 0; k < 3; ++k) std::memcpy(&c.hprm[8 + k], &in[k], sizeof(double));
+  c.hprm[11] = 0.0;
+  HIPX(hipMemcpyAsync(c.prm, c.hprm, PRM_WORDS * sizeof(double), hipMemcpyHostToDevice, c.st));
 }
 
-// The setup of one step from the internal copies of m^n (and F).
+// The setup of one step: the assembly reads the inputs at the addresses in
+// the parameter block, the field terms the internal copies of m^n (and
+// m^{n-1}).  forcing only selects the captured graph.
 template <typename T>
 void run_setup(llg_ctx& c, bool forcing, bool bdf2 = false, int field = 0) {
-  const double* F = forcing ? c.fin : nullptr;
+  const double* F = nullptr;
   const double* mp = bdf2 ? c.mprv : nullptr;
   if (use_graphs(c)) {
     hipGraphExec_t& gx = c.setup_graph[(forcing ? 1 : 0) + (bdf2 ? 2 : 0) + (field ? 4 : 0) + (field == 2 ? 8 : 0)];
@@ -1809,10 +1827,11 @@ llg_status run_step(llg_ctx& c, const double* m_n, const double* m_nm1, double a
   c.ev_used = 0;
   const int64_t fb = (int64_t)sizeof(double) * 3 * c.N;
   const bool bdf2 = c.opts.scheme == LLG_SCHEME_BDF2 && m_nm1 != nullptr;
-  HIPX(hipMemcpyAsync(c.min, m_n, fb, hipMemcpyDeviceToDevice, c.st));
-  if (F) HIPX(hipMemcpyAsync(c.fin, F, fb, hipMemcpyDeviceToDevice, c.st));
-  if (bdf2) HIPX(hipMemcpyAsync(c.mprv, m_nm1, fb, hipMemcpyDeviceToDevice, c.st));
-  write_params(c, alpha, dt, bdf2, fld);
+  if (fld) {  // the field terms read m^n (and m^{n-1}) at fixed addresses
+    HIPX(hipMemcpyAsync(c.min, m_n, fb, hipMemcpyDeviceToDevice, c.st));
+    if (bdf2) HIPX(hipMemcpyAsync(c.mprv, m_nm1, fb, hipMemcpyDeviceToDevice, c.st));
+  }
+  write_params(c, alpha, dt, bdf2, fld, m_n, bdf2 ? m_nm1 : nullptr, F);
   launch_fill_i32(c.st, c.flags, 1, 0);
   LCHK();
   const int field = fld ? (fld->stray ? 2 : 1) : 0;
@@ -1967,7 +1986,7 @@ llg_status llg_create(const llg_grid* grid, const llg_opts* opts, void* d_worksp
     c->omega = opts->omega > 0 ? opts->omega : (grid->dim == 2 ? 4.0 / 5.0 : 6.0 / 7.0);
     HIPX(hipHostMalloc((void**)&c->host, sizeof(double) * 16, hipHostMallocDefault));
     HIPX(hipHostMalloc((void**)&c->hflags, sizeof(int32_t) * 4, hipHostMallocDefault));
-    HIPX(hipHostMalloc((void**)&c->hprm, sizeof(double) * 8, hipHostMallocDefault));
+    HIPX(hipHostMalloc((void**)&c->hprm, sizeof(double) * PRM_WORDS, hipHostMallocDefault));
     HIPX(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
     HIPX(hipEventCreateWithFlags(&c->it_ev, hipEventDisableTiming));
     c->it_graph.assign(opts->restart, nullptr);
@@ -2042,8 +2061,7 @@ llg_status llg_setup(llg_ctx* ctx, const double* d_m_tilde, double alpha, double
       !std::isfinite(alpha))
     return LLG_ERR_INVALID_ARG;
   return guard([&]() -> llg_status {
-    HIPX(hipMemcpyAsync(ctx->min, d_m_tilde, sizeof(double) * 3 * ctx->N, hipMemcpyDeviceToDevice, ctx->st));
-    write_params(*ctx, alpha, dt);
+    write_params(*ctx, alpha, dt, false, nullptr, d_m_tilde, nullptr, nullptr);
     launch_fill_i32(ctx->st, ctx->flags, 1, 0);
     if (ctx->opts.precision == LLG_PREC_FP32_AMG)
       run_setup<float>(*ctx, false);

@@ -759,7 +759,8 @@ __global__ void __launch_bounds__(TPB) k_cg_fill(int64_t nc, const int32_t* __re
                                                  const int32_t* __restrict__ mate, const int32_t* __restrict__ grp,
                                                  const int32_t* __restrict__ gci, const int32_t* __restrict__ gw,
                                                  const int32_t* __restrict__ agg, const int32_t* __restrict__ cptr,
-                                                 int32_t* cj, int32_t* cw, int32_t* ucnt, int nx, int ny, int nz) {
+                                                 int32_t* cj, int32_t* cw, int32_t* ucnt, int nx, int ny, int nz,
+                                                 NodeSt* nsn, int32_t* maten, int32_t* propn) {
   static_assert(TPB % G == 0 && T % G == 0 && (T & (T - 1)) == 0, "table shape");
   constexpr int R = TPB / G;   // rows per workgroup
   constexpr int PS = T / G;    // table slots per lane
@@ -838,6 +839,7 @@ __global__ void __launch_bounds__(TPB) k_cg_fill(int64_t nc, const int32_t* __re
   for (int q = 0; q < PS; ++q)
     if (kk[q] != -1) ent[pos++] = make_int2(kk[q], ww[q]);
   __syncthreads();
+  int32_t mx = 0;  // the row's largest weight
   if (small) {
     // columns are distinct: an entry's rank is its place in the sorted row
     for (int t = lane; t < u; t += G) {
@@ -846,10 +848,22 @@ __global__ void __launch_bounds__(TPB) k_cg_fill(int64_t nc, const int32_t* __re
       for (int x = 0; x < u; ++x) rk += ent[x].x < v.x;
       cj[o + rk] = v.x;
       cw[o + rk] = v.y;
+      mx = max(mx, v.y);
     }
     if (lane == 0) ucnt[I] = u;
-  } else if (I < nc && lane == 0) {
-    ucnt[I] = cg_row_insert((int32_t)I, a, b, grp, gci, gw, agg, cj, cw, o);
+  }
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) mx = max(mx, __shfl_xor(mx, off, G));
+  if (!small && I < nc && lane == 0) {
+    const int32_t ub = cg_row_insert((int32_t)I, a, b, grp, gci, gw, agg, cj, cw, o);
+    ucnt[I] = ub;
+    for (int32_t q = 0; q < ub; ++q) mx = max(mx, cw[o + q]);
+  }
+  // the next pass's matching state of node I (what k_match_init writes)
+  if (nsn && I < nc && lane == 0) {
+    nsn[I] = NodeSt{mx, -1};
+    maten[I] = -1;
+    propn[I] = -1;
   }
 }
 
@@ -1075,9 +1089,7 @@ __global__ void k_cls_gather(int64_t n, const int32_t* __restrict__ rows, const 
 // initial guess written alongside.
 template <typename T>
 __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* __restrict__ prm,
-                           int left_scale, int x0_is_mn, const double* __restrict__ mn,
-                           const double* __restrict__ mprev, const double* __restrict__ F,
-                           const int32_t* __restrict__ sl_ptr,
+                           int left_scale, int x0_is_mn, const int32_t* __restrict__ sl_ptr,
                            const int32_t* __restrict__ col, double* __restrict__ Aval,
                            T* __restrict__ Lval, double* __restrict__ dinv0, T* __restrict__ ldinv,
                            double* __restrict__ b, double* __restrict__ u, int32_t* flag,
@@ -1087,6 +1099,11 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
   const int64_t N = (int64_t)nx * ny * nz;
   if (p >= N) return;
   const double alpha = prm[0], dt = prm[1];
+  // the step's inputs, by address (the caller's buffers): m^n, m^{n-1} or
+  // null, F or null
+  const double* __restrict__ mn = (const double*)(uintptr_t)__double_as_longlong(prm[8]);
+  const double* __restrict__ mprev = (const double*)(uintptr_t)__double_as_longlong(prm[9]);
+  const double* __restrict__ F = (const double*)(uintptr_t)__double_as_longlong(prm[10]);
   // frozen field: m^n (BDF1) or 2 m^n - m^{n-1} (BDF2, mprev != NULL)
   double mt[3], bb[3];
   bool fin = true;
@@ -1895,20 +1912,21 @@ void launch_cg_count(hipStream_t st, int64_t nc, const int32_t* lead, const int3
 }
 void launch_cg_fill(hipStream_t st, int64_t nc, const int32_t* lead, const int32_t* mate,
                     const int32_t* grp, const int32_t* gci, const int32_t* gw, const int32_t* agg,
-                    const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt, int wide, const int* grid) {
+                    const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt, int wide, const int* grid,
+                    NodeSt* nsn, int32_t* maten, int32_t* propn) {
   if (nc <= 0) return;
   // the grid level's rows, and all rows in 2D, have up to about 20
   // candidates: eight lanes and 32 slots; the coarse levels of 3D grids up
   // to about 50: sixteen lanes and 64 slots
   if (wide)
     hipLaunchKernelGGL((k_cg_fill<16, 64, false>), dim3(nblk(nc, TPB / 16)), dim3(TPB), 0, st, nc, lead, mate, grp,
-                       gci, gw, agg, cptr, cj, cw, ucnt, 0, 0, 0);
+                       gci, gw, agg, cptr, cj, cw, ucnt, 0, 0, 0, nsn, maten, propn);
   else if (grid)
     hipLaunchKernelGGL((k_cg_fill<8, 32, true>), dim3(nblk(nc, TPB / 8)), dim3(TPB), 0, st, nc, lead, mate, grp, gci,
-                       gw, agg, cptr, cj, cw, ucnt, grid[0], grid[1], grid[2]);
+                       gw, agg, cptr, cj, cw, ucnt, grid[0], grid[1], grid[2], nsn, maten, propn);
   else
     hipLaunchKernelGGL((k_cg_fill<8, 32, false>), dim3(nblk(nc, TPB / 8)), dim3(TPB), 0, st, nc, lead, mate, grp,
-                       gci, gw, agg, cptr, cj, cw, ucnt, 0, 0, 0);
+                       gci, gw, agg, cptr, cj, cw, ucnt, 0, 0, 0, nsn, maten, propn);
 }
 void launch_cg_copy(hipStream_t st, int64_t nc, const int32_t* cptr, const int32_t* cj,
                     const int32_t* cw, const int32_t* nrp, int32_t* nci, int32_t* nw) {
@@ -1948,22 +1966,19 @@ void launch_member_fill(hipStream_t st, int64_t nc, int np, const int32_t* const
 
 template <typename T>
 void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, const double* prm,
-                     int left_scale, int x0_is_mn, const double* m, const double* mprev, const double* F,
-                     Sell A, double* Aval, T* Lval, double* dinv0, T* ldinv, double* b, double* u,
-                     int32_t* flag, double* Mh, T* K, T* Knm, double* mt_out) {
+                     int left_scale, int x0_is_mn, Sell A, double* Aval, T* Lval, double* dinv0, T* ldinv,
+                     double* b, double* u, int32_t* flag, double* Mh, T* K, T* Knm, double* mt_out) {
   const int64_t N = (int64_t)nx * ny * nz;
   hipLaunchKernelGGL((k_assemble<T>), dim3(nblk(N)), dim3(TPB), 0, st, nx, ny, nz, inv_h2, prm,
-                     left_scale, x0_is_mn, m, mprev, F, A.sl_ptr, A.col, Aval, Lval, dinv0, ldinv, b, u, flag, Mh,
+                     left_scale, x0_is_mn, A.sl_ptr, A.col, Aval, Lval, dinv0, ldinv, b, u, flag, Mh,
                      K, Knm, mt_out);
 }
-template void launch_assemble<double>(hipStream_t, int, int, int, double, const double*, int, int,
-                                      const double*, const double*, const double*, Sell, double*, double*,
-                                      double*, double*, double*, double*, int32_t*, double*, double*, double*,
-                                      double*);
-template void launch_assemble<float>(hipStream_t, int, int, int, double, const double*, int, int,
-                                     const double*, const double*, const double*, Sell, double*, float*,
-                                     double*, float*, double*, double*, int32_t*, double*, float*, float*,
-                                     double*);
+template void launch_assemble<double>(hipStream_t, int, int, int, double, const double*, int, int, Sell,
+                                      double*, double*, double*, double*, double*, double*, int32_t*, double*,
+                                      double*, double*, double*);
+template void launch_assemble<float>(hipStream_t, int, int, int, double, const double*, int, int, Sell,
+                                     double*, float*, double*, float*, double*, double*, int32_t*, double*,
+                                     float*, float*, double*);
 
 void init_kernel_attributes() {
   const size_t lds_max = (size_t)(GJ_LDS_MAX * GJ_LDS_MAX + GJ_LDS_MAX + GJ_T) * sizeof(double) +

@@ -20,6 +20,7 @@ namespace llg {
 
 constexpr int SL = 64;          // rows per slice (wavefront size)
 constexpr int MAX_PASS = 3;     // pairwise matching passes per level
+constexpr int PRM_WORDS = 12;   // the step's parameter block (8 values, 3 input addresses, 1 spare)
 constexpr int RED_BLOCKS = 1024;  // fixed partial-sum count of grid reductions
 
 struct Sell {
@@ -224,11 +225,13 @@ void launch_cg_count(hipStream_t st, int64_t nc, const int32_t* lead, const int3
 // Coarse graph rows at the candidate offsets cptr (cj, cw; lengths ucnt).
 // wide: the coarse levels of a 3D grid (rows of up to about 50 candidates);
 // grid: {nx, ny, nz} when the graph is the grid graph itself (the grid
-// level's first pass; its rows are then computed), else null.
+// level's first pass; its rows are then computed), else null.  nsn, maten,
+// propn (or null): the next matching pass's state of the coarse nodes, set
+// as launch_match_init would set it on the new graph.
 void launch_cg_fill(hipStream_t st, int64_t nc, const int32_t* lead, const int32_t* mate,
                     const int32_t* grp, const int32_t* gci, const int32_t* gw, const int32_t* agg,
-                    const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt, int wide,
-                    const int* grid = nullptr);
+                    const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt, int wide, const int* grid,
+                    NodeSt* nsn, int32_t* maten, int32_t* propn);
 void launch_cg_copy(hipStream_t st, int64_t nc, const int32_t* cptr, const int32_t* cj,
                     const int32_t* cw, const int32_t* nrp, int32_t* nci, int32_t* nw);
 // Members of the composite aggregates of a level after np passes, from each
@@ -250,11 +253,13 @@ void launch_member_fill(hipStream_t st, int64_t nc, int np, const int32_t* const
 // Factored form (Mh != NULL): the per-node blocks Mh and K are written
 // instead of the sliced-ELL values Aval and Lval; Knm != NULL receives K
 // node-major as well (nine contiguous values per node).
+// The inputs m^n, m^{n-1} (or null) and F (or null) are read at the device
+// addresses held, as bit patterns, in prm[8], prm[9] and prm[10], so that a
+// captured setup serves every step's buffers.
 template <typename T>
 void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, const double* prm,
-                     int left_scale, int x0_is_mn, const double* m, const double* mprev, const double* F,
-                     Sell A, double* Aval, T* Lval, double* dinv0, T* ldinv, double* b, double* u,
-                     int32_t* flag, double* Mh, T* K, T* Knm, double* mt_out);
+                     int left_scale, int x0_is_mn, Sell A, double* Aval, T* Lval, double* dinv0, T* ldinv,
+                     double* b, double* u, int32_t* flag, double* Mh, T* K, T* Knm, double* mt_out);
 
 // Where a Galerkin product reads the fine blocks, and where it leaves a copy
 // of the coarse ones.  fk != NULL: the fine level is the factored grid level,
