@@ -1719,17 +1719,96 @@ __device__ void gauss_jordan(int64_t nd, double* a, int32_t* piv, int32_t* flag,
 
 constexpr int64_t GJ_LDS_MAX = 136;  // 136^2 doubles + work arrays fit in 160 KB LDS
 
-__global__ void __launch_bounds__(GJ_T) k_gauss_jordan_lds(int64_t nd, double* dense, int32_t* piv,
+// The same inversion with the matrix in LDS, in three barriers per pivot
+// step: the first wavefront finds the pivot (shuffles, the same rule); then
+// rows k and p are exchanged, row k normalised (also into rowk) and the
+// pivot column kept in colk; then every other row is eliminated.  The
+// values are those of gauss_jordan (the same operations on the same
+// operands).  The column interchanges are applied as one permutation when
+// the inverse is written back.
+__global__ void __launch_bounds__(GJ_T) k_gauss_jordan_lds(int64_t nd64, double* dense, int32_t* piv,
                                                            int32_t* flag) {
   extern __shared__ double lds[];
+  const int nd = (int)nd64;
   double* a = lds;
   double* colk = a + nd * nd;
-  double* redv = colk + nd;
-  int32_t* redi = (int32_t*)(redv + GJ_T);
-  for (int64_t e = threadIdx.x; e < nd * nd; e += GJ_T) a[e] = dense[e];
+  double* rowk = colk + nd;
+  int32_t* perm = (int32_t*)(rowk + nd);
+  __shared__ int s_p;
+  __shared__ double s_pk, s_kk;
+  const int t = (int)threadIdx.x;
+  for (int e = t; e < nd * nd; e += GJ_T) a[e] = dense[e];
   __syncthreads();
-  gauss_jordan(nd, a, piv, flag, colk, redv, redi);
-  for (int64_t e = threadIdx.x; e < nd * nd; e += GJ_T) dense[e] = a[e];
+  for (int k = 0; k < nd; ++k) {
+    if (t < 64) {
+      // first row of largest |a_ik|, i >= k
+      double best = -1.0;
+      int bi = nd;
+      for (int i = k + t; i < nd; i += 64) {
+        const double v = fabs(a[i * nd + k]);
+        if (v > best) {
+          best = v;
+          bi = i;
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double v2 = __shfl_xor(best, off, 64);
+        const int i2 = __shfl_xor(bi, off, 64);
+        if (v2 > best || (v2 == best && i2 < bi)) {
+          best = v2;
+          bi = i2;
+        }
+      }
+      if (t == 0) {
+        // no usable pivot (zero or NaN column): keep row k and report singular
+        const int p = (bi < nd && best > 0.0) ? bi : k;
+        s_p = p;
+        s_pk = a[p * nd + k];
+        s_kk = a[k * nd + k];
+        piv[k] = p;
+        if (!(best > 0.0)) atomicOr(flag, 2);
+      }
+    }
+    __syncthreads();
+    const int p = s_p;
+    const double pv = s_pk;
+    for (int j = t; j < nd; j += GJ_T) {
+      const double xk = a[k * nd + j], xp = a[p * nd + j];
+      const double r = (j == k ? 1.0 : xp) / pv;
+      if (p != k) a[p * nd + j] = xk;
+      a[k * nd + j] = r;
+      rowk[j] = r;
+    }
+    for (int i = t; i < nd; i += GJ_T) colk[i] = i == k ? s_pk : i == p ? s_kk : a[i * nd + k];
+    __syncthreads();
+    for (int e = t; e < nd * nd; e += GJ_T) {
+      const int i = e / nd, j = e - i * nd;
+      if (i == k) continue;
+      const double f = colk[i];
+      if (j == k)
+        a[e] = -f * rowk[k];
+      else
+        a[e] -= f * rowk[j];
+    }
+    __syncthreads();
+  }
+  // the column interchanges, last to first, as one permutation: position j
+  // of the inverse holds column perm[j] of a
+  if (t == 0) {
+    for (int j = 0; j < nd; ++j) perm[j] = j;
+    for (int k = nd - 1; k >= 0; --k) {
+      const int q = piv[k];
+      const int32_t x = perm[k];
+      perm[k] = perm[q];
+      perm[q] = x;
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < nd * nd; e += GJ_T) {
+    const int i = e / nd, j = e - i * nd;
+    dense[e] = a[i * nd + perm[j]];
+  }
 }
 
 __global__ void __launch_bounds__(GJ_T) k_gauss_jordan_global(int64_t nd, double* dense, int32_t* piv,
@@ -1981,8 +2060,8 @@ template void launch_assemble<float>(hipStream_t, int, int, int, double, const d
                                      float*, float*, double*);
 
 void init_kernel_attributes() {
-  const size_t lds_max = (size_t)(GJ_LDS_MAX * GJ_LDS_MAX + GJ_LDS_MAX + GJ_T) * sizeof(double) +
-                         GJ_T * sizeof(int32_t);
+  const size_t lds_max = (size_t)(GJ_LDS_MAX * GJ_LDS_MAX + 2 * GJ_LDS_MAX) * sizeof(double) +
+                         GJ_LDS_MAX * sizeof(int32_t);
   (void)hipFuncSetAttribute((const void*)k_gauss_jordan_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds_max);
   (void)hipGetLastError();
@@ -2068,13 +2147,13 @@ template void launch_cls_gather<float>(hipStream_t, int64_t, const int32_t*, Sel
 
 void launch_gauss_jordan(hipStream_t st, int64_t nd, double* dense, int32_t* piv, int32_t* flag) {
   static int lds_ok = -1;
-  const size_t lds_max = (size_t)(GJ_LDS_MAX * GJ_LDS_MAX + GJ_LDS_MAX + GJ_T) * sizeof(double) +
-                         GJ_T * sizeof(int32_t);
+  const size_t lds_max = (size_t)(GJ_LDS_MAX * GJ_LDS_MAX + 2 * GJ_LDS_MAX) * sizeof(double) +
+                         GJ_LDS_MAX * sizeof(int32_t);
   if (lds_ok < 0)
     lds_ok = hipFuncSetAttribute((const void*)k_gauss_jordan_lds,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max) == hipSuccess;
   if (nd <= GJ_LDS_MAX && lds_ok) {
-    const size_t lds = (size_t)(nd * nd + nd + GJ_T) * sizeof(double) + GJ_T * sizeof(int32_t);
+    const size_t lds = (size_t)(nd * nd + 2 * nd) * sizeof(double) + nd * sizeof(int32_t);
     hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(1), dim3(GJ_T), lds, st, nd, dense, piv, flag);
   } else {
     // the pivot column is staged after the pivot indices: callers size the
