@@ -627,19 +627,22 @@ int build_structure(llg_ctx& c, Arena& ar) {
       int32_t* cwt = ar.alloc<int32_t>(ncand);
       int32_t* nrp = ar.alloc<int32_t>(nc + 1);
       // rows of the coarse levels of a 3D grid reach about 50 candidates
+      const bool wide = nz > 1 && l > 0;
+      const int64_t tiles = ceil_div(nc, cg_tile_rows(wide));
+      int32_t* ttot = ar.alloc<int32_t>(tiles + 1);
       const int gdims[3] = {nx, ny, nz};
       // the next pass (of this level or the next) starts from these nodes
       ns_next = ar.alloc<NodeSt>(nc);
       mate_next = ar.alloc<int32_t>(nc);
       prop_next = ar.alloc<int32_t>(nc);
-      launch_cg_fill(st, nc, lead, mate, crp, cci, cw, aggp, cnt, cj, cwt, nrp, nz > 1 && l > 0,
+      launch_cg_fill(st, nc, lead, mate, crp, cci, cw, aggp, cnt, cj, cwt, nrp, ttot, wide,
                      l == 0 && p == 0 ? gdims : nullptr, ns_next, mate_next, prop_next);
-      launch_scan_excl(st, nrp, nrp, nc, nrp + nc, c.scan_tmp);
+      launch_scan_excl(st, ttot, ttot, tiles, ttot + tiles, c.scan_tmp);
       LCHK();
-      const int64_t ng = ar.count(nrp + nc);
+      const int64_t ng = ar.count(ttot + tiles);
       int32_t* nci = ar.alloc<int32_t>(ng);
       int32_t* nw = ar.alloc<int32_t>(ng);
-      launch_cg_copy(st, nc, cnt, cj, cwt, nrp, nci, nw);
+      launch_cg_copy(st, nc, wide, cnt, cj, cwt, ttot, nrp, nci, nw);
       LCHK();
       leads[p] = lead;
       mates[p] = mate;

@@ -692,50 +692,52 @@ __global__ void k_cg_count(int64_t nc, const int32_t* lead, const int32_t* mate,
 }
 
 // Coarse graph row I: (agg(j), w) over the rows of the (one or two) members,
-// sorted by coarse column, duplicates summed, the diagonal dropped, written
-// at cj/cw[cptr[I]...] (room for every candidate) with its length in
-// ucnt[I].
+// sorted by coarse column, duplicates summed, the diagonal dropped.
 //
 // G lanes take a row: they read the members' rows with contiguous loads and
 // insert the candidates into a hash table of T slots in LDS (open
 // addressing; equal columns meet in one slot, whose integer weight sums
 // them, so the order of the insertions does not matter).  The table's
-// entries are then compacted and each is written at its rank among them,
-// which sorts the row.  A row has 10-30 candidates and 8-27 entries on the
-// grid hierarchies; a row of more than T candidates (none on them) is built
-// by its first lane with insertion into its output range.
-__device__ int32_t cg_row_insert(int32_t I, int32_t a, int32_t b, const int32_t* __restrict__ grp,
+// entries are compacted and each is written at its rank among them, which
+// sorts the row.  A row has 10-30 candidates and 8-27 entries on the grid
+// hierarchies; a row of more than T candidates (none there) is counted and
+// then written in order by its first lane from the rows themselves.
+//
+// A workgroup's R rows (a tile) are written end to end from the start of
+// the tile's room for candidates (cptr of its first row): nrp[I] receives
+// row I's offset in the tile and ttot[tile] the tile's length.  After an
+// exclusive scan of ttot, k_cg_copy moves each tile to its place with
+// contiguous loads and stores and turns nrp into the row pointers.
+// The entries of row I in ascending column order, for a row of more than T
+// candidates: with emit, written at out/ow; returns their number.
+__device__ int32_t cg_row_select(int32_t I, int32_t ka, int32_t na, int32_t kb, int32_t nb,
                                  const int32_t* __restrict__ gci, const int32_t* __restrict__ gw,
-                                 const int32_t* __restrict__ agg, int32_t* cj, int32_t* cw, int32_t o) {
-  int32_t c = 0;
-  for (int mem = 0; mem < 2; ++mem) {
-    const int32_t v = mem == 0 ? a : b;
-    if (v < 0) break;
-    for (int32_t k = grp[v]; k < grp[v + 1]; ++k) {
-      const int32_t J = agg[gci[k]];
-      const int32_t w = gw[k];
-      int32_t q = c;
-      while (q > 0 && cj[o + q - 1] > J) {
-        cj[o + q] = cj[o + q - 1];
-        cw[o + q] = cw[o + q - 1];
-        --q;
+                                 const int32_t* __restrict__ agg, bool emit, int32_t* out, int32_t* ow,
+                                 int32_t* mx) {
+  const int32_t c = na + nb;
+  auto col = [&](int32_t e) { return agg[gci[e < na ? ka + e : kb + (e - na)]]; };
+  auto wgt = [&](int32_t e) { return gw[e < na ? ka + e : kb + (e - na)]; };
+  int32_t u = 0, last = -1;
+  for (;;) {
+    int32_t m = 0x7fffffff, w = 0;
+    for (int32_t e = 0; e < c; ++e) {
+      const int32_t J = col(e);
+      if (J == I || J <= last) continue;
+      if (J < m) {
+        m = J;
+        w = wgt(e);
+      } else if (J == m) {
+        w += wgt(e);
       }
-      cj[o + q] = J;
-      cw[o + q] = w;
-      ++c;
     }
-  }
-  int32_t u = 0;
-  for (int32_t q = 0; q < c; ++q) {
-    const int32_t J = cj[o + q], w = cw[o + q];
-    if (J == I) continue;
-    if (u > 0 && cj[o + u - 1] == J) {
-      cw[o + u - 1] += w;
-    } else {
-      cj[o + u] = J;
-      cw[o + u] = w;
-      ++u;
+    if (m == 0x7fffffff) break;
+    if (emit) {
+      out[u] = m;
+      ow[u] = w;
     }
+    *mx = max(*mx, w);
+    last = m;
+    ++u;
   }
   return u;
 }
@@ -759,8 +761,8 @@ __global__ void __launch_bounds__(TPB) k_cg_fill(int64_t nc, const int32_t* __re
                                                  const int32_t* __restrict__ mate, const int32_t* __restrict__ grp,
                                                  const int32_t* __restrict__ gci, const int32_t* __restrict__ gw,
                                                  const int32_t* __restrict__ agg, const int32_t* __restrict__ cptr,
-                                                 int32_t* cj, int32_t* cw, int32_t* ucnt, int nx, int ny, int nz,
-                                                 NodeSt* nsn, int32_t* maten, int32_t* propn) {
+                                                 int32_t* cj, int32_t* cw, int32_t* nrp, int32_t* ttot, int nx,
+                                                 int ny, int nz, NodeSt* nsn, int32_t* maten, int32_t* propn) {
   static_assert(TPB % G == 0 && T % G == 0 && (T & (T - 1)) == 0, "table shape");
   constexpr int R = TPB / G;   // rows per workgroup
   constexpr int PS = T / G;    // table slots per lane
@@ -768,8 +770,12 @@ __global__ void __launch_bounds__(TPB) k_cg_fill(int64_t nc, const int32_t* __re
   __shared__ int32_t s_key[R * T];
   __shared__ int32_t s_wt[R * T];
   __shared__ int2 s_ent[R * T];
-  const int r = (int)threadIdx.x / G, lane = (int)threadIdx.x % G;
-  const int64_t I = (int64_t)xcd_block(blockIdx.x, gridDim.x) * R + r;
+  __shared__ int32_t s_len[R], s_off[R];
+  static_assert(R <= 64, "one wavefront scans the tile's rows");
+  const int tid = (int)threadIdx.x;
+  const int r = tid / G, lane = tid % G;
+  const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t I = tile * R + r;
   int32_t* key = s_key + r * T;
   int32_t* wt = s_wt + r * T;
   int2* ent = s_ent + r * T;
@@ -778,10 +784,9 @@ __global__ void __launch_bounds__(TPB) k_cg_fill(int64_t nc, const int32_t* __re
     key[lane * PS + q] = -1;
     wt[lane * PS + q] = 0;
   }
-  int32_t a = 0, b = -1, ka = 0, na = 0, kb = 0, nb = 0, o = 0;
+  int32_t a = 0, b = -1, ka = 0, na = 0, kb = 0, nb = 0;
   if (I < nc) {
     a = lead[I];
-    o = cptr[I];
     b = mate[a];
     ka = grp[a];
     na = grp[a + 1] - ka;
@@ -833,32 +838,51 @@ __global__ void __launch_bounds__(TPB) k_cg_fill(int64_t nc, const int32_t* __re
     const int v = __shfl_up(incl, off, G);
     if (lane >= off) incl += v;
   }
-  const int u = __shfl(incl, G - 1, G);
+  int32_t u = __shfl(incl, G - 1, G);
   int pos = incl - cl;
 #pragma unroll
   for (int q = 0; q < PS; ++q)
     if (kk[q] != -1) ent[pos++] = make_int2(kk[q], ww[q]);
-  __syncthreads();
   int32_t mx = 0;  // the row's largest weight
-  if (small) {
-    // columns are distinct: an entry's rank is its place in the sorted row
-    for (int t = lane; t < u; t += G) {
-      const int2 v = ent[t];
-      int rk = 0;
-      for (int x = 0; x < u; ++x) rk += ent[x].x < v.x;
-      cj[o + rk] = v.x;
-      cw[o + rk] = v.y;
-      mx = max(mx, v.y);
+  if (!small) {
+    if (I < nc && lane == 0) u = cg_row_select((int32_t)I, ka, na, kb, nb, gci, gw, agg, false, nullptr, nullptr, &mx);
+    u = __shfl(u, 0, G);
+  }
+  if (I >= nc) u = 0;
+  if (lane == 0) s_len[r] = u;
+  __syncthreads();
+  // the rows' offsets in the tile, and the tile's length
+  if (tid < 64) {
+    const int32_t v = tid < R ? s_len[tid] : 0;
+    int32_t sc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t w = __shfl_up(sc, off, 64);
+      if (tid >= off) sc += w;
     }
-    if (lane == 0) ucnt[I] = u;
+    if (tid < R) s_off[tid] = sc - v;
+    if (tid == 63) ttot[tile] = sc;
+  }
+  __syncthreads();
+  if (I < nc) {
+    const int32_t o = cptr[tile * R] + s_off[r];
+    if (small) {
+      // columns are distinct: an entry's rank is its place in the sorted row
+      for (int t = lane; t < u; t += G) {
+        const int2 v = ent[t];
+        int rk = 0;
+        for (int x = 0; x < u; ++x) rk += ent[x].x < v.x;
+        cj[o + rk] = v.x;
+        cw[o + rk] = v.y;
+        mx = max(mx, v.y);
+      }
+    } else if (lane == 0) {
+      (void)cg_row_select((int32_t)I, ka, na, kb, nb, gci, gw, agg, true, cj + o, cw + o, &mx);
+    }
+    if (lane == 0) nrp[I] = s_off[r];
   }
 #pragma unroll
   for (int off = 1; off < G; off <<= 1) mx = max(mx, __shfl_xor(mx, off, G));
-  if (!small && I < nc && lane == 0) {
-    const int32_t ub = cg_row_insert((int32_t)I, a, b, grp, gci, gw, agg, cj, cw, o);
-    ucnt[I] = ub;
-    for (int32_t q = 0; q < ub; ++q) mx = max(mx, cw[o + q]);
-  }
   // the next pass's matching state of node I (what k_match_init writes)
   if (nsn && I < nc && lane == 0) {
     nsn[I] = NodeSt{mx, -1};
@@ -867,20 +891,22 @@ __global__ void __launch_bounds__(TPB) k_cg_fill(int64_t nc, const int32_t* __re
   }
 }
 
-// The rows' entries moved to their final offsets; CG_L lanes share a row so
-// that the reads and writes of a row are contiguous across the lanes.
-constexpr int CG_L = 8;
-__global__ void k_cg_copy(int64_t nc, const int32_t* cptr, const int32_t* cj, const int32_t* cw,
-                          const int32_t* nrp, int32_t* nci, int32_t* nw) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t I = t / CG_L;
-  const int sub = (int)(t - I * CG_L);
-  if (I >= nc) return;
-  const int32_t o = cptr[I], d = nrp[I], len = nrp[I + 1] - nrp[I];
-  for (int32_t q = sub; q < len; q += CG_L) {
-    nci[d + q] = cj[o + q];
-    nw[d + q] = cw[o + q];
+// Tile t's rows moved from cj/cw[cptr[t R]...] to nci/nw[tbase[t]...] (tbase:
+// the exclusive scan of the tile lengths, the total at tbase[nt]); nrp[I]
+// turns from the row's offset in its tile into the row pointer.
+__global__ void k_cg_copy(int64_t nc, int R, const int32_t* __restrict__ cptr, const int32_t* __restrict__ cj,
+                          const int32_t* __restrict__ cw, const int32_t* __restrict__ tbase, int32_t* nrp,
+                          int32_t* nci, int32_t* nw) {
+  const int64_t t = blockIdx.x;
+  const int64_t I0 = t * R;
+  const int32_t src = cptr[I0], dst = tbase[t], len = tbase[t + 1] - dst;
+  for (int32_t q = (int32_t)threadIdx.x; q < len; q += (int32_t)blockDim.x) {
+    nci[dst + q] = cj[src + q];
+    nw[dst + q] = cw[src + q];
   }
+  const int64_t I = I0 + threadIdx.x;
+  if ((int)threadIdx.x < R && I < nc) nrp[I] += dst;
+  if (threadIdx.x == 0 && I0 + R >= nc) nrp[nc] = dst + len;
 }
 
 // Members of the composite aggregates, from the passes' own records: an
@@ -1989,28 +2015,32 @@ void launch_cg_count(hipStream_t st, int64_t nc, const int32_t* lead, const int3
                      const int32_t* grp, int32_t* cnt) {
   if (nc > 0) hipLaunchKernelGGL(k_cg_count, dim3(nblk(nc)), dim3(TPB), 0, st, nc, lead, mate, grp, cnt);
 }
+int cg_tile_rows(bool wide) { return wide ? TPB / 16 : TPB / 8; }
+
 void launch_cg_fill(hipStream_t st, int64_t nc, const int32_t* lead, const int32_t* mate,
                     const int32_t* grp, const int32_t* gci, const int32_t* gw, const int32_t* agg,
-                    const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* ucnt, int wide, const int* grid,
-                    NodeSt* nsn, int32_t* maten, int32_t* propn) {
+                    const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* nrp, int32_t* ttot, bool wide,
+                    const int* grid, NodeSt* nsn, int32_t* maten, int32_t* propn) {
   if (nc <= 0) return;
+  const dim3 gr(nblk(nc, cg_tile_rows(wide)));
   // the grid level's rows, and all rows in 2D, have up to about 20
   // candidates: eight lanes and 32 slots; the coarse levels of 3D grids up
   // to about 50: sixteen lanes and 64 slots
   if (wide)
-    hipLaunchKernelGGL((k_cg_fill<16, 64, false>), dim3(nblk(nc, TPB / 16)), dim3(TPB), 0, st, nc, lead, mate, grp,
-                       gci, gw, agg, cptr, cj, cw, ucnt, 0, 0, 0, nsn, maten, propn);
+    hipLaunchKernelGGL((k_cg_fill<16, 64, false>), gr, dim3(TPB), 0, st, nc, lead, mate, grp, gci, gw, agg, cptr, cj,
+                       cw, nrp, ttot, 0, 0, 0, nsn, maten, propn);
   else if (grid)
-    hipLaunchKernelGGL((k_cg_fill<8, 32, true>), dim3(nblk(nc, TPB / 8)), dim3(TPB), 0, st, nc, lead, mate, grp, gci,
-                       gw, agg, cptr, cj, cw, ucnt, grid[0], grid[1], grid[2], nsn, maten, propn);
+    hipLaunchKernelGGL((k_cg_fill<8, 32, true>), gr, dim3(TPB), 0, st, nc, lead, mate, grp, gci, gw, agg, cptr, cj,
+                       cw, nrp, ttot, grid[0], grid[1], grid[2], nsn, maten, propn);
   else
-    hipLaunchKernelGGL((k_cg_fill<8, 32, false>), dim3(nblk(nc, TPB / 8)), dim3(TPB), 0, st, nc, lead, mate, grp,
-                       gci, gw, agg, cptr, cj, cw, ucnt, 0, 0, 0, nsn, maten, propn);
+    hipLaunchKernelGGL((k_cg_fill<8, 32, false>), gr, dim3(TPB), 0, st, nc, lead, mate, grp, gci, gw, agg, cptr, cj,
+                       cw, nrp, ttot, 0, 0, 0, nsn, maten, propn);
 }
-void launch_cg_copy(hipStream_t st, int64_t nc, const int32_t* cptr, const int32_t* cj,
-                    const int32_t* cw, const int32_t* nrp, int32_t* nci, int32_t* nw) {
-  if (nc > 0)
-    hipLaunchKernelGGL(k_cg_copy, dim3(nblk(nc * CG_L)), dim3(TPB), 0, st, nc, cptr, cj, cw, nrp, nci, nw);
+void launch_cg_copy(hipStream_t st, int64_t nc, bool wide, const int32_t* cptr, const int32_t* cj,
+                    const int32_t* cw, const int32_t* tbase, int32_t* nrp, int32_t* nci, int32_t* nw) {
+  if (nc <= 0) return;
+  const int R = cg_tile_rows(wide);
+  hipLaunchKernelGGL(k_cg_copy, dim3(nblk(nc, R)), dim3(TPB), 0, st, nc, R, cptr, cj, cw, tbase, nrp, nci, nw);
 }
 static PassMaps pass_maps(int np, const int32_t* const* lead, const int32_t* const* mate) {
   PassMaps pm{};
