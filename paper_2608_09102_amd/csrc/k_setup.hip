@@ -1460,6 +1460,139 @@ __global__ void __launch_bounds__(TPB) k_galerkin_slices(int64_t nc, const int32
   }
 }
 
+// Level 1 of a grid level stored per node, one thread per coarse block in
+// the coarse level's CSR order: a workgroup takes a slice of 64 coarse rows,
+// stages their members' rows once in LDS (each entry's aggregate, the
+// diagonal's position and K_i; up to GM members per row, larger aggregates
+// walk their rows from memory), and its threads take the slice's blocks in
+// order, so the CSR-ordered copy is written by consecutive threads.  Block
+// (I, J) sums, over the members of I in ascending order and over the entries
+// of each member's row in ascending order whose aggregate is J, the fine
+// block: the identity on the diagonal, K_i elsewhere (eq. Ac_direct), in
+// FP64 from zero, as k_galerkin_slices does.
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_galerkin_grid(int64_t nc, const int32_t* __restrict__ csl,
+                                                       T* __restrict__ cval, T* __restrict__ cdinv,
+                                                       const int32_t* __restrict__ mptr,
+                                                       const int32_t* __restrict__ mem,
+                                                       const int32_t* __restrict__ agg, const GalSrc<T> g) {
+  const int64_t s = xcd_block(blockIdx.x, gridDim.x);
+  constexpr int GM = 4;
+  __shared__ int32_t s_aa[SL * GM * 8];
+  __shared__ int32_t s_dp[SL * GM];
+  __shared__ int32_t s_nm[SL];
+  __shared__ T s_k[SL * GM * 9];
+  __shared__ int32_t s_rs[SL + 1];
+  for (int tt = threadIdx.x; tt < SL * GM; tt += blockDim.x) {
+    const int lr = tt / GM, m = tt - lr * GM;
+    const int64_t I = s * SL + lr;
+    int32_t nm = 0;
+    if (I < nc) {
+      const int32_t q0 = mptr[I];
+      nm = mptr[I + 1] - q0;
+      if (m < nm && nm <= GM) {
+        const int32_t i = mem[q0 + m];
+        const int32_t k0 = g.frp[i], len = min(g.frp[i + 1] - k0, 8);
+        int dp = -1;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int32_t j = k < len ? g.fci[k0 + k] : -1;
+          s_aa[(lr * GM + m) * 8 + k] = j >= 0 ? agg[j] : -1;
+          dp = j == i ? k : dp;
+        }
+        s_dp[lr * GM + m] = dp;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) s_k[(lr * GM + m) * 9 + e] = g.knm[9 * (int64_t)i + e];
+      }
+    }
+    if (m == 0) s_nm[lr] = nm;
+  }
+  for (int tt = threadIdx.x; tt <= SL; tt += blockDim.x) s_rs[tt] = g.crp[min(s * SL + tt, nc)];
+  __syncthreads();
+  const int32_t p0 = s_rs[0], tot = s_rs[SL] - p0;
+  const int64_t cb = csl[s];
+  for (int q = threadIdx.x; q < tot; q += blockDim.x) {
+    // the block's row: the last l with s_rs[l] <= p0 + q
+    int lo = 0, hi = SL;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_rs[mid] <= p0 + q)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const int l = lo;
+    const int64_t I = s * SL + l;
+    const int t = p0 + q - s_rs[l];
+    const int32_t J = g.cci[p0 + q];
+    double acc[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) acc[e] = 0.0;
+    auto add_row = [&](const int32_t* aa, int dpos, const double* kd) {
+      unsigned msk = 0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) msk |= aa[k] == J ? 1u << k : 0u;
+      while (msk) {
+        const int k = __ffs(msk) - 1;
+        msk &= msk - 1;
+        const bool d = k == dpos;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) acc[e] += d ? ((e == 0 || e == 4 || e == 8) ? 1.0 : 0.0) : kd[e];
+      }
+    };
+    const int nm = s_nm[l];
+    if (nm <= GM) {
+      for (int m = 0; m < nm; ++m) {
+        const int b = l * GM + m;
+        int32_t aa[8];
+        double kd[9];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) aa[k] = s_aa[b * 8 + k];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) kd[e] = (double)s_k[b * 9 + e];
+        add_row(aa, s_dp[b], kd);
+      }
+    } else {
+      for (int32_t qq = mptr[I]; qq < mptr[I + 1]; ++qq) {
+        const int32_t i = mem[qq];
+        const int32_t k0 = g.frp[i], len = min(g.frp[i + 1] - k0, 8);
+        int32_t aa[8];
+        int dpos = -1;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int32_t j = k < len ? g.fci[k0 + k] : -1;
+          aa[k] = j >= 0 ? agg[j] : -1;
+          dpos = j == i ? k : dpos;
+        }
+        double kd[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) kd[e] = (double)g.knm[9 * (int64_t)i + e];
+        add_row(aa, dpos, kd);
+      }
+    }
+    T stv[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) stv[e] = (T)acc[e];
+    const int64_t pos = (int64_t)p0 + q;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) g.cvt[pos * 9 + e] = stv[e];
+    if (cval) {
+      const int64_t vb = cb * 9 + (int64_t)t * 9 * SL + l;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) cval[vb + e * SL] = stv[e];
+    }
+    if (J == (int32_t)I) {
+      double D[9], Di[9];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) D[e] = (double)stv[e];
+      inv3(D, Di);
+      const int64_t db = s * 9 * SL + l;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) cdinv[db + e * SL] = (T)Di[e];
+    }
+  }
+}
+
 // Coarse levels of a coarse level, row by row: GR_L lanes share a
 // coarse row I, lane t owning its slots t and t + GR_L (further passes for
 // rows of more than 2 GR_L blocks).  The group walks the fine rows of I's
@@ -2110,14 +2243,18 @@ void launch_galerkin(hipStream_t st, Sell C, T* cval, T* cdinv, const int32_t* m
                        C.sl_ptr, C.col, cval, cdinv, mptr, mem, F.sl_ptr, F.col, agg, g)
   // the coarse levels of a coarse level row by row, from its CSR-ordered copy
   // (also the small ones: 24-71 us against 50-310 us by slot, one thread and
-  // one slice bisection each, at 1,000-32,000 rows).  (Level 1 of a grid level
-  // stored per node measured faster by slot
-  // groups: its blocks come from K_i, one load per member, and by slot groups
-  // 64 coarse rows share the FP64 adds of a wavefront, against 4 row by row.)
+  // one slice bisection each, at 1,000-32,000 rows).  Level 1 of a grid level
+  // stored per node block by block, a thread per block in CSR order (row by
+  // row it measured 5.2 ms at 256^3, by slot groups 2.31 ms, block by block
+  // 1.78 ms: its blocks come from K_i, one load per member).
   const bool rows = g.crp && g.cci && !g.fk && g.fvt != nullptr;
   const dim3 rg(nblk(C.n, TPB / GR_L)), rt(TPB);
   if (rows) {
     hipLaunchKernelGGL((k_galerkin_rows<T>), rg, rt, 0, st, C.n, C.sl_ptr, cval, cdinv, mptr, mem, agg, g);
+  } else if (g.fk && g.knm && g.crp && g.cci && g.cvt) {
+    // level 1 of the per-node grid level, block by block in CSR order
+    hipLaunchKernelGGL((k_galerkin_grid<T>), dim3((unsigned)C.nslices), rt, 0, st, C.n, C.sl_ptr, cval, cdinv, mptr,
+                       mem, agg, g);
   } else if (g.fk) {
     LLG_GAL(true);
   } else {
