@@ -1069,9 +1069,13 @@ void setup_values(llg_ctx& c, const double* m, const double* mprev, const double
   Level& L0 = c.lv[0];
   {
     KTimer kt(c, LLG_KT_ASSEMBLE);
+    // factored grid level: the solve recomputes its blocks and D^{-1} from
+    // the frozen field, so only the node-major K (Galerkin) and, for the
+    // Gauss-Seidel colour classes, the sliced K are stored
+    const bool kf = c.fact && c.opts.smoother == LLG_SMOOTHER_MCGS;
     launch_assemble<T>(st, g.n[0], g.n[1], g.n[2], 1.0 / (g.h * g.h), c.prm, c.opts.left_scale,
-                       c.opts.x0_is_mn, L0.A, c.Aval, (T*)L0.val, c.dinv0, (T*)L0.dinv, c.b, c.u, c.flags, c.Mh,
-                       (T*)L0.kf, (T*)L0.knm, c.mt);
+                       c.opts.x0_is_mn, L0.A, c.Aval, (T*)L0.val, c.fact ? nullptr : c.dinv0, (T*)L0.dinv, c.b, c.u,
+                       c.flags, c.fact, nullptr, kf ? (T*)L0.kf : nullptr, (T*)L0.knm, c.mt);
     if (c.f1) {
       launch_member_nbr_aggs(st, GridDims{g.n[0], g.n[1], g.n[2]}, L0.mem, L0.agg, L0.nagg);
       launch_member_fields<T>(st, L0.A.n, L0.mem, c.mt, (T*)L0.mtq);
@@ -2219,6 +2223,16 @@ llg_status llg_get_level(llg_ctx* ctx, int32_t level, int32_t* h_row_ptr, int32_
     const bool f32 = level >= 0 && ctx->opts.precision == LLG_PREC_FP32_AMG;
     const size_t ts = f32 ? 4 : 8;
     const bool fact = level <= 0 && ctx->fact;
+    if (fact) {  // the sliced blocks, from the frozen field of the last setup
+      const llg_grid& g = ctx->grid;
+      if (ctx->opts.precision == LLG_PREC_FP32_AMG)
+        launch_fact_blocks<float>(ctx->st, g.n[0], g.n[1], g.n[2], 1.0 / (g.h * g.h), ctx->prm, ctx->mt, ctx->Mh,
+                                  (float*)ctx->lv[0].kf);
+      else
+        launch_fact_blocks<double>(ctx->st, g.n[0], g.n[1], g.n[2], 1.0 / (g.h * g.h), ctx->prm, ctx->mt,
+                                   ctx->Mh, (double*)ctx->lv[0].kf);
+      LCHK();
+    }
     // a level whose products do not read sliced-ELL values keeps only its
     // CSR-ordered copy (level 1 applied through the grid blocks)
     const bool csr = !fact && level >= 0 && !L.val;

@@ -1120,7 +1120,7 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
                            T* __restrict__ Lval, double* __restrict__ dinv0, T* __restrict__ ldinv,
                            double* __restrict__ b, double* __restrict__ u, int32_t* flag,
                            double* __restrict__ Mh, T* __restrict__ K, T* __restrict__ Knm,
-                           double* __restrict__ mt_out) {
+                           double* __restrict__ mt_out, int fact) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t N = (int64_t)nx * ny * nz;
   if (p >= N) return;
@@ -1170,8 +1170,8 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
   const int64_t s = p / SL;
   const int l = (int)(p - s * SL);
   const int64_t cb = sl_ptr[s];
-  const int w = Mh ? 0 : (int)((sl_ptr[s + 1] - cb) / SL);
-  if (Mh) {
+  const int w = fact ? 0 : (int)((sl_ptr[s + 1] - cb) / SL);
+  if (fact) {
     // factored form: the off-diagonal block of the row and its scaled form,
     // the same values the sliced-ELL slots would hold
     double blk[9], sb[9];
@@ -1183,10 +1183,12 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
       for (int q = 0; q < 3; ++q)
         sb[3 * r + q] = (Di[3 * r] * blk[q] + Di[3 * r + 1] * blk[3 + q]) + Di[3 * r + 2] * blk[6 + q];
     const int64_t fb = s * 9 * SL + l;
+    // (the sliced copies only where a reader needs them: the solve
+    // recomputes the blocks from the frozen field)
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
-      Mh[fb + e * SL] = blk[e];
-      K[fb + e * SL] = (T)sb[e];
+      if (Mh) Mh[fb + e * SL] = blk[e];
+      if (K) K[fb + e * SL] = (T)sb[e];
       if (Knm) Knm[9 * p + e] = (T)sb[e];  // node-major copy for the Galerkin product
     }
   }
@@ -1229,13 +1231,33 @@ __global__ void k_assemble(int nx, int ny, int nz, double inv_h2, const double* 
   const int64_t db = s * 9 * SL + l;
 #pragma unroll
   for (int e = 0; e < 9; ++e) {
-    dinv0[db + e * SL] = Di[e];
+    if (dinv0) dinv0[db + e * SL] = Di[e];
     if (!left_scale) ldinv[db + e * SL] = (T)Di[e];
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     b[3 * p + c] = F ? bb[c] + prm[2] * F[3 * p + c] : bb[c];
     u[3 * p + c] = x0_is_mn ? mt[c] : 0.0;
+  }
+}
+
+// The sliced per-node blocks of the factored grid level (Mh, in FP64, and
+// K, in T) from the frozen field the assembly kept, for the callers that
+// read them back: the same values the assembly computes (grid_blocks).
+template <typename T>
+__global__ void k_fact_blocks(int nx, int ny, int nz, double inv_h2, const double* __restrict__ prm,
+                              const double* __restrict__ mt, double* __restrict__ Mh, T* __restrict__ K) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (int64_t)nx * ny * nz) return;
+  int64_t nb[6];
+  const int deg = grid_nbrs(nx, ny, nz, p, nb);
+  double blk[9], kb[9];
+  grid_blocks(mt + 3 * p, prm[0], prm[1], inv_h2, deg, blk, nullptr, kb);
+  const int64_t s = p / SL, l = p - s * SL;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    Mh[s * 9 * SL + e * SL + l] = blk[e];
+    K[s * 9 * SL + e * SL + l] = (T)kb[e];
   }
 }
 
@@ -2209,18 +2231,29 @@ void launch_member_fill(hipStream_t st, int64_t nc, int np, const int32_t* const
 template <typename T>
 void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, const double* prm,
                      int left_scale, int x0_is_mn, Sell A, double* Aval, T* Lval, double* dinv0, T* ldinv,
-                     double* b, double* u, int32_t* flag, double* Mh, T* K, T* Knm, double* mt_out) {
+                     double* b, double* u, int32_t* flag, bool fact, double* Mh, T* K, T* Knm, double* mt_out) {
   const int64_t N = (int64_t)nx * ny * nz;
   hipLaunchKernelGGL((k_assemble<T>), dim3(nblk(N)), dim3(TPB), 0, st, nx, ny, nz, inv_h2, prm,
                      left_scale, x0_is_mn, A.sl_ptr, A.col, Aval, Lval, dinv0, ldinv, b, u, flag, Mh,
-                     K, Knm, mt_out);
+                     K, Knm, mt_out, fact ? 1 : 0);
 }
 template void launch_assemble<double>(hipStream_t, int, int, int, double, const double*, int, int, Sell,
-                                      double*, double*, double*, double*, double*, double*, int32_t*, double*,
-                                      double*, double*, double*);
+                                      double*, double*, double*, double*, double*, double*, int32_t*, bool,
+                                      double*, double*, double*, double*);
 template void launch_assemble<float>(hipStream_t, int, int, int, double, const double*, int, int, Sell,
-                                     double*, float*, double*, float*, double*, double*, int32_t*, double*,
-                                     float*, float*, double*);
+                                     double*, float*, double*, float*, double*, double*, int32_t*, bool,
+                                     double*, float*, float*, double*);
+template <typename T>
+void launch_fact_blocks(hipStream_t st, int nx, int ny, int nz, double inv_h2, const double* prm, const double* mt,
+                        double* Mh, T* K) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  if (N > 0)
+    hipLaunchKernelGGL((k_fact_blocks<T>), dim3(nblk(N)), dim3(TPB), 0, st, nx, ny, nz, inv_h2, prm, mt, Mh, K);
+}
+template void launch_fact_blocks<double>(hipStream_t, int, int, int, double, const double*, const double*, double*,
+                                         double*);
+template void launch_fact_blocks<float>(hipStream_t, int, int, int, double, const double*, const double*, double*,
+                                        float*);
 
 void init_kernel_attributes() {
   const size_t lds_max = (size_t)(GJ_LDS_MAX * GJ_LDS_MAX + 2 * GJ_LDS_MAX) * sizeof(double) +

@@ -256,16 +256,24 @@ void launch_member_fill(hipStream_t st, int64_t nc, int np, const int32_t* const
 // prm[0] = alpha, prm[1] = the time-step factor of the operator, prm[2] = the
 // factor of the forcing and of the explicit field terms (device memory, so
 // captured graphs stay valid)
-// Factored form (Mh != NULL): the per-node blocks Mh and K are written
-// instead of the sliced-ELL values Aval and Lval; Knm != NULL receives K
-// node-major as well (nine contiguous values per node).
+// Factored form (fact): the per-node blocks are written instead of the
+// sliced-ELL values Aval and Lval, each where its pointer is not null: Mh
+// (FP64) and K (in T) sliced, Knm node-major (nine contiguous values per
+// node).  dinv0 may be null (nothing reads it when the preconditioner's
+// input scaling recomputes D^{-1} from the frozen field).
 // The inputs m^n, m^{n-1} (or null) and F (or null) are read at the device
 // addresses held, as bit patterns, in prm[8], prm[9] and prm[10], so that a
 // captured setup serves every step's buffers.
 template <typename T>
 void launch_assemble(hipStream_t st, int nx, int ny, int nz, double inv_h2, const double* prm,
                      int left_scale, int x0_is_mn, Sell A, double* Aval, T* Lval, double* dinv0, T* ldinv,
-                     double* b, double* u, int32_t* flag, double* Mh, T* K, T* Knm, double* mt_out);
+                     double* b, double* u, int32_t* flag, bool fact, double* Mh, T* K, T* Knm, double* mt_out);
+// The factored grid level's sliced blocks Mh (FP64) and K (in T) from the
+// frozen field mt the assembly wrote, with the parameters in prm (the values
+// the assembly computes; for callers that read the blocks back).
+template <typename T>
+void launch_fact_blocks(hipStream_t st, int nx, int ny, int nz, double inv_h2, const double* prm, const double* mt,
+                        double* Mh, T* K);
 
 // Where a Galerkin product reads the fine blocks, and where it leaves a copy
 // of the coarse ones.  fk != NULL: the fine level is the factored grid level,
