@@ -300,36 +300,36 @@ __device__ inline bool key_before(const EdgeKey& a, const EdgeKey& b, uint64_t s
 // slots [kb, k1) that lane sub of its G lanes visits (every G-th slot); best
 // and bk are updated in place.  Neighbours are examined four at a time so
 // that their loads are in flight together.
-template <int G>
+template <int G, int U = 4>
 __device__ inline void row_best(int64_t i, int sub, int32_t mxi, int32_t kb, int32_t k1,
                                 const int32_t* __restrict__ gci, const int32_t* __restrict__ gw,
                                 const NodeSt* __restrict__ ns, uint64_t salt, int32_t bnum, int32_t bden,
                                 int32_t& best, EdgeKey& bk) {
   const uint64_t ri = node_rank(i, salt);
-  for (int32_t k0 = kb + sub; k0 < k1; k0 += 4 * G) {
-    int32_t jj[4], ww[4];
+  for (int32_t k0 = kb + sub; k0 < k1; k0 += U * G) {
+    int32_t jj[U], ww[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       const bool ok = k0 + u * G < k1;
       jj[u] = ok ? gci[k0 + u * G] : -1;
       ww[u] = ok ? gw[k0 + u * G] : 0;
     }
-    // the candidates' records, all four loads issued together (a padding
+    // the candidates' records, all U loads issued together (a padding
     // slot reads node i's own record and is masked)
-    NodeSt sj[4];
+    NodeSt sj[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) sj[u] = ns[jj[u] >= 0 ? jj[u] : i];
-    bool fr[4];
-    uint64_t rr[4];
-    int32_t mj[4];
+    for (int u = 0; u < U; ++u) sj[u] = ns[jj[u] >= 0 ? jj[u] : i];
+    bool fr[U];
+    uint64_t rr[U];
+    int32_t mj[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       fr[u] = jj[u] >= 0 && sj[u].mate < 0;
       rr[u] = node_rank(jj[u] >= 0 ? jj[u] : i, salt);
       mj[u] = sj[u].mx;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       if (!fr[u]) continue;
       const int32_t j = jj[u], w = ww[u];
       const uint64_t rj = rr[u];
@@ -442,12 +442,15 @@ __global__ void __launch_bounds__(TPB) k_propose(int64_t n, const int32_t* __res
   if ((threadIdx.x & 63) == 0 && ballot && __atomic_load_n(count, __ATOMIC_RELAXED) == 0) atomicOr(count, 1);
 }
 
+
 // The round with one lane per node (the levels whose rows are short).  A
 // wavefront pays for a row walk when any of its lanes walks, which most do
 // for ten rounds while a fifth to a third of the nodes walk; so, as in
 // k_propose_grid, the workgroup lists its walkers in LDS (with the record
 // and row bounds loaded beside the last proposal's mate) and its first
-// threads walk them.  The decisions are those of propose_node.
+// threads walk them, sixteen slots at a time (a row's loads in flight
+// together; rows hold 8-30 entries).  The decisions are those of
+// propose_node.
 __global__ void __launch_bounds__(TPB) k_propose_packed(int64_t n, const int32_t* __restrict__ grp,
                                                         const int32_t* __restrict__ gci,
                                                         const int32_t* __restrict__ gw, int32_t* __restrict__ mate,
@@ -476,7 +479,7 @@ __global__ void __launch_bounds__(TPB) k_propose_packed(int64_t n, const int32_t
     const int4 wk = s_walk[threadIdx.x];
     int32_t best = -1;
     EdgeKey bk{};
-    row_best<1>(wk.x, 0, wk.y, wk.z, wk.w, gci, gw, ns, salt, bnum, bden, best, bk);
+    row_best<1, 16>(wk.x, 0, wk.y, wk.z, wk.w, gci, gw, ns, salt, bnum, bden, best, bk);
     prop[wk.x] = best;
     if (best < 0) mate[wk.x] = -2;
     proposed = proposed || best >= 0;
@@ -484,6 +487,13 @@ __global__ void __launch_bounds__(TPB) k_propose_packed(int64_t n, const int32_t
   const unsigned long long ballot = __ballot(proposed);
   if ((threadIdx.x & 63) == 0 && ballot && __atomic_load_n(count, __ATOMIC_RELAXED) == 0) atomicOr(count, 1);
 }
+
+// The grid pass and the accept pass give a thread RN nodes (a workgroup
+// TPB x RN), their loads in flight together: the rounds wait on dependent
+// loads, and more of them in flight per thread hides more of that wait
+// (the one-lane walk of k_propose_packed, with its registers, measured
+// best at one node per thread).
+constexpr int RN = 4;
 
 // The same round on the grid graph itself (the first pass of the grid level):
 // its rows are the grid neighbours in ascending order, every weight is 1, so
@@ -523,20 +533,31 @@ __global__ void __launch_bounds__(TPB) k_propose_grid(int nx, int ny, int nz, in
                                                       const uint64_t* __restrict__ rank, uint64_t salt,
                                                       int32_t bnum, int32_t bden, int32_t* __restrict__ prop,
                                                       int32_t* count, int first) {
-  __shared__ unsigned s_walk[TPB];
+  __shared__ unsigned s_walk[TPB * RN];
   __shared__ int s_nw;
   const unsigned N = (unsigned)nx * ny * nz;
-  const unsigned i = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+  const unsigned i0 = xcd_block(blockIdx.x, gridDim.x) * (TPB * RN) + threadIdx.x;
   if (threadIdx.x == 0) s_nw = 0;
   __syncthreads();
   bool proposed = false;
-  if (i < N) {
+  int32_t mi[RN], pj[RN], mp[RN];
+#pragma unroll
+  for (int k = 0; k < RN; ++k) {
+    const unsigned i = i0 + k * TPB;
+    mi[k] = (i < N && !first) ? mate[i] : -1;
+    pj[k] = (i < N && !first) ? prop[i] : -1;
+  }
+#pragma unroll
+  for (int k = 0; k < RN; ++k) mp[k] = (i0 + k * TPB < N && mi[k] == -1 && pj[k] >= 0) ? mate[pj[k]] : 0;
+#pragma unroll
+  for (int k = 0; k < RN; ++k) {
+    const unsigned i = i0 + k * TPB;
+    if (i >= N) continue;
     bool walk = first != 0;
     if (!walk) {
-      const int32_t mi = mate[i], pj = prop[i];
-      if (mi >= 0 && pj >= 0) prop[i] = -1;  // matched in the last round
-      if (mi == -1) {
-        if (pj >= 0 && mate[pj] < 0)
+      if (mi[k] >= 0 && pj[k] >= 0) prop[i] = -1;  // matched in the last round
+      if (mi[k] == -1) {
+        if (pj[k] >= 0 && mp[k] < 0)
           proposed = true;
         else
           walk = true;
@@ -546,8 +567,8 @@ __global__ void __launch_bounds__(TPB) k_propose_grid(int nx, int ny, int nz, in
   }
   __syncthreads();
   const int nw = s_nw;
-  if ((int)threadIdx.x < nw) {
-    const unsigned w = s_walk[threadIdx.x];
+  for (int t = threadIdx.x; t < nw; t += TPB) {
+    const unsigned w = s_walk[t];
     unsigned nb[6];
     const int c = grid_nbrs32(nx, ny, nz, w, nb);
     int32_t mj[6];
@@ -638,12 +659,19 @@ __global__ void __launch_bounds__(MATCH_T) k_match_small(int64_t n, const int32_
 // a match clears the matched nodes' proposals.  ns is null on the grid pass,
 // whose proposal rounds read no records.
 __global__ void k_accept(int64_t n, const int32_t* prop, int32_t* mate, NodeSt* ns) {
-  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int32_t p = prop[i];
-  if (p >= 0 && prop[p] == (int32_t)i) {
-    mate[i] = p;
-    if (ns) ns[i].mate = p;
+  const int64_t i0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (TPB * RN) + threadIdx.x;
+  int32_t p[RN], q[RN];
+#pragma unroll
+  for (int k = 0; k < RN; ++k) p[k] = i0 + k * TPB < n ? prop[i0 + k * TPB] : -1;
+#pragma unroll
+  for (int k = 0; k < RN; ++k) q[k] = p[k] >= 0 ? prop[p[k]] : -1;
+#pragma unroll
+  for (int k = 0; k < RN; ++k) {
+    const int64_t i = i0 + k * TPB;
+    if (p[k] >= 0 && q[k] == (int32_t)i) {
+      mate[i] = p[k];
+      if (ns) ns[i].mate = p[k];
+    }
   }
 }
 
@@ -2138,8 +2166,8 @@ void launch_propose_grid(hipStream_t st, int nx, int ny, int nz, int32_t* mate, 
                          uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop, int32_t* count, bool first) {
   const int64_t N = (int64_t)nx * ny * nz;
   if (N > 0)
-    hipLaunchKernelGGL(k_propose_grid, dim3(nblk(N)), dim3(TPB), 0, st, nx, ny, nz, mate, rank, salt, bnum, bden,
-                       prop, count, first ? 1 : 0);
+    hipLaunchKernelGGL(k_propose_grid, dim3(nblk(N, TPB * RN)), dim3(TPB), 0, st, nx, ny, nz, mate, rank, salt, bnum,
+                       bden, prop, count, first ? 1 : 0);
 }
 void launch_match_small(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gci, const int32_t* gw,
                         int32_t* mate, NodeSt* ns, uint64_t salt, int32_t bnum, int32_t bden, int32_t* prop,
@@ -2153,7 +2181,7 @@ void launch_match_small(hipStream_t st, int64_t n, const int32_t* grp, const int
                        prop, flag, bit);
 }
 void launch_accept(hipStream_t st, int64_t n, const int32_t* prop, int32_t* mate, NodeSt* ns) {
-  if (n > 0) hipLaunchKernelGGL(k_accept, dim3(nblk(n)), dim3(TPB), 0, st, n, prop, mate, ns);
+  if (n > 0) hipLaunchKernelGGL(k_accept, dim3(nblk(n, TPB * RN)), dim3(TPB), 0, st, n, prop, mate, ns);
 }
 void launch_match_init(hipStream_t st, int64_t n, const int32_t* grp, const int32_t* gw, uint64_t salt,
                        NodeSt* ns, int32_t* mate, int32_t* prop) {
