@@ -1010,12 +1010,15 @@ __global__ void k_spmv_dots(int64_t n, const int32_t* __restrict__ sl, const int
 // MODE 0: r = b - A1 x.  MODE 1: out = x' + omega D1^{-1} (b - A1 x') with
 // x'_J = x_J + ec[agg2_J] (ec may be NULL; XZ: x = 0).  MODE 2: w = A1 v with
 // the K-cycle's partial sums (q = 0 w.w, 1 w.d1, 2 w.d2).  A workgroup
-// takes 64 consecutive aggregates and their members (an aggregate of two
-// matching passes has at most four, so at most 256): one thread per member
-// for the product, then one thread per aggregate sums its members' products
-// from LDS in the fixed order ((p0 + p2) + (p1 + p3)).
-constexpr int L1_G = L1_LANES;
-constexpr int L1_AGG = TPB / L1_G;  // aggregates per workgroup: their members fill at most TPB threads
+// takes L1_AGG consecutive aggregates and their members (an aggregate of two
+// matching passes has at most four): L1_MPT members per thread for the
+// products, their loads in flight together (the kernel waits on its
+// gathers), then one thread per aggregate sums its members' products from
+// LDS in the fixed order ((p0 + p2) + (p1 + p3)).
+constexpr int L1_G = 4;                          // members of an aggregate, at most
+constexpr int L1_MPT = 2;                        // members per thread
+constexpr int L1_AGG = TPB * L1_MPT / L1_G;      // aggregates per workgroup
+static_assert(TPB / L1_AGG == L1_LANES, "workgroups per aggregate count");
 template <int DIM, typename T, int MODE, bool XZ, int ND>
 __global__ void __launch_bounds__(TPB) k_l1(GridDims gd, int64_t n1, const int32_t* __restrict__ mptr,
                                             const int32_t* __restrict__ nagg, const T* __restrict__ mtq,
@@ -1024,7 +1027,7 @@ __global__ void __launch_bounds__(TPB) k_l1(GridDims gd, int64_t n1, const int32
                                             const T* __restrict__ ec, T omega, T* __restrict__ out,
                                             const T* __restrict__ d1, const T* __restrict__ d2,
                                             double* __restrict__ part) {
-  __shared__ T pm[3][TPB];  // member products, by member slot in the workgroup
+  __shared__ T pm[3][TPB * L1_MPT];  // member products, by member slot in the workgroup
   __shared__ double sh[(TPB / 64) * (ND + 1)];
   __shared__ double res[ND + 1];
   // XCD-contiguous aggregate ranges: the neighbour aggregates a member
@@ -1058,36 +1061,48 @@ __global__ void __launch_bounds__(TPB) k_l1(GridDims gd, int64_t n1, const int32
     if (MODE == 2 && ND >= 1) dd1 = ld3(d1, I);
     if (MODE == 2 && ND >= 2) dd2 = ld3(d2, I);
   }
-  // one member per thread: K_i sum_{j~i} x'_agg(j)
+  // L1_MPT members per thread: K_i sum_{j~i} x'_agg(j)
   {
-    const int32_t q = qa + tid;
-    V3<T> kx{T(0), T(0), T(0)};
-    if (q < qb) {
+    int32_t a[L1_MPT][6];
+    int deg[L1_MPT];
+    bool hv[L1_MPT];
+#pragma unroll
+    for (int mm = 0; mm < L1_MPT; ++mm) {
+      const int32_t q = qa + tid + mm * TPB;
+      hv[mm] = q < qb;
       const int64_t sq = q / SL, lq = q - sq * SL;
-      int32_t a[6];
-      int deg = 0;
+      deg[mm] = 0;
 #pragma unroll
       for (int u = 0; u < 2 * DIM; ++u) {
-        a[u] = nagg[sq * 6 * SL + u * SL + lq];
-        deg += a[u] >= 0 ? 1 : 0;
+        a[mm][u] = hv[mm] ? nagg[sq * 6 * SL + u * SL + lq] : -1;
+        deg[mm] += a[mm][u] >= 0 ? 1 : 0;
       }
-      const B9<T> kb = node_K<T>(gd, mtq + 3 * (int64_t)q, deg);  // field in member order
-      V3<T> v[6];
-#pragma unroll
-      for (int u = 0; u < 2 * DIM; ++u) v[u] = xv((int64_t)(a[u] >= 0 ? a[u] : 0));
-      V3<T> sx{T(0), T(0), T(0)};
-#pragma unroll
-      for (int u = 0; u < 2 * DIM; ++u) {
-        sx.x += a[u] >= 0 ? v[u].x : T(0);
-        sx.y += a[u] >= 0 ? v[u].y : T(0);
-        sx.z += a[u] >= 0 ? v[u].z : T(0);
-      }
-      const V3<T> p = mv9(kb, sx);
-      kx = V3<T>{T(0) + p.x, T(0) + p.y, T(0) + p.z};
     }
-    pm[0][tid] = kx.x;
-    pm[1][tid] = kx.y;
-    pm[2][tid] = kx.z;
+    V3<T> v[L1_MPT][6];
+#pragma unroll
+    for (int mm = 0; mm < L1_MPT; ++mm)
+#pragma unroll
+      for (int u = 0; u < 2 * DIM; ++u) v[mm][u] = xv((int64_t)(a[mm][u] >= 0 ? a[mm][u] : 0));
+#pragma unroll
+    for (int mm = 0; mm < L1_MPT; ++mm) {
+      const int32_t q = qa + tid + mm * TPB;
+      V3<T> kx{T(0), T(0), T(0)};
+      if (hv[mm]) {
+        const B9<T> kb = node_K<T>(gd, mtq + 3 * (int64_t)q, deg[mm]);  // field in member order
+        V3<T> sx{T(0), T(0), T(0)};
+#pragma unroll
+        for (int u = 0; u < 2 * DIM; ++u) {
+          sx.x += a[mm][u] >= 0 ? v[mm][u].x : T(0);
+          sx.y += a[mm][u] >= 0 ? v[mm][u].y : T(0);
+          sx.z += a[mm][u] >= 0 ? v[mm][u].z : T(0);
+        }
+        const V3<T> p = mv9(kb, sx);
+        kx = V3<T>{T(0) + p.x, T(0) + p.y, T(0) + p.z};
+      }
+      pm[0][tid + mm * TPB] = kx.x;
+      pm[1][tid + mm * TPB] = kx.y;
+      pm[2][tid + mm * TPB] = kx.z;
+    }
   }
   __syncthreads();
   double dots[ND + 1];
@@ -2201,7 +2216,7 @@ void launch_l1(hipStream_t st, GridDims g, int mode, int xzero, int64_t n1, cons
                const T* mtq, const T* x, const T* b, const T* dinv1, const int32_t* agg2, const T* ec,
                double omega, T* out, const T* d1, const T* d2, double* part, hipEvent_t e0, hipEvent_t e1) {
   if (n1 <= 0) return;
-  const dim3 gr(nblk(n1 * L1_G)), t(TPB);
+  const dim3 gr((unsigned)ceil_div(n1, L1_AGG)), t(TPB);
   const T om = (T)omega;
 #define LLG_L1(D, M, XZ, ND)                                                                                      \
   hipExtLaunchKernelGGL((k_l1<D, T, M, XZ, ND>), gr, t, 0, st, e0, e1, 0, g, n1, mptr, nagg, mtq, x, b, dinv1, agg2, \

@@ -423,7 +423,7 @@ void launch_kc_coef(hipStream_t st, const double* part, int64_t G, int stage, do
 // mode 0 r = b - A1 x; mode 1 post-smoothing sweep (xzero: x = 0; ec, agg2
 // the coarse correction or NULL); mode 2 w = A1 x with the K-cycle partial
 // sums (d1, optional d2) over rows_blocks(n1, L1_LANES) workgroups of 256
-constexpr int L1_LANES = 4;
+constexpr int L1_LANES = 2;
 // mtq[q] = mt[mem[q]] for the n grid nodes (the field in the level-1 member order)
 template <typename T>
 void launch_member_fields(hipStream_t st, int64_t n, const int32_t* mem, const double* mt, T* mtq);
