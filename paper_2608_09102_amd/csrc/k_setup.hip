@@ -298,7 +298,7 @@ __device__ inline bool key_before(const EdgeKey& a, const EdgeKey& b, uint64_t s
 
 // The earliest candidate edge of node i (largest weight mxi) over the row
 // slots [kb, k1) that lane sub of its G lanes visits (every G-th slot); best
-// and bk are updated in place.  Neighbours are examined four at a time so
+// and bk are updated in place.  Neighbours are examined U at a time so
 // that their loads are in flight together.
 template <int G, int U = 4>
 __device__ inline void row_best(int64_t i, int sub, int32_t mxi, int32_t kb, int32_t k1,
@@ -443,14 +443,18 @@ __global__ void __launch_bounds__(TPB) k_propose(int64_t n, const int32_t* __res
 }
 
 
-// The round with one lane per node (the levels whose rows are short).  A
-// wavefront pays for a row walk when any of its lanes walks, which most do
-// for ten rounds while a fifth to a third of the nodes walk; so, as in
+// The round on the levels whose rows are short (8-30 entries).  A wavefront
+// pays for a row walk when any of its lanes walks, which most do for ten
+// rounds while a fifth to a third of the nodes walk; so, as in
 // k_propose_grid, the workgroup lists its walkers in LDS (with the record
-// and row bounds loaded beside the last proposal's mate) and its first
-// threads walk them, sixteen slots at a time (a row's loads in flight
-// together; rows hold 8-30 entries).  The decisions are those of
-// propose_node.
+// and row bounds loaded beside the last proposal's mate) and then walks
+// them PK_G lanes per walker, PK_U slots per lane at a time, the lanes'
+// keys merged by a butterfly.  A walker's lanes read consecutive slots of
+// its row, so a row load of a wavefront touches a few cache lines per
+// walker instead of one line per lane (one lane per walker took 1.7 ms more
+// per step at 256^3: the loads of 64 different rows per instruction are what
+// such a round waits on).  The decisions are those of propose_node.
+constexpr int PK_G = 4, PK_U = 4;
 __global__ void __launch_bounds__(TPB) k_propose_packed(int64_t n, const int32_t* __restrict__ grp,
                                                         const int32_t* __restrict__ gci,
                                                         const int32_t* __restrict__ gw, int32_t* __restrict__ mate,
@@ -475,14 +479,36 @@ __global__ void __launch_bounds__(TPB) k_propose_packed(int64_t n, const int32_t
     }
   }
   __syncthreads();
-  if ((int)threadIdx.x < s_nw) {
-    const int4 wk = s_walk[threadIdx.x];
+  const int nw = s_nw;
+  const int sub = (int)threadIdx.x % PK_G;
+  // the same trip count on every thread: the butterfly's shuffles run on all
+  // lanes, a lane group without a walker holds no candidate
+  for (int t0 = 0; t0 < nw; t0 += TPB / PK_G) {
+    const int t = t0 + (int)threadIdx.x / PK_G;
+    const bool act = t < nw;  // the same on a walker's lanes
+    const int4 wk = act ? s_walk[t] : make_int4(0, 0, 0, 0);
     int32_t best = -1;
     EdgeKey bk{};
-    row_best<1, 16>(wk.x, 0, wk.y, wk.z, wk.w, gci, gw, ns, salt, bnum, bden, best, bk);
-    prop[wk.x] = best;
-    if (best < 0) mate[wk.x] = -2;
-    proposed = proposed || best >= 0;
+    if (act) row_best<PK_G, PK_U>(wk.x, sub, wk.y, wk.z, wk.w, gci, gw, ns, salt, bnum, bden, best, bk);
+#pragma unroll
+    for (int off = 1; off < PK_G; off <<= 1) {
+      EdgeKey o;
+      const int32_t ob = __shfl_xor(best, off, PK_G);
+      o.rank = __shfl_xor(bk.rank, off, PK_G);
+      o.first = __shfl_xor(bk.first, off, PK_G);
+      o.w = __shfl_xor(bk.w, off, PK_G);
+      o.lo = __shfl_xor(bk.lo, off, PK_G);
+      o.hi = __shfl_xor(bk.hi, off, PK_G);
+      if (ob >= 0 && (best < 0 || key_before(o, bk, salt))) {
+        bk = o;
+        best = ob;
+      }
+    }
+    if (act && sub == 0) {
+      prop[wk.x] = best;
+      if (best < 0) mate[wk.x] = -2;
+      proposed = proposed || best >= 0;
+    }
   }
   const unsigned long long ballot = __ballot(proposed);
   if ((threadIdx.x & 63) == 0 && ballot && __atomic_load_n(count, __ATOMIC_RELAXED) == 0) atomicOr(count, 1);
@@ -491,8 +517,8 @@ __global__ void __launch_bounds__(TPB) k_propose_packed(int64_t n, const int32_t
 // The grid pass and the accept pass give a thread RN nodes (a workgroup
 // TPB x RN), their loads in flight together: the rounds wait on dependent
 // loads, and more of them in flight per thread hides more of that wait
-// (the one-lane walk of k_propose_packed, with its registers, measured
-// best at one node per thread).
+// (k_propose_packed, whose walk holds more registers, measured best at one
+// node per thread).
 constexpr int RN = 4;
 
 // The same round on the grid graph itself (the first pass of the grid level):
