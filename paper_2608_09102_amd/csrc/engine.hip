@@ -628,7 +628,8 @@ int build_structure(llg_ctx& c, Arena& ar) {
       int32_t* nrp = ar.alloc<int32_t>(nc + 1);
       // rows of the coarse levels of a 3D grid reach about 50 candidates
       const bool wide = nz > 1 && l > 0;
-      const int64_t tiles = ceil_div(nc, cg_tile_rows(wide));
+      const int shape = wide ? 1 : (l == 0 && p == 0) ? 2 : 0;
+      const int64_t tiles = ceil_div(nc, cg_tile_rows(shape));
       int32_t* ttot = ar.alloc<int32_t>(tiles + 1);
       const int gdims[3] = {nx, ny, nz};
       // the next pass (of this level or the next) starts from these nodes
@@ -642,7 +643,7 @@ int build_structure(llg_ctx& c, Arena& ar) {
       const int64_t ng = ar.count(ttot + tiles);
       int32_t* nci = ar.alloc<int32_t>(ng);
       int32_t* nw = ar.alloc<int32_t>(ng);
-      launch_cg_copy(st, nc, wide, cnt, cj, cwt, ttot, nrp, nci, nw);
+      launch_cg_copy(st, nc, shape, cnt, cj, cwt, ttot, nrp, nci, nw);
       LCHK();
       leads[p] = lead;
       mates[p] = mate;

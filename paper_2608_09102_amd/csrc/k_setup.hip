@@ -2224,31 +2224,33 @@ void launch_cg_count(hipStream_t st, int64_t nc, const int32_t* lead, const int3
                      const int32_t* grp, int32_t* cnt) {
   if (nc > 0) hipLaunchKernelGGL(k_cg_count, dim3(nblk(nc)), dim3(TPB), 0, st, nc, lead, mate, grp, cnt);
 }
-int cg_tile_rows(bool wide) { return wide ? TPB / 16 : TPB / 8; }
+int cg_tile_rows(int shape) { return shape == 1 ? TPB / 16 : shape == 2 ? TPB / 4 : TPB / 8; }
 
 void launch_cg_fill(hipStream_t st, int64_t nc, const int32_t* lead, const int32_t* mate,
                     const int32_t* grp, const int32_t* gci, const int32_t* gw, const int32_t* agg,
                     const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* nrp, int32_t* ttot, bool wide,
                     const int* grid, NodeSt* nsn, int32_t* maten, int32_t* propn) {
   if (nc <= 0) return;
-  const dim3 gr(nblk(nc, cg_tile_rows(wide)));
-  // the grid level's rows, and all rows in 2D, have up to about 20
-  // candidates: eight lanes and 32 slots; the coarse levels of 3D grids up
-  // to about 50: sixteen lanes and 64 slots
+  const dim3 gr(nblk(nc, cg_tile_rows(wide ? 1 : grid ? 2 : 0)));
+  // the rows of the grid graph have at most twelve candidates: four lanes
+  // and 16 slots (eight lanes and 32 slots took 0.45 ms more per step at
+  // 256^3); the grid level's second pass, and all rows in 2D, up to about
+  // 20: eight lanes and 32 slots; the coarse levels of 3D grids up to
+  // about 50: sixteen lanes and 64 slots
   if (wide)
     hipLaunchKernelGGL((k_cg_fill<16, 64, false>), gr, dim3(TPB), 0, st, nc, lead, mate, grp, gci, gw, agg, cptr, cj,
                        cw, nrp, ttot, 0, 0, 0, nsn, maten, propn);
   else if (grid)
-    hipLaunchKernelGGL((k_cg_fill<8, 32, true>), gr, dim3(TPB), 0, st, nc, lead, mate, grp, gci, gw, agg, cptr, cj,
+    hipLaunchKernelGGL((k_cg_fill<4, 16, true>), gr, dim3(TPB), 0, st, nc, lead, mate, grp, gci, gw, agg, cptr, cj,
                        cw, nrp, ttot, grid[0], grid[1], grid[2], nsn, maten, propn);
   else
     hipLaunchKernelGGL((k_cg_fill<8, 32, false>), gr, dim3(TPB), 0, st, nc, lead, mate, grp, gci, gw, agg, cptr, cj,
                        cw, nrp, ttot, 0, 0, 0, nsn, maten, propn);
 }
-void launch_cg_copy(hipStream_t st, int64_t nc, bool wide, const int32_t* cptr, const int32_t* cj,
+void launch_cg_copy(hipStream_t st, int64_t nc, int shape, const int32_t* cptr, const int32_t* cj,
                     const int32_t* cw, const int32_t* tbase, int32_t* nrp, int32_t* nci, int32_t* nw) {
   if (nc <= 0) return;
-  const int R = cg_tile_rows(wide);
+  const int R = cg_tile_rows(shape);
   hipLaunchKernelGGL(k_cg_copy, dim3(nblk(nc, R)), dim3(TPB), 0, st, nc, R, cptr, cj, cw, tbase, nrp, nci, nw);
 }
 static PassMaps pass_maps(int np, const int32_t* const* lead, const int32_t* const* mate) {

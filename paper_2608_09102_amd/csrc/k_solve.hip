@@ -261,30 +261,38 @@ __global__ void k_post_smooth(int64_t n, const int32_t* __restrict__ sl, const i
 // that copy: their rows vary in length, so their slices hold about 1.4 times
 // the stored blocks, and a slot line is fetched whole as soon as one row of
 // the slice reaches it.  G lanes share a row: lane sub takes the blocks
-// rp[i] + sub, + G, ..., two per pass with their loads in flight together,
-// and the group's partial sums are added by a butterfly (every lane ends with
-// the total).
+// rp[i] + sub, + G, ..., U = 2 per pass (the column indices, then the
+// values, then the x gathers of the U blocks, each group of loads in flight
+// together), and the group's partial sums are added by a butterfly (every
+// lane ends with the total).
 template <int G, typename T, typename XF>
 __device__ inline void csr_row_mv_g(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                     const T* __restrict__ vt, int64_t i, int sub, XF xf, T& a0, T& a1, T& a2) {
+  constexpr int U = 2;  // blocks per lane and pass
   const int32_t k1 = rp[i + 1];
-  for (int32_t k = rp[i] + sub; k < k1; k += 2 * G) {
-    const bool two = k + G < k1;
-    const int32_t kb = two ? k + G : k;  // a missing second block re-reads the first
-    const int32_t c0 = ci[k], c1 = ci[kb];
-    T p[9], q[9];
+  for (int32_t k = rp[i] + sub; k < k1; k += U * G) {
+    int32_t kk[U], cc[U];
+    bool ok[U];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) p[e] = vt[(int64_t)k * 9 + e];
+    for (int u = 0; u < U; ++u) {
+      ok[u] = k + u * G < k1;
+      kk[u] = ok[u] ? k + u * G : k;  // a missing block re-reads the first
+      cc[u] = ci[kk[u]];
+    }
+    T p[U][9];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) q[e] = vt[(int64_t)kb * 9 + e];
-    const V3<T> x0 = xf(c0), x1 = xf(c1);
-    a0 += p[0] * x0.x + p[1] * x0.y + p[2] * x0.z;
-    a1 += p[3] * x0.x + p[4] * x0.y + p[5] * x0.z;
-    a2 += p[6] * x0.x + p[7] * x0.y + p[8] * x0.z;
-    if (two) {
-      a0 += q[0] * x1.x + q[1] * x1.y + q[2] * x1.z;
-      a1 += q[3] * x1.x + q[4] * x1.y + q[5] * x1.z;
-      a2 += q[6] * x1.x + q[7] * x1.y + q[8] * x1.z;
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int e = 0; e < 9; ++e) p[u][e] = vt[(int64_t)kk[u] * 9 + e];
+    V3<T> xx[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) xx[u] = xf(cc[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!ok[u]) continue;
+      a0 += p[u][0] * xx[u].x + p[u][1] * xx[u].y + p[u][2] * xx[u].z;
+      a1 += p[u][3] * xx[u].x + p[u][4] * xx[u].y + p[u][5] * xx[u].z;
+      a2 += p[u][6] * xx[u].x + p[u][7] * xx[u].y + p[u][8] * xx[u].z;
     }
   }
 #pragma unroll

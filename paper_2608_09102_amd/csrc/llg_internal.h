@@ -222,15 +222,16 @@ void launch_assign(hipStream_t st, int64_t n, const int32_t* mate, const int32_t
                    int32_t* lead);
 void launch_cg_count(hipStream_t st, int64_t nc, const int32_t* lead, const int32_t* mate,
                      const int32_t* grp, int32_t* cnt);
-// Coarse graph rows, written tile by tile (cg_tile_rows(wide) rows per tile)
-// from the tile's candidate offset cptr[first row]: nrp[I] = row I's offset
-// in its tile, ttot[tile] = the tile's length.  wide: the coarse levels of a
-// 3D grid (rows of up to about 50 candidates); grid: {nx, ny, nz} when the
-// graph is the grid graph itself (the grid level's first pass; its rows are
-// then computed), else null.  nsn, maten, propn (or null): the next
+// Coarse graph rows, written tile by tile (cg_tile_rows(shape) rows per
+// tile) from the tile's candidate offset cptr[first row]: nrp[I] = row I's
+// offset in its tile, ttot[tile] = the tile's length.  wide: the coarse
+// levels of a 3D grid (rows of up to about 50 candidates); grid: {nx, ny,
+// nz} when the graph is the grid graph itself (the grid level's first pass;
+// its rows are then computed, at most twelve candidates), else null.  shape:
+// 1 wide, 2 grid, 0 the others.  nsn, maten, propn (or null): the next
 // matching pass's state of the coarse nodes, set as launch_match_init would
 // set it on the new graph.
-int cg_tile_rows(bool wide);
+int cg_tile_rows(int shape);
 void launch_cg_fill(hipStream_t st, int64_t nc, const int32_t* lead, const int32_t* mate,
                     const int32_t* grp, const int32_t* gci, const int32_t* gw, const int32_t* agg,
                     const int32_t* cptr, int32_t* cj, int32_t* cw, int32_t* nrp, int32_t* ttot, bool wide,
@@ -238,7 +239,7 @@ void launch_cg_fill(hipStream_t st, int64_t nc, const int32_t* lead, const int32
 // After an exclusive scan of ttot into tbase (total at tbase[tiles]): the
 // tiles moved to nci/nw end to end, nrp made the row pointers (nrp[nc] the
 // edge count).
-void launch_cg_copy(hipStream_t st, int64_t nc, bool wide, const int32_t* cptr, const int32_t* cj,
+void launch_cg_copy(hipStream_t st, int64_t nc, int shape, const int32_t* cptr, const int32_t* cj,
                     const int32_t* cw, const int32_t* tbase, int32_t* nrp, int32_t* nci, int32_t* nw);
 // Members of the composite aggregates of a level after np passes, from each
 // pass's leaders (lead[q][a]: the leader of aggregate a of pass q, a node of
