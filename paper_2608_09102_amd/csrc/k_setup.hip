@@ -251,7 +251,16 @@ __global__ void k_sell_cols(int64_t n, const int32_t* rows, const int32_t* brp, 
   const int w = (sl_ptr[s + 1] - base) / SL;
   const int64_t i = k < n ? (rows ? rows[k] : k) : -1;
   const int len = i >= 0 ? brp[i + 1] - brp[i] : 0;
-  for (int t = 0; t < w; ++t) col[base + t * SL + l] = t < len ? bci[brp[i] + t] : -1;
+  const int32_t r0 = i >= 0 ? brp[i] : 0;
+  // eight slots at a time, their loads in flight together
+  for (int t = 0; t < w; t += 8) {
+    int32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = t + u < len ? bci[r0 + t + u] : -1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (t + u < w) col[base + (t + u) * SL + l] = v[u];
+  }
 }
 
 // ---------------------------------------------------------------- matching
@@ -291,6 +300,27 @@ __device__ inline bool key_before(const EdgeKey& a, const EdgeKey& b, uint64_t s
   if (a.first != b.first) return a.first < b.first;
   if (a.w != b.w) return a.w > b.w;
   const uint64_t ha = edge_hash(a.lo, a.hi, salt), hb = edge_hash(b.lo, b.hi, salt);
+  if (ha != hb) return ha > hb;
+  if (a.lo != b.lo) return a.lo < b.lo;
+  return a.hi < b.hi;
+}
+
+// key_before with each key's edge hash evaluated at most once (ha, hb: the
+// hashes once hav, hbv are set).  The grid pass uses it: its weights are all
+// equal, so most comparisons of a walker's edges reach the hashes.
+__device__ inline bool key_before_h(const EdgeKey& a, uint64_t& ha, bool& hav, const EdgeKey& b, uint64_t& hb,
+                                    bool& hbv, uint64_t salt) {
+  if (a.rank != b.rank) return a.rank < b.rank;
+  if (a.first != b.first) return a.first < b.first;
+  if (a.w != b.w) return a.w > b.w;
+  if (!hav) {
+    ha = edge_hash(a.lo, a.hi, salt);
+    hav = true;
+  }
+  if (!hbv) {
+    hb = edge_hash(b.lo, b.hi, salt);
+    hbv = true;
+  }
   if (ha != hb) return ha > hb;
   if (a.lo != b.lo) return a.lo < b.lo;
   return a.hi < b.hi;
@@ -607,6 +637,8 @@ __global__ void __launch_bounds__(TPB) k_propose_grid(int nx, int ny, int nz, in
     const uint64_t ri = rank[w];
     int32_t best = -1;
     EdgeKey bk{};
+    uint64_t bh = 0;
+    bool bhv = false;
 #pragma unroll
     for (int u = 0; u < 6; ++u) {
       if (u >= c || mj[u] >= 0) continue;
@@ -620,8 +652,12 @@ __global__ void __launch_bounds__(TPB) k_propose_grid(int nx, int ny, int nz, in
       e.w = 1;
       e.lo = min((int32_t)w, j);
       e.hi = max((int32_t)w, j);
-      if (best < 0 || key_before(e, bk, salt)) {
+      uint64_t eh = 0;
+      bool ehv = false;
+      if (best < 0 || key_before_h(e, eh, ehv, bk, bh, bhv, salt)) {
         bk = e;
+        bh = eh;
+        bhv = ehv;
         best = j;
       }
     }
