@@ -628,7 +628,10 @@ int build_structure(llg_ctx& c, Arena& ar) {
       int32_t* nrp = ar.alloc<int32_t>(nc + 1);
       // rows of the coarse levels of a 3D grid reach about 50 candidates
       const bool wide = nz > 1 && l > 0;
-      const int shape = wide ? 1 : (l == 0 && p == 0) ? 2 : 0;
+      // the grid level's first pass fills from the grid graph (gdims passed
+      // below); the fill's tile rows follow the same choice
+      const bool from_grid = l == 0 && p == 0;
+      const int shape = wide ? 1 : from_grid ? 2 : 0;
       const int64_t tiles = ceil_div(nc, cg_tile_rows(shape));
       int32_t* ttot = ar.alloc<int32_t>(tiles + 1);
       const int gdims[3] = {nx, ny, nz};
@@ -637,7 +640,7 @@ int build_structure(llg_ctx& c, Arena& ar) {
       mate_next = ar.alloc<int32_t>(nc);
       prop_next = ar.alloc<int32_t>(nc);
       launch_cg_fill(st, nc, lead, mate, crp, cci, cw, aggp, cnt, cj, cwt, nrp, ttot, wide,
-                     l == 0 && p == 0 ? gdims : nullptr, ns_next, mate_next, prop_next);
+                     from_grid ? gdims : nullptr, ns_next, mate_next, prop_next);
       launch_scan_excl(st, ttot, ttot, tiles, ttot + tiles, c.scan_tmp);
       LCHK();
       const int64_t ng = ar.count(ttot + tiles);
